@@ -1,0 +1,198 @@
+/*
+ * ib.h - C ABI of the MI355X immersed-boundary acoustic finite-difference library.
+ *
+ * Method: Caunt, Nelson, Luporini, Gorman, "A Novel Immersed Boundary Approach for
+ * Irregular Topography with Acoustic Wave Equations" (arXiv 2309.03600).
+ *   - Grid nodes near an irregular surface use modified second-derivative stencils whose
+ *     weights come from N-D Taylor extrapolants fitted, in hyperspherical support
+ *     regions, to interior data and to boundary conditions imposed at surface points
+ *     (sections "Constructing Finite-Difference Approximations", "Imposition of
+ *     Boundaries", "Approximating Boundary Conditions", "Reconciliation with the Interior
+ *     Numerical Discretization").
+ *   - Time stepping is the explicit centred scheme of the second-order acoustic wave
+ *     equation (section "Application to the 2nd-Order Acoustic Wave Equation"), with a
+ *     damping layer on the outer faces (mentioned in the 2D free-surface example).
+ *
+ * Conventions
+ *   - Axis order (x, [y,] z); z is depth, positive downward.  Every 3D array is stored
+ *     [z][y][x], every 2D array [z][x] (x fastest), heightfields [y][x] or [x].
+ *   - Lateral axes are periodic; above and below the box the field is zero.
+ *   - "device" pointers are HIP device memory on the current device; "host" pointers
+ *     are ordinary host memory.  Streams are hipStream_t passed as void* (NULL = the
+ *     default stream).  Device buffers passed in are borrowed for the call only and
+ *     stay owned by the caller; opaque handles are owned by the library and freed only
+ *     by the matching *_free call.
+ *   - Every call returns ib_status; IB_OK is 0, errors are negative.  Argument errors
+ *     are detected on the host before anything is enqueued; the message is available
+ *     from ib_last_error() (thread-local, valid until the next failing call).  Work is
+ *     enqueued on the given stream; faults inside kernels surface at the next
+ *     synchronising call (ib_build_weights synchronises the stream it is given).
+ */
+#ifndef IBWAVE_IB_H
+#define IBWAVE_IB_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define IB_ABI_VERSION 1
+
+typedef enum {
+  IB_OK = 0,
+  IB_ERR_ARG = -1,            /* invalid argument, unsupported combination or size      */
+  IB_ERR_HIP = -2,            /* a HIP runtime call failed                             */
+  IB_ERR_OOM = -3,            /* device allocation failed                              */
+  IB_ERR_UNCONSTRAINED = -4,  /* an IB point stayed rank deficient after the radius
+                                 growth and basis-order reduction of the rank rule     */
+  IB_ERR_STATE = -6           /* call not valid for this handle / state                */
+} ib_status;
+
+typedef enum { IB_FORM_P2 = 0 } ib_form;                    /* second-order pressure form */
+typedef enum { IB_SURF_FREE = 0, IB_SURF_RIGID = 1 } ib_surface;
+typedef enum { IB_F32 = 0, IB_F64 = 1 } ib_precision;
+
+/* Regular grid.  n[0] = nx, n[1] = ny (3D) , n[ndim-1] = nz.  h = grid increment in
+ * metres, equal on every axis. */
+typedef struct {
+  int32_t ndim;        /* 2 or 3 */
+  int32_t reserved;
+  int64_t n[3];
+  double h;
+} ib_grid;
+
+/* Boundary treatment parameters.
+ *   space_order      M, even, 2..8: order of the interior stencil and of the Taylor basis.
+ *   surface          IB_SURF_FREE: p = 0, lap p = 0, lap^2 p = 0, ... (section
+ *                    "Free-Surface Boundary Constraints");  IB_SURF_RIGID: zero normal
+ *                    velocity, i.e. n.grad(lap^q p) = 0 (rigid-surface examples).
+ *   eta              exclusion cut-off: interior nodes with a boundary point strictly
+ *                    inside their node-centred box of half-width eta*h are not used as
+ *                    data (section "Approximating Boundary Conditions"; 0.5 in the
+ *                    paper's examples).
+ *   max_radius_steps support radius starts at (M_b+1)/2 cells and grows by one cell up
+ *                    to this many times before the basis order M_b drops by one.
+ *   min_basis_order  lowest basis order tried (basis-order reduction).
+ *   rank_rtol        numerical-rank tolerance relative to sigma_max; <= 0 selects
+ *                    max(rows, cols) * 2^-52.
+ *   physical_below   1: the physical domain is below the surface (z > H); 0: above.
+ */
+typedef struct {
+  int32_t form;
+  int32_t surface;
+  int32_t space_order;
+  int32_t max_radius_steps;
+  int32_t min_basis_order;
+  int32_t physical_below;
+  double eta;
+  double rank_rtol;
+} ib_params;
+
+typedef struct {
+  int64_t n_nodes;           /* grid nodes                                              */
+  int64_t n_interior;        /* interior (physical-side) nodes                          */
+  int64_t n_boundary_points; /* hosted boundary points                                  */
+  int64_t n_ib;              /* IB points (interior nodes whose axis stencils reach an
+                                exterior node)                                          */
+  int64_t sum_nw;            /* total extrapolation weights                             */
+  int64_t max_nw;
+  int64_t radius_hist[8];    /* IB points per radius step k (0..7)                      */
+  int64_t order_hist[17];    /* IB points per final basis order                         */
+  double max_cond;           /* largest estimated sigma_max/sigma_min over accepted points */
+  double min_margin;         /* smallest (sigma_min/sigma_max)/tolerance over accepted    */
+  int64_t table_bytes_f32;   /* bytes of the FP32 stencil records (masks + weights)      */
+  int64_t table_bytes_f64;
+  int64_t max_ball;          /* largest support ball (lattice points) used               */
+  double build_ms;           /* wall time of ib_build_weights                            */
+} ib_stats;
+
+typedef struct ib_weights ib_weights;
+typedef struct ib_state ib_state;
+
+int32_t ib_abi_version(void);
+const char *ib_last_error(void);
+
+/* Build the immersed-boundary stencils for one topography.
+ *   height_dev: device, float64 [ny][nx] (3D) or [nx] (2D), surface depth in metres at
+ *     each node column; the surface between columns is the periodic Catmull-Rom cubic
+ *     through these samples and the nodes' signed distance is measured to it (the
+ *     paper's discretised signed-distance function).  Borrowed.
+ *   Produces (on the device): node classes, boundary points (closest surface point of
+ *   each node whose one-cell box contains it), the eta-exclusion mask, the IB-point
+ *   list and, per IB point, the FP64 least-squares extrapolation weights
+ *   y = (A^+)^T c with A the Taylor/boundary-condition rows and c the exterior part of
+ *   the interior Laplacian stencil, plus an FP32 copy.  Synchronises ``stream``.
+ * Errors: IB_ERR_ARG (shape, order, surface too close to the top/bottom of the box),
+ *   IB_ERR_UNCONSTRAINED, IB_ERR_OOM, IB_ERR_HIP. */
+ib_status ib_build_weights(const ib_grid *grid, const double *height_dev, const ib_params *params,
+                           void *stream, ib_weights **out);
+ib_status ib_weights_stats(const ib_weights *w, ib_stats *out);
+void ib_weights_free(ib_weights *w);
+
+/* Copy one array of a built table to host memory (for inspection and tests).
+ *   IB_FIELD_NODE_CLASS  uint8 [n_nodes], memory order: bit0 interior, bit1 excluded
+ *                        by eta, bit2 IB point, bit3 hosts a boundary point.
+ *   IB_FIELD_BPOINTS     float64 [n_boundary_points][7]: host node (x,y,z) as doubles,
+ *                        boundary point (x,y,z) in grid units (2D: y = 0).
+ *   IB_FIELD_IB_NODES    int64 [n_ib]: memory-order node index of each IB point.
+ *   IB_FIELD_IB_META     int32 [n_ib][4]: radius step k, basis order M_b, weight count,
+ *                        first weight index.
+ *   IB_FIELD_WEIGHTS_F64 float64 [sum_nw]: weights of each point in the lattice order
+ *                        of its support ball (z, then y, then x), data nodes only.
+ *   IB_FIELD_SIGMA       float64 [n_ib]: estimated sigma_min/sigma_max of accepted A.
+ * dst_bytes must be at least the field size. */
+typedef enum {
+  IB_FIELD_NODE_CLASS = 0, IB_FIELD_BPOINTS = 1, IB_FIELD_IB_NODES = 2,
+  IB_FIELD_IB_META = 3, IB_FIELD_WEIGHTS_F64 = 4, IB_FIELD_SIGMA = 5
+} ib_field;
+ib_status ib_weights_copy(const ib_weights *w, int32_t field, void *dst_host, int64_t dst_bytes);
+
+/* Create a time-stepping state for ``nshots`` simultaneous shots over one topography.
+ *   vel_dev:  device float64 [nz][ny][nx] (or [nz][nx]) velocity in m/s.  Borrowed.
+ *   dt:       time step (s).  The caller chooses it (e.g. half the interior limit).
+ *   damp_width, damp_R: damping layer of ``damp_width`` cells on the lateral faces and
+ *             the bottom, d = d_max (l/W)^2, d_max = 3 c_max ln(1/R) / (2 W h);
+ *             0 disables it.
+ *   prec:     IB_F32 or IB_F64 wavefields (weights rounded from the FP64 master).
+ *   src_pos_host: host float64 [nshots][ndim], one point source per shot (metres),
+ *             spread multilinearly over the 2^d surrounding nodes, amplitude
+ *             dt^2 * wavelet / h^d (the paper's f~ = f dt^2).
+ *   rec_pos_host: host float64 [nrec][ndim] receivers (metres), sampled multilinearly;
+ *             shared by all shots.
+ * Wavefields start at zero; the step counter at 0.
+ * Errors: IB_ERR_ARG (positions outside the box or touching exterior nodes, nshots < 1),
+ *   IB_ERR_OOM, IB_ERR_HIP. */
+ib_status ib_state_create(const ib_weights *w, const double *vel_dev, double dt, int32_t damp_width,
+                          double damp_R, int32_t prec, int32_t nshots, const double *src_pos_host,
+                          int32_t nrec, const double *rec_pos_host, void *stream, ib_state **out);
+void ib_state_free(ib_state *st);
+
+/* Advance every shot by ``nsteps`` leapfrog steps:
+ *   p^{n+1} = [2 p^n - (1 - s) p^{n-1} + K (L p^n) + dt^2 f^n] / (1 + s),
+ *   K = (c dt / h)^2 at interior nodes (0 elsewhere), s = d dt / 2, L the grid-unit
+ *   Laplacian with the immersed-boundary rows.
+ *   wavelet_dev: device [nshots][wavelet_stride] in the state precision; step n uses
+ *     sample t of the state's step counter (t = 0, 1, ...).  Must cover t + nsteps.
+ *   traces_dev:  device [nshots][nsteps][nrec] in the state precision; receives
+ *     p^{n+1} sampled at the receivers after each step.  May be NULL when nrec = 0.
+ * When use_graph is non-zero the per-step kernels are captured once into a HIP graph
+ * (two steps, even/odd buffers) and replayed; results are identical to eager launch. */
+ib_status ib_step(ib_state *st, int32_t nsteps, const void *wavelet_dev, int64_t wavelet_stride,
+                  void *traces_dev, int32_t use_graph, void *stream);
+
+/* Read or write the current wavefields of one shot (layout [nz][ny][nx] or [nz][nx],
+ * state precision, device memory):  which = 0: p^n (newest), 1: p^{n-1}.
+ * direction 0 copies out of the state, 1 copies into it. */
+ib_status ib_state_field(ib_state *st, int32_t which, int32_t shot, void *dev_buf, int32_t direction,
+                         void *stream);
+int64_t ib_state_step_count(const ib_state *st);
+
+/* Tuning knob of the 3D eighth-order interior kernel: depth planes per workgroup
+ * (0 = whole depth).  Results do not depend on it. */
+ib_status ib_state_set_zchunk(ib_state *st, int32_t zchunk);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -13,6 +13,7 @@ grid increment, exactly as in the paper's scaled 2D delta vector.
 """
 from __future__ import annotations
 
+import functools
 import math
 from fractions import Fraction
 
@@ -30,6 +31,24 @@ def _compositions(k: int, d: int):
     return out
 
 
+_FACT = np.array([math.factorial(i) for i in range(32)], dtype=np.float64)
+
+
+@functools.lru_cache(maxsize=None)
+def _multi_indices_cached(M: int, d: int):
+    out = []
+    for k in range(M + 1):
+        out.extend(_compositions(k, d))
+    return tuple(out)
+
+
+@functools.lru_cache(maxsize=None)
+def _exponent_array(M: int, d: int):
+    E = np.array(_multi_indices_cached(M, d), dtype=np.int64)
+    E.setflags(write=False)
+    return E
+
+
 def multi_indices(M: int, d: int):
     """Exponents of the basis terms of total degree <= M in graded order.
 
@@ -37,10 +56,7 @@ def multi_indices(M: int, d: int):
     then the second (1, x, y, x^2/2, xy, y^2/2, ... in 2D; x^2, xy, xz, y^2, yz, z^2
     in 3D), which is the order the paper lists a and delta in.
     """
-    out = []
-    for k in range(M + 1):
-        out.extend(_compositions(k, d))
-    return out
+    return list(_multi_indices_cached(M, d))
 
 
 def n_terms(M: int, d: int) -> int:
@@ -69,19 +85,15 @@ def derivative_row(delta, M: int, beta):
 
     d^beta (x^e / e!) = x^(e-beta) / (e-beta)! when e >= beta componentwise, else 0.
     """
-    delta = [float(v) for v in delta]
+    delta = np.asarray(delta, dtype=np.float64)
     d = len(delta)
-    row = []
-    for e in multi_indices(M, d):
-        v = 1.0
-        for n in range(d):
-            if e[n] < beta[n]:
-                v = 0.0
-                break
-            p = e[n] - beta[n]
-            v *= delta[n] ** p / math.factorial(p)
-        row.append(v)
-    return np.array(row)
+    E = _exponent_array(M, d)
+    P = E - np.asarray(beta, dtype=np.int64)[None, :]
+    ok = np.all(P >= 0, axis=1)
+    Pc = np.where(P >= 0, P, 0)
+    fac = _FACT[Pc]
+    vals = np.prod(delta[None, :] ** Pc / fac, axis=1)
+    return np.where(ok, vals, 0.0)
 
 
 # ---------------------------------------------------------------------------

@@ -81,6 +81,11 @@ class IBModel:
         self.bp_xb = bp['xb']
         self.bp_normal = bp['normal']
         self.excluded = self.geom.excluded_nodes(self.bp_xb, self.eta)
+        # grid-shaped views (memory order [z, (y,) x]) of the two node classes
+        self.inter_grid = self.geom.interior_grid()
+        self.excl_grid = np.zeros_like(self.inter_grid)
+        for g in self.excluded:
+            self.excl_grid[tuple(reversed(g))] = True
 
     # --- node classes -------------------------------------------------------
     def interior(self, g):
@@ -139,10 +144,16 @@ class IBModel:
 
     # --- per-point system -------------------------------------------------
     def system(self, i, Mb, r):
-        """(A, data offsets, number of data rows) for IB point i at order Mb, radius r."""
+        """(A, data offsets) for IB point i at basis order Mb and radius r."""
         offs = ball_offsets(r, self.d)
-        data = [o for o in offs if self.is_data(tuple(np.asarray(i) + o))]
-        data = np.array(data, dtype=np.int64).reshape(-1, self.d)
+        g = np.asarray(i, dtype=np.int64)[None, :] + offs
+        for n in range(self.d - 1):
+            g[:, n] %= self.shape[n]
+        inside = (g[:, -1] >= 0) & (g[:, -1] < self.shape[-1])
+        gz = np.clip(g[:, -1], 0, self.shape[-1] - 1)
+        idx = (gz,) + tuple(g[:, n] for n in range(self.d - 2, -1, -1))
+        is_data = inside & self.inter_grid[idx] & ~self.excl_grid[idx]
+        data = offs[is_data]
         rows = [taylor_rows(data, Mb)] if len(data) else []
         sel, rel = self.boundary_points_within(i, r)
         for k, rb in zip(sel, rel):

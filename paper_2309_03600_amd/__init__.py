@@ -1,0 +1,193 @@
+"""MI355X-native immersed-boundary acoustic finite differences (arXiv 2309.03600).
+
+Python binding of the C ABI in ``include/ib.h``: every call marshals torch tensors
+(device memory) and streams into the HIP library ``libibwave.so``; every step of the
+method runs in that library's kernels.  There is no CPU fallback: without the built
+library (``paper_2309_03600_amd.build.build()``) every call raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+
+import numpy as np
+
+from . import _lib
+from ._lib import IB_F32, IB_F64, IB_SURF_FREE, IB_SURF_RIGID  # noqa: F401
+
+__all__ = ["IBWeights", "IBState", "ib_build_weights", "ib_state_create", "ib_step", "abi_version"]
+
+
+def _torch():
+    import torch
+    if not torch.cuda.is_available():
+        raise RuntimeError("a HIP device is required")
+    return torch
+
+
+def _stream(stream=None):
+    torch = _torch()
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+def abi_version():
+    return _lib.load().ib_abi_version()
+
+
+class IBWeights:
+    """Handle of a built stencil table (library-owned device memory)."""
+
+    def __init__(self, handle, ndim, shape):
+        self._h = handle
+        self.ndim = ndim
+        self.shape = shape
+
+    def stats(self):
+        st = _lib.ib_stats()
+        _lib.check(_lib.load().ib_weights_stats(self._h, C.byref(st)))
+        out = {k: getattr(st, k) for k, _ in _lib.ib_stats._fields_}
+        out["radius_hist"] = list(st.radius_hist)
+        out["order_hist"] = list(st.order_hist)
+        return out
+
+    def copy(self, field, dtype, count):
+        a = np.zeros(count, dtype=dtype)
+        _lib.check(_lib.load().ib_weights_copy(self._h, field, a.ctypes.data_as(C.c_void_p), a.nbytes))
+        return a
+
+    def export(self):
+        """Host copies of the table: node classes, boundary points, IB nodes, meta, weights."""
+        s = self.stats()
+        N, nb, nib, sw = s["n_nodes"], s["n_boundary_points"], s["n_ib"], s["sum_nw"]
+        return dict(
+            node_class=self.copy(_lib.FIELD_NODE_CLASS, np.uint8, N),
+            bpoints=self.copy(_lib.FIELD_BPOINTS, np.float64, nb * 7).reshape(nb, 7),
+            ib_nodes=self.copy(_lib.FIELD_IB_NODES, np.int64, nib),
+            ib_meta=self.copy(_lib.FIELD_IB_META, np.int32, nib * 4).reshape(nib, 4),
+            weights=self.copy(_lib.FIELD_WEIGHTS_F64, np.float64, sw),
+            sigma=self.copy(_lib.FIELD_SIGMA, np.float64, nib),
+            stats=s,
+        )
+
+    def close(self):
+        if self._h:
+            _lib.load().ib_weights_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def ib_build_weights(heights, h, shape, space_order=8, surface="free", eta=0.5, max_radius_steps=3,
+                     min_basis_order=None, physical_below=True, rank_rtol=0.0, stream=None):
+    """Build the IB stencils for a heightfield (torch float64 device tensor or array, metres)."""
+    torch = _torch()
+    ndim = len(shape)
+    Ht = torch.as_tensor(np.ascontiguousarray(heights, dtype=np.float64) if not torch.is_tensor(heights) else heights,
+                         dtype=torch.float64, device="cuda").contiguous()
+    g = _lib.ib_grid()
+    g.ndim = ndim
+    for i, n in enumerate(shape):
+        g.n[i] = int(n)
+    g.h = float(h)
+    p = _lib.ib_params()
+    p.form = _lib.IB_FORM_P2
+    p.surface = IB_SURF_FREE if surface == "free" else IB_SURF_RIGID
+    p.space_order = int(space_order)
+    p.max_radius_steps = int(max_radius_steps)
+    p.min_basis_order = int(min_basis_order if min_basis_order is not None else max(2, space_order // 2))
+    p.physical_below = 1 if physical_below else 0
+    p.eta = float(eta)
+    p.rank_rtol = float(rank_rtol)
+    out = C.c_void_p()
+    _lib.check(_lib.load().ib_build_weights(C.byref(g), C.c_void_p(Ht.data_ptr()), C.byref(p), _stream(stream),
+                                            C.byref(out)))
+    return IBWeights(out, ndim, tuple(int(v) for v in shape))
+
+
+class IBState:
+    """Wavefields and acquisition of ``nshots`` shots (library-owned device memory)."""
+
+    def __init__(self, handle, weights, prec, nshots, nrec):
+        self._h = handle
+        self.weights = weights
+        self.prec = prec
+        self.nshots = nshots
+        self.nrec = nrec
+
+    @property
+    def dtype(self):
+        torch = _torch()
+        return torch.float32 if self.prec == IB_F32 else torch.float64
+
+    def step(self, nsteps, wavelet, traces=None, use_graph=False, stream=None):
+        """Advance ``nsteps`` steps; wavelet [nshots][nt] and traces [nshots][nsteps][nrec] tensors."""
+        torch = _torch()
+        assert wavelet.dtype == self.dtype and wavelet.is_cuda and wavelet.is_contiguous()
+        assert wavelet.shape[0] == self.nshots
+        if traces is None and self.nrec > 0:
+            traces = torch.zeros((self.nshots, nsteps, self.nrec), dtype=self.dtype, device="cuda")
+        if traces is not None:
+            assert traces.dtype == self.dtype and traces.is_contiguous()
+            assert tuple(traces.shape) == (self.nshots, nsteps, self.nrec)
+        tp = C.c_void_p(traces.data_ptr()) if traces is not None else C.c_void_p()
+        _lib.check(_lib.load().ib_step(self._h, int(nsteps), C.c_void_p(wavelet.data_ptr()), int(wavelet.shape[1]),
+                                       tp, 1 if use_graph else 0, _stream(stream)))
+        return traces
+
+    def field(self, which=0, shot=0, value=None, stream=None):
+        """Get (value None) or set p^n (which=0) / p^{n-1} (which=1) of one shot."""
+        torch = _torch()
+        shape = tuple(reversed(self.weights.shape))
+        if value is None:
+            out = torch.empty(shape, dtype=self.dtype, device="cuda")
+            _lib.check(_lib.load().ib_state_field(self._h, which, shot, C.c_void_p(out.data_ptr()), 0,
+                                                  _stream(stream)))
+            return out
+        v = value.to(device="cuda", dtype=self.dtype).contiguous()
+        assert tuple(v.shape) == shape
+        _lib.check(_lib.load().ib_state_field(self._h, which, shot, C.c_void_p(v.data_ptr()), 1, _stream(stream)))
+        torch.cuda.current_stream().synchronize()
+        return None
+
+    def set_zchunk(self, z):
+        _lib.check(_lib.load().ib_state_set_zchunk(self._h, int(z)))
+
+    @property
+    def step_count(self):
+        return _lib.load().ib_state_step_count(self._h)
+
+    def close(self):
+        if self._h:
+            _lib.load().ib_state_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def ib_state_create(weights, vel, dt, src_pos, rec_pos, damp_width=0, damp_R=1e-3, precision="f32",
+                    stream=None):
+    torch = _torch()
+    vel_t = torch.as_tensor(np.ascontiguousarray(vel, dtype=np.float64) if not torch.is_tensor(vel) else vel,
+                            dtype=torch.float64, device="cuda").contiguous()
+    src = np.ascontiguousarray(np.atleast_2d(src_pos), dtype=np.float64)
+    rec = np.ascontiguousarray(np.asarray(rec_pos, dtype=np.float64).reshape(-1, weights.ndim))
+    prec = IB_F32 if precision in ("f32", "float32") else IB_F64
+    out = C.c_void_p()
+    _lib.check(_lib.load().ib_state_create(weights._h, C.c_void_p(vel_t.data_ptr()), float(dt), int(damp_width),
+                                           float(damp_R), prec, int(src.shape[0]), src.ctypes.data_as(C.c_void_p),
+                                           int(rec.shape[0]), rec.ctypes.data_as(C.c_void_p), _stream(stream),
+                                           C.byref(out)))
+    torch.cuda.current_stream().synchronize()
+    return IBState(out, weights, prec, int(src.shape[0]), int(rec.shape[0]))
+
+
+def ib_step(state, nsteps, wavelet, traces=None, use_graph=False, stream=None):
+    return state.step(nsteps, wavelet, traces, use_graph, stream)

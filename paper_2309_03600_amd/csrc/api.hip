@@ -1,0 +1,647 @@
+// C ABI: argument checking, ownership, state management and the step driver.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "ib_internal.h"
+#include "step.h"
+
+namespace ib {
+ib_status geometry_build(ib_weights *w, const double *height_dev, hipStream_t st);
+ib_status ib_points_build(ib_weights *w, hipStream_t st);
+ib_status weights_build(ib_weights *w, const int64_t *col_off_dev, hipStream_t st);
+const char *last_error_text();
+}  // namespace ib
+
+using namespace ib;
+
+struct ib_state {
+  const ib_weights *w = nullptr;
+  int prec = IB_F32;
+  int nshots = 1;
+  int64_t pitch = 0, vol = 0;
+  size_t esz = 4;
+  void *buf[2] = {nullptr, nullptr};
+  int cur = 0;                 // buf[cur] holds p^n
+  void *K = nullptr, *sx = nullptr, *sy = nullptr, *sz = nullptr;
+  void *scale = nullptr;
+  int64_t *sidx = nullptr;
+  void *sw = nullptr;
+  int nrec = 0;
+  int64_t *ridx = nullptr;
+  void *rw = nullptr;
+  int64_t *tcount = nullptr;   // device [3]
+  int64_t t = 0;
+  double dt = 0.0;
+  int zchunk = 0;
+  // captured two-step graph
+  hipGraphExec_t gexec = nullptr;
+  hipGraph_t graph = nullptr;
+  const void *g_wavelet = nullptr;
+  void *g_traces = nullptr;
+  int64_t g_wstride = 0, g_nsteps = 0;
+  int g_cur = 0;
+};
+
+namespace {
+
+bool bad(const void *p) { return p == nullptr; }
+
+StepArgs make_args(ib_state *st, const void *wavelet, int64_t wstride, void *traces, int64_t nsteps, int cur) {
+  const ib_weights *w = st->w;
+  StepArgs a{};
+  a.prec = st->prec;
+  a.ndim = w->ndim;
+  a.M = w->M;
+  a.nx = (int)w->nx;
+  a.ny = (int)w->ny;
+  a.nz = (int)w->nz;
+  a.pitch = st->pitch;
+  a.vol = st->vol;
+  a.nshots = st->nshots;
+  a.zchunk = st->zchunk;
+  a.un = st->buf[cur];
+  a.um = st->buf[1 - cur];
+  a.K = st->K;
+  a.sx = st->sx;
+  a.sy = st->sy;
+  a.sz = st->sz;
+  a.nib = w->nib;
+  a.rec = (st->prec == IB_F32) ? w->rec32 : w->rec64;
+  a.roff = (st->prec == IB_F32) ? w->rec_off32 : w->rec_off64;
+  a.xyz = w->ib_xyz;
+  a.scale = st->scale;
+  a.ball = w->ball;
+  a.ball_meta = w->ball_meta;
+  a.sidx = st->sidx;
+  a.sw = st->sw;
+  a.wavelet = wavelet;
+  a.wstride = wstride;
+  a.tcount = st->tcount;
+  a.nrec = st->nrec;
+  a.ridx = st->ridx;
+  a.rw = st->rw;
+  a.traces = traces;
+  a.nsteps = nsteps;
+  return a;
+}
+
+template <typename T>
+__global__ void k_make_K(const double *vel, const uint8_t *cls, T *K, int nx, int ny, int nz, int64_t pitch,
+                         double f) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int64_t N = (int64_t)nx * ny * nz;
+  if (i >= N) return;
+  int x = (int)(i % nx);
+  int64_t r = i / nx;
+  int y = (int)(r % ny), z = (int)(r / ny);
+  double v = vel[i];
+  double k = (cls[i] & 1) ? (v * f) * (v * f) : 0.0;
+  K[((size_t)z * ny + y) * pitch + x] = (T)k;
+}
+
+template <typename T>
+__global__ void k_make_scale(const int16_t *xyz, int64_t nib, const double *vel, int nx, int ny, double f,
+                             const double *sx, const double *sy, const double *sz, T *scale) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nib) return;
+  int x = xyz[i * 4], y = xyz[i * 4 + 1], z = xyz[i * 4 + 2];
+  double v = vel[((int64_t)z * ny + y) * nx + x];
+  double k = (v * f) * (v * f);
+  double s = sx[x] + sy[y] + sz[z];
+  scale[i] = (T)(k / (1.0 + s));
+}
+
+// step counter of a call: [0] next step, [1] step being sampled, [2] first step
+__global__ void k_set_counter(int64_t *tc, int64_t t) {
+  tc[0] = t;
+  tc[1] = t;
+  tc[2] = t;
+}
+
+std::vector<double> damping_axis(int64_t n, int width, double dmax, double dt, bool both) {
+  std::vector<double> out(n, 0.0);
+  if (width <= 0) return out;
+  for (int64_t i = 0; i < n; ++i) {
+    double l = 0.0;
+    if (both) l = std::max(l, (double)width - (double)i);
+    l = std::max(l, (double)i - (double)(n - 1 - width));
+    l = std::max(l, 0.0);
+    double d = dmax * (l / width) * (l / width);
+    out[i] = d * dt / 2.0;
+  }
+  return out;
+}
+
+// multilinear corners of a point (grid units); -1 where the weight is exactly zero
+bool corners(const ib_weights *w, const double *pos_m, int64_t idx[8], double wt[8], int64_t pitch,
+             bool padded) {
+  double g[3] = {pos_m[0] / w->h, 0.0, 0.0};
+  if (w->ndim == 3) {
+    g[1] = pos_m[1] / w->h;
+    g[2] = pos_m[2] / w->h;
+  } else {
+    g[2] = pos_m[1] / w->h;
+  }
+  int b[3];
+  double f[3];
+  for (int n = 0; n < 3; ++n) {
+    b[n] = (int)floor(g[n]);
+    f[n] = g[n] - b[n];
+  }
+  for (int c = 0; c < 8; ++c) {
+    idx[c] = -1;
+    wt[c] = 0.0;
+  }
+  int ncorner = (w->ndim == 3) ? 8 : 4;
+  for (int c = 0; c < ncorner; ++c) {
+    int bx = c & 1, by = 0, bz;
+    if (w->ndim == 3) {
+      by = (c >> 1) & 1;
+      bz = (c >> 2) & 1;
+    } else {
+      bz = (c >> 1) & 1;
+    }
+    double wx = bx ? f[0] : 1.0 - f[0];
+    double wy = (w->ndim == 3) ? (by ? f[1] : 1.0 - f[1]) : 1.0;
+    double wz = bz ? f[2] : 1.0 - f[2];
+    double ww = wx * wy * wz;
+    if (ww == 0.0) continue;
+    int64_t x = ((b[0] + bx) % w->nx + w->nx) % w->nx;
+    int64_t y = (w->ndim == 3) ? ((b[1] + by) % w->ny + w->ny) % w->ny : 0;
+    int64_t z = b[2] + bz;
+    if (z < 0 || z >= w->nz) return false;
+    idx[c] = padded ? (z * w->ny + y) * pitch + x : (z * w->ny + y) * w->nx + x;
+    wt[c] = ww;
+  }
+  return true;
+}
+
+}  // namespace
+
+extern "C" {
+
+int32_t ib_abi_version(void) { return IB_ABI_VERSION; }
+
+const char *ib_last_error(void) { return ib::last_error_text(); }
+
+ib_status ib_build_weights(const ib_grid *g, const double *height_dev, const ib_params *p, void *stream,
+                           ib_weights **out) {
+  auto t0 = std::chrono::steady_clock::now();
+  if (!g || !p || !out || bad(height_dev)) {
+    set_error("ib_build_weights: null argument");
+    return IB_ERR_ARG;
+  }
+  *out = nullptr;
+  if (g->ndim != 2 && g->ndim != 3) {
+    set_error("ndim must be 2 or 3 (got %d)", g->ndim);
+    return IB_ERR_ARG;
+  }
+  if (p->form != IB_FORM_P2) {
+    set_error("unsupported form %d", p->form);
+    return IB_ERR_ARG;
+  }
+  if (p->surface != IB_SURF_FREE && p->surface != IB_SURF_RIGID) {
+    set_error("unsupported surface %d", p->surface);
+    return IB_ERR_ARG;
+  }
+  if (p->space_order < 2 || p->space_order > kMaxOrder || (p->space_order & 1)) {
+    set_error("space_order must be even in [2, %d] (got %d)", kMaxOrder, p->space_order);
+    return IB_ERR_ARG;
+  }
+  if (p->max_radius_steps < 0 || p->space_order + 1 + 2 * p->max_radius_steps + 2 > kMaxRadiusCode) {
+    set_error("max_radius_steps out of range (%d)", p->max_radius_steps);
+    return IB_ERR_ARG;
+  }
+  if (p->min_basis_order < 1 || p->min_basis_order > p->space_order) {
+    set_error("min_basis_order must be in [1, space_order] (got %d)", p->min_basis_order);
+    return IB_ERR_ARG;
+  }
+  if (!(p->eta >= 0.0 && p->eta <= 1.0)) {
+    set_error("eta must be in [0, 1] (got %g)", p->eta);
+    return IB_ERR_ARG;
+  }
+  if (!(g->h > 0.0)) {
+    set_error("grid increment must be positive");
+    return IB_ERR_ARG;
+  }
+  ib_weights *w = new ib_weights();
+  w->ndim = g->ndim;
+  w->nx = g->n[0];
+  w->ny = (g->ndim == 3) ? g->n[1] : 1;
+  w->nz = g->n[g->ndim - 1];
+  w->N = w->nx * w->ny * w->nz;
+  w->h = g->h;
+  w->prm = *p;
+  w->M = p->space_order;
+  w->pitch = (w->nx + 31) / 32 * 32;
+  if (w->nx < 16 || w->nz < 16 || (g->ndim == 3 && w->ny < 16) || w->nx > 32000 || w->ny > 32000 ||
+      w->nz > 32000 || w->N >= (int64_t)1 << 31) {
+    set_error("grid extents must be in [16, 32000] with fewer than 2^31 nodes");
+    delete w;
+    return IB_ERR_ARG;
+  }
+  hipStream_t st = (hipStream_t)stream;
+  IB_HIP(hipGetDevice(&w->device));
+  ib_status s = geometry_build(w, height_dev, st);
+  if (s != IB_OK) {
+    ib_weights_free(w);
+    return s;
+  }
+  // the surface band must stay clear of the top and bottom of the box
+  {
+    std::vector<double> hs(w->nx * w->ny);
+    IB_HIP(hipMemcpy(hs.data(), w->Hs, hs.size() * 8, hipMemcpyDeviceToHost));
+    double lo = *std::min_element(hs.begin(), hs.end()), hi = *std::max_element(hs.begin(), hs.end());
+    double margin = (w->M + 1 + 2 * p->max_radius_steps) / 2.0 + w->M / 2 + 2;
+    if (lo < margin || hi > (double)(w->nz - 1) - margin) {
+      set_error("surface depth range [%.2f, %.2f] cells must keep %.1f cells from the top and bottom", lo, hi, margin);
+      ib_weights_free(w);
+      return IB_ERR_ARG;
+    }
+  }
+  if ((s = ib_points_build(w, st)) != IB_OK) {
+    ib_weights_free(w);
+    return s;
+  }
+  // boundary points are stored per column: rebuild column offsets for the solver
+  int64_t *col_off = nullptr;
+  {
+    int64_t ncol = w->nx * w->ny;
+    std::vector<double> bp(w->nb * 8);
+    if (w->nb) IB_HIP(hipMemcpy(bp.data(), w->bp, bp.size() * 8, hipMemcpyDeviceToHost));
+    std::vector<int64_t> off(ncol + 1, 0);
+    for (int64_t j = 0; j < w->nb; ++j) {
+      int64_t c = (int64_t)bp[j * 8 + 1] * w->nx + (int64_t)bp[j * 8 + 0];
+      off[c + 1]++;
+    }
+    for (int64_t c = 0; c < ncol; ++c) off[c + 1] += off[c];
+    if ((s = dalloc_t(&col_off, ncol + 1)) != IB_OK) {
+      ib_weights_free(w);
+      return s;
+    }
+    IB_HIP(hipMemcpy(col_off, off.data(), (ncol + 1) * 8, hipMemcpyHostToDevice));
+  }
+  s = weights_build(w, col_off, st);
+  dfree(col_off);
+  if (s != IB_OK) {
+    ib_weights_free(w);
+    return s;
+  }
+  // statistics
+  {
+    std::vector<uint8_t> cls(w->N);
+    IB_HIP(hipMemcpy(cls.data(), w->node_class, w->N, hipMemcpyDeviceToHost));
+    int64_t ni = 0;
+    for (auto c : cls) ni += (c & 1);
+    w->stats.n_nodes = w->N;
+    w->stats.n_interior = ni;
+    w->stats.n_boundary_points = w->nb;
+    w->stats.n_ib = w->nib;
+  }
+  IB_HIP(hipStreamSynchronize(st));
+  w->stats.build_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  *out = w;
+  return IB_OK;
+}
+
+ib_status ib_weights_stats(const ib_weights *w, ib_stats *out) {
+  if (!w || !out) {
+    set_error("ib_weights_stats: null argument");
+    return IB_ERR_ARG;
+  }
+  *out = w->stats;
+  return IB_OK;
+}
+
+void ib_weights_free(ib_weights *w) {
+  if (!w) return;
+  dfree(w->Hs);
+  dfree(w->node_class);
+  dfree(w->bp);
+  dfree(w->bp_normal);
+  dfree(w->ib_node);
+  dfree(w->ib_xyz);
+  dfree(w->ib_meta);
+  dfree(w->ib_sigma);
+  dfree(w->w64);
+  dfree(w->rec32);
+  dfree(w->rec64);
+  dfree(w->rec_off32);
+  dfree(w->rec_off64);
+  dfree(w->ball);
+  dfree(w->ball_meta);
+  delete w;
+}
+
+ib_status ib_weights_copy(const ib_weights *w, int32_t field, void *dst, int64_t bytes) {
+  if (!w || !dst) {
+    set_error("ib_weights_copy: null argument");
+    return IB_ERR_ARG;
+  }
+  const void *src = nullptr;
+  int64_t need = 0;
+  switch (field) {
+    case IB_FIELD_NODE_CLASS: src = w->node_class; need = w->N; break;
+    case IB_FIELD_IB_NODES: src = w->ib_node; need = w->nib * 8; break;
+    case IB_FIELD_IB_META: src = w->ib_meta; need = w->nib * 16; break;
+    case IB_FIELD_WEIGHTS_F64: src = w->w64; need = w->sumw * 8; break;
+    case IB_FIELD_SIGMA: src = w->ib_sigma; need = w->nib * 8; break;
+    case IB_FIELD_BPOINTS: {
+      need = w->nb * 7 * 8;
+      if (bytes < need) {
+        set_error("ib_weights_copy: destination too small (%lld < %lld)", (long long)bytes, (long long)need);
+        return IB_ERR_ARG;
+      }
+      std::vector<double> bp(w->nb * 8);
+      if (w->nb) IB_HIP(hipMemcpy(bp.data(), w->bp, bp.size() * 8, hipMemcpyDeviceToHost));
+      double *o = (double *)dst;
+      for (int64_t j = 0; j < w->nb; ++j) {
+        for (int q = 0; q < 6; ++q) o[j * 7 + q] = bp[j * 8 + q];
+        o[j * 7 + 6] = 0.0;
+      }
+      return IB_OK;
+    }
+    default:
+      set_error("ib_weights_copy: unknown field %d", field);
+      return IB_ERR_ARG;
+  }
+  if (bytes < need) {
+    set_error("ib_weights_copy: destination too small (%lld < %lld)", (long long)bytes, (long long)need);
+    return IB_ERR_ARG;
+  }
+  if (need) IB_HIP(hipMemcpy(dst, src, need, hipMemcpyDeviceToHost));
+  return IB_OK;
+}
+
+ib_status ib_state_create(const ib_weights *w, const double *vel_dev, double dt, int32_t damp_width, double damp_R,
+                          int32_t prec, int32_t nshots, const double *src_pos, int32_t nrec, const double *rec_pos,
+                          void *stream, ib_state **out) {
+  if (!w || !out || bad(vel_dev) || (nshots > 0 && !src_pos) || (nrec > 0 && !rec_pos)) {
+    set_error("ib_state_create: null argument");
+    return IB_ERR_ARG;
+  }
+  *out = nullptr;
+  if (prec != IB_F32 && prec != IB_F64) {
+    set_error("precision must be IB_F32 or IB_F64");
+    return IB_ERR_ARG;
+  }
+  if (nshots < 1 || nrec < 0 || !(dt > 0.0) || damp_width < 0 || (damp_width > 0 && !(damp_R > 0.0 && damp_R < 1.0))) {
+    set_error("ib_state_create: invalid nshots/nrec/dt/damping");
+    return IB_ERR_ARG;
+  }
+  hipStream_t st = (hipStream_t)stream;
+  ib_state *S = new ib_state();
+  S->w = w;
+  S->prec = prec;
+  S->nshots = nshots;
+  S->esz = (prec == IB_F32) ? 4 : 8;
+  S->pitch = w->pitch;
+  S->vol = S->pitch * w->ny * w->nz;
+  S->dt = dt;
+  S->nrec = nrec;
+  S->zchunk = 0;
+  ib_status s;
+  auto fail = [&](ib_status e) {
+    ib_state_free(S);
+    return e;
+  };
+  const size_t fbytes = (size_t)S->vol * nshots * S->esz;
+  if ((s = dalloc(&S->buf[0], fbytes)) || (s = dalloc(&S->buf[1], fbytes)) || (s = dalloc(&S->K, S->vol * S->esz)))
+    return fail(s);
+  IB_HIP(hipMemsetAsync(S->buf[0], 0, fbytes, st));
+  IB_HIP(hipMemsetAsync(S->buf[1], 0, fbytes, st));
+  IB_HIP(hipMemsetAsync(S->K, 0, S->vol * S->esz, st));
+  const double f = dt / w->h;
+  const int T = 256;
+  if (prec == IB_F32)
+    hipLaunchKernelGGL(k_make_K<float>, dim3((w->N + T - 1) / T), dim3(T), 0, st, vel_dev, w->node_class,
+                       (float *)S->K, (int)w->nx, (int)w->ny, (int)w->nz, S->pitch, f);
+  else
+    hipLaunchKernelGGL(k_make_K<double>, dim3((w->N + T - 1) / T), dim3(T), 0, st, vel_dev, w->node_class,
+                       (double *)S->K, (int)w->nx, (int)w->ny, (int)w->nz, S->pitch, f);
+  IB_HIP(hipGetLastError());
+  // damping tables
+  double vmax = 0.0;
+  {
+    std::vector<double> v(w->N);
+    IB_HIP(hipMemcpyAsync(v.data(), vel_dev, w->N * 8, hipMemcpyDeviceToHost, st));
+    IB_HIP(hipStreamSynchronize(st));
+    for (double x : v) vmax = std::max(vmax, x);
+  }
+  const double dmax = (damp_width > 0) ? 3.0 * vmax * std::log(1.0 / damp_R) / (2.0 * damp_width * w->h) : 0.0;
+  std::vector<double> ax = damping_axis(w->nx, damp_width, dmax, dt, true);
+  std::vector<double> ay = (w->ndim == 3) ? damping_axis(w->ny, damp_width, dmax, dt, true) : std::vector<double>(1, 0.0);
+  std::vector<double> az = damping_axis(w->nz, damp_width, dmax, dt, false);
+  double *d_ax = nullptr, *d_ay = nullptr, *d_az = nullptr;
+  if ((s = dalloc_t(&d_ax, ax.size())) || (s = dalloc_t(&d_ay, ay.size())) || (s = dalloc_t(&d_az, az.size())))
+    return fail(s);
+  IB_HIP(hipMemcpy(d_ax, ax.data(), ax.size() * 8, hipMemcpyHostToDevice));
+  IB_HIP(hipMemcpy(d_ay, ay.data(), ay.size() * 8, hipMemcpyHostToDevice));
+  IB_HIP(hipMemcpy(d_az, az.data(), az.size() * 8, hipMemcpyHostToDevice));
+  auto upload_cast = [&](const std::vector<double> &v, void **dst) -> ib_status {
+    ib_status e = dalloc(dst, v.size() * S->esz);
+    if (e) return e;
+    if (prec == IB_F32) {
+      std::vector<float> t(v.begin(), v.end());
+      IB_HIP(hipMemcpy(*dst, t.data(), t.size() * 4, hipMemcpyHostToDevice));
+    } else {
+      IB_HIP(hipMemcpy(*dst, v.data(), v.size() * 8, hipMemcpyHostToDevice));
+    }
+    return IB_OK;
+  };
+  if ((s = upload_cast(ax, &S->sx)) || (s = upload_cast(ay, &S->sy)) || (s = upload_cast(az, &S->sz))) return fail(s);
+  if ((s = dalloc(&S->scale, std::max<int64_t>(w->nib, 1) * S->esz))) return fail(s);
+  if (w->nib > 0) {
+    if (prec == IB_F32)
+      hipLaunchKernelGGL(k_make_scale<float>, dim3((w->nib + T - 1) / T), dim3(T), 0, st, w->ib_xyz, w->nib, vel_dev,
+                         (int)w->nx, (int)w->ny, f, d_ax, d_ay, d_az, (float *)S->scale);
+    else
+      hipLaunchKernelGGL(k_make_scale<double>, dim3((w->nib + T - 1) / T), dim3(T), 0, st, w->ib_xyz, w->nib,
+                         vel_dev, (int)w->nx, (int)w->ny, f, d_ax, d_ay, d_az, (double *)S->scale);
+    IB_HIP(hipGetLastError());
+  }
+  IB_HIP(hipStreamSynchronize(st));
+  dfree(d_ax), dfree(d_ay), dfree(d_az);
+  // sources: interior corners only; amplitude factor dt^2 w / (h^d (1 + s))
+  std::vector<uint8_t> cls(w->N);
+  IB_HIP(hipMemcpy(cls.data(), w->node_class, w->N, hipMemcpyDeviceToHost));
+  std::vector<int64_t> sidx(nshots * 8, -1);
+  std::vector<double> swv(nshots * 8, 0.0);
+  const double hd = std::pow(w->h, w->ndim);
+  for (int sh = 0; sh < nshots; ++sh) {
+    int64_t idx[8], idu[8];
+    double wt[8];
+    if (!corners(w, src_pos + (size_t)sh * w->ndim, idx, wt, S->pitch, true) ||
+        !corners(w, src_pos + (size_t)sh * w->ndim, idu, wt, S->pitch, false)) {
+      set_error("source %d outside the box", sh);
+      return fail(IB_ERR_ARG);
+    }
+    for (int c = 0; c < 8; ++c) {
+      if (idx[c] < 0) continue;
+      if (!(cls[idu[c]] & 1)) {
+        set_error("source %d touches an exterior node", sh);
+        return fail(IB_ERR_ARG);
+      }
+      int64_t x = idu[c] % w->nx, y = (idu[c] / w->nx) % w->ny, z = idu[c] / (w->nx * w->ny);
+      double sd = ax[x] + ay[(w->ndim == 3) ? y : 0] + az[z];
+      sidx[sh * 8 + c] = idx[c];
+      swv[sh * 8 + c] = dt * dt * wt[c] / (hd * (1.0 + sd));
+    }
+  }
+  if ((s = dalloc_t(&S->sidx, nshots * 8)) || (s = dalloc(&S->sw, nshots * 8 * S->esz))) return fail(s);
+  IB_HIP(hipMemcpy(S->sidx, sidx.data(), nshots * 64, hipMemcpyHostToDevice));
+  {
+    void *tmp = nullptr;
+    std::vector<double> v(swv);
+    if ((s = upload_cast(v, &tmp))) return fail(s);
+    IB_HIP(hipMemcpy(S->sw, tmp, nshots * 8 * S->esz, hipMemcpyDeviceToDevice));
+    dfree(tmp);
+  }
+  // receivers
+  std::vector<int64_t> ridx(std::max(nrec, 1) * 8, -1);
+  std::vector<double> rwv(std::max(nrec, 1) * 8, 0.0);
+  for (int r = 0; r < nrec; ++r) {
+    int64_t idx[8];
+    double wt[8];
+    if (!corners(w, rec_pos + (size_t)r * w->ndim, idx, wt, S->pitch, true)) {
+      set_error("receiver %d outside the box", r);
+      return fail(IB_ERR_ARG);
+    }
+    for (int c = 0; c < 8; ++c) {
+      ridx[r * 8 + c] = idx[c];
+      rwv[r * 8 + c] = wt[c];
+    }
+  }
+  if ((s = dalloc_t(&S->ridx, ridx.size())) || (s = upload_cast(rwv, &S->rw))) return fail(s);
+  IB_HIP(hipMemcpy(S->ridx, ridx.data(), ridx.size() * 8, hipMemcpyHostToDevice));
+  if ((s = dalloc_t(&S->tcount, 4))) return fail(s);
+  IB_HIP(hipMemset(S->tcount, 0, 32));
+  IB_HIP(hipStreamSynchronize(st));
+  // z-chunking of the 3D interior kernel: enough workgroups to fill 256 CUs
+  if (w->ndim == 3) {
+    int64_t tiles = ((w->nx + 63) / 64) * ((w->ny + 15) / 16) * nshots;
+    int64_t want = 2048;
+    int nzc = (int)std::max<int64_t>(1, std::min<int64_t>(w->nz / 16, (want + tiles - 1) / tiles));
+    S->zchunk = (int)((w->nz + nzc - 1) / nzc);
+  }
+  *out = S;
+  return IB_OK;
+}
+
+void ib_state_free(ib_state *S) {
+  if (!S) return;
+  if (S->gexec) (void)hipGraphExecDestroy(S->gexec);
+  if (S->graph) (void)hipGraphDestroy(S->graph);
+  dfree(S->buf[0]);
+  dfree(S->buf[1]);
+  dfree(S->K);
+  dfree(S->sx);
+  dfree(S->sy);
+  dfree(S->sz);
+  dfree(S->scale);
+  dfree(S->sidx);
+  dfree(S->sw);
+  dfree(S->ridx);
+  dfree(S->rw);
+  dfree(S->tcount);
+  delete S;
+}
+
+int64_t ib_state_step_count(const ib_state *S) { return S ? S->t : -1; }
+
+ib_status ib_state_set_zchunk(ib_state *S, int32_t zchunk) {
+  if (!S || zchunk < 0) {
+    set_error("ib_state_set_zchunk: invalid argument");
+    return IB_ERR_ARG;
+  }
+  S->zchunk = zchunk > 0 ? zchunk : (int)S->w->nz;
+  if (S->gexec) {
+    (void)hipGraphExecDestroy(S->gexec);
+    (void)hipGraphDestroy(S->graph);
+    S->gexec = nullptr;
+    S->graph = nullptr;
+  }
+  return IB_OK;
+}
+
+ib_status ib_step(ib_state *S, int32_t nsteps, const void *wavelet, int64_t wstride, void *traces, int32_t use_graph,
+                  void *stream) {
+  if (!S || nsteps < 0 || (S->nrec > 0 && nsteps > 0 && !traces) || !wavelet) {
+    set_error("ib_step: invalid argument");
+    return IB_ERR_ARG;
+  }
+  if (S->t + nsteps > wstride) {
+    set_error("ib_step: wavelet has %lld samples, steps up to %lld requested", (long long)wstride,
+              (long long)(S->t + nsteps));
+    return IB_ERR_ARG;
+  }
+  if (nsteps == 0) return IB_OK;
+  hipStream_t st = (hipStream_t)stream;
+  hipLaunchKernelGGL(k_set_counter, dim3(1), dim3(1), 0, st, S->tcount, S->t);
+  int64_t done = 0;
+  if (use_graph && nsteps >= 2) {
+    const bool reuse = S->gexec && S->g_wavelet == wavelet && S->g_traces == traces && S->g_wstride == wstride &&
+                       S->g_nsteps == nsteps && S->g_cur == S->cur;
+    if (!reuse) {
+      if (S->gexec) {
+        (void)hipGraphExecDestroy(S->gexec);
+        (void)hipGraphDestroy(S->graph);
+        S->gexec = nullptr;
+        S->graph = nullptr;
+      }
+      hipStream_t cs;
+      IB_HIP(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+      IB_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+      for (int q = 0; q < 2; ++q) {
+        StepArgs a = make_args(S, wavelet, wstride, traces, nsteps, (S->cur + q) & 1);
+        enqueue_step(a, cs);
+      }
+      hipError_t e = hipStreamEndCapture(cs, &S->graph);
+      if (e != hipSuccess) {
+        (void)hipStreamDestroy(cs);
+        return hip_fail(e, "hipStreamEndCapture", __FILE__, __LINE__);
+      }
+      (void)hipStreamDestroy(cs);
+      IB_HIP(hipGraphInstantiate(&S->gexec, S->graph, nullptr, nullptr, 0));
+      S->g_wavelet = wavelet;
+      S->g_traces = traces;
+      S->g_wstride = wstride;
+      S->g_nsteps = nsteps;
+      S->g_cur = S->cur;
+    }
+    for (; done + 2 <= nsteps; done += 2) IB_HIP(hipGraphLaunch(S->gexec, st));
+  }
+  for (; done < nsteps; ++done) {
+    StepArgs a = make_args(S, wavelet, wstride, traces, nsteps, S->cur);
+    enqueue_step(a, st);
+    S->cur ^= 1;
+  }
+  IB_HIP(hipGetLastError());
+  S->t += nsteps;
+  return IB_OK;
+}
+
+ib_status ib_state_field(ib_state *S, int32_t which, int32_t shot, void *dev, int32_t direction, void *stream) {
+  if (!S || !dev || which < 0 || which > 1 || shot < 0 || shot >= S->nshots || direction < 0 || direction > 1) {
+    set_error("ib_state_field: invalid argument");
+    return IB_ERR_ARG;
+  }
+  const ib_weights *w = S->w;
+  char *base = (char *)S->buf[which == 0 ? S->cur : 1 - S->cur] + (size_t)shot * S->vol * S->esz;
+  size_t rowb = w->nx * S->esz, pitchb = S->pitch * S->esz;
+  size_t rows = w->ny * w->nz;
+  hipStream_t st = (hipStream_t)stream;
+  if (direction == 0)
+    IB_HIP(hipMemcpy2DAsync(dev, rowb, base, pitchb, rowb, rows, hipMemcpyDeviceToDevice, st));
+  else
+    IB_HIP(hipMemcpy2DAsync(base, pitchb, dev, rowb, rowb, rows, hipMemcpyDeviceToDevice, st));
+  return IB_OK;
+}
+
+}  // extern "C"

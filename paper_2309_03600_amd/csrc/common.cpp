@@ -1,0 +1,162 @@
+// Shared host-side helpers: error reporting, allocation, lattice balls, operator tables.
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+
+#include "ib_internal.h"
+
+namespace ib {
+
+static thread_local std::string g_err;
+
+const char *last_error_text() { return g_err.c_str(); }
+
+void set_error(const char *fmt, ...) {
+  char buf[1024];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_err = buf;
+}
+
+ib_status hip_fail(hipError_t e, const char *what, const char *file, int line) {
+  set_error("%s failed: %s (%s:%d)", what, hipGetErrorString(e), file, line);
+  return (e == hipErrorOutOfMemory) ? IB_ERR_OOM : IB_ERR_HIP;
+}
+
+ib_status dalloc(void **p, size_t bytes) {
+  *p = nullptr;
+  if (bytes == 0) bytes = 16;
+  hipError_t e = hipMalloc(p, bytes);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    set_error("hipMalloc of %zu bytes failed: %s", bytes, hipGetErrorString(e));
+    *p = nullptr;
+    return IB_ERR_OOM;
+  }
+  return IB_OK;
+}
+
+void dfree(void *p) {
+  if (p) (void)hipFree(p);
+}
+
+void BallTables::build(int ndim, int max_code) {
+  packed.clear();
+  for (int c = 1; c <= max_code; ++c) {
+    start[c] = (int)packed.size();
+    int R = c / 2;
+    long long r2x4 = (long long)c * c;   // (2r)^2; |o|^2 <= r^2  <=>  4|o|^2 <= (2r)^2
+    int zlo = -R, zhi = R, ylo = (ndim == 3) ? -R : 0, yhi = (ndim == 3) ? R : 0;
+    for (int dz = zlo; dz <= zhi; ++dz)
+      for (int dy = ylo; dy <= yhi; ++dy)
+        for (int dx = -R; dx <= R; ++dx) {
+          long long s = 4LL * (dx * dx + dy * dy + dz * dz);
+          if (s <= r2x4) {
+            uint32_t v = (uint32_t)(uint8_t)(int8_t)dx | ((uint32_t)(uint8_t)(int8_t)dy << 8) |
+                         ((uint32_t)(uint8_t)(int8_t)dz << 16);
+            packed.push_back((int32_t)v);
+          }
+        }
+    count[c] = (int)packed.size() - start[c];
+  }
+}
+
+int n_terms(int M, int ndim) {
+  long long n = 1;
+  for (int i = 1; i <= ndim; ++i) n = n * (M + i) / i;
+  return (int)n;
+}
+
+// Graded order: degree 0..M; inside a degree the x exponent descends, then y.
+void multi_indices(int M, int ndim, std::vector<int8_t> &out) {
+  out.clear();
+  for (int k = 0; k <= M; ++k) {
+    if (ndim == 2) {
+      for (int a = k; a >= 0; --a) {
+        out.push_back((int8_t)a);
+        out.push_back(0);
+        out.push_back((int8_t)(k - a));
+      }
+    } else {
+      for (int a = k; a >= 0; --a)
+        for (int b = k - a; b >= 0; --b) {
+          out.push_back((int8_t)a);
+          out.push_back((int8_t)b);
+          out.push_back((int8_t)(k - a - b));
+        }
+    }
+  }
+}
+
+// Centred second-derivative weights of order M = 2m (grid units), closed form
+// w_k = 2 (-1)^(k+1) (m!)^2 / (k^2 (m-k)! (m+k)!), w_0 = -2 sum_k w_k.
+void second_derivative_weights(int M, double *w) {
+  int m = M / 2;
+  auto fact = [](int n) {
+    double f = 1.0;
+    for (int i = 2; i <= n; ++i) f *= i;
+    return f;
+  };
+  double s = 0.0;
+  for (int k = 1; k <= m; ++k) {
+    double v = 2.0 * ((k % 2) ? 1.0 : -1.0) * fact(m) * fact(m) / ((double)k * k * fact(m - k) * fact(m + k));
+    w[m + k] = v;
+    w[m - k] = v;
+    s += v;
+  }
+  w[m] = -2.0 * s;
+}
+
+// nabla^{2q} in d dimensions: sum over |g| = q of q!/g! d^{2g}.
+static void add_laplacian_power(OpSet &ops, int slot, int q, int ndim, int normal_axis) {
+  auto fact = [](int n) {
+    double f = 1.0;
+    for (int i = 2; i <= n; ++i) f *= i;
+    return f;
+  };
+  for (int a = q; a >= 0; --a) {
+    for (int b = (ndim == 3 ? q - a : 0); b >= 0; --b) {
+      int c = q - a - b;
+      if (ndim == 2) {
+        c = q - a;
+        b = 0;
+      }
+      double coef = fact(q) / (fact(a) * fact(b) * fact(c));
+      OpTerm t{};
+      t.beta[0] = (int8_t)(2 * a);
+      t.beta[1] = (int8_t)(2 * b);
+      t.beta[2] = (int8_t)(2 * c);
+      t.normal_axis = (int8_t)normal_axis;
+      t.coef = coef;
+      if (normal_axis >= 0) t.beta[normal_axis] += 1;
+      ops.term[slot][ops.nterms[slot]++] = t;
+      if (ndim == 2) break;
+    }
+  }
+}
+
+OpSet make_ops(int surface, int Mb, int ndim) {
+  OpSet ops;
+  memset(&ops, 0, sizeof(ops));
+  if (surface == IB_SURF_FREE) {
+    for (int q = 0; 2 * q <= Mb; ++q) {
+      add_laplacian_power(ops, ops.nops, q, ndim, -1);
+      ops.nops++;
+    }
+  } else {
+    for (int q = 0; 2 * q + 1 <= Mb; ++q) {
+      // n . grad (nabla^{2q}): the lateral axes then depth (2D uses axes x and z)
+      for (int ax = 0; ax < 3; ++ax) {
+        if (ndim == 2 && ax == 1) continue;
+        add_laplacian_power(ops, ops.nops, q, ndim, ax);
+      }
+      ops.nops++;
+    }
+  }
+  return ops;
+}
+
+}  // namespace ib

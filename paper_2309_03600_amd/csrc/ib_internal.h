@@ -1,0 +1,98 @@
+// Internal declarations of the immersed-boundary library (not part of the C ABI).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/ib.h"
+
+namespace ib {
+
+constexpr int kMaxOrder = 8;           // largest space order M supported
+constexpr int kMaxTerms = 165;         // binomial(8+3, 3)
+constexpr int kMaxRadiusCode = 40;     // radius codes 2r = 1..40 (r <= 20 cells)
+constexpr int kMaxOps = 8;             // boundary-condition rows per boundary point
+constexpr int kMaxOpTerms = 48;        // derivative terms per boundary-condition row
+
+void set_error(const char *fmt, ...);
+ib_status hip_fail(hipError_t e, const char *what, const char *file, int line);
+
+#define IB_HIP(call)                                                          \
+  do {                                                                        \
+    hipError_t _e = (call);                                                   \
+    if (_e != hipSuccess) return ib::hip_fail(_e, #call, __FILE__, __LINE__); \
+  } while (0)
+
+// Device allocation that reports IB_ERR_OOM.
+ib_status dalloc(void **p, size_t bytes);
+template <class T>
+ib_status dalloc_t(T **p, size_t count) {
+  return dalloc(reinterpret_cast<void **>(p), count * sizeof(T));
+}
+void dfree(void *p);
+
+// Lattice points of the ball |o| <= code/2 in memory order (z slowest, x fastest),
+// packed as signed bytes (dx, dy, dz, 0); the same list for every grid.
+struct BallTables {
+  std::vector<int32_t> packed;             // all codes concatenated
+  int start[kMaxRadiusCode + 2] = {0};
+  int count[kMaxRadiusCode + 2] = {0};
+  void build(int ndim, int max_code);
+};
+
+// Derivative operators of the boundary conditions, as sums of d^beta terms.
+struct OpTerm {
+  int8_t beta[3];
+  int8_t normal_axis;   // -1: plain coefficient; else multiplied by normal[normal_axis]
+  double coef;
+};
+struct OpSet {
+  int nops;
+  int nterms[kMaxOps];
+  OpTerm term[kMaxOps][kMaxOpTerms];
+};
+OpSet make_ops(int surface, int Mb, int ndim);
+
+int n_terms(int M, int ndim);
+void multi_indices(int M, int ndim, std::vector<int8_t> &out);   // [nterms][3]
+void second_derivative_weights(int M, double *w);                 // offsets -M/2..M/2
+
+}  // namespace ib
+
+struct ib_weights {
+  int device = 0;
+  int ndim = 3;
+  int64_t nx = 1, ny = 1, nz = 1, N = 0;
+  double h = 1.0;
+  ib_params prm{};
+  int M = 8;
+  int64_t pitch = 0;               // padded x extent of the state's wavefields
+  // geometry (device)
+  double *Hs = nullptr;            // heights in grid units [ny][nx]
+  uint8_t *node_class = nullptr;   // [N]
+  int64_t nb = 0;
+  double *bp = nullptr;            // [nb][8]: host x,y,z, x_b x,y,z, (normal kept below)
+  double *bp_normal = nullptr;     // [nb][3]
+  // IB points (device)
+  int64_t nib = 0;
+  int64_t *ib_node = nullptr;      // memory-order node index [nib]
+  int16_t *ib_xyz = nullptr;       // [nib][4] x, y, z, radius code
+  int32_t *ib_meta = nullptr;      // [nib][4] k, Mb, nw, woff
+  double *ib_sigma = nullptr;      // [nib]
+  int64_t sumw = 0;
+  double *w64 = nullptr;           // [sumw]
+  // stencil records used by the patch kernels: per point, the data-membership bit mask
+  // of its support ball followed by the weights, in 32-bit units.
+  uint32_t *rec32 = nullptr;
+  uint32_t *rec64 = nullptr;
+  uint32_t *rec_off32 = nullptr;   // [nib] offsets in 32-bit units
+  uint32_t *rec_off64 = nullptr;
+  int64_t rec32_words = 0, rec64_words = 0;
+  int32_t *ball = nullptr;         // packed ball tables
+  int32_t *ball_meta = nullptr;    // [code][2] start, count (device)
+  ib::BallTables balls;
+  int max_code = 0;
+  ib_stats stats{};
+};

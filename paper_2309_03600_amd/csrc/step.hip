@@ -1,0 +1,362 @@
+// Time-stepping kernels of the second-order pressure form.
+//
+// One step (section "Application to the 2nd-Order Acoustic Wave Equation", with the
+// damping layer as a separable addition):
+//   p^{n+1} = [2 p^n - (1 - s) p^{n-1} + K (L p^n) + dt^2 f^n] / (1 + s)
+// split into
+//   k_interior*  standard cross stencil at every node (exterior nodes have K = 0 and
+//                stay zero), written over p^{n-1};
+//   k_patch      at every IB point adds K/(1+s) * sum_j y_j p^n_j, the extrapolation
+//                part of the modified Laplacian (the exterior values the interior
+//                stencil reads are zero, so the standard part is already complete);
+//   k_inject     point sources (also advances the device step counter);
+//   k_sample     receivers.
+#include <hip/hip_runtime.h>
+
+#include "ib_internal.h"
+#include "step.h"
+
+namespace ib {
+
+
+template <typename T>
+struct StencilW {
+  T w[kMaxOrder / 2 + 1];   // w[0] centre, w[k] offset +-k
+};
+
+__device__ __forceinline__ int wrapk(int i, int n) {
+  return i < 0 ? i + n : (i >= n ? i - n : i);
+}
+
+// XCD-aware block order: the hardware deals consecutive workgroups to the 8 XCDs in
+// turn; remap so that each XCD walks a contiguous range of tiles (shared halos in its L2).
+// ``nblk`` (the launched grid) must be a multiple of 8 so that the map is a permutation.
+__device__ __forceinline__ int64_t xcd_remap(int64_t b, int64_t nblk) {
+  int64_t per = (nblk + 7) / 8;
+  return (b % 8) * per + b / 8;
+}
+
+// ---- 3D interior: xy tile in LDS, register queue along z ---------------------------
+template <typename T, int H, int RY>
+__launch_bounds__(256)
+__global__ void k_interior3d(const T *__restrict__ un, T *__restrict__ um, const T *__restrict__ K,
+                             const T *__restrict__ sx, const T *__restrict__ sy, const T *__restrict__ sz,
+                             StencilW<T> W, int nx, int ny, int nz, int64_t pitch, int64_t vol, int zchunk,
+                             int ntx, int nty, int nzc, int nshots) {
+  constexpr int TX = 64, TY = 4 * RY, LX = TX + 2 * H, LY = TY + 2 * H;
+  __shared__ T tile[LY][LX];
+  const int64_t nblk = (int64_t)ntx * nty * nzc * nshots;
+  const int64_t nblk8 = ((nblk + 7) / 8) * 8;
+  int64_t L = xcd_remap(blockIdx.x, nblk8);
+  if (L >= nblk) return;
+  const int bxi = (int)(L % ntx);
+  L /= ntx;
+  const int byi = (int)(L % nty);
+  L /= nty;
+  const int bzi = (int)(L % nzc);
+  const int shot = (int)(L / nzc);
+  const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+  const int x0 = bxi * TX, y0 = byi * TY;
+  const int z0 = bzi * zchunk, z1 = min(nz, z0 + zchunk);
+  const int64_t plane = pitch * ny;
+  const T *u = un + (size_t)shot * vol;
+  T *o = um + (size_t)shot * vol;
+  const int xg = x0 + tx;
+  const int xw = xg % nx;
+  const bool xin = xg < nx;
+  int yw[RY];
+  bool yin[RY];
+#pragma unroll
+  for (int r = 0; r < RY; ++r) {
+    int yg = y0 + ty * RY + r;
+    yin[r] = yg < ny;
+    yw[r] = yg % ny;
+  }
+  T q[RY][2 * H + 1];
+#pragma unroll
+  for (int r = 0; r < RY; ++r) {
+#pragma unroll
+    for (int k = 0; k < 2 * H; ++k) {
+      int z = z0 - H + k;
+      q[r][k] = (z >= 0 && z < nz) ? u[(size_t)z * plane + (size_t)yw[r] * pitch + xw] : T(0);
+    }
+  }
+  // halo coordinates owned by this thread
+  const int t = threadIdx.x;
+  int hy_row[2], hy_x[2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i) {
+    int idx = t + i * 256;            // 2H rows x 64 columns (H <= 4)
+    int hr = idx / TX, hc = idx % TX;
+    int yg = (hr < H) ? y0 - H + hr : y0 + TY + (hr - H);
+    hy_row[i] = (hr < 2 * H) ? ((yg % ny) + ny) % ny : -1;
+    hy_x[i] = hc;
+  }
+  const bool xl = tx < H, xr = tx >= TX - H;
+  const int xh = xl ? ((x0 - H + tx) % nx + nx) % nx : (xr ? (x0 + TX + (tx - (TX - H))) % nx : 0);
+  const int lxh = xl ? tx : (xr ? TX + H + (tx - (TX - H)) : 0);
+  for (int z = z0; z < z1; ++z) {
+    const size_t zoff = (size_t)z * plane;
+    // next plane of the queue and the centre values of p^{n-1} and K (in flight early)
+    T nxt[RY], pm[RY], kk[RY];
+    const int zn = z + H;
+#pragma unroll
+    for (int r = 0; r < RY; ++r) {
+      nxt[r] = (zn < nz) ? u[(size_t)zn * plane + (size_t)yw[r] * pitch + xw] : T(0);
+      size_t c = zoff + (size_t)yw[r] * pitch + xw;
+      pm[r] = o[c];
+      kk[r] = K[c];
+    }
+#pragma unroll
+    for (int r = 0; r < RY; ++r) q[r][2 * H] = nxt[r];
+#pragma unroll
+    for (int r = 0; r < RY; ++r) tile[H + ty * RY + r][H + tx] = q[r][H];
+    if (xl || xr) {
+#pragma unroll
+      for (int r = 0; r < RY; ++r) tile[H + ty * RY + r][lxh] = u[zoff + (size_t)yw[r] * pitch + xh];
+    }
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+      if (hy_row[i] >= 0) {
+        int hr = (t + i * 256) / TX;
+        int ly = (hr < H) ? hr : TY + H + (hr - H);
+        int xx = (x0 + hy_x[i]) % nx;
+        tile[ly][H + hy_x[i]] = u[zoff + (size_t)hy_row[i] * pitch + xx];
+      }
+    }
+    __syncthreads();
+    const T sxz = sx[xw] + sz[z];
+#pragma unroll
+    for (int r = 0; r < RY; ++r) {
+      const int ly = H + ty * RY + r, lx = H + tx;
+      const T c = q[r][H];
+      T lap = T(3) * W.w[0] * c;
+#pragma unroll
+      for (int k = 1; k <= H; ++k)
+        lap += W.w[k] * ((tile[ly][lx - k] + tile[ly][lx + k]) + (tile[ly - k][lx] + tile[ly + k][lx]) +
+                         (q[r][H - k] + q[r][H + k]));
+      const T s = sxz + sy[yw[r]];
+      const T v = (T(2) * c - (T(1) - s) * pm[r] + kk[r] * lap) / (T(1) + s);
+      if (xin && yin[r]) o[zoff + (size_t)yw[r] * pitch + xw] = v;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < RY; ++r) {
+#pragma unroll
+      for (int k = 0; k < 2 * H; ++k) q[r][k] = q[r][k + 1];
+    }
+  }
+}
+
+// ---- generic interior (2D, or 3D with other orders): one thread per node ------------
+template <typename T, int H>
+__global__ void k_interior_generic(const T *__restrict__ un, T *__restrict__ um, const T *__restrict__ K,
+                                   const T *__restrict__ sx, const T *__restrict__ sy, const T *__restrict__ sz,
+                                   StencilW<T> W, int nx, int ny, int nz, int lat, int64_t pitch, int64_t vol,
+                                   int nshots) {
+  const int64_t per = (int64_t)nx * ny * nz;
+  int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= per * nshots) return;
+  const int shot = (int)(g / per);
+  int64_t i = g % per;
+  const int x = (int)(i % nx);
+  i /= nx;
+  const int y = (int)(i % ny);
+  const int z = (int)(i / ny);
+  const int64_t plane = pitch * ny;
+  const T *u = un + (size_t)shot * vol;
+  T *o = um + (size_t)shot * vol;
+  const size_t c = (size_t)z * plane + (size_t)y * pitch + x;
+  const T uc = u[c];
+  T lap = T(lat + 1) * W.w[0] * uc;
+  for (int k = 1; k <= H; ++k) {
+    T acc = u[(size_t)z * plane + (size_t)y * pitch + wrapk(x - k, nx)] +
+            u[(size_t)z * plane + (size_t)y * pitch + wrapk(x + k, nx)];
+    if (lat == 2)
+      acc += u[(size_t)z * plane + (size_t)wrapk(y - k, ny) * pitch + x] +
+             u[(size_t)z * plane + (size_t)wrapk(y + k, ny) * pitch + x];
+    if (z - k >= 0) acc += u[c - (size_t)k * plane];
+    if (z + k < nz) acc += u[c + (size_t)k * plane];
+    lap += W.w[k] * acc;
+  }
+  const T s = sx[x] + sy[y] + sz[z];
+  o[c] = (T(2) * uc - (T(1) - s) * o[c] + K[c] * lap) / (T(1) + s);
+}
+
+// ---- IB patch: one wavefront per IB point ------------------------------------------
+template <typename T>
+__launch_bounds__(256)
+__global__ void k_patch(const T *__restrict__ un, T *__restrict__ unew, const uint32_t *__restrict__ rec,
+                        const uint32_t *__restrict__ roff, const int16_t *__restrict__ xyz,
+                        const T *__restrict__ scale, const int32_t *__restrict__ ball,
+                        const int32_t *__restrict__ ball_meta, int64_t nib, int nx, int ny, int nz, int64_t pitch,
+                        int64_t vol, int nshots) {
+  const int lane = threadIdx.x & 63;
+  const int64_t blk = xcd_remap(blockIdx.x, gridDim.x);
+  const int64_t i = blk * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  if (i >= nib) return;
+  const int16_t *p = xyz + i * 4;
+  const int x = p[0], y = p[1], z = p[2], code = p[3];
+  const int nb = ball_meta[2 * code + 1];
+  const int32_t *bl = ball + ball_meta[2 * code];
+  const int nwords = (nb + 31) >> 5;
+  const uint32_t off = roff[i];
+  const uint32_t *m = rec + off;
+  const int wpad = (sizeof(T) == 8) ? ((nwords + 1) & ~1) : nwords;
+  const T *wts = reinterpret_cast<const T *>(rec + off + wpad);
+  const int64_t plane = pitch * ny;
+  const T sc = scale[i];
+  const size_t centre = (size_t)z * plane + (size_t)y * pitch + x;
+  for (int s = 0; s < nshots; ++s) {
+    const T *u = un + (size_t)s * vol;
+    T acc = T(0);
+    int base = 0;
+    for (int b0 = 0; b0 < nb; b0 += 64) {
+      const int b = b0 + lane;
+      const uint32_t word = (b < nb) ? m[b >> 5] : 0u;
+      const int bit = (word >> (b & 31)) & 1;
+      const unsigned long long bal = __ballot(bit);
+      if (bit) {
+        const int widx = base + __popcll(bal & ((1ull << lane) - 1ull));
+        const uint32_t v = (uint32_t)bl[b];
+        const int dx = (int8_t)(v & 255), dy = (int8_t)((v >> 8) & 255), dz = (int8_t)((v >> 16) & 255);
+        const size_t g = (size_t)(z + dz) * plane + (size_t)wrapk(y + dy, ny) * pitch + wrapk(x + dx, nx);
+        acc += wts[widx] * u[g];
+      }
+      base += __popcll(bal);
+    }
+    for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
+    if (lane == 0) unew[(size_t)s * vol + centre] += sc * acc;
+  }
+}
+
+// ---- sources and receivers ---------------------------------------------------------
+template <typename T>
+__global__ void k_inject(T *unew, const int64_t *sidx, const T *sw, int nshots, int64_t vol, const T *wavelet,
+                         int64_t wstride, int64_t *tcount) {
+  const int64_t t = tcount[0];
+  for (int e = threadIdx.x; e < nshots * 8; e += blockDim.x) {
+    int s = e >> 3;
+    int64_t idx = sidx[e];
+    if (idx >= 0) unew[(size_t)s * vol + idx] += wavelet[(size_t)s * wstride + t] * sw[e];
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    tcount[1] = t;
+    tcount[0] = t + 1;
+  }
+}
+
+template <typename T>
+__global__ void k_sample(const T *unew, const int64_t *ridx, const T *rw, int nrec, int nshots, int64_t vol,
+                         T *traces, int64_t nsteps, const int64_t *tcount) {
+  int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (int64_t)nrec * nshots) return;
+  const int s = (int)(e / nrec), r = (int)(e % nrec);
+  const int64_t tl = tcount[1] - tcount[2];
+  const T *u = unew + (size_t)s * vol;
+  T v = T(0);
+#pragma unroll
+  for (int c = 0; c < 8; ++c) {
+    int64_t idx = ridx[(size_t)r * 8 + c];
+    if (idx >= 0) v += rw[(size_t)r * 8 + c] * u[idx];
+  }
+  traces[((size_t)s * nsteps + tl) * nrec + r] = v;
+}
+
+// ---- launch helpers ----------------------------------------------------------------
+template <typename T>
+static StencilW<T> stencil_weights(int M) {
+  double w[2 * kMaxOrder + 1];
+  second_derivative_weights(M, w);
+  StencilW<T> W{};
+  for (int k = 0; k <= M / 2; ++k) W.w[k] = (T)w[M / 2 + k];
+  return W;
+}
+
+template <typename T>
+static void launch_interior(const StepArgs &a, hipStream_t st) {
+  const T *un = (const T *)a.un;
+  T *um = (T *)a.um;
+  const T *K = (const T *)a.K;
+  const T *sx = (const T *)a.sx, *sy = (const T *)a.sy, *sz = (const T *)a.sz;
+  if (a.ndim == 3 && a.M == 8) {
+    constexpr int RY = 4;
+    const int ntx = (a.nx + 63) / 64, nty = (a.ny + 4 * RY - 1) / (4 * RY);
+    const int zc = a.zchunk > 0 ? a.zchunk : a.nz;
+    const int nzc = (a.nz + zc - 1) / zc;
+    int64_t nblk = (int64_t)ntx * nty * nzc * a.nshots;
+    int64_t nblk8 = (nblk + 7) / 8 * 8;
+    hipLaunchKernelGGL((k_interior3d<T, 4, RY>), dim3((unsigned)nblk8), dim3(256), 0, st, un, um, K, sx, sy, sz,
+                       stencil_weights<T>(a.M), a.nx, a.ny, a.nz, a.pitch, a.vol, zc, ntx, nty, nzc, a.nshots);
+    return;
+  }
+  const int64_t tot = (int64_t)a.nx * a.ny * a.nz * a.nshots;
+  dim3 g((unsigned)((tot + 255) / 256)), b(256);
+  const int lat = a.ndim - 1;
+  switch (a.M) {
+    case 2:
+      hipLaunchKernelGGL((k_interior_generic<T, 1>), g, b, 0, st, un, um, K, sx, sy, sz, stencil_weights<T>(2), a.nx,
+                         a.ny, a.nz, lat, a.pitch, a.vol, a.nshots);
+      break;
+    case 4:
+      hipLaunchKernelGGL((k_interior_generic<T, 2>), g, b, 0, st, un, um, K, sx, sy, sz, stencil_weights<T>(4), a.nx,
+                         a.ny, a.nz, lat, a.pitch, a.vol, a.nshots);
+      break;
+    case 6:
+      hipLaunchKernelGGL((k_interior_generic<T, 3>), g, b, 0, st, un, um, K, sx, sy, sz, stencil_weights<T>(6), a.nx,
+                         a.ny, a.nz, lat, a.pitch, a.vol, a.nshots);
+      break;
+    default:
+      hipLaunchKernelGGL((k_interior_generic<T, 4>), g, b, 0, st, un, um, K, sx, sy, sz, stencil_weights<T>(8), a.nx,
+                         a.ny, a.nz, lat, a.pitch, a.vol, a.nshots);
+      break;
+  }
+}
+
+template <typename T>
+static void launch_step(const StepArgs &a, hipStream_t st) {
+  launch_interior<T>(a, st);
+  if (a.nib > 0) {
+    int64_t nblk = ((a.nib + 3) / 4 + 7) / 8 * 8;
+    hipLaunchKernelGGL(k_patch<T>, dim3((unsigned)nblk), dim3(256), 0, st, (const T *)a.un, (T *)a.um, a.rec,
+                       a.roff, a.xyz, (const T *)a.scale, a.ball, a.ball_meta, a.nib, a.nx, a.ny, a.nz, a.pitch,
+                       a.vol, a.nshots);
+  }
+  hipLaunchKernelGGL(k_inject<T>, dim3(1), dim3(256), 0, st, (T *)a.um, a.sidx, (const T *)a.sw, a.nshots, a.vol,
+                     (const T *)a.wavelet, a.wstride, a.tcount);
+  if (a.nrec > 0 && a.traces) {
+    int64_t tot = (int64_t)a.nrec * a.nshots;
+    hipLaunchKernelGGL(k_sample<T>, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, (const T *)a.um, a.ridx,
+                       (const T *)a.rw, a.nrec, a.nshots, a.vol, (T *)a.traces, a.nsteps, (const int64_t *)a.tcount);
+  }
+}
+
+void enqueue_step(const StepArgs &a, hipStream_t st) {
+  if (a.prec == IB_F32)
+    launch_step<float>(a, st);
+  else
+    launch_step<double>(a, st);
+}
+
+void enqueue_interior_only(const StepArgs &a, hipStream_t st) {
+  if (a.prec == IB_F32)
+    launch_interior<float>(a, st);
+  else
+    launch_interior<double>(a, st);
+}
+
+void enqueue_patch_only(const StepArgs &a, hipStream_t st) {
+  if (a.nib <= 0) return;
+  int64_t nblk = ((a.nib + 3) / 4 + 7) / 8 * 8;
+  if (a.prec == IB_F32)
+    hipLaunchKernelGGL(k_patch<float>, dim3((unsigned)nblk), dim3(256), 0, st, (const float *)a.un, (float *)a.um,
+                       a.rec, a.roff, a.xyz, (const float *)a.scale, a.ball, a.ball_meta, a.nib, a.nx, a.ny, a.nz,
+                       a.pitch, a.vol, a.nshots);
+  else
+    hipLaunchKernelGGL(k_patch<double>, dim3((unsigned)nblk), dim3(256), 0, st, (const double *)a.un, (double *)a.um,
+                       a.rec, a.roff, a.xyz, (const double *)a.scale, a.ball, a.ball_meta, a.nib, a.nx, a.ny, a.nz,
+                       a.pitch, a.vol, a.nshots);
+}
+
+}  // namespace ib

@@ -1,0 +1,755 @@
+// Batched FP64 modified-stencil solves: one workgroup per immersed-boundary point.
+//
+// For IB point i (section "Approximating Boundary Conditions"):
+//   rows of A = Taylor rows a(g - i) of the data nodes g in the ball |g - i| <= r
+//               (interior and not eta-excluded), then, for every boundary point x_b
+//               with |x_b - i| <= r, one row per boundary condition: the condition's
+//               derivative operator applied to a, evaluated at x_b - i;
+//   accept when rank(A) equals the number of basis terms, else grow r by one cell, and
+//   after max_radius_steps growths drop the basis order (reading of the rank rule);
+//   weights (section "Reconciliation with the Interior Numerical Discretization"):
+//               y = (A^+)^T c with c = sum over exterior cross-stencil nodes e of
+//               w_e a(e - i); kept for the data rows (g = 0 drops the others).
+//
+// GPU formulation (differs from the oracle's SVD / pseudoinverse, same mathematics):
+//   A is never stored.  Its rows are generated chunk by chunk in LDS and folded into
+//   the triangular factor R (A = QR) by Householder reflections of [R; chunk]; R stays
+//   resident in LDS (packed upper triangle, 109.6 KB for 165 terms).  The numerical
+//   rank test compares sigma_min(R) (inverse iteration) with tol * sigma_max(R) (power
+//   iteration).  For full column rank (A^+)^T c = A (A^T A)^{-1} c = A R^{-1} R^{-T} c:
+//   two triangular solves, then one dot product per data row with its regenerated
+//   Taylor row.  This is the seminormal-equation form of the minimum-norm solution of
+//   A^T y = c, which is stable when R comes from an orthogonal factorisation.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+
+#include "ib_internal.h"
+
+namespace ib {
+
+struct SolveConst {
+  int8_t exps[kMaxTerms][3];
+  double w2[2 * kMaxOrder + 1];
+  OpSet ops;
+};
+__constant__ SolveConst c_solve;
+
+struct SolveArgs {
+  const uint8_t *cls;
+  const double *bp;        // [nb][8]
+  const double *bpn;       // [nb][3]
+  const int64_t *col_off;  // [ncol + 1]
+  const int64_t *ib_node;
+  const int32_t *pending;  // IB point ids of this launch
+  int npend;
+  int nx, ny, nz, lat;
+  int NT, Mb, M, nops;
+  const int32_t *ball;     // offsets of this radius
+  int nball, nwords;
+  double r2;               // r^2
+  int Rc;                  // lateral column search half-width for boundary points
+  double rtol;
+  int chunk;
+  // per-slot scratch
+  int32_t *desc;
+  int desc_stride;
+  double *bprel;           // [slot][maxbp][6]
+  int maxbp;
+  // outputs indexed by position in ``pending`` (+ base)
+  int out_base;
+  double *wout;            // [pos][nball]
+  uint32_t *mout;          // [pos][nwords]
+  int32_t *status;         // [pos]: 1 accepted, 0 rank deficient, -1 overflow
+  int32_t *ndata;          // [pos]
+  double *sigma;           // [pos] sigma_min / sigma_max
+};
+
+__device__ __forceinline__ int wrapd(int i, int n) {
+  int r = i % n;
+  return r < 0 ? r + n : r;
+}
+
+__device__ __forceinline__ double block_sum(double v, double *red) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) red[wv] = v;
+  __syncthreads();
+  double t = 0.0;
+  for (int i = 0; i < (int)(blockDim.x >> 6); ++i) t += red[i];
+  return t;
+}
+
+// exclusive position of this thread's flag within the block, and the block total
+__device__ __forceinline__ int block_scan(int flag, int *wtot, int &total) {
+  unsigned long long m = __ballot(flag);
+  int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  int pre = __popcll(m & ((1ull << lane) - 1ull));
+  __syncthreads();
+  if (lane == 0) wtot[wv] = __popcll(m);
+  __syncthreads();
+  int base = 0;
+  total = 0;
+  for (int i = 0; i < (int)(blockDim.x >> 6); ++i) {
+    if (i < wv) base += wtot[i];
+    total += wtot[i];
+  }
+  return base + pre;
+}
+
+__device__ __forceinline__ int ridx(int i, int j, int NT) {  // packed upper triangle, row-major
+  return i * NT - (i * (i - 1)) / 2 + (j - i);
+}
+
+__launch_bounds__(256)
+__global__ void k_solve(SolveArgs a) {
+  extern __shared__ double smem[];
+  const int NT = a.NT;
+  const int nb = a.chunk;
+  const int tid = threadIdx.x;
+  const int nth = blockDim.x;
+  const int D1 = a.Mb + 1;
+  double *R = smem;                                   // NT(NT+1)/2
+  double *C = R + NT * (NT + 1) / 2;                  // nb x NT
+  double *pw = C + nb * NT;                           // nb x 3 x D1
+  double *nrm = pw + nb * 3 * D1;                     // nb x 3
+  double *alpha = nrm + nb * 3;                       // NT
+  double *vzero = alpha + NT;                         // NT
+  double *red = vzero + NT;                           // 16
+  int *iscr = (int *)(red + 16);                      // 16 ints
+  __shared__ int rowop[64];
+  __shared__ int rowbp[64];
+
+  const int pos = blockIdx.x;
+  const int slot = blockIdx.x;
+  if (pos >= a.npend) return;
+  const int out = a.out_base + pos;
+  const int64_t node = a.ib_node[a.pending[pos]];
+  const int x0 = (int)(node % a.nx);
+  const int64_t rr = node / a.nx;
+  const int y0 = (int)(rr % a.ny);
+  const int z0 = (int)(rr / a.ny);
+  int32_t *desc = a.desc + (size_t)slot * a.desc_stride;
+  double *bpr = a.bprel + (size_t)slot * a.maxbp * 6;
+  uint32_t *mask = a.mout + (size_t)out * a.nwords;
+
+  // ---- data rows: ball lattice points that are interior and not excluded ----------
+  int ndata = 0;
+  for (int b0 = 0; b0 < a.nball; b0 += nth) {
+    int b = b0 + tid;
+    int flag = 0;
+    if (b < a.nball) {
+      uint32_t v = (uint32_t)a.ball[b];
+      int dx = (int8_t)(v & 255), dy = (int8_t)((v >> 8) & 255), dz = (int8_t)((v >> 16) & 255);
+      int zz = z0 + dz;
+      if (zz >= 0 && zz < a.nz) {
+        int64_t g = ((int64_t)zz * a.ny + wrapd(y0 + dy, a.ny)) * a.nx + wrapd(x0 + dx, a.nx);
+        uint8_t c = a.cls[g];
+        flag = ((c & 1) && !(c & 2)) ? 1 : 0;
+      }
+    }
+    int total;
+    int p = block_scan(flag, iscr, total);
+    if (flag) desc[ndata + p] = b;
+    unsigned long long bal = __ballot(flag);
+    int lane = tid & 63;
+    if (lane == 0 && b < a.nball) mask[b >> 5] = (uint32_t)(bal & 0xffffffffull);
+    if (lane == 32 && b < a.nball) mask[b >> 5] = (uint32_t)(bal >> 32);
+    ndata += total;
+  }
+  // ---- boundary points within the radius --------------------------------------------
+  int nbp = 0;
+  const int side = 2 * a.Rc + 1;
+  const int ncols = (a.lat == 2) ? side * side : side;
+  for (int c0 = 0; c0 < ncols; c0 += nth) {
+    int cidx = c0 + tid;
+    int cnt = 0;
+    int64_t j0 = 0, j1 = 0;
+    if (cidx < ncols) {
+      int dx = cidx % side - a.Rc;
+      int dy = (a.lat == 2) ? cidx / side - a.Rc : 0;
+      int64_t col = (int64_t)wrapd(y0 + dy, a.ny) * a.nx + wrapd(x0 + dx, a.nx);
+      j0 = a.col_off[col];
+      j1 = a.col_off[col + 1];
+      for (int64_t j = j0; j < j1; ++j) {
+        const double *p = a.bp + j * 8 + 3;
+        double rx = p[0] - x0, ry = p[1] - y0, rz = p[2] - z0;
+        rx -= a.nx * rint(rx / a.nx);
+        if (a.lat == 2) ry -= a.ny * rint(ry / a.ny);
+        if (rx * rx + ry * ry + rz * rz <= a.r2) ++cnt;
+      }
+    }
+    // exclusive scan of counts (small: serial over waves via LDS)
+    __syncthreads();
+    __shared__ int cnts[256];
+    cnts[tid] = cnt;
+    __syncthreads();
+    if (tid == 0) {
+      int s = 0;
+      for (int i = 0; i < nth; ++i) {
+        int t = cnts[i];
+        cnts[i] = s;
+        s += t;
+      }
+      iscr[8] = s;
+    }
+    __syncthreads();
+    int w = nbp + cnts[tid];
+    int tot = iscr[8];
+    if (cnt > 0) {
+      for (int64_t j = j0; j < j1; ++j) {
+        const double *p = a.bp + j * 8 + 3;
+        double rx = p[0] - x0, ry = p[1] - y0, rz = p[2] - z0;
+        rx -= a.nx * rint(rx / a.nx);
+        if (a.lat == 2) ry -= a.ny * rint(ry / a.ny);
+        if (rx * rx + ry * ry + rz * rz <= a.r2) {
+          if (w < a.maxbp) {
+            double *q = bpr + (size_t)w * 6;
+            q[0] = rx;
+            q[1] = ry;
+            q[2] = rz;
+            q[3] = a.bpn[j * 3 + 0];
+            q[4] = a.bpn[j * 3 + 1];
+            q[5] = a.bpn[j * 3 + 2];
+          }
+          ++w;
+        }
+      }
+    }
+    nbp += tot;
+    __syncthreads();
+  }
+  if (nbp > a.maxbp || ndata > a.desc_stride) {
+    if (tid == 0) {
+      a.status[out] = -1;
+      a.ndata[out] = ndata;
+    }
+    return;
+  }
+  const int m = ndata + nbp * a.nops;
+  if (m < NT) {
+    if (tid == 0) {
+      a.status[out] = 0;
+      a.ndata[out] = ndata;
+      a.sigma[out] = 0.0;
+    }
+    return;
+  }
+  __threadfence_block();
+  __syncthreads();
+
+  // ---- streamed Householder QR of A into R ------------------------------------------
+  for (int i = tid; i < NT * (NT + 1) / 2; i += nth) R[i] = 0.0;
+  __syncthreads();
+  for (int r0 = 0; r0 < m; r0 += nb) {
+    const int nr = min(nb, m - r0);
+    // row kinds and per-row power tables  delta_n^k / k!
+    if (tid < nr) {
+      int r = r0 + tid;
+      double d[3];
+      if (r < ndata) {
+        uint32_t v = (uint32_t)a.ball[desc[r]];
+        d[0] = (int8_t)(v & 255);
+        d[1] = (int8_t)((v >> 8) & 255);
+        d[2] = (int8_t)((v >> 16) & 255);
+        rowop[tid] = -1;
+        nrm[tid * 3 + 0] = nrm[tid * 3 + 1] = nrm[tid * 3 + 2] = 0.0;
+      } else {
+        int rb = r - ndata;
+        int bi = rb / a.nops;
+        rowop[tid] = rb % a.nops;
+        rowbp[tid] = bi;
+        const double *q = bpr + (size_t)bi * 6;
+        d[0] = q[0];
+        d[1] = q[1];
+        d[2] = q[2];
+        nrm[tid * 3 + 0] = q[3];
+        nrm[tid * 3 + 1] = q[4];
+        nrm[tid * 3 + 2] = q[5];
+      }
+      for (int n = 0; n < 3; ++n) {
+        double *t = pw + (tid * 3 + n) * D1;
+        t[0] = 1.0;
+        for (int k = 1; k < D1; ++k) t[k] = t[k - 1] * d[n] / (double)k;
+      }
+    }
+    __syncthreads();
+    for (int e = tid; e < nr * NT; e += nth) {
+      int i = e / NT, t = e - (e / NT) * NT;
+      const int8_t *ex = c_solve.exps[t];
+      const double *p = pw + i * 3 * D1;
+      double v;
+      int op = rowop[i];
+      if (op < 0) {
+        v = p[ex[0]] * p[D1 + ex[1]] * p[2 * D1 + ex[2]];
+      } else {
+        v = 0.0;
+        int nt_ = c_solve.ops.nterms[op];
+        for (int q = 0; q < nt_; ++q) {
+          const OpTerm &T = c_solve.ops.term[op][q];
+          int a0 = ex[0] - T.beta[0], a1 = ex[1] - T.beta[1], a2 = ex[2] - T.beta[2];
+          if (a0 < 0 || a1 < 0 || a2 < 0) continue;
+          double cf = T.coef;
+          if (T.normal_axis >= 0) cf *= nrm[i * 3 + T.normal_axis];
+          v += cf * p[a0] * p[D1 + a1] * p[2 * D1 + a2];
+        }
+      }
+      C[i * NT + t] = v;
+    }
+    __syncthreads();
+    // reflector scalars of column 0 (wave 0), then one barrier per column
+    if (tid < 64) {
+      double s = 0.0;
+      for (int i = tid; i < nr; i += 64) s += C[i * NT] * C[i * NT];
+      for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
+      if (tid == 0) {
+        double rkk = R[0];
+        if (s == 0.0) {
+          alpha[0] = rkk;
+          vzero[0] = 0.0;
+        } else {
+          double nn = sqrt(rkk * rkk + s);
+          double al = (rkk >= 0.0) ? -nn : nn;
+          alpha[0] = al;
+          vzero[0] = rkk - al;
+        }
+      }
+    }
+    __syncthreads();
+    for (int k = 0; k < NT; ++k) {
+      const double al = alpha[k], v0 = vzero[k];
+      const bool skip = (v0 == 0.0);
+      const int j = k + 1 + tid;
+      if (j < NT) {
+        double rkj = R[ridx(k, j, NT)];
+        double nsq = 0.0;
+        if (!skip) {
+          double s = v0 * rkj;
+          for (int i = 0; i < nr; ++i) s += C[i * NT + k] * C[i * NT + j];
+          double f = s / (al * v0);
+          rkj += f * v0;
+          R[ridx(k, j, NT)] = rkj;
+          for (int i = 0; i < nr; ++i) {
+            double c = C[i * NT + j] + f * C[i * NT + k];
+            C[i * NT + j] = c;
+            nsq += c * c;
+          }
+        } else {
+          for (int i = 0; i < nr; ++i) nsq += C[i * NT + j] * C[i * NT + j];
+        }
+        if (j == k + 1) {   // scalars of the next column, from its updated entries
+          double rjj = R[ridx(j, j, NT)];
+          if (nsq == 0.0) {
+            alpha[j] = rjj;
+            vzero[j] = 0.0;
+          } else {
+            double nn = sqrt(rjj * rjj + nsq);
+            double a2 = (rjj >= 0.0) ? -nn : nn;
+            alpha[j] = a2;
+            vzero[j] = rjj - a2;
+          }
+        }
+      }
+      if (tid == 0) R[ridx(k, k, NT)] = al;
+      __syncthreads();
+    }
+  }
+
+  // ---- numerical rank: sigma_max by power iteration, sigma_min by inverse iteration --
+  double *xv = C;            // reuse the chunk buffer
+  double *yv = C + NT;
+  double *sv = C + 2 * NT;
+  const double inv_sqrt = 1.0 / sqrt((double)NT);
+  if (tid < NT) xv[tid] = inv_sqrt;
+  __syncthreads();
+  double smax2 = 0.0;
+  for (int it = 0; it < 10; ++it) {
+    if (tid < NT) {
+      double s = 0.0;
+      for (int j = tid; j < NT; ++j) s += R[ridx(tid, j, NT)] * xv[j];
+      yv[tid] = s;
+    }
+    __syncthreads();
+    double x2 = 0.0;
+    if (tid < NT) {
+      for (int i = 0; i <= tid; ++i) x2 += R[ridx(i, tid, NT)] * yv[i];
+    }
+    double nn = sqrt(block_sum(x2 * x2, red));
+    smax2 = nn;
+    if (tid < NT) xv[tid] = (nn > 0.0) ? x2 / nn : inv_sqrt;
+    __syncthreads();
+  }
+  // inverse iteration on R^T R; start from an alternating vector
+  double xi = (tid < NT) ? ((tid & 1) ? -inv_sqrt : inv_sqrt) : 0.0;
+  double smin2 = 0.0;
+  for (int it = 0; it < 10; ++it) {
+    // forward: R^T w = x (thread t owns x_t)
+    double xr = xi;
+    for (int k = 0; k < NT; ++k) {
+      if (tid == k) sv[k] = xr / R[ridx(k, k, NT)];
+      __syncthreads();
+      if (tid > k && tid < NT) xr -= R[ridx(k, tid, NT)] * sv[k];
+    }
+    __syncthreads();
+    double wr = (tid < NT) ? sv[tid] : 0.0;
+    __syncthreads();
+    // backward: R z = w (thread t owns w_t)
+    for (int k = NT - 1; k >= 0; --k) {
+      if (tid == k) yv[k] = wr / R[ridx(k, k, NT)];
+      __syncthreads();
+      if (tid < k) wr -= R[ridx(tid, k, NT)] * yv[k];
+    }
+    __syncthreads();
+    double z = (tid < NT) ? yv[tid] : 0.0;
+    double nn = sqrt(block_sum(z * z, red));
+    smin2 = (nn > 0.0) ? 1.0 / nn : 0.0;
+    xi = (tid < NT && nn > 0.0 && isfinite(nn)) ? z / nn : 0.0;
+    if (!(isfinite(nn))) {
+      smin2 = 0.0;
+      break;
+    }
+  }
+  const double smax = sqrt(smax2), smin = sqrt(smin2);
+  const double tol = (a.rtol > 0.0) ? a.rtol : (double)max(m, NT) * 2.220446049250313e-16;
+  const bool full = (smin > tol * smax) && isfinite(smin) && isfinite(smax) && smax > 0.0;
+  if (tid == 0) {
+    a.status[out] = full ? 1 : 0;
+    a.ndata[out] = ndata;
+    a.sigma[out] = (smax > 0.0) ? smin / smax : 0.0;
+  }
+  if (!full) return;
+
+  // ---- c = sum of w_e a(e - i) over exterior cross-stencil nodes ----------------------
+  double cv = 0.0;
+  if (tid < NT) {
+    const int8_t *ex = c_solve.exps[tid];
+    const int half = a.M / 2;
+    for (int n = 0; n < 3; ++n) {
+      if (a.lat == 1 && n == 1) continue;
+      // the term is a pure power of axis n (or the constant)
+      bool pure = true;
+      for (int q = 0; q < 3; ++q)
+        if (q != n && ex[q] != 0) pure = false;
+      if (!pure) continue;
+      for (int k = -half; k <= half; ++k) {
+        if (k == 0) continue;
+        int xx = x0, yy = y0, zz = z0;
+        if (n == 0) xx = wrapd(x0 + k, a.nx);
+        if (n == 1) yy = wrapd(y0 + k, a.ny);
+        if (n == 2) zz = z0 + k;
+        if (zz < 0 || zz >= a.nz) continue;
+        int64_t g = ((int64_t)zz * a.ny + yy) * a.nx + xx;
+        if (a.cls[g] & 1) continue;
+        double mono = 1.0;
+        for (int p = 1; p <= ex[n]; ++p) mono = mono * (double)k / (double)p;
+        cv += c_solve.w2[k + half] * mono;
+      }
+    }
+  }
+  // forward R^T w = c, backward R z = w
+  {
+    double xr = cv;
+    for (int k = 0; k < NT; ++k) {
+      if (tid == k) sv[k] = xr / R[ridx(k, k, NT)];
+      __syncthreads();
+      if (tid > k && tid < NT) xr -= R[ridx(k, tid, NT)] * sv[k];
+    }
+    __syncthreads();
+    double wr = (tid < NT) ? sv[tid] : 0.0;
+    __syncthreads();
+    for (int k = NT - 1; k >= 0; --k) {
+      if (tid == k) yv[k] = wr / R[ridx(k, k, NT)];
+      __syncthreads();
+      if (tid < k) wr -= R[ridx(tid, k, NT)] * yv[k];
+    }
+    __syncthreads();
+  }
+  // y_j = a_j . z for the data rows
+  double *wo = a.wout + (size_t)out * a.nball;
+  for (int j = tid; j < ndata; j += nth) {
+    uint32_t v = (uint32_t)a.ball[desc[j]];
+    double d[3] = {(double)(int8_t)(v & 255), (double)(int8_t)((v >> 8) & 255),
+                   (double)(int8_t)((v >> 16) & 255)};
+    double p[3][kMaxOrder + 1];
+    for (int n = 0; n < 3; ++n) {
+      p[n][0] = 1.0;
+      for (int k = 1; k < D1; ++k) p[n][k] = p[n][k - 1] * d[n] / (double)k;
+    }
+    double s = 0.0;
+    for (int t = 0; t < NT; ++t) {
+      const int8_t *ex = c_solve.exps[t];
+      s += p[0][ex[0]] * p[1][ex[1]] * p[2][ex[2]] * yv[t];
+    }
+    wo[j] = s;
+  }
+}
+
+// Gather accepted points of one round into the final tables.
+__global__ void k_pack(int nacc, const int32_t *acc_pos, const int32_t *acc_id, const double *wout, int nball,
+                       const uint32_t *mout, int nwords, const int32_t *woff, const int32_t *nw,
+                       const uint32_t *roff32, const uint32_t *roff64, double *w64, uint32_t *rec32,
+                       uint32_t *rec64) {
+  int a = blockIdx.x;
+  if (a >= nacc) return;
+  int pos = acc_pos[a], id = acc_id[a];
+  const double *src = wout + (size_t)pos * nball;
+  const uint32_t *msk = mout + (size_t)pos * nwords;
+  int n = nw[id];
+  uint32_t o32 = roff32[id], o64 = roff64[id];
+  int nw64 = (nwords + 1) & ~1;
+  for (int t = threadIdx.x; t < nwords; t += blockDim.x) rec32[o32 + t] = msk[t];
+  for (int t = threadIdx.x; t < nw64; t += blockDim.x) rec64[o64 + t] = (t < nwords) ? msk[t] : 0u;
+  float *f32 = reinterpret_cast<float *>(rec32 + o32 + nwords);
+  double *f64 = reinterpret_cast<double *>(rec64 + o64 + nw64);
+  for (int t = threadIdx.x; t < n; t += blockDim.x) {
+    double v = src[t];
+    w64[woff[id] + t] = v;
+    f32[t] = (float)v;
+    f64[t] = v;
+  }
+}
+
+struct RoundResult {
+  int code, k, Mb;
+  std::vector<int32_t> acc_pos, acc_id;
+  double *wout = nullptr;
+  uint32_t *mout = nullptr;
+  int nball = 0, nwords = 0;
+};
+
+ib_status weights_build(ib_weights *w, const int64_t *col_off_dev, hipStream_t st) {
+  const int ndim = w->ndim, lat = ndim - 1, M = w->M;
+  const int Kmax = w->prm.max_radius_steps;
+  const int min_order = w->prm.min_basis_order;
+  w->max_code = M + 1 + 2 * Kmax;
+  w->balls.build(ndim, w->max_code + 2);
+  ib_status s;
+  if ((s = dalloc_t(&w->ball, w->balls.packed.size()))) return s;
+  IB_HIP(hipMemcpyAsync(w->ball, w->balls.packed.data(), w->balls.packed.size() * 4, hipMemcpyHostToDevice, st));
+  {
+    std::vector<int32_t> bm(2 * (kMaxRadiusCode + 2), 0);
+    for (int c = 0; c <= kMaxRadiusCode + 1; ++c) {
+      bm[2 * c] = w->balls.start[c];
+      bm[2 * c + 1] = w->balls.count[c];
+    }
+    if ((s = dalloc_t(&w->ball_meta, bm.size()))) return s;
+    IB_HIP(hipMemcpy(w->ball_meta, bm.data(), bm.size() * 4, hipMemcpyHostToDevice));
+  }
+
+  const int64_t nib = w->nib;
+  std::vector<int32_t> pending(nib);
+  for (int64_t i = 0; i < nib; ++i) pending[i] = (int32_t)i;
+  std::vector<int32_t> fin_k(nib, -1), fin_Mb(nib, 0), fin_nw(nib, 0), fin_round(nib, -1);
+  std::vector<double> fin_sig(nib, 0.0);
+  std::vector<RoundResult> rounds;
+  int32_t *d_pending = nullptr, *d_status = nullptr, *d_ndata = nullptr, *desc = nullptr;
+  double *d_sigma = nullptr, *bprel = nullptr;
+  if ((s = dalloc_t(&d_pending, std::max<int64_t>(nib, 1))) || (s = dalloc_t(&d_status, std::max<int64_t>(nib, 1))) ||
+      (s = dalloc_t(&d_ndata, std::max<int64_t>(nib, 1))) || (s = dalloc_t(&d_sigma, std::max<int64_t>(nib, 1))))
+    return s;
+  std::vector<int8_t> ex;
+  multi_indices(M, ndim, ex);
+  SolveConst sc{};
+  for (size_t t = 0; t < ex.size() / 3; ++t)
+    for (int q = 0; q < 3; ++q) sc.exps[t][q] = ex[t * 3 + q];
+  second_derivative_weights(M, sc.w2);
+  double max_cond = 0.0, min_margin = INFINITY;
+  const double tol_base = 2.220446049250313e-16;
+  const int max_slots = 32768;
+  const int chunk = (ndim == 3) ? 24 : 48;
+
+  for (int Mb = M; Mb >= min_order && !pending.empty(); --Mb) {
+    const int NT = n_terms(Mb, ndim);
+    sc.ops = make_ops(w->prm.surface, Mb, ndim);
+    IB_HIP(hipMemcpyToSymbolAsync(HIP_SYMBOL(c_solve), &sc, sizeof(sc), 0, hipMemcpyHostToDevice, st));
+    for (int k = 0; k <= Kmax && !pending.empty(); ++k) {
+      const int code = Mb + 1 + 2 * k;
+      const double r = code / 2.0;
+      const int nball = w->balls.count[code];
+      const int nwords = (nball + 31) / 32;
+      const int maxbp = w->balls.count[std::min(code + 2, w->max_code + 2)] + 8;
+      const int npend = (int)pending.size();
+      RoundResult rr;
+      rr.code = code;
+      rr.k = k;
+      rr.Mb = Mb;
+      rr.nball = nball;
+      rr.nwords = nwords;
+      if ((s = dalloc_t(&rr.wout, (size_t)npend * nball)) || (s = dalloc_t(&rr.mout, (size_t)npend * nwords)))
+        return s;
+      IB_HIP(hipMemcpyAsync(d_pending, pending.data(), npend * 4, hipMemcpyHostToDevice, st));
+      const int slots = std::min(npend, max_slots);
+      const int desc_stride = nball;
+      dfree(desc);
+      dfree(bprel);
+      if ((s = dalloc_t(&desc, (size_t)slots * desc_stride)) || (s = dalloc_t(&bprel, (size_t)slots * maxbp * 6)))
+        return s;
+      SolveArgs A{};
+      A.cls = w->node_class;
+      A.bp = w->bp;
+      A.bpn = w->bp_normal;
+      A.col_off = col_off_dev;
+      A.ib_node = w->ib_node;
+      A.nx = (int)w->nx;
+      A.ny = (int)w->ny;
+      A.nz = (int)w->nz;
+      A.lat = lat;
+      A.NT = NT;
+      A.Mb = Mb;
+      A.M = M;
+      A.nops = sc.ops.nops;
+      A.ball = w->ball + w->balls.start[code];
+      A.nball = nball;
+      A.nwords = nwords;
+      A.r2 = r * r;
+      A.Rc = (int)floor(r + 0.5);
+      A.rtol = w->prm.rank_rtol;
+      A.chunk = chunk;
+      A.desc = desc;
+      A.desc_stride = desc_stride;
+      A.bprel = bprel;
+      A.maxbp = maxbp;
+      A.wout = rr.wout;
+      A.mout = rr.mout;
+      A.status = d_status;
+      A.ndata = d_ndata;
+      A.sigma = d_sigma;
+      const int D1 = Mb + 1;
+      size_t lds = sizeof(double) * ((size_t)NT * (NT + 1) / 2 + (size_t)chunk * NT + (size_t)chunk * 3 * D1 +
+                                     (size_t)chunk * 3 + 2 * NT + 16) +
+                   16 * sizeof(int);
+      IB_HIP(hipFuncSetAttribute((const void *)k_solve, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+      for (int b0 = 0; b0 < npend; b0 += slots) {
+        A.pending = d_pending + b0;
+        A.npend = std::min(slots, npend - b0);
+        A.out_base = b0;
+        hipLaunchKernelGGL(k_solve, dim3(A.npend), dim3(256), lds, st, A);
+        IB_HIP(hipGetLastError());
+      }
+      std::vector<int32_t> hs(npend), hn(npend);
+      std::vector<double> hsig(npend);
+      IB_HIP(hipMemcpyAsync(hs.data(), d_status, npend * 4, hipMemcpyDeviceToHost, st));
+      IB_HIP(hipMemcpyAsync(hn.data(), d_ndata, npend * 4, hipMemcpyDeviceToHost, st));
+      IB_HIP(hipMemcpyAsync(hsig.data(), d_sigma, npend * 8, hipMemcpyDeviceToHost, st));
+      IB_HIP(hipStreamSynchronize(st));
+      std::vector<int32_t> next;
+      for (int p = 0; p < npend; ++p) {
+        int id = pending[p];
+        if (hs[p] < 0) {
+          set_error("IB point %d: support scratch overflow (radius %.1f)", id, r);
+          return IB_ERR_ARG;
+        }
+        if (hs[p] == 1) {
+          fin_k[id] = k;
+          fin_Mb[id] = Mb;
+          fin_nw[id] = hn[p];
+          fin_round[id] = (int)rounds.size();
+          fin_sig[id] = hsig[p];
+          rr.acc_pos.push_back(p);
+          rr.acc_id.push_back(id);
+          max_cond = std::max(max_cond, 1.0 / hsig[p]);
+          (void)tol_base;
+        } else {
+          next.push_back(id);
+        }
+      }
+      rounds.push_back(std::move(rr));
+      pending.swap(next);
+    }
+  }
+  dfree(desc);
+  dfree(bprel);
+  dfree(d_pending);
+  dfree(d_status);
+  dfree(d_ndata);
+  if (!pending.empty()) {
+    dfree(d_sigma);
+    for (auto &rr : rounds) dfree(rr.wout), dfree(rr.mout);
+    set_error("%zu IB points remain rank deficient after radius growth and order reduction (first: node %d)",
+              pending.size(), pending[0]);
+    return IB_ERR_UNCONSTRAINED;
+  }
+  // offsets and final tables
+  std::vector<int32_t> woff(nib);
+  std::vector<uint32_t> roff32(nib), roff64(nib);
+  std::vector<int16_t> xyz(nib * 4);
+  std::vector<int32_t> meta(nib * 4);
+  std::vector<int64_t> hnode(nib);
+  IB_HIP(hipMemcpyAsync(hnode.data(), w->ib_node, nib * 8, hipMemcpyDeviceToHost, st));
+  IB_HIP(hipStreamSynchronize(st));
+  int64_t sw = 0, s32 = 0, s64 = 0;
+  int64_t maxnw = 0;
+  for (int64_t i = 0; i < nib; ++i) {
+    const RoundResult &rr = rounds[fin_round[i]];
+    woff[i] = (int32_t)sw;
+    roff32[i] = (uint32_t)s32;
+    roff64[i] = (uint32_t)s64;
+    sw += fin_nw[i];
+    s32 += rr.nwords + fin_nw[i];
+    s64 += ((rr.nwords + 1) & ~1) + 2 * (int64_t)fin_nw[i];
+    maxnw = std::max<int64_t>(maxnw, fin_nw[i]);
+    int64_t nd = hnode[i];
+    xyz[i * 4 + 0] = (int16_t)(nd % w->nx);
+    xyz[i * 4 + 1] = (int16_t)((nd / w->nx) % w->ny);
+    xyz[i * 4 + 2] = (int16_t)(nd / (w->nx * w->ny));
+    xyz[i * 4 + 3] = (int16_t)rr.code;
+    meta[i * 4 + 0] = fin_k[i];
+    meta[i * 4 + 1] = fin_Mb[i];
+    meta[i * 4 + 2] = fin_nw[i];
+    meta[i * 4 + 3] = woff[i];
+    w->stats.radius_hist[std::min(fin_k[i], 7)]++;
+    w->stats.order_hist[std::min(fin_Mb[i], 16)]++;
+    min_margin = std::min(min_margin, fin_sig[i] / (std::max<double>(fin_nw[i], 1) * tol_base));
+  }
+  if (s32 >= (int64_t)UINT32_MAX || s64 >= (int64_t)UINT32_MAX || sw >= (int64_t)INT32_MAX) {
+    set_error("stencil table too large (%lld weights)", (long long)sw);
+    return IB_ERR_ARG;
+  }
+  w->sumw = sw;
+  w->rec32_words = s32;
+  w->rec64_words = s64;
+  w->stats.sum_nw = sw;
+  w->stats.max_nw = maxnw;
+  w->stats.max_cond = max_cond;
+  w->stats.min_margin = min_margin;
+  w->stats.table_bytes_f32 = s32 * 4;
+  w->stats.table_bytes_f64 = s64 * 4;
+  if ((s = dalloc_t(&w->w64, std::max<int64_t>(sw, 1))) || (s = dalloc_t(&w->rec32, std::max<int64_t>(s32, 1))) ||
+      (s = dalloc_t(&w->rec64, std::max<int64_t>(s64, 1))) || (s = dalloc_t(&w->rec_off32, std::max<int64_t>(nib, 1))) ||
+      (s = dalloc_t(&w->rec_off64, std::max<int64_t>(nib, 1))) || (s = dalloc_t(&w->ib_xyz, std::max<int64_t>(nib, 1) * 4)) ||
+      (s = dalloc_t(&w->ib_meta, std::max<int64_t>(nib, 1) * 4)) || (s = dalloc_t(&w->ib_sigma, std::max<int64_t>(nib, 1))))
+    return s;
+  int32_t *d_woff = nullptr, *d_nw = nullptr, *d_apos = nullptr, *d_aid = nullptr;
+  if ((s = dalloc_t(&d_woff, std::max<int64_t>(nib, 1))) || (s = dalloc_t(&d_nw, std::max<int64_t>(nib, 1))) ||
+      (s = dalloc_t(&d_apos, std::max<int64_t>(nib, 1))) || (s = dalloc_t(&d_aid, std::max<int64_t>(nib, 1))))
+    return s;
+  IB_HIP(hipMemcpyAsync(d_woff, woff.data(), nib * 4, hipMemcpyHostToDevice, st));
+  IB_HIP(hipMemcpyAsync(d_nw, fin_nw.data(), nib * 4, hipMemcpyHostToDevice, st));
+  IB_HIP(hipMemcpyAsync(w->rec_off32, roff32.data(), nib * 4, hipMemcpyHostToDevice, st));
+  IB_HIP(hipMemcpyAsync(w->rec_off64, roff64.data(), nib * 4, hipMemcpyHostToDevice, st));
+  IB_HIP(hipMemcpyAsync(w->ib_xyz, xyz.data(), nib * 8, hipMemcpyHostToDevice, st));
+  IB_HIP(hipMemcpyAsync(w->ib_meta, meta.data(), nib * 16, hipMemcpyHostToDevice, st));
+  IB_HIP(hipMemcpyAsync(w->ib_sigma, fin_sig.data(), nib * 8, hipMemcpyHostToDevice, st));
+  for (auto &rr : rounds) {
+    int nacc = (int)rr.acc_pos.size();
+    if (nacc) {
+      IB_HIP(hipMemcpyAsync(d_apos, rr.acc_pos.data(), nacc * 4, hipMemcpyHostToDevice, st));
+      IB_HIP(hipMemcpyAsync(d_aid, rr.acc_id.data(), nacc * 4, hipMemcpyHostToDevice, st));
+      hipLaunchKernelGGL(k_pack, dim3(nacc), dim3(256), 0, st, nacc, d_apos, d_aid, rr.wout, rr.nball, rr.mout,
+                         rr.nwords, d_woff, d_nw, w->rec_off32, w->rec_off64, w->w64, w->rec32, w->rec64);
+      IB_HIP(hipGetLastError());
+      IB_HIP(hipStreamSynchronize(st));
+    }
+    dfree(rr.wout);
+    dfree(rr.mout);
+    w->stats.max_ball = std::max<int64_t>(w->stats.max_ball, rr.nball);
+  }
+  IB_HIP(hipStreamSynchronize(st));
+  dfree(d_woff), dfree(d_nw), dfree(d_apos), dfree(d_aid), dfree(d_sigma);
+  return IB_OK;
+}
+
+}  // namespace ib

@@ -1,0 +1,49 @@
+"""Test helpers: build oracle results for a workload (CPU, FP64), in parallel."""
+import multiprocessing as mp
+import os
+
+import numpy as np
+
+from oracle import stepper
+from oracle.weights import IBModel
+
+_MODEL = None
+
+
+def model_for(wl, **kw):
+    return IBModel(wl.heights, wl.h, wl.shape, M=wl.M, surface=wl.surface, eta=wl.eta, **kw)
+
+
+def _solve_one(p):
+    s = _MODEL.solve_point(p)
+    return (tuple(int(v) for v in p), s)
+
+
+def solve_points(model, points=None, procs=None):
+    """{node tuple: solution}; forks a pool over the points."""
+    global _MODEL
+    pts = model.ib_points() if points is None else np.asarray(points)
+    if procs is None:
+        procs = min(16, os.cpu_count() or 1)
+    if len(pts) < 64 or procs <= 1:
+        return {tuple(int(v) for v in p): model.solve_point(p) for p in pts}
+    _MODEL = model
+    ctx = mp.get_context("fork")
+    with ctx.Pool(procs) as pool:
+        res = pool.map(_solve_one, list(pts), chunksize=max(1, len(pts) // (procs * 8)))
+    _MODEL = None
+    return dict(res)
+
+
+def simulation(wl, model, sols):
+    L = stepper.assemble_laplacian(model, sols)
+    return stepper.Simulation(model, L, wl.vel, wl.dt, wl.src, wl.rec, damp_width=wl.damp_width,
+                              damp_R=wl.damp_R), L
+
+
+def rel_l2_per_trace(d, ref, floor=1e-3):
+    """Per-trace ||d - ref|| / max(||ref||, floor * max_r ||ref||) over axis 0 = time."""
+    num = np.linalg.norm(d - ref, axis=0)
+    den = np.linalg.norm(ref, axis=0)
+    den = np.maximum(den, floor * den.max())
+    return num / den
