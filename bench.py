@@ -1,0 +1,211 @@
+"""Benchmark of the 3D eighth-order immersed-boundary step on one MI355X.
+
+Workload: 401 x 401 x 301 grid, 10 m, space order 8, seeded fractal free surface
+(spectral exponent -2, 300 m relief), depth-gradient velocity with a 5 % random
+perturbation, 40-cell damping layer, one Ricker 10 Hz source, 201 x 201 receivers.
+A step is one pass of the hot path: interior stencil + damping, IB patch, source
+injection, receiver sampling.  Inputs are generated on the host, the stencil table is
+built on the GPU, then W warm-up steps and K timed steps run with every input resident
+in HBM.  Prints one JSON line.
+
+Roofline: HIP events (torch.cuda.Event on the stream the library launches on) time
+each kernel over its own launches; algorithmic bytes per launch are
+  interior: 16 B per grid node (FP32; read p^n, p^{n-1}, K; write p^{n+1}), 32 B FP64;
+  IB patch: 4 B per weight + 13 B per IB point (FP32), 8 B per weight + 21 B (FP64).
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for f in ("step.hip", "step.h"):
+        h.update(open(os.path.join(ROOT, "paper_2309_03600_amd", "csrc", f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def load_traffic():
+    """HBM bytes per launch measured with rocprofv3 counters (profiles/traffic.json),
+    valid only for the kernel source they were taken on."""
+    p = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(p):
+        return {}
+    d = json.load(open(p))
+    if d.get("source_hash") != kernel_source_hash():
+        return {}
+    return d.get("kernels", {})
+
+
+def time_kernel(st, which, count, torch):
+    s = torch.cuda.current_stream()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    st.run_kernel(which, 2)                      # warm
+    e0.record(s)
+    st.run_kernel(which, count)
+    e1.record(s)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / count           # ms per launch
+
+
+def cpu_baseline(budget_steps=200):
+    """The FP64 oracle on a bounded sample: a 24 x 24 x 301 grid with the same recipe
+    (fractal free surface, M = 8, damping), weights from a process pool (untimed), then
+    ``budget_steps`` oracle steps timed on one core."""
+    from paper_2309_03600_amd import workloads as W
+    sys.path.insert(0, os.path.join(ROOT, "tests"))
+    from oracle_cases import model_for, simulation, solve_points
+    wl = W.small3d(cfg=95, n=24, nz=301, relief=50.0, nt=budget_steps, z_top_cells=20)
+    t0 = time.time()
+    m = model_for(wl)
+    sols = solve_points(m, procs=min(16, os.cpu_count() or 1))
+    sim, _ = simulation(wl, m, sols)
+    t_build = time.time() - t0
+    wav = wl.wavelets(np.float64)
+    t0 = time.perf_counter()
+    sim.run(wav, budget_steps)
+    t = time.perf_counter() - t0
+    npts = int(np.prod(wl.shape))
+    return {"value": npts * budget_steps / t / 1e9, "unit": "Gpts/s", "cores": 1, "kind": "oracle",
+            "sample": f"oracle FP64 stepping of a {wl.shape[0]}x{wl.shape[1]}x{wl.shape[2]} grid "
+                      f"(same recipe, {len(sols)} IB points) for {budget_steps} steps, {t:.1f} s on one core; "
+                      f"its weight build took {t_build:.1f} s over {min(16, os.cpu_count() or 1)} processes"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=500)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--lateral", type=int, default=401)
+    ap.add_argument("--depth", type=int, default=301)
+    ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--zchunk", type=int, default=-1)
+    ap.add_argument("--graph", type=int, default=1)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py: this build runs on one GPU only; multi-GPU sharding is a design note, "
+              "not an implemented path (use --gpus 1)", file=sys.stderr)
+        sys.exit(2)
+    import torch
+
+    import paper_2309_03600_amd as ib
+    from paper_2309_03600_amd import workloads as W
+
+    K, Wm = args.steps, args.warmup
+    t0 = time.time()
+    wl = W.config3(nt=K + Wm + 8, lateral=args.lateral, depth=args.depth)
+    log(f"[bench] inputs {wl.name} generated in {time.time() - t0:.1f} s")
+    torch.cuda.synchronize()
+    t0 = time.time()
+    w = ib.ib_build_weights(wl.heights, wl.h, wl.shape, space_order=wl.M, surface=wl.surface, eta=wl.eta)
+    torch.cuda.synchronize()
+    setup_s = time.time() - t0
+    stats = w.stats()
+    log(f"[bench] weights built in {setup_s:.1f} s: n_ib={stats['n_ib']} sum_nw={stats['sum_nw']} "
+        f"max_cond={stats['max_cond']:.3g} radius_hist={stats['radius_hist']} order_hist={stats['order_hist']}")
+    N = int(np.prod(wl.shape))
+    results = {}
+    traces = {}
+    for prec in (["f32"] if args.no_fp64 else ["f32", "f64"]):
+        dt = torch.float32 if prec == "f32" else torch.float64
+        st = ib.ib_state_create(w, wl.vel, wl.dt, wl.src, wl.rec, damp_width=wl.damp_width, precision=prec)
+        if args.zchunk >= 0:
+            st.set_zchunk(args.zchunk)
+        wav = torch.tensor(wl.wavelets(np.float64), dtype=dt, device="cuda")
+        tr_w = torch.empty((1, Wm, st.nrec), dtype=dt, device="cuda")
+        tr = torch.empty((1, K, st.nrec), dtype=dt, device="cuda")
+        st.step(Wm, wav, tr_w, use_graph=bool(args.graph))
+        torch.cuda.synchronize()
+        s = torch.cuda.current_stream()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        t_host = time.perf_counter()
+        e0.record(s)
+        st.step(K, wav, tr, use_graph=bool(args.graph))
+        e1.record(s)
+        torch.cuda.synchronize()
+        t_host = time.perf_counter() - t_host
+        ms = e0.elapsed_time(e1) / K
+        traces[prec] = tr.double().cpu().numpy()[0]
+        nrep = max(20, min(200, K))
+        ms_int = time_kernel(st, 0, nrep, torch)
+        ms_patch = time_kernel(st, 1, nrep, torch)
+        esz = 4 if prec == "f32" else 8
+        b_int = (4 * esz) * N
+        b_patch = esz * stats["sum_nw"] + (13 if prec == "f32" else 21) * stats["n_ib"]
+        results[prec] = dict(ms_per_step=ms, host_ms_per_step=t_host * 1e3 / K, gpts=N / (ms * 1e-3) / 1e9,
+                             interior_ms=ms_int, patch_ms=ms_patch,
+                             interior_GBs=b_int / (ms_int * 1e-3) / 1e9, patch_GBs=b_patch / (ms_patch * 1e-3) / 1e9,
+                             interior_bytes=b_int, patch_bytes=b_patch,
+                             step_alg_GBs=(b_int + b_patch) / (ms * 1e-3) / 1e9)
+        log(f"[bench] {prec}: {ms:.4f} ms/step, {results[prec]['gpts']:.1f} Gpts/s; interior {ms_int:.4f} ms "
+            f"({results[prec]['interior_GBs']:.0f} GB/s), patch {ms_patch:.4f} ms ({results[prec]['patch_GBs']:.0f} GB/s)")
+        st.close()
+        del wav, tr, tr_w
+        torch.cuda.synchronize()
+    r = results["f32"]
+    dom = "interior" if r["interior_ms"] >= r["patch_ms"] else "patch"
+    traffic = load_traffic()
+    tkey = "k_interior3d" if dom == "interior" else "k_patch"
+    roof = {"bound": "hbm", "achieved": r[f"{dom}_GBs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": r[f"{dom}_GBs"] / HBM_PEAK_GBS,
+            "traffic": traffic.get(tkey, {}).get("bytes_per_launch"), "kernel": tkey}
+    acc = None
+    if "f64" in traces:
+        from_ = traces["f32"]
+        ref = traces["f64"]
+        num = np.linalg.norm(from_ - ref, axis=0)
+        den = np.linalg.norm(ref, axis=0)
+        den = np.maximum(den, 1e-3 * den.max())
+        e = num / den
+        acc = {"max": float(e.max()), "median": float(np.median(e)), "p99": float(np.percentile(e, 99)),
+               "over": f"{K} timed steps, {len(e)} receivers, FP32 GPU vs FP64 GPU"}
+    cpu = None
+    if not args.no_cpu:
+        t0 = time.time()
+        cpu = cpu_baseline()
+        log(f"[bench] cpu baseline {cpu['value']:.4g} Gpts/s ({time.time() - t0:.1f} s)")
+    out = {
+        "metric": "Gpts/s & % HBM roofline, 3D 8th-order IB step, FP32 vs FP64 @1e-4 trace err",
+        "value": r["gpts"], "unit": "Gpts/s", "n_gpus": 1, "steps": K, "warmup": Wm,
+        "ms_per_step": r["ms_per_step"], "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"3D second-order acoustic IB step, {wl.shape[0]}x{wl.shape[1]}x{wl.shape[2]}, "
+                               "dx=10 m, space order 8, seeded fractal free surface (300 m relief), "
+                               "40-cell damping, 1 Ricker source, 201x201 receivers",
+                   "grid": list(wl.shape), "space_order": wl.M, "shots": 1, "hip_graph": bool(args.graph)},
+        "roofline": roof,
+        "cpu_baseline": cpu,
+        "kernels": results,
+        "fp64": results.get("f64"),
+        "fp32_vs_fp64_trace_relL2": acc,
+        "setup": {"weights_build_s": setup_s, "n_ib": stats["n_ib"], "sum_nw": stats["sum_nw"],
+                  "max_nw": stats["max_nw"], "radius_hist": stats["radius_hist"],
+                  "order_hist": stats["order_hist"], "max_cond": stats["max_cond"],
+                  "table_bytes_f32": stats["table_bytes_f32"]},
+    }
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

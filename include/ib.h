@@ -188,6 +188,12 @@ ib_status ib_state_field(ib_state *st, int32_t which, int32_t shot, void *dev_bu
                          void *stream);
 int64_t ib_state_step_count(const ib_state *st);
 
+/* Measurement aid: enqueue ``count`` launches of one kernel of the step on ``stream``
+ * with the current buffers (which = 0: interior stencil, 1: IB patch), rotating the
+ * buffers as a step would, without sources, receivers or the step counter.  Used to
+ * time each kernel on its own; it changes the wavefields. */
+ib_status ib_state_run_kernel(ib_state *st, int32_t which, int32_t count, void *stream);
+
 /* Tuning knob of the 3D eighth-order interior kernel: depth planes per workgroup
  * (0 = whole depth).  Results do not depend on it. */
 ib_status ib_state_set_zchunk(ib_state *st, int32_t zchunk);

@@ -17,8 +17,9 @@ Readings where the paper is silent (each is listed in the design notes):
   * node g is interior iff it is strictly on the physical side (for a heightfield the
     sign of the distance is the sign of z - H at the node's own column);
   * the closest point is found by a coarse search over lateral offsets -1..1 step 1/8
-    followed by Newton's method on |(xi, H(xi)) - g|^2 (a node can only host a
-    boundary point within sqrt(d)/2 of it, which the window covers);
+    followed by Newton's method on |(xi, H(xi)) - g|^2, halving steps longer than 1e-6
+    that would increase it (a node can only host a boundary point within sqrt(d)/2 of
+    it, which the window covers);
   * hosting uses the half-open box -1/2 <= (x_b - g)_n < 1/2; exclusion the strict
     |x_b - g|_n < eta for every axis;
   * lateral axes are periodic.
@@ -35,6 +36,7 @@ COARSE_STEPS = 8          # coarse search spacing 1/8 of a cell
 COARSE_HALF = 1.0         # lateral search window half-width (cells)
 NEWTON_ITERS = 20
 NEWTON_TOL = 1e-13
+BACKTRACK_MIN = 1e-6
 
 
 def _cr_weights(t):
@@ -159,10 +161,12 @@ def foot_points(surface: Surface, nodes):
             sx = -(d_ * grad[:, 0] - b * grad[:, 1]) / sdet
             sy = -(-b * grad[:, 0] + a * grad[:, 1]) / sdet
             step = np.where(ok[:, None], np.stack([sx, sy], 1), step)
+        # step halving only for large steps: below 1e-6 the objective changes by less
+        # than its rounding error and Newton's quadratic convergence takes over
         F0 = _objective(surface, x, xp[ids], z[ids])
         for _h in range(30):
             F1 = _objective(surface, x + step, xp[ids], z[ids])
-            worse = F1 > F0
+            worse = (F1 > F0) & (np.max(np.abs(step), axis=1) > BACKTRACK_MIN)
             if not worse.any():
                 break
             step = np.where(worse[:, None], 0.5 * step, step)

@@ -153,6 +153,10 @@ class IBState:
         torch.cuda.current_stream().synchronize()
         return None
 
+    def run_kernel(self, which, count, stream=None):
+        """Enqueue ``count`` launches of one step kernel (0 interior, 1 patch) for timing."""
+        _lib.check(_lib.load().ib_state_run_kernel(self._h, int(which), int(count), _stream(stream)))
+
     def set_zchunk(self, z):
         _lib.check(_lib.load().ib_state_set_zchunk(self._h, int(z)))
 

@@ -627,6 +627,25 @@ ib_status ib_step(ib_state *S, int32_t nsteps, const void *wavelet, int64_t wstr
   return IB_OK;
 }
 
+ib_status ib_state_run_kernel(ib_state *S, int32_t which, int32_t count, void *stream) {
+  if (!S || which < 0 || which > 1 || count < 0) {
+    set_error("ib_state_run_kernel: invalid argument");
+    return IB_ERR_ARG;
+  }
+  hipStream_t st = (hipStream_t)stream;
+  for (int i = 0; i < count; ++i) {
+    StepArgs a = make_args(S, nullptr, 0, nullptr, 0, S->cur);
+    if (which == 0) {
+      enqueue_interior_only(a, st);
+      S->cur ^= 1;
+    } else {
+      enqueue_patch_only(a, st);
+    }
+  }
+  IB_HIP(hipGetLastError());
+  return IB_OK;
+}
+
 ib_status ib_state_field(ib_state *S, int32_t which, int32_t shot, void *dev, int32_t direction, void *stream) {
   if (!S || !dev || which < 0 || which > 1 || shot < 0 || shot >= S->nshots || direction < 0 || direction > 1) {
     set_error("ib_state_field: invalid argument");

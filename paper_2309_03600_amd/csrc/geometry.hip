@@ -146,8 +146,11 @@ __device__ void foot_point(const SurfView &s, double xu, double xv, double z, do
         sv = -0.5 * gv;
       }
     }
+    // halve only long steps: below 1e-6 the objective's change is under its rounding
+    // error, and the Newton iteration converges quadratically on its own
     double F0 = objective(s, u, v, xu, xv, z);
     for (int hlv = 0; hlv < 30; ++hlv) {
+      if (!(fmax(fabs(su), fabs(sv)) > 1e-6)) break;
       double F1 = objective(s, u + su, v + sv, xu, xv, z);
       if (!(F1 > F0)) break;
       su *= 0.5;
