@@ -71,7 +71,7 @@ def smooth_noise(shape, corr_cells, seed_rng):
         sh = [1] * len(shape)
         sh[ax] = len(kk)
         g = g * np.exp(-0.5 * (2 * math.pi * kk * corr_cells) ** 2).reshape(sh).astype(np.float32)
-    y = np.fft.irfftn(F * g, s=shape).astype(np.float32)
+    y = np.fft.irfftn(F * g, s=shape, axes=tuple(range(len(shape)))).astype(np.float32)
     return y / np.abs(y).max()
 
 
