@@ -88,7 +88,10 @@ def test_weights_match_oracle(name):
         yg = W64[off:off + nw]
         yo = s["weights"]
         scale = max(1.0, np.abs(yo).max())
-        tol = max(1e-11, 200 * s["cond"] * 2.2e-16)
+        # boundary points from the two independent closest-point solvers agree to
+        # ~1e-14; rows of A move by ~1e-13 relative, and y = (A^+)^T c by up to cond(A)
+        # times that; both solvers add O(m cond eps).  Bound: cond * 1e-12.
+        tol = max(1e-11, s["cond"] * 1e-12)
         err = np.abs(yg - yo).max() / scale
         worst = max(worst, err / tol)
         assert err <= tol, (p, err, tol, s["cond"])
@@ -119,7 +122,8 @@ def test_one_step_matches_oracle(name, prec):
     umr = np.asarray(torch.tensor(um, dtype=dt).double()).ravel()
     ref = (2 * ur - (1 - sim.s) * umr + sim.K * (L @ ur)) / (1 + sim.s)
     err = np.abs(got - ref).max() / np.abs(ref).max()
-    tol = 1e-13 if prec == "f64" else 2e-6
+    # FP64: weight differences (cond * 1e-12, cond <~ 1e4) times K <~ 0.1; FP32: rounding
+    tol = 1e-11 if prec == "f64" else 2e-6
     print(f"[{name} {prec}] one-step max error {err:.2e}")
     assert err < tol
 
