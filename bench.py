@@ -70,13 +70,15 @@ def cpu_baseline(budget_steps=200):
     (fractal free surface, M = 8, damping), weights from a process pool (untimed), then
     ``budget_steps`` oracle steps timed on one core."""
     from paper_2309_03600_amd import workloads as W
-    sys.path.insert(0, os.path.join(ROOT, "tests"))
-    from oracle_cases import model_for, simulation, solve_points
+    from oracle import stepper
+    from oracle.parallel import solve_points
+    from oracle.weights import IBModel
     wl = W.small3d(cfg=95, n=24, nz=301, relief=50.0, nt=budget_steps, z_top_cells=20)
     t0 = time.time()
-    m = model_for(wl)
+    m = IBModel(wl.heights, wl.h, wl.shape, M=wl.M, surface=wl.surface, eta=wl.eta)
     sols = solve_points(m, procs=min(16, os.cpu_count() or 1))
-    sim, _ = simulation(wl, m, sols)
+    L = stepper.assemble_laplacian(m, sols)
+    sim = stepper.Simulation(m, L, wl.vel, wl.dt, wl.src, wl.rec, damp_width=wl.damp_width, damp_R=wl.damp_R)
     t_build = time.time() - t0
     wav = wl.wavelets(np.float64)
     t0 = time.perf_counter()

@@ -30,6 +30,8 @@ struct ib_state {
   int cur = 0;                 // buf[cur] holds p^n
   void *K = nullptr, *sx = nullptr, *sy = nullptr, *sz = nullptr;
   void *scale = nullptr;
+  void *pinfo = nullptr;
+  int32_t *delta = nullptr;
   int64_t *sidx = nullptr;
   void *sw = nullptr;
   int nrec = 0;
@@ -73,9 +75,8 @@ StepArgs make_args(ib_state *st, const void *wavelet, int64_t wstride, void *tra
   a.sz = st->sz;
   a.nib = w->nib;
   a.rec = (st->prec == IB_F32) ? w->rec32 : w->rec64;
-  a.roff = (st->prec == IB_F32) ? w->rec_off32 : w->rec_off64;
-  a.xyz = w->ib_xyz;
-  a.scale = st->scale;
+  a.pinfo = st->pinfo;
+  a.delta = st->delta;
   a.ball = w->ball;
   a.ball_meta = w->ball_meta;
   a.sidx = st->sidx;
@@ -229,6 +230,16 @@ ib_status ib_build_weights(const ib_grid *g, const double *height_dev, const ib_
   if (!(g->h > 0.0)) {
     set_error("grid increment must be positive");
     return IB_ERR_ARG;
+  }
+  {
+    // the IB patch kernel holds a support ball's mask in one wavefront (<= 2048 points)
+    BallTables bt;
+    int maxc = p->space_order + 1 + 2 * p->max_radius_steps;
+    bt.build(g->ndim, maxc);
+    if (bt.count[maxc] > 2048) {
+      set_error("largest support ball (radius %.1f) exceeds 2048 lattice points; lower max_radius_steps", maxc / 2.0);
+      return IB_ERR_ARG;
+    }
   }
   ib_weights *w = new ib_weights();
   w->ndim = g->ndim;
@@ -466,6 +477,12 @@ ib_status ib_state_create(const ib_weights *w, const double *vel_dev, double dt,
                          vel_dev, (int)w->nx, (int)w->ny, f, d_ax, d_ay, d_az, (double *)S->scale);
     IB_HIP(hipGetLastError());
   }
+  if ((s = dalloc(&S->pinfo, std::max<int64_t>(w->nib, 1) * pinfo_bytes(prec))) ||
+      (s = dalloc_t(&S->delta, std::max<size_t>(w->balls.packed.size(), 1))))
+    return fail(s);
+  enqueue_make_pinfo(prec, w->ib_xyz, prec == IB_F32 ? w->rec_off32 : w->rec_off64, S->scale, w->nib, S->pinfo, st);
+  enqueue_make_delta(w->ball, (int)w->balls.packed.size(), S->pitch, S->pitch * w->ny, S->delta, st);
+  IB_HIP(hipGetLastError());
   IB_HIP(hipStreamSynchronize(st));
   dfree(d_ax), dfree(d_ay), dfree(d_az);
   // sources: interior corners only; amplitude factor dt^2 w / (h^d (1 + s))
@@ -545,6 +562,8 @@ void ib_state_free(ib_state *S) {
   dfree(S->sy);
   dfree(S->sz);
   dfree(S->scale);
+  dfree(S->pinfo);
+  dfree(S->delta);
   dfree(S->sidx);
   dfree(S->sw);
   dfree(S->ridx);

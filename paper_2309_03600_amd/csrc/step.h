@@ -21,10 +21,10 @@ struct StepArgs {
   const void *sx, *sy, *sz;
   // IB patch
   int64_t nib;
-  const uint32_t *rec, *roff;
-  const int16_t *xyz;
-  const void *scale;
+  const uint32_t *rec;
+  const void *pinfo;          // per-point records (position, code, offset, scale)
   const int32_t *ball;
+  const int32_t *delta;       // linear offsets of the ball lattice points for this layout
   const int32_t *ball_meta;   // [code][2]: start, count
   // sources / receivers
   const int64_t *sidx;
@@ -42,5 +42,9 @@ struct StepArgs {
 void enqueue_step(const StepArgs &a, hipStream_t st);
 void enqueue_interior_only(const StepArgs &a, hipStream_t st);
 void enqueue_patch_only(const StepArgs &a, hipStream_t st);
+size_t pinfo_bytes(int prec);
+void enqueue_make_pinfo(int prec, const int16_t *xyz, const uint32_t *roff, const void *scale, int64_t nib,
+                        void *out, hipStream_t st);
+void enqueue_make_delta(const int32_t *ball, int n, int64_t pitch, int64_t plane, int32_t *delta, hipStream_t st);
 
 }  // namespace ib

@@ -184,49 +184,90 @@ __global__ void k_interior_generic(const T *__restrict__ un, T *__restrict__ um,
 }
 
 // ---- IB patch: one wavefront per IB point ------------------------------------------
+// Per point: one packed record (position, radius code, record offset, scale).  The
+// wavefront loads the data-membership mask words of the support ball once, then, in
+// groups of 8 x 64 lattice points, computes every lane's weight index (ballot + prefix
+// popcount) and gather address first and only then issues all gathers and weight loads,
+// so a point costs two dependent memory latencies instead of one per 64 lattice points.
+// Away from the lateral edges a precomputed linear offset table (per radius, for this
+// layout) replaces the periodic wrap.
+template <typename T>
+struct alignas(16) PInfo {
+  int16_t x, y, z, code;
+  uint32_t roff;
+  uint32_t pad;
+  T scale;
+};
+
+template <typename T, int G>
+__device__ __forceinline__ void patch_group(const T *__restrict__ u, const T *__restrict__ wts,
+                                            const int32_t *__restrict__ bl, const int32_t *__restrict__ dl,
+                                            uint32_t mw, int g0, int nb, int lane, bool edge, int x, int y, int z,
+                                            int nx, int ny, int64_t pitch, int64_t plane, size_t centre, int &wbase,
+                                            T &acc) {
+  int widx[G];
+  int64_t gofs[G];
+  bool ok[G];
+#pragma unroll
+  for (int k = 0; k < G; ++k) {
+    const int b = (g0 + k) * 64 + lane;
+    const uint32_t word = (uint32_t)__shfl((int)mw, (b >> 5) & 63);
+    const int bit = (b < nb) ? (int)((word >> (b & 31)) & 1u) : 0;
+    const unsigned long long bal = __ballot(bit);
+    widx[k] = wbase + __popcll(bal & ((1ull << lane) - 1ull));
+    wbase += __popcll(bal);
+    ok[k] = bit != 0;
+    if (!edge) {
+      gofs[k] = (int64_t)centre + (bit ? dl[b] : 0);
+    } else {
+      const uint32_t v = bit ? (uint32_t)bl[b] : 0u;
+      const int dx = (int8_t)(v & 255), dy = (int8_t)((v >> 8) & 255), dz = (int8_t)((v >> 16) & 255);
+      gofs[k] = (int64_t)(z + dz) * plane + (int64_t)wrapk(y + dy, ny) * pitch + wrapk(x + dx, nx);
+    }
+  }
+  T pv[G], wv[G];
+#pragma unroll
+  for (int k = 0; k < G; ++k) {
+    pv[k] = ok[k] ? u[gofs[k]] : T(0);
+    wv[k] = ok[k] ? wts[widx[k]] : T(0);
+  }
+#pragma unroll
+  for (int k = 0; k < G; ++k) acc += wv[k] * pv[k];
+}
+
 template <typename T>
 __launch_bounds__(256)
 __global__ void k_patch(const T *__restrict__ un, T *__restrict__ unew, const uint32_t *__restrict__ rec,
-                        const uint32_t *__restrict__ roff, const int16_t *__restrict__ xyz,
-                        const T *__restrict__ scale, const int32_t *__restrict__ ball,
-                        const int32_t *__restrict__ ball_meta, int64_t nib, int nx, int ny, int nz, int64_t pitch,
-                        int64_t vol, int nshots) {
+                        const PInfo<T> *__restrict__ pinfo, const int32_t *__restrict__ ball,
+                        const int32_t *__restrict__ delta, const int32_t *__restrict__ ball_meta, int64_t nib,
+                        int nx, int ny, int nz, int64_t pitch, int64_t vol, int nshots) {
   const int lane = threadIdx.x & 63;
   const int64_t blk = xcd_remap(blockIdx.x, gridDim.x);
   const int64_t i = blk * (blockDim.x >> 6) + (threadIdx.x >> 6);
   if (i >= nib) return;
-  const int16_t *p = xyz + i * 4;
-  const int x = p[0], y = p[1], z = p[2], code = p[3];
-  const int nb = ball_meta[2 * code + 1];
-  const int32_t *bl = ball + ball_meta[2 * code];
+  const PInfo<T> P = pinfo[i];
+  const int x = P.x, y = P.y, z = P.z, code = P.code;
+  const int bstart = ball_meta[2 * code], nb = ball_meta[2 * code + 1];
   const int nwords = (nb + 31) >> 5;
-  const uint32_t off = roff[i];
-  const uint32_t *m = rec + off;
+  const uint32_t *m = rec + P.roff;
   const int wpad = (sizeof(T) == 8) ? ((nwords + 1) & ~1) : nwords;
-  const T *wts = reinterpret_cast<const T *>(rec + off + wpad);
+  const T *wts = reinterpret_cast<const T *>(m + wpad);
+  const uint32_t mw = (lane < nwords) ? m[lane] : 0u;      // nb <= 2048 -> nwords <= 64
   const int64_t plane = pitch * ny;
-  const T sc = scale[i];
+  const int R = code / 2 + 1;
+  const bool edge = (x < R || x >= nx - R || (ny > 1 && (y < R || y >= ny - R)));
   const size_t centre = (size_t)z * plane + (size_t)y * pitch + x;
+  const int32_t *bl = ball + bstart;
+  const int32_t *dl = delta + bstart;
+  const int ngroups = (nb + 511) / 512;
   for (int s = 0; s < nshots; ++s) {
     const T *u = un + (size_t)s * vol;
     T acc = T(0);
-    int base = 0;
-    for (int b0 = 0; b0 < nb; b0 += 64) {
-      const int b = b0 + lane;
-      const uint32_t word = (b < nb) ? m[b >> 5] : 0u;
-      const int bit = (word >> (b & 31)) & 1;
-      const unsigned long long bal = __ballot(bit);
-      if (bit) {
-        const int widx = base + __popcll(bal & ((1ull << lane) - 1ull));
-        const uint32_t v = (uint32_t)bl[b];
-        const int dx = (int8_t)(v & 255), dy = (int8_t)((v >> 8) & 255), dz = (int8_t)((v >> 16) & 255);
-        const size_t g = (size_t)(z + dz) * plane + (size_t)wrapk(y + dy, ny) * pitch + wrapk(x + dx, nx);
-        acc += wts[widx] * u[g];
-      }
-      base += __popcll(bal);
-    }
+    int wbase = 0;
+    for (int g = 0; g < ngroups; ++g)
+      patch_group<T, 8>(u, wts, bl, dl, mw, g * 8, nb, lane, edge, x, y, z, nx, ny, pitch, plane, centre, wbase, acc);
     for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
-    if (lane == 0) unew[(size_t)s * vol + centre] += sc * acc;
+    if (lane == 0) unew[(size_t)s * vol + centre] += P.scale * acc;
   }
 }
 
@@ -320,7 +361,7 @@ static void launch_step(const StepArgs &a, hipStream_t st) {
   if (a.nib > 0) {
     int64_t nblk = ((a.nib + 3) / 4 + 7) / 8 * 8;
     hipLaunchKernelGGL(k_patch<T>, dim3((unsigned)nblk), dim3(256), 0, st, (const T *)a.un, (T *)a.um, a.rec,
-                       a.roff, a.xyz, (const T *)a.scale, a.ball, a.ball_meta, a.nib, a.nx, a.ny, a.nz, a.pitch,
+                       (const PInfo<T> *)a.pinfo, a.ball, a.delta, a.ball_meta, a.nib, a.nx, a.ny, a.nz, a.pitch,
                        a.vol, a.nshots);
   }
   hipLaunchKernelGGL(k_inject<T>, dim3(1), dim3(256), 0, st, (T *)a.um, a.sidx, (const T *)a.sw, a.nshots, a.vol,
@@ -351,12 +392,53 @@ void enqueue_patch_only(const StepArgs &a, hipStream_t st) {
   int64_t nblk = ((a.nib + 3) / 4 + 7) / 8 * 8;
   if (a.prec == IB_F32)
     hipLaunchKernelGGL(k_patch<float>, dim3((unsigned)nblk), dim3(256), 0, st, (const float *)a.un, (float *)a.um,
-                       a.rec, a.roff, a.xyz, (const float *)a.scale, a.ball, a.ball_meta, a.nib, a.nx, a.ny, a.nz,
+                       a.rec, (const PInfo<float> *)a.pinfo, a.ball, a.delta, a.ball_meta, a.nib, a.nx, a.ny, a.nz,
                        a.pitch, a.vol, a.nshots);
   else
     hipLaunchKernelGGL(k_patch<double>, dim3((unsigned)nblk), dim3(256), 0, st, (const double *)a.un, (double *)a.um,
-                       a.rec, a.roff, a.xyz, (const double *)a.scale, a.ball, a.ball_meta, a.nib, a.nx, a.ny, a.nz,
+                       a.rec, (const PInfo<double> *)a.pinfo, a.ball, a.delta, a.ball_meta, a.nib, a.nx, a.ny, a.nz,
                        a.pitch, a.vol, a.nshots);
+}
+
+size_t pinfo_bytes(int prec) { return prec == IB_F32 ? sizeof(PInfo<float>) : sizeof(PInfo<double>); }
+
+// per-point records and per-layout offset tables of a state
+template <typename T>
+__global__ void k_make_pinfo(const int16_t *xyz, const uint32_t *roff, const T *scale, int64_t nib, PInfo<T> *out) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nib) return;
+  PInfo<T> p;
+  p.x = xyz[i * 4];
+  p.y = xyz[i * 4 + 1];
+  p.z = xyz[i * 4 + 2];
+  p.code = xyz[i * 4 + 3];
+  p.roff = roff[i];
+  p.pad = 0;
+  p.scale = scale[i];
+  out[i] = p;
+}
+
+__global__ void k_make_delta(const int32_t *ball, int n, int64_t pitch, int64_t plane, int32_t *delta) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  uint32_t v = (uint32_t)ball[i];
+  int dx = (int8_t)(v & 255), dy = (int8_t)((v >> 8) & 255), dz = (int8_t)((v >> 16) & 255);
+  delta[i] = (int32_t)(dz * plane + dy * pitch + dx);
+}
+
+void enqueue_make_pinfo(int prec, const int16_t *xyz, const uint32_t *roff, const void *scale, int64_t nib,
+                        void *out, hipStream_t st) {
+  if (nib <= 0) return;
+  if (prec == IB_F32)
+    hipLaunchKernelGGL(k_make_pinfo<float>, dim3((unsigned)((nib + 255) / 256)), dim3(256), 0, st, xyz, roff,
+                       (const float *)scale, nib, (PInfo<float> *)out);
+  else
+    hipLaunchKernelGGL(k_make_pinfo<double>, dim3((unsigned)((nib + 255) / 256)), dim3(256), 0, st, xyz, roff,
+                       (const double *)scale, nib, (PInfo<double> *)out);
+}
+
+void enqueue_make_delta(const int32_t *ball, int n, int64_t pitch, int64_t plane, int32_t *delta, hipStream_t st) {
+  hipLaunchKernelGGL(k_make_delta, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, ball, n, pitch, plane, delta);
 }
 
 }  // namespace ib

@@ -1,57 +1,12 @@
 """Test helpers: build oracle results for a workload (CPU, FP64), in parallel."""
-import multiprocessing as mp
-import os
-
 import numpy as np
 
 from oracle import stepper
+from oracle.parallel import solve_points  # noqa: F401
 from oracle.weights import IBModel
-
-_MODEL = None
-
 
 def model_for(wl, **kw):
     return IBModel(wl.heights, wl.h, wl.shape, M=wl.M, surface=wl.surface, eta=wl.eta, **kw)
-
-
-def _init_worker(model):
-    global _MODEL
-    _MODEL = model
-
-
-def _solve_one(p):
-    s = _MODEL.solve_point(p)
-    return (tuple(int(v) for v in p), s)
-
-
-def solve_points(model, points=None, procs=None):
-    """{node tuple: solution}.  A spawned process pool (fresh interpreters with
-    single-threaded BLAS: forking after the parent started BLAS or HIP threads can
-    deadlock the children) solves the points in parallel."""
-    pts = model.ib_points() if points is None else np.asarray(points)
-    if procs is None:
-        procs = min(16, os.cpu_count() or 1)
-    if len(pts) < 64 or procs <= 1:
-        return {tuple(int(v) for v in p): model.solve_point(p) for p in pts}
-    saved = {k: os.environ.get(k) for k in ("OPENBLAS_NUM_THREADS", "OMP_NUM_THREADS", "MKL_NUM_THREADS")}
-    for k in saved:
-        os.environ[k] = "1"
-    try:
-        ctx = mp.get_context("spawn")
-        res = []
-        with ctx.Pool(procs, initializer=_init_worker, initargs=(model,)) as pool:
-            it = pool.imap(_solve_one, list(pts), chunksize=max(1, len(pts) // (procs * 16)))
-            for k, r in enumerate(it):
-                res.append(r)
-                if (k + 1) % 200 == 0:
-                    print(f"  [oracle] {k + 1}/{len(pts)} IB points solved", flush=True)
-    finally:
-        for k, v in saved.items():
-            if v is None:
-                os.environ.pop(k, None)
-            else:
-                os.environ[k] = v
-    return dict(res)
 
 
 def simulation(wl, model, sols):
