@@ -181,6 +181,27 @@ void ib_state_free(ib_state *st);
 ib_status ib_step(ib_state *st, int32_t nsteps, const void *wavelet_dev, int64_t wavelet_stride,
                   void *traces_dev, int32_t use_graph, void *stream);
 
+/* Forward modelling with time checkpoints, for a later ib_adjoint.  Restarts every shot
+ * from rest (step counter 0), runs ``nt`` steps exactly as ib_step (eager launches), and
+ * keeps (p^n, p^{n-1}) at every multiple of ``ckpt_every`` inside the state (device
+ * memory, 2 * nshots * grid * ceil(nt / ckpt_every) values).
+ *   traces_dev: device [nshots][nt][nrec] in the state precision (may be NULL if nrec = 0). */
+ib_status ib_forward(ib_state *st, int32_t nt, const void *wavelet_dev, int64_t wavelet_stride, void *traces_dev,
+                     int32_t ckpt_every, void *stream);
+
+/* Gradient of a misfit J with respect to the velocity, by the discrete adjoint of the
+ * stepper (not a result of the paper: full-waveform inversion is its motivation).
+ *   residual_dev: device [nshots][nt][nrec] (state precision) = dJ/d traces of the last
+ *     ib_forward (for J = 1/2 sum (d - d_obs)^2 it is d - d_obs).
+ *   grad_dev: device float64 [nz][ny][nx], overwritten with dJ/dc summed over shots (zero
+ *     at exterior nodes).  The damping profile is held fixed.
+ * Each checkpoint segment is recomputed forward and kept (ckpt_every fields) while the
+ * adjoint steps back through it; the adjoint of the IB rows uses a transposed stencil
+ * table (per receiving node) built on the first call.
+ * Errors: IB_ERR_STATE without a previous ib_forward. */
+ib_status ib_adjoint(ib_state *st, const void *residual_dev, const void *wavelet_dev, int64_t wavelet_stride,
+                     double *grad_dev, void *stream);
+
 /* Read or write the current wavefields of one shot (layout [nz][ny][nx] or [nz][nx],
  * state precision, device memory):  which = 0: p^n (newest), 1: p^{n-1}.
  * direction 0 copies out of the state, 1 copies into it. */

@@ -14,7 +14,7 @@ import numpy as np
 from . import _lib
 from ._lib import IB_F32, IB_F64, IB_SURF_FREE, IB_SURF_RIGID  # noqa: F401
 
-__all__ = ["IBWeights", "IBState", "ib_build_weights", "ib_state_create", "ib_step", "abi_version"]
+__all__ = ["IBWeights", "IBState", "ib_build_weights", "ib_state_create", "ib_step", "modelling", "abi_version"]
 
 
 def _torch():
@@ -153,6 +153,27 @@ class IBState:
         torch.cuda.current_stream().synchronize()
         return None
 
+    def forward(self, nt, wavelet, ckpt_every=50, traces=None, stream=None):
+        """Restart from rest and run ``nt`` steps keeping checkpoints for ``adjoint``."""
+        torch = _torch()
+        assert wavelet.dtype == self.dtype and wavelet.is_cuda and wavelet.is_contiguous()
+        if traces is None:
+            traces = torch.zeros((self.nshots, nt, self.nrec), dtype=self.dtype, device="cuda")
+        tp = C.c_void_p(traces.data_ptr()) if self.nrec > 0 else C.c_void_p()
+        _lib.check(_lib.load().ib_forward(self._h, int(nt), C.c_void_p(wavelet.data_ptr()), int(wavelet.shape[1]),
+                                          tp, int(ckpt_every), _stream(stream)))
+        return traces
+
+    def adjoint(self, residual, wavelet, stream=None):
+        """dJ/dc (float64 grid tensor) for residual = dJ/dtraces of the last ``forward``."""
+        torch = _torch()
+        res = residual.to(device="cuda", dtype=self.dtype).contiguous()
+        shape = tuple(reversed(self.weights.shape))
+        grad = torch.zeros(shape, dtype=torch.float64, device="cuda")
+        _lib.check(_lib.load().ib_adjoint(self._h, C.c_void_p(res.data_ptr()), C.c_void_p(wavelet.data_ptr()),
+                                          int(wavelet.shape[1]), C.c_void_p(grad.data_ptr()), _stream(stream)))
+        return grad
+
     def run_kernel(self, which, count, stream=None):
         """Enqueue ``count`` launches of one step kernel (0 interior, 1 patch) for timing."""
         _lib.check(_lib.load().ib_state_run_kernel(self._h, int(which), int(count), _stream(stream)))
@@ -195,3 +216,35 @@ def ib_state_create(weights, vel, dt, src_pos, rec_pos, damp_width=0, damp_R=1e-
 
 def ib_step(state, nsteps, wavelet, traces=None, use_graph=False, stream=None):
     return state.step(nsteps, wavelet, traces, use_graph, stream)
+
+
+def _autograd():
+    import torch
+
+    class IBModelling(torch.autograd.Function):
+        """traces = F(velocity); backward = the library's discrete adjoint (ib_adjoint)."""
+
+        @staticmethod
+        def forward(ctx, vel, weights, wavelet, src, rec, dt, nt, damp_width, precision, ckpt_every):
+            st = ib_state_create(weights, vel.detach().to(torch.float64), dt, src, rec, damp_width=damp_width,
+                                 precision=precision)
+            wav = wavelet.to(device="cuda", dtype=st.dtype).contiguous()
+            tr = st.forward(nt, wav, ckpt_every=ckpt_every)
+            ctx.st = st
+            ctx.wav = wav
+            ctx.vdtype = vel.dtype
+            return tr
+
+        @staticmethod
+        def backward(ctx, grad_traces):
+            g = ctx.st.adjoint(grad_traces, ctx.wav)
+            ctx.st.close()
+            return g.to(ctx.vdtype), None, None, None, None, None, None, None, None, None
+
+    return IBModelling
+
+
+def modelling(vel, weights, wavelet, src, rec, dt, nt, damp_width=0, precision="f32", ckpt_every=50):
+    """Differentiable forward modelling: traces [nshots][nt][nrec] as a function of the
+    velocity tensor (torch.autograd), gradients from the hand-written adjoint."""
+    return _autograd().apply(vel, weights, wavelet, src, rec, dt, nt, damp_width, precision, ckpt_every)

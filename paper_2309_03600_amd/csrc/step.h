@@ -43,6 +43,40 @@ void enqueue_step(const StepArgs &a, hipStream_t st);
 void enqueue_interior_only(const StepArgs &a, hipStream_t st);
 void enqueue_patch_only(const StepArgs &a, hipStream_t st);
 size_t pinfo_bytes(int prec);
+
+// One adjoint step (lambda^m from lambda^{m+1}, lambda^{m+2}) and its gradient term.
+struct AdjArgs {
+  int prec, ndim, M;
+  int nx, ny, nz;
+  int64_t pitch, vol;
+  int nshots;
+  const void *lam1;      // lambda^{m+1}
+  void *lam2;            // lambda^{m+2} in, lambda^m out
+  const void *K, *sx, *sy, *sz;
+  // transposed IB rows
+  int64_t nj;
+  const int64_t *jnode, *joff, *jsrc;
+  const void *jD, *jw;
+  // transposed receivers
+  int64_t nrn;
+  const int64_t *rnode, *roff;
+  const int32_t *rrec;
+  const void *rD, *rw;
+  const void *res;       // [nshots][nt][nrec]
+  int64_t nt;
+  int nrec;
+  int64_t step;          // m - 1
+  // gradient
+  double *gK;
+  const void *u;         // u^{m-1}
+  int64_t nib;
+  const uint32_t *rec;
+  const void *pinfo;
+  const int32_t *ball, *delta, *ball_meta;
+};
+void enqueue_adjoint_step(const AdjArgs &a, hipStream_t st);
+void enqueue_grad_out(int prec, const double *gK, const void *K, double *out, int nx, int ny, int nz, int64_t pitch,
+                      double dt_over_h, hipStream_t st);
 void enqueue_make_pinfo(int prec, const int16_t *xyz, const uint32_t *roff, const void *scale, int64_t nib,
                         void *out, hipStream_t st);
 void enqueue_make_delta(const int32_t *ball, int n, int64_t pitch, int64_t plane, int32_t *delta, hipStream_t st);

@@ -400,6 +400,258 @@ void enqueue_patch_only(const StepArgs &a, hipStream_t st) {
                        a.pitch, a.vol, a.nshots);
 }
 
+// ---- discrete adjoint ----------------------------------------------------------------
+// With D = 1/(1+s), the adjoint of the damped leapfrog (scaled lambda = D mu) is the same
+// recurrence with L^T K in place of K L:
+//   lambda^m = D [2 lambda^{m+1} - (1 - s) lambda^{m+2} + L^T (K lambda^{m+1}) + R^T res^{m-1}],
+// and dJ/dK = sum_m lambda^m (L u^{m-1}).  The standard part of L is symmetric, so its
+// transpose is the same stencil applied to K lambda; the IB rows are transposed through a
+// per-receiving-node table (a gather, deterministic, no atomics).
+template <typename T, int H>
+__global__ void k_adj_interior(const T *__restrict__ lam1, T *__restrict__ lam2, const T *__restrict__ K,
+                               const T *__restrict__ sx, const T *__restrict__ sy, const T *__restrict__ sz,
+                               StencilW<T> W, int nx, int ny, int nz, int lat, int64_t pitch, int64_t vol,
+                               int nshots) {
+  const int64_t per = (int64_t)nx * ny * nz;
+  int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= per * nshots) return;
+  const int shot = (int)(g / per);
+  int64_t i = g % per;
+  const int x = (int)(i % nx);
+  i /= nx;
+  const int y = (int)(i % ny);
+  const int z = (int)(i / ny);
+  const int64_t plane = pitch * ny;
+  const T *u = lam1 + (size_t)shot * vol;
+  T *o = lam2 + (size_t)shot * vol;
+  const size_t c = (size_t)z * plane + (size_t)y * pitch + x;
+  const T uc = u[c];
+  T lap = T(lat + 1) * W.w[0] * (K[c] * uc);
+  for (int k = 1; k <= H; ++k) {
+    size_t a0 = (size_t)z * plane + (size_t)y * pitch + wrapk(x - k, nx);
+    size_t a1 = (size_t)z * plane + (size_t)y * pitch + wrapk(x + k, nx);
+    T acc = K[a0] * u[a0] + K[a1] * u[a1];
+    if (lat == 2) {
+      size_t b0 = (size_t)z * plane + (size_t)wrapk(y - k, ny) * pitch + x;
+      size_t b1 = (size_t)z * plane + (size_t)wrapk(y + k, ny) * pitch + x;
+      acc += K[b0] * u[b0] + K[b1] * u[b1];
+    }
+    if (z - k >= 0) acc += K[c - (size_t)k * plane] * u[c - (size_t)k * plane];
+    if (z + k < nz) acc += K[c + (size_t)k * plane] * u[c + (size_t)k * plane];
+    lap += W.w[k] * acc;
+  }
+  const T s = sx[x] + sy[y] + sz[z];
+  o[c] = (T(2) * uc - (T(1) - s) * o[c] + lap) / (T(1) + s);
+}
+
+// lambda^m_j += D_j sum_k w_k K_{i_k} lambda^{m+1}_{i_k} over the IB rows i_k that use node j
+template <typename T>
+__global__ void k_adj_gather(T *__restrict__ lam, const T *__restrict__ lam1, const T *__restrict__ K,
+                             const int64_t *__restrict__ jnode, const T *__restrict__ jD,
+                             const int64_t *__restrict__ joff, const int64_t *__restrict__ src,
+                             const T *__restrict__ wt, int64_t nj, int nshots, int64_t vol) {
+  int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= nj) return;
+  const int64_t a = joff[j], b = joff[j + 1];
+  const int64_t node = jnode[j];
+  const T d = jD[j];
+  for (int s = 0; s < nshots; ++s) {
+    const T *l1 = lam1 + (size_t)s * vol;
+    T acc = T(0);
+    for (int64_t k = a; k < b; ++k) {
+      const int64_t q = src[k];
+      acc += wt[k] * (K[q] * l1[q]);
+    }
+    lam[(size_t)s * vol + node] += d * acc;
+  }
+}
+
+// lambda^m_j += D_j sum over receivers using node j of w * res^{m-1}
+template <typename T>
+__global__ void k_adj_receivers(T *__restrict__ lam, const T *__restrict__ res, int64_t nt, int nrec, int64_t step,
+                                const int64_t *__restrict__ rnode, const T *__restrict__ rD,
+                                const int64_t *__restrict__ roff, const int32_t *__restrict__ rrec,
+                                const T *__restrict__ rw, int64_t nrn, int nshots, int64_t vol) {
+  int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= nrn) return;
+  const int64_t a = roff[j], b = roff[j + 1];
+  for (int s = 0; s < nshots; ++s) {
+    const T *r = res + ((size_t)s * nt + step) * nrec;
+    T acc = T(0);
+    for (int64_t k = a; k < b; ++k) acc += rw[k] * r[rrec[k]];
+    lam[(size_t)s * vol + rnode[j]] += rD[j] * acc;
+  }
+}
+
+// g += sum over shots of lambda^m (L_std u^{m-1}) at interior nodes (K != 0)
+template <typename T, int H>
+__global__ void k_grad_std(double *__restrict__ gK, const T *__restrict__ lam, const T *__restrict__ un,
+                           const T *__restrict__ K, StencilW<T> W, int nx, int ny, int nz, int lat, int64_t pitch,
+                           int64_t vol, int nshots) {
+  const int64_t per = (int64_t)nx * ny * nz;
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= per) return;
+  const int x = (int)(i % nx);
+  int64_t r = i / nx;
+  const int y = (int)(r % ny);
+  const int z = (int)(r / ny);
+  const int64_t plane = pitch * ny;
+  const size_t c = (size_t)z * plane + (size_t)y * pitch + x;
+  if (K[c] == T(0)) return;
+  double tot = 0.0;
+  for (int s = 0; s < nshots; ++s) {
+    const T *u = un + (size_t)s * vol;
+    T lap = T(lat + 1) * W.w[0] * u[c];
+    for (int k = 1; k <= H; ++k) {
+      T acc = u[(size_t)z * plane + (size_t)y * pitch + wrapk(x - k, nx)] +
+              u[(size_t)z * plane + (size_t)y * pitch + wrapk(x + k, nx)];
+      if (lat == 2)
+        acc += u[(size_t)z * plane + (size_t)wrapk(y - k, ny) * pitch + x] +
+               u[(size_t)z * plane + (size_t)wrapk(y + k, ny) * pitch + x];
+      if (z - k >= 0) acc += u[c - (size_t)k * plane];
+      if (z + k < nz) acc += u[c + (size_t)k * plane];
+      lap += W.w[k] * acc;
+    }
+    tot += (double)lam[(size_t)s * vol + c] * (double)lap;
+  }
+  gK[c] += tot;
+}
+
+// g_i += sum over shots of lambda^m_i (sum_j y_ij u^{m-1}_j) at IB points
+template <typename T>
+__launch_bounds__(256)
+__global__ void k_grad_ib(double *__restrict__ gK, const T *__restrict__ lam, const T *__restrict__ un,
+                          const uint32_t *__restrict__ rec, const PInfo<T> *__restrict__ pinfo,
+                          const int32_t *__restrict__ ball, const int32_t *__restrict__ delta,
+                          const int32_t *__restrict__ ball_meta, int64_t nib, int nx, int ny, int nz, int64_t pitch,
+                          int64_t vol, int nshots) {
+  const int lane = threadIdx.x & 63;
+  const int64_t blk = xcd_remap(blockIdx.x, gridDim.x);
+  const int64_t i = blk * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  if (i >= nib) return;
+  const PInfo<T> P = pinfo[i];
+  const int x = P.x, y = P.y, z = P.z, code = P.code;
+  const int bstart = ball_meta[2 * code], nb = ball_meta[2 * code + 1];
+  const int nwords = (nb + 31) >> 5;
+  const uint32_t *m = rec + P.roff;
+  const int wpad = (sizeof(T) == 8) ? ((nwords + 1) & ~1) : nwords;
+  const T *wts = reinterpret_cast<const T *>(m + wpad);
+  const uint32_t mw = (lane < nwords) ? m[lane] : 0u;
+  const int64_t plane = pitch * ny;
+  const int R = code / 2 + 1;
+  const bool edge = (x < R || x >= nx - R || (ny > 1 && (y < R || y >= ny - R)));
+  const size_t centre = (size_t)z * plane + (size_t)y * pitch + x;
+  const int ngroups = (nb + 511) / 512;
+  double tot = 0.0;
+  for (int s = 0; s < nshots; ++s) {
+    const T *u = un + (size_t)s * vol;
+    T acc = T(0);
+    int wbase = 0;
+    for (int g = 0; g < ngroups; ++g)
+      patch_group<T, 8>(u, wts, ball + bstart, delta + bstart, mw, g * 8, nb, lane, edge, x, y, z, nx, ny, pitch,
+                        plane, centre, wbase, acc);
+    for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
+    tot += (double)lam[(size_t)s * vol + centre] * (double)acc;
+  }
+  if (lane == 0) gK[centre] += tot;
+}
+
+template <typename T>
+__global__ void k_grad_out(const double *__restrict__ gK, const T *__restrict__ K, double *__restrict__ out, int nx,
+                           int ny, int nz, int64_t pitch, double dt_over_h) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int64_t per = (int64_t)nx * ny * nz;
+  if (i >= per) return;
+  const int x = (int)(i % nx);
+  int64_t r = i / nx;
+  const int y = (int)(r % ny);
+  const int z = (int)(r / ny);
+  const size_t c = ((size_t)z * ny + y) * pitch + x;
+  const double k = (double)K[c];
+  out[i] = (k > 0.0) ? gK[c] * 2.0 * sqrt(k) * dt_over_h : 0.0;
+}
+
+template <typename T>
+static void adjoint_step_t(const AdjArgs &a, hipStream_t st) {
+  const int lat = a.ndim - 1;
+  const int64_t tot = (int64_t)a.nx * a.ny * a.nz * a.nshots;
+  dim3 g((unsigned)((tot + 255) / 256)), b(256);
+  const StencilW<T> W = stencil_weights<T>(a.M);
+  switch (a.M / 2) {
+    case 1:
+      hipLaunchKernelGGL((k_adj_interior<T, 1>), g, b, 0, st, (const T *)a.lam1, (T *)a.lam2, (const T *)a.K,
+                         (const T *)a.sx, (const T *)a.sy, (const T *)a.sz, W, a.nx, a.ny, a.nz, lat, a.pitch, a.vol,
+                         a.nshots);
+      break;
+    case 2:
+      hipLaunchKernelGGL((k_adj_interior<T, 2>), g, b, 0, st, (const T *)a.lam1, (T *)a.lam2, (const T *)a.K,
+                         (const T *)a.sx, (const T *)a.sy, (const T *)a.sz, W, a.nx, a.ny, a.nz, lat, a.pitch, a.vol,
+                         a.nshots);
+      break;
+    case 3:
+      hipLaunchKernelGGL((k_adj_interior<T, 3>), g, b, 0, st, (const T *)a.lam1, (T *)a.lam2, (const T *)a.K,
+                         (const T *)a.sx, (const T *)a.sy, (const T *)a.sz, W, a.nx, a.ny, a.nz, lat, a.pitch, a.vol,
+                         a.nshots);
+      break;
+    default:
+      hipLaunchKernelGGL((k_adj_interior<T, 4>), g, b, 0, st, (const T *)a.lam1, (T *)a.lam2, (const T *)a.K,
+                         (const T *)a.sx, (const T *)a.sy, (const T *)a.sz, W, a.nx, a.ny, a.nz, lat, a.pitch, a.vol,
+                         a.nshots);
+      break;
+  }
+  if (a.nj > 0)
+    hipLaunchKernelGGL(k_adj_gather<T>, dim3((unsigned)((a.nj + 255) / 256)), dim3(256), 0, st, (T *)a.lam2,
+                       (const T *)a.lam1, (const T *)a.K, a.jnode, (const T *)a.jD, a.joff, a.jsrc, (const T *)a.jw,
+                       a.nj, a.nshots, a.vol);
+  if (a.nrn > 0)
+    hipLaunchKernelGGL(k_adj_receivers<T>, dim3((unsigned)((a.nrn + 255) / 256)), dim3(256), 0, st, (T *)a.lam2,
+                       (const T *)a.res, a.nt, a.nrec, a.step, a.rnode, (const T *)a.rD, a.roff, a.rrec,
+                       (const T *)a.rw, a.nrn, a.nshots, a.vol);
+  const int64_t per = (int64_t)a.nx * a.ny * a.nz;
+  dim3 g2((unsigned)((per + 255) / 256));
+  switch (a.M / 2) {
+    case 1:
+      hipLaunchKernelGGL((k_grad_std<T, 1>), g2, b, 0, st, a.gK, (const T *)a.lam2, (const T *)a.u, (const T *)a.K, W,
+                         a.nx, a.ny, a.nz, lat, a.pitch, a.vol, a.nshots);
+      break;
+    case 2:
+      hipLaunchKernelGGL((k_grad_std<T, 2>), g2, b, 0, st, a.gK, (const T *)a.lam2, (const T *)a.u, (const T *)a.K, W,
+                         a.nx, a.ny, a.nz, lat, a.pitch, a.vol, a.nshots);
+      break;
+    case 3:
+      hipLaunchKernelGGL((k_grad_std<T, 3>), g2, b, 0, st, a.gK, (const T *)a.lam2, (const T *)a.u, (const T *)a.K, W,
+                         a.nx, a.ny, a.nz, lat, a.pitch, a.vol, a.nshots);
+      break;
+    default:
+      hipLaunchKernelGGL((k_grad_std<T, 4>), g2, b, 0, st, a.gK, (const T *)a.lam2, (const T *)a.u, (const T *)a.K, W,
+                         a.nx, a.ny, a.nz, lat, a.pitch, a.vol, a.nshots);
+      break;
+  }
+  if (a.nib > 0) {
+    int64_t nblk = ((a.nib + 3) / 4 + 7) / 8 * 8;
+    hipLaunchKernelGGL(k_grad_ib<T>, dim3((unsigned)nblk), dim3(256), 0, st, a.gK, (const T *)a.lam2,
+                       (const T *)a.u, a.rec, (const PInfo<T> *)a.pinfo, a.ball, a.delta, a.ball_meta, a.nib, a.nx,
+                       a.ny, a.nz, a.pitch, a.vol, a.nshots);
+  }
+}
+
+void enqueue_adjoint_step(const AdjArgs &a, hipStream_t st) {
+  if (a.prec == IB_F32)
+    adjoint_step_t<float>(a, st);
+  else
+    adjoint_step_t<double>(a, st);
+}
+
+void enqueue_grad_out(int prec, const double *gK, const void *K, double *out, int nx, int ny, int nz, int64_t pitch,
+                      double dt_over_h, hipStream_t st) {
+  int64_t per = (int64_t)nx * ny * nz;
+  dim3 g((unsigned)((per + 255) / 256)), b(256);
+  if (prec == IB_F32)
+    hipLaunchKernelGGL(k_grad_out<float>, g, b, 0, st, gK, (const float *)K, out, nx, ny, nz, pitch, dt_over_h);
+  else
+    hipLaunchKernelGGL(k_grad_out<double>, g, b, 0, st, gK, (const double *)K, out, nx, ny, nz, pitch, dt_over_h);
+}
+
 size_t pinfo_bytes(int prec) { return prec == IB_F32 ? sizeof(PInfo<float>) : sizeof(PInfo<double>); }
 
 // per-point records and per-layout offset tables of a state

@@ -1,0 +1,106 @@
+"""GPU adjoint (ib_forward / ib_adjoint through the C ABI) against the oracle adjoint and
+against central finite differences of the GPU forward model."""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+sys.path.insert(0, os.path.dirname(os.path.abspath(__file__)))
+from oracle_cases import model_for, simulation, solve_points  # noqa: E402
+
+from oracle.adjoint import forward_fields, gradient_c  # noqa: E402
+from paper_2309_03600_amd import workloads as W  # noqa: E402
+
+CASES = {
+    "2d-free": lambda: W.small2d(nx=48, nz=44, M=8, surface="free", nt=140, hill=30.0, cfg=96),
+    "2d-rigid": lambda: W.small2d(nx=48, nz=44, M=8, surface="rigid", nt=140, hill=30.0, cfg=97),
+    "3d-rigid": lambda: W.small3d(n=16, nz=40, relief=40.0, surface="rigid", nt=80, cfg=98, nshots=2),
+}
+
+
+def _anomaly(shape_zyx):
+    idx = np.indices(shape_zyx)
+    c = [n // 2 + 3 for n in shape_zyx]
+    r2 = sum((i - ci) ** 2 for i, ci in zip(idx, c))
+    return np.exp(-r2 / (2 * 4.0 ** 2))
+
+
+@pytest.mark.parametrize("name", list(CASES))
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_adjoint_gradient_matches_oracle(name, prec):
+    import torch
+
+    import paper_2309_03600_amd as ib
+    wl = CASES[name]()
+    print(f"[adjoint {name} {prec}] shape={wl.shape} shots={wl.src.shape[0]}", flush=True)
+    w = ib.ib_build_weights(wl.heights, wl.h, wl.shape, space_order=wl.M, surface=wl.surface, eta=wl.eta)
+    blob = _anomaly(wl.vel.shape)
+    v_true = wl.vel * (1 + 0.03 * blob)
+    dt = torch.float64 if prec == "f64" else torch.float32
+    wav = torch.tensor(wl.wavelets(np.float64), dtype=dt, device="cuda")
+    st_obs = ib.ib_state_create(w, v_true, wl.dt, wl.src, wl.rec, damp_width=0, precision=prec)
+    dobs = st_obs.forward(wl.nt, wav, ckpt_every=25)
+    st = ib.ib_state_create(w, wl.vel, wl.dt, wl.src, wl.rec, damp_width=0, precision=prec)
+    d = st.forward(wl.nt, wav, ckpt_every=25)
+    g = st.adjoint(d - dobs, wav).cpu().numpy().ravel()
+    # oracle gradient, summed over shots
+    m = model_for(wl)
+    sols = solve_points(m)
+    go = np.zeros_like(g)
+    for s in range(wl.src.shape[0]):
+        sim, L = simulation(wl, m, sols)
+        sim = type(sim)(m, L, wl.vel, wl.dt, wl.src[s:s + 1], wl.rec, damp_width=0)
+        tr, us = forward_fields(sim, wl.wavelets(np.float64)[s:s + 1], wl.nt)
+        simo = type(sim)(m, L, v_true, wl.dt, wl.src[s:s + 1], wl.rec, damp_width=0)
+        tro, _ = forward_fields(simo, wl.wavelets(np.float64)[s:s + 1], wl.nt)
+        go += gradient_c(sim, wl.vel, us, tr - tro)
+    err = np.linalg.norm(g - go) / np.linalg.norm(go)
+    print(f"[adjoint {name} {prec}] gradient rel-L2 vs oracle {err:.3e}")
+    assert err < (1e-9 if prec == "f64" else 2e-3)
+
+
+def test_adjoint_matches_finite_differences_fp64():
+    import torch
+
+    import paper_2309_03600_amd as ib
+    wl = CASES["2d-free"]()
+    w = ib.ib_build_weights(wl.heights, wl.h, wl.shape, space_order=wl.M, surface=wl.surface, eta=wl.eta)
+    wav = torch.tensor(wl.wavelets(np.float64), device="cuda")
+    blob = _anomaly(wl.vel.shape)
+    dobs = ib.ib_state_create(w, wl.vel * (1 + 0.03 * blob), wl.dt, wl.src, wl.rec,
+                              precision="f64").forward(wl.nt, wav)
+
+    def J(v):
+        st = ib.ib_state_create(w, v, wl.dt, wl.src, wl.rec, precision="f64")
+        d = st.forward(wl.nt, wav, ckpt_every=30)
+        return 0.5 * float(((d - dobs) ** 2).sum()), st, d
+
+    J0, st, d = J(wl.vel)
+    g = st.adjoint(d - dobs, wav).cpu().numpy()
+    rng = np.random.default_rng(2)
+    dv = 10.0 * _anomaly(wl.vel.shape) * (1 + 0.2 * rng.standard_normal(wl.vel.shape))
+    eps = 1e-3
+    fd = (J(wl.vel + eps * dv)[0] - J(wl.vel - eps * dv)[0]) / (2 * eps)
+    an = float(np.sum(g * dv))
+    print(f"[adjoint fd] fd {fd:.10e} adjoint {an:.10e}")
+    assert abs(fd - an) < 1e-6 * abs(fd)
+
+
+def test_autograd_function_fp32():
+    import torch
+
+    import paper_2309_03600_amd as ib
+    wl = CASES["2d-free"]()
+    w = ib.ib_build_weights(wl.heights, wl.h, wl.shape, space_order=wl.M, surface=wl.surface, eta=wl.eta)
+    wav = torch.tensor(wl.wavelets(np.float64), device="cuda")
+    v = torch.tensor(wl.vel, device="cuda", requires_grad=True)
+    tr = ib.modelling(v, w, wav, wl.src, wl.rec, wl.dt, wl.nt, precision="f32")
+    loss = 0.5 * (tr.double() ** 2).sum()
+    loss.backward()
+    st = ib.ib_state_create(w, wl.vel, wl.dt, wl.src, wl.rec, precision="f32")
+    d = st.forward(wl.nt, wav.float())
+    g = st.adjoint(d, wav.float())
+    assert torch.allclose(v.grad, g, rtol=1e-5, atol=1e-12 * float(g.abs().max()))
