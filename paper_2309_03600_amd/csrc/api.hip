@@ -30,7 +30,12 @@ struct ib_state {
   int cur = 0;                 // buf[cur] holds p^n
   void *K = nullptr, *sx = nullptr, *sy = nullptr, *sz = nullptr;
   void *scale = nullptr;
-  void *pinfo = nullptr;
+  void *pinfo = nullptr;       // all points, memory order (gradient kernels)
+  void *pinfo_t = nullptr;     // tiled points, tile order
+  void *pinfo_w = nullptr;     // wide-support points
+  int4 *tiles = nullptr;
+  int ntiles = 0;
+  int64_t nwide = 0;
   int32_t *delta = nullptr;
   int64_t *sidx = nullptr;
   void *sw = nullptr;
@@ -88,7 +93,11 @@ StepArgs make_args(ib_state *st, const void *wavelet, int64_t wstride, void *tra
   a.sz = st->sz;
   a.nib = w->nib;
   a.rec = (st->prec == IB_F32) ? w->rec32 : w->rec64;
-  a.pinfo = st->pinfo;
+  a.pinfo = st->pinfo_t;
+  a.tiles = st->tiles;
+  a.ntiles = st->ntiles;
+  a.pinfo_wide = st->pinfo_w;
+  a.nwide = st->nwide;
   a.delta = st->delta;
   a.ball = w->ball;
   a.ball_meta = w->ball_meta;
@@ -496,7 +505,58 @@ ib_status ib_state_create(const ib_weights *w, const double *vel_dev, double dt,
   if ((s = dalloc(&S->pinfo, std::max<int64_t>(w->nib, 1) * pinfo_bytes(prec))) ||
       (s = dalloc_t(&S->delta, std::max<size_t>(w->balls.packed.size(), 1))))
     return fail(s);
-  enqueue_make_pinfo(prec, w->ib_xyz, prec == IB_F32 ? w->rec_off32 : w->rec_off64, S->scale, w->nib, S->pinfo, st);
+  enqueue_make_pinfo(prec, w->ib_xyz, prec == IB_F32 ? w->rec_off32 : w->rec_off64, S->scale, nullptr, w->nib,
+                     S->pinfo, st);
+  {
+    // bucket the IB points into LDS tiles (3D); wider supports go to the gather kernel
+    std::vector<int16_t> xyz(w->nib * 4);
+    if (w->nib) IB_HIP(hipMemcpy(xyz.data(), w->ib_xyz, w->nib * 8, hipMemcpyDeviceToHost));
+    std::vector<int32_t> tiled, wide;
+    std::vector<int64_t> key;
+    const bool use_tiles = (w->ndim == 3);
+    const int64_t tx = (w->nx + kTileX - 1) / kTileX, ty = (w->ny + kTileY - 1) / kTileY;
+    for (int64_t i = 0; i < w->nib; ++i) {
+      const int code = xyz[i * 4 + 3];
+      if (use_tiles && code / 2 <= kTileHalo)
+        tiled.push_back((int32_t)i);
+      else
+        wide.push_back((int32_t)i);
+    }
+    auto tkey = [&](int32_t i) {
+      return ((int64_t)(xyz[i * 4 + 2] / kTileZ) * ty + xyz[i * 4 + 1] / kTileY) * tx + xyz[i * 4 + 0] / kTileX;
+    };
+    std::stable_sort(tiled.begin(), tiled.end(), [&](int32_t a, int32_t b) { return tkey(a) < tkey(b); });
+    std::vector<int4> tl;
+    for (size_t j = 0; j < tiled.size(); ++j) {
+      if (j == 0 || tkey(tiled[j]) != tkey(tiled[j - 1])) {
+        int32_t i = tiled[j];
+        tl.push_back(make_int4(xyz[i * 4] / kTileX * kTileX, xyz[i * 4 + 1] / kTileY * kTileY,
+                               xyz[i * 4 + 2] / kTileZ * kTileZ, (int)j));
+      }
+    }
+    tl.push_back(make_int4(0, 0, 0, (int)tiled.size()));
+    S->ntiles = (int)tl.size() - 1;
+    S->nwide = (int64_t)wide.size();
+    int32_t *d_perm = nullptr;
+    if ((s = dalloc(&S->pinfo_t, std::max<size_t>(tiled.size(), 1) * pinfo_bytes(prec))) ||
+        (s = dalloc(&S->pinfo_w, std::max<size_t>(wide.size(), 1) * pinfo_bytes(prec))) ||
+        (s = dalloc_t(&S->tiles, tl.size())) ||
+        (s = dalloc_t(&d_perm, std::max<size_t>(std::max(tiled.size(), wide.size()), 1))))
+      return fail(s);
+    IB_HIP(hipMemcpy(S->tiles, tl.data(), tl.size() * sizeof(int4), hipMemcpyHostToDevice));
+    const uint32_t *ro = (prec == IB_F32) ? w->rec_off32 : w->rec_off64;
+    if (!tiled.empty()) {
+      IB_HIP(hipMemcpy(d_perm, tiled.data(), tiled.size() * 4, hipMemcpyHostToDevice));
+      enqueue_make_pinfo(prec, w->ib_xyz, ro, S->scale, d_perm, (int64_t)tiled.size(), S->pinfo_t, st);
+      IB_HIP(hipStreamSynchronize(st));
+    }
+    if (!wide.empty()) {
+      IB_HIP(hipMemcpy(d_perm, wide.data(), wide.size() * 4, hipMemcpyHostToDevice));
+      enqueue_make_pinfo(prec, w->ib_xyz, ro, S->scale, d_perm, (int64_t)wide.size(), S->pinfo_w, st);
+      IB_HIP(hipStreamSynchronize(st));
+    }
+    dfree(d_perm);
+  }
   enqueue_make_delta(w->ball, (int)w->balls.packed.size(), S->pitch, S->pitch * w->ny, S->delta, st);
   IB_HIP(hipGetLastError());
   IB_HIP(hipStreamSynchronize(st));
@@ -581,6 +641,9 @@ void ib_state_free(ib_state *S) {
   dfree(S->sz);
   dfree(S->scale);
   dfree(S->pinfo);
+  dfree(S->pinfo_t);
+  dfree(S->pinfo_w);
+  dfree(S->tiles);
   dfree(S->delta);
   dfree(S->sidx);
   dfree(S->sw);

@@ -8,6 +8,9 @@
 
 namespace ib {
 
+// LDS tile of the 3D IB patch (points of support radius <= kTileHalo + 1/2)
+constexpr int kTileX = 16, kTileY = 16, kTileZ = 16, kTileHalo = 4;
+
 struct StepArgs {
   int prec;
   int ndim, M;
@@ -22,7 +25,11 @@ struct StepArgs {
   // IB patch
   int64_t nib;
   const uint32_t *rec;
-  const void *pinfo;          // per-point records (position, code, offset, scale)
+  const void *pinfo;          // per-point records (position, code, offset, scale), tile order
+  const int4 *tiles;          // [ntiles + 1]: x0, y0, z0, first point (the last holds the end)
+  int ntiles;
+  const void *pinfo_wide;     // points handled by the gather kernel
+  int64_t nwide;
   const int32_t *ball;
   const int32_t *delta;       // linear offsets of the ball lattice points for this layout
   const int32_t *ball_meta;   // [code][2]: start, count
@@ -77,8 +84,8 @@ struct AdjArgs {
 void enqueue_adjoint_step(const AdjArgs &a, hipStream_t st);
 void enqueue_grad_out(int prec, const double *gK, const void *K, double *out, int nx, int ny, int nz, int64_t pitch,
                       double dt_over_h, hipStream_t st);
-void enqueue_make_pinfo(int prec, const int16_t *xyz, const uint32_t *roff, const void *scale, int64_t nib,
-                        void *out, hipStream_t st);
+void enqueue_make_pinfo(int prec, const int16_t *xyz, const uint32_t *roff, const void *scale, const int32_t *perm,
+                        int64_t n, void *out, hipStream_t st);
 void enqueue_make_delta(const int32_t *ball, int n, int64_t pitch, int64_t plane, int32_t *delta, hipStream_t st);
 
 }  // namespace ib

@@ -271,6 +271,84 @@ __global__ void k_patch(const T *__restrict__ un, T *__restrict__ unew, const ui
   }
 }
 
+// ---- IB patch, LDS-tiled (3D) -------------------------------------------------------
+// IB points are bucketed into TX x TY x TZ tiles (host, at state creation).  A workgroup
+// stages p^n over its tile plus an HR-cell halo in LDS with coalesced row loads, then its
+// wavefronts evaluate the extrapolation sums of the tile's points from LDS: the support
+// balls of neighbouring points overlap almost entirely, so each p^n value is fetched
+// once per tile instead of once per support it belongs to.  Points whose support radius
+// exceeds HR + 1/2 are kept on the gather kernel above.
+template <typename T, int TX, int TY, int TZ, int HR>
+__launch_bounds__(512)
+__global__ void k_patch_tiled(const T *__restrict__ un, T *__restrict__ unew, const uint32_t *__restrict__ rec,
+                              const PInfo<T> *__restrict__ pinfo, const int32_t *__restrict__ ball,
+                              const int32_t *__restrict__ ball_meta, const int4 *__restrict__ tiles, int ntiles,
+                              int nx, int ny, int nz, int64_t pitch, int64_t vol, int nshots) {
+  constexpr int LX = TX + 2 * HR, LY = TY + 2 * HR, LZ = TZ + 2 * HR;
+  __shared__ T sp[LZ * LY * LX];
+  const int64_t tb = xcd_remap(blockIdx.x, gridDim.x);
+  if (tb >= ntiles) return;
+  const int4 tl = tiles[tb];
+  const int x0 = tl.x, y0 = tl.y, z0 = tl.z;
+  const int p0 = tl.w, p1 = tiles[tb + 1].w;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwave = blockDim.x >> 6;
+  const int64_t plane = pitch * ny;
+  for (int s = 0; s < nshots; ++s) {
+    const T *u = un + (size_t)s * vol;
+    for (int e = threadIdx.x; e < LZ * LY * LX; e += blockDim.x) {
+      const int lx = e % LX, ly = (e / LX) % LY, lz = e / (LX * LY);
+      const int gz = z0 - HR + lz;
+      const int gx = wrapk(x0 - HR + lx, nx), gy = wrapk(y0 - HR + ly, ny);
+      sp[e] = (gz >= 0 && gz < nz) ? u[(size_t)gz * plane + (size_t)gy * pitch + gx] : T(0);
+    }
+    __syncthreads();
+    for (int p = p0 + wave; p < p1; p += nwave) {
+      const PInfo<T> P = pinfo[p];
+      const int code = P.code;
+      const int bstart = ball_meta[2 * code], nb = ball_meta[2 * code + 1];
+      const int nwords = (nb + 31) >> 5;
+      const uint32_t *m = rec + P.roff;
+      const int wpad = (sizeof(T) == 8) ? ((nwords + 1) & ~1) : nwords;
+      const T *wts = reinterpret_cast<const T *>(m + wpad);
+      const uint32_t mw = (lane < nwords) ? m[lane] : 0u;
+      int cx = P.x - x0;
+      if (cx < 0) cx += nx;
+      int cy = P.y - y0;
+      if (cy < 0) cy += ny;
+      const int lc = ((P.z - z0 + HR) * LY + (cy + HR)) * LX + (cx + HR);
+      const int32_t *bl = ball + bstart;
+      T acc = T(0);
+      int wbase = 0;
+      for (int g0 = 0; g0 * 64 < nb; g0 += 8) {
+        int widx[8], lofs[8];
+        bool ok[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+          const int b = (g0 + k) * 64 + lane;
+          const uint32_t word = (uint32_t)__shfl((int)mw, (b >> 5) & 63);
+          const int bit = (b < nb) ? (int)((word >> (b & 31)) & 1u) : 0;
+          const unsigned long long bal = __ballot(bit);
+          widx[k] = wbase + __popcll(bal & ((1ull << lane) - 1ull));
+          wbase += __popcll(bal);
+          ok[k] = bit != 0;
+          const uint32_t v = bit ? (uint32_t)bl[b] : 0u;
+          const int dx = (int8_t)(v & 255), dy = (int8_t)((v >> 8) & 255), dz = (int8_t)((v >> 16) & 255);
+          lofs[k] = lc + (dz * LY + dy) * LX + dx;
+        }
+        T wv[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) wv[k] = ok[k] ? wts[widx[k]] : T(0);
+#pragma unroll
+        for (int k = 0; k < 8; ++k)
+          if (ok[k]) acc += wv[k] * sp[lofs[k]];
+      }
+      for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
+      if (lane == 0) unew[(size_t)s * vol + (size_t)P.z * plane + (size_t)P.y * pitch + P.x] += P.scale * acc;
+    }
+    __syncthreads();
+  }
+}
+
 // ---- sources and receivers ---------------------------------------------------------
 template <typename T>
 __global__ void k_inject(T *unew, const int64_t *sidx, const T *sw, int nshots, int64_t vol, const T *wavelet,
@@ -356,14 +434,25 @@ static void launch_interior(const StepArgs &a, hipStream_t st) {
 }
 
 template <typename T>
+static void launch_patch(const StepArgs &a, hipStream_t st) {
+  if (a.ntiles > 0) {
+    int64_t nblk = ((int64_t)a.ntiles + 7) / 8 * 8;
+    hipLaunchKernelGGL((k_patch_tiled<T, kTileX, kTileY, kTileZ, kTileHalo>), dim3((unsigned)nblk), dim3(512), 0, st,
+                       (const T *)a.un, (T *)a.um, a.rec, (const PInfo<T> *)a.pinfo, a.ball, a.ball_meta, a.tiles,
+                       a.ntiles, a.nx, a.ny, a.nz, a.pitch, a.vol, a.nshots);
+  }
+  if (a.nwide > 0) {
+    int64_t nblk = ((a.nwide + 3) / 4 + 7) / 8 * 8;
+    hipLaunchKernelGGL(k_patch<T>, dim3((unsigned)nblk), dim3(256), 0, st, (const T *)a.un, (T *)a.um, a.rec,
+                       (const PInfo<T> *)a.pinfo_wide, a.ball, a.delta, a.ball_meta, a.nwide, a.nx, a.ny, a.nz,
+                       a.pitch, a.vol, a.nshots);
+  }
+}
+
+template <typename T>
 static void launch_step(const StepArgs &a, hipStream_t st) {
   launch_interior<T>(a, st);
-  if (a.nib > 0) {
-    int64_t nblk = ((a.nib + 3) / 4 + 7) / 8 * 8;
-    hipLaunchKernelGGL(k_patch<T>, dim3((unsigned)nblk), dim3(256), 0, st, (const T *)a.un, (T *)a.um, a.rec,
-                       (const PInfo<T> *)a.pinfo, a.ball, a.delta, a.ball_meta, a.nib, a.nx, a.ny, a.nz, a.pitch,
-                       a.vol, a.nshots);
-  }
+  launch_patch<T>(a, st);
   hipLaunchKernelGGL(k_inject<T>, dim3(1), dim3(256), 0, st, (T *)a.um, a.sidx, (const T *)a.sw, a.nshots, a.vol,
                      (const T *)a.wavelet, a.wstride, a.tcount);
   if (a.nrec > 0 && a.traces) {
@@ -388,16 +477,10 @@ void enqueue_interior_only(const StepArgs &a, hipStream_t st) {
 }
 
 void enqueue_patch_only(const StepArgs &a, hipStream_t st) {
-  if (a.nib <= 0) return;
-  int64_t nblk = ((a.nib + 3) / 4 + 7) / 8 * 8;
   if (a.prec == IB_F32)
-    hipLaunchKernelGGL(k_patch<float>, dim3((unsigned)nblk), dim3(256), 0, st, (const float *)a.un, (float *)a.um,
-                       a.rec, (const PInfo<float> *)a.pinfo, a.ball, a.delta, a.ball_meta, a.nib, a.nx, a.ny, a.nz,
-                       a.pitch, a.vol, a.nshots);
+    launch_patch<float>(a, st);
   else
-    hipLaunchKernelGGL(k_patch<double>, dim3((unsigned)nblk), dim3(256), 0, st, (const double *)a.un, (double *)a.um,
-                       a.rec, (const PInfo<double> *)a.pinfo, a.ball, a.delta, a.ball_meta, a.nib, a.nx, a.ny, a.nz,
-                       a.pitch, a.vol, a.nshots);
+    launch_patch<double>(a, st);
 }
 
 // ---- discrete adjoint ----------------------------------------------------------------
@@ -656,9 +739,11 @@ size_t pinfo_bytes(int prec) { return prec == IB_F32 ? sizeof(PInfo<float>) : si
 
 // per-point records and per-layout offset tables of a state
 template <typename T>
-__global__ void k_make_pinfo(const int16_t *xyz, const uint32_t *roff, const T *scale, int64_t nib, PInfo<T> *out) {
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= nib) return;
+__global__ void k_make_pinfo(const int16_t *xyz, const uint32_t *roff, const T *scale, const int32_t *perm,
+                             int64_t nib, PInfo<T> *out) {
+  int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= nib) return;
+  const int64_t i = perm ? perm[j] : j;
   PInfo<T> p;
   p.x = xyz[i * 4];
   p.y = xyz[i * 4 + 1];
@@ -667,7 +752,7 @@ __global__ void k_make_pinfo(const int16_t *xyz, const uint32_t *roff, const T *
   p.roff = roff[i];
   p.pad = 0;
   p.scale = scale[i];
-  out[i] = p;
+  out[j] = p;
 }
 
 __global__ void k_make_delta(const int32_t *ball, int n, int64_t pitch, int64_t plane, int32_t *delta) {
@@ -678,15 +763,15 @@ __global__ void k_make_delta(const int32_t *ball, int n, int64_t pitch, int64_t 
   delta[i] = (int32_t)(dz * plane + dy * pitch + dx);
 }
 
-void enqueue_make_pinfo(int prec, const int16_t *xyz, const uint32_t *roff, const void *scale, int64_t nib,
-                        void *out, hipStream_t st) {
-  if (nib <= 0) return;
+void enqueue_make_pinfo(int prec, const int16_t *xyz, const uint32_t *roff, const void *scale, const int32_t *perm,
+                        int64_t n, void *out, hipStream_t st) {
+  if (n <= 0) return;
   if (prec == IB_F32)
-    hipLaunchKernelGGL(k_make_pinfo<float>, dim3((unsigned)((nib + 255) / 256)), dim3(256), 0, st, xyz, roff,
-                       (const float *)scale, nib, (PInfo<float> *)out);
+    hipLaunchKernelGGL(k_make_pinfo<float>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, xyz, roff,
+                       (const float *)scale, perm, n, (PInfo<float> *)out);
   else
-    hipLaunchKernelGGL(k_make_pinfo<double>, dim3((unsigned)((nib + 255) / 256)), dim3(256), 0, st, xyz, roff,
-                       (const double *)scale, nib, (PInfo<double> *)out);
+    hipLaunchKernelGGL(k_make_pinfo<double>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, xyz, roff,
+                       (const double *)scale, perm, n, (PInfo<double> *)out);
 }
 
 void enqueue_make_delta(const int32_t *ball, int n, int64_t pitch, int64_t plane, int32_t *delta, hipStream_t st) {

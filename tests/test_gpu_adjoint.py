@@ -15,8 +15,8 @@ from oracle.adjoint import forward_fields, gradient_c  # noqa: E402
 from paper_2309_03600_amd import workloads as W  # noqa: E402
 
 CASES = {
-    "2d-free": lambda: W.small2d(nx=48, nz=44, M=8, surface="free", nt=140, hill=30.0, cfg=96),
-    "2d-rigid": lambda: W.small2d(nx=48, nz=44, M=8, surface="rigid", nt=140, hill=30.0, cfg=97),
+    "2d-free": lambda: W.small2d(nx=48, nz=56, M=8, surface="free", nt=140, hill=30.0, cfg=96),
+    "2d-rigid": lambda: W.small2d(nx=48, nz=56, M=8, surface="rigid", nt=140, hill=30.0, cfg=97),
     "3d-rigid": lambda: W.small3d(n=16, nz=40, relief=40.0, surface="rigid", nt=80, cfg=98, nshots=2),
 }
 
