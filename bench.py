@@ -101,6 +101,7 @@ def main():
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--zchunk", type=int, default=-1)
+    ap.add_argument("--variant", type=int, default=-1)
     ap.add_argument("--graph", type=int, default=1)
     args = ap.parse_args()
     if args.gpus != 1:
@@ -130,8 +131,8 @@ def main():
     for prec in (["f32"] if args.no_fp64 else ["f32", "f64"]):
         dt = torch.float32 if prec == "f32" else torch.float64
         st = ib.ib_state_create(w, wl.vel, wl.dt, wl.src, wl.rec, damp_width=wl.damp_width, precision=prec)
-        if args.zchunk >= 0:
-            st.set_zchunk(args.zchunk)
+        if args.zchunk >= 0 or args.variant >= 0:
+            st.set_tuning(args.variant if args.variant >= 0 else 1, max(args.zchunk, 0))
         wav = torch.tensor(wl.wavelets(np.float64), dtype=dt, device="cuda")
         tr_w = torch.empty((1, Wm, st.nrec), dtype=dt, device="cuda")
         tr = torch.empty((1, K, st.nrec), dtype=dt, device="cuda")

@@ -105,6 +105,9 @@ typedef struct {
   int64_t table_bytes_f64;
   int64_t max_ball;          /* largest support ball (lattice points) used               */
   double build_ms;           /* wall time of ib_build_weights                            */
+  int64_t dense_weights;     /* entries of the dense-range records streamed by the 3D patch
+                                kernel (>= sum_nw; zeros fill non-data lattice points
+                                between a support's first and last data point)          */
 } ib_stats;
 
 typedef struct ib_weights ib_weights;
@@ -215,9 +218,11 @@ int64_t ib_state_step_count(const ib_state *st);
  * time each kernel on its own; it changes the wavefields. */
 ib_status ib_state_run_kernel(ib_state *st, int32_t which, int32_t count, void *stream);
 
-/* Tuning knob of the 3D eighth-order interior kernel: depth planes per workgroup
- * (0 = whole depth).  Results do not depend on it. */
-ib_status ib_state_set_zchunk(ib_state *st, int32_t zchunk);
+/* Tuning knobs of the 3D eighth-order interior kernel: variant 0 (one plane per barrier
+ * pair), 1 (software-pipelined, 64x16 tiles, default), 2 (pipelined, 64x32 tiles), and
+ * depth planes per workgroup (0 = automatic: enough workgroups to fill the device).
+ * Results do not depend on them. */
+ib_status ib_state_set_tuning(ib_state *st, int32_t variant, int32_t zchunk);
 
 #ifdef __cplusplus
 }

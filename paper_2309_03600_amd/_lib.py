@@ -29,7 +29,7 @@ class ib_stats(C.Structure):
                 ("n_ib", C.c_int64), ("sum_nw", C.c_int64), ("max_nw", C.c_int64),
                 ("radius_hist", C.c_int64 * 8), ("order_hist", C.c_int64 * 17), ("max_cond", C.c_double),
                 ("min_margin", C.c_double), ("table_bytes_f32", C.c_int64), ("table_bytes_f64", C.c_int64),
-                ("max_ball", C.c_int64), ("build_ms", C.c_double)]
+                ("max_ball", C.c_int64), ("build_ms", C.c_double), ("dense_weights", C.c_int64)]
 
 
 EXPORTS = {
@@ -49,7 +49,7 @@ EXPORTS = {
     "ib_adjoint": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p]),
     "ib_state_field": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_void_p, C.c_int32, C.c_void_p]),
     "ib_state_step_count": (C.c_int64, [C.c_void_p]),
-    "ib_state_set_zchunk": (C.c_int, [C.c_void_p, C.c_int32]),
+    "ib_state_set_tuning": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32]),
     "ib_state_run_kernel": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_void_p]),
 }
 

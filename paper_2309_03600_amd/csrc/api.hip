@@ -46,6 +46,8 @@ struct ib_state {
   int64_t t = 0;
   double dt = 0.0;
   int zchunk = 0;
+  int zchunk_auto = 0;
+  int variant = 1;
   // captured two-step graph
   hipGraphExec_t gexec = nullptr;
   hipGraph_t graph = nullptr;
@@ -85,6 +87,7 @@ StepArgs make_args(ib_state *st, const void *wavelet, int64_t wstride, void *tra
   a.vol = st->vol;
   a.nshots = st->nshots;
   a.zchunk = st->zchunk;
+  a.variant = st->variant;
   a.un = st->buf[cur];
   a.um = st->buf[1 - cur];
   a.K = st->K;
@@ -94,6 +97,7 @@ StepArgs make_args(ib_state *st, const void *wavelet, int64_t wstride, void *tra
   a.nib = w->nib;
   a.rec = (st->prec == IB_F32) ? w->rec32 : w->rec64;
   a.pinfo = st->pinfo_t;
+  a.dense = (st->prec == IB_F32) ? (const void *)w->dense32 : (const void *)w->dense64;
   a.tiles = st->tiles;
   a.ntiles = st->ntiles;
   a.pinfo_wide = st->pinfo_w;
@@ -369,6 +373,11 @@ void ib_weights_free(ib_weights *w) {
   dfree(w->rec_off64);
   dfree(w->ball);
   dfree(w->ball_meta);
+  dfree(w->dense32);
+  dfree(w->dense64);
+  dfree(w->dense_first);
+  dfree(w->dense_count);
+  dfree(w->dense_off);
   delete w;
 }
 
@@ -538,7 +547,7 @@ ib_status ib_state_create(const ib_weights *w, const double *vel_dev, double dt,
     S->ntiles = (int)tl.size() - 1;
     S->nwide = (int64_t)wide.size();
     int32_t *d_perm = nullptr;
-    if ((s = dalloc(&S->pinfo_t, std::max<size_t>(tiled.size(), 1) * pinfo_bytes(prec))) ||
+    if ((s = dalloc(&S->pinfo_t, std::max<size_t>(tiled.size(), 1) * pinfo_dense_bytes(prec))) ||
         (s = dalloc(&S->pinfo_w, std::max<size_t>(wide.size(), 1) * pinfo_bytes(prec))) ||
         (s = dalloc_t(&S->tiles, tl.size())) ||
         (s = dalloc_t(&d_perm, std::max<size_t>(std::max(tiled.size(), wide.size()), 1))))
@@ -547,7 +556,8 @@ ib_status ib_state_create(const ib_weights *w, const double *vel_dev, double dt,
     const uint32_t *ro = (prec == IB_F32) ? w->rec_off32 : w->rec_off64;
     if (!tiled.empty()) {
       IB_HIP(hipMemcpy(d_perm, tiled.data(), tiled.size() * 4, hipMemcpyHostToDevice));
-      enqueue_make_pinfo(prec, w->ib_xyz, ro, S->scale, d_perm, (int64_t)tiled.size(), S->pinfo_t, st);
+      enqueue_make_pinfo_dense(prec, w->ib_xyz, w->dense_first, w->dense_count, w->dense_off, S->scale, d_perm,
+                               (int64_t)tiled.size(), S->pinfo_t, st);
       IB_HIP(hipStreamSynchronize(st));
     }
     if (!wide.empty()) {
@@ -624,6 +634,7 @@ ib_status ib_state_create(const ib_weights *w, const double *vel_dev, double dt,
     int64_t want = 2048;
     int nzc = (int)std::max<int64_t>(1, std::min<int64_t>(w->nz / 16, (want + tiles - 1) / tiles));
     S->zchunk = (int)((w->nz + nzc - 1) / nzc);
+    S->zchunk_auto = S->zchunk;
   }
   *out = S;
   return IB_OK;
@@ -658,12 +669,13 @@ void ib_state_free(ib_state *S) {
 
 int64_t ib_state_step_count(const ib_state *S) { return S ? S->t : -1; }
 
-ib_status ib_state_set_zchunk(ib_state *S, int32_t zchunk) {
-  if (!S || zchunk < 0) {
-    set_error("ib_state_set_zchunk: invalid argument");
+ib_status ib_state_set_tuning(ib_state *S, int32_t variant, int32_t zchunk) {
+  if (!S || zchunk < 0 || variant < 0 || variant > 2) {
+    set_error("ib_state_set_tuning: invalid argument");
     return IB_ERR_ARG;
   }
-  S->zchunk = zchunk > 0 ? zchunk : (int)S->w->nz;
+  S->variant = variant;
+  S->zchunk = zchunk > 0 ? zchunk : S->zchunk_auto;
   if (S->gexec) {
     (void)hipGraphExecDestroy(S->gexec);
     (void)hipGraphDestroy(S->graph);

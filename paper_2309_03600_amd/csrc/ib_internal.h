@@ -90,6 +90,13 @@ struct ib_weights {
   uint32_t *rec_off32 = nullptr;   // [nib] offsets in 32-bit units
   uint32_t *rec_off64 = nullptr;
   int64_t rec32_words = 0, rec64_words = 0;
+  // dense-range records (weights of every ball lattice point between the first and the
+  // last data point of each support, zero where not data)
+  float *dense32 = nullptr;
+  double *dense64 = nullptr;
+  int32_t *dense_first = nullptr, *dense_count = nullptr;
+  uint32_t *dense_off = nullptr;
+  int64_t dense_words = 0;
   int32_t *ball = nullptr;         // packed ball tables
   int32_t *ball_meta = nullptr;    // [code][2] start, count (device)
   ib::BallTables balls;

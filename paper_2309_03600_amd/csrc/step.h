@@ -9,7 +9,7 @@
 namespace ib {
 
 // LDS tile of the 3D IB patch (points of support radius <= kTileHalo + 1/2)
-constexpr int kTileX = 16, kTileY = 16, kTileZ = 16, kTileHalo = 4;
+constexpr int kTileX = 8, kTileY = 8, kTileZ = 8, kTileHalo = 4;
 
 struct StepArgs {
   int prec;
@@ -18,6 +18,7 @@ struct StepArgs {
   int64_t pitch, vol;
   int nshots;
   int zchunk;
+  int variant;          // 3D M=8 interior kernel: 0 basic, 1 pipelined 64x16, 2 pipelined 64x32
   const void *un;       // p^n
   void *um;             // p^{n-1} in, p^{n+1} out
   const void *K;
@@ -25,7 +26,8 @@ struct StepArgs {
   // IB patch
   int64_t nib;
   const uint32_t *rec;
-  const void *pinfo;          // per-point records (position, code, offset, scale), tile order
+  const void *pinfo;          // dense-range point records of the tiled points, tile order
+  const void *dense;          // dense-range weights (state precision)
   const int4 *tiles;          // [ntiles + 1]: x0, y0, z0, first point (the last holds the end)
   int ntiles;
   const void *pinfo_wide;     // points handled by the gather kernel
@@ -50,6 +52,10 @@ void enqueue_step(const StepArgs &a, hipStream_t st);
 void enqueue_interior_only(const StepArgs &a, hipStream_t st);
 void enqueue_patch_only(const StepArgs &a, hipStream_t st);
 size_t pinfo_bytes(int prec);
+size_t pinfo_dense_bytes(int prec);
+void enqueue_make_pinfo_dense(int prec, const int16_t *xyz, const int32_t *first, const int32_t *count,
+                              const uint32_t *doff, const void *scale, const int32_t *perm, int64_t n, void *out,
+                              hipStream_t st);
 
 // One adjoint step (lambda^m from lambda^{m+1}, lambda^{m+2}) and its gradient term.
 struct AdjArgs {

@@ -148,6 +148,137 @@ __global__ void k_interior3d(const T *__restrict__ un, T *__restrict__ um, const
   }
 }
 
+// ---- 3D interior, software-pipelined ---------------------------------------------
+// Same tiling as k_interior3d, but everything plane z+1 needs from memory (the queue's
+// new plane, p^{n-1}, K and the LDS halo of the centre plane) is requested during plane
+// z, and the LDS centre plane is double buffered so one barrier per plane suffices.
+template <typename T, int H, int RY>
+__launch_bounds__(256)
+__global__ void k_interior3d_p(const T *__restrict__ un, T *__restrict__ um, const T *__restrict__ K,
+                               const T *__restrict__ sx, const T *__restrict__ sy, const T *__restrict__ sz,
+                               StencilW<T> W, int nx, int ny, int nz, int64_t pitch, int64_t vol, int zchunk,
+                               int ntx, int nty, int nzc, int nshots) {
+  constexpr int TX = 64, TY = 4 * RY, LX = TX + 2 * H, LY = TY + 2 * H;
+  __shared__ T tile[2][LY][LX];
+  const int64_t nblk = (int64_t)ntx * nty * nzc * nshots;
+  int64_t L = xcd_remap(blockIdx.x, gridDim.x);
+  if (L >= nblk) return;
+  const int bxi = (int)(L % ntx);
+  L /= ntx;
+  const int byi = (int)(L % nty);
+  L /= nty;
+  const int bzi = (int)(L % nzc);
+  const int shot = (int)(L / nzc);
+  const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+  const int x0 = bxi * TX, y0 = byi * TY;
+  const int z0 = bzi * zchunk, z1 = min(nz, z0 + zchunk);
+  const int64_t plane = pitch * ny;
+  const T *u = un + (size_t)shot * vol;
+  T *o = um + (size_t)shot * vol;
+  const int xg = x0 + tx;
+  const int xw = xg % nx;
+  const bool xin = xg < nx;
+  size_t rowoff[RY];
+  bool yin[RY];
+  int ywv[RY];
+#pragma unroll
+  for (int r = 0; r < RY; ++r) {
+    int yg = y0 + ty * RY + r;
+    yin[r] = yg < ny;
+    ywv[r] = yg % ny;
+    rowoff[r] = (size_t)ywv[r] * pitch + xw;
+  }
+  // halo sources of this thread (x halo: up to RY values; y halo: 2 values)
+  const bool xl = tx < H, xr = tx >= TX - H;
+  const int xh = xl ? ((x0 - H + tx) % nx + nx) % nx : (xr ? (x0 + TX + (tx - (TX - H))) % nx : 0);
+  const int lxh = xl ? tx : (xr ? TX + H + (tx - (TX - H)) : 0);
+  size_t hyoff[2];
+  int hyly[2], hylx[2];
+  const int t = threadIdx.x;
+#pragma unroll
+  for (int i = 0; i < 2; ++i) {
+    int idx = t + i * 256;
+    int hr = idx / TX, hc = idx % TX;
+    int yg = (hr < H) ? y0 - H + hr : y0 + TY + (hr - H);
+    int yy = ((yg % ny) + ny) % ny;
+    hyoff[i] = (size_t)yy * pitch + (x0 + hc) % nx;
+    hyly[i] = (hr < H) ? hr : TY + H + (hr - H);
+    hylx[i] = H + hc;
+  }
+  T q[RY][2 * H + 1];
+#pragma unroll
+  for (int r = 0; r < RY; ++r) {
+#pragma unroll
+    for (int k = 0; k <= 2 * H; ++k) {
+      int z = z0 - H + k;
+      q[r][k] = (z >= 0 && z < nz) ? u[(size_t)z * plane + rowoff[r]] : T(0);
+    }
+  }
+  T pm[RY], kk[RY], hx[RY], hy[2];
+#pragma unroll
+  for (int r = 0; r < RY; ++r) {
+    pm[r] = o[(size_t)z0 * plane + rowoff[r]];
+    kk[r] = K[(size_t)z0 * plane + rowoff[r]];
+    hx[r] = (xl || xr) ? u[(size_t)z0 * plane + (size_t)ywv[r] * pitch + xh] : T(0);
+  }
+#pragma unroll
+  for (int i = 0; i < 2; ++i) hy[i] = u[(size_t)z0 * plane + hyoff[i]];
+  int buf = 0;
+  for (int z = z0; z < z1; ++z) {
+    // centre plane and its halo into LDS
+#pragma unroll
+    for (int r = 0; r < RY; ++r) tile[buf][H + ty * RY + r][H + tx] = q[r][H];
+    if (xl || xr) {
+#pragma unroll
+      for (int r = 0; r < RY; ++r) tile[buf][H + ty * RY + r][lxh] = hx[r];
+    }
+#pragma unroll
+    for (int i = 0; i < 2; ++i) tile[buf][hyly[i]][hylx[i]] = hy[i];
+    // requests for the next plane
+    T nq[RY], npm[RY], nk[RY], nhx[RY], nhy[2];
+    const int zn = z + 1;
+    const bool more = zn < z1;
+    const size_t znoff = (size_t)zn * plane;
+    const int zq = z + H + 1;
+#pragma unroll
+    for (int r = 0; r < RY; ++r) {
+      nq[r] = (zq < nz) ? u[(size_t)zq * plane + rowoff[r]] : T(0);
+      npm[r] = more ? o[znoff + rowoff[r]] : T(0);
+      nk[r] = more ? K[znoff + rowoff[r]] : T(0);
+      nhx[r] = (more && (xl || xr)) ? u[znoff + (size_t)ywv[r] * pitch + xh] : T(0);
+    }
+#pragma unroll
+    for (int i = 0; i < 2; ++i) nhy[i] = more ? u[znoff + hyoff[i]] : T(0);
+    __syncthreads();
+    const T sxz = sx[xw] + sz[z];
+#pragma unroll
+    for (int r = 0; r < RY; ++r) {
+      const int ly = H + ty * RY + r, lx = H + tx;
+      const T c = q[r][H];
+      T lap = T(3) * W.w[0] * c;
+#pragma unroll
+      for (int k = 1; k <= H; ++k)
+        lap += W.w[k] * ((tile[buf][ly][lx - k] + tile[buf][ly][lx + k]) +
+                         (tile[buf][ly - k][lx] + tile[buf][ly + k][lx]) + (q[r][H - k] + q[r][H + k]));
+      const T s = sxz + sy[ywv[r]];
+      const T v = (T(2) * c - (T(1) - s) * pm[r] + kk[r] * lap) / (T(1) + s);
+      if (xin && yin[r]) o[(size_t)z * plane + rowoff[r]] = v;
+    }
+#pragma unroll
+    for (int r = 0; r < RY; ++r) {
+#pragma unroll
+      for (int k = 0; k < 2 * H; ++k) q[r][k] = q[r][k + 1];
+      q[r][2 * H] = nq[r];
+      pm[r] = npm[r];
+      kk[r] = nk[r];
+      hx[r] = nhx[r];
+    }
+    hy[0] = nhy[0];
+    hy[1] = nhy[1];
+    buf ^= 1;
+  }
+}
+
 // ---- generic interior (2D, or 3D with other orders): one thread per node ------------
 template <typename T, int H>
 __global__ void k_interior_generic(const T *__restrict__ un, T *__restrict__ um, const T *__restrict__ K,
@@ -273,15 +404,24 @@ __global__ void k_patch(const T *__restrict__ un, T *__restrict__ unew, const ui
 
 // ---- IB patch, LDS-tiled (3D) -------------------------------------------------------
 // IB points are bucketed into TX x TY x TZ tiles (host, at state creation).  A workgroup
-// stages p^n over its tile plus an HR-cell halo in LDS with coalesced row loads, then its
-// wavefronts evaluate the extrapolation sums of the tile's points from LDS: the support
-// balls of neighbouring points overlap almost entirely, so each p^n value is fetched
-// once per tile instead of once per support it belongs to.  Points whose support radius
-// exceeds HR + 1/2 are kept on the gather kernel above.
+// stages p^n over its tile plus an HR-cell halo in LDS with coalesced row loads; its
+// wavefronts then evaluate the tile's points from LDS, each streaming the point's
+// dense-range weights (coalesced, no mask decoding) while the next point's record is
+// already in flight.  The support balls of neighbouring points overlap almost entirely,
+// so each p^n value is fetched from memory about once per tile.  Points whose support
+// radius exceeds HR + 1/2 stay on the gather kernel above.
+template <typename T>
+struct alignas(16) PInfoD {
+  int16_t x, y, z, code;
+  uint16_t first, count;
+  uint32_t woff;
+  T scale;
+};
+
 template <typename T, int TX, int TY, int TZ, int HR>
-__launch_bounds__(512)
-__global__ void k_patch_tiled(const T *__restrict__ un, T *__restrict__ unew, const uint32_t *__restrict__ rec,
-                              const PInfo<T> *__restrict__ pinfo, const int32_t *__restrict__ ball,
+__launch_bounds__(256)
+__global__ void k_patch_tiled(const T *__restrict__ un, T *__restrict__ unew, const T *__restrict__ dense,
+                              const PInfoD<T> *__restrict__ pinfo, const int32_t *__restrict__ ball,
                               const int32_t *__restrict__ ball_meta, const int4 *__restrict__ tiles, int ntiles,
                               int nx, int ny, int nz, int64_t pitch, int64_t vol, int nshots) {
   constexpr int LX = TX + 2 * HR, LY = TY + 2 * HR, LZ = TZ + 2 * HR;
@@ -302,51 +442,77 @@ __global__ void k_patch_tiled(const T *__restrict__ un, T *__restrict__ unew, co
       sp[e] = (gz >= 0 && gz < nz) ? u[(size_t)gz * plane + (size_t)gy * pitch + gx] : T(0);
     }
     __syncthreads();
-    for (int p = p0 + wave; p < p1; p += nwave) {
-      const PInfo<T> P = pinfo[p];
-      const int code = P.code;
-      const int bstart = ball_meta[2 * code], nb = ball_meta[2 * code + 1];
-      const int nwords = (nb + 31) >> 5;
-      const uint32_t *m = rec + P.roff;
-      const int wpad = (sizeof(T) == 8) ? ((nwords + 1) & ~1) : nwords;
-      const T *wts = reinterpret_cast<const T *>(m + wpad);
-      const uint32_t mw = (lane < nwords) ? m[lane] : 0u;
+    int p = p0 + wave;
+    PInfoD<T> Pn;
+    if (p < p1) Pn = pinfo[p];
+    while (p < p1) {
+      const PInfoD<T> P = Pn;
+      const int pn = p + nwave;
+      if (pn < p1) Pn = pinfo[pn];
       int cx = P.x - x0;
       if (cx < 0) cx += nx;
       int cy = P.y - y0;
       if (cy < 0) cy += ny;
       const int lc = ((P.z - z0 + HR) * LY + (cy + HR)) * LX + (cx + HR);
-      const int32_t *bl = ball + bstart;
+      const int32_t *bl = ball + ball_meta[2 * P.code] + P.first;
+      const T *wp = dense + P.woff;
+      const int n = P.count;
       T acc = T(0);
-      int wbase = 0;
-      for (int g0 = 0; g0 * 64 < nb; g0 += 8) {
-        int widx[8], lofs[8];
-        bool ok[8];
+      for (int e0 = 0; e0 < n; e0 += 256) {
+        T wv[4];
+        int lo[4];
 #pragma unroll
-        for (int k = 0; k < 8; ++k) {
-          const int b = (g0 + k) * 64 + lane;
-          const uint32_t word = (uint32_t)__shfl((int)mw, (b >> 5) & 63);
-          const int bit = (b < nb) ? (int)((word >> (b & 31)) & 1u) : 0;
-          const unsigned long long bal = __ballot(bit);
-          widx[k] = wbase + __popcll(bal & ((1ull << lane) - 1ull));
-          wbase += __popcll(bal);
-          ok[k] = bit != 0;
-          const uint32_t v = bit ? (uint32_t)bl[b] : 0u;
+        for (int k = 0; k < 4; ++k) {
+          const int e = e0 + k * 64 + lane;
+          const bool in = e < n;
+          wv[k] = in ? wp[e] : T(0);
+          const uint32_t v = in ? (uint32_t)bl[e] : 0u;
           const int dx = (int8_t)(v & 255), dy = (int8_t)((v >> 8) & 255), dz = (int8_t)((v >> 16) & 255);
-          lofs[k] = lc + (dz * LY + dy) * LX + dx;
+          lo[k] = lc + (dz * LY + dy) * LX + dx;
         }
-        T wv[8];
 #pragma unroll
-        for (int k = 0; k < 8; ++k) wv[k] = ok[k] ? wts[widx[k]] : T(0);
-#pragma unroll
-        for (int k = 0; k < 8; ++k)
-          if (ok[k]) acc += wv[k] * sp[lofs[k]];
+        for (int k = 0; k < 4; ++k) acc += wv[k] * sp[lo[k]];
       }
       for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
       if (lane == 0) unew[(size_t)s * vol + (size_t)P.z * plane + (size_t)P.y * pitch + P.x] += P.scale * acc;
+      p = pn;
     }
     __syncthreads();
   }
+}
+
+template <typename T>
+__global__ void k_make_pinfo_dense(const int16_t *xyz, const int32_t *first, const int32_t *count,
+                                   const uint32_t *doff, const T *scale, const int32_t *perm, int64_t n,
+                                   PInfoD<T> *out) {
+  int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= n) return;
+  const int64_t i = perm[j];
+  PInfoD<T> p;
+  p.x = xyz[i * 4];
+  p.y = xyz[i * 4 + 1];
+  p.z = xyz[i * 4 + 2];
+  p.code = xyz[i * 4 + 3];
+  p.first = (uint16_t)first[i];
+  p.count = (uint16_t)count[i];
+  p.woff = doff[i];
+  p.scale = scale[i];
+  out[j] = p;
+}
+
+size_t pinfo_dense_bytes(int prec) { return prec == IB_F32 ? sizeof(PInfoD<float>) : sizeof(PInfoD<double>); }
+
+void enqueue_make_pinfo_dense(int prec, const int16_t *xyz, const int32_t *first, const int32_t *count,
+                              const uint32_t *doff, const void *scale, const int32_t *perm, int64_t n, void *out,
+                              hipStream_t st) {
+  if (n <= 0) return;
+  dim3 g((unsigned)((n + 255) / 256)), b(256);
+  if (prec == IB_F32)
+    hipLaunchKernelGGL(k_make_pinfo_dense<float>, g, b, 0, st, xyz, first, count, doff, (const float *)scale, perm, n,
+                       (PInfoD<float> *)out);
+  else
+    hipLaunchKernelGGL(k_make_pinfo_dense<double>, g, b, 0, st, xyz, first, count, doff, (const double *)scale, perm,
+                       n, (PInfoD<double> *)out);
 }
 
 // ---- sources and receivers ---------------------------------------------------------
@@ -399,6 +565,21 @@ static void launch_interior(const StepArgs &a, hipStream_t st) {
   T *um = (T *)a.um;
   const T *K = (const T *)a.K;
   const T *sx = (const T *)a.sx, *sy = (const T *)a.sy, *sz = (const T *)a.sz;
+  if (a.ndim == 3 && a.M == 8 && a.variant >= 1) {
+    const int RY = (a.variant == 2) ? 8 : 4;
+    const int ntx = (a.nx + 63) / 64, nty = (a.ny + 4 * RY - 1) / (4 * RY);
+    const int zc = a.zchunk > 0 ? a.zchunk : a.nz;
+    const int nzc = (a.nz + zc - 1) / zc;
+    int64_t nblk = (int64_t)ntx * nty * nzc * a.nshots;
+    int64_t nblk8 = (nblk + 7) / 8 * 8;
+    if (RY == 8)
+      hipLaunchKernelGGL((k_interior3d_p<T, 4, 8>), dim3((unsigned)nblk8), dim3(256), 0, st, un, um, K, sx, sy, sz,
+                         stencil_weights<T>(a.M), a.nx, a.ny, a.nz, a.pitch, a.vol, zc, ntx, nty, nzc, a.nshots);
+    else
+      hipLaunchKernelGGL((k_interior3d_p<T, 4, 4>), dim3((unsigned)nblk8), dim3(256), 0, st, un, um, K, sx, sy, sz,
+                         stencil_weights<T>(a.M), a.nx, a.ny, a.nz, a.pitch, a.vol, zc, ntx, nty, nzc, a.nshots);
+    return;
+  }
   if (a.ndim == 3 && a.M == 8) {
     constexpr int RY = 4;
     const int ntx = (a.nx + 63) / 64, nty = (a.ny + 4 * RY - 1) / (4 * RY);
@@ -437,9 +618,9 @@ template <typename T>
 static void launch_patch(const StepArgs &a, hipStream_t st) {
   if (a.ntiles > 0) {
     int64_t nblk = ((int64_t)a.ntiles + 7) / 8 * 8;
-    hipLaunchKernelGGL((k_patch_tiled<T, kTileX, kTileY, kTileZ, kTileHalo>), dim3((unsigned)nblk), dim3(512), 0, st,
-                       (const T *)a.un, (T *)a.um, a.rec, (const PInfo<T> *)a.pinfo, a.ball, a.ball_meta, a.tiles,
-                       a.ntiles, a.nx, a.ny, a.nz, a.pitch, a.vol, a.nshots);
+    hipLaunchKernelGGL((k_patch_tiled<T, kTileX, kTileY, kTileZ, kTileHalo>), dim3((unsigned)nblk), dim3(256), 0, st,
+                       (const T *)a.un, (T *)a.um, (const T *)a.dense, (const PInfoD<T> *)a.pinfo, a.ball, a.ball_meta,
+                       a.tiles, a.ntiles, a.nx, a.ny, a.nz, a.pitch, a.vol, a.nshots);
   }
   if (a.nwide > 0) {
     int64_t nblk = ((a.nwide + 3) / 4 + 7) / 8 * 8;

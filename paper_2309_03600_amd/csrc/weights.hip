@@ -358,115 +358,150 @@ __global__ void k_solve(SolveArgs a) {
     }
   }
 
-  // ---- numerical rank: sigma_max by power iteration, sigma_min by inverse iteration --
-  double *xv = C;            // reuse the chunk buffer
-  double *yv = C + NT;
-  double *sv = C + 2 * NT;
-  const double inv_sqrt = 1.0 / sqrt((double)NT);
-  if (tid < NT) xv[tid] = inv_sqrt;
-  __syncthreads();
-  double smax2 = 0.0;
-  for (int it = 0; it < 10; ++it) {
-    if (tid < NT) {
-      double s = 0.0;
-      for (int j = tid; j < NT; ++j) s += R[ridx(tid, j, NT)] * xv[j];
-      yv[tid] = s;
+  // ---- numerical rank and the solve, in wavefront 0 ---------------------------------
+  // Vectors of length NT <= 192 live in registers (entry j in lane j % 64, slot j / 64);
+  // triangular solves and mat-vecs broadcast one entry per step with readlane, so no
+  // workgroup barrier is needed until z is published in LDS.
+  double *zv = C;            // reuse the chunk buffer for the published solution
+  if (tid < 64) {
+    const int lane = tid;
+    auto bcast = [](double v, int src) {
+      int lo = __builtin_amdgcn_readlane(__double2loint(v), src);
+      int hi = __builtin_amdgcn_readlane(__double2hiint(v), src);
+      return __hiloint2double(hi, lo);
+    };
+    auto get = [&](const double x[3], int k) { return bcast(k < 64 ? x[0] : (k < 128 ? x[1] : x[2]), k & 63); };
+    auto wsum = [](double v) {
+      for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+      return v;
+    };
+    // R^T w = x in place (x becomes w)
+    auto solve_rt = [&](double x[3]) {
+      for (int k = 0; k < NT; ++k) {
+        const double wk = get(x, k) / R[ridx(k, k, NT)];
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+          const int j = lane + 64 * q;
+          if (j > k && j < NT) x[q] -= R[ridx(k, j, NT)] * wk;
+          if (j == k) x[q] = wk;
+        }
+      }
+    };
+    // R z = w in place
+    auto solve_r = [&](double x[3]) {
+      for (int k = NT - 1; k >= 0; --k) {
+        const double zk = get(x, k) / R[ridx(k, k, NT)];
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+          const int j = lane + 64 * q;
+          if (j < k) x[q] -= R[ridx(j, k, NT)] * zk;
+          if (j == k) x[q] = zk;
+        }
+      }
+    };
+    const double inv_sqrt = 1.0 / sqrt((double)NT);
+    // sigma_max: power iteration on R^T R
+    double x[3], y[3];
+#pragma unroll
+    for (int q = 0; q < 3; ++q) x[q] = (lane + 64 * q < NT) ? inv_sqrt : 0.0;
+    double smax2 = 0.0;
+    for (int it = 0; it < 8; ++it) {
+#pragma unroll
+      for (int q = 0; q < 3; ++q) y[q] = 0.0;
+      for (int j = 0; j < NT; ++j) {      // y = R x
+        const double xj = get(x, j);
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+          const int i = lane + 64 * q;
+          if (i <= j && i < NT) y[q] += R[ridx(i, j, NT)] * xj;
+        }
+      }
+      double x2[3] = {0.0, 0.0, 0.0};
+      for (int i = 0; i < NT; ++i) {      // x2 = R^T y
+        const double yi = get(y, i);
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+          const int j = lane + 64 * q;
+          if (j >= i && j < NT) x2[q] += R[ridx(i, j, NT)] * yi;
+        }
+      }
+      const double nn = sqrt(wsum(x2[0] * x2[0] + x2[1] * x2[1] + x2[2] * x2[2]));
+      smax2 = nn;
+#pragma unroll
+      for (int q = 0; q < 3; ++q) x[q] = (nn > 0.0) ? x2[q] / nn : 0.0;
     }
-    __syncthreads();
-    double x2 = 0.0;
-    if (tid < NT) {
-      for (int i = 0; i <= tid; ++i) x2 += R[ridx(i, tid, NT)] * yv[i];
+    // sigma_min: inverse iteration on R^T R from an alternating start
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+      const int j = lane + 64 * q;
+      x[q] = (j < NT) ? ((j & 1) ? -inv_sqrt : inv_sqrt) : 0.0;
     }
-    double nn = sqrt(block_sum(x2 * x2, red));
-    smax2 = nn;
-    if (tid < NT) xv[tid] = (nn > 0.0) ? x2 / nn : inv_sqrt;
-    __syncthreads();
-  }
-  // inverse iteration on R^T R; start from an alternating vector
-  double xi = (tid < NT) ? ((tid & 1) ? -inv_sqrt : inv_sqrt) : 0.0;
-  double smin2 = 0.0;
-  for (int it = 0; it < 10; ++it) {
-    // forward: R^T w = x (thread t owns x_t)
-    double xr = xi;
-    for (int k = 0; k < NT; ++k) {
-      if (tid == k) sv[k] = xr / R[ridx(k, k, NT)];
-      __syncthreads();
-      if (tid > k && tid < NT) xr -= R[ridx(k, tid, NT)] * sv[k];
+    double smin2 = 0.0;
+    for (int it = 0; it < 6; ++it) {
+      solve_rt(x);
+      solve_r(x);
+      const double nn = sqrt(wsum(x[0] * x[0] + x[1] * x[1] + x[2] * x[2]));
+      if (!isfinite(nn) || !(nn > 0.0)) {
+        smin2 = 0.0;
+        break;
+      }
+      smin2 = 1.0 / nn;
+#pragma unroll
+      for (int q = 0; q < 3; ++q) x[q] /= nn;
     }
-    __syncthreads();
-    double wr = (tid < NT) ? sv[tid] : 0.0;
-    __syncthreads();
-    // backward: R z = w (thread t owns w_t)
-    for (int k = NT - 1; k >= 0; --k) {
-      if (tid == k) yv[k] = wr / R[ridx(k, k, NT)];
-      __syncthreads();
-      if (tid < k) wr -= R[ridx(tid, k, NT)] * yv[k];
+    const double smax = sqrt(smax2), smin = sqrt(smin2);
+    const double tol = (a.rtol > 0.0) ? a.rtol : (double)max(m, NT) * 2.220446049250313e-16;
+    const bool full = (smin > tol * smax) && isfinite(smin) && isfinite(smax) && smax > 0.0;
+    if (lane == 0) {
+      a.status[out] = full ? 1 : 0;
+      a.ndata[out] = ndata;
+      a.sigma[out] = (smax > 0.0) ? smin / smax : 0.0;
+      iscr[9] = full ? 1 : 0;
     }
-    __syncthreads();
-    double z = (tid < NT) ? yv[tid] : 0.0;
-    double nn = sqrt(block_sum(z * z, red));
-    smin2 = (nn > 0.0) ? 1.0 / nn : 0.0;
-    xi = (tid < NT && nn > 0.0 && isfinite(nn)) ? z / nn : 0.0;
-    if (!(isfinite(nn))) {
-      smin2 = 0.0;
-      break;
-    }
-  }
-  const double smax = sqrt(smax2), smin = sqrt(smin2);
-  const double tol = (a.rtol > 0.0) ? a.rtol : (double)max(m, NT) * 2.220446049250313e-16;
-  const bool full = (smin > tol * smax) && isfinite(smin) && isfinite(smax) && smax > 0.0;
-  if (tid == 0) {
-    a.status[out] = full ? 1 : 0;
-    a.ndata[out] = ndata;
-    a.sigma[out] = (smax > 0.0) ? smin / smax : 0.0;
-  }
-  if (!full) return;
-
-  // ---- c = sum of w_e a(e - i) over exterior cross-stencil nodes ----------------------
-  double cv = 0.0;
-  if (tid < NT) {
-    const int8_t *ex = c_solve.exps[tid];
-    const int half = a.M / 2;
-    for (int n = 0; n < 3; ++n) {
-      if (a.lat == 1 && n == 1) continue;
-      // the term is a pure power of axis n (or the constant)
-      bool pure = true;
-      for (int q = 0; q < 3; ++q)
-        if (q != n && ex[q] != 0) pure = false;
-      if (!pure) continue;
-      for (int k = -half; k <= half; ++k) {
-        if (k == 0) continue;
-        int xx = x0, yy = y0, zz = z0;
-        if (n == 0) xx = wrapd(x0 + k, a.nx);
-        if (n == 1) yy = wrapd(y0 + k, a.ny);
-        if (n == 2) zz = z0 + k;
-        if (zz < 0 || zz >= a.nz) continue;
-        int64_t g = ((int64_t)zz * a.ny + yy) * a.nx + xx;
-        if (a.cls[g] & 1) continue;
-        double mono = 1.0;
-        for (int p = 1; p <= ex[n]; ++p) mono = mono * (double)k / (double)p;
-        cv += c_solve.w2[k + half] * mono;
+    if (full) {
+      // c = sum of w_e a(e - i) over exterior cross-stencil nodes, then R^T w = c, R z = w
+#pragma unroll
+      for (int q = 0; q < 3; ++q) {
+        const int t = lane + 64 * q;
+        double cv = 0.0;
+        if (t < NT) {
+          const int8_t *ex = c_solve.exps[t];
+          const int half = a.M / 2;
+          for (int n = 0; n < 3; ++n) {
+            if (a.lat == 1 && n == 1) continue;
+            bool pure = true;      // the term must be a pure power of axis n (or the constant)
+            for (int qq = 0; qq < 3; ++qq)
+              if (qq != n && ex[qq] != 0) pure = false;
+            if (!pure) continue;
+            for (int k = -half; k <= half; ++k) {
+              if (k == 0) continue;
+              int xx = x0, yy = y0, zz = z0;
+              if (n == 0) xx = wrapd(x0 + k, a.nx);
+              if (n == 1) yy = wrapd(y0 + k, a.ny);
+              if (n == 2) zz = z0 + k;
+              if (zz < 0 || zz >= a.nz) continue;
+              const int64_t g = ((int64_t)zz * a.ny + yy) * a.nx + xx;
+              if (a.cls[g] & 1) continue;
+              double mono = 1.0;
+              for (int pp = 1; pp <= ex[n]; ++pp) mono = mono * (double)k / (double)pp;
+              cv += c_solve.w2[k + half] * mono;
+            }
+          }
+        }
+        x[q] = cv;
+      }
+      solve_rt(x);
+      solve_r(x);
+#pragma unroll
+      for (int q = 0; q < 3; ++q) {
+        const int t = lane + 64 * q;
+        if (t < NT) zv[t] = x[q];
       }
     }
   }
-  // forward R^T w = c, backward R z = w
-  {
-    double xr = cv;
-    for (int k = 0; k < NT; ++k) {
-      if (tid == k) sv[k] = xr / R[ridx(k, k, NT)];
-      __syncthreads();
-      if (tid > k && tid < NT) xr -= R[ridx(k, tid, NT)] * sv[k];
-    }
-    __syncthreads();
-    double wr = (tid < NT) ? sv[tid] : 0.0;
-    __syncthreads();
-    for (int k = NT - 1; k >= 0; --k) {
-      if (tid == k) yv[k] = wr / R[ridx(k, k, NT)];
-      __syncthreads();
-      if (tid < k) wr -= R[ridx(tid, k, NT)] * yv[k];
-    }
-    __syncthreads();
-  }
+  __syncthreads();
+  if (!iscr[9]) return;
+  double *yv = zv;
   // y_j = a_j . z for the data rows
   double *wo = a.wout + (size_t)out * a.nball;
   for (int j = tid; j < ndata; j += nth) {
@@ -509,6 +544,55 @@ __global__ void k_pack(int nacc, const int32_t *acc_pos, const int32_t *acc_id, 
     w64[woff[id] + t] = v;
     f32[t] = (float)v;
     f64[t] = v;
+  }
+}
+
+// Dense-range records: per point, the weights of every support-ball lattice point from
+// the first to the last data point (zero where the lattice point is not data), so a
+// kernel can stream them without decoding the mask.
+__global__ void k_mask_range(int64_t nib, const uint32_t *rec32, const uint32_t *roff32, const int16_t *xyz,
+                             const int32_t *ball_meta, int32_t *first, int32_t *count) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nib) return;
+  const int code = xyz[i * 4 + 3];
+  const int nb = ball_meta[2 * code + 1];
+  const uint32_t *m = rec32 + roff32[i];
+  int f = -1, l = -1;
+  for (int b = 0; b < nb; ++b) {
+    if ((m[b >> 5] >> (b & 31)) & 1u) {
+      if (f < 0) f = b;
+      l = b;
+    }
+  }
+  first[i] = (f < 0) ? 0 : f;
+  count[i] = (f < 0) ? 0 : l - f + 1;
+}
+
+__global__ void k_dense(int64_t nib, const uint32_t *rec32, const uint32_t *roff32, const int32_t *meta,
+                        const double *w64, const int32_t *first, const int32_t *count, const uint32_t *doff,
+                        float *d32, double *d64) {
+  const int64_t i = blockIdx.x;
+  if (i >= nib) return;
+  const int lane = threadIdx.x;     // one wavefront per point
+  const uint32_t *m = rec32 + roff32[i];
+  const int f = first[i], n = count[i];
+  const int64_t woff = meta[i * 4 + 3];
+  // data points before the range start
+  int base = 0;
+  for (int b = lane; b < f; b += 64) base += (int)((m[b >> 5] >> (b & 31)) & 1u);
+  for (int o = 32; o > 0; o >>= 1) base += __shfl_xor(base, o);
+  for (int e0 = 0; e0 < n; e0 += 64) {
+    const int e = e0 + lane;
+    const int b = f + e;
+    const int bit = (e < n) ? (int)((m[b >> 5] >> (b & 31)) & 1u) : 0;
+    const unsigned long long bal = __ballot(bit);
+    const int k = base + __popcll(bal & ((1ull << lane) - 1ull));
+    if (e < n) {
+      const double v = bit ? w64[woff + k] : 0.0;
+      d32[doff[i] + e] = (float)v;
+      d64[doff[i] + e] = v;
+    }
+    base += __popcll(bal);
   }
 }
 
@@ -749,6 +833,44 @@ ib_status weights_build(ib_weights *w, const int64_t *col_off_dev, hipStream_t s
   }
   IB_HIP(hipStreamSynchronize(st));
   dfree(d_woff), dfree(d_nw), dfree(d_apos), dfree(d_aid), dfree(d_sigma);
+  // dense-range records
+  {
+    int32_t *d_first = nullptr, *d_count = nullptr;
+    uint32_t *d_doff = nullptr;
+    if ((s = dalloc_t(&d_first, std::max<int64_t>(nib, 1))) || (s = dalloc_t(&d_count, std::max<int64_t>(nib, 1))) ||
+        (s = dalloc_t(&d_doff, std::max<int64_t>(nib, 1))))
+      return s;
+    if (nib)
+      hipLaunchKernelGGL(k_mask_range, dim3((unsigned)((nib + 255) / 256)), dim3(256), 0, st, nib, w->rec32,
+                         w->rec_off32, w->ib_xyz, w->ball_meta, d_first, d_count);
+    std::vector<int32_t> hf(nib), hc(nib);
+    std::vector<uint32_t> ho(nib);
+    IB_HIP(hipMemcpyAsync(hf.data(), d_first, nib * 4, hipMemcpyDeviceToHost, st));
+    IB_HIP(hipMemcpyAsync(hc.data(), d_count, nib * 4, hipMemcpyDeviceToHost, st));
+    IB_HIP(hipStreamSynchronize(st));
+    int64_t sd = 0;
+    for (int64_t i = 0; i < nib; ++i) {
+      ho[i] = (uint32_t)sd;
+      sd += hc[i];
+    }
+    if (sd >= (int64_t)UINT32_MAX) {
+      set_error("dense stencil table too large");
+      return IB_ERR_ARG;
+    }
+    w->dense_words = sd;
+    w->stats.dense_weights = sd;
+    if ((s = dalloc_t(&w->dense32, std::max<int64_t>(sd, 1))) || (s = dalloc_t(&w->dense64, std::max<int64_t>(sd, 1))))
+      return s;
+    IB_HIP(hipMemcpyAsync(d_doff, ho.data(), nib * 4, hipMemcpyHostToDevice, st));
+    if (nib)
+      hipLaunchKernelGGL(k_dense, dim3((unsigned)nib), dim3(64), 0, st, nib, w->rec32, w->rec_off32, w->ib_meta,
+                         w->w64, d_first, d_count, d_doff, w->dense32, w->dense64);
+    IB_HIP(hipGetLastError());
+    IB_HIP(hipStreamSynchronize(st));
+    w->dense_first = d_first;
+    w->dense_count = d_count;
+    w->dense_off = d_doff;
+  }
   return IB_OK;
 }
 
