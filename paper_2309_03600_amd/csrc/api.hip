@@ -209,6 +209,47 @@ bool corners(const ib_weights *w, const double *pos_m, int64_t idx[8], double wt
   return true;
 }
 
+// Tile-depth autotuner of the 3D eighth-order interior kernel: times each candidate
+// (HIP events, on the state's own buffers, whose contents it leaves unchanged because
+// they are zero) and keeps the fastest.
+ib_status autotune_interior(ib_state *S, hipStream_t st) {
+  const ib_weights *w = S->w;
+  if (!(w->ndim == 3 && w->M == 8)) return IB_OK;
+  std::vector<int> cands;
+  for (int d : {2, 3, 4, 5, 6, 8, 10, 12, 16}) {
+    int zc = (int)((w->nz + d - 1) / d);
+    if (zc >= 12 && std::find(cands.begin(), cands.end(), zc) == cands.end()) cands.push_back(zc);
+  }
+  hipEvent_t e0, e1;
+  IB_HIP(hipEventCreate(&e0));
+  IB_HIP(hipEventCreate(&e1));
+  float best = 1e30f;
+  int bestzc = S->zchunk;
+  const int save_variant = S->variant;
+  S->variant = 1;
+  for (int zc : cands) {
+    S->zchunk = zc;
+    StepArgs a = make_args(S, nullptr, 0, nullptr, 0, S->cur);
+    for (int i = 0; i < 2; ++i) enqueue_interior_only(a, st);
+    IB_HIP(hipEventRecord(e0, st));
+    for (int i = 0; i < 5; ++i) enqueue_interior_only(a, st);
+    IB_HIP(hipEventRecord(e1, st));
+    IB_HIP(hipEventSynchronize(e1));
+    float ms = 0.f;
+    IB_HIP(hipEventElapsedTime(&ms, e0, e1));
+    if (ms < best) {
+      best = ms;
+      bestzc = zc;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  S->variant = save_variant;
+  S->zchunk = bestzc;
+  S->zchunk_auto = bestzc;
+  return IB_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -526,7 +567,7 @@ ib_status ib_state_create(const ib_weights *w, const double *vel_dev, double dt,
     const int64_t tx = (w->nx + kTileX - 1) / kTileX, ty = (w->ny + kTileY - 1) / kTileY;
     for (int64_t i = 0; i < w->nib; ++i) {
       const int code = xyz[i * 4 + 3];
-      if (use_tiles && code / 2 <= kTileHalo)
+      if (use_tiles && (code == 8 || code == 9) && kTileHalo == 4)
         tiled.push_back((int32_t)i);
       else
         wide.push_back((int32_t)i);
@@ -635,6 +676,7 @@ ib_status ib_state_create(const ib_weights *w, const double *vel_dev, double dt,
     int nzc = (int)std::max<int64_t>(1, std::min<int64_t>(w->nz / 16, (want + tiles - 1) / tiles));
     S->zchunk = (int)((w->nz + nzc - 1) / nzc);
     S->zchunk_auto = S->zchunk;
+    if ((s = autotune_interior(S, st))) return fail(s);
   }
   *out = S;
   return IB_OK;

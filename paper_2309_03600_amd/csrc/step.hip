@@ -425,7 +425,10 @@ __global__ void k_patch_tiled(const T *__restrict__ un, T *__restrict__ unew, co
                               const int32_t *__restrict__ ball_meta, const int4 *__restrict__ tiles, int ntiles,
                               int nx, int ny, int nz, int64_t pitch, int64_t vol, int nshots) {
   constexpr int LX = TX + 2 * HR, LY = TY + 2 * HR, LZ = TZ + 2 * HR;
+  constexpr int NS = 7;                       // 64-lane slots per point (ball of radius 4.5: 389 points)
+  constexpr int BMAX = 64 * NS;
   __shared__ T sp[LZ * LY * LX];
+  __shared__ int16_t lofs[2][BMAX];           // LDS offsets of the ball lattice points, radius codes 8 and 9
   const int64_t tb = xcd_remap(blockIdx.x, gridDim.x);
   if (tb >= ntiles) return;
   const int4 tl = tiles[tb];
@@ -433,6 +436,18 @@ __global__ void k_patch_tiled(const T *__restrict__ un, T *__restrict__ unew, co
   const int p0 = tl.w, p1 = tiles[tb + 1].w;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwave = blockDim.x >> 6;
   const int64_t plane = pitch * ny;
+  for (int q = 0; q < 2; ++q) {
+    const int code = 8 + q, st0 = ball_meta[2 * code], nbq = ball_meta[2 * code + 1];
+    for (int b = threadIdx.x; b < BMAX; b += blockDim.x) {
+      int v = 0;
+      if (b < nbq) {
+        const uint32_t e = (uint32_t)ball[st0 + b];
+        const int dx = (int8_t)(e & 255), dy = (int8_t)((e >> 8) & 255), dz = (int8_t)((e >> 16) & 255);
+        v = (dz * LY + dy) * LX + dx;
+      }
+      lofs[q][b] = (int16_t)v;
+    }
+  }
   for (int s = 0; s < nshots; ++s) {
     const T *u = un + (size_t)s * vol;
     for (int e = threadIdx.x; e < LZ * LY * LX; e += blockDim.x) {
@@ -442,39 +457,49 @@ __global__ void k_patch_tiled(const T *__restrict__ un, T *__restrict__ unew, co
       sp[e] = (gz >= 0 && gz < nz) ? u[(size_t)gz * plane + (size_t)gy * pitch + gx] : T(0);
     }
     __syncthreads();
+    // software pipeline over this wavefront's points: record of p+2w and weights of
+    // p+w are in flight while p is evaluated
     int p = p0 + wave;
-    PInfoD<T> Pn;
-    if (p < p1) Pn = pinfo[p];
+    PInfoD<T> Pc, Pn;
+    T wc[NS], wn[NS];
+    if (p < p1) {
+      Pc = pinfo[p];
+#pragma unroll
+      for (int k = 0; k < NS; ++k) {
+        const int e = k * 64 + lane;
+        wc[k] = (e < Pc.count) ? dense[Pc.woff + e] : T(0);
+      }
+    }
+    if (p + nwave < p1) Pn = pinfo[p + nwave];
     while (p < p1) {
-      const PInfoD<T> P = Pn;
       const int pn = p + nwave;
-      if (pn < p1) Pn = pinfo[pn];
-      int cx = P.x - x0;
-      if (cx < 0) cx += nx;
-      int cy = P.y - y0;
-      if (cy < 0) cy += ny;
-      const int lc = ((P.z - z0 + HR) * LY + (cy + HR)) * LX + (cx + HR);
-      const int32_t *bl = ball + ball_meta[2 * P.code] + P.first;
-      const T *wp = dense + P.woff;
-      const int n = P.count;
-      T acc = T(0);
-      for (int e0 = 0; e0 < n; e0 += 256) {
-        T wv[4];
-        int lo[4];
+      PInfoD<T> Pnn;
+      if (pn < p1) {
 #pragma unroll
-        for (int k = 0; k < 4; ++k) {
-          const int e = e0 + k * 64 + lane;
-          const bool in = e < n;
-          wv[k] = in ? wp[e] : T(0);
-          const uint32_t v = in ? (uint32_t)bl[e] : 0u;
-          const int dx = (int8_t)(v & 255), dy = (int8_t)((v >> 8) & 255), dz = (int8_t)((v >> 16) & 255);
-          lo[k] = lc + (dz * LY + dy) * LX + dx;
+        for (int k = 0; k < NS; ++k) {
+          const int e = k * 64 + lane;
+          wn[k] = (e < Pn.count) ? dense[Pn.woff + e] : T(0);
         }
+        if (pn + nwave < p1) Pnn = pinfo[pn + nwave];
+      }
+      int cx = Pc.x - x0;
+      if (cx < 0) cx += nx;
+      int cy = Pc.y - y0;
+      if (cy < 0) cy += ny;
+      const int lc = ((Pc.z - z0 + HR) * LY + (cy + HR)) * LX + (cx + HR);
+      const int16_t *lt = lofs[Pc.code == 9 ? 1 : 0] + Pc.first;
+      T acc = T(0);
 #pragma unroll
-        for (int k = 0; k < 4; ++k) acc += wv[k] * sp[lo[k]];
+      for (int k = 0; k < NS; ++k) {
+        const int e = k * 64 + lane;
+        if (e < Pc.count) acc += wc[k] * sp[lc + lt[e]];
       }
       for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
-      if (lane == 0) unew[(size_t)s * vol + (size_t)P.z * plane + (size_t)P.y * pitch + P.x] += P.scale * acc;
+      if (lane == 0) unew[(size_t)s * vol + (size_t)Pc.z * plane + (size_t)Pc.y * pitch + Pc.x] += Pc.scale * acc;
+      Pc = Pn;
+#pragma unroll
+      for (int k = 0; k < NS; ++k) wc[k] = wn[k];
+      Pn = Pnn;
       p = pn;
     }
     __syncthreads();

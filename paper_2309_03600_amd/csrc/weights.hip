@@ -104,21 +104,22 @@ __device__ __forceinline__ int ridx(int i, int j, int NT) {  // packed upper tri
   return i * NT - (i * (i - 1)) / 2 + (j - i);
 }
 
+template <int CH>
 __launch_bounds__(256)
 __global__ void k_solve(SolveArgs a) {
   extern __shared__ double smem[];
   const int NT = a.NT;
-  const int nb = a.chunk;
+  constexpr int nb = CH;
   const int tid = threadIdx.x;
   const int nth = blockDim.x;
   const int D1 = a.Mb + 1;
-  double *R = smem;                                   // NT(NT+1)/2
-  double *C = R + NT * (NT + 1) / 2;                  // nb x NT
-  double *pw = C + nb * NT;                           // nb x 3 x D1
-  double *nrm = pw + nb * 3 * D1;                     // nb x 3
-  double *alpha = nrm + nb * 3;                       // NT
-  double *vzero = alpha + NT;                         // NT
-  double *red = vzero + NT;                           // 16
+  double *R = smem;                                   // NT(NT+1)/2, packed upper triangle
+  double *pw = R + NT * (NT + 1) / 2;                 // CH x 3 x D1 power tables of the chunk rows
+  double *nrm = pw + nb * 3 * D1;                     // CH x 3 normals of the chunk rows
+  double *vcol = nrm + nb * 3;                        // 2 x CH reflector columns (double buffered)
+  double *vsc = vcol + 2 * nb;                        // 2 x 2 reflector scalars
+  double *C = vsc + 4;                                // NT: the published solution z
+  double *red = C + NT;                               // 16
   int *iscr = (int *)(red + 16);                      // 16 ints
   __shared__ int rowop[64];
   __shared__ int rowbp[64];
@@ -242,7 +243,13 @@ __global__ void k_solve(SolveArgs a) {
   __syncthreads();
 
   // ---- streamed Householder QR of A into R ------------------------------------------
+  // Thread j owns column j of the current row chunk in registers.  Column step k: thread
+  // k forms the reflector of [R_kk; chunk column k] from its own registers and publishes
+  // it in LDS (double buffered); every thread j > k applies it to [R_kj; its column].
   for (int i = tid; i < NT * (NT + 1) / 2; i += nth) R[i] = 0.0;
+  const int8_t ej0 = (tid < NT) ? c_solve.exps[tid][0] : 0;
+  const int8_t ej1 = (tid < NT) ? c_solve.exps[tid][1] : 0;
+  const int8_t ej2 = (tid < NT) ? c_solve.exps[tid][2] : 0;
   __syncthreads();
   for (int r0 = 0; r0 < m; r0 += nb) {
     const int nr = min(nb, m - r0);
@@ -277,85 +284,67 @@ __global__ void k_solve(SolveArgs a) {
       }
     }
     __syncthreads();
-    for (int e = tid; e < nr * NT; e += nth) {
-      int i = e / NT, t = e - (e / NT) * NT;
-      const int8_t *ex = c_solve.exps[t];
-      const double *p = pw + i * 3 * D1;
-      double v;
-      int op = rowop[i];
-      if (op < 0) {
-        v = p[ex[0]] * p[D1 + ex[1]] * p[2 * D1 + ex[2]];
-      } else {
-        v = 0.0;
-        int nt_ = c_solve.ops.nterms[op];
-        for (int q = 0; q < nt_; ++q) {
-          const OpTerm &T = c_solve.ops.term[op][q];
-          int a0 = ex[0] - T.beta[0], a1 = ex[1] - T.beta[1], a2 = ex[2] - T.beta[2];
-          if (a0 < 0 || a1 < 0 || a2 < 0) continue;
-          double cf = T.coef;
-          if (T.normal_axis >= 0) cf *= nrm[i * 3 + T.normal_axis];
-          v += cf * p[a0] * p[D1 + a1] * p[2 * D1 + a2];
-        }
-      }
-      C[i * NT + t] = v;
-    }
-    __syncthreads();
-    // reflector scalars of column 0 (wave 0), then one barrier per column
-    if (tid < 64) {
-      double s = 0.0;
-      for (int i = tid; i < nr; i += 64) s += C[i * NT] * C[i * NT];
-      for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
-      if (tid == 0) {
-        double rkk = R[0];
-        if (s == 0.0) {
-          alpha[0] = rkk;
-          vzero[0] = 0.0;
+    double cj[CH];
+#pragma unroll
+    for (int i = 0; i < CH; ++i) {
+      double v = 0.0;
+      if (i < nr && tid < NT) {
+        const double *p = pw + i * 3 * D1;
+        const int op = rowop[i];
+        if (op < 0) {
+          v = p[ej0] * p[D1 + ej1] * p[2 * D1 + ej2];
         } else {
-          double nn = sqrt(rkk * rkk + s);
-          double al = (rkk >= 0.0) ? -nn : nn;
-          alpha[0] = al;
-          vzero[0] = rkk - al;
+          const int nt_ = c_solve.ops.nterms[op];
+          for (int q = 0; q < nt_; ++q) {
+            const OpTerm &T = c_solve.ops.term[op][q];
+            const int a0 = ej0 - T.beta[0], a1 = ej1 - T.beta[1], a2 = ej2 - T.beta[2];
+            if (a0 < 0 || a1 < 0 || a2 < 0) continue;
+            double cf = T.coef;
+            if (T.normal_axis >= 0) cf *= nrm[i * 3 + T.normal_axis];
+            v += cf * p[a0] * p[D1 + a1] * p[2 * D1 + a2];
+          }
         }
       }
+      cj[i] = v;
     }
-    __syncthreads();
     for (int k = 0; k < NT; ++k) {
-      const double al = alpha[k], v0 = vzero[k];
-      const bool skip = (v0 == 0.0);
-      const int j = k + 1 + tid;
-      if (j < NT) {
-        double rkj = R[ridx(k, j, NT)];
+      double *vc = vcol + (k & 1) * nb;
+      double *sc = vsc + (k & 1) * 2;
+      if (tid == k) {
         double nsq = 0.0;
-        if (!skip) {
-          double s = v0 * rkj;
-          for (int i = 0; i < nr; ++i) s += C[i * NT + k] * C[i * NT + j];
-          double f = s / (al * v0);
-          rkj += f * v0;
-          R[ridx(k, j, NT)] = rkj;
-          for (int i = 0; i < nr; ++i) {
-            double c = C[i * NT + j] + f * C[i * NT + k];
-            C[i * NT + j] = c;
-            nsq += c * c;
-          }
+#pragma unroll
+        for (int i = 0; i < CH; ++i) nsq += cj[i] * cj[i];
+        const double rkk = R[ridx(k, k, NT)];
+        double al, v0;
+        if (nsq == 0.0) {
+          al = rkk;
+          v0 = 0.0;
         } else {
-          for (int i = 0; i < nr; ++i) nsq += C[i * NT + j] * C[i * NT + j];
+          const double nn = sqrt(rkk * rkk + nsq);
+          al = (rkk >= 0.0) ? -nn : nn;
+          v0 = rkk - al;
         }
-        if (j == k + 1) {   // scalars of the next column, from its updated entries
-          double rjj = R[ridx(j, j, NT)];
-          if (nsq == 0.0) {
-            alpha[j] = rjj;
-            vzero[j] = 0.0;
-          } else {
-            double nn = sqrt(rjj * rjj + nsq);
-            double a2 = (rjj >= 0.0) ? -nn : nn;
-            alpha[j] = a2;
-            vzero[j] = rjj - a2;
-          }
-        }
+        sc[0] = al;
+        sc[1] = v0;
+#pragma unroll
+        for (int i = 0; i < CH; ++i) vc[i] = cj[i];
+        R[ridx(k, k, NT)] = al;
       }
-      if (tid == 0) R[ridx(k, k, NT)] = al;
       __syncthreads();
+      const double al = sc[0], v0 = sc[1];
+      if (tid > k && tid < NT && v0 != 0.0) {
+        const int rk = ridx(k, tid, NT);
+        const double rkj = R[rk];
+        double sdot = v0 * rkj;
+#pragma unroll
+        for (int i = 0; i < CH; ++i) sdot += vc[i] * cj[i];
+        const double f = sdot / (al * v0);
+        R[rk] = rkj + f * v0;
+#pragma unroll
+        for (int i = 0; i < CH; ++i) cj[i] += f * vc[i];
+      }
     }
+    __syncthreads();
   }
 
   // ---- numerical rank and the solve, in wavefront 0 ---------------------------------
@@ -643,7 +632,7 @@ ib_status weights_build(ib_weights *w, const int64_t *col_off_dev, hipStream_t s
   double max_cond = 0.0, min_margin = INFINITY;
   const double tol_base = 2.220446049250313e-16;
   const int max_slots = 32768;
-  const int chunk = (ndim == 3) ? 24 : 48;
+  const int chunk = (ndim == 3) ? 32 : 48;
 
   for (int Mb = M; Mb >= min_order && !pending.empty(); --Mb) {
     const int NT = n_terms(Mb, ndim);
@@ -702,15 +691,19 @@ ib_status weights_build(ib_weights *w, const int64_t *col_off_dev, hipStream_t s
       A.ndata = d_ndata;
       A.sigma = d_sigma;
       const int D1 = Mb + 1;
-      size_t lds = sizeof(double) * ((size_t)NT * (NT + 1) / 2 + (size_t)chunk * NT + (size_t)chunk * 3 * D1 +
-                                     (size_t)chunk * 3 + 2 * NT + 16) +
+      size_t lds = sizeof(double) * ((size_t)NT * (NT + 1) / 2 + (size_t)chunk * 3 * D1 + (size_t)chunk * 3 +
+                                     2 * (size_t)chunk + 4 + NT + 16) +
                    16 * sizeof(int);
-      IB_HIP(hipFuncSetAttribute((const void *)k_solve, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+      const void *kfn = (chunk == 32) ? (const void *)k_solve<32> : (const void *)k_solve<48>;
+      IB_HIP(hipFuncSetAttribute(kfn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
       for (int b0 = 0; b0 < npend; b0 += slots) {
         A.pending = d_pending + b0;
         A.npend = std::min(slots, npend - b0);
         A.out_base = b0;
-        hipLaunchKernelGGL(k_solve, dim3(A.npend), dim3(256), lds, st, A);
+        if (chunk == 32)
+          hipLaunchKernelGGL(k_solve<32>, dim3(A.npend), dim3(256), lds, st, A);
+        else
+          hipLaunchKernelGGL(k_solve<48>, dim3(A.npend), dim3(256), lds, st, A);
         IB_HIP(hipGetLastError());
       }
       std::vector<int32_t> hs(npend), hn(npend);
