@@ -457,49 +457,74 @@ __global__ void k_patch_tiled(const T *__restrict__ un, T *__restrict__ unew, co
       sp[e] = (gz >= 0 && gz < nz) ? u[(size_t)gz * plane + (size_t)gy * pitch + gx] : T(0);
     }
     __syncthreads();
-    // software pipeline over this wavefront's points: record of p+2w and weights of
-    // p+w are in flight while p is evaluated
+    // software pipeline over this wavefront's points, two at a time: the weights of the
+    // next pair and the records of the pair after it are in flight while a pair is
+    // evaluated (four points' weights outstanding per wavefront)
+    const int step2 = 2 * nwave;
     int p = p0 + wave;
-    PInfoD<T> Pc, Pn;
-    T wc[NS], wn[NS];
-    if (p < p1) {
-      Pc = pinfo[p];
+    PInfoD<T> Pc[2], Pn[2];
+    T wc[2][NS], wn[2][NS];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int q = p + h * nwave;
+      if (q < p1) Pc[h] = pinfo[q];
+    }
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int q = p + h * nwave;
 #pragma unroll
       for (int k = 0; k < NS; ++k) {
         const int e = k * 64 + lane;
-        wc[k] = (e < Pc.count) ? dense[Pc.woff + e] : T(0);
+        wc[h][k] = (q < p1 && e < Pc[h].count) ? dense[Pc[h].woff + e] : T(0);
       }
     }
-    if (p + nwave < p1) Pn = pinfo[p + nwave];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int q = p + step2 + h * nwave;
+      if (q < p1) Pn[h] = pinfo[q];
+    }
     while (p < p1) {
-      const int pn = p + nwave;
-      PInfoD<T> Pnn;
-      if (pn < p1) {
+      const int pn = p + step2;
+      PInfoD<T> Pnn[2];
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int q = pn + h * nwave;
 #pragma unroll
         for (int k = 0; k < NS; ++k) {
           const int e = k * 64 + lane;
-          wn[k] = (e < Pn.count) ? dense[Pn.woff + e] : T(0);
+          wn[h][k] = (q < p1 && e < Pn[h].count) ? dense[Pn[h].woff + e] : T(0);
         }
-        if (pn + nwave < p1) Pnn = pinfo[pn + nwave];
+        const int q2 = pn + step2 + h * nwave;
+        if (q2 < p1) Pnn[h] = pinfo[q2];
       }
-      int cx = Pc.x - x0;
-      if (cx < 0) cx += nx;
-      int cy = Pc.y - y0;
-      if (cy < 0) cy += ny;
-      const int lc = ((Pc.z - z0 + HR) * LY + (cy + HR)) * LX + (cx + HR);
-      const int16_t *lt = lofs[Pc.code == 9 ? 1 : 0] + Pc.first;
-      T acc = T(0);
 #pragma unroll
-      for (int k = 0; k < NS; ++k) {
-        const int e = k * 64 + lane;
-        if (e < Pc.count) acc += wc[k] * sp[lc + lt[e]];
+      for (int h = 0; h < 2; ++h) {
+        const int q = p + h * nwave;
+        if (q < p1) {
+          const PInfoD<T> &P = Pc[h];
+          int cx = P.x - x0;
+          if (cx < 0) cx += nx;
+          int cy = P.y - y0;
+          if (cy < 0) cy += ny;
+          const int lc = ((P.z - z0 + HR) * LY + (cy + HR)) * LX + (cx + HR);
+          const int16_t *lt = lofs[P.code == 9 ? 1 : 0] + P.first;
+          T acc = T(0);
+#pragma unroll
+          for (int k = 0; k < NS; ++k) {
+            const int e = k * 64 + lane;
+            if (e < P.count) acc += wc[h][k] * sp[lc + lt[e]];
+          }
+          for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
+          if (lane == 0) unew[(size_t)s * vol + (size_t)P.z * plane + (size_t)P.y * pitch + P.x] += P.scale * acc;
+        }
       }
-      for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
-      if (lane == 0) unew[(size_t)s * vol + (size_t)Pc.z * plane + (size_t)Pc.y * pitch + Pc.x] += Pc.scale * acc;
-      Pc = Pn;
 #pragma unroll
-      for (int k = 0; k < NS; ++k) wc[k] = wn[k];
-      Pn = Pnn;
+      for (int h = 0; h < 2; ++h) {
+        Pc[h] = Pn[h];
+        Pn[h] = Pnn[h];
+#pragma unroll
+        for (int k = 0; k < NS; ++k) wc[h][k] = wn[h][k];
+      }
       p = pn;
     }
     __syncthreads();
