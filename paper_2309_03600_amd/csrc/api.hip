@@ -578,7 +578,7 @@ ib_status ib_state_create(const ib_weights *w, const double *vel_dev, double dt,
     std::stable_sort(tiled.begin(), tiled.end(), [&](int32_t a, int32_t b) { return tkey(a) < tkey(b); });
     std::vector<int4> tl;
     for (size_t j = 0; j < tiled.size(); ++j) {
-      if (j == 0 || tkey(tiled[j]) != tkey(tiled[j - 1])) {
+      if (j == 0 || tkey(tiled[j]) != tkey(tiled[j - 1]) || (int)j - tl.back().w >= kTileMaxPoints) {
         int32_t i = tiled[j];
         tl.push_back(make_int4(xyz[i * 4] / kTileX * kTileX, xyz[i * 4 + 1] / kTileY * kTileY,
                                xyz[i * 4 + 2] / kTileZ * kTileZ, (int)j));

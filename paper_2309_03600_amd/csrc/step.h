@@ -10,6 +10,7 @@ namespace ib {
 
 // LDS tile of the 3D IB patch (points of support radius <= kTileHalo + 1/2)
 constexpr int kTileX = 8, kTileY = 8, kTileZ = 8, kTileHalo = 4;
+constexpr int kTileMaxPoints = 512;   // longer tile lists are split
 
 struct StepArgs {
   int prec;

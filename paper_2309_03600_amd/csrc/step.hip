@@ -429,6 +429,7 @@ __global__ void k_patch_tiled(const T *__restrict__ un, T *__restrict__ unew, co
   constexpr int BMAX = 64 * NS;
   __shared__ T sp[LZ * LY * LX];
   __shared__ int16_t lofs[2][BMAX];           // LDS offsets of the ball lattice points, radius codes 8 and 9
+  __shared__ T res[kTileMaxPoints];            // per-point results, written back together
   const int64_t tb = xcd_remap(blockIdx.x, gridDim.x);
   if (tb >= ntiles) return;
   const int4 tl = tiles[tb];
@@ -515,7 +516,7 @@ __global__ void k_patch_tiled(const T *__restrict__ un, T *__restrict__ unew, co
             if (e < P.count) acc += wc[h][k] * sp[lc + lt[e]];
           }
           for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
-          if (lane == 0) unew[(size_t)s * vol + (size_t)P.z * plane + (size_t)P.y * pitch + P.x] += P.scale * acc;
+          if (lane == 0) res[q - p0] = P.scale * acc;
         }
       }
 #pragma unroll
@@ -526,6 +527,13 @@ __global__ void k_patch_tiled(const T *__restrict__ un, T *__restrict__ unew, co
         for (int k = 0; k < NS; ++k) wc[h][k] = wn[h][k];
       }
       p = pn;
+    }
+    __syncthreads();
+    // read-modify-write of p^{n+1} for all points of the tile at once (kept off the
+    // per-point path, where its load would wait behind the prefetched weights)
+    for (int q = p0 + (int)threadIdx.x; q < p1; q += blockDim.x) {
+      const PInfoD<T> P = pinfo[q];
+      unew[(size_t)s * vol + (size_t)P.z * plane + (size_t)P.y * pitch + P.x] += res[q - p0];
     }
     __syncthreads();
   }
