@@ -219,7 +219,8 @@ int64_t ib_state_step_count(const ib_state *st);
 ib_status ib_state_run_kernel(ib_state *st, int32_t which, int32_t count, void *stream);
 
 /* Tuning knobs of the 3D eighth-order interior kernel: variant 0 (one plane per barrier
- * pair), 1 (software-pipelined, 64x16 tiles, default), 2 (pipelined, 64x32 tiles), and
+ * pair), 1 (software-pipelined, 64x16 tiles), 2 (pipelined, 64x32 tiles, 8 rows per thread),
+ * 3 (pipelined, 64x32 tiles, 512 threads), and
  * depth planes per workgroup (0 = automatic: enough workgroups to fill the device).
  * Results do not depend on them. */
 ib_status ib_state_set_tuning(ib_state *st, int32_t variant, int32_t zchunk);

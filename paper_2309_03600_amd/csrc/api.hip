@@ -225,9 +225,11 @@ ib_status autotune_interior(ib_state *S, hipStream_t st) {
   IB_HIP(hipEventCreate(&e1));
   float best = 1e30f;
   int bestzc = S->zchunk;
-  const int save_variant = S->variant;
-  S->variant = 1;
-  for (int zc : cands) {
+  int bestv = 1;
+  for (int cand = 0; cand < 2 * (int)cands.size(); ++cand) {
+    const int v = (cand % 2 == 0) ? 1 : 3;
+    const int zc = cands[cand / 2];
+    S->variant = v;
     S->zchunk = zc;
     StepArgs a = make_args(S, nullptr, 0, nullptr, 0, S->cur);
     for (int i = 0; i < 2; ++i) enqueue_interior_only(a, st);
@@ -240,11 +242,12 @@ ib_status autotune_interior(ib_state *S, hipStream_t st) {
     if (ms < best) {
       best = ms;
       bestzc = zc;
+      bestv = v;
     }
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
-  S->variant = save_variant;
+  S->variant = bestv;
   S->zchunk = bestzc;
   S->zchunk_auto = bestzc;
   return IB_OK;
@@ -712,7 +715,7 @@ void ib_state_free(ib_state *S) {
 int64_t ib_state_step_count(const ib_state *S) { return S ? S->t : -1; }
 
 ib_status ib_state_set_tuning(ib_state *S, int32_t variant, int32_t zchunk) {
-  if (!S || zchunk < 0 || variant < 0 || variant > 2) {
+  if (!S || zchunk < 0 || variant < 0 || variant > 3) {
     set_error("ib_state_set_tuning: invalid argument");
     return IB_ERR_ARG;
   }

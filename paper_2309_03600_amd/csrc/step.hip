@@ -152,13 +152,13 @@ __global__ void k_interior3d(const T *__restrict__ un, T *__restrict__ um, const
 // Same tiling as k_interior3d, but everything plane z+1 needs from memory (the queue's
 // new plane, p^{n-1}, K and the LDS halo of the centre plane) is requested during plane
 // z, and the LDS centre plane is double buffered so one barrier per plane suffices.
-template <typename T, int H, int RY>
-__launch_bounds__(256)
+template <typename T, int H, int RY, int NW>
+__launch_bounds__(64 * NW)
 __global__ void k_interior3d_p(const T *__restrict__ un, T *__restrict__ um, const T *__restrict__ K,
                                const T *__restrict__ sx, const T *__restrict__ sy, const T *__restrict__ sz,
                                StencilW<T> W, int nx, int ny, int nz, int64_t pitch, int64_t vol, int zchunk,
                                int ntx, int nty, int nzc, int nshots) {
-  constexpr int TX = 64, TY = 4 * RY, LX = TX + 2 * H, LY = TY + 2 * H;
+  constexpr int TX = 64, TY = NW * RY, LX = TX + 2 * H, LY = TY + 2 * H;
   __shared__ T tile[2][LY][LX];
   const int64_t nblk = (int64_t)ntx * nty * nzc * nshots;
   int64_t L = xcd_remap(blockIdx.x, gridDim.x);
@@ -192,12 +192,16 @@ __global__ void k_interior3d_p(const T *__restrict__ un, T *__restrict__ um, con
   const bool xl = tx < H, xr = tx >= TX - H;
   const int xh = xl ? ((x0 - H + tx) % nx + nx) % nx : (xr ? (x0 + TX + (tx - (TX - H))) % nx : 0);
   const int lxh = xl ? tx : (xr ? TX + H + (tx - (TX - H)) : 0);
-  size_t hyoff[2];
-  int hyly[2], hylx[2];
+  constexpr int NHY = (2 * H * TX + 64 * NW - 1) / (64 * NW);   // y-halo values per thread
+  size_t hyoff[NHY];
+  int hyly[NHY], hylx[NHY];
+  bool hyon[NHY];
   const int t = threadIdx.x;
 #pragma unroll
-  for (int i = 0; i < 2; ++i) {
-    int idx = t + i * 256;
+  for (int i = 0; i < NHY; ++i) {
+    int idx = t + i * 64 * NW;
+    hyon[i] = idx < 2 * H * TX;
+    if (!hyon[i]) idx = 0;
     int hr = idx / TX, hc = idx % TX;
     int yg = (hr < H) ? y0 - H + hr : y0 + TY + (hr - H);
     int yy = ((yg % ny) + ny) % ny;
@@ -214,7 +218,7 @@ __global__ void k_interior3d_p(const T *__restrict__ un, T *__restrict__ um, con
       q[r][k] = (z >= 0 && z < nz) ? u[(size_t)z * plane + rowoff[r]] : T(0);
     }
   }
-  T pm[RY], kk[RY], hx[RY], hy[2];
+  T pm[RY], kk[RY], hx[RY], hy[NHY];
 #pragma unroll
   for (int r = 0; r < RY; ++r) {
     pm[r] = o[(size_t)z0 * plane + rowoff[r]];
@@ -222,7 +226,7 @@ __global__ void k_interior3d_p(const T *__restrict__ un, T *__restrict__ um, con
     hx[r] = (xl || xr) ? u[(size_t)z0 * plane + (size_t)ywv[r] * pitch + xh] : T(0);
   }
 #pragma unroll
-  for (int i = 0; i < 2; ++i) hy[i] = u[(size_t)z0 * plane + hyoff[i]];
+  for (int i = 0; i < NHY; ++i) hy[i] = hyon[i] ? u[(size_t)z0 * plane + hyoff[i]] : T(0);
   int buf = 0;
   for (int z = z0; z < z1; ++z) {
     // centre plane and its halo into LDS
@@ -233,9 +237,10 @@ __global__ void k_interior3d_p(const T *__restrict__ un, T *__restrict__ um, con
       for (int r = 0; r < RY; ++r) tile[buf][H + ty * RY + r][lxh] = hx[r];
     }
 #pragma unroll
-    for (int i = 0; i < 2; ++i) tile[buf][hyly[i]][hylx[i]] = hy[i];
+    for (int i = 0; i < NHY; ++i)
+      if (hyon[i]) tile[buf][hyly[i]][hylx[i]] = hy[i];
     // requests for the next plane
-    T nq[RY], npm[RY], nk[RY], nhx[RY], nhy[2];
+    T nq[RY], npm[RY], nk[RY], nhx[RY], nhy[NHY];
     const int zn = z + 1;
     const bool more = zn < z1;
     const size_t znoff = (size_t)zn * plane;
@@ -248,7 +253,7 @@ __global__ void k_interior3d_p(const T *__restrict__ un, T *__restrict__ um, con
       nhx[r] = (more && (xl || xr)) ? u[znoff + (size_t)ywv[r] * pitch + xh] : T(0);
     }
 #pragma unroll
-    for (int i = 0; i < 2; ++i) nhy[i] = more ? u[znoff + hyoff[i]] : T(0);
+    for (int i = 0; i < NHY; ++i) nhy[i] = (more && hyon[i]) ? u[znoff + hyoff[i]] : T(0);
     __syncthreads();
     const T sxz = sx[xw] + sz[z];
 #pragma unroll
@@ -273,8 +278,8 @@ __global__ void k_interior3d_p(const T *__restrict__ un, T *__restrict__ um, con
       kk[r] = nk[r];
       hx[r] = nhx[r];
     }
-    hy[0] = nhy[0];
-    hy[1] = nhy[1];
+#pragma unroll
+    for (int i = 0; i < NHY; ++i) hy[i] = nhy[i];
     buf ^= 1;
   }
 }
@@ -419,12 +424,13 @@ struct alignas(16) PInfoD {
 };
 
 template <typename T, int TX, int TY, int TZ, int HR>
-__launch_bounds__(256)
+__launch_bounds__(512)
 __global__ void k_patch_tiled(const T *__restrict__ un, T *__restrict__ unew, const T *__restrict__ dense,
                               const PInfoD<T> *__restrict__ pinfo, const int32_t *__restrict__ ball,
                               const int32_t *__restrict__ ball_meta, const int4 *__restrict__ tiles, int ntiles,
                               int nx, int ny, int nz, int64_t pitch, int64_t vol, int nshots) {
-  constexpr int LX = TX + 2 * HR, LY = TY + 2 * HR, LZ = TZ + 2 * HR;
+  // odd row pitch in LDS: the lattice rows of a support ball fall in different banks
+  constexpr int LX = TX + 2 * HR + 1, LY = TY + 2 * HR, LZ = TZ + 2 * HR;
   constexpr int NS = 7;                       // 64-lane slots per point (ball of radius 4.5: 389 points)
   constexpr int BMAX = 64 * NS;
   __shared__ T sp[LZ * LY * LX];
@@ -455,7 +461,7 @@ __global__ void k_patch_tiled(const T *__restrict__ un, T *__restrict__ unew, co
       const int lx = e % LX, ly = (e / LX) % LY, lz = e / (LX * LY);
       const int gz = z0 - HR + lz;
       const int gx = wrapk(x0 - HR + lx, nx), gy = wrapk(y0 - HR + ly, ny);
-      sp[e] = (gz >= 0 && gz < nz) ? u[(size_t)gz * plane + (size_t)gy * pitch + gx] : T(0);
+      sp[e] = (lx < LX - 1 && gz >= 0 && gz < nz) ? u[(size_t)gz * plane + (size_t)gy * pitch + gx] : T(0);
     }
     __syncthreads();
     // software pipeline over this wavefront's points, two at a time: the weights of the
@@ -625,17 +631,23 @@ static void launch_interior(const StepArgs &a, hipStream_t st) {
   const T *sx = (const T *)a.sx, *sy = (const T *)a.sy, *sz = (const T *)a.sz;
   if (a.ndim == 3 && a.M == 8 && a.variant >= 1) {
     const int RY = (a.variant == 2) ? 8 : 4;
-    const int ntx = (a.nx + 63) / 64, nty = (a.ny + 4 * RY - 1) / (4 * RY);
+    const int NW = (a.variant == 3) ? 8 : 4;
+    const int TY = RY * NW;
+    const int ntx = (a.nx + 63) / 64, nty = (a.ny + TY - 1) / TY;
     const int zc = a.zchunk > 0 ? a.zchunk : a.nz;
     const int nzc = (a.nz + zc - 1) / zc;
     int64_t nblk = (int64_t)ntx * nty * nzc * a.nshots;
     int64_t nblk8 = (nblk + 7) / 8 * 8;
-    if (RY == 8)
-      hipLaunchKernelGGL((k_interior3d_p<T, 4, 8>), dim3((unsigned)nblk8), dim3(256), 0, st, un, um, K, sx, sy, sz,
-                         stencil_weights<T>(a.M), a.nx, a.ny, a.nz, a.pitch, a.vol, zc, ntx, nty, nzc, a.nshots);
+    const StencilW<T> W = stencil_weights<T>(a.M);
+    if (a.variant == 2)
+      hipLaunchKernelGGL((k_interior3d_p<T, 4, 8, 4>), dim3((unsigned)nblk8), dim3(256), 0, st, un, um, K, sx, sy, sz,
+                         W, a.nx, a.ny, a.nz, a.pitch, a.vol, zc, ntx, nty, nzc, a.nshots);
+    else if (a.variant == 3)
+      hipLaunchKernelGGL((k_interior3d_p<T, 4, 4, 8>), dim3((unsigned)nblk8), dim3(512), 0, st, un, um, K, sx, sy, sz,
+                         W, a.nx, a.ny, a.nz, a.pitch, a.vol, zc, ntx, nty, nzc, a.nshots);
     else
-      hipLaunchKernelGGL((k_interior3d_p<T, 4, 4>), dim3((unsigned)nblk8), dim3(256), 0, st, un, um, K, sx, sy, sz,
-                         stencil_weights<T>(a.M), a.nx, a.ny, a.nz, a.pitch, a.vol, zc, ntx, nty, nzc, a.nshots);
+      hipLaunchKernelGGL((k_interior3d_p<T, 4, 4, 4>), dim3((unsigned)nblk8), dim3(256), 0, st, un, um, K, sx, sy, sz,
+                         W, a.nx, a.ny, a.nz, a.pitch, a.vol, zc, ntx, nty, nzc, a.nshots);
     return;
   }
   if (a.ndim == 3 && a.M == 8) {
@@ -676,7 +688,7 @@ template <typename T>
 static void launch_patch(const StepArgs &a, hipStream_t st) {
   if (a.ntiles > 0) {
     int64_t nblk = ((int64_t)a.ntiles + 7) / 8 * 8;
-    hipLaunchKernelGGL((k_patch_tiled<T, kTileX, kTileY, kTileZ, kTileHalo>), dim3((unsigned)nblk), dim3(256), 0, st,
+    hipLaunchKernelGGL((k_patch_tiled<T, kTileX, kTileY, kTileZ, kTileHalo>), dim3((unsigned)nblk), dim3(512), 0, st,
                        (const T *)a.un, (T *)a.um, (const T *)a.dense, (const PInfoD<T> *)a.pinfo, a.ball, a.ball_meta,
                        a.tiles, a.ntiles, a.nx, a.ny, a.nz, a.pitch, a.vol, a.nshots);
   }

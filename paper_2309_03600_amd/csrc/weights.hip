@@ -32,12 +32,28 @@ namespace ib {
 
 struct SolveConst {
   int8_t exps[kMaxTerms][3];
-  double w2[2 * kMaxOrder + 1];
-  OpSet ops;
+  double w2[2 * kMaxOrder + 1];   // centred second derivative, offsets -M/2..M/2
+  double ws[kMaxOrder];           // staggered first derivative, offsets -(M-1)/2..(M-1)/2
+  OpSet ops[3];                   // boundary-condition rows, per unknown block
 };
 __constant__ SolveConst c_solve;
 
+// A family of modified operators: which fields supply data, where the expansion point
+// sits, which unknown blocks the boundary rows span, and which stencil is completed.
+//   family 0: Laplacian at nodes (one field, one block);
+//   family 1: staggered d/dx_g of p at the v_g node (expansion at node + e_g / 2);
+//   family 2: staggered divergence of v at p nodes (one field and block per component).
 struct SolveArgs {
+  int family, gaxis;
+  int nfields, nblocks;
+  const uint8_t *fcls[3];  // node classes of each data field (bit0 interior, bit1 excluded)
+  const int32_t *fball[3]; // lattice points o of the field with |o + fshift| <= r
+  int fnball[3], fnwords[3], fwoff[3];
+  double fshift[3][3];     // position of field node (anchor + o) relative to the expansion point, minus o
+  int fblock[3];
+  int baxis[3];            // family 2: axis of the velocity component of each block
+  double x0off[3];         // expansion point relative to the anchor node
+  const uint8_t *xcls[3];  // classes of the nodes completed by the stencil (family 1: p; 2: v_n)
   const uint8_t *cls;
   const double *bp;        // [nb][8]
   const double *bpn;       // [nb][3]
@@ -47,8 +63,7 @@ struct SolveArgs {
   int npend;
   int nx, ny, nz, lat;
   int NT, Mb, M, nops;
-  const int32_t *ball;     // offsets of this radius
-  int nball, nwords;
+  int nball, nwords;       // totals over the fields
   double r2;               // r^2
   int Rc;                  // lateral column search half-width for boundary points
   double rtol;
@@ -108,7 +123,8 @@ template <int CH>
 __launch_bounds__(256)
 __global__ void k_solve(SolveArgs a) {
   extern __shared__ double smem[];
-  const int NT = a.NT;
+  const int NTB = a.NT;                 // basis terms per block
+  const int NT = a.NT * a.nblocks;      // unknowns (columns of A)
   constexpr int nb = CH;
   const int tid = threadIdx.x;
   const int nth = blockDim.x;
@@ -137,30 +153,36 @@ __global__ void k_solve(SolveArgs a) {
   double *bpr = a.bprel + (size_t)slot * a.maxbp * 6;
   uint32_t *mask = a.mout + (size_t)out * a.nwords;
 
-  // ---- data rows: ball lattice points that are interior and not excluded ----------
+  // ---- data rows: lattice points of each field that are interior and not excluded ----
   int ndata = 0;
-  for (int b0 = 0; b0 < a.nball; b0 += nth) {
-    int b = b0 + tid;
-    int flag = 0;
-    if (b < a.nball) {
-      uint32_t v = (uint32_t)a.ball[b];
-      int dx = (int8_t)(v & 255), dy = (int8_t)((v >> 8) & 255), dz = (int8_t)((v >> 16) & 255);
-      int zz = z0 + dz;
-      if (zz >= 0 && zz < a.nz) {
-        int64_t g = ((int64_t)zz * a.ny + wrapd(y0 + dy, a.ny)) * a.nx + wrapd(x0 + dx, a.nx);
-        uint8_t c = a.cls[g];
-        flag = ((c & 1) && !(c & 2)) ? 1 : 0;
+  for (int f = 0; f < a.nfields; ++f) {
+    const int32_t *fb = a.fball[f];
+    const uint8_t *fc = a.fcls[f];
+    uint32_t *fmask = mask + a.fwoff[f];
+    for (int b0 = 0; b0 < a.fnball[f]; b0 += nth) {
+      int b = b0 + tid;
+      int flag = 0;
+      if (b < a.fnball[f]) {
+        uint32_t v = (uint32_t)fb[b];
+        int dx = (int8_t)(v & 255), dy = (int8_t)((v >> 8) & 255), dz = (int8_t)((v >> 16) & 255);
+        int zz = z0 + dz;
+        if (zz >= 0 && zz < a.nz) {
+          int64_t g = ((int64_t)zz * a.ny + wrapd(y0 + dy, a.ny)) * a.nx + wrapd(x0 + dx, a.nx);
+          uint8_t c = fc[g];
+          flag = ((c & 1) && !(c & 2)) ? 1 : 0;
+        }
       }
+      int total;
+      int p = block_scan(flag, iscr, total);
+      if (flag && ndata + p < a.desc_stride) desc[ndata + p] = (f << 16) | b;
+      unsigned long long bal = __ballot(flag);
+      int lane = tid & 63;
+      if (lane == 0 && b < a.fnball[f]) fmask[b >> 5] = (uint32_t)(bal & 0xffffffffull);
+      if (lane == 32 && b < a.fnball[f]) fmask[b >> 5] = (uint32_t)(bal >> 32);
+      ndata += total;
     }
-    int total;
-    int p = block_scan(flag, iscr, total);
-    if (flag) desc[ndata + p] = b;
-    unsigned long long bal = __ballot(flag);
-    int lane = tid & 63;
-    if (lane == 0 && b < a.nball) mask[b >> 5] = (uint32_t)(bal & 0xffffffffull);
-    if (lane == 32 && b < a.nball) mask[b >> 5] = (uint32_t)(bal >> 32);
-    ndata += total;
   }
+  const double xc0 = x0 + a.x0off[0], yc0 = y0 + a.x0off[1], zc0 = z0 + a.x0off[2];
   // ---- boundary points within the radius --------------------------------------------
   int nbp = 0;
   const int side = 2 * a.Rc + 1;
@@ -177,7 +199,7 @@ __global__ void k_solve(SolveArgs a) {
       j1 = a.col_off[col + 1];
       for (int64_t j = j0; j < j1; ++j) {
         const double *p = a.bp + j * 8 + 3;
-        double rx = p[0] - x0, ry = p[1] - y0, rz = p[2] - z0;
+        double rx = p[0] - xc0, ry = p[1] - yc0, rz = p[2] - zc0;
         rx -= a.nx * rint(rx / a.nx);
         if (a.lat == 2) ry -= a.ny * rint(ry / a.ny);
         if (rx * rx + ry * ry + rz * rz <= a.r2) ++cnt;
@@ -203,7 +225,7 @@ __global__ void k_solve(SolveArgs a) {
     if (cnt > 0) {
       for (int64_t j = j0; j < j1; ++j) {
         const double *p = a.bp + j * 8 + 3;
-        double rx = p[0] - x0, ry = p[1] - y0, rz = p[2] - z0;
+        double rx = p[0] - xc0, ry = p[1] - yc0, rz = p[2] - zc0;
         rx -= a.nx * rint(rx / a.nx);
         if (a.lat == 2) ry -= a.ny * rint(ry / a.ny);
         if (rx * rx + ry * ry + rz * rz <= a.r2) {
@@ -223,7 +245,7 @@ __global__ void k_solve(SolveArgs a) {
     nbp += tot;
     __syncthreads();
   }
-  if (nbp > a.maxbp || ndata > a.desc_stride) {
+  if (nbp > a.maxbp || ndata > a.desc_stride || NT > 192) {
     if (tid == 0) {
       a.status[out] = -1;
       a.ndata[out] = ndata;
@@ -231,7 +253,7 @@ __global__ void k_solve(SolveArgs a) {
     return;
   }
   const int m = ndata + nbp * a.nops;
-  if (m < NT) {
+  if (m < NT) {   // fewer rows than unknowns: rank deficient
     if (tid == 0) {
       a.status[out] = 0;
       a.ndata[out] = ndata;
@@ -247,9 +269,11 @@ __global__ void k_solve(SolveArgs a) {
   // k forms the reflector of [R_kk; chunk column k] from its own registers and publishes
   // it in LDS (double buffered); every thread j > k applies it to [R_kj; its column].
   for (int i = tid; i < NT * (NT + 1) / 2; i += nth) R[i] = 0.0;
-  const int8_t ej0 = (tid < NT) ? c_solve.exps[tid][0] : 0;
-  const int8_t ej1 = (tid < NT) ? c_solve.exps[tid][1] : 0;
-  const int8_t ej2 = (tid < NT) ? c_solve.exps[tid][2] : 0;
+  const int bj = (tid < NT) ? tid / NTB : 0;        // unknown block of column tid
+  const int tj = (tid < NT) ? tid - bj * NTB : 0;   // basis term of column tid
+  const int8_t ej0 = c_solve.exps[tj][0];
+  const int8_t ej1 = c_solve.exps[tj][1];
+  const int8_t ej2 = c_solve.exps[tj][2];
   __syncthreads();
   for (int r0 = 0; r0 < m; r0 += nb) {
     const int nr = min(nb, m - r0);
@@ -258,11 +282,12 @@ __global__ void k_solve(SolveArgs a) {
       int r = r0 + tid;
       double d[3];
       if (r < ndata) {
-        uint32_t v = (uint32_t)a.ball[desc[r]];
-        d[0] = (int8_t)(v & 255);
-        d[1] = (int8_t)((v >> 8) & 255);
-        d[2] = (int8_t)((v >> 16) & 255);
-        rowop[tid] = -1;
+        const int f = desc[r] >> 16;
+        uint32_t v = (uint32_t)a.fball[f][desc[r] & 0xffff];
+        d[0] = (int8_t)(v & 255) + a.fshift[f][0];
+        d[1] = (int8_t)((v >> 8) & 255) + a.fshift[f][1];
+        d[2] = (int8_t)((v >> 16) & 255) + a.fshift[f][2];
+        rowop[tid] = -1 - a.fblock[f];
         nrm[tid * 3 + 0] = nrm[tid * 3 + 1] = nrm[tid * 3 + 2] = 0.0;
       } else {
         int rb = r - ndata;
@@ -292,11 +317,12 @@ __global__ void k_solve(SolveArgs a) {
         const double *p = pw + i * 3 * D1;
         const int op = rowop[i];
         if (op < 0) {
-          v = p[ej0] * p[D1 + ej1] * p[2 * D1 + ej2];
+          v = (-1 - op == bj) ? p[ej0] * p[D1 + ej1] * p[2 * D1 + ej2] : 0.0;
         } else {
-          const int nt_ = c_solve.ops.nterms[op];
+          const OpSet &OS = c_solve.ops[bj];
+          const int nt_ = OS.nterms[op];
           for (int q = 0; q < nt_; ++q) {
-            const OpTerm &T = c_solve.ops.term[op][q];
+            const OpTerm &T = OS.term[op][q];
             const int a0 = ej0 - T.beta[0], a1 = ej1 - T.beta[1], a2 = ej2 - T.beta[2];
             if (a0 < 0 || a1 < 0 || a2 < 0) continue;
             double cf = T.coef;
@@ -448,32 +474,59 @@ __global__ void k_solve(SolveArgs a) {
       iscr[9] = full ? 1 : 0;
     }
     if (full) {
-      // c = sum of w_e a(e - i) over exterior cross-stencil nodes, then R^T w = c, R z = w
+      // c = sum of w_e a(x_e - x_0) over the exterior nodes the completed stencil reads
+      // (family 0: Laplacian cross; 1: staggered gradient; 2: staggered divergence,
+      // one block per velocity component), then R^T w = c, R z = w
+      const int half = a.M / 2;
 #pragma unroll
       for (int q = 0; q < 3; ++q) {
-        const int t = lane + 64 * q;
+        const int col = lane + 64 * q;
         double cv = 0.0;
-        if (t < NT) {
+        if (col < NT) {
+          const int blk = col / NTB, t = col - blk * NTB;
           const int8_t *ex = c_solve.exps[t];
-          const int half = a.M / 2;
-          for (int n = 0; n < 3; ++n) {
-            if (a.lat == 1 && n == 1) continue;
-            bool pure = true;      // the term must be a pure power of axis n (or the constant)
+          auto pure_in = [&](int n) {
             for (int qq = 0; qq < 3; ++qq)
-              if (qq != n && ex[qq] != 0) pure = false;
-            if (!pure) continue;
-            for (int k = -half; k <= half; ++k) {
-              if (k == 0) continue;
-              int xx = x0, yy = y0, zz = z0;
-              if (n == 0) xx = wrapd(x0 + k, a.nx);
-              if (n == 1) yy = wrapd(y0 + k, a.ny);
-              if (n == 2) zz = z0 + k;
-              if (zz < 0 || zz >= a.nz) continue;
-              const int64_t g = ((int64_t)zz * a.ny + yy) * a.nx + xx;
-              if (a.cls[g] & 1) continue;
-              double mono = 1.0;
-              for (int pp = 1; pp <= ex[n]; ++pp) mono = mono * (double)k / (double)pp;
-              cv += c_solve.w2[k + half] * mono;
+              if (qq != n && ex[qq] != 0) return false;
+            return true;
+          };
+          auto mono = [&](int n, double rel) {
+            double v = 1.0;
+            for (int pp = 1; pp <= ex[n]; ++pp) v = v * rel / (double)pp;
+            return v;
+          };
+          auto exterior = [&](const uint8_t *cl, int xx, int yy, int zz) {
+            if (zz < 0 || zz >= a.nz) return false;
+            return !(cl[((int64_t)zz * a.ny + wrapd(yy, a.ny)) * a.nx + wrapd(xx, a.nx)] & 1);
+          };
+          if (a.family == 0) {
+            for (int n = 0; n < 3; ++n) {
+              if (a.lat == 1 && n == 1) continue;
+              if (!pure_in(n)) continue;
+              for (int k = -half; k <= half; ++k) {
+                if (k == 0) continue;
+                const int xx = x0 + (n == 0 ? k : 0), yy = y0 + (n == 1 ? k : 0), zz = z0 + (n == 2 ? k : 0);
+                if (!exterior(a.cls, xx, yy, zz)) continue;
+                cv += c_solve.w2[k + half] * mono(n, (double)k);
+              }
+            }
+          } else if (a.family == 1) {
+            const int n = a.gaxis;
+            if (pure_in(n)) {
+              for (int k = -half + 1; k <= half; ++k) {
+                const int xx = x0 + (n == 0 ? k : 0), yy = y0 + (n == 1 ? k : 0), zz = z0 + (n == 2 ? k : 0);
+                if (!exterior(a.xcls[0], xx, yy, zz)) continue;
+                cv += c_solve.ws[k + half - 1] * mono(n, (double)k - 0.5);
+              }
+            }
+          } else {
+            const int n = a.baxis[blk];
+            if (pure_in(n)) {
+              for (int k = -half; k <= half - 1; ++k) {
+                const int xx = x0 + (n == 0 ? k : 0), yy = y0 + (n == 1 ? k : 0), zz = z0 + (n == 2 ? k : 0);
+                if (!exterior(a.xcls[blk], xx, yy, zz)) continue;
+                cv += c_solve.ws[k + half] * mono(n, (double)k + 0.5);
+              }
             }
           }
         }
@@ -494,18 +547,20 @@ __global__ void k_solve(SolveArgs a) {
   // y_j = a_j . z for the data rows
   double *wo = a.wout + (size_t)out * a.nball;
   for (int j = tid; j < ndata; j += nth) {
-    uint32_t v = (uint32_t)a.ball[desc[j]];
-    double d[3] = {(double)(int8_t)(v & 255), (double)(int8_t)((v >> 8) & 255),
-                   (double)(int8_t)((v >> 16) & 255)};
+    const int f = desc[j] >> 16;
+    uint32_t v = (uint32_t)a.fball[f][desc[j] & 0xffff];
+    double d[3] = {(double)(int8_t)(v & 255) + a.fshift[f][0], (double)(int8_t)((v >> 8) & 255) + a.fshift[f][1],
+                   (double)(int8_t)((v >> 16) & 255) + a.fshift[f][2]};
+    const double *zb = yv + a.fblock[f] * NTB;
     double p[3][kMaxOrder + 1];
     for (int n = 0; n < 3; ++n) {
       p[n][0] = 1.0;
       for (int k = 1; k < D1; ++k) p[n][k] = p[n][k - 1] * d[n] / (double)k;
     }
     double s = 0.0;
-    for (int t = 0; t < NT; ++t) {
+    for (int t = 0; t < NTB; ++t) {
       const int8_t *ex = c_solve.exps[t];
-      s += p[0][ex[0]] * p[1][ex[1]] * p[2][ex[2]] * yv[t];
+      s += p[0][ex[0]] * p[1][ex[1]] * p[2][ex[2]] * zb[t];
     }
     wo[j] = s;
   }
@@ -636,7 +691,7 @@ ib_status weights_build(ib_weights *w, const int64_t *col_off_dev, hipStream_t s
 
   for (int Mb = M; Mb >= min_order && !pending.empty(); --Mb) {
     const int NT = n_terms(Mb, ndim);
-    sc.ops = make_ops(w->prm.surface, Mb, ndim);
+    sc.ops[0] = make_ops(w->prm.surface, Mb, ndim);
     IB_HIP(hipMemcpyToSymbolAsync(HIP_SYMBOL(c_solve), &sc, sizeof(sc), 0, hipMemcpyHostToDevice, st));
     for (int k = 0; k <= Kmax && !pending.empty(); ++k) {
       const int code = Mb + 1 + 2 * k;
@@ -673,8 +728,23 @@ ib_status weights_build(ib_weights *w, const int64_t *col_off_dev, hipStream_t s
       A.NT = NT;
       A.Mb = Mb;
       A.M = M;
-      A.nops = sc.ops.nops;
-      A.ball = w->ball + w->balls.start[code];
+      A.nops = sc.ops[0].nops;
+      A.family = 0;
+      A.gaxis = 0;
+      A.nfields = 1;
+      A.nblocks = 1;
+      A.fcls[0] = w->node_class;
+      A.fball[0] = w->ball + w->balls.start[code];
+      A.fnball[0] = nball;
+      A.fnwords[0] = nwords;
+      A.fwoff[0] = 0;
+      A.fblock[0] = 0;
+      A.baxis[0] = 0;
+      for (int q = 0; q < 3; ++q) {
+        A.fshift[0][q] = 0.0;
+        A.x0off[q] = 0.0;
+      }
+      A.xcls[0] = w->node_class;
       A.nball = nball;
       A.nwords = nwords;
       A.r2 = r * r;
