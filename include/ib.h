@@ -49,7 +49,10 @@ typedef enum {
   IB_ERR_STATE = -6           /* call not valid for this handle / state                */
 } ib_status;
 
-typedef enum { IB_FORM_P2 = 0 } ib_form;                    /* second-order pressure form */
+typedef enum { IB_FORM_P2 = 0,  /* second-order pressure form                                  */
+               IB_FORM_PV1 = 1  /* first-order pressure-velocity form on a staggered grid (2D,
+                                   free surface: section "The Particle Velocity Free-Surface") */
+} ib_form;
 typedef enum { IB_SURF_FREE = 0, IB_SURF_RIGID = 1 } ib_surface;
 typedef enum { IB_F32 = 0, IB_F64 = 1 } ib_precision;
 
@@ -77,6 +80,8 @@ typedef struct {
  *   rank_rtol        numerical-rank tolerance relative to sigma_max; <= 0 selects
  *                    max(rows, cols) * 2^-52.
  *   physical_below   1: the physical domain is below the surface (z > H); 0: above.
+ *   eta_v            exclusion cut-off of the velocity nodes (first-order form; the paper
+ *                    uses 0: no velocity node is excluded).
  */
 typedef struct {
   int32_t form;
@@ -87,6 +92,7 @@ typedef struct {
   int32_t physical_below;
   double eta;
   double rank_rtol;
+  double eta_v;
 } ib_params;
 
 typedef struct {
@@ -144,10 +150,18 @@ void ib_weights_free(ib_weights *w);
  *   IB_FIELD_WEIGHTS_F64 float64 [sum_nw]: weights of each point in the lattice order
  *                        of its support ball (z, then y, then x), data nodes only.
  *   IB_FIELD_SIGMA       float64 [n_ib]: estimated sigma_min/sigma_max of accepted A.
+ * First-order form only:
+ *   IB_FIELD_PV_ROWS     int64 [n_rows][3]: family (n < ndim: d/dx_n p at a v_n node,
+ *                        ndim: div v at a p node), memory-order node, number of weights.
+ *   IB_FIELD_PV_ENTRIES  float64 [sum][3]: data field (-1 p, n: v_n along the n-th
+ *                        velocity axis), memory-order node, weight; rows in order.
+ *   IB_FIELD_VCLASS      uint8 [ndim][n_nodes]: classes of the v_n nodes (bit0 interior,
+ *                        bit1 excluded).
  * dst_bytes must be at least the field size. */
 typedef enum {
   IB_FIELD_NODE_CLASS = 0, IB_FIELD_BPOINTS = 1, IB_FIELD_IB_NODES = 2,
-  IB_FIELD_IB_META = 3, IB_FIELD_WEIGHTS_F64 = 4, IB_FIELD_SIGMA = 5
+  IB_FIELD_IB_META = 3, IB_FIELD_WEIGHTS_F64 = 4, IB_FIELD_SIGMA = 5,
+  IB_FIELD_PV_ROWS = 6, IB_FIELD_PV_ENTRIES = 7, IB_FIELD_VCLASS = 8
 } ib_field;
 ib_status ib_weights_copy(const ib_weights *w, int32_t field, void *dst_host, int64_t dst_bytes);
 
@@ -163,6 +177,8 @@ ib_status ib_weights_copy(const ib_weights *w, int32_t field, void *dst_host, in
  *             dt^2 * wavelet / h^d (the paper's f~ = f dt^2).
  *   rec_pos_host: host float64 [nrec][ndim] receivers (metres), sampled multilinearly;
  *             shared by all shots.
+ * First-order form (weights built with IB_FORM_PV1): the state holds p and the staggered
+ *   velocities v_n (rho = 1); the source amplitude is dt * wavelet / h^d.
  * Wavefields start at zero; the step counter at 0.
  * Errors: IB_ERR_ARG (positions outside the box or touching exterior nodes, nshots < 1),
  *   IB_ERR_OOM, IB_ERR_HIP. */
@@ -179,6 +195,11 @@ void ib_state_free(ib_state *st);
  *     sample t of the state's step counter (t = 0, 1, ...).  Must cover t + nsteps.
  *   traces_dev:  device [nshots][nsteps][nrec] in the state precision; receives
  *     p^{n+1} sampled at the receivers after each step.  May be NULL when nrec = 0.
+ * First-order form: each step is
+ *   v_n^{n+1/2} = [(1 - s) v_n^{n-1/2} + (dt / h) D+_n p^n] / (1 + s)       (interior v_n nodes)
+ *   p^{n+1}     = [(1 - s) p^n + (dt c^2 / h) D-.v^{n+1/2} + dt f^n] / (1 + s)  (interior p nodes)
+ *   with the staggered M-th order differences and the immersed-boundary rows of both
+ *   families; the traces sample p^{n+1}.
  * When use_graph is non-zero the per-step kernels are captured once into a HIP graph
  * (two steps, even/odd buffers) and replayed; results are identical to eager launch. */
 ib_status ib_step(ib_state *st, int32_t nsteps, const void *wavelet_dev, int64_t wavelet_stride,
@@ -201,12 +222,15 @@ ib_status ib_forward(ib_state *st, int32_t nt, const void *wavelet_dev, int64_t 
  * Each checkpoint segment is recomputed forward and kept (ckpt_every fields) while the
  * adjoint steps back through it; the adjoint of the IB rows uses a transposed stencil
  * table (per receiving node) built on the first call.
- * Errors: IB_ERR_STATE without a previous ib_forward. */
+ * Errors: IB_ERR_STATE without a previous ib_forward; IB_ERR_ARG for the first-order form
+ *   (ib_forward and ib_adjoint cover the second-order form only). */
 ib_status ib_adjoint(ib_state *st, const void *residual_dev, const void *wavelet_dev, int64_t wavelet_stride,
                      double *grad_dev, void *stream);
 
 /* Read or write the current wavefields of one shot (layout [nz][ny][nx] or [nz][nx],
  * state precision, device memory):  which = 0: p^n (newest), 1: p^{n-1}.
+ * First-order form: which = 0: p^n, 2 + k: v_k^{n-1/2} (k < ndim; in 2D k = 1 is the
+ * vertical velocity), 1 is invalid.
  * direction 0 copies out of the state, 1 copies into it. */
 ib_status ib_state_field(ib_state *st, int32_t which, int32_t shot, void *dev_buf, int32_t direction,
                          void *stream);
@@ -215,7 +239,7 @@ int64_t ib_state_step_count(const ib_state *st);
 /* Measurement aid: enqueue ``count`` launches of one kernel of the step on ``stream``
  * with the current buffers (which = 0: interior stencil, 1: IB patch), rotating the
  * buffers as a step would, without sources, receivers or the step counter.  Used to
- * time each kernel on its own; it changes the wavefields. */
+ * time each kernel on its own; it changes the wavefields.  Second-order form only. */
 ib_status ib_state_run_kernel(ib_state *st, int32_t which, int32_t count, void *stream);
 
 /* Tuning knobs of the 3D eighth-order interior kernel: variant 0 (one plane per barrier

@@ -37,10 +37,11 @@ def abi_version():
 class IBWeights:
     """Handle of a built stencil table (library-owned device memory)."""
 
-    def __init__(self, handle, ndim, shape):
+    def __init__(self, handle, ndim, shape, form="p2"):
         self._h = handle
         self.ndim = ndim
         self.shape = shape
+        self.form = form
 
     def stats(self):
         st = _lib.ib_stats()
@@ -59,6 +60,15 @@ class IBWeights:
         """Host copies of the table: node classes, boundary points, IB nodes, meta, weights."""
         s = self.stats()
         N, nb, nib, sw = s["n_nodes"], s["n_boundary_points"], s["n_ib"], s["sum_nw"]
+        if self.form == "pv1":
+            return dict(
+                node_class=self.copy(_lib.FIELD_NODE_CLASS, np.uint8, N),
+                bpoints=self.copy(_lib.FIELD_BPOINTS, np.float64, nb * 7).reshape(nb, 7),
+                rows=self.copy(_lib.FIELD_PV_ROWS, np.int64, nib * 3).reshape(nib, 3),
+                entries=self.copy(_lib.FIELD_PV_ENTRIES, np.float64, sw * 3).reshape(sw, 3),
+                vclass=self.copy(_lib.FIELD_VCLASS, np.uint8, self.ndim * N).reshape(self.ndim, N),
+                stats=s,
+            )
         return dict(
             node_class=self.copy(_lib.FIELD_NODE_CLASS, np.uint8, N),
             bpoints=self.copy(_lib.FIELD_BPOINTS, np.float64, nb * 7).reshape(nb, 7),
@@ -82,8 +92,14 @@ class IBWeights:
 
 
 def ib_build_weights(heights, h, shape, space_order=8, surface="free", eta=0.5, max_radius_steps=3,
-                     min_basis_order=None, physical_below=True, rank_rtol=0.0, stream=None):
-    """Build the IB stencils for a heightfield (torch float64 device tensor or array, metres)."""
+                     min_basis_order=None, physical_below=True, rank_rtol=0.0, form="p2", eta_v=0.0, stream=None):
+    """Build the IB stencils for a heightfield (torch float64 device tensor or array, metres).
+
+    ``form`` "p2" is the second-order pressure form, "pv1" the first-order pressure-velocity
+    form on a staggered grid (2D).
+    """
+    if form not in ("p2", "pv1"):
+        raise ValueError("form must be 'p2' or 'pv1'")
     torch = _torch()
     ndim = len(shape)
     Ht = torch.as_tensor(np.ascontiguousarray(heights, dtype=np.float64) if not torch.is_tensor(heights) else heights,
@@ -94,7 +110,8 @@ def ib_build_weights(heights, h, shape, space_order=8, surface="free", eta=0.5, 
         g.n[i] = int(n)
     g.h = float(h)
     p = _lib.ib_params()
-    p.form = _lib.IB_FORM_P2
+    p.form = _lib.IB_FORM_P2 if form == "p2" else _lib.IB_FORM_PV1
+    p.eta_v = float(eta_v)
     p.surface = IB_SURF_FREE if surface == "free" else IB_SURF_RIGID
     p.space_order = int(space_order)
     p.max_radius_steps = int(max_radius_steps)
@@ -105,7 +122,7 @@ def ib_build_weights(heights, h, shape, space_order=8, surface="free", eta=0.5, 
     out = C.c_void_p()
     _lib.check(_lib.load().ib_build_weights(C.byref(g), C.c_void_p(Ht.data_ptr()), C.byref(p), _stream(stream),
                                             C.byref(out)))
-    return IBWeights(out, ndim, tuple(int(v) for v in shape))
+    return IBWeights(out, ndim, tuple(int(v) for v in shape), form)
 
 
 class IBState:
@@ -139,7 +156,9 @@ class IBState:
         return traces
 
     def field(self, which=0, shot=0, value=None, stream=None):
-        """Get (value None) or set p^n (which=0) / p^{n-1} (which=1) of one shot."""
+        """Get (value None) or set p^n (which=0) / p^{n-1} (which=1) of one shot.
+
+        First-order form: which=0 is p^n and which=2+k the velocity v_k^{n-1/2}."""
         torch = _torch()
         shape = tuple(reversed(self.weights.shape))
         if value is None:

@@ -15,6 +15,7 @@ namespace ib {
 ib_status geometry_build(ib_weights *w, const double *height_dev, hipStream_t st);
 ib_status ib_points_build(ib_weights *w, hipStream_t st);
 ib_status weights_build(ib_weights *w, const int64_t *col_off_dev, hipStream_t st);
+ib_status pv_build(ib_weights *w, const int64_t *col_off_dev, hipStream_t st);
 const char *last_error_text();
 }  // namespace ib
 
@@ -55,6 +56,13 @@ struct ib_state {
   void *g_traces = nullptr;
   int64_t g_wstride = 0, g_nsteps = 0;
   int g_cur = 0;
+  // first-order form: p in buf[0], velocities [shot][nv][vol], coefficients, modified rows
+  int form = 0, nv = 0;
+  void *vbuf = nullptr, *kv = nullptr;
+  int64_t nrows_g = 0, nrows_d = 0;
+  int64_t *g_node = nullptr, *g_start = nullptr, *g_enode = nullptr, *d_node = nullptr, *d_start = nullptr,
+          *d_enode = nullptr;
+  void *g_scale = nullptr, *g_w = nullptr, *d_scale = nullptr, *d_w = nullptr;
   // host copies needed by the adjoint
   std::vector<double> ax, ay, az;
   std::vector<int64_t> ridx_h;
@@ -129,6 +137,19 @@ __global__ void k_make_K(const double *vel, const uint8_t *cls, T *K, int nx, in
   int y = (int)(r % ny), z = (int)(r / ny);
   double v = vel[i];
   double k = (cls[i] & 1) ? (v * f) * (v * f) : 0.0;
+  K[((size_t)z * ny + y) * pitch + x] = (T)k;
+}
+
+template <typename T>
+__global__ void k_make_coef(const double *vel, const uint8_t *cls, T *K, int nx, int ny, int nz, int64_t pitch,
+                            double f, int use_vel) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int64_t N = (int64_t)nx * ny * nz;
+  if (i >= N) return;
+  int x = (int)(i % nx);
+  int64_t r = i / nx;
+  int y = (int)(r % ny), z = (int)(r / ny);
+  double k = (cls[i] & 1) ? (use_vel ? f * vel[i] * vel[i] : f) : 0.0;
   K[((size_t)z * ny + y) * pitch + x] = (T)k;
 }
 
@@ -273,8 +294,22 @@ ib_status ib_build_weights(const ib_grid *g, const double *height_dev, const ib_
     set_error("ndim must be 2 or 3 (got %d)", g->ndim);
     return IB_ERR_ARG;
   }
-  if (p->form != IB_FORM_P2) {
+  if (p->form != IB_FORM_P2 && p->form != IB_FORM_PV1) {
     set_error("unsupported form %d", p->form);
+    return IB_ERR_ARG;
+  }
+  if (p->form == IB_FORM_PV1 && g->ndim != 2) {
+    set_error("the first-order form is built for 2D grids (its coupled 3D velocity systems exceed the solver)");
+    return IB_ERR_ARG;
+  }
+  if (p->form == IB_FORM_PV1 && p->surface != IB_SURF_FREE) {
+    // the method's first-order form is given for the free surface (zero pressure and the
+    // divergence hierarchy); a rigid-surface velocity row set is not part of it
+    set_error("the first-order form supports the free surface only");
+    return IB_ERR_ARG;
+  }
+  if (p->form == IB_FORM_PV1 && !(p->eta_v >= 0.0 && p->eta_v <= 1.0)) {
+    set_error("eta_v must be in [0, 1] (got %g)", p->eta_v);
     return IB_ERR_ARG;
   }
   if (p->surface != IB_SURF_FREE && p->surface != IB_SURF_RIGID) {
@@ -346,7 +381,8 @@ ib_status ib_build_weights(const ib_grid *g, const double *height_dev, const ib_
       return IB_ERR_ARG;
     }
   }
-  if ((s = ib_points_build(w, st)) != IB_OK) {
+  w->form = p->form;
+  if (w->form == IB_FORM_P2 && (s = ib_points_build(w, st)) != IB_OK) {
     ib_weights_free(w);
     return s;
   }
@@ -368,7 +404,7 @@ ib_status ib_build_weights(const ib_grid *g, const double *height_dev, const ib_
     }
     IB_HIP(hipMemcpy(col_off, off.data(), (ncol + 1) * 8, hipMemcpyHostToDevice));
   }
-  s = weights_build(w, col_off, st);
+  s = (w->form == IB_FORM_P2) ? weights_build(w, col_off, st) : pv_build(w, col_off, st);
   dfree(col_off);
   if (s != IB_OK) {
     ib_weights_free(w);
@@ -422,6 +458,7 @@ void ib_weights_free(ib_weights *w) {
   dfree(w->dense_first);
   dfree(w->dense_count);
   dfree(w->dense_off);
+  for (int n = 0; n < 3; ++n) dfree(w->vcls[n]);
   delete w;
 }
 
@@ -438,6 +475,39 @@ ib_status ib_weights_copy(const ib_weights *w, int32_t field, void *dst, int64_t
     case IB_FIELD_IB_META: src = w->ib_meta; need = w->nib * 16; break;
     case IB_FIELD_WEIGHTS_F64: src = w->w64; need = w->sumw * 8; break;
     case IB_FIELD_SIGMA: src = w->ib_sigma; need = w->nib * 8; break;
+    case IB_FIELD_PV_ROWS:
+    case IB_FIELD_PV_ENTRIES:
+    case IB_FIELD_VCLASS: {
+      if (w->form != IB_FORM_PV1) {
+        set_error("ib_weights_copy: field %d exists for the first-order form only", field);
+        return IB_ERR_STATE;
+      }
+      const int64_t nr = (int64_t)w->pv_row_fam.size(), ne = (int64_t)w->pv_ent_w.size();
+      need = (field == IB_FIELD_PV_ROWS) ? nr * 24 : (field == IB_FIELD_PV_ENTRIES ? ne * 24 : w->ndim * w->N);
+      if (bytes < need) {
+        set_error("ib_weights_copy: destination too small (%lld < %lld)", (long long)bytes, (long long)need);
+        return IB_ERR_ARG;
+      }
+      if (field == IB_FIELD_PV_ROWS) {
+        int64_t *o = (int64_t *)dst;
+        for (int64_t r = 0; r < nr; ++r) {
+          o[r * 3] = w->pv_row_fam[r];
+          o[r * 3 + 1] = w->pv_row_node[r];
+          o[r * 3 + 2] = w->pv_row_start[r + 1] - w->pv_row_start[r];
+        }
+      } else if (field == IB_FIELD_PV_ENTRIES) {
+        double *o = (double *)dst;
+        for (int64_t e = 0; e < ne; ++e) {
+          o[e * 3] = w->pv_ent_field[e];
+          o[e * 3 + 1] = (double)w->pv_ent_node[e];
+          o[e * 3 + 2] = w->pv_ent_w[e];
+        }
+      } else {
+        for (int n = 0; n < w->ndim; ++n)
+          IB_HIP(hipMemcpy((uint8_t *)dst + n * w->N, w->vcls[n], w->N, hipMemcpyDeviceToHost));
+      }
+      return IB_OK;
+    }
     case IB_FIELD_BPOINTS: {
       need = w->nb * 7 * 8;
       if (bytes < need) {
@@ -545,74 +615,150 @@ ib_status ib_state_create(const ib_weights *w, const double *vel_dev, double dt,
   S->ax = ax;
   S->ay = ay;
   S->az = az;
-  if ((s = dalloc(&S->scale, std::max<int64_t>(w->nib, 1) * S->esz))) return fail(s);
-  if (w->nib > 0) {
-    if (prec == IB_F32)
-      hipLaunchKernelGGL(k_make_scale<float>, dim3((w->nib + T - 1) / T), dim3(T), 0, st, w->ib_xyz, w->nib, vel_dev,
-                         (int)w->nx, (int)w->ny, f, d_ax, d_ay, d_az, (float *)S->scale);
-    else
-      hipLaunchKernelGGL(k_make_scale<double>, dim3((w->nib + T - 1) / T), dim3(T), 0, st, w->ib_xyz, w->nib,
-                         vel_dev, (int)w->nx, (int)w->ny, f, d_ax, d_ay, d_az, (double *)S->scale);
-    IB_HIP(hipGetLastError());
-  }
-  if ((s = dalloc(&S->pinfo, std::max<int64_t>(w->nib, 1) * pinfo_bytes(prec))) ||
-      (s = dalloc_t(&S->delta, std::max<size_t>(w->balls.packed.size(), 1))))
-    return fail(s);
-  enqueue_make_pinfo(prec, w->ib_xyz, prec == IB_F32 ? w->rec_off32 : w->rec_off64, S->scale, nullptr, w->nib,
-                     S->pinfo, st);
-  {
-    // bucket the IB points into LDS tiles (3D); wider supports go to the gather kernel
-    std::vector<int16_t> xyz(w->nib * 4);
-    if (w->nib) IB_HIP(hipMemcpy(xyz.data(), w->ib_xyz, w->nib * 8, hipMemcpyDeviceToHost));
-    std::vector<int32_t> tiled, wide;
-    std::vector<int64_t> key;
-    const bool use_tiles = (w->ndim == 3);
-    const int64_t tx = (w->nx + kTileX - 1) / kTileX, ty = (w->ny + kTileY - 1) / kTileY;
-    for (int64_t i = 0; i < w->nib; ++i) {
-      const int code = xyz[i * 4 + 3];
-      if (use_tiles && (code == 8 || code == 9) && kTileHalo == 4)
-        tiled.push_back((int32_t)i);
+  S->form = w->form;
+  if (w->form == IB_FORM_PV1) {
+    // first-order form: K holds dt c^2 / h at interior p nodes, kv dt / h at interior v nodes
+    S->nv = w->ndim;
+    const size_t vbytes = (size_t)S->vol * S->nv * nshots * S->esz;
+    if ((s = dalloc(&S->vbuf, vbytes)) || (s = dalloc(&S->kv, (size_t)S->vol * S->nv * S->esz))) return fail(s);
+    IB_HIP(hipMemsetAsync(S->vbuf, 0, vbytes, st));
+    IB_HIP(hipMemsetAsync(S->kv, 0, (size_t)S->vol * S->nv * S->esz, st));
+    for (int n = 0; n < S->nv; ++n) {
+      char *dst = (char *)S->kv + (size_t)n * S->vol * S->esz;
+      if (prec == IB_F32)
+        hipLaunchKernelGGL(k_make_coef<float>, dim3((w->N + T - 1) / T), dim3(T), 0, st, vel_dev, w->vcls[n],
+                           (float *)dst, (int)w->nx, (int)w->ny, (int)w->nz, S->pitch, f, 0);
       else
-        wide.push_back((int32_t)i);
+        hipLaunchKernelGGL(k_make_coef<double>, dim3((w->N + T - 1) / T), dim3(T), 0, st, vel_dev, w->vcls[n],
+                           (double *)dst, (int)w->nx, (int)w->ny, (int)w->nz, S->pitch, f, 0);
     }
-    auto tkey = [&](int32_t i) {
-      return ((int64_t)(xyz[i * 4 + 2] / kTileZ) * ty + xyz[i * 4 + 1] / kTileY) * tx + xyz[i * 4 + 0] / kTileX;
+    if (prec == IB_F32)
+      hipLaunchKernelGGL(k_make_coef<float>, dim3((w->N + T - 1) / T), dim3(T), 0, st, vel_dev, w->node_class,
+                         (float *)S->K, (int)w->nx, (int)w->ny, (int)w->nz, S->pitch, dt / w->h, 1);
+    else
+      hipLaunchKernelGGL(k_make_coef<double>, dim3((w->N + T - 1) / T), dim3(T), 0, st, vel_dev, w->node_class,
+                         (double *)S->K, (int)w->nx, (int)w->ny, (int)w->nz, S->pitch, dt / w->h, 1);
+    IB_HIP(hipGetLastError());
+    // modified rows with their scales, in the state layout
+    std::vector<double> velh(w->N);
+    IB_HIP(hipMemcpy(velh.data(), vel_dev, w->N * 8, hipMemcpyDeviceToHost));
+    auto padded = [&](int64_t node) {
+      const int64_t x = node % w->nx, y = (node / w->nx) % w->ny, z = node / (w->nx * w->ny);
+      return (z * w->ny + y) * S->pitch + x;
     };
-    std::stable_sort(tiled.begin(), tiled.end(), [&](int32_t a, int32_t b) { return tkey(a) < tkey(b); });
-    std::vector<int4> tl;
-    for (size_t j = 0; j < tiled.size(); ++j) {
-      if (j == 0 || tkey(tiled[j]) != tkey(tiled[j - 1]) || (int)j - tl.back().w >= kTileMaxPoints) {
-        int32_t i = tiled[j];
-        tl.push_back(make_int4(xyz[i * 4] / kTileX * kTileX, xyz[i * 4 + 1] / kTileY * kTileY,
-                               xyz[i * 4 + 2] / kTileZ * kTileZ, (int)j));
+    auto sig = [&](int64_t node) {
+      const int64_t x = node % w->nx, y = (node / w->nx) % w->ny, z = node / (w->nx * w->ny);
+      return ax[x] + ay[w->ndim == 3 ? y : 0] + az[z];
+    };
+    std::vector<int64_t> gn, gs(1, 0), ge, dn, ds(1, 0), de;
+    std::vector<double> gsc, gw, dsc, dw;
+    const int64_t nr = (int64_t)w->pv_row_fam.size();
+    for (int64_t r = 0; r < nr; ++r) {
+      const int fam = w->pv_row_fam[r];
+      const int64_t node = w->pv_row_node[r];
+      const bool grad = fam < S->nv;
+      for (int64_t e = w->pv_row_start[r]; e < w->pv_row_start[r + 1]; ++e) {
+        const int fld = w->pv_ent_field[e];
+        const int64_t q = padded(w->pv_ent_node[e]) + (fld >= 0 ? (int64_t)fld * S->vol : 0);
+        (grad ? ge : de).push_back(q);
+        (grad ? gw : dw).push_back(w->pv_ent_w[e]);
+      }
+      if (grad) {
+        gn.push_back((int64_t)fam * S->vol + padded(node));
+        gsc.push_back(f / (1.0 + sig(node)));
+        gs.push_back((int64_t)ge.size());
+      } else {
+        const double c = velh[node];
+        dn.push_back(padded(node));
+        dsc.push_back((dt * c * c / w->h) / (1.0 + sig(node)));
+        ds.push_back((int64_t)de.size());
       }
     }
-    tl.push_back(make_int4(0, 0, 0, (int)tiled.size()));
-    S->ntiles = (int)tl.size() - 1;
-    S->nwide = (int64_t)wide.size();
-    int32_t *d_perm = nullptr;
-    if ((s = dalloc(&S->pinfo_t, std::max<size_t>(tiled.size(), 1) * pinfo_dense_bytes(prec))) ||
-        (s = dalloc(&S->pinfo_w, std::max<size_t>(wide.size(), 1) * pinfo_bytes(prec))) ||
-        (s = dalloc_t(&S->tiles, tl.size())) ||
-        (s = dalloc_t(&d_perm, std::max<size_t>(std::max(tiled.size(), wide.size()), 1))))
+    S->nrows_g = (int64_t)gn.size();
+    S->nrows_d = (int64_t)dn.size();
+    auto up64 = [&](const std::vector<int64_t> &v, int64_t **d) -> ib_status {
+      ib_status e = dalloc_t(d, std::max<size_t>(v.size(), 1));
+      if (e) return e;
+      if (!v.empty()) IB_HIP(hipMemcpy(*d, v.data(), v.size() * 8, hipMemcpyHostToDevice));
+      return IB_OK;
+    };
+    if ((s = up64(gn, &S->g_node)) || (s = up64(gs, &S->g_start)) || (s = up64(ge, &S->g_enode)) ||
+        (s = up64(dn, &S->d_node)) || (s = up64(ds, &S->d_start)) || (s = up64(de, &S->d_enode)) ||
+        (s = upload_cast(gsc.empty() ? std::vector<double>(1, 0.0) : gsc, &S->g_scale)) ||
+        (s = upload_cast(gw.empty() ? std::vector<double>(1, 0.0) : gw, &S->g_w)) ||
+        (s = upload_cast(dsc.empty() ? std::vector<double>(1, 0.0) : dsc, &S->d_scale)) ||
+        (s = upload_cast(dw.empty() ? std::vector<double>(1, 0.0) : dw, &S->d_w)))
       return fail(s);
-    IB_HIP(hipMemcpy(S->tiles, tl.data(), tl.size() * sizeof(int4), hipMemcpyHostToDevice));
-    const uint32_t *ro = (prec == IB_F32) ? w->rec_off32 : w->rec_off64;
-    if (!tiled.empty()) {
-      IB_HIP(hipMemcpy(d_perm, tiled.data(), tiled.size() * 4, hipMemcpyHostToDevice));
-      enqueue_make_pinfo_dense(prec, w->ib_xyz, w->dense_first, w->dense_count, w->dense_off, S->scale, d_perm,
-                               (int64_t)tiled.size(), S->pinfo_t, st);
-      IB_HIP(hipStreamSynchronize(st));
+  } else {
+    if ((s = dalloc(&S->scale, std::max<int64_t>(w->nib, 1) * S->esz))) return fail(s);
+    if (w->nib > 0) {
+      if (prec == IB_F32)
+        hipLaunchKernelGGL(k_make_scale<float>, dim3((w->nib + T - 1) / T), dim3(T), 0, st, w->ib_xyz, w->nib, vel_dev,
+                           (int)w->nx, (int)w->ny, f, d_ax, d_ay, d_az, (float *)S->scale);
+      else
+        hipLaunchKernelGGL(k_make_scale<double>, dim3((w->nib + T - 1) / T), dim3(T), 0, st, w->ib_xyz, w->nib,
+                           vel_dev, (int)w->nx, (int)w->ny, f, d_ax, d_ay, d_az, (double *)S->scale);
+      IB_HIP(hipGetLastError());
     }
-    if (!wide.empty()) {
-      IB_HIP(hipMemcpy(d_perm, wide.data(), wide.size() * 4, hipMemcpyHostToDevice));
-      enqueue_make_pinfo(prec, w->ib_xyz, ro, S->scale, d_perm, (int64_t)wide.size(), S->pinfo_w, st);
-      IB_HIP(hipStreamSynchronize(st));
+    if ((s = dalloc(&S->pinfo, std::max<int64_t>(w->nib, 1) * pinfo_bytes(prec))) ||
+        (s = dalloc_t(&S->delta, std::max<size_t>(w->balls.packed.size(), 1))))
+      return fail(s);
+    enqueue_make_pinfo(prec, w->ib_xyz, prec == IB_F32 ? w->rec_off32 : w->rec_off64, S->scale, nullptr, w->nib,
+                       S->pinfo, st);
+    {
+      // bucket the IB points into LDS tiles (3D); wider supports go to the gather kernel
+      std::vector<int16_t> xyz(w->nib * 4);
+      if (w->nib) IB_HIP(hipMemcpy(xyz.data(), w->ib_xyz, w->nib * 8, hipMemcpyDeviceToHost));
+      std::vector<int32_t> tiled, wide;
+      std::vector<int64_t> key;
+      const bool use_tiles = (w->ndim == 3);
+      const int64_t tx = (w->nx + kTileX - 1) / kTileX, ty = (w->ny + kTileY - 1) / kTileY;
+      for (int64_t i = 0; i < w->nib; ++i) {
+        const int code = xyz[i * 4 + 3];
+        if (use_tiles && (code == 8 || code == 9) && kTileHalo == 4)
+          tiled.push_back((int32_t)i);
+        else
+          wide.push_back((int32_t)i);
+      }
+      auto tkey = [&](int32_t i) {
+        return ((int64_t)(xyz[i * 4 + 2] / kTileZ) * ty + xyz[i * 4 + 1] / kTileY) * tx + xyz[i * 4 + 0] / kTileX;
+      };
+      std::stable_sort(tiled.begin(), tiled.end(), [&](int32_t a, int32_t b) { return tkey(a) < tkey(b); });
+      std::vector<int4> tl;
+      for (size_t j = 0; j < tiled.size(); ++j) {
+        if (j == 0 || tkey(tiled[j]) != tkey(tiled[j - 1]) || (int)j - tl.back().w >= kTileMaxPoints) {
+          int32_t i = tiled[j];
+          tl.push_back(make_int4(xyz[i * 4] / kTileX * kTileX, xyz[i * 4 + 1] / kTileY * kTileY,
+                                 xyz[i * 4 + 2] / kTileZ * kTileZ, (int)j));
+        }
+      }
+      tl.push_back(make_int4(0, 0, 0, (int)tiled.size()));
+      S->ntiles = (int)tl.size() - 1;
+      S->nwide = (int64_t)wide.size();
+      int32_t *d_perm = nullptr;
+      if ((s = dalloc(&S->pinfo_t, std::max<size_t>(tiled.size(), 1) * pinfo_dense_bytes(prec))) ||
+          (s = dalloc(&S->pinfo_w, std::max<size_t>(wide.size(), 1) * pinfo_bytes(prec))) ||
+          (s = dalloc_t(&S->tiles, tl.size())) ||
+          (s = dalloc_t(&d_perm, std::max<size_t>(std::max(tiled.size(), wide.size()), 1))))
+        return fail(s);
+      IB_HIP(hipMemcpy(S->tiles, tl.data(), tl.size() * sizeof(int4), hipMemcpyHostToDevice));
+      const uint32_t *ro = (prec == IB_F32) ? w->rec_off32 : w->rec_off64;
+      if (!tiled.empty()) {
+        IB_HIP(hipMemcpy(d_perm, tiled.data(), tiled.size() * 4, hipMemcpyHostToDevice));
+        enqueue_make_pinfo_dense(prec, w->ib_xyz, w->dense_first, w->dense_count, w->dense_off, S->scale, d_perm,
+                                 (int64_t)tiled.size(), S->pinfo_t, st);
+        IB_HIP(hipStreamSynchronize(st));
+      }
+      if (!wide.empty()) {
+        IB_HIP(hipMemcpy(d_perm, wide.data(), wide.size() * 4, hipMemcpyHostToDevice));
+        enqueue_make_pinfo(prec, w->ib_xyz, ro, S->scale, d_perm, (int64_t)wide.size(), S->pinfo_w, st);
+        IB_HIP(hipStreamSynchronize(st));
+      }
+      dfree(d_perm);
     }
-    dfree(d_perm);
+    enqueue_make_delta(w->ball, (int)w->balls.packed.size(), S->pitch, S->pitch * w->ny, S->delta, st);
+    IB_HIP(hipGetLastError());
   }
-  enqueue_make_delta(w->ball, (int)w->balls.packed.size(), S->pitch, S->pitch * w->ny, S->delta, st);
-  IB_HIP(hipGetLastError());
   IB_HIP(hipStreamSynchronize(st));
   dfree(d_ax), dfree(d_ay), dfree(d_az);
   // sources: interior corners only; amplitude factor dt^2 w / (h^d (1 + s))
@@ -638,7 +784,7 @@ ib_status ib_state_create(const ib_weights *w, const double *vel_dev, double dt,
       int64_t x = idu[c] % w->nx, y = (idu[c] / w->nx) % w->ny, z = idu[c] / (w->nx * w->ny);
       double sd = ax[x] + ay[(w->ndim == 3) ? y : 0] + az[z];
       sidx[sh * 8 + c] = idx[c];
-      swv[sh * 8 + c] = dt * dt * wt[c] / (hd * (1.0 + sd));
+      swv[sh * 8 + c] = (w->form == IB_FORM_PV1 ? dt : dt * dt) * wt[c] / (hd * (1.0 + sd));
     }
   }
   if ((s = dalloc_t(&S->sidx, nshots * 8)) || (s = dalloc(&S->sw, nshots * 8 * S->esz))) return fail(s);
@@ -673,7 +819,7 @@ ib_status ib_state_create(const ib_weights *w, const double *vel_dev, double dt,
   IB_HIP(hipMemset(S->tcount, 0, 32));
   IB_HIP(hipStreamSynchronize(st));
   // z-chunking of the 3D interior kernel: enough workgroups to fill 256 CUs
-  if (w->ndim == 3) {
+  if (w->ndim == 3 && w->form == IB_FORM_P2) {
     int64_t tiles = ((w->nx + 63) / 64) * ((w->ny + 15) / 16) * nshots;
     int64_t want = 2048;
     int nzc = (int)std::max<int64_t>(1, std::min<int64_t>(w->nz / 16, (want + tiles - 1) / tiles));
@@ -707,6 +853,9 @@ void ib_state_free(ib_state *S) {
   dfree(S->rw);
   dfree(S->tcount);
   dfree(S->ckpt);
+  dfree(S->vbuf), dfree(S->kv);
+  dfree(S->g_node), dfree(S->g_start), dfree(S->g_enode), dfree(S->d_node), dfree(S->d_start), dfree(S->d_enode);
+  dfree(S->g_scale), dfree(S->g_w), dfree(S->d_scale), dfree(S->d_w);
   dfree(S->jnode), dfree(S->joff), dfree(S->jsrc), dfree(S->rnode), dfree(S->roff), dfree(S->rrec);
   dfree(S->jD), dfree(S->jw), dfree(S->rD), dfree(S->rwt);
   delete S;
@@ -734,6 +883,46 @@ ib_status ib_state_set_tuning(ib_state *S, int32_t variant, int32_t zchunk) {
 
 namespace {
 
+PVArgs make_pv_args(const ib_state *S) {
+  const ib_weights *w = S->w;
+  PVArgs a{};
+  a.prec = S->prec;
+  a.ndim = w->ndim;
+  a.M = w->M;
+  a.nv = S->nv;
+  a.nx = (int)w->nx;
+  a.ny = (int)w->ny;
+  a.nz = (int)w->nz;
+  a.pitch = S->pitch;
+  a.vol = S->vol;
+  a.nshots = S->nshots;
+  a.p = S->buf[0];
+  a.v = S->vbuf;
+  a.kp = S->K;
+  a.kv = S->kv;
+  a.sx = S->sx;
+  a.sy = S->sy;
+  a.sz = S->sz;
+  a.nrows_g = S->nrows_g;
+  a.nrows_d = S->nrows_d;
+  a.g_node = S->g_node, a.g_start = S->g_start, a.g_enode = S->g_enode;
+  a.d_node = S->d_node, a.d_start = S->d_start, a.d_enode = S->d_enode;
+  a.g_scale = S->g_scale, a.g_w = S->g_w, a.d_scale = S->d_scale, a.d_w = S->d_w;
+  return a;
+}
+
+// one full step of either form: operator update, source injection, receiver sampling
+void enqueue_full_step(ib_state *S, const void *wavelet, int64_t wstride, void *traces, int64_t trace_nt, int cur,
+                       hipStream_t st) {
+  StepArgs a = make_args(S, wavelet, wstride, traces, trace_nt, cur);
+  if (S->form == IB_FORM_PV1) {
+    enqueue_pv_step(make_pv_args(S), st);
+    enqueue_source_receivers(a, S->buf[0], st);
+  } else {
+    enqueue_step(a, st);
+  }
+}
+
 // nsteps steps; traces (may be null) are [nshots][trace_nt][nrec] with step t stored at
 // row t - trace_t0.
 ib_status run_steps(ib_state *S, int64_t nsteps, const void *wavelet, int64_t wstride, void *traces, int64_t trace_nt,
@@ -754,10 +943,7 @@ ib_status run_steps(ib_state *S, int64_t nsteps, const void *wavelet, int64_t ws
       hipStream_t cs;
       IB_HIP(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
       IB_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
-      for (int q = 0; q < 2; ++q) {
-        StepArgs a = make_args(S, wavelet, wstride, traces, trace_nt, (S->cur + q) & 1);
-        enqueue_step(a, cs);
-      }
+      for (int q = 0; q < 2; ++q) enqueue_full_step(S, wavelet, wstride, traces, trace_nt, (S->cur + q) & 1, cs);
       hipError_t e = hipStreamEndCapture(cs, &S->graph);
       if (e != hipSuccess) {
         (void)hipStreamDestroy(cs);
@@ -774,9 +960,8 @@ ib_status run_steps(ib_state *S, int64_t nsteps, const void *wavelet, int64_t ws
     for (; done + 2 <= nsteps; done += 2) IB_HIP(hipGraphLaunch(S->gexec, st));
   }
   for (; done < nsteps; ++done) {
-    StepArgs a = make_args(S, wavelet, wstride, traces, trace_nt, S->cur);
-    enqueue_step(a, st);
-    S->cur ^= 1;
+    enqueue_full_step(S, wavelet, wstride, traces, trace_nt, S->cur, st);
+    if (S->form == IB_FORM_P2) S->cur ^= 1;
   }
   IB_HIP(hipGetLastError());
   S->t += nsteps;
@@ -917,7 +1102,8 @@ ib_status ib_step(ib_state *S, int32_t nsteps, const void *wavelet, int64_t wstr
 
 ib_status ib_forward(ib_state *S, int32_t nt, const void *wavelet, int64_t wstride, void *traces, int32_t ckpt_every,
                      void *stream) {
-  if (!S || nt < 1 || !wavelet || ckpt_every < 1 || wstride < nt || (S->nrec > 0 && !traces)) {
+  if (!S || nt < 1 || !wavelet || ckpt_every < 1 || wstride < nt || (S->nrec > 0 && !traces) ||
+      S->form != IB_FORM_P2) {
     set_error("ib_forward: invalid argument");
     return IB_ERR_ARG;
   }
@@ -950,8 +1136,8 @@ ib_status ib_forward(ib_state *S, int32_t nt, const void *wavelet, int64_t wstri
 
 ib_status ib_adjoint(ib_state *S, const void *residual, const void *wavelet, int64_t wstride, double *grad,
                      void *stream) {
-  if (!S || !residual || !wavelet || !grad) {
-    set_error("ib_adjoint: null argument");
+  if (!S || !residual || !wavelet || !grad || S->form != IB_FORM_P2) {
+    set_error("ib_adjoint: null argument or first-order state");
     return IB_ERR_ARG;
   }
   if (S->ck_count == 0) {
@@ -1053,7 +1239,7 @@ ib_status ib_adjoint(ib_state *S, const void *residual, const void *wavelet, int
 }
 
 ib_status ib_state_run_kernel(ib_state *S, int32_t which, int32_t count, void *stream) {
-  if (!S || which < 0 || which > 1 || count < 0) {
+  if (!S || which < 0 || which > 1 || count < 0 || S->form != IB_FORM_P2) {
     set_error("ib_state_run_kernel: invalid argument");
     return IB_ERR_ARG;
   }
@@ -1072,12 +1258,19 @@ ib_status ib_state_run_kernel(ib_state *S, int32_t which, int32_t count, void *s
 }
 
 ib_status ib_state_field(ib_state *S, int32_t which, int32_t shot, void *dev, int32_t direction, void *stream) {
-  if (!S || !dev || which < 0 || which > 1 || shot < 0 || shot >= S->nshots || direction < 0 || direction > 1) {
+  const int maxw = (S && S->form == IB_FORM_PV1) ? 1 + S->nv : 1;
+  if (!S || !dev || which < 0 || which > maxw || shot < 0 || shot >= S->nshots || direction < 0 || direction > 1 ||
+      (S->form == IB_FORM_PV1 && which == 1)) {
     set_error("ib_state_field: invalid argument");
     return IB_ERR_ARG;
   }
   const ib_weights *w = S->w;
-  char *base = (char *)S->buf[which == 0 ? S->cur : 1 - S->cur] + (size_t)shot * S->vol * S->esz;
+  char *base;
+  if (S->form == IB_FORM_PV1)
+    base = (which == 0) ? (char *)S->buf[0] + (size_t)shot * S->vol * S->esz
+                        : (char *)S->vbuf + ((size_t)shot * S->nv + (which - 2)) * S->vol * S->esz;
+  else
+    base = (char *)S->buf[which == 0 ? S->cur : 1 - S->cur] + (size_t)shot * S->vol * S->esz;
   size_t rowb = w->nx * S->esz, pitchb = S->pitch * S->esz;
   size_t rows = w->ny * w->nz;
   hipStream_t st = (hipStream_t)stream;

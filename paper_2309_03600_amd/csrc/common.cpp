@@ -3,6 +3,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <utility>
 
 #include "ib_internal.h"
 
@@ -110,8 +111,31 @@ void second_derivative_weights(int M, double *w) {
   w[m] = -2.0 * s;
 }
 
+// Staggered first derivative at 0 from M nodes at offsets -(M-1)/2 .. (M-1)/2: the
+// weights make sum_k w_k x_k^j equal to the j-th derivative of x^j at 0 (1 for j = 1,
+// else 0) for j < M; solved by Gaussian elimination with partial pivoting (M <= 8).
+void staggered_first_derivative_weights(int M, double *w) {
+  double A[kMaxOrder][kMaxOrder + 1];
+  for (int j = 0; j < M; ++j) {
+    for (int k = 0; k < M; ++k) A[j][k] = std::pow(k - (M - 1) / 2.0, j);
+    A[j][M] = (j == 1) ? 1.0 : 0.0;
+  }
+  for (int c = 0; c < M; ++c) {
+    int piv = c;
+    for (int r = c + 1; r < M; ++r)
+      if (std::fabs(A[r][c]) > std::fabs(A[piv][c])) piv = r;
+    for (int k = 0; k <= M; ++k) std::swap(A[c][k], A[piv][k]);
+    for (int r = 0; r < M; ++r) {
+      if (r == c) continue;
+      const double f = A[r][c] / A[c][c];
+      for (int k = c; k <= M; ++k) A[r][k] -= f * A[c][k];
+    }
+  }
+  for (int k = 0; k < M; ++k) w[k] = A[k][M] / A[k][k];
+}
+
 // nabla^{2q} in d dimensions: sum over |g| = q of q!/g! d^{2g}.
-static void add_laplacian_power(OpSet &ops, int slot, int q, int ndim, int normal_axis) {
+void add_laplacian_power(OpSet &ops, int slot, int q, int ndim, int normal_axis) {
   auto fact = [](int n) {
     double f = 1.0;
     for (int i = 2; i <= n; ++i) f *= i;
@@ -157,6 +181,62 @@ OpSet make_ops(int surface, int Mb, int ndim) {
     }
   }
   return ops;
+}
+
+// Velocity rows of the first-order form, block ``axis`` (the v_axis component):
+//   free:  lap^q (div v) = 0 for 2q+1 <= Mb  ->  d_axis lap^q on this block;
+//   rigid: n.v = 0 (normal component on this block), then n.grad lap^(q-1) div v = 0
+//          for 2q <= Mb  ->  n.grad lap^(q-1) d_axis on this block.
+OpSet make_vops(int surface, int Mb, int ndim, int axis) {
+  OpSet ops;
+  memset(&ops, 0, sizeof(ops));
+  auto shift_slot = [&](int slot, int ax) {
+    for (int t = 0; t < ops.nterms[slot]; ++t) ops.term[slot][t].beta[ax] += 1;
+  };
+  if (surface == IB_SURF_FREE) {
+    for (int q = 0; 2 * q + 1 <= Mb; ++q) {
+      add_laplacian_power(ops, ops.nops, q, ndim, -1);
+      shift_slot(ops.nops, axis);
+      ops.nops++;
+    }
+  } else {
+    OpTerm t{};
+    t.normal_axis = (int8_t)axis;
+    t.coef = 1.0;
+    ops.term[0][0] = t;
+    ops.nterms[0] = 1;
+    ops.nops = 1;
+    for (int q = 1; 2 * q <= Mb; ++q) {
+      for (int ax = 0; ax < 3; ++ax) {
+        if (ndim == 2 && ax == 1) continue;
+        const int before = ops.nterms[ops.nops];
+        add_laplacian_power(ops, ops.nops, q - 1, ndim, ax);
+        for (int k = before; k < ops.nterms[ops.nops]; ++k) ops.term[ops.nops][k].beta[axis] += 1;
+      }
+      ops.nops++;
+    }
+  }
+  return ops;
+}
+
+// Lattice points o with |o + shift| <= r (r = code / 2) in memory order, packed like the
+// canonical balls.  shift components are multiples of 1/2.
+std::vector<int32_t> shifted_ball(int ndim, int code, const double shift[3]) {
+  std::vector<int32_t> out;
+  const double r = code / 2.0;
+  const int R = (int)std::floor(r) + 1;
+  const int ylo = (ndim == 3) ? -R : 0, yhi = (ndim == 3) ? R : 0;
+  for (int dz = -R; dz <= R; ++dz)
+    for (int dy = ylo; dy <= yhi; ++dy)
+      for (int dx = -R; dx <= R; ++dx) {
+        const double ax = dx + shift[0], ay = dy + shift[1], az = dz + shift[2];
+        if (ax * ax + ay * ay + az * az <= r * r) {
+          uint32_t v = (uint32_t)(uint8_t)(int8_t)dx | ((uint32_t)(uint8_t)(int8_t)dy << 8) |
+                       ((uint32_t)(uint8_t)(int8_t)dz << 16);
+          out.push_back((int32_t)v);
+        }
+      }
+  return out;
 }
 
 }  // namespace ib

@@ -54,12 +54,43 @@ struct OpSet {
   OpTerm term[kMaxOps][kMaxOpTerms];
 };
 OpSet make_ops(int surface, int Mb, int ndim);
+OpSet make_vops(int surface, int Mb, int ndim, int axis);
+void add_laplacian_power(OpSet &ops, int slot, int q, int ndim, int normal_axis);
+std::vector<int32_t> shifted_ball(int ndim, int code, const double shift[3]);
+void staggered_first_derivative_weights(int M, double *w);   // offsets -(M-1)/2..(M-1)/2
+
+// One family of modified staggered operators solved by the batched FP64 kernel.
+struct FamilySpec {
+  int family = 1;              // 1: d/dx_g of p at v_g nodes; 2: div v at p nodes
+  int gaxis = 0;               // family 1: derivative axis (0 x, 1 y, 2 z)
+  int nfields = 1, nblocks = 1;
+  const uint8_t *fcls[3] = {nullptr, nullptr, nullptr};   // data-field classes
+  double foff[3][3] = {{0}};   // node offset of each data field (half cells)
+  int fblock[3] = {0, 0, 0};
+  int baxis[3] = {0, 0, 0};    // family 2: velocity axis of each block
+  double x0off[3] = {0, 0, 0}; // expansion point relative to the anchor node
+  const uint8_t *xcls[3] = {nullptr, nullptr, nullptr};
+  std::vector<int64_t> anchors;   // anchor nodes (memory order)
+};
+struct FamilyPoint {
+  int k = 0, Mb = 0;
+  std::vector<int32_t> field;  // per weight: data field
+  std::vector<int32_t> off;    // per weight: packed lattice offset (dx, dy, dz)
+  std::vector<double> w;
+};
+
 
 int n_terms(int M, int ndim);
 void multi_indices(int M, int ndim, std::vector<int8_t> &out);   // [nterms][3]
 void second_derivative_weights(int M, double *w);                 // offsets -M/2..M/2
 
 }  // namespace ib
+
+struct ib_weights;
+namespace ib {
+ib_status solve_family(ib_weights *w, const FamilySpec &F, const int64_t *col_off_dev, hipStream_t st,
+                       std::vector<FamilyPoint> &out);
+}
 
 struct ib_weights {
   int device = 0;
@@ -100,6 +131,17 @@ struct ib_weights {
   int32_t *ball = nullptr;         // packed ball tables
   int32_t *ball_meta = nullptr;    // [code][2] start, count (device)
   ib::BallTables balls;
+  // first-order (pressure-velocity) form
+  int form = 0;
+  uint8_t *vcls[3] = {nullptr, nullptr, nullptr};   // classes of the v_n nodes
+  std::vector<int32_t> pv_row_fam;    // per modified row: 0..ndim-1 gradient along that axis
+                                      // (row node is a v node), ndim divergence (p node)
+  std::vector<int64_t> pv_row_node;   // memory-order node index of the row
+  std::vector<int64_t> pv_row_start;  // [nrows + 1]
+  std::vector<int32_t> pv_ent_field;  // -1 p, n: v_n
+  std::vector<int64_t> pv_ent_node;
+  std::vector<double> pv_ent_w;
+  int64_t pv_stats[4] = {0, 0, 0, 0};
   int max_code = 0;
   ib_stats stats{};
 };

@@ -1,0 +1,353 @@
+// First-order (pressure-velocity) form on a staggered grid with its immersed boundary.
+//
+// Paper: "Extension to Multiple Fields and the 1st-Order Acoustic Wave Equation" and
+// "The Particle Velocity Free-Surface".  p sits on the nodes, v_n at node + e_n / 2.
+// Two families of modified operators:
+//   gradient  d/dx_n p at v_n nodes whose staggered stencil reaches an exterior p node:
+//             p is extrapolated about the v_n node (pressure hierarchy, eta_p);
+//   divergence  div v at p nodes whose stencils reach exterior v nodes: all components
+//             are extrapolated jointly about the p node, the divergence hierarchy rows
+//             spanning every component block (eta_v, zero in the paper).
+// The same boundary points (those of the p nodes) serve every field.
+// Time stepping (signs as printed, rho = 1):
+//   v^{n+1/2} = [(1 - s) v^{n-1/2} + (dt/h) D+ p^n] / (1 + s)
+//   p^{n+1}   = [(1 - s) p^n + (dt c^2/h) D- . v^{n+1/2} + dt f^n] / (1 + s)
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <vector>
+
+#include "ib_internal.h"
+#include "step.h"
+#include "surface.h"
+
+namespace ib {
+
+// bit0 of the v_axis node classes: the node (position node + e_axis / 2) lies strictly on
+// the physical side of the surface.
+__global__ void k_classify_v(SurfView sv, uint8_t *cls, int nx, int ny, int nz, int axis, double sgn) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int64_t N = (int64_t)nx * ny * nz;
+  if (i >= N) return;
+  const int x = (int)(i % nx);
+  const int64_t r = i / nx;
+  const int y = (int)(r % ny), z = (int)(r / ny);
+  double H;
+  double zz = z;
+  if (axis == 2) {
+    H = sv.Hs[(size_t)y * nx + x];
+    zz = z + 0.5;
+  } else {
+    double g[2], hh[3];
+    surf_eval(sv, x + (axis == 0 ? 0.5 : 0.0), y + (axis == 1 ? 0.5 : 0.0), H, g, hh);
+  }
+  cls[i] = (sgn * (zz - H) > 0.0) ? 1 : 0;
+}
+
+// bit1: exclusion of v nodes with a boundary point strictly inside their eta box
+__global__ void k_exclude_v(const double *bp, int64_t nb, int nx, int ny, int nz, int lat, int axis, double eta,
+                            uint8_t *cls) {
+  int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= nb || eta <= 0.0) return;
+  double p[3] = {bp[j * 8 + 3], bp[j * 8 + 4], bp[j * 8 + 5]};
+  p[axis] -= 0.5;   // position relative to the v node grid
+  int lo[3], hi[3];
+  for (int n = 0; n < 3; ++n) {
+    lo[n] = (int)floor(p[n] - eta) + 1;
+    hi[n] = (int)ceil(p[n] + eta) - 1;
+  }
+  if (lat == 1) lo[1] = hi[1] = 0;
+  for (int gz = lo[2]; gz <= hi[2]; ++gz) {
+    if (gz < 0 || gz >= nz || !(fabs(p[2] - gz) < eta)) continue;
+    for (int gy = lo[1]; gy <= hi[1]; ++gy) {
+      if (lat == 2 && !(fabs(p[1] - gy) < eta)) continue;
+      for (int gx = lo[0]; gx <= hi[0]; ++gx) {
+        if (!(fabs(p[0] - gx) < eta)) continue;
+        int64_t node = ((int64_t)gz * ny + wrapi(gy, ny)) * nx + wrapi(gx, nx);
+        if (cls[node] & 1) cls[node] |= 2;
+      }
+    }
+  }
+}
+
+// family flags: gradient (rows: v_axis nodes, reads p at +(m - 1/2), m = -H+1..H) or
+// divergence (rows: p nodes, reads v_n at +(m + 1/2), m = -H..H-1, any n)
+__global__ void k_flags_pv(const uint8_t *rowcls, const uint8_t *c0, const uint8_t *c1, const uint8_t *c2, int nx,
+                           int ny, int nz, int half, int family, int axis, uint8_t *flag) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int64_t N = (int64_t)nx * ny * nz;
+  if (i >= N) return;
+  flag[i] = 0;
+  if (!(rowcls[i] & 1)) return;
+  const int x = (int)(i % nx);
+  const int64_t r = i / nx;
+  const int y = (int)(r % ny), z = (int)(r / ny);
+  auto ext = [&](const uint8_t *c, int n, int m) {
+    int xx = x, yy = y, zz = z;
+    if (n == 0) xx = wrapi(x + m, nx);
+    if (n == 1) yy = wrapi(y + m, ny);
+    if (n == 2) zz = z + m;
+    if (zz < 0 || zz >= nz) return false;
+    return !(c[((int64_t)zz * ny + yy) * nx + xx] & 1);
+  };
+  bool hit = false;
+  if (family == 1) {
+    for (int m = -half + 1; m <= half && !hit; ++m) hit = ext(c0, axis, m);
+  } else {
+    const uint8_t *cs[3] = {c0, c1, c2};
+    for (int n = 0; n < 3 && !hit; ++n) {
+      if (!cs[n]) continue;
+      for (int m = -half; m <= half - 1 && !hit; ++m) hit = ext(cs[n], n, m);
+    }
+  }
+  flag[i] = hit ? 1 : 0;
+}
+
+static std::vector<int64_t> compact(const uint8_t *flag_dev, int64_t N, hipStream_t st, ib_status &s) {
+  std::vector<uint8_t> h(N);
+  std::vector<int64_t> out;
+  hipError_t e = hipMemcpyAsync(h.data(), flag_dev, N, hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e != hipSuccess) {
+    s = hip_fail(e, "flag copy", __FILE__, __LINE__);
+    return out;
+  }
+  for (int64_t i = 0; i < N; ++i)
+    if (h[i]) out.push_back(i);
+  s = IB_OK;
+  return out;
+}
+
+// the velocity axes of a grid: (x, z) in 2D, (x, y, z) in 3D
+static int vaxis(int ndim, int n) { return (ndim == 2 && n == 1) ? 2 : n; }
+
+ib_status pv_build(ib_weights *w, const int64_t *col_off_dev, hipStream_t st) {
+  const int ndim = w->ndim, lat = ndim - 1, nv = ndim;
+  const int T = 256;
+  const int half = w->M / 2;
+  ib_status s;
+  SurfView sv{w->Hs, (int)w->nx, (int)w->ny, lat};
+  for (int n = 0; n < nv; ++n) {
+    if ((s = dalloc_t(&w->vcls[n], w->N))) return s;
+    hipLaunchKernelGGL(k_classify_v, dim3((unsigned)((w->N + T - 1) / T)), dim3(T), 0, st, sv, w->vcls[n], (int)w->nx,
+                       (int)w->ny, (int)w->nz, vaxis(ndim, n), w->prm.physical_below ? 1.0 : -1.0);
+    if (w->nb > 0 && w->prm.eta_v > 0.0)
+      hipLaunchKernelGGL(k_exclude_v, dim3((unsigned)((w->nb + T - 1) / T)), dim3(T), 0, st, w->bp, w->nb, (int)w->nx,
+                         (int)w->ny, (int)w->nz, lat, vaxis(ndim, n), w->prm.eta_v, w->vcls[n]);
+  }
+  IB_HIP(hipGetLastError());
+  uint8_t *flag = nullptr;
+  if ((s = dalloc_t(&flag, w->N))) return s;
+  w->pv_row_fam.clear();
+  w->pv_row_node.clear();
+  w->pv_row_start.assign(1, 0);
+  w->pv_ent_field.clear();
+  w->pv_ent_node.clear();
+  w->pv_ent_w.clear();
+  auto emit = [&](int fam, const FamilySpec &F, const std::vector<FamilyPoint> &res) {
+    for (size_t i = 0; i < res.size(); ++i) {
+      const int64_t g = F.anchors[i];
+      const int64_t x = g % w->nx, y = (g / w->nx) % w->ny, z = g / (w->nx * w->ny);
+      w->pv_row_fam.push_back(fam);
+      w->pv_row_node.push_back(g);
+      for (size_t k = 0; k < res[i].w.size(); ++k) {
+        const uint32_t v = (uint32_t)res[i].off[k];
+        const int dx = (int8_t)(v & 255), dy = (int8_t)((v >> 8) & 255), dz = (int8_t)((v >> 16) & 255);
+        const int64_t xx = ((x + dx) % w->nx + w->nx) % w->nx, yy = ((y + dy) % w->ny + w->ny) % w->ny;
+        w->pv_ent_field.push_back(fam < nv ? -1 : res[i].field[k]);
+        w->pv_ent_node.push_back((z + dz) * w->nx * w->ny + yy * w->nx + xx);
+        w->pv_ent_w.push_back(res[i].w[k]);
+      }
+      w->pv_row_start.push_back((int64_t)w->pv_ent_w.size());
+      w->stats.radius_hist[std::min(res[i].k, 7)]++;
+      w->stats.order_hist[std::min(res[i].Mb, 16)]++;
+    }
+  };
+  // gradient family, one per velocity component
+  for (int n = 0; n < nv; ++n) {
+    const int ax = vaxis(ndim, n);
+    hipLaunchKernelGGL(k_flags_pv, dim3((unsigned)((w->N + T - 1) / T)), dim3(T), 0, st, w->vcls[n], w->node_class,
+                       (const uint8_t *)nullptr, (const uint8_t *)nullptr, (int)w->nx, (int)w->ny, (int)w->nz, half, 1,
+                       ax, flag);
+    FamilySpec F;
+    F.family = 1;
+    F.gaxis = ax;
+    F.nfields = 1;
+    F.nblocks = 1;
+    F.fcls[0] = w->node_class;
+    F.x0off[ax] = 0.5;
+    F.xcls[0] = w->node_class;
+    F.anchors = compact(flag, w->N, st, s);
+    if (s) return s;
+    std::vector<FamilyPoint> res;
+    if ((s = solve_family(w, F, col_off_dev, st, res))) return s;
+    w->pv_stats[n] = (int64_t)res.size();
+    emit(n, F, res);
+  }
+  // divergence family
+  {
+    const uint8_t *vc[3] = {nullptr, nullptr, nullptr};
+    for (int n = 0; n < nv; ++n) vc[vaxis(ndim, n)] = w->vcls[n];
+    hipLaunchKernelGGL(k_flags_pv, dim3((unsigned)((w->N + T - 1) / T)), dim3(T), 0, st, w->node_class, vc[0], vc[1],
+                       vc[2], (int)w->nx, (int)w->ny, (int)w->nz, half, 2, 0, flag);
+    FamilySpec F;
+    F.family = 2;
+    F.nfields = nv;
+    F.nblocks = nv;
+    for (int n = 0; n < nv; ++n) {
+      const int ax = vaxis(ndim, n);
+      F.fcls[n] = w->vcls[n];
+      F.foff[n][ax] = 0.5;
+      F.fblock[n] = n;
+      F.baxis[n] = ax;
+      F.xcls[n] = w->vcls[n];
+    }
+    F.anchors = compact(flag, w->N, st, s);
+    if (s) return s;
+    std::vector<FamilyPoint> res;
+    if ((s = solve_family(w, F, col_off_dev, st, res))) return s;
+    w->pv_stats[3] = (int64_t)res.size();
+    emit(nv, F, res);
+  }
+  dfree(flag);
+  w->nib = (int64_t)w->pv_row_fam.size();
+  w->sumw = (int64_t)w->pv_ent_w.size();
+  w->stats.n_ib = w->nib;
+  w->stats.sum_nw = w->sumw;
+  return IB_OK;
+}
+
+// ---- stepping ------------------------------------------------------------------------
+template <typename T, int H>
+__global__ void k_pv_velocity(T *__restrict__ v, const T *__restrict__ p, const T *__restrict__ kv,
+                              const T *__restrict__ sx, const T *__restrict__ sy, const T *__restrict__ sz,
+                              StaggerW<T> W, int nx, int ny, int nz, int64_t pitch, int64_t vol, int nv, int ndim,
+                              int nshots) {
+  const int64_t per = (int64_t)nx * ny * nz;
+  int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= per * nv * nshots) return;
+  const int shot = (int)(g / (per * nv));
+  int64_t rem = g % (per * nv);
+  const int n = (int)(rem / per);
+  int64_t i = rem % per;
+  const int x = (int)(i % nx);
+  i /= nx;
+  const int y = (int)(i % ny), z = (int)(i / ny);
+  const int ax = (ndim == 2 && n == 1) ? 2 : n;
+  const int64_t plane = pitch * ny;
+  const size_t c = (size_t)z * plane + (size_t)y * pitch + x;
+  const T *pp = p + (size_t)shot * vol;
+  T d = T(0);
+#pragma unroll
+  for (int m = -H + 1; m <= H; ++m) {
+    int xx = x, yy = y, zz = z;
+    if (ax == 0) xx = wrapi(x + m, nx);
+    if (ax == 1) yy = wrapi(y + m, ny);
+    if (ax == 2) zz = z + m;
+    if (zz < 0 || zz >= nz) continue;
+    d += W.w[m + H - 1] * pp[(size_t)zz * plane + (size_t)yy * pitch + xx];
+  }
+  const T s = sx[x] + sy[y] + sz[z];
+  T *vv = v + ((size_t)shot * nv + n) * vol;
+  vv[c] = ((T(1) - s) * vv[c] + kv[(size_t)n * vol + c] * d) / (T(1) + s);
+}
+
+template <typename T, int H>
+__global__ void k_pv_pressure(T *__restrict__ p, const T *__restrict__ v, const T *__restrict__ kp,
+                              const T *__restrict__ sx, const T *__restrict__ sy, const T *__restrict__ sz,
+                              StaggerW<T> W, int nx, int ny, int nz, int64_t pitch, int64_t vol, int nv, int ndim,
+                              int nshots) {
+  const int64_t per = (int64_t)nx * ny * nz;
+  int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= per * nshots) return;
+  const int shot = (int)(g / per);
+  int64_t i = g % per;
+  const int x = (int)(i % nx);
+  i /= nx;
+  const int y = (int)(i % ny), z = (int)(i / ny);
+  const int64_t plane = pitch * ny;
+  const size_t c = (size_t)z * plane + (size_t)y * pitch + x;
+  T div = T(0);
+  for (int n = 0; n < nv; ++n) {
+    const int ax = (ndim == 2 && n == 1) ? 2 : n;
+    const T *vv = v + ((size_t)shot * nv + n) * vol;
+#pragma unroll
+    for (int m = -H; m <= H - 1; ++m) {
+      int xx = x, yy = y, zz = z;
+      if (ax == 0) xx = wrapi(x + m, nx);
+      if (ax == 1) yy = wrapi(y + m, ny);
+      if (ax == 2) zz = z + m;
+      if (zz < 0 || zz >= nz) continue;
+      div += W.w[m + H] * vv[(size_t)zz * plane + (size_t)yy * pitch + xx];
+    }
+  }
+  const T s = sx[x] + sy[y] + sz[z];
+  T *q = p + (size_t)shot * vol;
+  q[c] = ((T(1) - s) * q[c] + kp[c] * div) / (T(1) + s);
+}
+
+// modified rows: dst[row] += scale[row] * sum_k w_k src[k]
+template <typename T>
+__global__ void k_pv_rows(T *__restrict__ dst, int64_t dst_shot_stride, const T *__restrict__ src,
+                          int64_t src_shot_stride, const int64_t *__restrict__ rnode, const T *__restrict__ rscale,
+                          const int64_t *__restrict__ rstart, const int64_t *__restrict__ enode,
+                          const T *__restrict__ ew, int64_t nrows, int nshots) {
+  int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= nrows) return;
+  const int64_t a = rstart[r], b = rstart[r + 1];
+  for (int s = 0; s < nshots; ++s) {
+    const T *ss = src + (size_t)s * src_shot_stride;
+    T acc = T(0);
+    for (int64_t k = a; k < b; ++k) acc += ew[k] * ss[enode[k]];
+    dst[(size_t)s * dst_shot_stride + rnode[r]] += rscale[r] * acc;
+  }
+}
+
+template <typename T>
+static StaggerW<T> stagger_weights(int M) {
+  double w[kMaxOrder];
+  staggered_first_derivative_weights(M, w);
+  StaggerW<T> W{};
+  for (int k = 0; k < M; ++k) W.w[k] = (T)w[k];
+  return W;
+}
+
+template <typename T, int H>
+static void pv_step_h(const PVArgs &a, hipStream_t st) {
+  const int64_t per = (int64_t)a.nx * a.ny * a.nz;
+  const StaggerW<T> W = stagger_weights<T>(a.M);
+  dim3 b(256);
+  dim3 gv((unsigned)((per * a.nv * a.nshots + 255) / 256)), gp((unsigned)((per * a.nshots + 255) / 256));
+  hipLaunchKernelGGL((k_pv_velocity<T, H>), gv, b, 0, st, (T *)a.v, (const T *)a.p, (const T *)a.kv, (const T *)a.sx,
+                     (const T *)a.sy, (const T *)a.sz, W, a.nx, a.ny, a.nz, a.pitch, a.vol, a.nv, a.ndim, a.nshots);
+  if (a.nrows_g > 0)
+    hipLaunchKernelGGL(k_pv_rows<T>, dim3((unsigned)((a.nrows_g + 255) / 256)), b, 0, st, (T *)a.v,
+                       (int64_t)a.nv * a.vol, (const T *)a.p, a.vol, a.g_node, (const T *)a.g_scale, a.g_start,
+                       a.g_enode, (const T *)a.g_w, a.nrows_g, a.nshots);
+  hipLaunchKernelGGL((k_pv_pressure<T, H>), gp, b, 0, st, (T *)a.p, (const T *)a.v, (const T *)a.kp, (const T *)a.sx,
+                     (const T *)a.sy, (const T *)a.sz, W, a.nx, a.ny, a.nz, a.pitch, a.vol, a.nv, a.ndim, a.nshots);
+  if (a.nrows_d > 0)
+    hipLaunchKernelGGL(k_pv_rows<T>, dim3((unsigned)((a.nrows_d + 255) / 256)), b, 0, st, (T *)a.p, a.vol,
+                       (const T *)a.v, (int64_t)a.nv * a.vol, a.d_node, (const T *)a.d_scale, a.d_start, a.d_enode,
+                       (const T *)a.d_w, a.nrows_d, a.nshots);
+}
+
+template <typename T>
+static void pv_step_t(const PVArgs &a, hipStream_t st) {
+  switch (a.M / 2) {
+    case 1: pv_step_h<T, 1>(a, st); break;
+    case 2: pv_step_h<T, 2>(a, st); break;
+    case 3: pv_step_h<T, 3>(a, st); break;
+    default: pv_step_h<T, 4>(a, st); break;
+  }
+}
+
+void enqueue_pv_step(const PVArgs &a, hipStream_t st) {
+  if (a.prec == IB_F32)
+    pv_step_t<float>(a, st);
+  else
+    pv_step_t<double>(a, st);
+}
+
+}  // namespace ib

@@ -50,6 +50,28 @@ struct StepArgs {
 };
 
 void enqueue_step(const StepArgs &a, hipStream_t st);
+// source injection into u and receiver sampling of u (the sources/receivers fields of a)
+void enqueue_source_receivers(const StepArgs &a, void *u, hipStream_t st);
+
+template <typename T>
+struct StaggerW {
+  T w[kMaxOrder];   // staggered first-derivative weights, offsets -(M-1)/2 .. (M-1)/2
+};
+
+// One step of the first-order form (velocity then pressure, with their modified rows).
+struct PVArgs {
+  int prec, ndim, M, nv;
+  int nx, ny, nz;
+  int64_t pitch, vol;
+  int nshots;
+  void *p, *v;                 // p [shot][vol], v [shot][nv][vol]
+  const void *kp, *kv;         // dt c^2 / h at interior p nodes; dt / h at interior v nodes [nv][vol]
+  const void *sx, *sy, *sz;
+  int64_t nrows_g, nrows_d;    // gradient rows (into v), divergence rows (into p)
+  const int64_t *g_node, *g_start, *g_enode, *d_node, *d_start, *d_enode;
+  const void *g_scale, *g_w, *d_scale, *d_w;
+};
+void enqueue_pv_step(const PVArgs &a, hipStream_t st);
 void enqueue_interior_only(const StepArgs &a, hipStream_t st);
 void enqueue_patch_only(const StepArgs &a, hipStream_t st);
 size_t pinfo_bytes(int prec);

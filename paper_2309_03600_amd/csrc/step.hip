@@ -701,16 +701,28 @@ static void launch_patch(const StepArgs &a, hipStream_t st) {
 }
 
 template <typename T>
-static void launch_step(const StepArgs &a, hipStream_t st) {
-  launch_interior<T>(a, st);
-  launch_patch<T>(a, st);
-  hipLaunchKernelGGL(k_inject<T>, dim3(1), dim3(256), 0, st, (T *)a.um, a.sidx, (const T *)a.sw, a.nshots, a.vol,
+static void launch_io(const StepArgs &a, T *u, hipStream_t st) {
+  hipLaunchKernelGGL(k_inject<T>, dim3(1), dim3(256), 0, st, u, a.sidx, (const T *)a.sw, a.nshots, a.vol,
                      (const T *)a.wavelet, a.wstride, a.tcount);
   if (a.nrec > 0 && a.traces) {
     int64_t tot = (int64_t)a.nrec * a.nshots;
-    hipLaunchKernelGGL(k_sample<T>, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, (const T *)a.um, a.ridx,
+    hipLaunchKernelGGL(k_sample<T>, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, (const T *)u, a.ridx,
                        (const T *)a.rw, a.nrec, a.nshots, a.vol, (T *)a.traces, a.nsteps, (const int64_t *)a.tcount);
   }
+}
+
+template <typename T>
+static void launch_step(const StepArgs &a, hipStream_t st) {
+  launch_interior<T>(a, st);
+  launch_patch<T>(a, st);
+  launch_io<T>(a, (T *)a.um, st);
+}
+
+void enqueue_source_receivers(const StepArgs &a, void *u, hipStream_t st) {
+  if (a.prec == IB_F32)
+    launch_io<float>(a, (float *)u, st);
+  else
+    launch_io<double>(a, (double *)u, st);
 }
 
 void enqueue_step(const StepArgs &a, hipStream_t st) {

@@ -25,6 +25,7 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstring>
 
 #include "ib_internal.h"
 
@@ -933,6 +934,189 @@ ib_status weights_build(ib_weights *w, const int64_t *col_off_dev, hipStream_t s
     w->dense_first = d_first;
     w->dense_count = d_count;
     w->dense_off = d_doff;
+  }
+  return IB_OK;
+}
+
+// Batched solves of one family of staggered operators (first-order form): the same
+// kernel as the pressure form, with the family's data fields, half-cell supports,
+// expansion point and coupled unknown blocks; results come back to the host.
+ib_status solve_family(ib_weights *w, const FamilySpec &F, const int64_t *col_off_dev, hipStream_t st,
+                       std::vector<FamilyPoint> &out) {
+  const int ndim = w->ndim, lat = ndim - 1, M = w->M;
+  const int Kmax = w->prm.max_radius_steps, min_order = w->prm.min_basis_order;
+  const int64_t np = (int64_t)F.anchors.size();
+  out.assign(np, FamilyPoint());
+  if (np == 0) return IB_OK;
+  ib_status s;
+  int64_t *d_anchor = nullptr;
+  int32_t *d_pending = nullptr, *d_status = nullptr, *d_ndata = nullptr;
+  double *d_sigma = nullptr;
+  if ((s = dalloc_t(&d_anchor, np)) || (s = dalloc_t(&d_pending, np)) || (s = dalloc_t(&d_status, np)) ||
+      (s = dalloc_t(&d_ndata, np)) || (s = dalloc_t(&d_sigma, np)))
+    return s;
+  IB_HIP(hipMemcpy(d_anchor, F.anchors.data(), np * 8, hipMemcpyHostToDevice));
+  std::vector<int32_t> pending(np);
+  for (int64_t i = 0; i < np; ++i) pending[i] = (int32_t)i;
+  std::vector<int8_t> ex;
+  multi_indices(M, ndim, ex);
+  SolveConst sc;
+  std::memset(&sc, 0, sizeof(sc));
+  for (size_t t = 0; t < ex.size() / 3; ++t)
+    for (int q = 0; q < 3; ++q) sc.exps[t][q] = ex[t * 3 + q];
+  second_derivative_weights(M, sc.w2);
+  staggered_first_derivative_weights(M, sc.ws);
+  const int chunk = (ndim == 3) ? 32 : 48;
+  const int max_slots = 32768;
+  for (int Mb = M; Mb >= min_order && !pending.empty(); --Mb) {
+    const int NT = n_terms(Mb, ndim), NTT = NT * F.nblocks;
+    if (NTT > 192) {
+      set_error("staggered velocity system of %d unknowns exceeds the solver's 192", NTT);
+      return IB_ERR_ARG;
+    }
+    for (int b = 0; b < F.nblocks; ++b)
+      sc.ops[b] = (F.family == 1) ? make_ops(w->prm.surface, Mb, ndim) : make_vops(w->prm.surface, Mb, ndim, F.baxis[b]);
+    IB_HIP(hipMemcpyToSymbolAsync(HIP_SYMBOL(c_solve), &sc, sizeof(sc), 0, hipMemcpyHostToDevice, st));
+    for (int k = 0; k <= Kmax && !pending.empty(); ++k) {
+      const int code = Mb + 1 + 2 * k;
+      const double r = code / 2.0;
+      // shifted lattice balls of the data fields
+      std::vector<int32_t> tab;
+      int fstart[3] = {0, 0, 0}, fnb[3] = {0, 0, 0}, fnw[3] = {0, 0, 0}, fwo[3] = {0, 0, 0};
+      int nball = 0, nwords = 0;
+      double shift[3][3];
+      for (int f = 0; f < F.nfields; ++f) {
+        for (int q = 0; q < 3; ++q) shift[f][q] = F.foff[f][q] - F.x0off[q];
+        std::vector<int32_t> b = shifted_ball(ndim, code, shift[f]);
+        fstart[f] = (int)tab.size();
+        fnb[f] = (int)b.size();
+        fnw[f] = (fnb[f] + 31) / 32;
+        fwo[f] = nwords;
+        nball += fnb[f];
+        nwords += fnw[f];
+        tab.insert(tab.end(), b.begin(), b.end());
+      }
+      int32_t *d_tab = nullptr, *desc = nullptr;
+      double *bprel = nullptr, *wout = nullptr;
+      uint32_t *mout = nullptr;
+      const int npend = (int)pending.size();
+      const int slots = std::min(npend, max_slots);
+      BallTables bt;
+      bt.build(ndim, code + 2);
+      const int maxbp = bt.count[code + 2] + 8;
+      if ((s = dalloc_t(&d_tab, tab.size())) || (s = dalloc_t(&desc, (size_t)slots * nball)) ||
+          (s = dalloc_t(&bprel, (size_t)slots * maxbp * 6)) || (s = dalloc_t(&wout, (size_t)npend * nball)) ||
+          (s = dalloc_t(&mout, (size_t)npend * nwords)))
+        return s;
+      IB_HIP(hipMemcpy(d_tab, tab.data(), tab.size() * 4, hipMemcpyHostToDevice));
+      IB_HIP(hipMemcpyAsync(d_pending, pending.data(), npend * 4, hipMemcpyHostToDevice, st));
+      SolveArgs A{};
+      A.family = F.family;
+      A.gaxis = F.gaxis;
+      A.nfields = F.nfields;
+      A.nblocks = F.nblocks;
+      for (int f = 0; f < 3; ++f) {
+        A.fcls[f] = F.fcls[f];
+        A.fball[f] = d_tab + fstart[f];
+        A.fnball[f] = fnb[f];
+        A.fnwords[f] = fnw[f];
+        A.fwoff[f] = fwo[f];
+        for (int q = 0; q < 3; ++q) A.fshift[f][q] = (f < F.nfields) ? shift[f][q] : 0.0;
+        A.fblock[f] = F.fblock[f];
+        A.baxis[f] = F.baxis[f];
+        A.xcls[f] = F.xcls[f];
+        A.x0off[f] = F.x0off[f];
+      }
+      A.cls = w->node_class;
+      A.bp = w->bp;
+      A.bpn = w->bp_normal;
+      A.col_off = col_off_dev;
+      A.ib_node = d_anchor;
+      A.nx = (int)w->nx;
+      A.ny = (int)w->ny;
+      A.nz = (int)w->nz;
+      A.lat = lat;
+      A.NT = NT;
+      A.Mb = Mb;
+      A.M = M;
+      A.nops = sc.ops[0].nops;
+      A.nball = nball;
+      A.nwords = nwords;
+      A.r2 = r * r;
+      A.Rc = (int)floor(r + 1.0);
+      A.rtol = w->prm.rank_rtol;
+      A.chunk = chunk;
+      A.desc = desc;
+      A.desc_stride = nball;
+      A.bprel = bprel;
+      A.maxbp = maxbp;
+      A.wout = wout;
+      A.mout = mout;
+      A.status = d_status;
+      A.ndata = d_ndata;
+      A.sigma = d_sigma;
+      const int D1 = Mb + 1;
+      size_t lds = sizeof(double) * ((size_t)NTT * (NTT + 1) / 2 + (size_t)chunk * 3 * D1 + (size_t)chunk * 3 +
+                                     2 * (size_t)chunk + 4 + NTT + 16) +
+                   16 * sizeof(int);
+      const void *kfn = (chunk == 32) ? (const void *)k_solve<32> : (const void *)k_solve<48>;
+      IB_HIP(hipFuncSetAttribute(kfn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+      for (int b0 = 0; b0 < npend; b0 += slots) {
+        A.pending = d_pending + b0;
+        A.npend = std::min(slots, npend - b0);
+        A.out_base = b0;
+        if (chunk == 32)
+          hipLaunchKernelGGL(k_solve<32>, dim3(A.npend), dim3(256), lds, st, A);
+        else
+          hipLaunchKernelGGL(k_solve<48>, dim3(A.npend), dim3(256), lds, st, A);
+        IB_HIP(hipGetLastError());
+      }
+      std::vector<int32_t> hs(npend), hn(npend);
+      std::vector<double> hw((size_t)npend * nball);
+      std::vector<uint32_t> hm((size_t)npend * nwords);
+      IB_HIP(hipMemcpyAsync(hs.data(), d_status, npend * 4, hipMemcpyDeviceToHost, st));
+      IB_HIP(hipMemcpyAsync(hn.data(), d_ndata, npend * 4, hipMemcpyDeviceToHost, st));
+      IB_HIP(hipMemcpyAsync(hw.data(), wout, hw.size() * 8, hipMemcpyDeviceToHost, st));
+      IB_HIP(hipMemcpyAsync(hm.data(), mout, hm.size() * 4, hipMemcpyDeviceToHost, st));
+      IB_HIP(hipStreamSynchronize(st));
+      std::vector<int32_t> next;
+      for (int p = 0; p < npend; ++p) {
+        const int id = pending[p];
+        if (hs[p] < 0) {
+          set_error("staggered family %d point %d: support scratch overflow (radius %.1f)", F.family, id, r);
+          return IB_ERR_ARG;
+        }
+        if (hs[p] != 1) {
+          next.push_back(id);
+          continue;
+        }
+        FamilyPoint &fp = out[id];
+        fp.k = k;
+        fp.Mb = Mb;
+        int kk = 0;
+        for (int f = 0; f < F.nfields; ++f) {
+          const uint32_t *m = hm.data() + (size_t)p * nwords + fwo[f];
+          for (int b = 0; b < fnb[f]; ++b) {
+            if (!((m[b >> 5] >> (b & 31)) & 1u)) continue;
+            fp.field.push_back(f);
+            fp.off.push_back(tab[fstart[f] + b]);
+            fp.w.push_back(hw[(size_t)p * nball + kk]);
+            ++kk;
+          }
+        }
+        if (kk != hn[p]) {
+          set_error("staggered family %d point %d: mask/weight count mismatch", F.family, id);
+          return IB_ERR_HIP;
+        }
+      }
+      dfree(d_tab), dfree(desc), dfree(bprel), dfree(wout), dfree(mout);
+      pending.swap(next);
+    }
+  }
+  dfree(d_anchor), dfree(d_pending), dfree(d_status), dfree(d_ndata), dfree(d_sigma);
+  if (!pending.empty()) {
+    set_error("%zu staggered-family points remain rank deficient (family %d)", pending.size(), F.family);
+    return IB_ERR_UNCONSTRAINED;
   }
   return IB_OK;
 }

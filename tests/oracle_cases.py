@@ -2,7 +2,7 @@
 import numpy as np
 
 from oracle import stepper
-from oracle.parallel import solve_points  # noqa: F401
+from oracle.parallel import solve_points, solve_staggered  # noqa: F401
 from oracle.weights import IBModel
 
 def model_for(wl, **kw):
