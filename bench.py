@@ -12,6 +12,9 @@ Roofline: HIP events (torch.cuda.Event on the stream the library launches on) ti
 each kernel over its own launches; algorithmic bytes per launch are
   interior: 16 B per grid node (FP32; read p^n, p^{n-1}, K; write p^{n+1}), 32 B FP64;
   IB patch: 4 B per weight + 13 B per IB point (FP32), 8 B per weight + 21 B (FP64).
+HBM traffic per launch comes from rocprofv3 FETCH_SIZE / WRITE_SIZE runs of this script
+(``--calibrate`` adds a 1 GiB device copy whose counters give the scale factors), turned
+into profiles/traffic.json by ``--summarize-counters FETCH_DIR WRITE_DIR``.
 """
 from __future__ import annotations
 
@@ -34,6 +37,18 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+KERNELS = {"interior": "k_interior3d_p", "patch": "k_patch_tiled_r"}
+TRAFFIC_FILE = "hbm_traffic_interior_patch_config3.json"
+PROFILE_CMDS = [
+    "rocprofv3 --pmc FETCH_SIZE --output-format csv -d gpurun_out/prof_f -o f -- "
+    "python3 bench.py --steps 20 --warmup 5 --no-cpu --calibrate",
+    "rocprofv3 --pmc WRITE_SIZE --output-format csv -d gpurun_out/prof_w -o w -- "
+    "python3 bench.py --steps 20 --warmup 5 --no-cpu --calibrate",
+    "python3 bench.py --summarize-counters gpurun_out/prof_f gpurun_out/prof_w",
+]
+CALIB_BYTES = 1 << 30
+
+
 def kernel_source_hash():
     h = hashlib.sha256()
     for f in ("step.hip", "step.h"):
@@ -44,7 +59,7 @@ def kernel_source_hash():
 def load_traffic():
     """HBM bytes per launch measured with rocprofv3 counters (profiles/traffic.json),
     valid only for the kernel source they were taken on."""
-    p = os.path.join(ROOT, "profiles", "traffic.json")
+    p = os.path.join(ROOT, "profiles", TRAFFIC_FILE)
     if not os.path.exists(p):
         return {}
     d = json.load(open(p))
@@ -65,7 +80,61 @@ def time_kernel(st, which, count, torch):
     return e0.elapsed_time(e1) / count           # ms per launch
 
 
-def cpu_baseline(budget_steps=200):
+def summarize_counters(fetch_dir, write_dir):
+    """profiles/traffic.json from two rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE, KiB per
+    dispatch) of ``bench.py --calibrate``: each kernel's mean per dispatch, scaled by what
+    the same counter reads for the 1 GiB calibration copy."""
+    import csv
+    import glob
+
+    def per_kernel(d, counter):
+        rows = []
+        for f in glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True):
+            for r in csv.DictReader(open(f)):
+                if r["Counter_Name"] == counter:
+                    rows.append((int(r["Dispatch_Id"]), r["Kernel_Name"], float(r["Counter_Value"]) * 1024.0))
+        out = {}
+        for i, k, v in sorted(rows):
+            out.setdefault(k, []).append((i, v))
+        return out
+
+    fetch, write = per_kernel(fetch_dir, "FETCH_SIZE"), per_kernel(write_dir, "WRITE_SIZE")
+
+    def copy_value(tab):
+        vals = [v for k, vs in tab.items() if "copy" in k.lower() or "elementwise" in k.lower() for _, v in vs]
+        vals = [v for v in vals if v > 0.25 * CALIB_BYTES]
+        return float(np.median(vals)) if vals else None
+
+    cf, cw = copy_value(fetch), copy_value(write)
+    res = {"source_hash": kernel_source_hash(), "commands": PROFILE_CMDS, "calibration": {
+        "copy_bytes_each_way": CALIB_BYTES, "fetch_reads": cf, "write_reads": cw,
+        "fetch_factor": CALIB_BYTES / cf if cf else None, "write_factor": CALIB_BYTES / cw if cw else None},
+        "kernels": {}}
+    def launches(tab, sym, tname, last):
+        # dispatches in launch order; the interior kernel's autotuning launches (other
+        # variants and depth chunks) precede the timed ones, so only the trailing ``last``
+        # dispatches (as many as the patch kernel had: one per step or timing launch) count
+        rows = sorted((i, v) for k, vs in tab.items() if sym + "<" + tname in k for i, v in vs)
+        return [v for _, v in rows[-last:]] if last else [v for _, v in rows]
+
+    for short, sym in KERNELS.items():
+        for prec, tname in (("f32", "float"), ("f64", "double")):
+            npatch = len([v for k, vs in fetch.items() if KERNELS["patch"] + "<" + tname in k for v in vs])
+            fk = launches(fetch, sym, tname, npatch)
+            wk = launches(write, sym, tname, npatch)
+            if not fk or not wk or not cf or not cw:
+                continue
+            rd = float(np.mean(fk)) * CALIB_BYTES / cf
+            wr = float(np.mean(wk)) * CALIB_BYTES / cw
+            res["kernels"][f"{sym}/{prec}"] = {"read_bytes_per_launch": rd, "write_bytes_per_launch": wr,
+                                              "bytes_per_launch": rd + wr, "dispatches": len(fk)}
+    os.makedirs(os.path.join(ROOT, "profiles"), exist_ok=True)
+    with open(os.path.join(ROOT, "profiles", TRAFFIC_FILE), "w") as f:
+        json.dump(res, f, indent=1)
+    print(json.dumps(res, indent=1))
+
+
+def cpu_baseline(budget_steps=5000):
     """The FP64 oracle on a bounded sample: a 24 x 24 x 301 grid with the same recipe
     (fractal free surface, M = 8, damping), weights from a process pool (untimed), then
     ``budget_steps`` oracle steps timed on one core."""
@@ -103,7 +172,13 @@ def main():
     ap.add_argument("--zchunk", type=int, default=-1)
     ap.add_argument("--variant", type=int, default=-1)
     ap.add_argument("--graph", type=int, default=1)
+    ap.add_argument("--patch-variant", type=int, default=-1)
+    ap.add_argument("--calibrate", action="store_true", help="add a 1 GiB device copy (counter calibration)")
+    ap.add_argument("--summarize-counters", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"))
     args = ap.parse_args()
+    if args.summarize_counters:
+        summarize_counters(*args.summarize_counters)
+        return
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU only; multi-GPU sharding is a design note, "
               "not an implemented path (use --gpus 1)", file=sys.stderr)
@@ -131,8 +206,8 @@ def main():
     for prec in (["f32"] if args.no_fp64 else ["f32", "f64"]):
         dt = torch.float32 if prec == "f32" else torch.float64
         st = ib.ib_state_create(w, wl.vel, wl.dt, wl.src, wl.rec, damp_width=wl.damp_width, precision=prec)
-        if args.zchunk >= 0 or args.variant >= 0:
-            st.set_tuning(args.variant if args.variant >= 0 else 1, max(args.zchunk, 0))
+        if args.zchunk >= 0 or args.variant >= 0 or args.patch_variant >= 0:
+            st.set_tuning(args.variant if args.variant >= 0 else 1, max(args.zchunk, 0), args.patch_variant)
         wav = torch.tensor(wl.wavelets(np.float64), dtype=dt, device="cuda")
         tr_w = torch.empty((1, Wm, st.nrec), dtype=dt, device="cuda")
         tr = torch.empty((1, K, st.nrec), dtype=dt, device="cuda")
@@ -166,13 +241,25 @@ def main():
         st.close()
         del wav, tr, tr_w
         torch.cuda.synchronize()
+    if args.calibrate:
+        a = torch.ones(CALIB_BYTES // 4, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(5):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
     r = results["f32"]
     dom = "interior" if r["interior_ms"] >= r["patch_ms"] else "patch"
     traffic = load_traffic()
-    tkey = "k_interior3d" if dom == "interior" else "k_patch"
+    tkey = KERNELS[dom]
     roof = {"bound": "hbm", "achieved": r[f"{dom}_GBs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": r[f"{dom}_GBs"] / HBM_PEAK_GBS,
-            "traffic": traffic.get(tkey, {}).get("bytes_per_launch"), "kernel": tkey}
+            "traffic": traffic.get(tkey + "/f32", {}).get("bytes_per_launch"), "kernel": tkey,
+            "algorithmic_bytes": r[f"{dom}_bytes"], "ms_per_launch": r[f"{dom}_ms"]}
+    other = "patch" if dom == "interior" else "interior"
+    roof_other = {"kernel": KERNELS[other], "achieved": r[f"{other}_GBs"], "frac": r[f"{other}_GBs"] / HBM_PEAK_GBS,
+                  "traffic": traffic.get(KERNELS[other] + "/f32", {}).get("bytes_per_launch"),
+                  "algorithmic_bytes": r[f"{other}_bytes"], "ms_per_launch": r[f"{other}_ms"]}
     acc = None
     if "f64" in traces:
         from_ = traces["f32"]
@@ -198,6 +285,7 @@ def main():
                                "40-cell damping, 1 Ricker source, 201x201 receivers",
                    "grid": list(wl.shape), "space_order": wl.M, "shots": 1, "hip_graph": bool(args.graph)},
         "roofline": roof,
+        "roofline_other_kernel": roof_other,
         "cpu_baseline": cpu,
         "kernels": results,
         "fp64": results.get("f64"),

@@ -242,12 +242,18 @@ int64_t ib_state_step_count(const ib_state *st);
  * time each kernel on its own; it changes the wavefields.  Second-order form only. */
 ib_status ib_state_run_kernel(ib_state *st, int32_t which, int32_t count, void *stream);
 
-/* Tuning knobs of the 3D eighth-order interior kernel: variant 0 (one plane per barrier
- * pair), 1 (software-pipelined, 64x16 tiles), 2 (pipelined, 64x32 tiles, 8 rows per thread),
- * 3 (pipelined, 64x32 tiles, 512 threads), and
- * depth planes per workgroup (0 = automatic: enough workgroups to fill the device).
- * Results do not depend on them. */
-ib_status ib_state_set_tuning(ib_state *st, int32_t variant, int32_t zchunk);
+/* Tuning knobs of the 3D eighth-order step kernels.
+ *   variant (interior stencil): 0 (one plane per barrier pair), 1 (software-pipelined,
+ *     64x16 tiles), 2 (pipelined, 64x32 tiles, 8 rows per thread), 3 (pipelined, 64x32
+ *     tiles, 512 threads);
+ *   zchunk: depth planes per interior workgroup (0 = automatic: enough workgroups to fill
+ *     the device);
+ *   patch_variant (tiled IB patch): 0-3 point records read per wavefront (bit 0 as scalar
+ *     loads, bit 1 DPP wavefront sums); 4-6 records staged in LDS per tile with DPP sums and
+ *     1-3 groups of two points' weights in flight (default 4); -1 keeps the current one.
+ * Results do not depend on the interior knobs; the patch variants differ only in the
+ * summation order of each point's weighted sum. */
+ib_status ib_state_set_tuning(ib_state *st, int32_t variant, int32_t zchunk, int32_t patch_variant);
 
 #ifdef __cplusplus
 }

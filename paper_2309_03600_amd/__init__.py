@@ -197,9 +197,9 @@ class IBState:
         """Enqueue ``count`` launches of one step kernel (0 interior, 1 patch) for timing."""
         _lib.check(_lib.load().ib_state_run_kernel(self._h, int(which), int(count), _stream(stream)))
 
-    def set_tuning(self, variant, zchunk):
+    def set_tuning(self, variant, zchunk, patch_variant=-1):
         """Interior-kernel variant (0, 1, 2) and depth planes per workgroup (0 = all)."""
-        _lib.check(_lib.load().ib_state_set_tuning(self._h, int(variant), int(zchunk)))
+        _lib.check(_lib.load().ib_state_set_tuning(self._h, int(variant), int(zchunk), int(patch_variant)))
 
     @property
     def step_count(self):

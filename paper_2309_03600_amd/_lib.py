@@ -51,7 +51,7 @@ EXPORTS = {
     "ib_adjoint": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p]),
     "ib_state_field": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_void_p, C.c_int32, C.c_void_p]),
     "ib_state_step_count": (C.c_int64, [C.c_void_p]),
-    "ib_state_set_tuning": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32]),
+    "ib_state_set_tuning": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_int32]),
     "ib_state_run_kernel": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_void_p]),
 }
 

@@ -20,6 +20,7 @@ struct StepArgs {
   int nshots;
   int zchunk;
   int variant;          // 3D M=8 interior kernel: 0 basic, 1 pipelined 64x16, 2 pipelined 64x32
+  int patch_variant;    // tiled IB patch: bit0 scalar records + weights fetched before staging, bit1 DPP sum
   const void *un;       // p^n
   void *um;             // p^{n-1} in, p^{n+1} out
   const void *K;

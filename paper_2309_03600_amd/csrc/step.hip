@@ -200,7 +200,8 @@ __global__ void k_interior3d_p(const T *__restrict__ un, T *__restrict__ um, con
 #pragma unroll
   for (int i = 0; i < NHY; ++i) {
     int idx = t + i * 64 * NW;
-    hyon[i] = idx < 2 * H * TX;
+    // every thread holds NHY halo values when the halo divides evenly (no predicate)
+    hyon[i] = ((2 * H * TX) % (64 * NW) == 0) || idx < 2 * H * TX;
     if (!hyon[i]) idx = 0;
     int hr = idx / TX, hc = idx % TX;
     int yg = (hr < H) ? y0 - H + hr : y0 + TY + (hr - H);
@@ -407,6 +408,39 @@ __global__ void k_patch(const T *__restrict__ un, T *__restrict__ unew, const ui
   }
 }
 
+// ---- wavefront sum without LDS traffic ------------------------------------------------
+// Four DPP row rotations leave every lane of a 16-lane row holding the row's sum; the four
+// row sums are then read as scalars.
+template <int C>
+__device__ __forceinline__ float dpp_mov(float v) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), C, 0xF, 0xF, false));
+}
+template <int C>
+__device__ __forceinline__ double dpp_mov(double v) {
+  const unsigned long long b = __builtin_bit_cast(unsigned long long, v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(b & 0xffffffffull), C, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(b >> 32), C, 0xF, 0xF, false);
+  return __builtin_bit_cast(double, ((unsigned long long)(unsigned)hi << 32) | (unsigned)lo);
+}
+__device__ __forceinline__ float read_lane(float v, int l) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), l));
+}
+__device__ __forceinline__ double read_lane(double v, int l) {
+  const unsigned long long b = __builtin_bit_cast(unsigned long long, v);
+  const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(b & 0xffffffffull), l);
+  const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(b >> 32), l);
+  return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
+}
+// full-wavefront sum (every lane active), returned in every lane
+template <typename T>
+__device__ __forceinline__ T wave_sum(T v) {
+  v += dpp_mov<0x128>(v);   // row_ror:8
+  v += dpp_mov<0x124>(v);   // row_ror:4
+  v += dpp_mov<0x122>(v);   // row_ror:2
+  v += dpp_mov<0x121>(v);   // row_ror:1
+  return (read_lane(v, 0) + read_lane(v, 16)) + (read_lane(v, 32) + read_lane(v, 48));
+}
+
 // ---- IB patch, LDS-tiled (3D) -------------------------------------------------------
 // IB points are bucketed into TX x TY x TZ tiles (host, at state creation).  A workgroup
 // stages p^n over its tile plus an HR-cell halo in LDS with coalesced row loads; its
@@ -423,7 +457,7 @@ struct alignas(16) PInfoD {
   T scale;
 };
 
-template <typename T, int TX, int TY, int TZ, int HR>
+template <typename T, int TX, int TY, int TZ, int HR, int PV>
 __launch_bounds__(512)
 __global__ void k_patch_tiled(const T *__restrict__ un, T *__restrict__ unew, const T *__restrict__ dense,
                               const PInfoD<T> *__restrict__ pinfo, const int32_t *__restrict__ ball,
@@ -441,7 +475,10 @@ __global__ void k_patch_tiled(const T *__restrict__ un, T *__restrict__ unew, co
   const int4 tl = tiles[tb];
   const int x0 = tl.x, y0 = tl.y, z0 = tl.z;
   const int p0 = tl.w, p1 = tiles[tb + 1].w;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwave = blockDim.x >> 6;
+  const int lane = threadIdx.x & 63, nwave = blockDim.x >> 6;
+  // the wavefront index is uniform: make it a scalar so that the per-point records are
+  // scalar loads and the weight addresses are scalar base + lane offset
+  const int wave = (PV & 1) ? __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6)) : (int)(threadIdx.x >> 6);
   const int64_t plane = pitch * ny;
   for (int q = 0; q < 2; ++q) {
     const int code = 8 + q, st0 = ball_meta[2 * code], nbq = ball_meta[2 * code + 1];
@@ -457,13 +494,6 @@ __global__ void k_patch_tiled(const T *__restrict__ un, T *__restrict__ unew, co
   }
   for (int s = 0; s < nshots; ++s) {
     const T *u = un + (size_t)s * vol;
-    for (int e = threadIdx.x; e < LZ * LY * LX; e += blockDim.x) {
-      const int lx = e % LX, ly = (e / LX) % LY, lz = e / (LX * LY);
-      const int gz = z0 - HR + lz;
-      const int gx = wrapk(x0 - HR + lx, nx), gy = wrapk(y0 - HR + ly, ny);
-      sp[e] = (lx < LX - 1 && gz >= 0 && gz < nz) ? u[(size_t)gz * plane + (size_t)gy * pitch + gx] : T(0);
-    }
-    __syncthreads();
     // software pipeline over this wavefront's points, two at a time: the weights of the
     // next pair and the records of the pair after it are in flight while a pair is
     // evaluated (four points' weights outstanding per wavefront)
@@ -490,6 +520,13 @@ __global__ void k_patch_tiled(const T *__restrict__ un, T *__restrict__ unew, co
       const int q = p + step2 + h * nwave;
       if (q < p1) Pn[h] = pinfo[q];
     }
+    for (int e = threadIdx.x; e < LZ * LY * LX; e += blockDim.x) {
+      const int lx = e % LX, ly = (e / LX) % LY, lz = e / (LX * LY);
+      const int gz = z0 - HR + lz;
+      const int gx = wrapk(x0 - HR + lx, nx), gy = wrapk(y0 - HR + ly, ny);
+      sp[e] = (lx < LX - 1 && gz >= 0 && gz < nz) ? u[(size_t)gz * plane + (size_t)gy * pitch + gx] : T(0);
+    }
+    __syncthreads();
     while (p < p1) {
       const int pn = p + step2;
       PInfoD<T> Pnn[2];
@@ -521,7 +558,11 @@ __global__ void k_patch_tiled(const T *__restrict__ un, T *__restrict__ unew, co
             const int e = k * 64 + lane;
             if (e < P.count) acc += wc[h][k] * sp[lc + lt[e]];
           }
-          for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
+          if (PV & 2) {
+            acc = wave_sum(acc);
+          } else {
+            for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
+          }
           if (lane == 0) res[q - p0] = P.scale * acc;
         }
       }
@@ -540,6 +581,153 @@ __global__ void k_patch_tiled(const T *__restrict__ un, T *__restrict__ unew, co
     for (int q = p0 + (int)threadIdx.x; q < p1; q += blockDim.x) {
       const PInfoD<T> P = pinfo[q];
       unew[(size_t)s * vol + (size_t)P.z * plane + (size_t)P.y * pitch + P.x] += res[q - p0];
+    }
+    __syncthreads();
+  }
+}
+
+// Same computation with the tile's point records staged in LDS (read back as scalars, so
+// no scalar memory load is outstanding while LDS results are awaited), the weights of D
+// groups of two points per wavefront in flight, DPP wavefront sums, and the scale applied
+// in the per-tile read-modify-write.
+struct TileRec {
+  uint32_t woff;      // first dense weight
+  uint32_t fc;        // first lattice index | count << 16
+  uint32_t lcc;       // LDS index of the point | radius code 9 << 31
+  uint32_t pad;
+};
+
+template <typename T, int NS>
+struct PairW {
+  T w[2][NS];
+};
+
+template <typename T, int TX, int TY, int TZ, int HR, int D>
+__launch_bounds__(512)
+__global__ void k_patch_tiled_r(const T *__restrict__ un, T *__restrict__ unew, const T *__restrict__ dense,
+                                const PInfoD<T> *__restrict__ pinfo, const int32_t *__restrict__ ball,
+                                const int32_t *__restrict__ ball_meta, const int4 *__restrict__ tiles, int ntiles,
+                                int nx, int ny, int nz, int64_t pitch, int64_t vol, int nshots) {
+  constexpr int LX = TX + 2 * HR + 1, LY = TY + 2 * HR, LZ = TZ + 2 * HR;
+  constexpr int NS = 7;
+  constexpr int BMAX = 64 * NS;
+  constexpr int NW = 8;                       // wavefronts per workgroup (512 threads)
+  constexpr int STEP = 2 * NW;                // points per wavefront group step
+  __shared__ T sp[LZ * LY * LX];
+  __shared__ int16_t lofs[2][BMAX];
+  __shared__ TileRec rec[kTileMaxPoints];
+  __shared__ T res[kTileMaxPoints];
+  const int64_t tb = xcd_remap(blockIdx.x, gridDim.x);
+  if (tb >= ntiles) return;
+  const int4 tl = tiles[tb];
+  const int x0 = tl.x, y0 = tl.y, z0 = tl.z;
+  const int p0 = tl.w, np = tiles[tb + 1].w - tl.w;
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  const int64_t plane = pitch * ny;
+  for (int q = 0; q < 2; ++q) {
+    const int code = 8 + q, st0 = ball_meta[2 * code], nbq = ball_meta[2 * code + 1];
+    for (int b = threadIdx.x; b < BMAX; b += blockDim.x) {
+      int v = 0;
+      if (b < nbq) {
+        const uint32_t e = (uint32_t)ball[st0 + b];
+        const int dx = (int8_t)(e & 255), dy = (int8_t)((e >> 8) & 255), dz = (int8_t)((e >> 16) & 255);
+        v = (dz * LY + dy) * LX + dx;
+      }
+      lofs[q][b] = (int16_t)v;
+    }
+  }
+  for (int i = threadIdx.x; i < np; i += blockDim.x) {
+    const PInfoD<T> P = pinfo[p0 + i];
+    int cx = P.x - x0;
+    if (cx < 0) cx += nx;
+    int cy = P.y - y0;
+    if (cy < 0) cy += ny;
+    const int lc = ((P.z - z0 + HR) * LY + (cy + HR)) * LX + (cx + HR);
+    TileRec r;
+    r.woff = P.woff;
+    r.fc = (uint32_t)P.first | ((uint32_t)P.count << 16);
+    r.lcc = (uint32_t)lc | (P.code == 9 ? 0x80000000u : 0u);
+    r.pad = 0;
+    rec[i] = r;
+  }
+  __syncthreads();
+  auto get = [&](int i, uint32_t &woff, uint32_t &fc, uint32_t &lcc) {
+    if (i < np) {
+      const TileRec r = rec[i];
+      woff = __builtin_amdgcn_readfirstlane(r.woff);
+      fc = __builtin_amdgcn_readfirstlane(r.fc);
+      lcc = __builtin_amdgcn_readfirstlane(r.lcc);
+    } else {
+      woff = 0, fc = 0, lcc = 0;           // count 0: nothing loaded, nothing evaluated
+    }
+  };
+  auto load = [&](PairW<T, NS> &W, const uint32_t (&wo)[2], const uint32_t (&fc)[2]) {
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int cnt = (int)(fc[h] >> 16);
+#pragma unroll
+      for (int k = 0; k < NS; ++k) {
+        const int e = k * 64 + lane;
+        W.w[h][k] = (e < cnt) ? dense[wo[h] + e] : T(0);
+      }
+    }
+  };
+  for (int s = 0; s < nshots; ++s) {
+    const T *u = un + (size_t)s * vol;
+    // records of D + 1 groups ahead, weights of D groups in flight before the staging
+    uint32_t wo[D + 1][2], fc[D + 1][2], lcc[D + 1][2];
+    PairW<T, NS> W[D + 1];
+#pragma unroll
+    for (int d = 0; d <= D; ++d)
+#pragma unroll
+      for (int h = 0; h < 2; ++h) get(wave + d * STEP + h * NW, wo[d][h], fc[d][h], lcc[d][h]);
+#pragma unroll
+    for (int d = 0; d < D; ++d) load(W[d], wo[d], fc[d]);
+    for (int e = threadIdx.x; e < LZ * LY * LX; e += blockDim.x) {
+      const int lx = e % LX, ly = (e / LX) % LY, lz = e / (LX * LY);
+      const int gz = z0 - HR + lz;
+      const int gx = wrapk(x0 - HR + lx, nx), gy = wrapk(y0 - HR + ly, ny);
+      sp[e] = (lx < LX - 1 && gz >= 0 && gz < nz) ? u[(size_t)gz * plane + (size_t)gy * pitch + gx] : T(0);
+    }
+    __syncthreads();
+    for (int p = wave; p < np; p += STEP) {
+      // weights of the group D steps ahead; its successor's records
+      load(W[D], wo[D], fc[D]);
+      uint32_t nwo[2], nfc[2], nlcc[2];
+#pragma unroll
+      for (int h = 0; h < 2; ++h) get(p + (D + 1) * STEP + h * NW, nwo[h], nfc[h], nlcc[h]);
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int q = p + h * NW;
+        const int cnt = (int)(fc[0][h] >> 16);
+        if (cnt > 0) {
+          const int first = (int)(fc[0][h] & 0xffffu);
+          const int lc = (int)(lcc[0][h] & 0x7fffffffu);
+          const int16_t *lt = lofs[lcc[0][h] >> 31] + first;
+          T acc = T(0);
+#pragma unroll
+          for (int k = 0; k < NS; ++k) {
+            const int e = k * 64 + lane;
+            if (e < cnt) acc += W[0].w[h][k] * sp[lc + lt[e]];
+          }
+          acc = wave_sum(acc);
+          if (lane == 0) res[q] = acc;
+        }
+      }
+#pragma unroll
+      for (int d = 0; d < D; ++d) {
+        W[d] = W[d + 1];
+#pragma unroll
+        for (int h = 0; h < 2; ++h) wo[d][h] = wo[d + 1][h], fc[d][h] = fc[d + 1][h], lcc[d][h] = lcc[d + 1][h];
+      }
+#pragma unroll
+      for (int h = 0; h < 2; ++h) wo[D][h] = nwo[h], fc[D][h] = nfc[h], lcc[D][h] = nlcc[h];
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < np; i += blockDim.x) {
+      const PInfoD<T> P = pinfo[p0 + i];
+      unew[(size_t)s * vol + (size_t)P.z * plane + (size_t)P.y * pitch + P.x] += P.scale * res[i];
     }
     __syncthreads();
   }
@@ -688,9 +876,25 @@ template <typename T>
 static void launch_patch(const StepArgs &a, hipStream_t st) {
   if (a.ntiles > 0) {
     int64_t nblk = ((int64_t)a.ntiles + 7) / 8 * 8;
-    hipLaunchKernelGGL((k_patch_tiled<T, kTileX, kTileY, kTileZ, kTileHalo>), dim3((unsigned)nblk), dim3(512), 0, st,
-                       (const T *)a.un, (T *)a.um, (const T *)a.dense, (const PInfoD<T> *)a.pinfo, a.ball, a.ball_meta,
-                       a.tiles, a.ntiles, a.nx, a.ny, a.nz, a.pitch, a.vol, a.nshots);
+#define IB_PATCH_TILED(PVV)                                                                                         \
+  hipLaunchKernelGGL((k_patch_tiled<T, kTileX, kTileY, kTileZ, kTileHalo, PVV>), dim3((unsigned)nblk), dim3(512), 0, \
+                     st, (const T *)a.un, (T *)a.um, (const T *)a.dense, (const PInfoD<T> *)a.pinfo, a.ball,           \
+                     a.ball_meta, a.tiles, a.ntiles, a.nx, a.ny, a.nz, a.pitch, a.vol, a.nshots)
+#define IB_PATCH_TILED_R(DD)                                                                                        \
+  hipLaunchKernelGGL((k_patch_tiled_r<T, kTileX, kTileY, kTileZ, kTileHalo, DD>), dim3((unsigned)nblk), dim3(512),   \
+                     0, st, (const T *)a.un, (T *)a.um, (const T *)a.dense, (const PInfoD<T> *)a.pinfo, a.ball,       \
+                     a.ball_meta, a.tiles, a.ntiles, a.nx, a.ny, a.nz, a.pitch, a.vol, a.nshots)
+    switch (a.patch_variant) {
+      case 0: IB_PATCH_TILED(0); break;
+      case 1: IB_PATCH_TILED(1); break;
+      case 2: IB_PATCH_TILED(2); break;
+      case 3: IB_PATCH_TILED(3); break;
+      case 4: IB_PATCH_TILED_R(1); break;
+      case 5: IB_PATCH_TILED_R(2); break;
+      default: IB_PATCH_TILED_R(3); break;
+    }
+#undef IB_PATCH_TILED
+#undef IB_PATCH_TILED_R
   }
   if (a.nwide > 0) {
     int64_t nblk = ((a.nwide + 3) / 4 + 7) / 8 * 8;
