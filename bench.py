@@ -160,6 +160,162 @@ def cpu_baseline(budget_steps=5000):
                       f"its weight build took {t_build:.1f} s over {min(16, os.cpu_count() or 1)} processes"}
 
 
+def _time_steps(torch, st, wav, K, Wm, graph=True):
+    """Wm untimed steps, then K steps between HIP events; returns (ms per step, traces)."""
+    tr_w = torch.empty((st.nshots, Wm, st.nrec), dtype=wav.dtype, device="cuda") if st.nrec else None
+    tr = torch.empty((st.nshots, K, st.nrec), dtype=wav.dtype, device="cuda") if st.nrec else None
+    st.step(Wm, wav, tr_w, use_graph=graph)
+    torch.cuda.synchronize()
+    s = torch.cuda.current_stream()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(s)
+    st.step(K, wav, tr, use_graph=graph)
+    e1.record(s)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / K, tr
+
+
+def _trace_err(a, b):
+    num = np.linalg.norm(a - b, axis=0)
+    den = np.linalg.norm(b, axis=0)
+    den = np.maximum(den, 1e-3 * den.max())
+    e = num / den
+    return {"max": float(e.max()), "p99": float(np.percentile(e, 99)), "median": float(np.median(e))}
+
+
+def bench_config2(args):
+    """2D 801x401, M = 8: both forms (second-order p; first-order staggered p-v), free and
+    rigid surfaces (the first-order form is built for the free surface), FP32 and FP64."""
+    import torch
+
+    import paper_2309_03600_amd as ib
+    from paper_2309_03600_amd import workloads as W
+    K, Wm = args.steps, args.warmup
+    rows = []
+    for form, surface in (("p2", "free"), ("p2", "rigid"), ("pv1", "free")):
+        wl = W.config2(surface=surface, nt=K + Wm + 8)
+        w = ib.ib_build_weights(wl.heights, wl.h, wl.shape, space_order=wl.M, surface=wl.surface, eta=wl.eta,
+                                form=form)
+        N = int(np.prod(wl.shape))
+        tr = {}
+        row = {"form": form, "surface": surface, "rows_or_ib_points": w.stats()["n_ib"]}
+        for prec in ("f32", "f64"):
+            tdt = torch.float32 if prec == "f32" else torch.float64
+            st = ib.ib_state_create(w, wl.vel, wl.dt, wl.src, wl.rec, damp_width=wl.damp_width, precision=prec)
+            wav = torch.tensor(wl.wavelets(np.float64), dtype=tdt, device="cuda")
+            ms, t = _time_steps(torch, st, wav, K, Wm)
+            tr[prec] = t.double().cpu().numpy()[0]
+            row[prec] = {"ms_per_step": ms, "gpts": N / (ms * 1e-3) / 1e9}
+            st.close()
+        row["fp32_vs_fp64_trace_relL2"] = _trace_err(tr["f32"], tr["f64"])
+        log(f"[bench config2] {form} {surface}: FP32 {row['f32']['gpts']:.2f} Gpts/s, FP64 {row['f64']['gpts']:.2f}"
+            f" Gpts/s, FP32 vs FP64 max {row['fp32_vs_fp64_trace_relL2']['max']:.2e}")
+        rows.append(row)
+        w.close()
+    out = {"metric": "Gpts/s, 2D eighth-order IB step (second-order and first-order forms)",
+           "value": rows[0]["f32"]["gpts"], "unit": "Gpts/s", "n_gpus": 1, "steps": K, "warmup": Wm,
+           "ms_per_step": rows[0]["f32"]["ms_per_step"], "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+           "config": {"workload": "2D 801x401, dx=5 m, space order 8, Gaussian hill 150 m / 400 m, "
+                                  "1 Ricker source, 161 receivers, 40-cell damping"},
+           "results": rows}
+    print(json.dumps(out))
+
+
+def bench_config4(args):
+    """64 shots over one 301x301x201 topography (FP32, one batched state, graph replay)
+    against the plain single-shot FP64 path, with the FP32 error on a shot."""
+    import torch
+
+    import paper_2309_03600_amd as ib
+    from paper_2309_03600_amd import workloads as W
+    K, Wm = args.steps, args.warmup
+    wl = W.config4(nt=K + Wm + 8)
+    w = ib.ib_build_weights(wl.heights, wl.h, wl.shape, space_order=wl.M, surface=wl.surface, eta=wl.eta)
+    N = int(np.prod(wl.shape))
+    S = wl.src.shape[0]
+    st = ib.ib_state_create(w, wl.vel, wl.dt, wl.src, wl.rec, damp_width=wl.damp_width, precision="f32")
+    wav = torch.tensor(wl.wavelets(np.float64), dtype=torch.float32, device="cuda")
+    ms_b, tr_b = _time_steps(torch, st, wav, K, Wm)
+    tr_b0 = tr_b[0].double().cpu().numpy()
+    st.close()
+    del tr_b
+    single = {}
+    for prec in ("f64", "f32"):
+        tdt = torch.float64 if prec == "f64" else torch.float32
+        st = ib.ib_state_create(w, wl.vel, wl.dt, wl.src[:1], wl.rec, damp_width=wl.damp_width, precision=prec)
+        ms, tr = _time_steps(torch, st, wav[:1].to(tdt).contiguous(), K, Wm)
+        single[prec] = {"ms_per_step": ms, "gpts": N / (ms * 1e-3) / 1e9, "tr": tr[0].double().cpu().numpy()}
+        st.close()
+    gb = N * S / (ms_b * 1e-3) / 1e9
+    err = _trace_err(tr_b0, single["f64"]["tr"])
+    log(f"[bench config4] batched {S} shots FP32: {gb:.1f} Gpts/s ({ms_b:.3f} ms/step); single-shot FP64 "
+        f"{single['f64']['gpts']:.1f}, FP32 {single['f32']['gpts']:.1f} Gpts/s; shot 0 FP32 vs FP64 max {err['max']:.2e}")
+    out = {"metric": "Gpts/s (shot-points per second), batched shots, 3D eighth-order IB step", "value": gb,
+           "unit": "Gpts/s", "n_gpus": 1, "steps": K, "warmup": Wm, "ms_per_step": ms_b, "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+           "config": {"workload": f"3D 301x301x201, dx=10 m, space order 8, {S} shots in one state, "
+                                  "shared fractal topography and weights, hipGraph replay, 151x151 receivers"},
+           "single_shot_fp64": {k: v for k, v in single["f64"].items() if k != "tr"},
+           "single_shot_fp32": {k: v for k, v in single["f32"].items() if k != "tr"},
+           "speedup_vs_single_shot_fp64": gb / single["f64"]["gpts"],
+           "shot0_fp32_batched_vs_fp64_single_trace_relL2": err}
+    print(json.dumps(out))
+
+
+def bench_config5(args):
+    """FWI gradient: forward with checkpoints every 50 steps and the discrete adjoint, 16
+    shots FP32 over 256^3, against one FP64 shot, with the FP32 vs FP64 gradient error."""
+    import torch
+
+    import paper_2309_03600_amd as ib
+    from paper_2309_03600_amd import workloads as W
+    nt = args.steps
+    wl = W.config5(nt=nt)
+    w = ib.ib_build_weights(wl.heights, wl.h, wl.shape, space_order=wl.M, surface=wl.surface, eta=wl.eta)
+    N = int(np.prod(wl.shape))
+    res = {}
+    grads = {}
+    for prec, shots in (("f32", slice(0, 16)), ("f64", slice(5, 6)), ("f32_1", slice(5, 6))):
+        p = prec[:3]
+        tdt = torch.float32 if p == "f32" else torch.float64
+        src = wl.src[shots]
+        S = src.shape[0]
+        wav = torch.tensor(wl.wavelets(np.float64)[shots], dtype=tdt, device="cuda").contiguous()
+        obs = ib.ib_state_create(w, wl.extra["v_true"], wl.dt, src, wl.rec, damp_width=wl.damp_width, precision=p)
+        dobs = obs.forward(nt, wav, ckpt_every=50)
+        obs.close()
+        st = ib.ib_state_create(w, wl.vel, wl.dt, src, wl.rec, damp_width=wl.damp_width, precision=p)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        d = st.forward(nt, wav, ckpt_every=50)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        g = st.adjoint(d - dobs, wav)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        st.close()
+        grads[prec] = g.cpu().numpy()
+        del d, dobs, g
+        torch.cuda.empty_cache()
+        res[prec] = {"shots": S, "forward_s": t1 - t0, "adjoint_s": t2 - t1,
+                     "forward_gpts": N * S * nt / (t1 - t0) / 1e9,
+                     "gradient_gpts": N * S * nt / (t2 - t0) / 1e9}
+        log(f"[bench config5] {prec}: {S} shots, forward {t1 - t0:.2f} s, adjoint {t2 - t1:.2f} s, "
+            f"gradient {res[prec]['gradient_gpts']:.2f} Gpts/s")
+    e = float(np.linalg.norm(grads["f32_1"] - grads["f64"]) / np.linalg.norm(grads["f64"]))
+    out = {"metric": "Gpts/s (shot-points per second of forward + adjoint), FWI gradient, 3D eighth-order IB",
+           "value": res["f32"]["gradient_gpts"], "unit": "Gpts/s", "n_gpus": 1, "steps": nt, "warmup": 0,
+           "ms_per_step": (res["f32"]["forward_s"] + res["f32"]["adjoint_s"]) / nt * 1e3, "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+           "config": {"workload": "3D 256^3, dx=10 m, space order 8, rigid fractal surface, 16 shots, "
+                                  "64x64 receivers, +3% Gaussian velocity anomaly, checkpoints every 50 steps"},
+           "results": res, "single_shot_fp32_vs_fp64_gradient_relL2": e,
+           "speedup_vs_single_shot_fp64": res["f32"]["gradient_gpts"] / res["f64"]["gradient_gpts"]}
+    print(json.dumps(out))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -175,6 +331,8 @@ def main():
     ap.add_argument("--patch-variant", type=int, default=-1)
     ap.add_argument("--calibrate", action="store_true", help="add a 1 GiB device copy (counter calibration)")
     ap.add_argument("--summarize-counters", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"))
+    ap.add_argument("--workload", default="config3", choices=["config3", "config2", "config4", "config5"],
+                    help="config3 is the headline benchmark; the others report the secondary workloads")
     args = ap.parse_args()
     if args.summarize_counters:
         summarize_counters(*args.summarize_counters)
@@ -183,6 +341,9 @@ def main():
         print("bench.py: this build runs on one GPU only; multi-GPU sharding is a design note, "
               "not an implemented path (use --gpus 1)", file=sys.stderr)
         sys.exit(2)
+    if args.workload != "config3":
+        {"config2": bench_config2, "config4": bench_config4, "config5": bench_config5}[args.workload](args)
+        return
     import torch
 
     import paper_2309_03600_amd as ib

@@ -200,6 +200,34 @@ def config4(nt=2000, nshots=64, lateral=301, depth=201):
                     0.616e-3, nt, 10.0, np.array(src), rec, damp_width=40)
 
 
+def config5(nt=1500, nshots=16, n=256, damp_width=20):
+    """3D, 256^3, 10 m, M = 8, rigid fractal surface (physical side below it), velocity a
+    linear depth gradient v0 = 1500 -> 3500 m/s; the observed data come from
+    v_true = v0 (1 + 0.03 G), G a Gaussian blob (sigma 10 dx, peak 1) centred 90 dx deep;
+    16 sources in a 4x4 pattern 50 m below the surface, 64x64 receivers (every 4th column)
+    15 m below the surface, dt = 0.616 ms, 20-cell damping."""
+    nx = ny = nz = n
+    h = 10.0
+    H = _fractal3d(nx, ny, nz, h, 5)
+    vel = gradient_velocity((nz, ny, nx), h, 1500.0, 3500.0, 0.0, 10.0, rng(5, 1))
+    idx = np.indices((nz, ny, nx)).astype(np.float64)
+    cz, cy, cx = 90.0, ny / 2.0, nx / 2.0
+    G = np.exp(-((idx[0] - cz) ** 2 + (idx[1] - cy) ** 2 + (idx[2] - cx) ** 2) / (2 * 10.0 ** 2))
+    v_true = vel * (1.0 + 0.03 * G)
+    k = 4
+    lo, hi = damp_width + 8, n - damp_width - 9
+    pos = np.linspace(lo, hi, k)
+    src = []
+    for j in range(k):
+        for i in range(k):
+            xi, yj = int(round(pos[i])), int(round(pos[j]))
+            src.append([xi * h, yj * h, H[yj, xi] + 50.0])
+    src = np.array(src[:nshots])
+    rec = _rec_on_surface(H, h, max(1, n // 64), 15.0, nx, ny)
+    return Workload(f"config5-3d-m8-rigid-adjoint-{n}^3-{nshots}shots", 3, (nx, ny, nz), h, 8, "rigid", H, vel,
+                    0.616e-3, nt, 10.0, src, rec, damp_width=damp_width, extra=dict(v_true=v_true))
+
+
 def small3d(cfg=90, n=24, nz=44, relief=50.0, surface="free", nt=100, h=10.0, nshots=1, z_top_cells=16):
     """Small 3D fractal case for parity tests (same recipe, scaled down)."""
     H = fractal_surface(n, n, h, relief, z_top_cells * h, rng(cfg, 0))

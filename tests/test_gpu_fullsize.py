@@ -1,0 +1,222 @@
+"""Full-size workloads in the benchmark's launch configuration: sampled outputs against the
+FP64 oracle (config 3, one IB point or node at a time), complete oracle runs where the
+oracle finishes in about a minute (config 2, 2D), and properties that hold at any size
+(FP32 tracking FP64, batched shots equal to single shots, the adjoint against finite
+differences)."""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+sys.path.insert(0, os.path.dirname(os.path.abspath(__file__)))
+from oracle_cases import (model_for, pool_map, rel_l2_per_trace, simulation, solve_points,  # noqa: E402
+                          solve_staggered, window_task)
+
+from paper_2309_03600_amd import workloads as W  # noqa: E402
+
+_c3 = {}
+
+
+def config3_case():
+    if not _c3:
+        import torch
+
+        import paper_2309_03600_amd as ib
+        wl = W.config3(nt=310)
+        print(f"[config3] building {wl.shape}", flush=True)
+        w = ib.ib_build_weights(wl.heights, wl.h, wl.shape, space_order=wl.M, surface=wl.surface, eta=wl.eta)
+        torch.cuda.synchronize()
+        _c3.update(wl=wl, w=w, ex=w.export())
+    return _c3
+
+
+def test_config3_sampled_points_match_oracle():
+    import torch
+
+    import paper_2309_03600_amd as ib
+    from oracle.fd import second_derivative_weights
+    from oracle.stepper import damping_profile
+    c = config3_case()
+    wl, w, ex = c["wl"], c["w"], c["ex"]
+    nx, ny, nz = wl.shape
+    N = nx * ny * nz
+    rng = np.random.default_rng([2309, 3, 11])
+    nib = len(ex["ib_nodes"])
+    pick = np.sort(rng.choice(nib, 48, replace=False))
+    nodes = ex["ib_nodes"][pick]
+    pts = np.stack([nodes % nx, (nodes // nx) % ny, nodes // (nx * ny)], 1)
+    print(f"[config3] oracle solves of {len(pts)} sampled IB points", flush=True)
+    res = pool_map(window_task, [(wl.heights, wl.h, nz, wl.M, wl.surface, wl.eta, tuple(p)) for p in pts])
+    worst = 0.0
+    for j, (s, _) in zip(pick, res):
+        k, Mb, nw, off = ex["ib_meta"][j]
+        assert (k, Mb, nw) == (s["radius_step"], s["order"], len(s["weights"]))
+        yo = s["weights"]
+        err = np.abs(ex["weights"][off:off + nw] - yo).max() / max(1.0, np.abs(yo).max())
+        tol = max(1e-11, s["cond"] * 1e-12)           # as for the small cases
+        worst = max(worst, err / tol)
+        assert err <= tol
+    print(f"[config3] sampled weights: worst error / tolerance {worst:.3f}", flush=True)
+    # one step from random fields, checked at the sampled IB points and at sampled
+    # interior nodes off the boundary
+    cls = ex["node_class"]
+    inter = (cls & 1).astype(bool)
+    plain = np.nonzero(inter & ~((cls >> 2) & 1).astype(bool))[0]
+    others = np.sort(rng.choice(plain, 48, replace=False))
+    s_damp = damping_profile(wl.shape, wl.h, wl.dt, float(wl.vel.max()), wl.damp_width, wl.damp_R)
+    vel = wl.vel.ravel()
+    w2 = second_derivative_weights(wl.M)
+    half = wl.M // 2
+    rows = [r for _, r in res]
+    for q in others:
+        x, y, z = q % nx, (q // nx) % ny, q // (nx * ny)
+        row = {}
+        for axis in range(3):
+            for kk in range(-half, half + 1):
+                g = [x, y, z]
+                g[axis] += kk
+                if not 0 <= g[2] < nz:
+                    continue
+                qq = (g[2] * ny + g[1] % ny) * nx + g[0] % nx
+                row[qq] = row.get(qq, 0.0) + w2[kk + half]
+        rows.append(row)
+    check = np.concatenate([nodes, others])
+    g = torch.Generator(device="cuda")
+    g.manual_seed(2309)
+    mask = torch.tensor(inter.reshape(nz, ny, nx), device="cuda")
+    u = torch.randn((nz, ny, nx), generator=g, device="cuda", dtype=torch.float64) * mask
+    um = torch.randn((nz, ny, nx), generator=g, device="cuda", dtype=torch.float64) * mask
+    for prec, tol in (("f64", 1e-11), ("f32", 2e-6)):
+        tdt = torch.float64 if prec == "f64" else torch.float32
+        st = ib.ib_state_create(w, wl.vel, wl.dt, wl.src, wl.rec, damp_width=wl.damp_width, precision=prec)
+        st.field(0, 0, u.to(tdt))
+        st.field(1, 0, um.to(tdt))
+        st.step(1, torch.zeros((1, 4), dtype=tdt, device="cuda"))
+        out = st.field(0, 0).double().cpu().numpy().ravel()
+        st.close()
+        uh = u.to(tdt).double().cpu().numpy().ravel()
+        umh = um.to(tdt).double().cpu().numpy().ravel()
+        ref = np.empty(len(check))
+        for t, (q, row) in enumerate(zip(check, rows)):
+            K = (vel[q] * wl.dt / wl.h) ** 2
+            Lu = sum(wv * uh[qq] for qq, wv in row.items())
+            ref[t] = (2 * uh[q] - (1 - s_damp[q]) * umh[q] + K * Lu) / (1 + s_damp[q])
+        err = np.abs(out[check] - ref).max() / np.abs(ref).max()
+        print(f"[config3 {prec}] one step at {len(check)} sampled nodes: max rel error {err:.2e}", flush=True)
+        assert err < tol
+    assert N == len(cls)
+
+
+def test_config3_fp32_tracks_fp64():
+    import torch
+
+    import paper_2309_03600_amd as ib
+    c = config3_case()
+    wl, w = c["wl"], c["w"]
+    tr = {}
+    for prec in ("f64", "f32"):
+        tdt = torch.float64 if prec == "f64" else torch.float32
+        st = ib.ib_state_create(w, wl.vel, wl.dt, wl.src, wl.rec, damp_width=wl.damp_width, precision=prec)
+        wav = torch.tensor(wl.wavelets(np.float64), dtype=tdt, device="cuda")
+        tr[prec] = st.step(wl.nt, wav, use_graph=True).double().cpu().numpy()[0]
+        st.close()
+    e = rel_l2_per_trace(tr["f32"], tr["f64"])
+    print(f"[config3] FP32 vs FP64 over {wl.nt} steps, {e.size} receivers: max {e.max():.2e} "
+          f"p99 {np.percentile(e, 99):.2e}", flush=True)
+    assert e.max() < 1e-4
+
+
+@pytest.mark.parametrize("form,surface", [("p2", "free"), ("p2", "rigid"), ("pv1", "free")])
+def test_config2_matches_oracle(form, surface):
+    import torch
+
+    import paper_2309_03600_amd as ib
+    from oracle import staggered as S
+    wl = W.config2(surface=surface, nt=600)
+    print(f"[config2 {form} {surface}] {wl.shape}", flush=True)
+    w = ib.ib_build_weights(wl.heights, wl.h, wl.shape, space_order=wl.M, surface=wl.surface, eta=wl.eta,
+                            form=form)
+    tr = {}
+    for prec in ("f64", "f32"):
+        tdt = torch.float64 if prec == "f64" else torch.float32
+        st = ib.ib_state_create(w, wl.vel, wl.dt, wl.src, wl.rec, damp_width=wl.damp_width, precision=prec)
+        wav = torch.tensor(wl.wavelets(np.float64), dtype=tdt, device="cuda")
+        tr[prec] = st.step(wl.nt, wav, use_graph=True).double().cpu().numpy()[0]
+        st.close()
+    if form == "p2":
+        m = model_for(wl)
+        sim, _ = simulation(wl, m, solve_points(m))
+    else:
+        m = S.StaggeredModel(wl.heights, wl.h, wl.shape, M=wl.M, surface=wl.surface, eta_p=wl.eta, eta_v=0.0)
+        G, D = S.assemble(m, *solve_staggered(m))
+        sim = S.StaggeredSimulation(m, G, D, wl.vel, wl.dt, wl.src, wl.rec, damp_width=wl.damp_width,
+                                    damp_R=wl.damp_R)
+    ref = sim.run(wl.wavelets(np.float64), wl.nt)
+    e64 = rel_l2_per_trace(tr["f64"], ref)
+    e32 = rel_l2_per_trace(tr["f32"], ref)
+    print(f"[config2 {form} {surface}] per-trace rel-L2 vs oracle: FP64 max {e64.max():.2e}, "
+          f"FP32 max {e32.max():.2e} median {np.median(e32):.2e}", flush=True)
+    assert e64.max() < 1e-9
+    assert e32.max() < 1e-4
+
+
+def test_config4_batched_shots_equal_single_shots():
+    import torch
+
+    import paper_2309_03600_amd as ib
+    wl = W.config4(nt=60)
+    print(f"[config4] {wl.shape}, {wl.src.shape[0]} shots", flush=True)
+    w = ib.ib_build_weights(wl.heights, wl.h, wl.shape, space_order=wl.M, surface=wl.surface, eta=wl.eta)
+    wav = torch.tensor(wl.wavelets(np.float64), dtype=torch.float32, device="cuda")
+    st = ib.ib_state_create(w, wl.vel, wl.dt, wl.src, wl.rec, damp_width=wl.damp_width, precision="f32")
+    batched = st.step(wl.nt, wav, use_graph=True).cpu().numpy()
+    st.close()
+    assert np.isfinite(batched).all()
+    for s in (0, 37, 63):
+        one = ib.ib_state_create(w, wl.vel, wl.dt, wl.src[s:s + 1], wl.rec, damp_width=wl.damp_width,
+                                 precision="f32")
+        tr = one.step(wl.nt, wav[s:s + 1].contiguous(), use_graph=True).cpu().numpy()[0]
+        one.close()
+        assert np.array_equal(tr, batched[s]), s
+
+
+def test_config5_adjoint_matches_finite_differences_fp64():
+    import torch
+
+    import paper_2309_03600_amd as ib
+    wl = W.config5(nt=1000)
+    wl.src = wl.src[5:7]                               # the two inner shots nearest the anomaly
+    print(f"[config5] {wl.shape}, {wl.src.shape[0]} shots, {wl.rec.shape[0]} receivers", flush=True)
+    w = ib.ib_build_weights(wl.heights, wl.h, wl.shape, space_order=wl.M, surface=wl.surface, eta=wl.eta)
+    wav = torch.tensor(wl.wavelets(np.float64), device="cuda")
+    st_obs = ib.ib_state_create(w, wl.extra["v_true"], wl.dt, wl.src, wl.rec, damp_width=wl.damp_width,
+                                precision="f64")
+    dobs = st_obs.forward(wl.nt, wav, ckpt_every=50)
+    st_obs.close()
+
+    def misfit(v):
+        st = ib.ib_state_create(w, v, wl.dt, wl.src, wl.rec, damp_width=wl.damp_width, precision="f64")
+        d = st.forward(wl.nt, wav, ckpt_every=50)
+        return st, d, 0.5 * float(((d - dobs) ** 2).sum())
+
+    st, d, _ = misfit(wl.vel)
+    g = st.adjoint(d - dobs, wav).cpu().numpy()
+    st.close()
+    # a smooth direction below the surface (the gradient is zero outside the interior)
+    nz, ny, nx = wl.vel.shape
+    idx = np.indices((nz, ny, nx)).astype(np.float64)
+    dv = np.exp(-((idx[0] - 90) ** 2 + (idx[1] - ny / 2) ** 2 + (idx[2] - nx / 2) ** 2) / (2 * 14.0 ** 2)) * 10.0
+    eps = 1e-3
+    jp = misfit(wl.vel + eps * dv)
+    jp[0].close()
+    jm = misfit(wl.vel - eps * dv)
+    jm[0].close()
+    fd = (jp[2] - jm[2]) / (2 * eps)
+    ad = float((g * dv).sum())
+    print(f"[config5] directional derivative: adjoint {ad:.10e}, central difference {fd:.10e}, "
+          f"misfit {jp[2]:.4e}", flush=True)
+    assert abs(fd) > 1e-6 * jp[2]                      # the direction reaches the data
+    assert abs(ad - fd) <= 1e-6 * abs(fd)
