@@ -74,9 +74,9 @@ struct ib_state {
   // adjoint work space and transposed tables (built on first use)
   bool adj_ready = false;
   int64_t nj = 0, nrn = 0;
-  int64_t *jnode = nullptr, *joff = nullptr, *jsrc = nullptr, *rnode = nullptr, *roff = nullptr;
+  int64_t *rnode = nullptr, *roff = nullptr;
   int32_t *rrec = nullptr;
-  void *jD = nullptr, *jw = nullptr, *rD = nullptr, *rwt = nullptr;
+  void *jD = nullptr, *ibvals = nullptr, *rD = nullptr, *rwt = nullptr;
 };
 
 namespace {
@@ -465,6 +465,7 @@ void ib_weights_free(ib_weights *w) {
   dfree(w->dense_count);
   dfree(w->dense_off);
   for (int n = 0; n < 3; ++n) dfree(w->vcls[n]);
+  dfree(w->adj_jnode), dfree(w->adj_joff), dfree(w->adj_jsrc), dfree(w->adj_jw32), dfree(w->adj_jw64);
   delete w;
 }
 
@@ -862,8 +863,8 @@ void ib_state_free(ib_state *S) {
   dfree(S->vbuf), dfree(S->kv);
   dfree(S->g_node), dfree(S->g_start), dfree(S->g_enode), dfree(S->d_node), dfree(S->d_start), dfree(S->d_enode);
   dfree(S->g_scale), dfree(S->g_w), dfree(S->d_scale), dfree(S->d_w);
-  dfree(S->jnode), dfree(S->joff), dfree(S->jsrc), dfree(S->rnode), dfree(S->roff), dfree(S->rrec);
-  dfree(S->jD), dfree(S->jw), dfree(S->rD), dfree(S->rwt);
+  dfree(S->rnode), dfree(S->roff), dfree(S->rrec);
+  dfree(S->jD), dfree(S->ibvals), dfree(S->rD), dfree(S->rwt);
   delete S;
 }
 
@@ -975,77 +976,23 @@ ib_status run_steps(ib_state *S, int64_t nsteps, const void *wavelet, int64_t ws
   return IB_OK;
 }
 
-// Transposed IB rows and receivers for the adjoint (host construction, once per state).
+// Transposed IB rows (built on the device once per stencil table and shared by its
+// states) with this state's damping factors, and the transposed receivers (host, once per
+// state).
 template <typename T>
-ib_status build_adjoint_tables(ib_state *S) {
-  const ib_weights *w = S->w;
-  const int64_t nib = w->nib;
-  std::vector<int16_t> xyz(nib * 4);
-  std::vector<int32_t> meta(nib * 4);
-  std::vector<uint32_t> roff(nib);
-  std::vector<double> w64(w->sumw);
-  std::vector<uint32_t> rec(w->rec32_words);
-  if (nib) {
-    IB_HIP(hipMemcpy(xyz.data(), w->ib_xyz, nib * 8, hipMemcpyDeviceToHost));
-    IB_HIP(hipMemcpy(meta.data(), w->ib_meta, nib * 16, hipMemcpyDeviceToHost));
-    IB_HIP(hipMemcpy(roff.data(), w->rec_off32, nib * 4, hipMemcpyDeviceToHost));
-    IB_HIP(hipMemcpy(w64.data(), w->w64, w->sumw * 8, hipMemcpyDeviceToHost));
-    IB_HIP(hipMemcpy(rec.data(), w->rec32, w->rec32_words * 4, hipMemcpyDeviceToHost));
-  }
-  const int64_t nx = w->nx, ny = w->ny, pitch = S->pitch;
-  auto padded = [&](int64_t x, int64_t y, int64_t z) { return (z * ny + y) * pitch + x; };
+ib_status build_adjoint_tables(ib_state *S, hipStream_t st) {
+  // the table is a cache of the (otherwise immutable) stencil table
+  ib_weights *w = const_cast<ib_weights *>(S->w);
+  const int64_t pitch = S->pitch, ny = w->ny;
   auto Dof = [&](int64_t x, int64_t y, int64_t z) { return 1.0 / (1.0 + S->ax[x] + S->ay[w->ndim == 3 ? y : 0] + S->az[z]); };
-  // entries (receiving node, source IB node, weight), grouped by receiving node
-  struct E {
-    int64_t j, i;
-    double w;
-  };
-  std::vector<E> ent;
-  ent.reserve(w->sumw);
-  for (int64_t p = 0; p < nib; ++p) {
-    const int x = xyz[p * 4], y = xyz[p * 4 + 1], z = xyz[p * 4 + 2], code = xyz[p * 4 + 3];
-    const int nb = w->balls.count[code], st0 = w->balls.start[code];
-    const uint32_t *m = rec.data() + roff[p];
-    int64_t k = meta[p * 4 + 3];
-    for (int b = 0; b < nb; ++b) {
-      if (!((m[b >> 5] >> (b & 31)) & 1u)) continue;
-      uint32_t v = (uint32_t)w->balls.packed[st0 + b];
-      int dx = (int8_t)(v & 255), dy = (int8_t)((v >> 8) & 255), dz = (int8_t)((v >> 16) & 255);
-      int64_t xx = ((x + dx) % nx + nx) % nx, yy = ((y + dy) % ny + ny) % ny, zz = z + dz;
-      ent.push_back({padded(xx, yy, zz), padded(x, y, z), w64[k++]});
-    }
-  }
-  std::stable_sort(ent.begin(), ent.end(), [](const E &a, const E &b) { return a.j < b.j; });
-  std::vector<int64_t> jn, jo, js;
-  std::vector<T> jd, jwv;
-  js.reserve(ent.size());
-  jwv.reserve(ent.size());
-  for (size_t e = 0; e < ent.size(); ++e) {
-    if (e == 0 || ent[e].j != ent[e - 1].j) {
-      jn.push_back(ent[e].j);
-      jo.push_back((int64_t)e);
-      int64_t j = ent[e].j;
-      int64_t x = j % pitch, y = (j / pitch) % ny, z = j / (pitch * ny);
-      jd.push_back((T)Dof(x, y, z));
-    }
-    js.push_back(ent[e].i);
-    jwv.push_back((T)ent[e].w);
-  }
-  jo.push_back((int64_t)ent.size());
-  S->nj = (int64_t)jn.size();
   ib_status s;
-  if ((s = dalloc_t(&S->jnode, std::max<size_t>(jn.size(), 1))) || (s = dalloc_t(&S->joff, jo.size())) ||
-      (s = dalloc_t(&S->jsrc, std::max<size_t>(js.size(), 1))) ||
-      (s = dalloc(&S->jD, std::max<size_t>(jd.size(), 1) * sizeof(T))) ||
-      (s = dalloc(&S->jw, std::max<size_t>(jwv.size(), 1) * sizeof(T))))
+  if ((s = adjoint_table_build(w, st))) return s;
+  S->nj = w->adj_nj;
+  if ((s = dalloc(&S->jD, std::max<int64_t>(S->nj, 1) * sizeof(T))) ||
+      (s = dalloc(&S->ibvals, std::max<int64_t>(w->nib * S->nshots, 1) * sizeof(T))))
     return s;
-  if (!jn.empty()) {
-    IB_HIP(hipMemcpy(S->jnode, jn.data(), jn.size() * 8, hipMemcpyHostToDevice));
-    IB_HIP(hipMemcpy(S->jsrc, js.data(), js.size() * 8, hipMemcpyHostToDevice));
-    IB_HIP(hipMemcpy(S->jD, jd.data(), jd.size() * sizeof(T), hipMemcpyHostToDevice));
-    IB_HIP(hipMemcpy(S->jw, jwv.data(), jwv.size() * sizeof(T), hipMemcpyHostToDevice));
-  }
-  IB_HIP(hipMemcpy(S->joff, jo.data(), jo.size() * 8, hipMemcpyHostToDevice));
+  enqueue_adj_D(S->prec, w->adj_jnode, S->nj, S->sx, S->sy, S->sz, (int)ny, pitch, S->jD, st);
+  IB_HIP(hipGetLastError());
   // receivers: node -> (receiver, weight)
   struct RE {
     int64_t j;
@@ -1155,7 +1102,7 @@ ib_status ib_adjoint(ib_state *S, const void *residual, const void *wavelet, int
   const ib_weights *w = S->w;
   ib_status s;
   if (!S->adj_ready) {
-    s = (S->prec == IB_F32) ? build_adjoint_tables<float>(S) : build_adjoint_tables<double>(S);
+    s = (S->prec == IB_F32) ? build_adjoint_tables<float>(S, st) : build_adjoint_tables<double>(S, st);
     if (s) return s;
   }
   const int64_t nt = S->ck_nt, C = S->ck_every;
@@ -1210,11 +1157,13 @@ ib_status ib_adjoint(ib_state *S, const void *residual, const void *wavelet, int
       a.sy = S->sy;
       a.sz = S->sz;
       a.nj = S->nj;
-      a.jnode = S->jnode;
-      a.joff = S->joff;
-      a.jsrc = S->jsrc;
+      a.jnode = w->adj_jnode;
+      a.joff = w->adj_joff;
+      a.jsrc = w->adj_jsrc;
       a.jD = S->jD;
-      a.jw = S->jw;
+      a.jw = (S->prec == IB_F32) ? (const void *)w->adj_jw32 : (const void *)w->adj_jw64;
+      a.ibxyz = w->ib_xyz;
+      a.vals = S->ibvals;
       a.nrn = S->nrn;
       a.rnode = S->rnode;
       a.roff = S->roff;

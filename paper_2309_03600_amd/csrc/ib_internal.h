@@ -144,4 +144,10 @@ struct ib_weights {
   int64_t pv_stats[4] = {0, 0, 0, 0};
   int max_code = 0;
   ib_stats stats{};
+  // transposed IB rows for the adjoint, built on first use (-1: not built): receiving
+  // nodes (padded index), run offsets [nj + 1], IB point and weight of each entry
+  int64_t adj_nj = -1;
+  uint32_t *adj_jnode = nullptr, *adj_joff = nullptr, *adj_jsrc = nullptr;
+  float *adj_jw32 = nullptr;
+  double *adj_jw64 = nullptr;
 };

@@ -90,10 +90,12 @@ struct AdjArgs {
   const void *lam1;      // lambda^{m+1}
   void *lam2;            // lambda^{m+2} in, lambda^m out
   const void *K, *sx, *sy, *sz;
-  // transposed IB rows
+  // transposed IB rows (receiving nodes, run offsets, IB point and weight per entry)
   int64_t nj;
-  const int64_t *jnode, *joff, *jsrc;
+  const uint32_t *jnode, *joff, *jsrc;
   const void *jD, *jw;
+  const int16_t *ibxyz;  // IB points (x, y, z, code)
+  void *vals;            // scratch [nib][nshots]: K lambda^{m+1} at the IB points
   // transposed receivers
   int64_t nrn;
   const int64_t *rnode, *roff;
@@ -112,6 +114,9 @@ struct AdjArgs {
   const int32_t *ball, *delta, *ball_meta;
 };
 void enqueue_adjoint_step(const AdjArgs &a, hipStream_t st);
+void enqueue_adj_D(int prec, const uint32_t *jnode, int64_t nj, const void *sx, const void *sy, const void *sz, int ny,
+                   int64_t pitch, void *D, hipStream_t st);
+ib_status adjoint_table_build(ib_weights *w, hipStream_t st);
 void enqueue_grad_out(int prec, const double *gK, const void *K, double *out, int nx, int ny, int nz, int64_t pitch,
                       double dt_over_h, hipStream_t st);
 void enqueue_make_pinfo(int prec, const int16_t *xyz, const uint32_t *roff, const void *scale, const int32_t *perm,

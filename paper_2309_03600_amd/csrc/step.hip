@@ -994,26 +994,61 @@ __global__ void k_adj_interior(const T *__restrict__ lam1, T *__restrict__ lam2,
   o[c] = (T(2) * uc - (T(1) - s) * o[c] + lap) / (T(1) + s);
 }
 
-// lambda^m_j += D_j sum_k w_k K_{i_k} lambda^{m+1}_{i_k} over the IB rows i_k that use node j
+// v[i][s] = K_i lambda^{m+1}_{s,i} at the IB points (shots fastest), for the gather below
 template <typename T>
-__global__ void k_adj_gather(T *__restrict__ lam, const T *__restrict__ lam1, const T *__restrict__ K,
-                             const int64_t *__restrict__ jnode, const T *__restrict__ jD,
-                             const int64_t *__restrict__ joff, const int64_t *__restrict__ src,
-                             const T *__restrict__ wt, int64_t nj, int nshots, int64_t vol) {
-  int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= nj) return;
-  const int64_t a = joff[j], b = joff[j + 1];
-  const int64_t node = jnode[j];
-  const T d = jD[j];
-  for (int s = 0; s < nshots; ++s) {
-    const T *l1 = lam1 + (size_t)s * vol;
-    T acc = T(0);
-    for (int64_t k = a; k < b; ++k) {
-      const int64_t q = src[k];
-      acc += wt[k] * (K[q] * l1[q]);
-    }
-    lam[(size_t)s * vol + node] += d * acc;
+__global__ void k_adj_ibvals(T *__restrict__ v, const T *__restrict__ lam1, const T *__restrict__ K,
+                             const int16_t *__restrict__ xyz, int64_t nib, int nshots, int ny, int64_t pitch,
+                             int64_t vol) {
+  int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= nib * nshots) return;
+  const int64_t i = e / nshots;
+  const int s = (int)(e - i * nshots);
+  const size_t q = ((size_t)xyz[i * 4 + 2] * ny + xyz[i * 4 + 1]) * pitch + xyz[i * 4];
+  v[e] = K[q] * lam1[(size_t)s * vol + q];
+}
+
+// lambda^m_j += D_j sum_k w_k v[i_k] over the IB points i_k whose rows use node j, for SC
+// shots at a time.  A 16-lane row of a wavefront takes one receiving node: its lanes read
+// the node's run of (point, weight) entries together (coalesced), gather v, and the row's
+// partial sums are combined with DPP rotations inside the row.
+template <typename T>
+__device__ __forceinline__ T row_sum16(T v) {
+  v += dpp_mov<0x128>(v);
+  v += dpp_mov<0x124>(v);
+  v += dpp_mov<0x122>(v);
+  v += dpp_mov<0x121>(v);
+  return v;
+}
+
+template <typename T, int SC>
+__launch_bounds__(256)
+__global__ void k_adj_gather(T *__restrict__ lam, const T *__restrict__ v, const uint32_t *__restrict__ jnode,
+                             const T *__restrict__ jD, const uint32_t *__restrict__ joff,
+                             const uint32_t *__restrict__ src, const T *__restrict__ wt, int64_t nj, int nshots,
+                             int s0, int64_t vol) {
+  const int sub = threadIdx.x & 15;
+  const int64_t j = (int64_t)blockIdx.x * (blockDim.x >> 4) + (threadIdx.x >> 4);
+  const bool live = j < nj;
+  // rows stay complete (no early return) so that the DPP rotations see all 16 lanes
+  const uint32_t a = live ? joff[j] : 0u, b = live ? joff[j + 1] : 0u;
+  T acc[SC];
+#pragma unroll
+  for (int c = 0; c < SC; ++c) acc[c] = T(0);
+  for (uint32_t k = a + sub; k < b; k += 16) {
+    const T w = wt[k];
+    const T *vi = v + (size_t)src[k] * nshots + s0;
+#pragma unroll
+    for (int c = 0; c < SC; ++c)
+      if (s0 + c < nshots) acc[c] += w * vi[c];
   }
+  T mine = T(0);
+#pragma unroll
+  for (int c = 0; c < SC; ++c) {
+    const T t = row_sum16(acc[c]);
+    if (sub == c) mine = t;
+  }
+  if (live && sub < SC && s0 + sub < nshots)
+    lam[(size_t)(s0 + sub) * vol + jnode[j]] += jD[j] * mine;
 }
 
 // lambda^m_j += D_j sum over receivers using node j of w * res^{m-1}
@@ -1149,10 +1184,28 @@ static void adjoint_step_t(const AdjArgs &a, hipStream_t st) {
                          a.nshots);
       break;
   }
-  if (a.nj > 0)
-    hipLaunchKernelGGL(k_adj_gather<T>, dim3((unsigned)((a.nj + 255) / 256)), dim3(256), 0, st, (T *)a.lam2,
-                       (const T *)a.lam1, (const T *)a.K, a.jnode, (const T *)a.jD, a.joff, a.jsrc, (const T *)a.jw,
-                       a.nj, a.nshots, a.vol);
+  if (a.nj > 0) {
+    const int64_t nv = a.nib * a.nshots;
+    hipLaunchKernelGGL(k_adj_ibvals<T>, dim3((unsigned)((nv + 255) / 256)), dim3(256), 0, st, (T *)a.vals,
+                       (const T *)a.lam1, (const T *)a.K, a.ibxyz, a.nib, a.nshots, a.ny, a.pitch, a.vol);
+    const dim3 gj((unsigned)((a.nj + 15) / 16));
+    for (int s0 = 0; s0 < a.nshots;) {
+      const int left = a.nshots - s0;
+      if (left >= 8) {
+        hipLaunchKernelGGL((k_adj_gather<T, 8>), gj, dim3(256), 0, st, (T *)a.lam2, (const T *)a.vals, a.jnode,
+                           (const T *)a.jD, a.joff, a.jsrc, (const T *)a.jw, a.nj, a.nshots, s0, a.vol);
+        s0 += 8;
+      } else if (left >= 4) {
+        hipLaunchKernelGGL((k_adj_gather<T, 4>), gj, dim3(256), 0, st, (T *)a.lam2, (const T *)a.vals, a.jnode,
+                           (const T *)a.jD, a.joff, a.jsrc, (const T *)a.jw, a.nj, a.nshots, s0, a.vol);
+        s0 += 4;
+      } else {
+        hipLaunchKernelGGL((k_adj_gather<T, 1>), gj, dim3(256), 0, st, (T *)a.lam2, (const T *)a.vals, a.jnode,
+                           (const T *)a.jD, a.joff, a.jsrc, (const T *)a.jw, a.nj, a.nshots, s0, a.vol);
+        s0 += 1;
+      }
+    }
+  }
   if (a.nrn > 0)
     hipLaunchKernelGGL(k_adj_receivers<T>, dim3((unsigned)((a.nrn + 255) / 256)), dim3(256), 0, st, (T *)a.lam2,
                        (const T *)a.res, a.nt, a.nrec, a.step, a.rnode, (const T *)a.rD, a.roff, a.rrec,
