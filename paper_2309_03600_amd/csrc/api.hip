@@ -34,6 +34,7 @@ struct ib_state {
   void *pinfo = nullptr;       // all points, memory order (gradient kernels)
   void *pinfo_t = nullptr;     // tiled points, tile order
   void *pinfo_w = nullptr;     // wide-support points
+  void *pinfo_tm = nullptr;    // tiled points, compact records
   int4 *tiles = nullptr;
   int ntiles = 0;
   int64_t nwide = 0;
@@ -111,6 +112,7 @@ StepArgs make_args(ib_state *st, const void *wavelet, int64_t wstride, void *tra
   a.tiles = st->tiles;
   a.ntiles = st->ntiles;
   a.pinfo_wide = st->pinfo_w;
+  a.pinfo_tm = st->pinfo_tm;
   a.nwide = st->nwide;
   a.delta = st->delta;
   a.ball = w->ball;
@@ -745,6 +747,7 @@ ib_status ib_state_create(const ib_weights *w, const double *vel_dev, double dt,
       int32_t *d_perm = nullptr;
       if ((s = dalloc(&S->pinfo_t, std::max<size_t>(tiled.size(), 1) * pinfo_dense_bytes(prec))) ||
           (s = dalloc(&S->pinfo_w, std::max<size_t>(wide.size(), 1) * pinfo_bytes(prec))) ||
+          (s = dalloc(&S->pinfo_tm, std::max<size_t>(tiled.size(), 1) * pinfo_bytes(prec))) ||
           (s = dalloc_t(&S->tiles, tl.size())) ||
           (s = dalloc_t(&d_perm, std::max<size_t>(std::max(tiled.size(), wide.size()), 1))))
         return fail(s);
@@ -754,6 +757,7 @@ ib_status ib_state_create(const ib_weights *w, const double *vel_dev, double dt,
         IB_HIP(hipMemcpy(d_perm, tiled.data(), tiled.size() * 4, hipMemcpyHostToDevice));
         enqueue_make_pinfo_dense(prec, w->ib_xyz, w->dense_first, w->dense_count, w->dense_off, S->scale, d_perm,
                                  (int64_t)tiled.size(), S->pinfo_t, st);
+        enqueue_make_pinfo(prec, w->ib_xyz, ro, S->scale, d_perm, (int64_t)tiled.size(), S->pinfo_tm, st);
         IB_HIP(hipStreamSynchronize(st));
       }
       if (!wide.empty()) {
@@ -852,6 +856,7 @@ void ib_state_free(ib_state *S) {
   dfree(S->pinfo);
   dfree(S->pinfo_t);
   dfree(S->pinfo_w);
+  dfree(S->pinfo_tm);
   dfree(S->tiles);
   dfree(S->delta);
   dfree(S->sidx);
@@ -871,7 +876,7 @@ void ib_state_free(ib_state *S) {
 int64_t ib_state_step_count(const ib_state *S) { return S ? S->t : -1; }
 
 ib_status ib_state_set_tuning(ib_state *S, int32_t variant, int32_t zchunk, int32_t patch_variant) {
-  if (!S || zchunk < 0 || variant < 0 || variant > 3 || patch_variant < -1 || patch_variant > 6) {
+  if (!S || zchunk < 0 || variant < 0 || variant > 3 || patch_variant < -1 || patch_variant > 7) {
     set_error("ib_state_set_tuning: invalid argument");
     return IB_ERR_ARG;
   }

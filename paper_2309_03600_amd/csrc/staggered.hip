@@ -21,6 +21,7 @@
 #include "ib_internal.h"
 #include "step.h"
 #include "surface.h"
+#include "wave.h"
 
 namespace ib {
 
@@ -287,20 +288,26 @@ __global__ void k_pv_pressure(T *__restrict__ p, const T *__restrict__ v, const 
   q[c] = ((T(1) - s) * q[c] + kp[c] * div) / (T(1) + s);
 }
 
-// modified rows: dst[row] += scale[row] * sum_k w_k src[k]
+// modified rows: dst[row] += scale[row] * sum_k w_k src[k].  A 16-lane row of a wavefront
+// takes one modified row: its lanes read the row's entries together and the partial sums
+// are combined by DPP rotations inside the 16 lanes; shots loop inside.
 template <typename T>
+__launch_bounds__(256)
 __global__ void k_pv_rows(T *__restrict__ dst, int64_t dst_shot_stride, const T *__restrict__ src,
                           int64_t src_shot_stride, const int64_t *__restrict__ rnode, const T *__restrict__ rscale,
                           const int64_t *__restrict__ rstart, const int64_t *__restrict__ enode,
                           const T *__restrict__ ew, int64_t nrows, int nshots) {
-  int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (r >= nrows) return;
-  const int64_t a = rstart[r], b = rstart[r + 1];
+  const int sub = threadIdx.x & 15;
+  const int64_t r = (int64_t)blockIdx.x * (blockDim.x >> 4) + (threadIdx.x >> 4);
+  const bool live = r < nrows;
+  // rows stay complete (no early return) so that the DPP rotations see all 16 lanes
+  const int64_t a = live ? rstart[r] : 0, b = live ? rstart[r + 1] : 0;
   for (int s = 0; s < nshots; ++s) {
     const T *ss = src + (size_t)s * src_shot_stride;
     T acc = T(0);
-    for (int64_t k = a; k < b; ++k) acc += ew[k] * ss[enode[k]];
-    dst[(size_t)s * dst_shot_stride + rnode[r]] += rscale[r] * acc;
+    for (int64_t k = a + sub; k < b; k += 16) acc += ew[k] * ss[enode[k]];
+    acc = row_sum16(acc);
+    if (live && sub == 0) dst[(size_t)s * dst_shot_stride + rnode[r]] += rscale[r] * acc;
   }
 }
 
@@ -322,13 +329,13 @@ static void pv_step_h(const PVArgs &a, hipStream_t st) {
   hipLaunchKernelGGL((k_pv_velocity<T, H>), gv, b, 0, st, (T *)a.v, (const T *)a.p, (const T *)a.kv, (const T *)a.sx,
                      (const T *)a.sy, (const T *)a.sz, W, a.nx, a.ny, a.nz, a.pitch, a.vol, a.nv, a.ndim, a.nshots);
   if (a.nrows_g > 0)
-    hipLaunchKernelGGL(k_pv_rows<T>, dim3((unsigned)((a.nrows_g + 255) / 256)), b, 0, st, (T *)a.v,
+    hipLaunchKernelGGL(k_pv_rows<T>, dim3((unsigned)((a.nrows_g + 15) / 16)), b, 0, st, (T *)a.v,
                        (int64_t)a.nv * a.vol, (const T *)a.p, a.vol, a.g_node, (const T *)a.g_scale, a.g_start,
                        a.g_enode, (const T *)a.g_w, a.nrows_g, a.nshots);
   hipLaunchKernelGGL((k_pv_pressure<T, H>), gp, b, 0, st, (T *)a.p, (const T *)a.v, (const T *)a.kp, (const T *)a.sx,
                      (const T *)a.sy, (const T *)a.sz, W, a.nx, a.ny, a.nz, a.pitch, a.vol, a.nv, a.ndim, a.nshots);
   if (a.nrows_d > 0)
-    hipLaunchKernelGGL(k_pv_rows<T>, dim3((unsigned)((a.nrows_d + 255) / 256)), b, 0, st, (T *)a.p, a.vol,
+    hipLaunchKernelGGL(k_pv_rows<T>, dim3((unsigned)((a.nrows_d + 15) / 16)), b, 0, st, (T *)a.p, a.vol,
                        (const T *)a.v, (int64_t)a.nv * a.vol, a.d_node, (const T *)a.d_scale, a.d_start, a.d_enode,
                        (const T *)a.d_w, a.nrows_d, a.nshots);
 }

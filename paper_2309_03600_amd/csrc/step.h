@@ -29,6 +29,7 @@ struct StepArgs {
   int64_t nib;
   const uint32_t *rec;
   const void *pinfo;          // dense-range point records of the tiled points, tile order
+  const void *pinfo_tm;       // compact-record point records of the tiled points, tile order
   const void *dense;          // dense-range weights (state precision)
   const int4 *tiles;          // [ntiles + 1]: x0, y0, z0, first point (the last holds the end)
   int ntiles;

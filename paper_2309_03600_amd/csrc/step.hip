@@ -15,6 +15,7 @@
 
 #include "ib_internal.h"
 #include "step.h"
+#include "wave.h"
 
 namespace ib {
 
@@ -408,39 +409,6 @@ __global__ void k_patch(const T *__restrict__ un, T *__restrict__ unew, const ui
   }
 }
 
-// ---- wavefront sum without LDS traffic ------------------------------------------------
-// Four DPP row rotations leave every lane of a 16-lane row holding the row's sum; the four
-// row sums are then read as scalars.
-template <int C>
-__device__ __forceinline__ float dpp_mov(float v) {
-  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), C, 0xF, 0xF, false));
-}
-template <int C>
-__device__ __forceinline__ double dpp_mov(double v) {
-  const unsigned long long b = __builtin_bit_cast(unsigned long long, v);
-  const int lo = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(b & 0xffffffffull), C, 0xF, 0xF, false);
-  const int hi = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(b >> 32), C, 0xF, 0xF, false);
-  return __builtin_bit_cast(double, ((unsigned long long)(unsigned)hi << 32) | (unsigned)lo);
-}
-__device__ __forceinline__ float read_lane(float v, int l) {
-  return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), l));
-}
-__device__ __forceinline__ double read_lane(double v, int l) {
-  const unsigned long long b = __builtin_bit_cast(unsigned long long, v);
-  const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(b & 0xffffffffull), l);
-  const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(b >> 32), l);
-  return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
-}
-// full-wavefront sum (every lane active), returned in every lane
-template <typename T>
-__device__ __forceinline__ T wave_sum(T v) {
-  v += dpp_mov<0x128>(v);   // row_ror:8
-  v += dpp_mov<0x124>(v);   // row_ror:4
-  v += dpp_mov<0x122>(v);   // row_ror:2
-  v += dpp_mov<0x121>(v);   // row_ror:1
-  return (read_lane(v, 0) + read_lane(v, 16)) + (read_lane(v, 32) + read_lane(v, 48));
-}
-
 // ---- IB patch, LDS-tiled (3D) -------------------------------------------------------
 // IB points are bucketed into TX x TY x TZ tiles (host, at state creation).  A workgroup
 // stages p^n over its tile plus an HR-cell halo in LDS with coalesced row loads; its
@@ -733,6 +701,172 @@ __global__ void k_patch_tiled_r(const T *__restrict__ un, T *__restrict__ unew, 
   }
 }
 
+// Tiled patch streaming the compact records (bit mask of the support ball's data nodes,
+// then the weights of the set bits): only the weights of data nodes cross HBM.  A point's
+// mask words arrive one group ahead of its weights; each 64-lattice-point slot's word is
+// read into scalars, a lane's weight index is the count of set bits below it plus the
+// slot's base, and the lanes' LDS offsets for the two tiled ball sizes sit in registers.
+struct TileRecM {
+  uint32_t roff;      // record offset (32-bit words)
+  uint32_t lcc;       // LDS index of the point | radius code 9 << 31
+};
+
+template <typename T, int TX, int TY, int TZ, int HR>
+__launch_bounds__(512)
+__global__ void k_patch_tiled_m(const T *__restrict__ un, T *__restrict__ unew, const uint32_t *__restrict__ rec,
+                                const PInfo<T> *__restrict__ pinfo, const int32_t *__restrict__ ball,
+                                const int32_t *__restrict__ ball_meta, const int4 *__restrict__ tiles, int ntiles,
+                                int nx, int ny, int nz, int64_t pitch, int64_t vol, int nshots) {
+  constexpr int LX = TX + 2 * HR + 1, LY = TY + 2 * HR, LZ = TZ + 2 * HR;
+  constexpr int NS = 7;                       // 64-lattice-point slots (balls of up to 448 points)
+  constexpr int NW = 8;
+  constexpr int STEP = 2 * NW;
+  __shared__ T sp[LZ * LY * LX];
+  __shared__ TileRecM trec[kTileMaxPoints];
+  __shared__ T res[kTileMaxPoints];
+  const int64_t tb = xcd_remap(blockIdx.x, gridDim.x);
+  if (tb >= ntiles) return;
+  const int4 tl = tiles[tb];
+  const int x0 = tl.x, y0 = tl.y, z0 = tl.z;
+  const int p0 = tl.w, np = tiles[tb + 1].w - tl.w;
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  const int64_t plane = pitch * ny;
+  // ball codes 8 and 9: sizes, mask words, weight start (FP64 weights are 8-byte aligned)
+  int nbc[2], nwc[2], wpc[2];
+  int lo[2][NS];
+#pragma unroll
+  for (int q = 0; q < 2; ++q) {
+    const int code = 8 + q, st0 = ball_meta[2 * code];
+    nbc[q] = ball_meta[2 * code + 1];
+    nwc[q] = (nbc[q] + 31) >> 5;
+    wpc[q] = (sizeof(T) == 8) ? ((nwc[q] + 1) & ~1) : nwc[q];
+#pragma unroll
+    for (int k = 0; k < NS; ++k) {
+      const int b = k * 64 + lane;
+      int v = 0;
+      if (b < nbc[q]) {
+        const uint32_t e = (uint32_t)ball[st0 + b];
+        const int dx = (int8_t)(e & 255), dy = (int8_t)((e >> 8) & 255), dz = (int8_t)((e >> 16) & 255);
+        v = (dz * LY + dy) * LX + dx;
+      }
+      lo[q][k] = v;
+    }
+  }
+  for (int i = threadIdx.x; i < np; i += blockDim.x) {
+    const PInfo<T> P = pinfo[p0 + i];
+    int cx = P.x - x0;
+    if (cx < 0) cx += nx;
+    int cy = P.y - y0;
+    if (cy < 0) cy += ny;
+    const int lc = ((P.z - z0 + HR) * LY + (cy + HR)) * LX + (cx + HR);
+    TileRecM r;
+    r.roff = P.roff;
+    r.lcc = (uint32_t)lc | (P.code == 9 ? 0x80000000u : 0u);
+    trec[i] = r;
+  }
+  __syncthreads();
+  auto get = [&](int i, uint32_t &roff, uint32_t &lcc) {
+    if (i < np) {
+      const TileRecM r = trec[i];
+      roff = __builtin_amdgcn_readfirstlane(r.roff);
+      lcc = __builtin_amdgcn_readfirstlane(r.lcc);
+    } else {
+      roff = 0u, lcc = 0xffffffffu;          // no point
+    }
+  };
+  // the mask words of a point, one per lane (lanes beyond the word count read nothing)
+  auto load_mask = [&](uint32_t roff, uint32_t lcc) -> uint32_t {
+    if (lcc == 0xffffffffu) return 0u;
+    const int nwd = nwc[lcc >> 31];
+    return lane < nwd ? rec[roff + lane] : 0u;
+  };
+  // the weights of a point from its mask (all lanes take part in the scalar reads)
+  auto load_w = [&](T (&w)[NS], uint32_t mk, uint32_t roff, uint32_t lcc) {
+    const bool live = lcc != 0xffffffffu;
+    const int q = (int)(lcc >> 31) & 1;
+    const T *wts = reinterpret_cast<const T *>(rec + roff + (live ? wpc[q] : 0));
+    uint32_t base = 0;
+#pragma unroll
+    for (int k = 0; k < NS; ++k) {
+      const uint32_t wl = (uint32_t)__builtin_amdgcn_readlane((int)mk, 2 * k);
+      const uint32_t wh = (uint32_t)__builtin_amdgcn_readlane((int)mk, 2 * k + 1);
+      const uint32_t word = lane < 32 ? wl : wh;
+      const bool on = live && ((word >> (lane & 31)) & 1u);
+      const uint32_t rank = __builtin_amdgcn_mbcnt_hi(wh, __builtin_amdgcn_mbcnt_lo(wl, 0u));
+      w[k] = on ? wts[base + rank] : T(0);
+      base += (uint32_t)(__builtin_popcount(wl) + __builtin_popcount(wh));
+    }
+  };
+  for (int s = 0; s < nshots; ++s) {
+    const T *u = un + (size_t)s * vol;
+    // group g = points (p, p + NW); records two groups ahead, masks one group ahead
+    uint32_t ro0[2], lc0[2], ro1[2], lc1[2], ro2[2], lc2[2], mk1[2];
+    T w0[2][NS];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      get(wave + h * NW, ro0[h], lc0[h]);
+      get(wave + STEP + h * NW, ro1[h], lc1[h]);
+      get(wave + 2 * STEP + h * NW, ro2[h], lc2[h]);
+    }
+    {
+      uint32_t mk0[2];
+#pragma unroll
+      for (int h = 0; h < 2; ++h) mk0[h] = load_mask(ro0[h], lc0[h]);
+#pragma unroll
+      for (int h = 0; h < 2; ++h) mk1[h] = load_mask(ro1[h], lc1[h]);
+#pragma unroll
+      for (int h = 0; h < 2; ++h) load_w(w0[h], mk0[h], ro0[h], lc0[h]);
+    }
+    for (int e = threadIdx.x; e < LZ * LY * LX; e += blockDim.x) {
+      const int lx = e % LX, ly = (e / LX) % LY, lz = e / (LX * LY);
+      const int gz = z0 - HR + lz;
+      const int gx = wrapk(x0 - HR + lx, nx), gy = wrapk(y0 - HR + ly, ny);
+      sp[e] = (lx < LX - 1 && gz >= 0 && gz < nz) ? u[(size_t)gz * plane + (size_t)gy * pitch + gx] : T(0);
+    }
+    __syncthreads();
+    for (int p = wave; p < np; p += STEP) {
+      // masks of the group two ahead, weights of the next group
+      uint32_t mk2[2];
+      T w1[2][NS];
+#pragma unroll
+      for (int h = 0; h < 2; ++h) mk2[h] = load_mask(ro2[h], lc2[h]);
+#pragma unroll
+      for (int h = 0; h < 2; ++h) load_w(w1[h], mk1[h], ro1[h], lc1[h]);
+      uint32_t ro3[2], lc3[2];
+#pragma unroll
+      for (int h = 0; h < 2; ++h) get(p + 3 * STEP + h * NW, ro3[h], lc3[h]);
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        if (lc0[h] != 0xffffffffu) {
+          const int lcx = (int)(lc0[h] & 0x7fffffffu);
+          const bool c9 = (lc0[h] >> 31) != 0u;
+          T acc = T(0);
+#pragma unroll
+          for (int k = 0; k < NS; ++k) acc += w0[h][k] * sp[lcx + (c9 ? lo[1][k] : lo[0][k])];
+          acc = wave_sum(acc);
+          if (lane == 0) res[p + h * NW] = acc;
+        }
+      }
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        ro0[h] = ro1[h], lc0[h] = lc1[h];
+        ro1[h] = ro2[h], lc1[h] = lc2[h];
+        ro2[h] = ro3[h], lc2[h] = lc3[h];
+        mk1[h] = mk2[h];
+#pragma unroll
+        for (int k = 0; k < NS; ++k) w0[h][k] = w1[h][k];
+      }
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < np; i += blockDim.x) {
+      const PInfo<T> P = pinfo[p0 + i];
+      unew[(size_t)s * vol + (size_t)P.z * plane + (size_t)P.y * pitch + P.x] += P.scale * res[i];
+    }
+    __syncthreads();
+  }
+}
+
 template <typename T>
 __global__ void k_make_pinfo_dense(const int16_t *xyz, const int32_t *first, const int32_t *count,
                                    const uint32_t *doff, const T *scale, const int32_t *perm, int64_t n,
@@ -891,7 +1025,12 @@ static void launch_patch(const StepArgs &a, hipStream_t st) {
       case 3: IB_PATCH_TILED(3); break;
       case 4: IB_PATCH_TILED_R(1); break;
       case 5: IB_PATCH_TILED_R(2); break;
-      default: IB_PATCH_TILED_R(3); break;
+      case 6: IB_PATCH_TILED_R(3); break;
+      default:
+        hipLaunchKernelGGL((k_patch_tiled_m<T, kTileX, kTileY, kTileZ, kTileHalo>), dim3((unsigned)nblk), dim3(512), 0,
+                           st, (const T *)a.un, (T *)a.um, a.rec, (const PInfo<T> *)a.pinfo_tm, a.ball, a.ball_meta,
+                           a.tiles, a.ntiles, a.nx, a.ny, a.nz, a.pitch, a.vol, a.nshots);
+        break;
     }
 #undef IB_PATCH_TILED
 #undef IB_PATCH_TILED_R
@@ -1011,14 +1150,6 @@ __global__ void k_adj_ibvals(T *__restrict__ v, const T *__restrict__ lam1, cons
 // shots at a time.  A 16-lane row of a wavefront takes one receiving node: its lanes read
 // the node's run of (point, weight) entries together (coalesced), gather v, and the row's
 // partial sums are combined with DPP rotations inside the row.
-template <typename T>
-__device__ __forceinline__ T row_sum16(T v) {
-  v += dpp_mov<0x128>(v);
-  v += dpp_mov<0x124>(v);
-  v += dpp_mov<0x122>(v);
-  v += dpp_mov<0x121>(v);
-  return v;
-}
 
 template <typename T, int SC>
 __launch_bounds__(256)

@@ -1,0 +1,49 @@
+// Wavefront reductions with DPP lane rotations (no LDS traffic), for 64-wide wavefronts.
+#pragma once
+#include <hip/hip_runtime.h>
+
+namespace ib {
+
+// Four DPP row rotations leave every lane of a 16-lane row holding the row's sum; the four
+// row sums are then read as scalars.
+template <int C>
+__device__ __forceinline__ float dpp_mov(float v) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), C, 0xF, 0xF, false));
+}
+template <int C>
+__device__ __forceinline__ double dpp_mov(double v) {
+  const unsigned long long b = __builtin_bit_cast(unsigned long long, v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(b & 0xffffffffull), C, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(b >> 32), C, 0xF, 0xF, false);
+  return __builtin_bit_cast(double, ((unsigned long long)(unsigned)hi << 32) | (unsigned)lo);
+}
+__device__ __forceinline__ float read_lane(float v, int l) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), l));
+}
+__device__ __forceinline__ double read_lane(double v, int l) {
+  const unsigned long long b = __builtin_bit_cast(unsigned long long, v);
+  const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(b & 0xffffffffull), l);
+  const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(b >> 32), l);
+  return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
+}
+// full-wavefront sum (every lane active), returned in every lane
+template <typename T>
+__device__ __forceinline__ T wave_sum(T v) {
+  v += dpp_mov<0x128>(v);   // row_ror:8
+  v += dpp_mov<0x124>(v);   // row_ror:4
+  v += dpp_mov<0x122>(v);   // row_ror:2
+  v += dpp_mov<0x121>(v);   // row_ror:1
+  return (read_lane(v, 0) + read_lane(v, 16)) + (read_lane(v, 32) + read_lane(v, 48));
+}
+
+// sum over each 16-lane row, returned in every lane of the row
+template <typename T>
+__device__ __forceinline__ T row_sum16(T v) {
+  v += dpp_mov<0x128>(v);
+  v += dpp_mov<0x124>(v);
+  v += dpp_mov<0x122>(v);
+  v += dpp_mov<0x121>(v);
+  return v;
+}
+
+}  // namespace ib
