@@ -50,8 +50,9 @@ typedef enum {
 } ib_status;
 
 typedef enum { IB_FORM_P2 = 0,  /* second-order pressure form                                  */
-               IB_FORM_PV1 = 1  /* first-order pressure-velocity form on a staggered grid (2D,
-                                   free surface: section "The Particle Velocity Free-Surface") */
+               IB_FORM_PV1 = 1  /* first-order pressure-velocity form on a staggered grid (free
+                                   surface: section "The Particle Velocity Free-Surface"; in 3D
+                                   space_order <= 4, the order of the paper's examples) */
 } ib_form;
 typedef enum { IB_SURF_FREE = 0, IB_SURF_RIGID = 1 } ib_surface;
 typedef enum { IB_F32 = 0, IB_F64 = 1 } ib_precision;
@@ -245,12 +246,13 @@ ib_status ib_state_run_kernel(ib_state *st, int32_t which, int32_t count, void *
 /* Tuning knobs of the 3D eighth-order step kernels.
  *   variant (interior stencil): 0 (one plane per barrier pair), 1 (software-pipelined,
  *     64x16 tiles), 2 (pipelined, 64x32 tiles, 8 rows per thread), 3 (pipelined, 64x32
- *     tiles, 512 threads);
+ *     tiles, 512 threads), 4 (pipelined, 64x16 tiles, 512 threads, 2 rows per thread);
  *   zchunk: depth planes per interior workgroup (0 = automatic: enough workgroups to fill
  *     the device);
  *   patch_variant (tiled IB patch): 0-3 point records read per wavefront (bit 0 as scalar
  *     loads, bit 1 DPP wavefront sums); 4-6 records staged in LDS per tile with DPP sums and
- *     1-3 groups of two points' weights in flight (default 4); -1 keeps the current one.
+ *     1-3 groups of two points' weights in flight (default 4); 7 compact records (bit masks
+ *     and the data nodes' weights only); -1 keeps the current one.
  * Results do not depend on the interior knobs; the patch variants differ only in the
  * summation order of each point's weighted sum. */
 ib_status ib_state_set_tuning(ib_state *st, int32_t variant, int32_t zchunk, int32_t patch_variant);

@@ -253,11 +253,13 @@ ib_status autotune_interior(ib_state *S, hipStream_t st) {
   int bestv = 1;
   // two passes over every (variant, zchunk) pair, each timed over 8 launches after 2
   // warm-up launches; the minimum of the two passes is kept (clocks ramp up during the first)
-  std::vector<float> tbest(2 * cands.size(), 1e30f);
+  const int variants[3] = {1, 3, 4};
+  const int nv = 3;
+  std::vector<float> tbest(nv * cands.size(), 1e30f);
   for (int pass = 0; pass < 2; ++pass)
-    for (int cand = 0; cand < 2 * (int)cands.size(); ++cand) {
-      S->variant = (cand % 2 == 0) ? 1 : 3;
-      S->zchunk = cands[cand / 2];
+    for (int cand = 0; cand < nv * (int)cands.size(); ++cand) {
+      S->variant = variants[cand % nv];
+      S->zchunk = cands[cand / nv];
       StepArgs a = make_args(S, nullptr, 0, nullptr, 0, S->cur);
       for (int i = 0; i < 2; ++i) enqueue_interior_only(a, st);
       IB_HIP(hipEventRecord(e0, st));
@@ -268,11 +270,11 @@ ib_status autotune_interior(ib_state *S, hipStream_t st) {
       IB_HIP(hipEventElapsedTime(&ms, e0, e1));
       tbest[cand] = std::min(tbest[cand], ms);
     }
-  for (int cand = 0; cand < 2 * (int)cands.size(); ++cand)
+  for (int cand = 0; cand < nv * (int)cands.size(); ++cand)
     if (tbest[cand] < best) {
       best = tbest[cand];
-      bestzc = cands[cand / 2];
-      bestv = (cand % 2 == 0) ? 1 : 3;
+      bestzc = cands[cand / nv];
+      bestv = variants[cand % nv];
     }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
@@ -306,8 +308,11 @@ ib_status ib_build_weights(const ib_grid *g, const double *height_dev, const ib_
     set_error("unsupported form %d", p->form);
     return IB_ERR_ARG;
   }
-  if (p->form == IB_FORM_PV1 && g->ndim != 2) {
-    set_error("the first-order form is built for 2D grids (its coupled 3D velocity systems exceed the solver)");
+  if (p->form == IB_FORM_PV1 && g->ndim == 3 && p->space_order >= 2 && p->space_order <= kMaxOrder &&
+      3 * n_terms(p->space_order, 3) > 192) {
+    // the divergence family couples the three velocity blocks of the Taylor basis
+    set_error("the 3D first-order form needs space_order <= 4 (its coupled velocity system has %d unknowns, "
+              "the solver takes 192)", 3 * n_terms(p->space_order, 3));
     return IB_ERR_ARG;
   }
   if (p->form == IB_FORM_PV1 && p->surface != IB_SURF_FREE) {
@@ -876,7 +881,7 @@ void ib_state_free(ib_state *S) {
 int64_t ib_state_step_count(const ib_state *S) { return S ? S->t : -1; }
 
 ib_status ib_state_set_tuning(ib_state *S, int32_t variant, int32_t zchunk, int32_t patch_variant) {
-  if (!S || zchunk < 0 || variant < 0 || variant > 3 || patch_variant < -1 || patch_variant > 7) {
+  if (!S || zchunk < 0 || variant < 0 || variant > 4 || patch_variant < -1 || patch_variant > 7) {
     set_error("ib_state_set_tuning: invalid argument");
     return IB_ERR_ARG;
   }

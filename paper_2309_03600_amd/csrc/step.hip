@@ -173,13 +173,15 @@ __global__ void k_interior3d_p(const T *__restrict__ un, T *__restrict__ um, con
   const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
   const int x0 = bxi * TX, y0 = byi * TY;
   const int z0 = bzi * zchunk, z1 = min(nz, z0 + zchunk);
-  const int64_t plane = pitch * ny;
+  // 32-bit element offsets inside one shot's volume (the launcher checks the volume fits),
+  // so that addresses are a scalar base plus one 32-bit offset
+  const uint32_t plane = (uint32_t)(pitch * ny);
   const T *u = un + (size_t)shot * vol;
   T *o = um + (size_t)shot * vol;
   const int xg = x0 + tx;
   const int xw = xg % nx;
   const bool xin = xg < nx;
-  size_t rowoff[RY];
+  uint32_t rowoff[RY];
   bool yin[RY];
   int ywv[RY];
 #pragma unroll
@@ -187,14 +189,14 @@ __global__ void k_interior3d_p(const T *__restrict__ un, T *__restrict__ um, con
     int yg = y0 + ty * RY + r;
     yin[r] = yg < ny;
     ywv[r] = yg % ny;
-    rowoff[r] = (size_t)ywv[r] * pitch + xw;
+    rowoff[r] = (uint32_t)ywv[r] * (uint32_t)pitch + (uint32_t)xw;
   }
   // halo sources of this thread (x halo: up to RY values; y halo: 2 values)
   const bool xl = tx < H, xr = tx >= TX - H;
   const int xh = xl ? ((x0 - H + tx) % nx + nx) % nx : (xr ? (x0 + TX + (tx - (TX - H))) % nx : 0);
   const int lxh = xl ? tx : (xr ? TX + H + (tx - (TX - H)) : 0);
   constexpr int NHY = (2 * H * TX + 64 * NW - 1) / (64 * NW);   // y-halo values per thread
-  size_t hyoff[NHY];
+  uint32_t hyoff[NHY];
   int hyly[NHY], hylx[NHY];
   bool hyon[NHY];
   const int t = threadIdx.x;
@@ -207,7 +209,7 @@ __global__ void k_interior3d_p(const T *__restrict__ un, T *__restrict__ um, con
     int hr = idx / TX, hc = idx % TX;
     int yg = (hr < H) ? y0 - H + hr : y0 + TY + (hr - H);
     int yy = ((yg % ny) + ny) % ny;
-    hyoff[i] = (size_t)yy * pitch + (x0 + hc) % nx;
+    hyoff[i] = (uint32_t)yy * (uint32_t)pitch + (uint32_t)((x0 + hc) % nx);
     hyly[i] = (hr < H) ? hr : TY + H + (hr - H);
     hylx[i] = H + hc;
   }
@@ -217,18 +219,18 @@ __global__ void k_interior3d_p(const T *__restrict__ un, T *__restrict__ um, con
 #pragma unroll
     for (int k = 0; k <= 2 * H; ++k) {
       int z = z0 - H + k;
-      q[r][k] = (z >= 0 && z < nz) ? u[(size_t)z * plane + rowoff[r]] : T(0);
+      q[r][k] = (z >= 0 && z < nz) ? u[(uint32_t)z * plane + rowoff[r]] : T(0);
     }
   }
   T pm[RY], kk[RY], hx[RY], hy[NHY];
 #pragma unroll
   for (int r = 0; r < RY; ++r) {
-    pm[r] = o[(size_t)z0 * plane + rowoff[r]];
-    kk[r] = K[(size_t)z0 * plane + rowoff[r]];
-    hx[r] = (xl || xr) ? u[(size_t)z0 * plane + (size_t)ywv[r] * pitch + xh] : T(0);
+    pm[r] = o[(uint32_t)z0 * plane + rowoff[r]];
+    kk[r] = K[(uint32_t)z0 * plane + rowoff[r]];
+    hx[r] = (xl || xr) ? u[(uint32_t)z0 * plane + (uint32_t)ywv[r] * (uint32_t)pitch + (uint32_t)xh] : T(0);
   }
 #pragma unroll
-  for (int i = 0; i < NHY; ++i) hy[i] = hyon[i] ? u[(size_t)z0 * plane + hyoff[i]] : T(0);
+  for (int i = 0; i < NHY; ++i) hy[i] = hyon[i] ? u[(uint32_t)z0 * plane + hyoff[i]] : T(0);
   int buf = 0;
   for (int z = z0; z < z1; ++z) {
     // centre plane and its halo into LDS
@@ -245,14 +247,14 @@ __global__ void k_interior3d_p(const T *__restrict__ un, T *__restrict__ um, con
     T nq[RY], npm[RY], nk[RY], nhx[RY], nhy[NHY];
     const int zn = z + 1;
     const bool more = zn < z1;
-    const size_t znoff = (size_t)zn * plane;
+    const uint32_t znoff = (uint32_t)zn * plane;
     const int zq = z + H + 1;
 #pragma unroll
     for (int r = 0; r < RY; ++r) {
-      nq[r] = (zq < nz) ? u[(size_t)zq * plane + rowoff[r]] : T(0);
+      nq[r] = (zq < nz) ? u[(uint32_t)zq * plane + rowoff[r]] : T(0);
       npm[r] = more ? o[znoff + rowoff[r]] : T(0);
       nk[r] = more ? K[znoff + rowoff[r]] : T(0);
-      nhx[r] = (more && (xl || xr)) ? u[znoff + (size_t)ywv[r] * pitch + xh] : T(0);
+      nhx[r] = (more && (xl || xr)) ? u[znoff + (uint32_t)ywv[r] * (uint32_t)pitch + (uint32_t)xh] : T(0);
     }
 #pragma unroll
     for (int i = 0; i < NHY; ++i) nhy[i] = (more && hyon[i]) ? u[znoff + hyoff[i]] : T(0);
@@ -269,7 +271,7 @@ __global__ void k_interior3d_p(const T *__restrict__ un, T *__restrict__ um, con
                          (tile[buf][ly - k][lx] + tile[buf][ly + k][lx]) + (q[r][H - k] + q[r][H + k]));
       const T s = sxz + sy[ywv[r]];
       const T v = (T(2) * c - (T(1) - s) * pm[r] + kk[r] * lap) / (T(1) + s);
-      if (xin && yin[r]) o[(size_t)z * plane + rowoff[r]] = v;
+      if (xin && yin[r]) o[(uint32_t)z * plane + rowoff[r]] = v;
     }
 #pragma unroll
     for (int r = 0; r < RY; ++r) {
@@ -951,9 +953,9 @@ static void launch_interior(const StepArgs &a, hipStream_t st) {
   T *um = (T *)a.um;
   const T *K = (const T *)a.K;
   const T *sx = (const T *)a.sx, *sy = (const T *)a.sy, *sz = (const T *)a.sz;
-  if (a.ndim == 3 && a.M == 8 && a.variant >= 1) {
-    const int RY = (a.variant == 2) ? 8 : 4;
-    const int NW = (a.variant == 3) ? 8 : 4;
+  if (a.ndim == 3 && a.M == 8 && a.variant >= 1 && a.vol * (int64_t)sizeof(T) < (int64_t(1) << 31)) {
+    const int RY = (a.variant == 2) ? 8 : (a.variant == 4 ? 2 : 4);
+    const int NW = (a.variant == 3 || a.variant == 4) ? 8 : 4;
     const int TY = RY * NW;
     const int ntx = (a.nx + 63) / 64, nty = (a.ny + TY - 1) / TY;
     const int zc = a.zchunk > 0 ? a.zchunk : a.nz;
@@ -966,6 +968,9 @@ static void launch_interior(const StepArgs &a, hipStream_t st) {
                          W, a.nx, a.ny, a.nz, a.pitch, a.vol, zc, ntx, nty, nzc, a.nshots);
     else if (a.variant == 3)
       hipLaunchKernelGGL((k_interior3d_p<T, 4, 4, 8>), dim3((unsigned)nblk8), dim3(512), 0, st, un, um, K, sx, sy, sz,
+                         W, a.nx, a.ny, a.nz, a.pitch, a.vol, zc, ntx, nty, nzc, a.nshots);
+    else if (a.variant == 4)
+      hipLaunchKernelGGL((k_interior3d_p<T, 4, 2, 8>), dim3((unsigned)nblk8), dim3(512), 0, st, un, um, K, sx, sy, sz,
                          W, a.nx, a.ny, a.nz, a.pitch, a.vol, zc, ntx, nty, nzc, a.nshots);
     else
       hipLaunchKernelGGL((k_interior3d_p<T, 4, 4, 4>), dim3((unsigned)nblk8), dim3(256), 0, st, un, um, K, sx, sy, sz,
