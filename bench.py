@@ -316,6 +316,44 @@ def bench_config5(args):
     print(json.dumps(out))
 
 
+def bench_pv3d(args):
+    """3D first-order p-v form, fourth order (the order of the paper's examples), over the
+    401x401x301 fractal free surface of the headline workload; FP32 and FP64."""
+    import dataclasses
+
+    import torch
+
+    import paper_2309_03600_amd as ib
+    from paper_2309_03600_amd import workloads as W
+    K, Wm = args.steps, args.warmup
+    wl = dataclasses.replace(W.config3(nt=K + Wm + 8, lateral=args.lateral, depth=args.depth), M=4)
+    t0 = time.time()
+    w = ib.ib_build_weights(wl.heights, wl.h, wl.shape, space_order=4, surface=wl.surface, eta=wl.eta, form="pv1")
+    torch.cuda.synchronize()
+    build_s = time.time() - t0
+    N = int(np.prod(wl.shape))
+    res, tr = {}, {}
+    for prec in ("f32", "f64"):
+        tdt = torch.float32 if prec == "f32" else torch.float64
+        st = ib.ib_state_create(w, wl.vel, wl.dt, wl.src, wl.rec, damp_width=wl.damp_width, precision=prec)
+        wav = torch.tensor(wl.wavelets(np.float64), dtype=tdt, device="cuda")
+        ms, t = _time_steps(torch, st, wav, K, Wm)
+        tr[prec] = t.double().cpu().numpy()[0]
+        res[prec] = {"ms_per_step": ms, "gpts": N / (ms * 1e-3) / 1e9}
+        st.close()
+    err = _trace_err(tr["f32"], tr["f64"])
+    log(f"[bench pv3d] rows {w.stats()['n_ib']} built in {build_s:.1f} s; FP32 {res['f32']['gpts']:.1f} Gpts/s, "
+        f"FP64 {res['f64']['gpts']:.1f} Gpts/s; FP32 vs FP64 max {err['max']:.2e}")
+    out = {"metric": "Gpts/s, 3D fourth-order first-order (p-v) IB step", "value": res["f32"]["gpts"],
+           "unit": "Gpts/s", "n_gpus": 1, "steps": K, "warmup": Wm, "ms_per_step": res["f32"]["ms_per_step"],
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+           "config": {"workload": f"3D first-order form {wl.shape[0]}x{wl.shape[1]}x{wl.shape[2]}, dx=10 m, "
+                                  "space order 4, fractal free surface, 40-cell damping, 201x201 receivers"},
+           "results": res, "fp32_vs_fp64_trace_relL2": err, "modified_rows": w.stats()["n_ib"],
+           "weights_build_s": build_s}
+    print(json.dumps(out))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -331,7 +369,7 @@ def main():
     ap.add_argument("--patch-variant", type=int, default=-1)
     ap.add_argument("--calibrate", action="store_true", help="add a 1 GiB device copy (counter calibration)")
     ap.add_argument("--summarize-counters", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"))
-    ap.add_argument("--workload", default="config3", choices=["config3", "config2", "config4", "config5"],
+    ap.add_argument("--workload", default="config3", choices=["config3", "config2", "config4", "config5", "pv3d"],
                     help="config3 is the headline benchmark; the others report the secondary workloads")
     args = ap.parse_args()
     if args.summarize_counters:
@@ -342,7 +380,8 @@ def main():
               "not an implemented path (use --gpus 1)", file=sys.stderr)
         sys.exit(2)
     if args.workload != "config3":
-        {"config2": bench_config2, "config4": bench_config4, "config5": bench_config5}[args.workload](args)
+        {"config2": bench_config2, "config4": bench_config4, "config5": bench_config5,
+         "pv3d": bench_pv3d}[args.workload](args)
         return
     import torch
 
