@@ -55,6 +55,7 @@ typedef enum { IB_FORM_P2 = 0,  /* second-order pressure form                   
                                    space_order <= 4, the order of the paper's examples) */
 } ib_form;
 typedef enum { IB_SURF_FREE = 0, IB_SURF_RIGID = 1 } ib_surface;
+typedef enum { IB_METHOD_ND = 0, IB_METHOD_1D = 1 } ib_method;
 typedef enum { IB_F32 = 0, IB_F64 = 1 } ib_precision;
 
 /* Regular grid.  n[0] = nx, n[1] = ny (3D) , n[ndim-1] = nz.  h = grid increment in
@@ -83,6 +84,12 @@ typedef struct {
  *   physical_below   1: the physical domain is below the surface (z > H); 0: above.
  *   eta_v            exclusion cut-off of the velocity nodes (first-order form; the paper
  *                    uses 0: no velocity node is excluded).
+ *   method           IB_METHOD_ND: the N-D Taylor extrapolants over hyperspherical supports
+ *                    (the paper's method); IB_METHOD_1D: one 1D extrapolation per truncated
+ *                    side of each axis stencil, from the free-surface conditions where the
+ *                    axis line crosses the surface and the M/2 nearest interior nodes of the
+ *                    line farther than eta from it (section "Reduction to 1D"; second-order
+ *                    form, free surface).
  */
 typedef struct {
   int32_t form;
@@ -94,6 +101,8 @@ typedef struct {
   double eta;
   double rank_rtol;
   double eta_v;
+  int32_t method;
+  int32_t reserved;
 } ib_params;
 
 typedef struct {

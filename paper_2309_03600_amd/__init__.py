@@ -92,14 +92,19 @@ class IBWeights:
 
 
 def ib_build_weights(heights, h, shape, space_order=8, surface="free", eta=0.5, max_radius_steps=3,
-                     min_basis_order=None, physical_below=True, rank_rtol=0.0, form="p2", eta_v=0.0, stream=None):
+                     min_basis_order=None, physical_below=True, rank_rtol=0.0, form="p2", eta_v=0.0, method="nd",
+                     stream=None):
     """Build the IB stencils for a heightfield (torch float64 device tensor or array, metres).
 
     ``form`` "p2" is the second-order pressure form, "pv1" the first-order pressure-velocity
-    form on a staggered grid (2D).
+    form on a staggered grid.  ``method`` "nd" builds the N-D extrapolants of the paper,
+    "1d" the per-axis 1D extrapolations of its reduction to 1D (second-order form, free
+    surface).
     """
     if form not in ("p2", "pv1"):
         raise ValueError("form must be 'p2' or 'pv1'")
+    if method not in ("nd", "1d"):
+        raise ValueError("method must be 'nd' or '1d'")
     torch = _torch()
     ndim = len(shape)
     Ht = torch.as_tensor(np.ascontiguousarray(heights, dtype=np.float64) if not torch.is_tensor(heights) else heights,
@@ -112,6 +117,7 @@ def ib_build_weights(heights, h, shape, space_order=8, surface="free", eta=0.5, 
     p = _lib.ib_params()
     p.form = _lib.IB_FORM_P2 if form == "p2" else _lib.IB_FORM_PV1
     p.eta_v = float(eta_v)
+    p.method = _lib.IB_METHOD_ND if method == "nd" else _lib.IB_METHOD_1D
     p.surface = IB_SURF_FREE if surface == "free" else IB_SURF_RIGID
     p.space_order = int(space_order)
     p.max_radius_steps = int(max_radius_steps)

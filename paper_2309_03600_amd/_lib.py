@@ -12,6 +12,8 @@ IB_F32, IB_F64 = 0, 1
 IB_SURF_FREE, IB_SURF_RIGID = 0, 1
 IB_FORM_P2 = 0
 IB_FORM_PV1 = 1
+IB_METHOD_ND = 0
+IB_METHOD_1D = 1
 FIELD_NODE_CLASS, FIELD_BPOINTS, FIELD_IB_NODES, FIELD_IB_META, FIELD_WEIGHTS_F64, FIELD_SIGMA = range(6)
 FIELD_PV_ROWS, FIELD_PV_ENTRIES, FIELD_VCLASS = 6, 7, 8
 
@@ -23,7 +25,8 @@ class ib_grid(C.Structure):
 class ib_params(C.Structure):
     _fields_ = [("form", C.c_int32), ("surface", C.c_int32), ("space_order", C.c_int32),
                 ("max_radius_steps", C.c_int32), ("min_basis_order", C.c_int32), ("physical_below", C.c_int32),
-                ("eta", C.c_double), ("rank_rtol", C.c_double), ("eta_v", C.c_double)]
+                ("eta", C.c_double), ("rank_rtol", C.c_double), ("eta_v", C.c_double), ("method", C.c_int32),
+                ("reserved", C.c_int32)]
 
 
 class ib_stats(C.Structure):

@@ -11,7 +11,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libibwave.so")
-SOURCES = ["common.cpp", "geometry.hip", "weights.hip", "step.hip", "staggered.hip", "adjoint.hip", "api.hip"]
+SOURCES = ["common.cpp", "geometry.hip", "weights.hip", "step.hip", "staggered.hip", "adjoint.hip", "mulder.hip", "api.hip"]
 FLAGS = ["--offload-arch=gfx950", "-O3", "-fPIC", "-std=c++17",
          # packed FP32 instructions are kept out of generated code on this target
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]

@@ -16,6 +16,7 @@ ib_status geometry_build(ib_weights *w, const double *height_dev, hipStream_t st
 ib_status ib_points_build(ib_weights *w, hipStream_t st);
 ib_status weights_build(ib_weights *w, const int64_t *col_off_dev, hipStream_t st);
 ib_status pv_build(ib_weights *w, const int64_t *col_off_dev, hipStream_t st);
+ib_status mulder_build(ib_weights *w, hipStream_t st);
 const char *last_error_text();
 }  // namespace ib
 
@@ -315,6 +316,15 @@ ib_status ib_build_weights(const ib_grid *g, const double *height_dev, const ib_
               "the solver takes 192)", 3 * n_terms(p->space_order, 3));
     return IB_ERR_ARG;
   }
+  if (p->method != IB_METHOD_ND && p->method != IB_METHOD_1D) {
+    set_error("unsupported method %d", p->method);
+    return IB_ERR_ARG;
+  }
+  if (p->method == IB_METHOD_1D && (p->form != IB_FORM_P2 || p->surface != IB_SURF_FREE)) {
+    // the reduction to 1D is given for the free-surface conditions of the pressure form
+    set_error("the 1D extrapolation method is defined for the second-order form with a free surface");
+    return IB_ERR_ARG;
+  }
   if (p->form == IB_FORM_PV1 && p->surface != IB_SURF_FREE) {
     // the method's first-order form is given for the free surface (zero pressure and the
     // divergence hierarchy); a rigid-surface velocity row set is not part of it
@@ -417,7 +427,10 @@ ib_status ib_build_weights(const ib_grid *g, const double *height_dev, const ib_
     }
     IB_HIP(hipMemcpy(col_off, off.data(), (ncol + 1) * 8, hipMemcpyHostToDevice));
   }
-  s = (w->form == IB_FORM_P2) ? weights_build(w, col_off, st) : pv_build(w, col_off, st);
+  if (w->form == IB_FORM_PV1)
+    s = pv_build(w, col_off, st);
+  else
+    s = (p->method == IB_METHOD_1D) ? mulder_build(w, st) : weights_build(w, col_off, st);
   dfree(col_off);
   if (s != IB_OK) {
     ib_weights_free(w);

@@ -88,6 +88,8 @@ void second_derivative_weights(int M, double *w);                 // offsets -M/
 
 struct ib_weights;
 namespace ib {
+ib_status upload_ball_tables(ib_weights *w, hipStream_t st);
+ib_status build_dense_records(ib_weights *w, hipStream_t st);
 ib_status solve_family(ib_weights *w, const FamilySpec &F, const int64_t *col_off_dev, hipStream_t st,
                        std::vector<FamilyPoint> &out);
 }

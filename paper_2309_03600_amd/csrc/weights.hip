@@ -649,24 +649,74 @@ struct RoundResult {
   int nball = 0, nwords = 0;
 };
 
+// Ball lattice tables (all radius codes up to max_code + 2) on the device.
+ib_status upload_ball_tables(ib_weights *w, hipStream_t st) {
+  w->balls.build(w->ndim, w->max_code + 2);
+  ib_status s;
+  if ((s = dalloc_t(&w->ball, w->balls.packed.size()))) return s;
+  IB_HIP(hipMemcpyAsync(w->ball, w->balls.packed.data(), w->balls.packed.size() * 4, hipMemcpyHostToDevice, st));
+  std::vector<int32_t> bm(2 * (kMaxRadiusCode + 2), 0);
+  for (int c = 0; c <= kMaxRadiusCode + 1; ++c) {
+    bm[2 * c] = w->balls.start[c];
+    bm[2 * c + 1] = w->balls.count[c];
+  }
+  if ((s = dalloc_t(&w->ball_meta, bm.size()))) return s;
+  IB_HIP(hipMemcpy(w->ball_meta, bm.data(), bm.size() * 4, hipMemcpyHostToDevice));
+  return IB_OK;
+}
+
+// Dense-range records (weights of every ball lattice point from the first to the last data
+// point of each support) from the compact records.
+ib_status build_dense_records(ib_weights *w, hipStream_t st) {
+  const int64_t nib = w->nib;
+  ib_status s;
+  {
+    int32_t *d_first = nullptr, *d_count = nullptr;
+    uint32_t *d_doff = nullptr;
+    if ((s = dalloc_t(&d_first, std::max<int64_t>(nib, 1))) || (s = dalloc_t(&d_count, std::max<int64_t>(nib, 1))) ||
+        (s = dalloc_t(&d_doff, std::max<int64_t>(nib, 1))))
+      return s;
+    if (nib)
+      hipLaunchKernelGGL(k_mask_range, dim3((unsigned)((nib + 255) / 256)), dim3(256), 0, st, nib, w->rec32,
+                         w->rec_off32, w->ib_xyz, w->ball_meta, d_first, d_count);
+    std::vector<int32_t> hf(nib), hc(nib);
+    std::vector<uint32_t> ho(nib);
+    IB_HIP(hipMemcpyAsync(hf.data(), d_first, nib * 4, hipMemcpyDeviceToHost, st));
+    IB_HIP(hipMemcpyAsync(hc.data(), d_count, nib * 4, hipMemcpyDeviceToHost, st));
+    IB_HIP(hipStreamSynchronize(st));
+    int64_t sd = 0;
+    for (int64_t i = 0; i < nib; ++i) {
+      ho[i] = (uint32_t)sd;
+      sd += hc[i];
+    }
+    if (sd >= (int64_t)UINT32_MAX) {
+      set_error("dense stencil table too large");
+      return IB_ERR_ARG;
+    }
+    w->dense_words = sd;
+    w->stats.dense_weights = sd;
+    if ((s = dalloc_t(&w->dense32, std::max<int64_t>(sd, 1))) || (s = dalloc_t(&w->dense64, std::max<int64_t>(sd, 1))))
+      return s;
+    IB_HIP(hipMemcpyAsync(d_doff, ho.data(), nib * 4, hipMemcpyHostToDevice, st));
+    if (nib)
+      hipLaunchKernelGGL(k_dense, dim3((unsigned)nib), dim3(64), 0, st, nib, w->rec32, w->rec_off32, w->ib_meta,
+                         w->w64, d_first, d_count, d_doff, w->dense32, w->dense64);
+    IB_HIP(hipGetLastError());
+    IB_HIP(hipStreamSynchronize(st));
+    w->dense_first = d_first;
+    w->dense_count = d_count;
+    w->dense_off = d_doff;
+  }
+  return IB_OK;
+}
+
 ib_status weights_build(ib_weights *w, const int64_t *col_off_dev, hipStream_t st) {
   const int ndim = w->ndim, lat = ndim - 1, M = w->M;
   const int Kmax = w->prm.max_radius_steps;
   const int min_order = w->prm.min_basis_order;
   w->max_code = M + 1 + 2 * Kmax;
-  w->balls.build(ndim, w->max_code + 2);
   ib_status s;
-  if ((s = dalloc_t(&w->ball, w->balls.packed.size()))) return s;
-  IB_HIP(hipMemcpyAsync(w->ball, w->balls.packed.data(), w->balls.packed.size() * 4, hipMemcpyHostToDevice, st));
-  {
-    std::vector<int32_t> bm(2 * (kMaxRadiusCode + 2), 0);
-    for (int c = 0; c <= kMaxRadiusCode + 1; ++c) {
-      bm[2 * c] = w->balls.start[c];
-      bm[2 * c + 1] = w->balls.count[c];
-    }
-    if ((s = dalloc_t(&w->ball_meta, bm.size()))) return s;
-    IB_HIP(hipMemcpy(w->ball_meta, bm.data(), bm.size() * 4, hipMemcpyHostToDevice));
-  }
+  if ((s = upload_ball_tables(w, st))) return s;
 
   const int64_t nib = w->nib;
   std::vector<int32_t> pending(nib);
@@ -897,45 +947,7 @@ ib_status weights_build(ib_weights *w, const int64_t *col_off_dev, hipStream_t s
   }
   IB_HIP(hipStreamSynchronize(st));
   dfree(d_woff), dfree(d_nw), dfree(d_apos), dfree(d_aid), dfree(d_sigma);
-  // dense-range records
-  {
-    int32_t *d_first = nullptr, *d_count = nullptr;
-    uint32_t *d_doff = nullptr;
-    if ((s = dalloc_t(&d_first, std::max<int64_t>(nib, 1))) || (s = dalloc_t(&d_count, std::max<int64_t>(nib, 1))) ||
-        (s = dalloc_t(&d_doff, std::max<int64_t>(nib, 1))))
-      return s;
-    if (nib)
-      hipLaunchKernelGGL(k_mask_range, dim3((unsigned)((nib + 255) / 256)), dim3(256), 0, st, nib, w->rec32,
-                         w->rec_off32, w->ib_xyz, w->ball_meta, d_first, d_count);
-    std::vector<int32_t> hf(nib), hc(nib);
-    std::vector<uint32_t> ho(nib);
-    IB_HIP(hipMemcpyAsync(hf.data(), d_first, nib * 4, hipMemcpyDeviceToHost, st));
-    IB_HIP(hipMemcpyAsync(hc.data(), d_count, nib * 4, hipMemcpyDeviceToHost, st));
-    IB_HIP(hipStreamSynchronize(st));
-    int64_t sd = 0;
-    for (int64_t i = 0; i < nib; ++i) {
-      ho[i] = (uint32_t)sd;
-      sd += hc[i];
-    }
-    if (sd >= (int64_t)UINT32_MAX) {
-      set_error("dense stencil table too large");
-      return IB_ERR_ARG;
-    }
-    w->dense_words = sd;
-    w->stats.dense_weights = sd;
-    if ((s = dalloc_t(&w->dense32, std::max<int64_t>(sd, 1))) || (s = dalloc_t(&w->dense64, std::max<int64_t>(sd, 1))))
-      return s;
-    IB_HIP(hipMemcpyAsync(d_doff, ho.data(), nib * 4, hipMemcpyHostToDevice, st));
-    if (nib)
-      hipLaunchKernelGGL(k_dense, dim3((unsigned)nib), dim3(64), 0, st, nib, w->rec32, w->rec_off32, w->ib_meta,
-                         w->w64, d_first, d_count, d_doff, w->dense32, w->dense64);
-    IB_HIP(hipGetLastError());
-    IB_HIP(hipStreamSynchronize(st));
-    w->dense_first = d_first;
-    w->dense_count = d_count;
-    w->dense_off = d_doff;
-  }
-  return IB_OK;
+  return build_dense_records(w, st);
 }
 
 // Batched solves of one family of staggered operators (first-order form): the same

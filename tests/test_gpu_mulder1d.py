@@ -1,0 +1,191 @@
+"""Per-axis 1D extrapolation table (the paper's reduction to 1D) built on the GPU, against
+the oracle's 1D rows, and its comparison with the N-D table on the same workload."""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+sys.path.insert(0, os.path.dirname(os.path.abspath(__file__)))
+from oracle_cases import model_for, rel_l2_per_trace, simulation, solve_points  # noqa: E402
+
+from paper_2309_03600_amd import workloads as W  # noqa: E402
+
+CASES = {
+    "2d-m8": lambda: W.small2d(M=8, surface="free", nt=300),
+    "2d-m4": lambda: W.small2d(M=4, surface="free", nt=300, cfg=92),
+    # the 1D reduction needs M/2 interior nodes along each truncated axis line: a gentler
+    # relief than the N-D cases (on the rougher one a lateral line leaves the interior)
+    "3d-m8": lambda: W.small3d(n=16, nz=40, relief=15.0, surface="free", nt=120),
+}
+
+_cache = {}
+
+
+def case(name):
+    if name not in _cache:
+        import torch
+
+        import paper_2309_03600_amd as ib
+        from oracle import mulder1d
+        wl = CASES[name]()
+        print(f"[1d case {name}] shape={wl.shape} M={wl.M}", flush=True)
+        w = ib.ib_build_weights(wl.heights, wl.h, wl.shape, space_order=wl.M, surface=wl.surface, eta=wl.eta,
+                                method="1d")
+        torch.cuda.synchronize()
+        m = model_for(wl)
+        L = mulder1d.assemble_laplacian_1d(m)
+        _cache[name] = (wl, w, m, L)
+    return _cache[name]
+
+
+@pytest.mark.parametrize("name", list(CASES))
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_one_step_matches_oracle_rows(name, prec):
+    """Every modified row at once: one step from random fields against the oracle's L."""
+    import torch
+
+    import paper_2309_03600_amd as ib
+    from oracle import stepper
+    wl, w, m, L = case(name)
+    sim = stepper.Simulation(m, L, wl.vel, wl.dt, wl.src, wl.rec, damp_width=wl.damp_width, damp_R=wl.damp_R)
+    st = ib.ib_state_create(w, wl.vel, wl.dt, wl.src, wl.rec, damp_width=wl.damp_width, precision=prec)
+    inter = m.geom.interior_grid()
+    tdt = torch.float64 if prec == "f64" else torch.float32
+    for seed in (3, 4):
+        rng = np.random.default_rng(seed)
+        u = np.where(inter, rng.standard_normal(inter.shape), 0.0)
+        um = np.where(inter, rng.standard_normal(inter.shape), 0.0)
+        st.field(0, 0, torch.tensor(u, dtype=tdt))
+        st.field(1, 0, torch.tensor(um, dtype=tdt))
+        st.step(1, torch.zeros((1, st.step_count + 2), dtype=tdt, device="cuda"))
+        got = st.field(0, 0).double().cpu().numpy().ravel()
+        ur = torch.tensor(u, dtype=tdt).double().numpy().ravel()
+        umr = torch.tensor(um, dtype=tdt).double().numpy().ravel()
+        ref = (2 * ur - (1 - sim.s) * umr + sim.K * (L @ ur)) / (1 + sim.s)
+        err = np.abs(got - ref).max() / np.abs(ref).max()
+        print(f"[1d {name} {prec} seed {seed}] one-step max error {err:.2e}")
+        assert err < (1e-11 if prec == "f64" else 2e-6)
+
+
+@pytest.mark.parametrize("name", list(CASES))
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_traces_match_oracle(name, prec):
+    import torch
+
+    import paper_2309_03600_amd as ib
+    from oracle import stepper
+    wl, w, m, L = case(name)
+    sim = stepper.Simulation(m, L, wl.vel, wl.dt, wl.src, wl.rec, damp_width=wl.damp_width, damp_R=wl.damp_R)
+    ref = sim.run(wl.wavelets(np.float64), wl.nt)
+    st = ib.ib_state_create(w, wl.vel, wl.dt, wl.src, wl.rec, damp_width=wl.damp_width, precision=prec)
+    tdt = torch.float64 if prec == "f64" else torch.float32
+    tr = st.step(wl.nt, torch.tensor(wl.wavelets(np.float64), dtype=tdt, device="cuda"), use_graph=True)
+    e = rel_l2_per_trace(tr.double().cpu().numpy()[0], ref)
+    print(f"[1d {name} {prec}] per-trace rel-L2: max {e.max():.2e} median {np.median(e):.2e}")
+    assert e.max() < (1e-9 if prec == "f64" else 1e-4)
+
+
+def test_1d_method_rejects_rigid_and_first_order():
+    import paper_2309_03600_amd as ib
+    wl = W.small2d(M=8, surface="rigid", nt=10)
+    for kw in (dict(surface="rigid"), dict(surface="free", form="pv1")):
+        with pytest.raises(RuntimeError, match="1D extrapolation"):
+            ib.ib_build_weights(wl.heights, wl.h, wl.shape, space_order=8, method="1d", **kw)
+
+
+def _sinusoid(h, M=4, nt=None):
+    """The paper's comparison set-up in 2D: a free surface over a sinusoidal hill (100 m
+    amplitude, 1000 m wavelength, mean depth 400 m), c = 2.5 km/s, Ricker 8 Hz 500 m below
+    the crest line, receivers on nodes 150 m below the mean surface."""
+    import math
+    nx, nz = int(round(2000.0 / h)), int(round(1500.0 / h))
+    x = np.arange(nx) * h
+    H = 400.0 + 100.0 * np.sin(2 * math.pi * x / 1000.0)
+    vel = np.full((nz, nx), 2500.0)
+    dt = 0.5 * 2 * 10.0 / (2500.0 * math.sqrt(2 * 16.0 / 3.0)) * (h / 10.0)
+    nt = nt if nt is not None else int(round(0.7 / dt))
+    src = np.array([[1000.0, 900.0]])
+    rec = np.array([[xr, 550.0] for xr in np.arange(100.0, 1901.0, 50.0)])
+    return W.Workload(f"sinusoid-{h}", 2, (nx, nz), h, M, "free", H, vel, dt, nt, 8.0, src, rec)
+
+
+def _traces(wl, method):
+    import torch
+
+    import paper_2309_03600_amd as ib
+    w = ib.ib_build_weights(wl.heights, wl.h, wl.shape, space_order=wl.M, surface="free", eta=0.5, method=method)
+    st = ib.ib_state_create(w, wl.vel, wl.dt, wl.src, wl.rec, precision="f64")
+    return st.step(wl.nt, torch.tensor(wl.wavelets(np.float64), device="cuda"), use_graph=True).cpu().numpy()[0]
+
+
+def test_nd_and_1d_tables_on_the_sinusoidal_hill():
+    """The paper's comparison: both tables give nearly the same wavefield.  Each is compared
+    with the N-D table on a grid twice as fine (the same receivers, every other step)."""
+    coarse = _sinusoid(10.0)
+    fine = _sinusoid(5.0, nt=2 * coarse.nt)
+    ref = _traces(fine, "nd")[1::2]
+    nd, od = _traces(coarse, "nd"), _traces(coarse, "1d")
+    e_nd = np.linalg.norm(nd - ref) / np.linalg.norm(ref)
+    e_1d = np.linalg.norm(od - ref) / np.linalg.norm(ref)
+    d = np.linalg.norm(od - nd) / np.linalg.norm(nd)
+    print(f"[1d vs nd, sinusoid, h = 10 m, M = 4] error vs h = 5 m N-D: N-D {e_nd:.3e}, 1D {e_1d:.3e}; "
+          f"1D - N-D {d:.3e}", flush=True)
+    assert e_nd < 0.05 and e_1d < 0.05
+    assert d < 0.05
+
+
+def _leapfrog_growth(L, inter, K):
+    """Largest modulus of the undamped leapfrog's amplification factors g (roots of
+    g^2 - (2 + lambda) g + 1 = 0) over the eigenvalues lambda of K L on the interior."""
+    ev = np.linalg.eigvals(K * L[np.ix_(inter, inter)])
+    b = 2.0 + ev
+    disc = np.sqrt(b * b - 4.0 + 0j)
+    return max(np.abs((b + disc) / 2).max(), np.abs((b - disc) / 2).max())
+
+
+@pytest.mark.parametrize("M", [4, 8])
+def test_long_run_growth_matches_the_oracle_spectrum(M):
+    """Stability comparison of the two tables.  On a curved surface the modified operator is
+    not symmetric; its complex eigenvalues give the undamped leapfrog amplification factors
+    slightly above one.  The growth rate the GPU shows over a long undamped run from a
+    random field must be the one the oracle's spectrum predicts, for both tables."""
+    import math
+
+    import torch
+
+    import paper_2309_03600_amd as ib
+    from oracle import mulder1d
+    h, c = 10.0, 2500.0
+    nx, nz = 64, 64
+    H = 350.0 + 100.0 * np.sin(2 * math.pi * np.arange(nx) * h / 640.0)
+    dt = 0.5 * 2 * h / (c * math.sqrt(2 * {4: 16.0 / 3.0, 8: 6.501587301587301}[M]))
+    K = (c * dt / h) ** 2
+    wl = W.Workload("sinusoid-small", 2, (nx, nz), h, M, "free", H, np.full((nz, nx), c), dt, 20000, 8.0,
+                    np.array([[320.0, 550.0]]), np.zeros((0, 2)))
+    m = model_for(wl)
+    inter = m.geom.interior_grid().ravel()
+    for method in ("nd", "1d"):
+        L = (mulder1d.assemble_laplacian_1d(m) if method == "1d" else simulation(wl, m, solve_points(m))[1]).toarray()
+        g = _leapfrog_growth(L, inter, K)
+        w = ib.ib_build_weights(H, h, (nx, nz), space_order=M, surface="free", eta=0.5, method=method)
+        st = ib.ib_state_create(w, wl.vel, dt, wl.src, wl.rec, precision="f64")
+        rng = np.random.default_rng(5)
+        u = torch.tensor(np.where(inter.reshape(nz, nx), rng.standard_normal((nz, nx)), 0.0), device="cuda")
+        st.field(0, 0, u)
+        st.field(1, 0, u)
+        wav = torch.zeros((1, 20001), dtype=torch.float64, device="cuda")
+        norms = []
+        for _ in range(20):
+            st.step(1000, wav, use_graph=True)
+            norms.append(float(st.field(0, 0).norm()))
+        measured = (norms[-1] / norms[-6]) ** (1.0 / 5000.0)
+        print(f"[stability M={M} {method}] oracle max|g| - 1 = {g - 1:.3e}, GPU growth per step - 1 = "
+              f"{measured - 1:.3e}; norm every 1000 steps {['%.3g' % v for v in norms]}", flush=True)
+        if g - 1.0 > 1e-6:
+            # the dominant mode has taken over: the measured rate is the predicted one
+            assert abs(math.log(measured) / math.log(g) - 1.0) < 0.1
+        else:
+            assert norms[-1] < 10.0 * norms[0]
