@@ -21,6 +21,8 @@ stepper    sparse modified Laplacian and the damped leapfrog time stepper
 analytic   method-of-images solutions for flat free / rigid surfaces
 adjoint    discrete adjoint of the stepper and the velocity gradient
 staggered  first-order pressure-velocity form on a staggered grid
+mulder1d   per-axis 1D extrapolation (the reduction to 1D)
+forcing    inhomogeneous boundary conditions (the forcing columns of B A^+)
 
 Parity status: every function is pinned by tests under ``tests/test_oracle_*.py``
 except where a docstring says "parity unpinned".

@@ -145,8 +145,13 @@ def multilinear(pos, shape):
 class Simulation:
     """FP64 stepping of one shot of the second-order form."""
 
-    def __init__(self, model, L, vel, dt, src_pos, rec_pos, damp_width=0, damp_R=1e-3):
+    def __init__(self, model, L, vel, dt, src_pos, rec_pos, damp_width=0, damp_R=1e-3, forcing=None):
+        """forcing: optional (B, s) of inhomogeneous boundary conditions, B[q] the affine
+        part of the grid-unit Laplacian per condition (``forcing.forcing_vectors``) and
+        s[q][n] its time function; step n adds K * sum_q B[q] s[q][n] to K (L p^n)."""
         self.model = model
+        self.forcing = forcing
+        self.n = 0
         self.shape = model.shape
         self.d = model.d
         self.N = int(np.prod(self.shape))
@@ -168,8 +173,13 @@ class Simulation:
         for ws, a in zip(self.src, wavelets_n):
             for j, w in ws:
                 f[j] += a * w / self.h ** self.d
-        new = (2.0 * self.u - (1.0 - self.s) * self.um + self.K * (self.L @ self.u)
+        Lu = self.L @ self.u
+        if self.forcing is not None:
+            B, sq = self.forcing
+            Lu = Lu + np.asarray(B).T @ np.asarray(sq)[:, self.n]
+        new = (2.0 * self.u - (1.0 - self.s) * self.um + self.K * Lu
                + self.dt ** 2 * f) / (1.0 + self.s)
+        self.n += 1
         self.um = self.u
         self.u = new
         return np.array([sum(w * new[j] for j, w in r) for r in self.rec])

@@ -12,7 +12,8 @@ Paper sections followed, in order:
     the interior stencil needs are the projection B delta with delta = A^+ [...]; the
     modified stencil is w_i . f(X_i) + w_e . B A^+ [f(X); g].  With g = 0 the forcing
     columns drop out, so the data weights are y = (A^+)^T c with c = B^T w_e
-    = sum_e w_e a(x_e - x_0).
+    = sum_e w_e a(x_e - x_0); the entries of the same y on the boundary-condition rows
+    are the weights of the values g (kept for inhomogeneous conditions).
   * "Application to the 2nd-Order Acoustic Wave Equation": one modified second
     derivative per axis; they share the one extrapolant of their stencil centre, so
     the modified Laplacian row is the standard cross stencil plus sum_j y_j f(x_j)
@@ -196,9 +197,16 @@ class IBModel:
                 if rank == nt:
                     c = self.extrapolation_target(i, Mb)
                     y = np.linalg.pinv(A).T @ c
+                    # entries of y on the boundary-condition rows: the forcing columns
+                    # of B A^+ (they multiply the condition values g, zero in the
+                    # homogeneous case), one row per (boundary point, condition)
+                    sel, _ = self.boundary_points_within(i, r)
+                    nbc = A.shape[0] - len(data)
+                    nops = nbc // len(sel) if len(sel) else 0
                     return dict(radius_step=k, order=Mb, radius=r, offsets=data,
                                 weights=y[:len(data)], rank=rank, cond=s.max() / s.min(),
-                                m=A.shape[0], sigma_ratio=s.min() / s.max(), tol_ratio=tol / s.max())
+                                m=A.shape[0], sigma_ratio=s.min() / s.max(), tol_ratio=tol / s.max(),
+                                bc_points=sel, bc_weights=y[len(data):].reshape(len(sel), nops))
         raise RuntimeError(f"IB point {tuple(i)} unconstrained after radius growth and order reduction")
 
     def laplacian_row(self, i, sol=None):

@@ -1,0 +1,205 @@
+"""Pins of the oracle's inhomogeneous boundary conditions (the forcing columns of B A^+).
+
+Polynomial exactness: a polynomial field P of degree <= M_b is in the Taylor basis, so
+when the boundary rows carry P's own condition values the extrapolated exterior values
+are P's and the modified Laplacian row returns the Laplacian of P exactly (the centred
+stencils are exact for degree <= M + 1).  The condition values and the Laplacian are
+computed here with numpy's polynomial calculus, independently of the oracle's Taylor
+rows and operator tables.  A manufactured standing wave then pins the stepper's use of
+the forcing: with the wave's boundary values it follows the exact solution, without them
+it does not."""
+import math
+
+import numpy as np
+import pytest
+from numpy.polynomial import polynomial as Pn
+
+from oracle import fd, forcing, stepper
+from oracle.weights import IBModel
+from paper_2309_03600_amd import workloads as W
+
+
+def _pad_to(D, shape):
+    return np.pad(D, [(0, s - n) for s, n in zip(shape, D.shape)])
+
+
+def _lap(C):
+    return sum(_pad_to(Pn.polyder(C, 2, axis=a), C.shape) for a in range(C.ndim))
+
+
+def _grad_n(C, nvec):
+    return sum(nvec[a] * _pad_to(Pn.polyder(C, 1, axis=a), C.shape) for a in range(C.ndim))
+
+
+def _val(C, u):
+    return Pn.polyval2d(u[0], u[1], C) if C.ndim == 2 else Pn.polyval3d(u[0], u[1], u[2], C)
+
+
+def _condition_poly(C, surface, q, nvec):
+    D = C
+    for _ in range(q):
+        D = _lap(D)
+    return D if surface == "free" else _grad_n(D, nvec)
+
+
+def _random_poly(rng, d, deg):
+    C = rng.standard_normal((deg + 1,) * d)
+    idx = np.indices(C.shape).sum(axis=0)
+    C[idx > deg] = 0.0
+    return C
+
+
+def _check_point(m, i, rng):
+    """(|row(P) + forcing - lap P|, scale, tolerance) for one IB point and a random P."""
+    sol = m.solve_point(i)
+    Mb, d, half = sol["order"], m.d, m.M // 2
+    C = _random_poly(rng, d, Mb)
+    terms = []
+    for n in range(d):                                   # interior cross stencil
+        for k in range(-half, half + 1):
+            e = np.array(i)
+            e[n] += k
+            if m.interior(tuple(e)):
+                off = np.zeros(d)
+                off[n] = k
+                terms.append(m.w2[k + half] * _val(C, off))
+    for o, y in zip(sol["offsets"], sol["weights"]):     # extrapolation: data part
+        terms.append(y * _val(C, o.astype(float)))
+    sel, rel = m.boundary_points_within(i, sol["radius"])
+    relpos = {int(b): r for b, r in zip(sel, rel)}
+    for b, q, v in forcing.forcing_row(sol):             # extrapolation: condition values
+        terms.append(v * _val(_condition_poly(C, m.surface_kind, q, m.bp_normal[b]), relpos[b]))
+    got = sum(terms)
+    want = _val(_lap(C), np.zeros(d))
+    scale = max(1.0, sum(abs(t) for t in terms))
+    return abs(got - want), scale, max(1e-13, sol["cond"] * 1e-15) * scale
+
+
+@pytest.mark.parametrize("surface", ["free", "rigid"])
+@pytest.mark.parametrize("M", [4, 8])
+def test_rows_with_condition_values_are_exact_on_polynomials_2d(surface, M):
+    wl = W.small2d(M=M, nt=10, hill=60.0, nx=60, nz=60)
+    m = IBModel(wl.heights, wl.h, wl.shape, M=M, surface=surface, eta=wl.eta)
+    rng = np.random.default_rng(11)
+    pts = m.ib_points()
+    for i in pts[:: max(1, len(pts) // 40)]:
+        err, scale, tol = _check_point(m, tuple(int(v) for v in i), rng)
+        assert err <= tol, (tuple(i), err, tol)
+
+
+@pytest.mark.parametrize("surface", ["free", "rigid"])
+def test_rows_with_condition_values_are_exact_on_polynomials_3d(surface):
+    wl = W.small3d(n=16, nz=36, relief=30.0, nt=10, z_top_cells=12)
+    m = IBModel(wl.heights, wl.h, wl.shape, M=4, surface=surface, eta=wl.eta)
+    rng = np.random.default_rng(12)
+    pts = m.ib_points()
+    for i in pts[:: max(1, len(pts) // 12)]:
+        err, scale, tol = _check_point(m, tuple(int(v) for v in i), rng)
+        assert err <= tol, (tuple(i), err, tol)
+
+
+def test_dropping_the_condition_values_breaks_exactness():
+    # the homogeneous rows alone are not exact for a P with non-zero boundary values
+    wl = W.small2d(M=4, nt=10, hill=60.0, nx=60, nz=60)
+    m = IBModel(wl.heights, wl.h, wl.shape, M=4, surface="free", eta=wl.eta)
+    i = tuple(int(v) for v in m.ib_points()[0])
+    sol = m.solve_point(i)
+    C = np.zeros((3, 3))
+    C[0, 0] = 1.0                                      # P = 1: lap P = 0, g_0 = 1
+    row = sum(y for y in sol["weights"]) + sum(m.w2[k + 2] for n in range(2) for k in range(-2, 3)
+                                                if m.interior(tuple(np.array(i) + np.eye(2, dtype=int)[n] * k)))
+    forced = sum(v for b, q, v in forcing.forcing_row(sol) if q == 0)
+    assert abs(row) > 1e-3                               # homogeneous rows see p = 0 at the surface
+    assert abs(row + forced) < 1e-10                     # the forcing restores the constant
+
+
+@pytest.mark.parametrize("surface", ["free", "rigid"])
+def test_forcing_vectors_scale_physical_values(surface):
+    # a depth-only polynomial (periodic laterally) in physical units with h = 10 m:
+    # (L P)_i + B_i = h^2 P''(z_i) at every IB point
+    h = 10.0
+    wl = W.small2d(M=8, nt=10, hill=60.0, nx=60, nz=60, h=h)
+    m = IBModel(wl.heights, h, wl.shape, M=8, surface=surface, eta=wl.eta)
+    sols = stepper.solve_all(m)
+    z0 = 30.0 * h
+    a = np.array([0.3, -1.1, 0.7, 0.25, -0.4])          # p(u) = sum a_k u^k, u = (z - z0) / h
+    nq = forcing.n_conditions(surface, 8)
+    nb = len(m.bp_xb)
+    g = np.zeros((nb, nq))
+    for b in range(nb):
+        ub = (m.bp_xb[b][-1] * h - z0) / h
+        for q in range(nq):
+            o = forcing.order_of(surface, q)
+            dp = Pn.polyval(ub, Pn.polyder(a, o)) if o < len(a) else 0.0
+            g[b, q] = dp / h ** o * (m.bp_normal[b][-1] if surface == "rigid" else 1.0)
+    B = forcing.forcing_vectors(m, sols, g)
+    L = stepper.assemble_laplacian(m, sols)
+    inter = m.geom.interior_grid()
+    nz, nx = inter.shape
+    u = (np.arange(nz) * h - z0) / h
+    Pf = np.where(inter, Pn.polyval(u, a)[:, None] * np.ones((1, nx)), 0.0).ravel()
+    lhs = L @ Pf + B.sum(axis=0)
+    want = np.repeat(Pn.polyval(u, Pn.polyder(a, 2)), nx)
+    for i in m.ib_points():
+        r = int(i[1]) * nx + int(i[0])
+        assert abs(lhs[r] - want[r]) < 1e-8 * max(1.0, abs(want[r])), (tuple(i), lhs[r], want[r])
+
+
+# ---- manufactured standing wave ----------------------------------------------------------
+def standing_wave(nx, h, c):
+    """p = cos(w t) cos(kx x) cos(kz (z - z0)) solves p_tt = c^2 lap p (no source) with
+    w = c |k|; returns (p(x, z, t), free-surface condition values g_q(x_b), w)."""
+    kx = 2 * math.pi * 2 / (nx * h)
+    kz = 2 * math.pi / 300.0
+    z0 = 37.0
+    kk = kx * kx + kz * kz
+    w = c * math.sqrt(kk)
+
+    def p(x, z, t):
+        return math.cos(w * t) * np.cos(kx * x) * np.cos(kz * (z - z0))
+
+    def g(xb, q):
+        return (-kk) ** q * np.cos(kx * xb[..., 0]) * np.cos(kz * (xb[..., -1] - z0))
+
+    return p, g, w
+
+
+def manufactured_error(h, M=4, T=0.04, c=1500.0, with_forcing=True):
+    """Max error over interior nodes above depth 240 m at time ~T (bottom at 400 m, so
+    the zero padding below the box cannot reach them), oracle FP64."""
+    nx, nz = int(round(240.0 / h)), int(round(400.0 / h))
+    x = np.arange(nx) * h
+    H = 100.0 + 25.0 * np.sin(2 * math.pi * x / (nx * h)) + 10.0 * np.cos(6 * math.pi * x / (nx * h))
+    m = IBModel(H, h, (nx, nz), M=M, surface="free", eta=0.5)
+    sols = stepper.solve_all(m)
+    L = stepper.assemble_laplacian(m, sols)
+    dt = 0.1 * fd.critical_dt(h, c, M, 2)
+    nt = int(round(T / dt))
+    p, g, w = standing_wave(nx, h, c)
+    nq = forcing.n_conditions("free", M)
+    xb = m.bp_xb * h
+    G = np.stack([g(xb, q) for q in range(nq)], axis=1)
+    s = np.cos(w * np.arange(nt + 1) * dt)[None, :].repeat(nq, axis=0)
+    B = forcing.forcing_vectors(m, sols, G if with_forcing else 0.0 * G)
+    sim = stepper.Simulation(m, L, np.full((nz, nx), c), dt, [], [], forcing=(B, s))
+    inter = m.geom.interior_grid()
+    X, Z = np.meshgrid(x, np.arange(nz) * h)
+    sim.u = np.where(inter, p(X, Z, 0.0), 0.0).ravel()
+    sim.um = np.where(inter, p(X, Z, -dt), 0.0).ravel()
+    for _ in range(nt):
+        sim.step([])
+    exact = np.where(inter, p(X, Z, nt * dt), 0.0)
+    sel = inter & (Z < 240.0)
+    return np.abs(sim.u.reshape(nz, nx) - exact)[sel].max()
+
+
+def test_manufactured_standing_wave_needs_the_boundary_values():
+    e_forced = manufactured_error(5.0)
+    e_plain = manufactured_error(5.0, with_forcing=False)
+    assert e_forced < 1e-3, e_forced
+    assert e_plain > 30 * e_forced, (e_plain, e_forced)
+
+
+def test_manufactured_standing_wave_converges():
+    e1, e2 = manufactured_error(10.0), manufactured_error(5.0)
+    assert np.log2(e1 / e2) > 2.5, (e1, e2)
