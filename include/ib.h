@@ -90,6 +90,12 @@ typedef struct {
  *                    axis line crosses the surface and the M/2 nearest interior nodes of the
  *                    line farther than eta from it (section "Reduction to 1D"; second-order
  *                    form, free surface).
+ *   keep_bc_weights  1: also keep, per IB point, the weights of the boundary-condition
+ *                    values (the entries of y on the condition rows: the columns of B A^+
+ *                    that multiply g, section "Reconciliation with the Interior Numerical
+ *                    Discretization"), needed for non-zero boundary values
+ *                    (ib_state_set_forcing).  Second-order form, N-D method only.  0: drop
+ *                    them (homogeneous conditions; the paper's examples).
  */
 typedef struct {
   int32_t form;
@@ -102,7 +108,7 @@ typedef struct {
   double rank_rtol;
   double eta_v;
   int32_t method;
-  int32_t reserved;
+  int32_t keep_bc_weights;
 } ib_params;
 
 typedef struct {
@@ -160,6 +166,12 @@ void ib_weights_free(ib_weights *w);
  *   IB_FIELD_WEIGHTS_F64 float64 [sum_nw]: weights of each point in the lattice order
  *                        of its support ball (z, then y, then x), data nodes only.
  *   IB_FIELD_SIGMA       float64 [n_ib]: estimated sigma_min/sigma_max of accepted A.
+ * Built with keep_bc_weights = 1 only:
+ *   IB_FIELD_BC_COUNTS   int32 [n_ib]: condition-value weights of each IB point.
+ *   IB_FIELD_BC_ENTRIES  float64 [sum][3]: boundary point (index into IB_FIELD_BPOINTS),
+ *                        condition q of the hierarchy, weight (grid units: the value of
+ *                        a condition of derivative order o enters as h^o g); IB points in
+ *                        order, each point's entries by boundary point, then q.
  * First-order form only:
  *   IB_FIELD_PV_ROWS     int64 [n_rows][3]: family (n < ndim: d/dx_n p at a v_n node,
  *                        ndim: div v at a p node), memory-order node, number of weights.
@@ -171,7 +183,8 @@ void ib_weights_free(ib_weights *w);
 typedef enum {
   IB_FIELD_NODE_CLASS = 0, IB_FIELD_BPOINTS = 1, IB_FIELD_IB_NODES = 2,
   IB_FIELD_IB_META = 3, IB_FIELD_WEIGHTS_F64 = 4, IB_FIELD_SIGMA = 5,
-  IB_FIELD_PV_ROWS = 6, IB_FIELD_PV_ENTRIES = 7, IB_FIELD_VCLASS = 8
+  IB_FIELD_PV_ROWS = 6, IB_FIELD_PV_ENTRIES = 7, IB_FIELD_VCLASS = 8,
+  IB_FIELD_BC_COUNTS = 9, IB_FIELD_BC_ENTRIES = 10
 } ib_field;
 ib_status ib_weights_copy(const ib_weights *w, int32_t field, void *dst_host, int64_t dst_bytes);
 
@@ -232,7 +245,8 @@ ib_status ib_forward(ib_state *st, int32_t nt, const void *wavelet_dev, int64_t 
  * Each checkpoint segment is recomputed forward and kept (ckpt_every fields) while the
  * adjoint steps back through it; the adjoint of the IB rows uses a transposed stencil
  * table (per receiving node) built on the first call.
- * Errors: IB_ERR_STATE without a previous ib_forward; IB_ERR_ARG for the first-order form
+ * Errors: IB_ERR_STATE without a previous ib_forward or with boundary values set
+ *   (ib_state_set_forcing); IB_ERR_ARG for the first-order form
  *   (ib_forward and ib_adjoint cover the second-order form only). */
 ib_status ib_adjoint(ib_state *st, const void *residual_dev, const void *wavelet_dev, int64_t wavelet_stride,
                      double *grad_dev, void *stream);
@@ -245,6 +259,28 @@ ib_status ib_adjoint(ib_state *st, const void *residual_dev, const void *wavelet
 ib_status ib_state_field(ib_state *st, int32_t which, int32_t shot, void *dev_buf, int32_t direction,
                          void *stream);
 int64_t ib_state_step_count(const ib_state *st);
+
+/* Non-zero boundary values (inhomogeneous conditions; section "Approximating Boundary
+ * Conditions" lets each condition equal a value g(x_b), and section "Reconciliation with
+ * the Interior Numerical Discretization" keeps the columns of B A^+ that multiply it).
+ * Second-order form, weights built with keep_bc_weights = 1.
+ *   The conditions of the surface get right-hand sides, condition q of the hierarchy
+ *     free:  lap^q p (x_b) = g_q(x_b) s_q(t),   rigid:  n.grad(lap^q p)(x_b) = g_q(x_b) s_q(t),
+ *   so step n adds K (sum_q s_q(t_n) sum_b v_ibq h^{o_q} g_q(x_b)) / (1 + s) at each IB
+ *   point i (o_q = 2q free, 2q + 1 rigid; v the condition-value weights).
+ *   g_dev:   device float64 [n_boundary_points][nq] (IB_FIELD_BPOINTS order), physical
+ *            units (Pa / m^{o_q}).  Borrowed: contracted with the weights during the call.
+ *   s_host:  host float64 [nq][s_len]: step t uses s_q[t] (t = the state's step counter);
+ *            copied into the state.
+ *   nq:      1 .. conditions at full order (M/2 + 1 free, (M - 1)/2 + 1 rigid); conditions
+ *            beyond nq stay homogeneous.
+ *   g_dev = NULL clears the forcing.  The same values drive every shot.  ib_step then
+ *   needs s_len >= step counter + nsteps; ib_forward and ib_adjoint refuse a forced state
+ *   (the boundary values are not differentiated).
+ * Errors: IB_ERR_ARG (nq, s_len, null s_host), IB_ERR_STATE (first-order form, weights
+ *   without condition-value weights), IB_ERR_OOM, IB_ERR_HIP. */
+ib_status ib_state_set_forcing(ib_state *st, const double *g_dev, int32_t nq, const double *s_host, int64_t s_len,
+                               void *stream);
 
 /* Measurement aid: enqueue ``count`` launches of one kernel of the step on ``stream``
  * with the current buffers (which = 0: interior stencil, 1: IB patch), rotating the

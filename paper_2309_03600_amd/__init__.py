@@ -37,11 +37,12 @@ def abi_version():
 class IBWeights:
     """Handle of a built stencil table (library-owned device memory)."""
 
-    def __init__(self, handle, ndim, shape, form="p2"):
+    def __init__(self, handle, ndim, shape, form="p2", keep_bc_weights=False):
         self._h = handle
         self.ndim = ndim
         self.shape = shape
         self.form = form
+        self.keep_bc_weights = keep_bc_weights
 
     def stats(self):
         st = _lib.ib_stats()
@@ -69,7 +70,7 @@ class IBWeights:
                 vclass=self.copy(_lib.FIELD_VCLASS, np.uint8, self.ndim * N).reshape(self.ndim, N),
                 stats=s,
             )
-        return dict(
+        out = dict(
             node_class=self.copy(_lib.FIELD_NODE_CLASS, np.uint8, N),
             bpoints=self.copy(_lib.FIELD_BPOINTS, np.float64, nb * 7).reshape(nb, 7),
             ib_nodes=self.copy(_lib.FIELD_IB_NODES, np.int64, nib),
@@ -78,6 +79,11 @@ class IBWeights:
             sigma=self.copy(_lib.FIELD_SIGMA, np.float64, nib),
             stats=s,
         )
+        if self.keep_bc_weights:
+            cnt = self.copy(_lib.FIELD_BC_COUNTS, np.int32, nib)
+            out["bc_counts"] = cnt
+            out["bc_entries"] = self.copy(_lib.FIELD_BC_ENTRIES, np.float64, int(cnt.sum()) * 3).reshape(-1, 3)
+        return out
 
     def close(self):
         if self._h:
@@ -93,13 +99,14 @@ class IBWeights:
 
 def ib_build_weights(heights, h, shape, space_order=8, surface="free", eta=0.5, max_radius_steps=3,
                      min_basis_order=None, physical_below=True, rank_rtol=0.0, form="p2", eta_v=0.0, method="nd",
-                     stream=None):
+                     keep_bc_weights=False, stream=None):
     """Build the IB stencils for a heightfield (torch float64 device tensor or array, metres).
 
     ``form`` "p2" is the second-order pressure form, "pv1" the first-order pressure-velocity
     form on a staggered grid.  ``method`` "nd" builds the N-D extrapolants of the paper,
     "1d" the per-axis 1D extrapolations of its reduction to 1D (second-order form, free
-    surface).
+    surface).  ``keep_bc_weights`` also keeps the weights of the boundary-condition values
+    (needed by ``IBState.set_forcing``; second-order form, N-D method).
     """
     if form not in ("p2", "pv1"):
         raise ValueError("form must be 'p2' or 'pv1'")
@@ -125,10 +132,11 @@ def ib_build_weights(heights, h, shape, space_order=8, surface="free", eta=0.5, 
     p.physical_below = 1 if physical_below else 0
     p.eta = float(eta)
     p.rank_rtol = float(rank_rtol)
+    p.keep_bc_weights = 1 if keep_bc_weights else 0
     out = C.c_void_p()
     _lib.check(_lib.load().ib_build_weights(C.byref(g), C.c_void_p(Ht.data_ptr()), C.byref(p), _stream(stream),
                                             C.byref(out)))
-    return IBWeights(out, ndim, tuple(int(v) for v in shape), form)
+    return IBWeights(out, ndim, tuple(int(v) for v in shape), form, bool(keep_bc_weights))
 
 
 class IBState:
@@ -198,6 +206,22 @@ class IBState:
         _lib.check(_lib.load().ib_adjoint(self._h, C.c_void_p(res.data_ptr()), C.c_void_p(wavelet.data_ptr()),
                                           int(wavelet.shape[1]), C.c_void_p(grad.data_ptr()), _stream(stream)))
         return grad
+
+    def set_forcing(self, g, s, stream=None):
+        """Non-zero boundary values g_q(x_b) s_q(t): g [n_boundary_points][nq] (float64, physical
+        units, boundary points in the table's order), s [nq][len] host array of time functions;
+        ``g=None`` restores homogeneous conditions."""
+        torch = _torch()
+        if g is None:
+            _lib.check(_lib.load().ib_state_set_forcing(self._h, C.c_void_p(), 0, C.c_void_p(), 0, _stream(stream)))
+            return
+        gt = torch.as_tensor(np.ascontiguousarray(g, dtype=np.float64) if not torch.is_tensor(g) else g,
+                             dtype=torch.float64, device="cuda").contiguous()
+        sh = np.ascontiguousarray(np.atleast_2d(s), dtype=np.float64)
+        assert gt.dim() == 2 and sh.shape[0] == gt.shape[1]
+        _lib.check(_lib.load().ib_state_set_forcing(self._h, C.c_void_p(gt.data_ptr()), int(gt.shape[1]),
+                                                    sh.ctypes.data_as(C.c_void_p), int(sh.shape[1]),
+                                                    _stream(stream)))
 
     def run_kernel(self, which, count, stream=None):
         """Enqueue ``count`` launches of one step kernel (0 interior, 1 patch) for timing."""

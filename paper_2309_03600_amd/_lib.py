@@ -16,6 +16,7 @@ IB_METHOD_ND = 0
 IB_METHOD_1D = 1
 FIELD_NODE_CLASS, FIELD_BPOINTS, FIELD_IB_NODES, FIELD_IB_META, FIELD_WEIGHTS_F64, FIELD_SIGMA = range(6)
 FIELD_PV_ROWS, FIELD_PV_ENTRIES, FIELD_VCLASS = 6, 7, 8
+FIELD_BC_COUNTS, FIELD_BC_ENTRIES = 9, 10
 
 
 class ib_grid(C.Structure):
@@ -26,7 +27,7 @@ class ib_params(C.Structure):
     _fields_ = [("form", C.c_int32), ("surface", C.c_int32), ("space_order", C.c_int32),
                 ("max_radius_steps", C.c_int32), ("min_basis_order", C.c_int32), ("physical_below", C.c_int32),
                 ("eta", C.c_double), ("rank_rtol", C.c_double), ("eta_v", C.c_double), ("method", C.c_int32),
-                ("reserved", C.c_int32)]
+                ("keep_bc_weights", C.c_int32)]
 
 
 class ib_stats(C.Structure):
@@ -56,6 +57,7 @@ EXPORTS = {
     "ib_state_step_count": (C.c_int64, [C.c_void_p]),
     "ib_state_set_tuning": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_int32]),
     "ib_state_run_kernel": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_void_p]),
+    "ib_state_set_forcing": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p, C.c_int64, C.c_void_p]),
 }
 
 _lib = None

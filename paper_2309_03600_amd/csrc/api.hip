@@ -79,6 +79,11 @@ struct ib_state {
   int64_t *rnode = nullptr, *roff = nullptr;
   int32_t *rrec = nullptr;
   void *jD = nullptr, *ibvals = nullptr, *rD = nullptr, *rwt = nullptr;
+  // non-zero boundary values (ib_state_set_forcing): F [nib][fnq] and the time functions
+  // [fnq][flen], state precision; fF == nullptr: homogeneous conditions
+  void *fF = nullptr, *fs = nullptr;
+  int fnq = 0;
+  int64_t flen = 0;
 };
 
 namespace {
@@ -128,6 +133,11 @@ StepArgs make_args(ib_state *st, const void *wavelet, int64_t wstride, void *tra
   a.rw = st->rw;
   a.traces = traces;
   a.nsteps = nsteps;
+  a.ib_xyz = w->ib_xyz;
+  a.fF = st->fF;
+  a.fs = st->fs;
+  a.fnq = st->fnq;
+  a.fstride = st->flen;
   return a;
 }
 
@@ -287,6 +297,29 @@ ib_status autotune_interior(ib_state *S, hipStream_t st) {
 
 }  // namespace
 
+namespace {
+struct HPow {
+  double v[8];
+};
+
+// F[i][q] = scale_i h^{o_q} sum over the point's entries of condition q of weight * g[b][q]
+template <typename T>
+__global__ void k_forcing_setup(int64_t nib, const int64_t *off, const int32_t *cnt, const int32_t *idx,
+                                const double *wv, const double *g, int nq, HPow hp, const T *scale, T *F) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nib) return;
+  double acc[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  const int64_t e0 = off[i], e1 = off[i] + cnt[i];
+  for (int64_t e = e0; e < e1; ++e) {
+    const int v = idx[e];
+    const int b = v >> 3, q = v & 7;
+    if (q < nq) acc[q] += wv[e] * g[(int64_t)b * nq + q];
+  }
+  const double sc = (double)scale[i];
+  for (int q = 0; q < nq; ++q) F[i * nq + q] = (T)(sc * hp.v[q] * acc[q]);
+}
+}  // namespace
+
 extern "C" {
 
 int32_t ib_abi_version(void) { return IB_ABI_VERSION; }
@@ -318,6 +351,14 @@ ib_status ib_build_weights(const ib_grid *g, const double *height_dev, const ib_
   }
   if (p->method != IB_METHOD_ND && p->method != IB_METHOD_1D) {
     set_error("unsupported method %d", p->method);
+    return IB_ERR_ARG;
+  }
+  if (p->keep_bc_weights != 0 && p->keep_bc_weights != 1) {
+    set_error("keep_bc_weights must be 0 or 1 (got %d)", p->keep_bc_weights);
+    return IB_ERR_ARG;
+  }
+  if (p->keep_bc_weights && (p->form != IB_FORM_P2 || p->method != IB_METHOD_ND)) {
+    set_error("condition-value weights are kept for the second-order form with the N-D method only");
     return IB_ERR_ARG;
   }
   if (p->method == IB_METHOD_1D && (p->form != IB_FORM_P2 || p->surface != IB_SURF_FREE)) {
@@ -486,6 +527,7 @@ void ib_weights_free(ib_weights *w) {
   dfree(w->dense_off);
   for (int n = 0; n < 3; ++n) dfree(w->vcls[n]);
   dfree(w->adj_jnode), dfree(w->adj_joff), dfree(w->adj_jsrc), dfree(w->adj_jw32), dfree(w->adj_jw64);
+  dfree(w->bc_off), dfree(w->bc_cnt), dfree(w->bc_idx), dfree(w->bc_w);
   delete w;
 }
 
@@ -533,6 +575,43 @@ ib_status ib_weights_copy(const ib_weights *w, int32_t field, void *dst, int64_t
         for (int n = 0; n < w->ndim; ++n)
           IB_HIP(hipMemcpy((uint8_t *)dst + n * w->N, w->vcls[n], w->N, hipMemcpyDeviceToHost));
       }
+      return IB_OK;
+    }
+    case IB_FIELD_BC_COUNTS:
+    case IB_FIELD_BC_ENTRIES: {
+      if (!w->bc_off) {
+        set_error("ib_weights_copy: the table was built without condition-value weights (keep_bc_weights = 0)");
+        return IB_ERR_STATE;
+      }
+      std::vector<int64_t> off(w->nib);
+      std::vector<int32_t> cnt(w->nib);
+      if (w->nib) {
+        IB_HIP(hipMemcpy(off.data(), w->bc_off, w->nib * 8, hipMemcpyDeviceToHost));
+        IB_HIP(hipMemcpy(cnt.data(), w->bc_cnt, w->nib * 4, hipMemcpyDeviceToHost));
+      }
+      need = (field == IB_FIELD_BC_COUNTS) ? w->nib * 4 : w->nbc * 24;
+      if (bytes < need) {
+        set_error("ib_weights_copy: destination too small (%lld < %lld)", (long long)bytes, (long long)need);
+        return IB_ERR_ARG;
+      }
+      if (field == IB_FIELD_BC_COUNTS) {
+        std::memcpy(dst, cnt.data(), w->nib * 4);
+        return IB_OK;
+      }
+      std::vector<int32_t> idx(w->nbc);
+      std::vector<double> wv(w->nbc);
+      if (w->nbc) {
+        IB_HIP(hipMemcpy(idx.data(), w->bc_idx, w->nbc * 4, hipMemcpyDeviceToHost));
+        IB_HIP(hipMemcpy(wv.data(), w->bc_w, w->nbc * 8, hipMemcpyDeviceToHost));
+      }
+      double *o = (double *)dst;
+      int64_t k = 0;
+      for (int64_t i = 0; i < w->nib; ++i)
+        for (int64_t e = off[i]; e < off[i] + cnt[i]; ++e, ++k) {
+          o[k * 3] = (double)(idx[e] >> 3);
+          o[k * 3 + 1] = (double)(idx[e] & 7);
+          o[k * 3 + 2] = wv[e];
+        }
       return IB_OK;
     }
     case IB_FIELD_BPOINTS: {
@@ -888,6 +967,7 @@ void ib_state_free(ib_state *S) {
   dfree(S->g_scale), dfree(S->g_w), dfree(S->d_scale), dfree(S->d_w);
   dfree(S->rnode), dfree(S->roff), dfree(S->rrec);
   dfree(S->jD), dfree(S->ibvals), dfree(S->rD), dfree(S->rwt);
+  dfree(S->fF), dfree(S->fs);
   delete S;
 }
 
@@ -1074,6 +1154,11 @@ ib_status ib_step(ib_state *S, int32_t nsteps, const void *wavelet, int64_t wstr
               (long long)(S->t + nsteps));
     return IB_ERR_ARG;
   }
+  if (S->fF && S->t + nsteps > S->flen) {
+    set_error("ib_step: boundary-value time functions have %lld samples, steps up to %lld requested",
+              (long long)S->flen, (long long)(S->t + nsteps));
+    return IB_ERR_ARG;
+  }
   return run_steps(S, nsteps, wavelet, wstride, traces, nsteps, S->t, use_graph != 0, (hipStream_t)stream);
 }
 
@@ -1083,6 +1168,10 @@ ib_status ib_forward(ib_state *S, int32_t nt, const void *wavelet, int64_t wstri
       S->form != IB_FORM_P2) {
     set_error("ib_forward: invalid argument");
     return IB_ERR_ARG;
+  }
+  if (S->fF) {
+    set_error("ib_forward: the state has non-zero boundary values (not differentiated by ib_adjoint)");
+    return IB_ERR_STATE;
   }
   hipStream_t st = (hipStream_t)stream;
   const size_t fbytes = (size_t)S->vol * S->nshots * S->esz;
@@ -1119,6 +1208,10 @@ ib_status ib_adjoint(ib_state *S, const void *residual, const void *wavelet, int
   }
   if (S->ck_count == 0) {
     set_error("ib_adjoint: no checkpoints (call ib_forward first)");
+    return IB_ERR_STATE;
+  }
+  if (S->fF) {
+    set_error("ib_adjoint: the state has non-zero boundary values (not differentiated)");
     return IB_ERR_STATE;
   }
   hipStream_t st = (hipStream_t)stream;
@@ -1233,6 +1326,83 @@ ib_status ib_state_run_kernel(ib_state *S, int32_t which, int32_t count, void *s
     }
   }
   IB_HIP(hipGetLastError());
+  return IB_OK;
+}
+
+
+ib_status ib_state_set_forcing(ib_state *S, const double *g, int32_t nq, const double *s_host, int64_t s_len,
+                               void *stream) {
+  if (!S) {
+    set_error("ib_state_set_forcing: null state");
+    return IB_ERR_ARG;
+  }
+  const ib_weights *w = S->w;
+  if (S->form != IB_FORM_P2) {
+    set_error("ib_state_set_forcing: boundary values are supported for the second-order form only");
+    return IB_ERR_STATE;
+  }
+  hipStream_t st = (hipStream_t)stream;
+  // the captured graph holds the old pointers
+  if (S->gexec) {
+    (void)hipGraphExecDestroy(S->gexec);
+    (void)hipGraphDestroy(S->graph);
+    S->gexec = nullptr;
+    S->graph = nullptr;
+  }
+  if (!g) {
+    IB_HIP(hipStreamSynchronize(st));
+    dfree(S->fF), dfree(S->fs);
+    S->fF = S->fs = nullptr;
+    S->fnq = 0;
+    S->flen = 0;
+    return IB_OK;
+  }
+  if (!w->bc_off) {
+    set_error("ib_state_set_forcing: the weights were built without condition-value weights (keep_bc_weights = 0)");
+    return IB_ERR_STATE;
+  }
+  if (nq < 1 || nq > w->bc_nq || !s_host || s_len < 1) {
+    set_error("ib_state_set_forcing: need 1 <= nq <= %d, a time function and s_len >= 1", w->bc_nq);
+    return IB_ERR_ARG;
+  }
+  IB_HIP(hipStreamSynchronize(st));
+  dfree(S->fF), dfree(S->fs);
+  S->fF = S->fs = nullptr;
+  S->fnq = 0;
+  S->flen = 0;
+  ib_status s;
+  void *F = nullptr, *fs = nullptr;
+  if ((s = dalloc(&F, (size_t)std::max<int64_t>(w->nib, 1) * nq * S->esz)) ||
+      (s = dalloc(&fs, (size_t)nq * s_len * S->esz))) {
+    dfree(F);
+    return s;
+  }
+  std::vector<char> hs((size_t)nq * s_len * S->esz);
+  for (int64_t k = 0; k < (int64_t)nq * s_len; ++k) {
+    if (S->prec == IB_F32)
+      ((float *)hs.data())[k] = (float)s_host[k];
+    else
+      ((double *)hs.data())[k] = s_host[k];
+  }
+  IB_HIP(hipMemcpy(fs, hs.data(), hs.size(), hipMemcpyHostToDevice));
+  HPow hp{};
+  const bool rigid = w->prm.surface == IB_SURF_RIGID;
+  for (int q = 0; q < 8; ++q) hp.v[q] = std::pow(w->h, rigid ? 2 * q + 1 : 2 * q);
+  if (w->nib) {
+    const unsigned nb = (unsigned)((w->nib + 255) / 256);
+    if (S->prec == IB_F32)
+      hipLaunchKernelGGL(k_forcing_setup<float>, dim3(nb), dim3(256), 0, st, w->nib, w->bc_off, w->bc_cnt, w->bc_idx,
+                         w->bc_w, g, nq, hp, (const float *)S->scale, (float *)F);
+    else
+      hipLaunchKernelGGL(k_forcing_setup<double>, dim3(nb), dim3(256), 0, st, w->nib, w->bc_off, w->bc_cnt,
+                         w->bc_idx, w->bc_w, g, nq, hp, (const double *)S->scale, (double *)F);
+    IB_HIP(hipGetLastError());
+  }
+  IB_HIP(hipStreamSynchronize(st));
+  S->fF = F;
+  S->fs = fs;
+  S->fnq = nq;
+  S->flen = s_len;
   return IB_OK;
 }
 

@@ -152,4 +152,13 @@ struct ib_weights {
   uint32_t *adj_jnode = nullptr, *adj_joff = nullptr, *adj_jsrc = nullptr;
   float *adj_jw32 = nullptr;
   double *adj_jw64 = nullptr;
+  // weights of the boundary-condition values (kept on request, second-order form): the
+  // entries of IB point i are bc_off[i] .. bc_off[i] + bc_cnt[i] - 1, each
+  // (boundary point << 3 | condition q) with its FP64 weight (grid units)
+  int64_t nbc = 0;
+  int bc_nq = 0;                   // conditions of the hierarchy at full order
+  int64_t *bc_off = nullptr;
+  int32_t *bc_cnt = nullptr;
+  int32_t *bc_idx = nullptr;
+  double *bc_w = nullptr;
 };

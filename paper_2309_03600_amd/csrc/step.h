@@ -49,6 +49,13 @@ struct StepArgs {
   const void *rw;
   void *traces;
   int64_t nsteps;
+  // non-zero boundary values (null: homogeneous conditions): per IB point the scaled
+  // contraction F[i][q] of its condition-value weights with g_q, and the time functions
+  const int16_t *ib_xyz;
+  const void *fF;       // [nib][fnq], state precision
+  const void *fs;       // [fnq][fstride], state precision
+  int fnq;
+  int64_t fstride;
 };
 
 void enqueue_step(const StepArgs &a, hipStream_t st);

@@ -937,6 +937,22 @@ __global__ void k_sample(const T *unew, const int64_t *ridx, const T *rw, int nr
   traces[((size_t)s * nsteps + tl) * nrec + r] = v;
 }
 
+// ---- boundary values ----------------------------------------------------------------
+// Inhomogeneous conditions: p^{n+1}_i += sum_q F[i][q] s_q(t_n) at every IB point, F
+// holding K_i / (1 + s_i) times the point's condition-value weights contracted with g_q.
+// Runs before the source injection advances the step counter.
+template <typename T>
+__global__ void k_ib_forcing(T *unew, const int16_t *xyz, const T *F, const T *fs, int nq, int64_t fstride,
+                             int64_t nib, int ny, int64_t pitch, int64_t vol, int nshots, const int64_t *tcount) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nib) return;
+  const int64_t t = tcount[0];
+  T v = T(0);
+  for (int q = 0; q < nq; ++q) v += F[i * nq + q] * fs[(size_t)q * fstride + t];
+  const int64_t idx = ((int64_t)xyz[i * 4 + 2] * ny + xyz[i * 4 + 1]) * pitch + xyz[i * 4];
+  for (int s = 0; s < nshots; ++s) unew[(size_t)s * vol + idx] += v;
+}
+
 // ---- launch helpers ----------------------------------------------------------------
 template <typename T>
 static StencilW<T> stencil_weights(int M) {
@@ -1063,6 +1079,10 @@ template <typename T>
 static void launch_step(const StepArgs &a, hipStream_t st) {
   launch_interior<T>(a, st);
   launch_patch<T>(a, st);
+  if (a.fF && a.nib > 0)
+    hipLaunchKernelGGL(k_ib_forcing<T>, dim3((unsigned)((a.nib + 255) / 256)), dim3(256), 0, st, (T *)a.um, a.ib_xyz,
+                       (const T *)a.fF, (const T *)a.fs, a.fnq, a.fstride, a.nib, a.ny, a.pitch, a.vol, a.nshots,
+                       (const int64_t *)a.tcount);
   launch_io<T>(a, (T *)a.um, st);
 }
 

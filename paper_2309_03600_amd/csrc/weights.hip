@@ -72,7 +72,7 @@ struct SolveArgs {
   // per-slot scratch
   int32_t *desc;
   int desc_stride;
-  double *bprel;           // [slot][maxbp][6]
+  double *bprel;           // [slot][maxbp][7]: relative position, normal, global index
   int maxbp;
   // outputs indexed by position in ``pending`` (+ base)
   int out_base;
@@ -81,6 +81,12 @@ struct SolveArgs {
   int32_t *status;         // [pos]: 1 accepted, 0 rank deficient, -1 overflow
   int32_t *ndata;          // [pos]
   double *sigma;           // [pos] sigma_min / sigma_max
+  // optional (family 0): entries of y on the boundary-condition rows, the weights of
+  // the condition values g in the modified row (null: not produced)
+  // (indexed by the position in this launch, not offset by out_base)
+  int32_t *fbp;            // [pos][maxbp] global index of each support boundary point
+  double *fwout;           // [pos][maxbp][nops]
+  int32_t *fnbp;           // [pos] support boundary points
 };
 
 __device__ __forceinline__ int wrapd(int i, int n) {
@@ -151,7 +157,7 @@ __global__ void k_solve(SolveArgs a) {
   const int y0 = (int)(rr % a.ny);
   const int z0 = (int)(rr / a.ny);
   int32_t *desc = a.desc + (size_t)slot * a.desc_stride;
-  double *bpr = a.bprel + (size_t)slot * a.maxbp * 6;
+  double *bpr = a.bprel + (size_t)slot * a.maxbp * 7;
   uint32_t *mask = a.mout + (size_t)out * a.nwords;
 
   // ---- data rows: lattice points of each field that are interior and not excluded ----
@@ -231,13 +237,14 @@ __global__ void k_solve(SolveArgs a) {
         if (a.lat == 2) ry -= a.ny * rint(ry / a.ny);
         if (rx * rx + ry * ry + rz * rz <= a.r2) {
           if (w < a.maxbp) {
-            double *q = bpr + (size_t)w * 6;
+            double *q = bpr + (size_t)w * 7;
             q[0] = rx;
             q[1] = ry;
             q[2] = rz;
             q[3] = a.bpn[j * 3 + 0];
             q[4] = a.bpn[j * 3 + 1];
             q[5] = a.bpn[j * 3 + 2];
+            q[6] = (double)j;
           }
           ++w;
         }
@@ -295,7 +302,7 @@ __global__ void k_solve(SolveArgs a) {
         int bi = rb / a.nops;
         rowop[tid] = rb % a.nops;
         rowbp[tid] = bi;
-        const double *q = bpr + (size_t)bi * 6;
+        const double *q = bpr + (size_t)bi * 7;
         d[0] = q[0];
         d[1] = q[1];
         d[2] = q[2];
@@ -565,6 +572,39 @@ __global__ void k_solve(SolveArgs a) {
     }
     wo[j] = s;
   }
+  // y on the boundary-condition rows: row (b, op) . z with the row regenerated exactly as
+  // in the factorisation (one block: the second-order form's Laplacian family)
+  if (a.fwout && a.nblocks == 1) {
+    int32_t *fb = a.fbp + (size_t)pos * a.maxbp;
+    double *fw = a.fwout + (size_t)pos * a.maxbp * a.nops;
+    if (tid == 0) a.fnbp[pos] = nbp;
+    const OpSet &OS = c_solve.ops[0];
+    for (int r = tid; r < nbp * a.nops; r += nth) {
+      const int bi = r / a.nops, op = r - bi * a.nops;
+      const double *q = bpr + (size_t)bi * 7;
+      if (op == 0) fb[bi] = (int32_t)q[6];
+      double p[3][kMaxOrder + 1];
+      for (int n = 0; n < 3; ++n) {
+        p[n][0] = 1.0;
+        for (int k = 1; k < D1; ++k) p[n][k] = p[n][k - 1] * q[n] / (double)k;
+      }
+      double s = 0.0;
+      for (int t = 0; t < NTB; ++t) {
+        const int8_t *ex = c_solve.exps[t];
+        double v = 0.0;
+        for (int u = 0; u < OS.nterms[op]; ++u) {
+          const OpTerm &T = OS.term[op][u];
+          const int a0 = ex[0] - T.beta[0], a1 = ex[1] - T.beta[1], a2 = ex[2] - T.beta[2];
+          if (a0 < 0 || a1 < 0 || a2 < 0) continue;
+          double cf = T.coef;
+          if (T.normal_axis >= 0) cf *= q[3 + T.normal_axis];
+          v += cf * p[0][a0] * p[1][a1] * p[2][a2];
+        }
+        s += v * yv[t];
+      }
+      fw[r] = s;
+    }
+  }
 }
 
 // Gather accepted points of one round into the final tables.
@@ -589,6 +629,22 @@ __global__ void k_pack(int nacc, const int32_t *acc_pos, const int32_t *acc_id, 
     w64[woff[id] + t] = v;
     f32[t] = (float)v;
     f64[t] = v;
+  }
+}
+
+// Condition-value weights of the accepted points of one launch, compacted: entry e of
+// point a is (boundary point << 3 | condition) and its weight.
+__global__ void k_pack_bc(int nacc, const int32_t *apos, const int64_t *aoff, const int32_t *fbp, const double *fw,
+                          const int32_t *fnbp, int maxbp, int nops, int32_t *oidx, double *ow) {
+  const int a = blockIdx.x;
+  if (a >= nacc) return;
+  const int pos = apos[a];
+  const int n = fnbp[pos] * nops;
+  const int64_t o = aoff[a];
+  for (int e = threadIdx.x; e < n; e += blockDim.x) {
+    const int bi = e / nops, q = e - bi * nops;
+    oidx[o + e] = (fbp[(size_t)pos * maxbp + bi] << 3) | q;
+    ow[o + e] = fw[(size_t)pos * maxbp * nops + e];
   }
 }
 
@@ -737,8 +793,29 @@ ib_status weights_build(ib_weights *w, const int64_t *col_off_dev, hipStream_t s
   second_derivative_weights(M, sc.w2);
   double max_cond = 0.0, min_margin = INFINITY;
   const double tol_base = 2.220446049250313e-16;
-  const int max_slots = 32768;
   const int chunk = (ndim == 3) ? 32 : 48;
+  // condition-value weights, kept on request: compacted per launch into device chunks,
+  // concatenated at the end
+  const bool keep_bc = w->prm.keep_bc_weights != 0;
+  const int max_slots = keep_bc ? 8192 : 32768;
+  struct BcChunk {
+    int32_t *idx;
+    double *w;
+    int64_t n;
+  };
+  std::vector<BcChunk> bc_chunks;
+  std::vector<int32_t> bc_chunk_of(keep_bc ? nib : 0, -1), bc_cnt(keep_bc ? nib : 0, 0);
+  std::vector<int64_t> bc_loc(keep_bc ? nib : 0, 0);
+  int32_t *d_fbp = nullptr, *d_fnbp = nullptr, *d_bpos = nullptr;
+  double *d_fw = nullptr;
+  int64_t *d_boff = nullptr;
+  auto free_bc = [&]() {
+    dfree(d_fbp), dfree(d_fnbp), dfree(d_bpos), dfree(d_fw), dfree(d_boff);
+    d_fbp = d_fnbp = d_bpos = nullptr;
+    d_fw = nullptr;
+    d_boff = nullptr;
+  };
+  if (keep_bc && ((s = dalloc_t(&d_bpos, max_slots)) || (s = dalloc_t(&d_boff, max_slots)))) return s;
 
   for (int Mb = M; Mb >= min_order && !pending.empty(); --Mb) {
     const int NT = n_terms(Mb, ndim);
@@ -764,7 +841,7 @@ ib_status weights_build(ib_weights *w, const int64_t *col_off_dev, hipStream_t s
       const int desc_stride = nball;
       dfree(desc);
       dfree(bprel);
-      if ((s = dalloc_t(&desc, (size_t)slots * desc_stride)) || (s = dalloc_t(&bprel, (size_t)slots * maxbp * 6)))
+      if ((s = dalloc_t(&desc, (size_t)slots * desc_stride)) || (s = dalloc_t(&bprel, (size_t)slots * maxbp * 7)))
         return s;
       SolveArgs A{};
       A.cls = w->node_class;
@@ -811,6 +888,17 @@ ib_status weights_build(ib_weights *w, const int64_t *col_off_dev, hipStream_t s
       A.status = d_status;
       A.ndata = d_ndata;
       A.sigma = d_sigma;
+      if (keep_bc) {
+        dfree(d_fbp), dfree(d_fw), dfree(d_fnbp);
+        d_fbp = d_fnbp = nullptr;
+        d_fw = nullptr;
+        if ((s = dalloc_t(&d_fbp, (size_t)slots * maxbp)) || (s = dalloc_t(&d_fw, (size_t)slots * maxbp * A.nops)) ||
+            (s = dalloc_t(&d_fnbp, slots)))
+          return s;
+        A.fbp = d_fbp;
+        A.fwout = d_fw;
+        A.fnbp = d_fnbp;
+      }
       const int D1 = Mb + 1;
       size_t lds = sizeof(double) * ((size_t)NT * (NT + 1) / 2 + (size_t)chunk * 3 * D1 + (size_t)chunk * 3 +
                                      2 * (size_t)chunk + 4 + NT + 16) +
@@ -826,6 +914,38 @@ ib_status weights_build(ib_weights *w, const int64_t *col_off_dev, hipStream_t s
         else
           hipLaunchKernelGGL(k_solve<48>, dim3(A.npend), dim3(256), lds, st, A);
         IB_HIP(hipGetLastError());
+        if (keep_bc) {
+          // compact this launch's condition-value weights of the accepted points
+          const int nl = A.npend;
+          std::vector<int32_t> ls(nl), lf(nl), apos;
+          std::vector<int64_t> aoff;
+          IB_HIP(hipMemcpyAsync(ls.data(), d_status + b0, nl * 4, hipMemcpyDeviceToHost, st));
+          IB_HIP(hipMemcpyAsync(lf.data(), d_fnbp, nl * 4, hipMemcpyDeviceToHost, st));
+          IB_HIP(hipStreamSynchronize(st));
+          int64_t tot = 0;
+          for (int q = 0; q < nl; ++q) {
+            if (ls[q] != 1) continue;
+            const int id = pending[b0 + q];
+            apos.push_back(q);
+            aoff.push_back(tot);
+            bc_chunk_of[id] = (int32_t)bc_chunks.size();
+            bc_loc[id] = tot;
+            bc_cnt[id] = lf[q] * A.nops;
+            tot += (int64_t)lf[q] * A.nops;
+          }
+          BcChunk c{nullptr, nullptr, tot};
+          if ((s = dalloc_t(&c.idx, std::max<int64_t>(tot, 1))) || (s = dalloc_t(&c.w, std::max<int64_t>(tot, 1))))
+            return s;
+          bc_chunks.push_back(c);
+          if (!apos.empty()) {
+            IB_HIP(hipMemcpyAsync(d_bpos, apos.data(), apos.size() * 4, hipMemcpyHostToDevice, st));
+            IB_HIP(hipMemcpyAsync(d_boff, aoff.data(), aoff.size() * 8, hipMemcpyHostToDevice, st));
+            hipLaunchKernelGGL(k_pack_bc, dim3((unsigned)apos.size()), dim3(256), 0, st, (int)apos.size(), d_bpos,
+                               d_boff, d_fbp, d_fw, d_fnbp, maxbp, A.nops, c.idx, c.w);
+            IB_HIP(hipGetLastError());
+            IB_HIP(hipStreamSynchronize(st));
+          }
+        }
       }
       std::vector<int32_t> hs(npend), hn(npend);
       std::vector<double> hsig(npend);
@@ -863,9 +983,11 @@ ib_status weights_build(ib_weights *w, const int64_t *col_off_dev, hipStream_t s
   dfree(d_pending);
   dfree(d_status);
   dfree(d_ndata);
+  free_bc();
   if (!pending.empty()) {
     dfree(d_sigma);
     for (auto &rr : rounds) dfree(rr.wout), dfree(rr.mout);
+    for (auto &c : bc_chunks) dfree(c.idx), dfree(c.w);
     set_error("%zu IB points remain rank deficient after radius growth and order reduction (first: node %d)",
               pending.size(), pending[0]);
     return IB_ERR_UNCONSTRAINED;
@@ -947,6 +1069,28 @@ ib_status weights_build(ib_weights *w, const int64_t *col_off_dev, hipStream_t s
   }
   IB_HIP(hipStreamSynchronize(st));
   dfree(d_woff), dfree(d_nw), dfree(d_apos), dfree(d_aid), dfree(d_sigma);
+  if (keep_bc) {
+    std::vector<int64_t> base(bc_chunks.size() + 1, 0);
+    for (size_t c = 0; c < bc_chunks.size(); ++c) base[c + 1] = base[c] + bc_chunks[c].n;
+    const int64_t nbc = base.back();
+    if ((s = dalloc_t(&w->bc_idx, std::max<int64_t>(nbc, 1))) || (s = dalloc_t(&w->bc_w, std::max<int64_t>(nbc, 1))) ||
+        (s = dalloc_t(&w->bc_off, std::max<int64_t>(nib, 1))) || (s = dalloc_t(&w->bc_cnt, std::max<int64_t>(nib, 1))))
+      return s;
+    for (size_t c = 0; c < bc_chunks.size(); ++c) {
+      if (bc_chunks[c].n) {
+        IB_HIP(hipMemcpyAsync(w->bc_idx + base[c], bc_chunks[c].idx, bc_chunks[c].n * 4, hipMemcpyDeviceToDevice, st));
+        IB_HIP(hipMemcpyAsync(w->bc_w + base[c], bc_chunks[c].w, bc_chunks[c].n * 8, hipMemcpyDeviceToDevice, st));
+      }
+    }
+    std::vector<int64_t> off(nib);
+    for (int64_t i = 0; i < nib; ++i) off[i] = base[bc_chunk_of[i]] + bc_loc[i];
+    IB_HIP(hipMemcpyAsync(w->bc_off, off.data(), nib * 8, hipMemcpyHostToDevice, st));
+    IB_HIP(hipMemcpyAsync(w->bc_cnt, bc_cnt.data(), nib * 4, hipMemcpyHostToDevice, st));
+    IB_HIP(hipStreamSynchronize(st));
+    for (auto &c : bc_chunks) dfree(c.idx), dfree(c.w);
+    w->nbc = nbc;
+    w->bc_nq = make_ops(w->prm.surface, M, ndim).nops;
+  }
   return build_dense_records(w, st);
 }
 
@@ -1017,7 +1161,7 @@ ib_status solve_family(ib_weights *w, const FamilySpec &F, const int64_t *col_of
       bt.build(ndim, code + 2);
       const int maxbp = bt.count[code + 2] + 8;
       if ((s = dalloc_t(&d_tab, tab.size())) || (s = dalloc_t(&desc, (size_t)slots * nball)) ||
-          (s = dalloc_t(&bprel, (size_t)slots * maxbp * 6)) || (s = dalloc_t(&wout, (size_t)npend * nball)) ||
+          (s = dalloc_t(&bprel, (size_t)slots * maxbp * 7)) || (s = dalloc_t(&wout, (size_t)npend * nball)) ||
           (s = dalloc_t(&mout, (size_t)npend * nwords)))
         return s;
       IB_HIP(hipMemcpy(d_tab, tab.data(), tab.size() * 4, hipMemcpyHostToDevice));
