@@ -23,6 +23,7 @@ adjoint    discrete adjoint of the stepper and the velocity gradient
 staggered  first-order pressure-velocity form on a staggered grid
 mulder1d   per-axis 1D extrapolation (the reduction to 1D)
 forcing    inhomogeneous boundary conditions (the forcing columns of B A^+)
+           (the mixed surface p + a(x_b) dp/dn = 0 lives in basis and weights)
 
 Parity status: every function is pinned by tests under ``tests/test_oracle_*.py``
 except where a docstring says "parity unpinned".

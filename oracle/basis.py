@@ -178,6 +178,23 @@ def rigid_surface_ops(M: int, d: int, normal):
             for q in range((M - 1) // 2 + 1) if 2 * q + 1 <= M]
 
 
+def robin_surface_ops(M: int, d: int, normal_out, a: float):
+    """Mixed surface with a position-varying coefficient: lap^q p + a n.grad(lap^q p) = 0
+    for 2q <= M, n the normal pointing out of the physical domain, a (grid units) the value
+    at the boundary point.
+
+    Section "Approximating Boundary Conditions" allows the coefficients of a condition to
+    vary with the boundary point.  The zeroth member is p + a dp/dn = 0; differentiating
+    it twice in time through the wave equation (c constant near the surface, as for the
+    free-surface hierarchy) gives the higher members.  A member is kept while its order
+    2q + 1 fits the basis (2q + 1 <= M): on a degree-M basis the member with 2q = M would
+    lose its normal-derivative part and impose lap^q p = 0, which the condition does not
+    imply (it lowers the convergence order by one).
+    """
+    return [op_add(op_laplacian_power(q, d), op_normal_derivative(op_laplacian_power(q, d), [a * v for v in normal_out]))
+            for q in range(M // 2 + 1) if 2 * q + 1 <= M]
+
+
 # ---------------------------------------------------------------------------
 # Exact rational helpers used by the worked-example pins.
 # ---------------------------------------------------------------------------

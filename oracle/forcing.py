@@ -10,6 +10,7 @@ columns that multiply g only because g is zero in its examples.  Keeping those c
 
     free  surface:  nabla^{2q} p (x_b)             = g_q(x_b),  q = 0 .. M_b / 2
     rigid surface:  n . grad(nabla^{2q} p) (x_b)   = g_q(x_b),  2q + 1 <= M_b
+    robin surface:  (1 + a n_out . grad) nabla^{2q} p (x_b) = g_q(x_b),  2q + 1 <= M_b
 
 and the modified Laplacian of IB point i becomes, in grid units,
 
@@ -35,8 +36,9 @@ def n_conditions(surface: str, M: int) -> int:
 
 
 def order_of(surface: str, q: int) -> int:
-    """Derivative order of condition q."""
-    return 2 * q if surface == "free" else 2 * q + 1
+    """Derivative order of condition q (the robin member lap^q p + a dp/dn counts as 2q: a
+    carries the extra length)."""
+    return 2 * q + 1 if surface == "rigid" else 2 * q
 
 
 def forcing_row(sol):

@@ -67,7 +67,10 @@ class IBModel:
     """Classification + modified stencils of the second-order pressure form."""
 
     def __init__(self, heights, h, shape, M=8, surface='free', physical_below=True,
-                 eta=0.5, max_radius_steps=3, min_basis_order=None, columns=None):
+                 eta=0.5, max_radius_steps=3, min_basis_order=None, columns=None, robin=None):
+        """surface: 'free', 'rigid' or 'robin' (p + a dp/dn = 0 with the outward normal and
+        a(x_b) in metres, linear (2D) or bilinear (3D) periodic interpolation of the
+        per-column samples ``robin``, shaped like ``heights``)."""
         self.geom = Geometry(heights, h, shape, physical_below)
         self.d = self.geom.d
         self.shape = self.geom.shape
@@ -81,6 +84,10 @@ class IBModel:
         self.bp_host = bp['host']
         self.bp_xb = bp['xb']
         self.bp_normal = bp['normal']
+        if surface == 'robin':
+            if robin is None:
+                raise ValueError("the robin surface needs its coefficient samples")
+            self.bp_robin = _periodic_lerp(np.asarray(robin, dtype=np.float64), self.bp_xb[:, :-1]) / float(h)
         self.excluded = self.geom.excluded_nodes(self.bp_xb, self.eta)
         # grid-shaped views (memory order [z, (y,) x]) of the two node classes
         self.inter_grid = self.geom.interior_grid()
@@ -138,10 +145,14 @@ class IBModel:
         sel = np.nonzero(dist2 <= r * r)[0]
         return sel, rel[sel]
 
-    def bc_ops(self, Mb, normal):
+    def bc_ops(self, Mb, k):
+        """Condition operators at boundary point k (grid units)."""
         if self.surface_kind == 'free':
             return basis.free_surface_ops(Mb, self.d)
-        return basis.rigid_surface_ops(Mb, self.d, normal)
+        if self.surface_kind == 'robin':
+            n_out = -self.geom.sign * np.asarray(self.bp_normal[k])
+            return basis.robin_surface_ops(Mb, self.d, n_out, float(self.bp_robin[k]))
+        return basis.rigid_surface_ops(Mb, self.d, self.bp_normal[k])
 
     # --- per-point system -------------------------------------------------
     def system(self, i, Mb, r):
@@ -158,7 +169,7 @@ class IBModel:
         rows = [taylor_rows(data, Mb)] if len(data) else []
         sel, rel = self.boundary_points_within(i, r)
         for k, rb in zip(sel, rel):
-            for op in self.bc_ops(Mb, self.bp_normal[k]):
+            for op in self.bc_ops(Mb, k):
                 rows.append(basis.apply_op_row(op, rb, Mb)[None, :])
         A = np.concatenate(rows, axis=0) if rows else np.zeros((0, basis.n_terms(Mb, self.d)))
         return A, data
@@ -228,3 +239,23 @@ class IBModel:
             g = self.geom.wrap(i + o)
             row[g] = row.get(g, 0.0) + w
         return row
+
+
+def _periodic_lerp(samples, lat):
+    """Linear (2D: samples [nx]) or bilinear (3D: samples [ny][nx]) periodic interpolation of
+    per-column samples at lateral positions ``lat`` (grid units, (P, d-1))."""
+    out = np.zeros(len(lat))
+    if samples.ndim == 1:
+        nx = samples.shape[0]
+        for k, (x,) in enumerate(lat):
+            i = math.floor(x)
+            f = x - i
+            out[k] = (1 - f) * samples[i % nx] + f * samples[(i + 1) % nx]
+        return out
+    ny, nx = samples.shape
+    for k, (x, y) in enumerate(lat):
+        i, j = math.floor(x), math.floor(y)
+        fx, fy = x - i, y - j
+        out[k] = ((1 - fx) * (1 - fy) * samples[j % ny, i % nx] + fx * (1 - fy) * samples[j % ny, (i + 1) % nx]
+                  + (1 - fx) * fy * samples[(j + 1) % ny, i % nx] + fx * fy * samples[(j + 1) % ny, (i + 1) % nx])
+    return out

@@ -27,3 +27,23 @@ def standing_wave(nx, h, c):
         return (-kk) ** q * np.cos(kx * xb[..., 0]) * np.cos(kz * (xb[..., -1] - z0))
 
     return p, g, w
+
+
+def robin_coefficient(x, Lx):
+    """Positive, laterally varying coefficient a (m) of the mixed surface p + a dp/dn = 0."""
+    return 12.0 + 6.0 * np.sin(2 * math.pi * x / Lx + 0.4)
+
+
+def robin_standing_wave(Lx, zs, a, c):
+    """Standing wave below a flat surface z = zs satisfying p + a dp/dn = 0 there (n the
+    outward normal, -z): p = cos(w t) cos(kx x) (a kz cos(kz (z - zs)) + sin(kz (z - zs))).
+    Every member lap^q p + a dp/dn of the hierarchy then vanishes too (lap^q p is a multiple
+    of p); a = 0 is the free-surface standing wave.  Returns (p(x, z, t), w)."""
+    kx = 2 * math.pi * 2 / Lx
+    kz = 2 * math.pi / 300.0
+    w = c * math.sqrt(kx * kx + kz * kz)
+
+    def p(x, z, t):
+        return math.cos(w * t) * np.cos(kx * x) * (a * kz * np.cos(kz * (z - zs)) + np.sin(kz * (z - zs)))
+
+    return p, w

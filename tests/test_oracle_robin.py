@@ -1,0 +1,136 @@
+"""Pins of the oracle's mixed (robin) surface p + a(x_b) dp/dn = 0, whose coefficient varies
+with the boundary point: exactness on random polynomials carrying their own condition
+values (computed with numpy's polynomial calculus and scipy's interpolation, independently of
+the oracle), and flat-surface standing waves that satisfy the homogeneous hierarchy exactly
+(a > 0, and a = 0, the free surface)."""
+import math
+import os
+import sys
+
+import numpy as np
+import pytest
+from numpy.polynomial import polynomial as Pn
+from scipy.ndimage import map_coordinates
+
+from oracle import fd, forcing, stepper
+from oracle.weights import IBModel
+from paper_2309_03600_amd import workloads as W
+
+sys.path.insert(0, os.path.dirname(os.path.abspath(__file__)))
+from manufactured import robin_coefficient, robin_standing_wave  # noqa: E402
+from test_oracle_forcing import _grad_n, _lap, _random_poly, _val  # noqa: E402
+
+
+def _coef_at(samples, lat):
+    """a at lateral grid positions: periodic linear / bilinear interpolation (scipy)."""
+    samples = np.asarray(samples, dtype=np.float64)
+    if samples.ndim == 1:
+        return map_coordinates(samples, [lat[:, 0]], order=1, mode="grid-wrap")
+    return map_coordinates(samples, [lat[:, 1], lat[:, 0]], order=1, mode="grid-wrap")
+
+
+def _check_point(m, robin, i, rng):
+    sol = m.solve_point(i)
+    Mb, d, half, h = sol["order"], m.d, m.M // 2, m.geom.h
+    C = _random_poly(rng, d, Mb)
+    terms = []
+    for n in range(d):
+        for k in range(-half, half + 1):
+            e = np.array(i)
+            e[n] += k
+            if m.interior(tuple(e)):
+                off = np.zeros(d)
+                off[n] = k
+                terms.append(m.w2[k + half] * _val(C, off))
+    for o, y in zip(sol["offsets"], sol["weights"]):
+        terms.append(y * _val(C, o.astype(float)))
+    sel, rel = m.boundary_points_within(i, sol["radius"])
+    relpos = {int(b): r for b, r in zip(sel, rel)}
+    a_grid = _coef_at(robin, m.bp_xb[:, :-1]) / h
+    for b, q, v in forcing.forcing_row(sol):
+        D = C
+        for _ in range(q):
+            D = _lap(D)
+        n_out = -np.asarray(m.bp_normal[b])                 # physical domain below the surface
+        cond = _val(D, relpos[b]) + a_grid[b] * _val(_grad_n(D, n_out), relpos[b])
+        terms.append(v * cond)
+    got = sum(terms)
+    want = _val(_lap(C), np.zeros(d))
+    scale = max(1.0, sum(abs(t) for t in terms))
+    return abs(got - want), max(1e-13, sol["cond"] * 1e-15) * scale
+
+
+@pytest.mark.parametrize("M", [4, 8])
+def test_robin_rows_with_condition_values_are_exact_on_polynomials_2d(M):
+    wl = W.small2d(M=M, nt=10, hill=60.0, nx=60, nz=60)
+    robin = robin_coefficient(np.arange(60) * wl.h, 60 * wl.h)
+    m = IBModel(wl.heights, wl.h, wl.shape, M=M, surface="robin", eta=wl.eta, robin=robin)
+    rng = np.random.default_rng(13)
+    pts = m.ib_points()
+    for i in pts[:: max(1, len(pts) // 40)]:
+        err, tol = _check_point(m, robin, tuple(int(v) for v in i), rng)
+        assert err <= tol, (tuple(i), err, tol)
+
+
+def test_robin_rows_with_condition_values_are_exact_on_polynomials_3d():
+    wl = W.small3d(n=16, nz=36, relief=30.0, nt=10, z_top_cells=12)
+    x = np.arange(16) * wl.h
+    robin = robin_coefficient(x[None, :], 16 * wl.h) * (1.0 + 0.3 * np.sin(2 * math.pi * x[:, None] / (16 * wl.h)))
+    m = IBModel(wl.heights, wl.h, wl.shape, M=4, surface="robin", eta=wl.eta, robin=robin)
+    rng = np.random.default_rng(14)
+    pts = m.ib_points()
+    for i in pts[:: max(1, len(pts) // 12)]:
+        err, tol = _check_point(m, robin, tuple(int(v) for v in i), rng)
+        assert err <= tol, (tuple(i), err, tol)
+
+
+def robin_flat_error(h, a=15.0, M=4, T=0.04, c=1500.0, surface="robin"):
+    """Max error of the unforced oracle against the flat-surface robin standing wave."""
+    nx, nz = int(round(240.0 / h)), int(round(500.0 / h))
+    zs = 200.3
+    m = IBModel(np.full(nx, zs), h, (nx, nz), M=M, surface=surface, eta=0.5,
+                robin=np.full(nx, a) if surface == "robin" else None)
+    sols = stepper.solve_all(m)
+    L = stepper.assemble_laplacian(m, sols)
+    dt = 0.1 * fd.critical_dt(h, c, M, 2)
+    nt = int(round(T / dt))
+    p, om = robin_standing_wave(nx * h, zs, a, c)
+    sim = stepper.Simulation(m, L, np.full((nz, nx), c), dt, [], [])
+    inter = m.geom.interior_grid()
+    X, Z = np.meshgrid(np.arange(nx) * h, np.arange(nz) * h)
+    sim.u = np.where(inter, p(X, Z, 0.0), 0.0).ravel()
+    sim.um = np.where(inter, p(X, Z, -dt), 0.0).ravel()
+    for _ in range(nt):
+        sim.step([])
+    exact = np.where(inter, p(X, Z, nt * dt), 0.0)
+    sel = inter & (Z < 340.0)
+    return np.abs(sim.u.reshape(nz, nx) - exact)[sel].max()
+
+
+def test_flat_robin_surface_follows_the_standing_wave():
+    e10, e5 = robin_flat_error(10.0), robin_flat_error(5.0)
+    e5_free = robin_flat_error(5.0, surface="free")
+    # max-norm errors over the nodes near the surface converge at about third order here
+    # (8.1e-3, 1.05e-3, 1.2e-4 at 10, 5, 2.5 m); the free surface misses the wave entirely
+    assert e5 < 2e-3, e5
+    assert np.log2(e10 / e5) > 2.5, (e10, e5)
+    assert e5_free > 30 * e5, (e5_free, e5)
+
+
+def test_zero_coefficient_follows_the_free_surface_standing_wave():
+    # a = 0: p = 0 on the surface (the standing wave is the free-surface one)
+    e10, e5 = robin_flat_error(10.0, a=0.0), robin_flat_error(5.0, a=0.0)
+    assert e5 < 1e-3 and np.log2(e10 / e5) > 3.5, (e10, e5)
+
+
+@pytest.mark.parametrize("M", [2, 3, 4, 5, 6, 7, 8])
+def test_hierarchies_keep_exactly_the_members_of_order_at_most_M(M):
+    # the paper drops conditions of order above the basis order; a robin member has order
+    # 2q + 1 (its normal-derivative part), a free member 2q, a rigid member 2q + 1
+    from oracle import basis
+    for d in (2, 3):
+        n = [0.0] * (d - 1) + [-1.0]
+        for ops, order in ((basis.free_surface_ops(M, d), lambda q: 2 * q),
+                           (basis.rigid_surface_ops(M, d, n), lambda q: 2 * q + 1),
+                           (basis.robin_surface_ops(M, d, n, 0.7), lambda q: 2 * q + 1)):
+            assert [basis.op_order(op) for op in ops] == [order(q) for q in range(M + 1) if order(q) <= M]

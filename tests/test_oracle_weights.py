@@ -65,7 +65,7 @@ def test_forced_polynomial_reproduction_2d(kind, M):
         sel, rel = m.boundary_points_within(i, r)
         for k, rb in zip(sel, rel):
             xb = (np.asarray(i, float) + rb)[None, :]
-            for op in m.bc_ops(Mb, m.bp_normal[k]):
+            for op in m.bc_ops(Mb, k):
                 rhs.append(_apply_op_poly(op, q, xb))
         rhs = np.concatenate(rhs)
         delta = np.linalg.pinv(A) @ rhs
