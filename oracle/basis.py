@@ -186,13 +186,15 @@ def robin_surface_ops(M: int, d: int, normal_out, a: float):
     Section "Approximating Boundary Conditions" allows the coefficients of a condition to
     vary with the boundary point.  The zeroth member is p + a dp/dn = 0; differentiating
     it twice in time through the wave equation (c constant near the surface, as for the
-    free-surface hierarchy) gives the higher members.  A member is kept while its order
-    2q + 1 fits the basis (2q + 1 <= M): on a degree-M basis the member with 2q = M would
-    lose its normal-derivative part and impose lap^q p = 0, which the condition does not
-    imply (it lowers the convergence order by one).
+    free-surface hierarchy) gives the higher members.  The paper drops the conditions that
+    reduce to 0 = 0 on the basis; a member with 2q <= M never does (its lap^q part
+    survives), so the members are those of the free surface, q = 0 .. M/2, and a = 0 gives
+    the free surface exactly.  The normal-derivative part of the member with 2q = M has
+    order M + 1 and vanishes on the basis.  (Dropping that member instead leaves the M = 4
+    operator with growing modes on curved surfaces.)
     """
     return [op_add(op_laplacian_power(q, d), op_normal_derivative(op_laplacian_power(q, d), [a * v for v in normal_out]))
-            for q in range(M // 2 + 1) if 2 * q + 1 <= M]
+            for q in range(M // 2 + 1)]
 
 
 # ---------------------------------------------------------------------------

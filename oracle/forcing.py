@@ -10,7 +10,7 @@ columns that multiply g only because g is zero in its examples.  Keeping those c
 
     free  surface:  nabla^{2q} p (x_b)             = g_q(x_b),  q = 0 .. M_b / 2
     rigid surface:  n . grad(nabla^{2q} p) (x_b)   = g_q(x_b),  2q + 1 <= M_b
-    robin surface:  (1 + a n_out . grad) nabla^{2q} p (x_b) = g_q(x_b),  2q + 1 <= M_b
+    robin surface:  (1 + a n_out . grad) nabla^{2q} p (x_b) = g_q(x_b),  q = 0 .. M_b / 2
 
 and the modified Laplacian of IB point i becomes, in grid units,
 
@@ -32,7 +32,7 @@ import numpy as np
 
 def n_conditions(surface: str, M: int) -> int:
     """Members of the condition hierarchy at basis order M."""
-    return M // 2 + 1 if surface == "free" else (M - 1) // 2 + 1
+    return (M - 1) // 2 + 1 if surface == "rigid" else M // 2 + 1
 
 
 def order_of(surface: str, q: int) -> int:
