@@ -54,7 +54,7 @@ typedef enum { IB_FORM_P2 = 0,  /* second-order pressure form                   
                                    surface: section "The Particle Velocity Free-Surface"; in 3D
                                    space_order <= 4, the order of the paper's examples) */
 } ib_form;
-typedef enum { IB_SURF_FREE = 0, IB_SURF_RIGID = 1 } ib_surface;
+typedef enum { IB_SURF_FREE = 0, IB_SURF_RIGID = 1, IB_SURF_ROBIN = 2 } ib_surface;
 typedef enum { IB_METHOD_ND = 0, IB_METHOD_1D = 1 } ib_method;
 typedef enum { IB_F32 = 0, IB_F64 = 1 } ib_precision;
 
@@ -71,7 +71,14 @@ typedef struct {
  *   space_order      M, even, 2..8: order of the interior stencil and of the Taylor basis.
  *   surface          IB_SURF_FREE: p = 0, lap p = 0, lap^2 p = 0, ... (section
  *                    "Free-Surface Boundary Constraints");  IB_SURF_RIGID: zero normal
- *                    velocity, i.e. n.grad(lap^q p) = 0 (rigid-surface examples).
+ *                    velocity, i.e. n.grad(lap^q p) = 0 (rigid-surface examples);
+ *                    IB_SURF_ROBIN: p + a(x_b) dp/dn = 0 with n the normal pointing out of
+ *                    the physical domain and a coefficient that varies along the surface
+ *                    (section "Approximating Boundary Conditions" lets the coefficients
+ *                    vary with the boundary point), and its members
+ *                    lap^q p + a n.grad(lap^q p) = 0 obtained through the wave equation,
+ *                    q = 0 .. M_b/2 (a = 0 is the free surface).  Second-order form, N-D
+ *                    method.
  *   eta              exclusion cut-off: interior nodes with a boundary point strictly
  *                    inside their node-centred box of half-width eta*h are not used as
  *                    data (section "Approximating Boundary Conditions"; 0.5 in the
@@ -96,6 +103,11 @@ typedef struct {
  *                    Discretization"), needed for non-zero boundary values
  *                    (ib_state_set_forcing).  Second-order form, N-D method only.  0: drop
  *                    them (homogeneous conditions; the paper's examples).
+ *   robin_dev        IB_SURF_ROBIN only: device float64 samples of a (metres, >= 0 for an
+ *                    energy-stable condition) at the node columns, laid out like the
+ *                    heightfield; a(x_b) is their periodic bilinear (2D: linear)
+ *                    interpolation at the boundary point's lateral position.  Borrowed for
+ *                    the call.  NULL for the other surfaces.
  */
 typedef struct {
   int32_t form;
@@ -109,6 +121,7 @@ typedef struct {
   double eta_v;
   int32_t method;
   int32_t keep_bc_weights;
+  const double *robin_dev;
 } ib_params;
 
 typedef struct {
@@ -159,7 +172,8 @@ void ib_weights_free(ib_weights *w);
  *   IB_FIELD_NODE_CLASS  uint8 [n_nodes], memory order: bit0 interior, bit1 excluded
  *                        by eta, bit2 IB point, bit3 hosts a boundary point.
  *   IB_FIELD_BPOINTS     float64 [n_boundary_points][7]: host node (x,y,z) as doubles,
- *                        boundary point (x,y,z) in grid units (2D: y = 0).
+ *                        boundary point (x,y,z) in grid units (2D: y = 0), the mixed
+ *                        surface's coefficient a(x_b) in metres (0 for the others).
  *   IB_FIELD_IB_NODES    int64 [n_ib]: memory-order node index of each IB point.
  *   IB_FIELD_IB_META     int32 [n_ib][4]: radius step k, basis order M_b, weight count,
  *                        first weight index.
@@ -266,13 +280,14 @@ int64_t ib_state_step_count(const ib_state *st);
  * Second-order form, weights built with keep_bc_weights = 1.
  *   The conditions of the surface get right-hand sides, condition q of the hierarchy
  *     free:  lap^q p (x_b) = g_q(x_b) s_q(t),   rigid:  n.grad(lap^q p)(x_b) = g_q(x_b) s_q(t),
+ *     robin: lap^q p + a n.grad(lap^q p) = g_q(x_b) s_q(t),
  *   so step n adds K (sum_q s_q(t_n) sum_b v_ibq h^{o_q} g_q(x_b)) / (1 + s) at each IB
- *   point i (o_q = 2q free, 2q + 1 rigid; v the condition-value weights).
+ *   point i (o_q = 2q free and robin, 2q + 1 rigid; v the condition-value weights).
  *   g_dev:   device float64 [n_boundary_points][nq] (IB_FIELD_BPOINTS order), physical
  *            units (Pa / m^{o_q}).  Borrowed: contracted with the weights during the call.
  *   s_host:  host float64 [nq][s_len]: step t uses s_q[t] (t = the state's step counter);
  *            copied into the state.
- *   nq:      1 .. conditions at full order (M/2 + 1 free, (M - 1)/2 + 1 rigid); conditions
+ *   nq:      1 .. conditions at full order (M/2 + 1 free and robin, (M - 1)/2 + 1 rigid); conditions
  *            beyond nq stay homogeneous.
  *   g_dev = NULL clears the forcing.  The same values drive every shot.  ib_step then
  *   needs s_len >= step counter + nsteps; ib_forward and ib_adjoint refuse a forced state

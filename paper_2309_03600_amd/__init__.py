@@ -12,7 +12,7 @@ import ctypes as C
 import numpy as np
 
 from . import _lib
-from ._lib import IB_F32, IB_F64, IB_SURF_FREE, IB_SURF_RIGID  # noqa: F401
+from ._lib import IB_F32, IB_F64, IB_SURF_FREE, IB_SURF_RIGID, IB_SURF_ROBIN  # noqa: F401
 
 __all__ = ["IBWeights", "IBState", "ib_build_weights", "ib_state_create", "ib_step", "modelling", "abi_version"]
 
@@ -99,14 +99,16 @@ class IBWeights:
 
 def ib_build_weights(heights, h, shape, space_order=8, surface="free", eta=0.5, max_radius_steps=3,
                      min_basis_order=None, physical_below=True, rank_rtol=0.0, form="p2", eta_v=0.0, method="nd",
-                     keep_bc_weights=False, stream=None):
+                     keep_bc_weights=False, robin=None, stream=None):
     """Build the IB stencils for a heightfield (torch float64 device tensor or array, metres).
 
     ``form`` "p2" is the second-order pressure form, "pv1" the first-order pressure-velocity
     form on a staggered grid.  ``method`` "nd" builds the N-D extrapolants of the paper,
     "1d" the per-axis 1D extrapolations of its reduction to 1D (second-order form, free
     surface).  ``keep_bc_weights`` also keeps the weights of the boundary-condition values
-    (needed by ``IBState.set_forcing``; second-order form, N-D method).
+    (needed by ``IBState.set_forcing``; second-order form, N-D method).  ``surface`` is
+    "free", "rigid" or "robin": p + a dp/dn = 0 with the outward normal and a (metres) given
+    by ``robin``, per-column samples shaped like ``heights``.
     """
     if form not in ("p2", "pv1"):
         raise ValueError("form must be 'p2' or 'pv1'")
@@ -125,7 +127,15 @@ def ib_build_weights(heights, h, shape, space_order=8, surface="free", eta=0.5, 
     p.form = _lib.IB_FORM_P2 if form == "p2" else _lib.IB_FORM_PV1
     p.eta_v = float(eta_v)
     p.method = _lib.IB_METHOD_ND if method == "nd" else _lib.IB_METHOD_1D
-    p.surface = IB_SURF_FREE if surface == "free" else IB_SURF_RIGID
+    if surface not in ("free", "rigid", "robin"):
+        raise ValueError("surface must be 'free', 'rigid' or 'robin'")
+    p.surface = {"free": IB_SURF_FREE, "rigid": IB_SURF_RIGID, "robin": IB_SURF_ROBIN}[surface]
+    Rt = None
+    if robin is not None:
+        Rt = torch.as_tensor(np.ascontiguousarray(robin, dtype=np.float64) if not torch.is_tensor(robin) else robin,
+                             dtype=torch.float64, device="cuda").contiguous()
+        assert tuple(Rt.shape) == tuple(Ht.shape)
+        p.robin_dev = Rt.data_ptr()
     p.space_order = int(space_order)
     p.max_radius_steps = int(max_radius_steps)
     p.min_basis_order = int(min_basis_order if min_basis_order is not None else max(2, space_order // 2))

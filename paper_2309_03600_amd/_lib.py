@@ -9,7 +9,7 @@ LIB_PATH = os.path.join(HERE, "libibwave.so")
 
 IB_OK = 0
 IB_F32, IB_F64 = 0, 1
-IB_SURF_FREE, IB_SURF_RIGID = 0, 1
+IB_SURF_FREE, IB_SURF_RIGID, IB_SURF_ROBIN = 0, 1, 2
 IB_FORM_P2 = 0
 IB_FORM_PV1 = 1
 IB_METHOD_ND = 0
@@ -27,7 +27,7 @@ class ib_params(C.Structure):
     _fields_ = [("form", C.c_int32), ("surface", C.c_int32), ("space_order", C.c_int32),
                 ("max_radius_steps", C.c_int32), ("min_basis_order", C.c_int32), ("physical_below", C.c_int32),
                 ("eta", C.c_double), ("rank_rtol", C.c_double), ("eta_v", C.c_double), ("method", C.c_int32),
-                ("keep_bc_weights", C.c_int32)]
+                ("keep_bc_weights", C.c_int32), ("robin_dev", C.c_void_p)]
 
 
 class ib_stats(C.Structure):

@@ -298,6 +298,29 @@ ib_status autotune_interior(ib_state *S, hipStream_t st) {
 }  // namespace
 
 namespace {
+// a(x_b): periodic bilinear (lat == 1: linear) interpolation of the per-column samples
+__global__ void k_bp_robin(double *bp, int64_t nb, const double *a, int nx, int ny, int lat) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= nb) return;
+  double *o = bp + j * 8;
+  const double x = o[3], y = (lat == 2) ? o[4] : 0.0;
+  const double fx0 = floor(x), fy0 = floor(y);
+  const double tx = x - fx0, ty = y - fy0;
+  auto wrap = [](long long i, int n) { return (int)(((i % n) + n) % n); };
+  const int i0 = wrap((long long)fx0, nx), i1 = wrap((long long)fx0 + 1, nx);
+  double v;
+  if (lat == 1) {
+    v = (1.0 - tx) * a[i0] + tx * a[i1];
+  } else {
+    const int j0 = wrap((long long)fy0, ny), j1 = wrap((long long)fy0 + 1, ny);
+    v = (1.0 - tx) * (1.0 - ty) * a[(int64_t)j0 * nx + i0] + tx * (1.0 - ty) * a[(int64_t)j0 * nx + i1] +
+        (1.0 - tx) * ty * a[(int64_t)j1 * nx + i0] + tx * ty * a[(int64_t)j1 * nx + i1];
+  }
+  o[6] = v;
+}
+}  // namespace
+
+namespace {
 struct HPow {
   double v[8];
 };
@@ -376,8 +399,16 @@ ib_status ib_build_weights(const ib_grid *g, const double *height_dev, const ib_
     set_error("eta_v must be in [0, 1] (got %g)", p->eta_v);
     return IB_ERR_ARG;
   }
-  if (p->surface != IB_SURF_FREE && p->surface != IB_SURF_RIGID) {
+  if (p->surface != IB_SURF_FREE && p->surface != IB_SURF_RIGID && p->surface != IB_SURF_ROBIN) {
     set_error("unsupported surface %d", p->surface);
+    return IB_ERR_ARG;
+  }
+  if ((p->surface == IB_SURF_ROBIN) != (p->robin_dev != nullptr)) {
+    set_error("robin_dev is required by the mixed (robin) surface and only by it");
+    return IB_ERR_ARG;
+  }
+  if (p->surface == IB_SURF_ROBIN && (p->form != IB_FORM_P2 || p->method != IB_METHOD_ND)) {
+    set_error("the mixed (robin) surface is built for the second-order form with the N-D method");
     return IB_ERR_ARG;
   }
   if (p->space_order < 2 || p->space_order > kMaxOrder || (p->space_order & 1)) {
@@ -433,6 +464,14 @@ ib_status ib_build_weights(const ib_grid *g, const double *height_dev, const ib_
     ib_weights_free(w);
     return s;
   }
+  if (p->surface == IB_SURF_ROBIN && w->nb > 0) {
+    // the coefficient at each boundary point, kept in slot 6 of its record
+    hipLaunchKernelGGL(k_bp_robin, dim3((unsigned)((w->nb + 255) / 256)), dim3(256), 0, st, w->bp, w->nb,
+                       p->robin_dev, (int)w->nx, (int)w->ny, w->ndim - 1);
+    IB_HIP(hipGetLastError());
+    IB_HIP(hipStreamSynchronize(st));
+  }
+  w->prm.robin_dev = nullptr;   // borrowed for this call only
   // the surface band must stay clear of the top and bottom of the box
   {
     std::vector<double> hs(w->nx * w->ny);
@@ -624,8 +663,7 @@ ib_status ib_weights_copy(const ib_weights *w, int32_t field, void *dst, int64_t
       if (w->nb) IB_HIP(hipMemcpy(bp.data(), w->bp, bp.size() * 8, hipMemcpyDeviceToHost));
       double *o = (double *)dst;
       for (int64_t j = 0; j < w->nb; ++j) {
-        for (int q = 0; q < 6; ++q) o[j * 7 + q] = bp[j * 8 + q];
-        o[j * 7 + 6] = 0.0;
+        for (int q = 0; q < 7; ++q) o[j * 7 + q] = bp[j * 8 + q];
       }
       return IB_OK;
     }
@@ -1386,7 +1424,7 @@ ib_status ib_state_set_forcing(ib_state *S, const double *g, int32_t nq, const d
   }
   IB_HIP(hipMemcpy(fs, hs.data(), hs.size(), hipMemcpyHostToDevice));
   HPow hp{};
-  const bool rigid = w->prm.surface == IB_SURF_RIGID;
+  const bool rigid = w->prm.surface == IB_SURF_RIGID;   // free and robin members have order 2q in g
   for (int q = 0; q < 8; ++q) hp.v[q] = std::pow(w->h, rigid ? 2 * q + 1 : 2 * q);
   if (w->nib) {
     const unsigned nb = (unsigned)((w->nib + 255) / 256);

@@ -135,7 +135,7 @@ void staggered_first_derivative_weights(int M, double *w) {
 }
 
 // nabla^{2q} in d dimensions: sum over |g| = q of q!/g! d^{2g}.
-void add_laplacian_power(OpSet &ops, int slot, int q, int ndim, int normal_axis) {
+void add_laplacian_power(OpSet &ops, int slot, int q, int ndim, int normal_axis, int scaled) {
   auto fact = [](int n) {
     double f = 1.0;
     for (int i = 2; i <= n; ++i) f *= i;
@@ -154,6 +154,7 @@ void add_laplacian_power(OpSet &ops, int slot, int q, int ndim, int normal_axis)
       t.beta[1] = (int8_t)(2 * b);
       t.beta[2] = (int8_t)(2 * c);
       t.normal_axis = (int8_t)normal_axis;
+      t.scaled = (int8_t)scaled;
       t.coef = coef;
       if (normal_axis >= 0) t.beta[normal_axis] += 1;
       ops.term[slot][ops.nterms[slot]++] = t;
@@ -168,6 +169,19 @@ OpSet make_ops(int surface, int Mb, int ndim) {
   if (surface == IB_SURF_FREE) {
     for (int q = 0; 2 * q <= Mb; ++q) {
       add_laplacian_power(ops, ops.nops, q, ndim, -1);
+      ops.nops++;
+    }
+  } else if (surface == IB_SURF_ROBIN) {
+    // (1 + a n_out . grad) nabla^{2q} for 2q <= Mb (the free-surface members; none reduces
+    // to 0 = 0 on the basis); the normal part of order 2q + 1 > Mb vanishes on the basis and
+    // is left out.  The sign of n_out relative to the stored normal is folded into the
+    // per-point coefficient.
+    for (int q = 0; 2 * q <= Mb; ++q) {
+      add_laplacian_power(ops, ops.nops, q, ndim, -1);
+      for (int ax = 0; ax < 3 && 2 * q + 1 <= Mb; ++ax) {
+        if (ndim == 2 && ax == 1) continue;
+        add_laplacian_power(ops, ops.nops, q, ndim, ax, 1);
+      }
       ops.nops++;
     }
   } else {

@@ -46,6 +46,7 @@ struct BallTables {
 struct OpTerm {
   int8_t beta[3];
   int8_t normal_axis;   // -1: plain coefficient; else multiplied by normal[normal_axis]
+  int8_t scaled;        // 1: also multiplied by the boundary point's mixed-surface coefficient
   double coef;
 };
 struct OpSet {
@@ -55,7 +56,7 @@ struct OpSet {
 };
 OpSet make_ops(int surface, int Mb, int ndim);
 OpSet make_vops(int surface, int Mb, int ndim, int axis);
-void add_laplacian_power(OpSet &ops, int slot, int q, int ndim, int normal_axis);
+void add_laplacian_power(OpSet &ops, int slot, int q, int ndim, int normal_axis, int scaled = 0);
 std::vector<int32_t> shifted_ball(int ndim, int code, const double shift[3]);
 void staggered_first_derivative_weights(int M, double *w);   // offsets -(M-1)/2..(M-1)/2
 

@@ -66,13 +66,14 @@ struct SolveArgs {
   int NT, Mb, M, nops;
   int nball, nwords;       // totals over the fields
   double r2;               // r^2
+  double robin_scale;      // mixed surface: grid-unit coefficient = robin_scale * a(x_b) (sign: n_out vs n)
   int Rc;                  // lateral column search half-width for boundary points
   double rtol;
   int chunk;
   // per-slot scratch
   int32_t *desc;
   int desc_stride;
-  double *bprel;           // [slot][maxbp][7]: relative position, normal, global index
+  double *bprel;           // [slot][maxbp][8]: relative position, normal, global index, coefficient
   int maxbp;
   // outputs indexed by position in ``pending`` (+ base)
   int out_base;
@@ -146,6 +147,7 @@ __global__ void k_solve(SolveArgs a) {
   int *iscr = (int *)(red + 16);                      // 16 ints
   __shared__ int rowop[64];
   __shared__ int rowbp[64];
+  __shared__ double rowrob[64];   // mixed-surface coefficient of each chunk row
 
   const int pos = blockIdx.x;
   const int slot = blockIdx.x;
@@ -157,7 +159,7 @@ __global__ void k_solve(SolveArgs a) {
   const int y0 = (int)(rr % a.ny);
   const int z0 = (int)(rr / a.ny);
   int32_t *desc = a.desc + (size_t)slot * a.desc_stride;
-  double *bpr = a.bprel + (size_t)slot * a.maxbp * 7;
+  double *bpr = a.bprel + (size_t)slot * a.maxbp * 8;
   uint32_t *mask = a.mout + (size_t)out * a.nwords;
 
   // ---- data rows: lattice points of each field that are interior and not excluded ----
@@ -237,7 +239,7 @@ __global__ void k_solve(SolveArgs a) {
         if (a.lat == 2) ry -= a.ny * rint(ry / a.ny);
         if (rx * rx + ry * ry + rz * rz <= a.r2) {
           if (w < a.maxbp) {
-            double *q = bpr + (size_t)w * 7;
+            double *q = bpr + (size_t)w * 8;
             q[0] = rx;
             q[1] = ry;
             q[2] = rz;
@@ -245,6 +247,7 @@ __global__ void k_solve(SolveArgs a) {
             q[4] = a.bpn[j * 3 + 1];
             q[5] = a.bpn[j * 3 + 2];
             q[6] = (double)j;
+            q[7] = a.robin_scale * a.bp[j * 8 + 6];
           }
           ++w;
         }
@@ -296,13 +299,15 @@ __global__ void k_solve(SolveArgs a) {
         d[1] = (int8_t)((v >> 8) & 255) + a.fshift[f][1];
         d[2] = (int8_t)((v >> 16) & 255) + a.fshift[f][2];
         rowop[tid] = -1 - a.fblock[f];
+        rowrob[tid] = 0.0;
         nrm[tid * 3 + 0] = nrm[tid * 3 + 1] = nrm[tid * 3 + 2] = 0.0;
       } else {
         int rb = r - ndata;
         int bi = rb / a.nops;
         rowop[tid] = rb % a.nops;
         rowbp[tid] = bi;
-        const double *q = bpr + (size_t)bi * 7;
+        const double *q = bpr + (size_t)bi * 8;
+        rowrob[tid] = q[7];
         d[0] = q[0];
         d[1] = q[1];
         d[2] = q[2];
@@ -335,6 +340,7 @@ __global__ void k_solve(SolveArgs a) {
             if (a0 < 0 || a1 < 0 || a2 < 0) continue;
             double cf = T.coef;
             if (T.normal_axis >= 0) cf *= nrm[i * 3 + T.normal_axis];
+            if (T.scaled) cf *= rowrob[i];
             v += cf * p[a0] * p[D1 + a1] * p[2 * D1 + a2];
           }
         }
@@ -581,7 +587,7 @@ __global__ void k_solve(SolveArgs a) {
     const OpSet &OS = c_solve.ops[0];
     for (int r = tid; r < nbp * a.nops; r += nth) {
       const int bi = r / a.nops, op = r - bi * a.nops;
-      const double *q = bpr + (size_t)bi * 7;
+      const double *q = bpr + (size_t)bi * 8;
       if (op == 0) fb[bi] = (int32_t)q[6];
       double p[3][kMaxOrder + 1];
       for (int n = 0; n < 3; ++n) {
@@ -598,6 +604,7 @@ __global__ void k_solve(SolveArgs a) {
           if (a0 < 0 || a1 < 0 || a2 < 0) continue;
           double cf = T.coef;
           if (T.normal_axis >= 0) cf *= q[3 + T.normal_axis];
+          if (T.scaled) cf *= q[7];
           v += cf * p[0][a0] * p[1][a1] * p[2][a2];
         }
         s += v * yv[t];
@@ -841,7 +848,7 @@ ib_status weights_build(ib_weights *w, const int64_t *col_off_dev, hipStream_t s
       const int desc_stride = nball;
       dfree(desc);
       dfree(bprel);
-      if ((s = dalloc_t(&desc, (size_t)slots * desc_stride)) || (s = dalloc_t(&bprel, (size_t)slots * maxbp * 7)))
+      if ((s = dalloc_t(&desc, (size_t)slots * desc_stride)) || (s = dalloc_t(&bprel, (size_t)slots * maxbp * 8)))
         return s;
       SolveArgs A{};
       A.cls = w->node_class;
@@ -878,6 +885,7 @@ ib_status weights_build(ib_weights *w, const int64_t *col_off_dev, hipStream_t s
       A.r2 = r * r;
       A.Rc = (int)floor(r + 0.5);
       A.rtol = w->prm.rank_rtol;
+      A.robin_scale = (w->prm.physical_below ? -1.0 : 1.0) / w->h;
       A.chunk = chunk;
       A.desc = desc;
       A.desc_stride = desc_stride;
@@ -1161,7 +1169,7 @@ ib_status solve_family(ib_weights *w, const FamilySpec &F, const int64_t *col_of
       bt.build(ndim, code + 2);
       const int maxbp = bt.count[code + 2] + 8;
       if ((s = dalloc_t(&d_tab, tab.size())) || (s = dalloc_t(&desc, (size_t)slots * nball)) ||
-          (s = dalloc_t(&bprel, (size_t)slots * maxbp * 7)) || (s = dalloc_t(&wout, (size_t)npend * nball)) ||
+          (s = dalloc_t(&bprel, (size_t)slots * maxbp * 8)) || (s = dalloc_t(&wout, (size_t)npend * nball)) ||
           (s = dalloc_t(&mout, (size_t)npend * nwords)))
         return s;
       IB_HIP(hipMemcpy(d_tab, tab.data(), tab.size() * 4, hipMemcpyHostToDevice));
