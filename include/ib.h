@@ -215,7 +215,8 @@ ib_status ib_weights_copy(const ib_weights *w, int32_t field, void *dst_host, in
  *   rec_pos_host: host float64 [nrec][ndim] receivers (metres), sampled multilinearly;
  *             shared by all shots.
  * First-order form (weights built with IB_FORM_PV1): the state holds p and the staggered
- *   velocities v_n (rho = 1); the source amplitude is dt * wavelet / h^d.
+ *   velocities v_n (rho = 1); the source amplitude is dt * wavelet / h^d; ndim times the padded
+ *   grid (x rounded up to 32) must stay below 2^32 nodes.
  * Wavefields start at zero; the step counter at 0.
  * Errors: IB_ERR_ARG (positions outside the box or touching exterior nodes, nshots < 1),
  *   IB_ERR_OOM, IB_ERR_HIP. */

@@ -63,8 +63,9 @@ struct ib_state {
   int form = 0, nv = 0;
   void *vbuf = nullptr, *kv = nullptr;
   int64_t nrows_g = 0, nrows_d = 0;
-  int64_t *g_node = nullptr, *g_start = nullptr, *g_enode = nullptr, *d_node = nullptr, *d_start = nullptr,
-          *d_enode = nullptr;
+  int g_lanes = 16, d_lanes = 16;
+  int64_t *g_node = nullptr, *g_start = nullptr, *d_node = nullptr, *d_start = nullptr;
+  uint32_t *g_enode = nullptr, *d_enode = nullptr;   // source node (padded index + field offset)
   void *g_scale = nullptr, *g_w = nullptr, *d_scale = nullptr, *d_w = nullptr;
   // host copies needed by the adjoint
   std::vector<double> ax, ay, az;
@@ -763,6 +764,11 @@ ib_status ib_state_create(const ib_weights *w, const double *vel_dev, double dt,
   if (w->form == IB_FORM_PV1) {
     // first-order form: K holds dt c^2 / h at interior p nodes, kv dt / h at interior v nodes
     S->nv = w->ndim;
+    if ((int64_t)S->vol * S->nv >= ((int64_t)1 << 32)) {
+      // modified-row entries address the velocity fields with 32-bit indices
+      set_error("the first-order form needs ndim * padded grid < 2^32 nodes");
+      return fail(IB_ERR_ARG);
+    }
     const size_t vbytes = (size_t)S->vol * S->nv * nshots * S->esz;
     if ((s = dalloc(&S->vbuf, vbytes)) || (s = dalloc(&S->kv, (size_t)S->vol * S->nv * S->esz))) return fail(s);
     IB_HIP(hipMemsetAsync(S->vbuf, 0, vbytes, st));
@@ -820,14 +826,24 @@ ib_status ib_state_create(const ib_weights *w, const double *vel_dev, double dt,
     }
     S->nrows_g = (int64_t)gn.size();
     S->nrows_d = (int64_t)dn.size();
+    // rows of fewer than 40 entries on average take 8 lanes each (more rows per wavefront)
+    S->g_lanes = (gn.empty() || ge.size() >= 40 * gn.size()) ? 16 : 8;
+    S->d_lanes = (dn.empty() || de.size() >= 40 * dn.size()) ? 16 : 8;
     auto up64 = [&](const std::vector<int64_t> &v, int64_t **d) -> ib_status {
       ib_status e = dalloc_t(d, std::max<size_t>(v.size(), 1));
       if (e) return e;
       if (!v.empty()) IB_HIP(hipMemcpy(*d, v.data(), v.size() * 8, hipMemcpyHostToDevice));
       return IB_OK;
     };
-    if ((s = up64(gn, &S->g_node)) || (s = up64(gs, &S->g_start)) || (s = up64(ge, &S->g_enode)) ||
-        (s = up64(dn, &S->d_node)) || (s = up64(ds, &S->d_start)) || (s = up64(de, &S->d_enode)) ||
+    auto up32 = [&](const std::vector<int64_t> &v, uint32_t **d) -> ib_status {
+      std::vector<uint32_t> n32(v.begin(), v.end());
+      ib_status e = dalloc_t(d, std::max<size_t>(n32.size(), 1));
+      if (e) return e;
+      if (!n32.empty()) IB_HIP(hipMemcpy(*d, n32.data(), n32.size() * 4, hipMemcpyHostToDevice));
+      return IB_OK;
+    };
+    if ((s = up64(gn, &S->g_node)) || (s = up64(gs, &S->g_start)) || (s = up32(ge, &S->g_enode)) ||
+        (s = up64(dn, &S->d_node)) || (s = up64(ds, &S->d_start)) || (s = up32(de, &S->d_enode)) ||
         (s = upload_cast(gsc.empty() ? std::vector<double>(1, 0.0) : gsc, &S->g_scale)) ||
         (s = upload_cast(gw.empty() ? std::vector<double>(1, 0.0) : gw, &S->g_w)) ||
         (s = upload_cast(dsc.empty() ? std::vector<double>(1, 0.0) : dsc, &S->d_scale)) ||
@@ -1049,6 +1065,8 @@ PVArgs make_pv_args(const ib_state *S) {
   a.v = S->vbuf;
   a.kp = S->K;
   a.kv = S->kv;
+  for (int n = 0; n < 3; ++n) a.vcls[n] = w->vcls[n];
+  a.fv = S->dt / w->h;
   a.sx = S->sx;
   a.sy = S->sy;
   a.sz = S->sz;
@@ -1057,6 +1075,8 @@ PVArgs make_pv_args(const ib_state *S) {
   a.g_node = S->g_node, a.g_start = S->g_start, a.g_enode = S->g_enode;
   a.d_node = S->d_node, a.d_start = S->d_start, a.d_enode = S->d_enode;
   a.g_scale = S->g_scale, a.g_w = S->g_w, a.d_scale = S->d_scale, a.d_w = S->d_w;
+  a.g_lanes = S->g_lanes;
+  a.d_lanes = S->d_lanes;
   return a;
 }
 

@@ -288,25 +288,137 @@ __global__ void k_pv_pressure(T *__restrict__ p, const T *__restrict__ v, const 
   q[c] = ((T(1) - s) * q[c] + kp[c] * div) / (T(1) + s);
 }
 
-// modified rows: dst[row] += scale[row] * sum_k w_k src[k].  A 16-lane row of a wavefront
-// takes one modified row: its lanes read the row's entries together and the partial sums
-// are combined by DPP rotations inside the 16 lanes; shots loop inside.
-template <typename T>
+// 3D forms of the two updates: one thread per (x, y) column of a 64 x 4 tile marching down a
+// chunk of zc planes.  The depth stencil comes from a register queue along z; the lateral
+// stencils read neighbouring columns, which the tile's wavefronts share through the caches.
+// The sums run in the same order as the one-node-per-thread kernels above.
+template <typename T, int H>
+__launch_bounds__(256)
+__global__ void k_pv_velocity3d(T *__restrict__ v, const T *__restrict__ p, const uint8_t *__restrict__ c0,
+                                const uint8_t *__restrict__ c1, const uint8_t *__restrict__ c2, T fv,
+                                const T *__restrict__ sx, const T *__restrict__ sy, const T *__restrict__ sz,
+                                StaggerW<T> W, int nx, int ny, int nz, int64_t pitch, int64_t vol, int zc) {
+  const int x = blockIdx.x * 64 + (threadIdx.x & 63);
+  const int y = blockIdx.y * 4 + (threadIdx.x >> 6);
+  const int nzc = (nz + zc - 1) / zc;
+  const int shot = blockIdx.z / nzc;
+  const int z0 = (blockIdx.z - shot * nzc) * zc;
+  if (x >= nx || y >= ny) return;
+  const int z1 = min(z0 + zc, nz);
+  const int64_t plane = pitch * ny;
+  const T *pp = p + (size_t)shot * vol;
+  int xo[2 * H], yo[2 * H];
+#pragma unroll
+  for (int k = 0; k < 2 * H; ++k) {
+    xo[k] = wrapi(x + k - H + 1, nx);
+    yo[k] = wrapi(y + k - H + 1, ny) * (int)pitch;
+  }
+  T q[2 * H];   // p at z + k - H + 1
+#pragma unroll
+  for (int k = 0; k < 2 * H; ++k) {
+    const int zz = z0 + k - H + 1;
+    q[k] = (zz >= 0 && zz < nz) ? pp[(size_t)zz * plane + (size_t)y * pitch + x] : T(0);
+  }
+  const T sxy = sx[x] + sy[y];
+  T *v0 = v + (size_t)shot * 3 * vol, *v1 = v0 + vol, *v2 = v1 + vol;
+  for (int z = z0; z < z1; ++z) {
+    const T *row = pp + (size_t)z * plane;
+    const size_t c = (size_t)z * plane + (size_t)y * pitch + x;
+    const size_t cu = ((size_t)z * ny + y) * nx + x;   // class arrays are unpadded
+    // dt / h at interior v_n nodes, 0 elsewhere (the coefficient the 2D kernels read)
+    const T k0 = (c0[cu] & 1) ? fv : T(0), k1 = (c1[cu] & 1) ? fv : T(0), k2 = (c2[cu] & 1) ? fv : T(0);
+    T dx = T(0), dy = T(0), dz = T(0);
+#pragma unroll
+    for (int k = 0; k < 2 * H; ++k) dx += W.w[k] * row[(size_t)y * pitch + xo[k]];
+#pragma unroll
+    for (int k = 0; k < 2 * H; ++k) dy += W.w[k] * row[(size_t)yo[k] + x];
+#pragma unroll
+    for (int k = 0; k < 2 * H; ++k) dz += W.w[k] * q[k];
+    const T s = sxy + sz[z];
+    v0[c] = ((T(1) - s) * v0[c] + k0 * dx) / (T(1) + s);
+    v1[c] = ((T(1) - s) * v1[c] + k1 * dy) / (T(1) + s);
+    v2[c] = ((T(1) - s) * v2[c] + k2 * dz) / (T(1) + s);
+#pragma unroll
+    for (int k = 0; k < 2 * H - 1; ++k) q[k] = q[k + 1];
+    const int zn = z + H + 1;
+    q[2 * H - 1] = (zn < nz) ? pp[(size_t)zn * plane + (size_t)y * pitch + x] : T(0);
+  }
+}
+
+template <typename T, int H>
+__launch_bounds__(256)
+__global__ void k_pv_pressure3d(T *__restrict__ p, const T *__restrict__ v, const T *__restrict__ kp,
+                                const T *__restrict__ sx, const T *__restrict__ sy, const T *__restrict__ sz,
+                                StaggerW<T> W, int nx, int ny, int nz, int64_t pitch, int64_t vol, int zc) {
+  const int x = blockIdx.x * 64 + (threadIdx.x & 63);
+  const int y = blockIdx.y * 4 + (threadIdx.x >> 6);
+  const int nzc = (nz + zc - 1) / zc;
+  const int shot = blockIdx.z / nzc;
+  const int z0 = (blockIdx.z - shot * nzc) * zc;
+  if (x >= nx || y >= ny) return;
+  const int z1 = min(z0 + zc, nz);
+  const int64_t plane = pitch * ny;
+  const T *v0 = v + (size_t)shot * 3 * vol, *v1 = v0 + vol, *v2 = v1 + vol;
+  int xo[2 * H], yo[2 * H];
+#pragma unroll
+  for (int k = 0; k < 2 * H; ++k) {
+    xo[k] = wrapi(x + k - H, nx);
+    yo[k] = wrapi(y + k - H, ny) * (int)pitch;
+  }
+  T q[2 * H];   // v_z at z + k - H
+#pragma unroll
+  for (int k = 0; k < 2 * H; ++k) {
+    const int zz = z0 + k - H;
+    q[k] = (zz >= 0 && zz < nz) ? v2[(size_t)zz * plane + (size_t)y * pitch + x] : T(0);
+  }
+  const T sxy = sx[x] + sy[y];
+  T *pp = p + (size_t)shot * vol;
+  for (int z = z0; z < z1; ++z) {
+    const size_t rz = (size_t)z * plane;
+    const size_t c = rz + (size_t)y * pitch + x;
+    T div = T(0);
+#pragma unroll
+    for (int k = 0; k < 2 * H; ++k) div += W.w[k] * v0[rz + (size_t)y * pitch + xo[k]];
+#pragma unroll
+    for (int k = 0; k < 2 * H; ++k) div += W.w[k] * v1[rz + (size_t)yo[k] + x];
+#pragma unroll
+    for (int k = 0; k < 2 * H; ++k) div += W.w[k] * q[k];
+    const T s = sxy + sz[z];
+    pp[c] = ((T(1) - s) * pp[c] + kp[c] * div) / (T(1) + s);
+#pragma unroll
+    for (int k = 0; k < 2 * H - 1; ++k) q[k] = q[k + 1];
+    const int zn = z + H;
+    q[2 * H - 1] = (zn < nz) ? v2[(size_t)zn * plane + (size_t)y * pitch + x] : T(0);
+  }
+}
+
+// modified rows: dst[row] += scale[row] * sum_k w_k src[k].  A group of L lanes (8 or 16)
+// takes one modified row: its lanes read the row's entries together, two entries per lane in
+// flight, and the partial sums are combined by DPP inside the group; shots loop inside.
+template <typename T, int L>
 __launch_bounds__(256)
 __global__ void k_pv_rows(T *__restrict__ dst, int64_t dst_shot_stride, const T *__restrict__ src,
                           int64_t src_shot_stride, const int64_t *__restrict__ rnode, const T *__restrict__ rscale,
-                          const int64_t *__restrict__ rstart, const int64_t *__restrict__ enode,
+                          const int64_t *__restrict__ rstart, const uint32_t *__restrict__ enode,
                           const T *__restrict__ ew, int64_t nrows, int nshots) {
-  const int sub = threadIdx.x & 15;
-  const int64_t r = (int64_t)blockIdx.x * (blockDim.x >> 4) + (threadIdx.x >> 4);
+  const int sub = threadIdx.x & (L - 1);
+  const int64_t r = (int64_t)blockIdx.x * (blockDim.x / L) + threadIdx.x / L;
   const bool live = r < nrows;
-  // rows stay complete (no early return) so that the DPP rotations see all 16 lanes
+  // rows stay complete (no early return) so that the DPP exchanges see all lanes
   const int64_t a = live ? rstart[r] : 0, b = live ? rstart[r + 1] : 0;
   for (int s = 0; s < nshots; ++s) {
     const T *ss = src + (size_t)s * src_shot_stride;
-    T acc = T(0);
-    for (int64_t k = a + sub; k < b; k += 16) acc += ew[k] * ss[enode[k]];
-    acc = row_sum16(acc);
+    T acc = T(0), acc1 = T(0);
+    int64_t k = a + sub;
+    for (; k + L < b; k += 2 * L) {
+      const uint32_t e0 = enode[k], e1 = enode[k + L];
+      const T w0 = ew[k], w1 = ew[k + L];
+      const T p0 = ss[e0], p1 = ss[e1];
+      acc += w0 * p0;
+      acc1 += w1 * p1;
+    }
+    if (k < b) acc += ew[k] * ss[enode[k]];
+    acc = (L == 16) ? row_sum16(acc + acc1) : row_sum8(acc + acc1);
     if (live && sub == 0) dst[(size_t)s * dst_shot_stride + rnode[r]] += rscale[r] * acc;
   }
 }
@@ -326,18 +438,44 @@ static void pv_step_h(const PVArgs &a, hipStream_t st) {
   const StaggerW<T> W = stagger_weights<T>(a.M);
   dim3 b(256);
   dim3 gv((unsigned)((per * a.nv * a.nshots + 255) / 256)), gp((unsigned)((per * a.nshots + 255) / 256));
-  hipLaunchKernelGGL((k_pv_velocity<T, H>), gv, b, 0, st, (T *)a.v, (const T *)a.p, (const T *)a.kv, (const T *)a.sx,
-                     (const T *)a.sy, (const T *)a.sz, W, a.nx, a.ny, a.nz, a.pitch, a.vol, a.nv, a.ndim, a.nshots);
-  if (a.nrows_g > 0)
-    hipLaunchKernelGGL(k_pv_rows<T>, dim3((unsigned)((a.nrows_g + 15) / 16)), b, 0, st, (T *)a.v,
-                       (int64_t)a.nv * a.vol, (const T *)a.p, a.vol, a.g_node, (const T *)a.g_scale, a.g_start,
-                       a.g_enode, (const T *)a.g_w, a.nrows_g, a.nshots);
-  hipLaunchKernelGGL((k_pv_pressure<T, H>), gp, b, 0, st, (T *)a.p, (const T *)a.v, (const T *)a.kp, (const T *)a.sx,
-                     (const T *)a.sy, (const T *)a.sz, W, a.nx, a.ny, a.nz, a.pitch, a.vol, a.nv, a.ndim, a.nshots);
-  if (a.nrows_d > 0)
-    hipLaunchKernelGGL(k_pv_rows<T>, dim3((unsigned)((a.nrows_d + 15) / 16)), b, 0, st, (T *)a.p, a.vol,
-                       (const T *)a.v, (int64_t)a.nv * a.vol, a.d_node, (const T *)a.d_scale, a.d_start, a.d_enode,
-                       (const T *)a.d_w, a.nrows_d, a.nshots);
+  const int zc = 32;
+  const dim3 g3((unsigned)((a.nx + 63) / 64), (unsigned)((a.ny + 3) / 4),
+                (unsigned)(((a.nz + zc - 1) / zc) * a.nshots));
+  if (a.ndim == 3)
+    hipLaunchKernelGGL((k_pv_velocity3d<T, H>), g3, b, 0, st, (T *)a.v, (const T *)a.p, a.vcls[0], a.vcls[1],
+                       a.vcls[2], (T)a.fv, (const T *)a.sx, (const T *)a.sy, (const T *)a.sz, W, a.nx, a.ny, a.nz,
+                       a.pitch, a.vol, zc);
+  else
+    hipLaunchKernelGGL((k_pv_velocity<T, H>), gv, b, 0, st, (T *)a.v, (const T *)a.p, (const T *)a.kv,
+                       (const T *)a.sx, (const T *)a.sy, (const T *)a.sz, W, a.nx, a.ny, a.nz, a.pitch, a.vol, a.nv,
+                       a.ndim, a.nshots);
+  if (a.nrows_g > 0) {
+    if (a.g_lanes == 8)
+      hipLaunchKernelGGL((k_pv_rows<T, 8>), dim3((unsigned)((a.nrows_g + 31) / 32)), b, 0, st, (T *)a.v,
+                         (int64_t)a.nv * a.vol, (const T *)a.p, a.vol, a.g_node, (const T *)a.g_scale, a.g_start,
+                         a.g_enode, (const T *)a.g_w, a.nrows_g, a.nshots);
+    else
+      hipLaunchKernelGGL((k_pv_rows<T, 16>), dim3((unsigned)((a.nrows_g + 15) / 16)), b, 0, st, (T *)a.v,
+                         (int64_t)a.nv * a.vol, (const T *)a.p, a.vol, a.g_node, (const T *)a.g_scale, a.g_start,
+                         a.g_enode, (const T *)a.g_w, a.nrows_g, a.nshots);
+  }
+  if (a.ndim == 3)
+    hipLaunchKernelGGL((k_pv_pressure3d<T, H>), g3, b, 0, st, (T *)a.p, (const T *)a.v, (const T *)a.kp,
+                       (const T *)a.sx, (const T *)a.sy, (const T *)a.sz, W, a.nx, a.ny, a.nz, a.pitch, a.vol, zc);
+  else
+    hipLaunchKernelGGL((k_pv_pressure<T, H>), gp, b, 0, st, (T *)a.p, (const T *)a.v, (const T *)a.kp,
+                       (const T *)a.sx, (const T *)a.sy, (const T *)a.sz, W, a.nx, a.ny, a.nz, a.pitch, a.vol, a.nv,
+                       a.ndim, a.nshots);
+  if (a.nrows_d > 0) {
+    if (a.d_lanes == 8)
+      hipLaunchKernelGGL((k_pv_rows<T, 8>), dim3((unsigned)((a.nrows_d + 31) / 32)), b, 0, st, (T *)a.p, a.vol,
+                         (const T *)a.v, (int64_t)a.nv * a.vol, a.d_node, (const T *)a.d_scale, a.d_start,
+                         a.d_enode, (const T *)a.d_w, a.nrows_d, a.nshots);
+    else
+      hipLaunchKernelGGL((k_pv_rows<T, 16>), dim3((unsigned)((a.nrows_d + 15) / 16)), b, 0, st, (T *)a.p, a.vol,
+                         (const T *)a.v, (int64_t)a.nv * a.vol, a.d_node, (const T *)a.d_scale, a.d_start,
+                         a.d_enode, (const T *)a.d_w, a.nrows_d, a.nshots);
+  }
 }
 
 template <typename T>

@@ -75,10 +75,14 @@ struct PVArgs {
   int nshots;
   void *p, *v;                 // p [shot][vol], v [shot][nv][vol]
   const void *kp, *kv;         // dt c^2 / h at interior p nodes; dt / h at interior v nodes [nv][vol]
+  const uint8_t *vcls[3];      // classes of the v_n nodes ([z][y][x], bit0 interior): the 3D
+  double fv;                   // kernels use (class & 1) * dt / h in place of kv
   const void *sx, *sy, *sz;
   int64_t nrows_g, nrows_d;    // gradient rows (into v), divergence rows (into p)
-  const int64_t *g_node, *g_start, *g_enode, *d_node, *d_start, *d_enode;
+  const int64_t *g_node, *g_start, *d_node, *d_start;
+  const uint32_t *g_enode, *d_enode;   // entry source nodes: padded index + field * vol (< 2^32)
   const void *g_scale, *g_w, *d_scale, *d_w;
+  int g_lanes, d_lanes;        // lanes per modified row (8 for short rows, else 16)
 };
 void enqueue_pv_step(const PVArgs &a, hipStream_t st);
 void enqueue_interior_only(const StepArgs &a, hipStream_t st);

@@ -46,4 +46,14 @@ __device__ __forceinline__ T row_sum16(T v) {
   return v;
 }
 
+// sum over each 8-lane group (lanes 8k .. 8k+7), returned in every lane of the group:
+// half-row mirror pairs lane i with 7 - i, then two quad permutations combine the pairs
+template <typename T>
+__device__ __forceinline__ T row_sum8(T v) {
+  v += dpp_mov<0x141>(v);   // row_half_mirror
+  v += dpp_mov<0x4E>(v);    // quad_perm [2, 3, 0, 1]
+  v += dpp_mov<0xB1>(v);    // quad_perm [1, 0, 3, 2]
+  return v;
+}
+
 }  // namespace ib
