@@ -159,27 +159,45 @@ ib_status adjoint_table_build(ib_weights *w, hipStream_t st) {
 // ---- per-step kernels --------------------------------------------------------------
 // D_j = 1 / (1 + s_j) at the receiving nodes (per state: the damping is the state's)
 template <typename T>
-__global__ void k_adj_D(const uint32_t *__restrict__ jnode, int64_t nj, const T *__restrict__ sx,
-                        const T *__restrict__ sy, const T *__restrict__ sz, int ny, int64_t pitch, T *__restrict__ D) {
+__global__ void k_adj_D(const uint32_t *__restrict__ jnode, int64_t nj, const T *__restrict__ K,
+                        const T *__restrict__ sx, const T *__restrict__ sy, const T *__restrict__ sz, int ny,
+                        int64_t pitch, T *__restrict__ D) {
   int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= nj) return;
   const int64_t q = jnode[j];
   const int x = (int)(q % pitch);
   const int64_t r = q / pitch;
   const int y = (int)(r % ny), z = (int)(r / ny);
-  D[j] = T(1) / (T(1) + sx[x] + sy[y] + sz[z]);
+  D[j] = K[q] / (T(1) + sx[x] + sy[y] + sz[z]);
 }
 
-void enqueue_adj_D(int prec, const uint32_t *jnode, int64_t nj, const void *sx, const void *sy, const void *sz, int ny,
-                   int64_t pitch, void *D, hipStream_t st) {
+// receiving-node factor K_j / (1 + s_j) of the transposed IB rows (the adjoint runs on
+// mu = K lambda)
+void enqueue_adj_D(int prec, const uint32_t *jnode, int64_t nj, const void *K, const void *sx, const void *sy,
+                   const void *sz, int ny, int64_t pitch, void *D, hipStream_t st) {
   if (nj <= 0) return;
   dim3 g((unsigned)((nj + 255) / 256)), b(256);
   if (prec == IB_F32)
-    hipLaunchKernelGGL(k_adj_D<float>, g, b, 0, st, jnode, nj, (const float *)sx, (const float *)sy,
-                       (const float *)sz, ny, pitch, (float *)D);
+    hipLaunchKernelGGL(k_adj_D<float>, g, b, 0, st, jnode, nj, (const float *)K, (const float *)sx,
+                       (const float *)sy, (const float *)sz, ny, pitch, (float *)D);
   else
-    hipLaunchKernelGGL(k_adj_D<double>, g, b, 0, st, jnode, nj, (const double *)sx, (const double *)sy,
-                       (const double *)sz, ny, pitch, (double *)D);
+    hipLaunchKernelGGL(k_adj_D<double>, g, b, 0, st, jnode, nj, (const double *)K, (const double *)sx,
+                       (const double *)sy, (const double *)sz, ny, pitch, (double *)D);
+}
+
+template <typename T>
+__global__ void k_scale_by_K(T *__restrict__ v, const int64_t *__restrict__ node, int64_t n, const T *__restrict__ K) {
+  int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j < n) v[j] *= K[node[j]];
+}
+
+void enqueue_scale_by_K(int prec, void *v, const int64_t *node, int64_t n, const void *K, hipStream_t st) {
+  if (n <= 0) return;
+  dim3 g((unsigned)((n + 255) / 256)), b(256);
+  if (prec == IB_F32)
+    hipLaunchKernelGGL(k_scale_by_K<float>, g, b, 0, st, (float *)v, node, n, (const float *)K);
+  else
+    hipLaunchKernelGGL(k_scale_by_K<double>, g, b, 0, st, (double *)v, node, n, (const double *)K);
 }
 
 }  // namespace ib

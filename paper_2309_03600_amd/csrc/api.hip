@@ -1152,7 +1152,7 @@ ib_status build_adjoint_tables(ib_state *S, hipStream_t st) {
   if ((s = dalloc(&S->jD, std::max<int64_t>(S->nj, 1) * sizeof(T))) ||
       (s = dalloc(&S->ibvals, std::max<int64_t>(w->nib * S->nshots, 1) * sizeof(T))))
     return s;
-  enqueue_adj_D(S->prec, w->adj_jnode, S->nj, S->sx, S->sy, S->sz, (int)ny, pitch, S->jD, st);
+  enqueue_adj_D(S->prec, w->adj_jnode, S->nj, S->K, S->sx, S->sy, S->sz, (int)ny, pitch, S->jD, st);
   IB_HIP(hipGetLastError());
   // receivers: node -> (receiver, weight)
   struct RE {
@@ -1191,6 +1191,10 @@ ib_status build_adjoint_tables(ib_state *S, hipStream_t st) {
     IB_HIP(hipMemcpy(S->rrec, rr.data(), rr.size() * 4, hipMemcpyHostToDevice));
     IB_HIP(hipMemcpy(S->rD, rd.data(), rd.size() * sizeof(T), hipMemcpyHostToDevice));
     IB_HIP(hipMemcpy(S->rwt, rwv.data(), rwv.size() * sizeof(T), hipMemcpyHostToDevice));
+    // the adjoint runs on mu = K lambda: receiver rows carry K_j / (1 + s_j)
+    enqueue_scale_by_K(S->prec, S->rD, S->rnode, (int64_t)rn.size(), S->K, st);
+    IB_HIP(hipGetLastError());
+    IB_HIP(hipStreamSynchronize(st));
   }
   IB_HIP(hipMemcpy(S->roff, ro.data(), ro.size() * 8, hipMemcpyHostToDevice));
   S->adj_ready = true;
@@ -1290,7 +1294,8 @@ ib_status ib_adjoint(ib_state *S, const void *residual, const void *wavelet, int
     dfree(seg);
     dfree(gK);
   };
-  if ((s = dalloc(&lam[0], fbytes)) || (s = dalloc(&lam[1], fbytes)) || (s = dalloc(&seg, fbytes * C)) ||
+  // seg holds u^{t0-1} .. u^{t0+len} of the segment being reversed (C + 2 fields)
+  if ((s = dalloc(&lam[0], fbytes)) || (s = dalloc(&lam[1], fbytes)) || (s = dalloc(&seg, fbytes * (C + 2))) ||
       (s = dalloc_t(&gK, S->vol))) {
     cleanup();
     return s;
@@ -1298,22 +1303,29 @@ ib_status ib_adjoint(ib_state *S, const void *residual, const void *wavelet, int
   IB_HIP(hipMemsetAsync(lam[0], 0, fbytes, st));
   IB_HIP(hipMemsetAsync(lam[1], 0, fbytes, st));
   IB_HIP(hipMemsetAsync(gK, 0, S->vol * sizeof(double), st));
-  int a1 = 0, a2 = 1;   // lam[a1] = lambda^{m+1}, lam[a2] = lambda^{m+2}
+  int a1 = 0, a2 = 1;   // lam[a1] = mu^{m+1}, lam[a2] = mu^{m+2}
+  auto field = [&](int64_t q) { return (char *)seg + (size_t)q * fbytes; };
   for (int64_t k = S->ck_count - 1; k >= 0; --k) {
     const int64_t t0 = k * C, len = std::min<int64_t>(C, nt - t0);
     char *ck = (char *)S->ckpt + (size_t)k * 2 * fbytes;
     IB_HIP(hipMemcpyAsync(S->buf[S->cur], ck, fbytes, hipMemcpyDeviceToDevice, st));
     IB_HIP(hipMemcpyAsync(S->buf[1 - S->cur], ck + fbytes, fbytes, hipMemcpyDeviceToDevice, st));
     S->t = t0;
-    IB_HIP(hipMemcpyAsync(seg, S->buf[S->cur], fbytes, hipMemcpyDeviceToDevice, st));
-    for (int64_t q = 1; q < len; ++q) {
+    IB_HIP(hipMemcpyAsync(field(0), ck + fbytes, fbytes, hipMemcpyDeviceToDevice, st));
+    IB_HIP(hipMemcpyAsync(field(1), ck, fbytes, hipMemcpyDeviceToDevice, st));
+    for (int64_t q = 1; q <= len; ++q) {
       if ((s = run_steps(S, 1, wavelet, wstride, nullptr, 0, 0, false, st))) {
         cleanup();
         return s;
       }
-      IB_HIP(hipMemcpyAsync((char *)seg + q * fbytes, S->buf[S->cur], fbytes, hipMemcpyDeviceToDevice, st));
+      IB_HIP(hipMemcpyAsync(field(q + 1), S->buf[S->cur], fbytes, hipMemcpyDeviceToDevice, st));
     }
     for (int64_t m = t0 + len; m >= t0 + 1; --m) {
+      // interior part: the forward interior kernel on mu (mu^{m+2} is overwritten by mu^m)
+      StepArgs sa = make_args(S, nullptr, 0, nullptr, 0, S->cur);
+      sa.un = lam[a1];
+      sa.um = lam[a2];
+      enqueue_interior_only(sa, st);
       AdjArgs a{};
       a.prec = S->prec;
       a.ndim = w->ndim;
@@ -1338,6 +1350,7 @@ ib_status ib_adjoint(ib_state *S, const void *residual, const void *wavelet, int
       a.jw = (S->prec == IB_F32) ? (const void *)w->adj_jw32 : (const void *)w->adj_jw64;
       a.ibxyz = w->ib_xyz;
       a.vals = S->ibvals;
+      a.nib = w->nib;
       a.nrn = S->nrn;
       a.rnode = S->rnode;
       a.roff = S->roff;
@@ -1349,13 +1362,13 @@ ib_status ib_adjoint(ib_state *S, const void *residual, const void *wavelet, int
       a.nrec = S->nrec;
       a.step = m - 1;
       a.gK = gK;
-      a.u = (char *)seg + (m - 1 - t0) * fbytes;
-      a.nib = w->nib;
-      a.rec = (S->prec == IB_F32) ? w->rec32 : w->rec64;
-      a.pinfo = S->pinfo;
-      a.ball = w->ball;
-      a.delta = S->delta;
-      a.ball_meta = w->ball_meta;
+      a.u2 = field(m - t0 + 1);   // u^m
+      a.u1 = field(m - t0);       // u^{m-1}
+      a.u0 = field(m - t0 - 1);   // u^{m-2}
+      a.sidx = S->sidx;
+      a.sw = S->sw;
+      a.wavelet = wavelet;
+      a.wstride = wstride;
       enqueue_adjoint_step(a, st);
       std::swap(a1, a2);
     }

@@ -99,35 +99,37 @@ struct AdjArgs {
   int nx, ny, nz;
   int64_t pitch, vol;
   int nshots;
-  const void *lam1;      // lambda^{m+1}
-  void *lam2;            // lambda^{m+2} in, lambda^m out
+  const void *lam1;      // mu^{m+1} = K lambda^{m+1}
+  void *lam2;            // mu^m after the interior stencil (the forward kernel on mu)
   const void *K, *sx, *sy, *sz;
   // transposed IB rows (receiving nodes, run offsets, IB point and weight per entry)
   int64_t nj;
   const uint32_t *jnode, *joff, *jsrc;
-  const void *jD, *jw;
+  const void *jD, *jw;   // jD = K_j / (1 + s_j) at the receiving node
   const int16_t *ibxyz;  // IB points (x, y, z, code)
-  void *vals;            // scratch [nib][nshots]: K lambda^{m+1} at the IB points
+  void *vals;            // scratch [nib][nshots]: mu^{m+1} at the IB points
+  int64_t nib;
   // transposed receivers
   int64_t nrn;
   const int64_t *rnode, *roff;
   const int32_t *rrec;
-  const void *rD, *rw;
+  const void *rD, *rw;   // rD = K_j / (1 + s_j)
   const void *res;       // [nshots][nt][nrec]
   int64_t nt;
   int nrec;
   int64_t step;          // m - 1
-  // gradient
+  // gradient: gK += mu^m (K L u^{m-1}), K L u^{m-1} recovered from three time levels;
+  // dJ/dK = gK / K^2
   double *gK;
-  const void *u;         // u^{m-1}
-  int64_t nib;
-  const uint32_t *rec;
-  const void *pinfo;
-  const int32_t *ball, *delta, *ball_meta;
+  const void *u2, *u1, *u0;   // u^m, u^{m-1}, u^{m-2}
+  const int64_t *sidx;   // source injection of step m - 1 (subtracted from the recovery)
+  const void *sw, *wavelet;
+  int64_t wstride;
 };
 void enqueue_adjoint_step(const AdjArgs &a, hipStream_t st);
-void enqueue_adj_D(int prec, const uint32_t *jnode, int64_t nj, const void *sx, const void *sy, const void *sz, int ny,
-                   int64_t pitch, void *D, hipStream_t st);
+void enqueue_adj_D(int prec, const uint32_t *jnode, int64_t nj, const void *K, const void *sx, const void *sy,
+                   const void *sz, int ny, int64_t pitch, void *D, hipStream_t st);
+void enqueue_scale_by_K(int prec, void *v, const int64_t *node, int64_t n, const void *K, hipStream_t st);
 ib_status adjoint_table_build(ib_weights *w, hipStream_t st);
 void enqueue_grad_out(int prec, const double *gK, const void *K, double *out, int nx, int ny, int nz, int64_t pitch,
                       double dt_over_h, hipStream_t st);

@@ -1115,67 +1115,36 @@ void enqueue_patch_only(const StepArgs &a, hipStream_t st) {
 }
 
 // ---- discrete adjoint ----------------------------------------------------------------
-// With D = 1/(1+s), the adjoint of the damped leapfrog (scaled lambda = D mu) is the same
+// With D = 1/(1+s), the adjoint of the damped leapfrog (scaled lambda = D mu') is the same
 // recurrence with L^T K in place of K L:
 //   lambda^m = D [2 lambda^{m+1} - (1 - s) lambda^{m+2} + L^T (K lambda^{m+1}) + R^T res^{m-1}],
-// and dJ/dK = sum_m lambda^m (L u^{m-1}).  The standard part of L is symmetric, so its
-// transpose is the same stencil applied to K lambda; the IB rows are transposed through a
-// per-receiving-node table (a gather, deterministic, no atomics).
-template <typename T, int H>
-__global__ void k_adj_interior(const T *__restrict__ lam1, T *__restrict__ lam2, const T *__restrict__ K,
-                               const T *__restrict__ sx, const T *__restrict__ sy, const T *__restrict__ sz,
-                               StencilW<T> W, int nx, int ny, int nz, int lat, int64_t pitch, int64_t vol,
-                               int nshots) {
-  const int64_t per = (int64_t)nx * ny * nz;
-  int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (g >= per * nshots) return;
-  const int shot = (int)(g / per);
-  int64_t i = g % per;
-  const int x = (int)(i % nx);
-  i /= nx;
-  const int y = (int)(i % ny);
-  const int z = (int)(i / ny);
-  const int64_t plane = pitch * ny;
-  const T *u = lam1 + (size_t)shot * vol;
-  T *o = lam2 + (size_t)shot * vol;
-  const size_t c = (size_t)z * plane + (size_t)y * pitch + x;
-  const T uc = u[c];
-  T lap = T(lat + 1) * W.w[0] * (K[c] * uc);
-  for (int k = 1; k <= H; ++k) {
-    size_t a0 = (size_t)z * plane + (size_t)y * pitch + wrapk(x - k, nx);
-    size_t a1 = (size_t)z * plane + (size_t)y * pitch + wrapk(x + k, nx);
-    T acc = K[a0] * u[a0] + K[a1] * u[a1];
-    if (lat == 2) {
-      size_t b0 = (size_t)z * plane + (size_t)wrapk(y - k, ny) * pitch + x;
-      size_t b1 = (size_t)z * plane + (size_t)wrapk(y + k, ny) * pitch + x;
-      acc += K[b0] * u[b0] + K[b1] * u[b1];
-    }
-    if (z - k >= 0) acc += K[c - (size_t)k * plane] * u[c - (size_t)k * plane];
-    if (z + k < nz) acc += K[c + (size_t)k * plane] * u[c + (size_t)k * plane];
-    lap += W.w[k] * acc;
-  }
-  const T s = sx[x] + sy[y] + sz[z];
-  o[c] = (T(2) * uc - (T(1) - s) * o[c] + lap) / (T(1) + s);
-}
+// and dJ/dK = sum_m lambda^m (L u^{m-1}).  The adjoint runs on mu = K lambda: multiplying by
+// K gives mu^m = D [2 mu^{m+1} - (1 - s) mu^{m+2} + K L_std(mu^{m+1})] + K D (IB^T mu^{m+1} +
+// R^T res^{m-1}), because the standard stencil is symmetric.  The first part is the forward
+// interior kernel applied to mu; the IB rows are transposed through a per-receiving-node
+// table (a gather, deterministic, no atomics) and the receivers likewise, both with the
+// factor K_j D_j.  (lambda and mu differ only where K = 0, where lambda never feeds back.)
+// The gradient needs L u^{m-1} with the IB rows; the forward step gives it pointwise:
+//   K L u^{m-1} = (1 + s) u^m - 2 u^{m-1} + (1 - s) u^{m-2} - (1 + s) (source injected into u^m),
+// so with lambda = mu / K, dJ/dK = (sum_m mu^m (K L u^{m-1})) / K^2: the sum is accumulated
+// in FP64 and divided once at the end.
 
-// v[i][s] = K_i lambda^{m+1}_{s,i} at the IB points (shots fastest), for the gather below
+// v[i][s] = mu^{m+1}_{s,i} at the IB points (shots fastest), for the gather below
 template <typename T>
-__global__ void k_adj_ibvals(T *__restrict__ v, const T *__restrict__ lam1, const T *__restrict__ K,
-                             const int16_t *__restrict__ xyz, int64_t nib, int nshots, int ny, int64_t pitch,
-                             int64_t vol) {
+__global__ void k_adj_ibvals(T *__restrict__ v, const T *__restrict__ lam1, const int16_t *__restrict__ xyz,
+                             int64_t nib, int nshots, int ny, int64_t pitch, int64_t vol) {
   int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= nib * nshots) return;
   const int64_t i = e / nshots;
   const int s = (int)(e - i * nshots);
   const size_t q = ((size_t)xyz[i * 4 + 2] * ny + xyz[i * 4 + 1]) * pitch + xyz[i * 4];
-  v[e] = K[q] * lam1[(size_t)s * vol + q];
+  v[e] = lam1[(size_t)s * vol + q];
 }
 
-// lambda^m_j += D_j sum_k w_k v[i_k] over the IB points i_k whose rows use node j, for SC
+// mu^m_j += (K D)_j sum_k w_k v[i_k] over the IB points i_k whose rows use node j, for SC
 // shots at a time.  A 16-lane row of a wavefront takes one receiving node: its lanes read
 // the node's run of (point, weight) entries together (coalesced), gather v, and the row's
 // partial sums are combined with DPP rotations inside the row.
-
 template <typename T, int SC>
 __launch_bounds__(256)
 __global__ void k_adj_gather(T *__restrict__ lam, const T *__restrict__ v, const uint32_t *__restrict__ jnode,
@@ -1207,7 +1176,7 @@ __global__ void k_adj_gather(T *__restrict__ lam, const T *__restrict__ v, const
     lam[(size_t)(s0 + sub) * vol + jnode[j]] += jD[j] * mine;
 }
 
-// lambda^m_j += D_j sum over receivers using node j of w * res^{m-1}
+// mu^m_j += (K D)_j sum over receivers using node j of w * res^{m-1}
 template <typename T>
 __global__ void k_adj_receivers(T *__restrict__ lam, const T *__restrict__ res, int64_t nt, int nrec, int64_t step,
                                 const int64_t *__restrict__ rnode, const T *__restrict__ rD,
@@ -1224,77 +1193,48 @@ __global__ void k_adj_receivers(T *__restrict__ lam, const T *__restrict__ res, 
   }
 }
 
-// g += sum over shots of lambda^m (L_std u^{m-1}) at interior nodes (K != 0)
-template <typename T, int H>
-__global__ void k_grad_std(double *__restrict__ gK, const T *__restrict__ lam, const T *__restrict__ un,
-                           const T *__restrict__ K, StencilW<T> W, int nx, int ny, int nz, int lat, int64_t pitch,
-                           int64_t vol, int nshots) {
-  const int64_t per = (int64_t)nx * ny * nz;
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= per) return;
-  const int x = (int)(i % nx);
-  int64_t r = i / nx;
-  const int y = (int)(r % ny);
-  const int z = (int)(r / ny);
-  const int64_t plane = pitch * ny;
-  const size_t c = (size_t)z * plane + (size_t)y * pitch + x;
+// g += sum over shots of mu^m ((1 + s) u^m - 2 u^{m-1} + (1 - s) u^{m-2}) at interior nodes,
+// in FP64 from the stored time levels; one thread per node of a padded row
+template <typename T>
+__launch_bounds__(256)
+__global__ void k_grad_pt(double *__restrict__ gK, const T *__restrict__ mu, const T *__restrict__ u2,
+                          const T *__restrict__ u1, const T *__restrict__ u0, const T *__restrict__ K,
+                          const T *__restrict__ sx, const T *__restrict__ sy, const T *__restrict__ sz, int nx,
+                          int ny, int64_t pitch, int64_t vol, int nshots) {
+  const int x = blockIdx.x * blockDim.x + threadIdx.x;
+  const int y = blockIdx.y, z = blockIdx.z;
+  if (x >= nx) return;
+  const size_t c = ((size_t)z * ny + y) * pitch + x;
   if (K[c] == T(0)) return;
+  const double s = (double)sx[x] + (double)sy[y] + (double)sz[z];
   double tot = 0.0;
-  for (int s = 0; s < nshots; ++s) {
-    const T *u = un + (size_t)s * vol;
-    T lap = T(lat + 1) * W.w[0] * u[c];
-    for (int k = 1; k <= H; ++k) {
-      T acc = u[(size_t)z * plane + (size_t)y * pitch + wrapk(x - k, nx)] +
-              u[(size_t)z * plane + (size_t)y * pitch + wrapk(x + k, nx)];
-      if (lat == 2)
-        acc += u[(size_t)z * plane + (size_t)wrapk(y - k, ny) * pitch + x] +
-               u[(size_t)z * plane + (size_t)wrapk(y + k, ny) * pitch + x];
-      if (z - k >= 0) acc += u[c - (size_t)k * plane];
-      if (z + k < nz) acc += u[c + (size_t)k * plane];
-      lap += W.w[k] * acc;
-    }
-    tot += (double)lam[(size_t)s * vol + c] * (double)lap;
+  for (int sh = 0; sh < nshots; ++sh) {
+    const size_t q = (size_t)sh * vol + c;
+    const double l = (1.0 + s) * (double)u2[q] - 2.0 * (double)u1[q] + (1.0 - s) * (double)u0[q];
+    tot += (double)mu[q] * l;
   }
   gK[c] += tot;
 }
 
-// g_i += sum over shots of lambda^m_i (sum_j y_ij u^{m-1}_j) at IB points
+// the source injected into u^m is not part of K L u^{m-1}: remove its term (one thread, in
+// order, so the accumulation stays deterministic)
 template <typename T>
-__launch_bounds__(256)
-__global__ void k_grad_ib(double *__restrict__ gK, const T *__restrict__ lam, const T *__restrict__ un,
-                          const uint32_t *__restrict__ rec, const PInfo<T> *__restrict__ pinfo,
-                          const int32_t *__restrict__ ball, const int32_t *__restrict__ delta,
-                          const int32_t *__restrict__ ball_meta, int64_t nib, int nx, int ny, int nz, int64_t pitch,
-                          int64_t vol, int nshots) {
-  const int lane = threadIdx.x & 63;
-  const int64_t blk = xcd_remap(blockIdx.x, gridDim.x);
-  const int64_t i = blk * (blockDim.x >> 6) + (threadIdx.x >> 6);
-  if (i >= nib) return;
-  const PInfo<T> P = pinfo[i];
-  const int x = P.x, y = P.y, z = P.z, code = P.code;
-  const int bstart = ball_meta[2 * code], nb = ball_meta[2 * code + 1];
-  const int nwords = (nb + 31) >> 5;
-  const uint32_t *m = rec + P.roff;
-  const int wpad = (sizeof(T) == 8) ? ((nwords + 1) & ~1) : nwords;
-  const T *wts = reinterpret_cast<const T *>(m + wpad);
-  const uint32_t mw = (lane < nwords) ? m[lane] : 0u;
-  const int64_t plane = pitch * ny;
-  const int R = code / 2 + 1;
-  const bool edge = (x < R || x >= nx - R || (ny > 1 && (y < R || y >= ny - R)));
-  const size_t centre = (size_t)z * plane + (size_t)y * pitch + x;
-  const int ngroups = (nb + 511) / 512;
-  double tot = 0.0;
-  for (int s = 0; s < nshots; ++s) {
-    const T *u = un + (size_t)s * vol;
-    T acc = T(0);
-    int wbase = 0;
-    for (int g = 0; g < ngroups; ++g)
-      patch_group<T, 8>(u, wts, ball + bstart, delta + bstart, mw, g * 8, nb, lane, edge, x, y, z, nx, ny, pitch,
-                        plane, centre, wbase, acc);
-    for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
-    tot += (double)lam[(size_t)s * vol + centre] * (double)acc;
+__global__ void k_grad_src(double *__restrict__ gK, const T *__restrict__ mu, const int64_t *__restrict__ sidx,
+                           const T *__restrict__ sw, const T *__restrict__ wavelet, int64_t wstride, int64_t t,
+                           const T *__restrict__ sx, const T *__restrict__ sy, const T *__restrict__ sz, int ny,
+                           int64_t pitch, int64_t vol, int nshots) {
+  if (blockIdx.x != 0 || threadIdx.x != 0) return;
+  for (int e = 0; e < nshots * 8; ++e) {
+    const int64_t q = sidx[e];
+    if (q < 0) continue;
+    const int sh = e >> 3;
+    const int x = (int)(q % pitch);
+    const int64_t r = q / pitch;
+    const int y = (int)(r % ny), z = (int)(r / ny);
+    const double s = (double)sx[x] + (double)sy[y] + (double)sz[z];
+    const double inj = (double)(wavelet[(size_t)sh * wstride + t] * sw[e]);
+    gK[q] -= (double)mu[(size_t)sh * vol + q] * (1.0 + s) * inj;
   }
-  if (lane == 0) gK[centre] += tot;
 }
 
 template <typename T>
@@ -1309,41 +1249,16 @@ __global__ void k_grad_out(const double *__restrict__ gK, const T *__restrict__ 
   const int z = (int)(r / ny);
   const size_t c = ((size_t)z * ny + y) * pitch + x;
   const double k = (double)K[c];
-  out[i] = (k > 0.0) ? gK[c] * 2.0 * sqrt(k) * dt_over_h : 0.0;
+  // gK holds sum mu (K L u) = K^2 dJ/dK; dK/dc = 2 sqrt(K) dt / h
+  out[i] = (k > 0.0) ? gK[c] / (k * k) * 2.0 * sqrt(k) * dt_over_h : 0.0;
 }
 
 template <typename T>
 static void adjoint_step_t(const AdjArgs &a, hipStream_t st) {
-  const int lat = a.ndim - 1;
-  const int64_t tot = (int64_t)a.nx * a.ny * a.nz * a.nshots;
-  dim3 g((unsigned)((tot + 255) / 256)), b(256);
-  const StencilW<T> W = stencil_weights<T>(a.M);
-  switch (a.M / 2) {
-    case 1:
-      hipLaunchKernelGGL((k_adj_interior<T, 1>), g, b, 0, st, (const T *)a.lam1, (T *)a.lam2, (const T *)a.K,
-                         (const T *)a.sx, (const T *)a.sy, (const T *)a.sz, W, a.nx, a.ny, a.nz, lat, a.pitch, a.vol,
-                         a.nshots);
-      break;
-    case 2:
-      hipLaunchKernelGGL((k_adj_interior<T, 2>), g, b, 0, st, (const T *)a.lam1, (T *)a.lam2, (const T *)a.K,
-                         (const T *)a.sx, (const T *)a.sy, (const T *)a.sz, W, a.nx, a.ny, a.nz, lat, a.pitch, a.vol,
-                         a.nshots);
-      break;
-    case 3:
-      hipLaunchKernelGGL((k_adj_interior<T, 3>), g, b, 0, st, (const T *)a.lam1, (T *)a.lam2, (const T *)a.K,
-                         (const T *)a.sx, (const T *)a.sy, (const T *)a.sz, W, a.nx, a.ny, a.nz, lat, a.pitch, a.vol,
-                         a.nshots);
-      break;
-    default:
-      hipLaunchKernelGGL((k_adj_interior<T, 4>), g, b, 0, st, (const T *)a.lam1, (T *)a.lam2, (const T *)a.K,
-                         (const T *)a.sx, (const T *)a.sy, (const T *)a.sz, W, a.nx, a.ny, a.nz, lat, a.pitch, a.vol,
-                         a.nshots);
-      break;
-  }
   if (a.nj > 0) {
     const int64_t nv = a.nib * a.nshots;
     hipLaunchKernelGGL(k_adj_ibvals<T>, dim3((unsigned)((nv + 255) / 256)), dim3(256), 0, st, (T *)a.vals,
-                       (const T *)a.lam1, (const T *)a.K, a.ibxyz, a.nib, a.nshots, a.ny, a.pitch, a.vol);
+                       (const T *)a.lam1, a.ibxyz, a.nib, a.nshots, a.ny, a.pitch, a.vol);
     const dim3 gj((unsigned)((a.nj + 15) / 16));
     for (int s0 = 0; s0 < a.nshots;) {
       const int left = a.nshots - s0;
@@ -1366,32 +1281,13 @@ static void adjoint_step_t(const AdjArgs &a, hipStream_t st) {
     hipLaunchKernelGGL(k_adj_receivers<T>, dim3((unsigned)((a.nrn + 255) / 256)), dim3(256), 0, st, (T *)a.lam2,
                        (const T *)a.res, a.nt, a.nrec, a.step, a.rnode, (const T *)a.rD, a.roff, a.rrec,
                        (const T *)a.rw, a.nrn, a.nshots, a.vol);
-  const int64_t per = (int64_t)a.nx * a.ny * a.nz;
-  dim3 g2((unsigned)((per + 255) / 256));
-  switch (a.M / 2) {
-    case 1:
-      hipLaunchKernelGGL((k_grad_std<T, 1>), g2, b, 0, st, a.gK, (const T *)a.lam2, (const T *)a.u, (const T *)a.K, W,
-                         a.nx, a.ny, a.nz, lat, a.pitch, a.vol, a.nshots);
-      break;
-    case 2:
-      hipLaunchKernelGGL((k_grad_std<T, 2>), g2, b, 0, st, a.gK, (const T *)a.lam2, (const T *)a.u, (const T *)a.K, W,
-                         a.nx, a.ny, a.nz, lat, a.pitch, a.vol, a.nshots);
-      break;
-    case 3:
-      hipLaunchKernelGGL((k_grad_std<T, 3>), g2, b, 0, st, a.gK, (const T *)a.lam2, (const T *)a.u, (const T *)a.K, W,
-                         a.nx, a.ny, a.nz, lat, a.pitch, a.vol, a.nshots);
-      break;
-    default:
-      hipLaunchKernelGGL((k_grad_std<T, 4>), g2, b, 0, st, a.gK, (const T *)a.lam2, (const T *)a.u, (const T *)a.K, W,
-                         a.nx, a.ny, a.nz, lat, a.pitch, a.vol, a.nshots);
-      break;
-  }
-  if (a.nib > 0) {
-    int64_t nblk = ((a.nib + 3) / 4 + 7) / 8 * 8;
-    hipLaunchKernelGGL(k_grad_ib<T>, dim3((unsigned)nblk), dim3(256), 0, st, a.gK, (const T *)a.lam2,
-                       (const T *)a.u, a.rec, (const PInfo<T> *)a.pinfo, a.ball, a.delta, a.ball_meta, a.nib, a.nx,
-                       a.ny, a.nz, a.pitch, a.vol, a.nshots);
-  }
+  const dim3 gg((unsigned)((a.nx + 255) / 256), (unsigned)a.ny, (unsigned)a.nz);
+  hipLaunchKernelGGL(k_grad_pt<T>, gg, dim3(256), 0, st, a.gK, (const T *)a.lam2, (const T *)a.u2,
+                     (const T *)a.u1, (const T *)a.u0, (const T *)a.K, (const T *)a.sx, (const T *)a.sy,
+                     (const T *)a.sz, a.nx, a.ny, a.pitch, a.vol, a.nshots);
+  hipLaunchKernelGGL(k_grad_src<T>, dim3(1), dim3(64), 0, st, a.gK, (const T *)a.lam2, a.sidx, (const T *)a.sw,
+                     (const T *)a.wavelet, a.wstride, a.step, (const T *)a.sx, (const T *)a.sy, (const T *)a.sz, a.ny,
+                     a.pitch, a.vol, a.nshots);
 }
 
 void enqueue_adjoint_step(const AdjArgs &a, hipStream_t st) {
