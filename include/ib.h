@@ -37,7 +37,7 @@
 extern "C" {
 #endif
 
-#define IB_ABI_VERSION 1
+#define IB_ABI_VERSION 2
 
 typedef enum {
   IB_OK = 0,

@@ -39,7 +39,7 @@ def test_binding_declares_the_same_functions():
 
 def test_abi_version_and_error_text(lib):
     lib.ib_abi_version.restype = ctypes.c_int32
-    assert lib.ib_abi_version() == 1
+    assert lib.ib_abi_version() == 2
     lib.ib_last_error.restype = ctypes.c_char_p
     assert lib.ib_last_error() is not None
 
@@ -51,3 +51,40 @@ def test_argument_errors_without_gpu(lib):
     assert lib.ib_build_weights(None, None, None, None, ctypes.byref(out)) == -1
     lib.ib_step.restype = ctypes.c_int
     assert lib.ib_step(None, 1, None, 0, None, 0, None) == -1
+
+
+def test_struct_layouts_match_the_header(tmp_path):
+    # the binding's ctypes structures against the header, compiled by the host C compiler
+    import shutil
+    import subprocess
+
+    from paper_2309_03600_amd import _lib
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no host C compiler")
+    structs = {"ib_grid": _lib.ib_grid, "ib_params": _lib.ib_params, "ib_stats": _lib.ib_stats}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "ib.h"', "int main(void) {"]
+    for name, cls in structs.items():
+        lines.append(f'  printf("{name} size %zu\\n", sizeof({name}));')
+        for f, _ in cls._fields_:
+            lines.append(f'  printf("{name} {f} %zu\\n", offsetof({name}, {f}));')
+    lines += ["  return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run([cc, "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    got = {}
+    for line in out:
+        if line:
+            name, field, val = line.split()
+            got[(name, field)] = int(val)
+    for name, cls in structs.items():
+        assert got[(name, "size")] == ctypes.sizeof(cls), name
+        for f, _ in cls._fields_:
+            assert got[(name, f)] == getattr(cls, f).offset, (name, f)
+
+
+def test_forcing_rejects_a_null_state_without_gpu(lib):
+    lib.ib_state_set_forcing.restype = ctypes.c_int
+    assert lib.ib_state_set_forcing(None, None, 0, None, 0, None) == -1
