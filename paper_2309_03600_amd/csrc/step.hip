@@ -1216,7 +1216,10 @@ __global__ void k_grad_pt(double *__restrict__ gK, const T *__restrict__ mu, con
   double tot = 0.0;
   for (int sh = 0; sh < nshots; ++sh) {
     const size_t q = (size_t)sh * vol + c;
-    const double l = (1.0 + s) * (double)u2[q] - 2.0 * (double)u1[q] + (1.0 - s) * (double)u0[q];
+    // the three time levels are read once here: non-temporal
+    const double l = (1.0 + s) * (double)__builtin_nontemporal_load(&u2[q]) -
+                     2.0 * (double)__builtin_nontemporal_load(&u1[q]) +
+                     (1.0 - s) * (double)__builtin_nontemporal_load(&u0[q]);
     tot += (double)mu[q] * l;
   }
   gK[c] += tot;
@@ -1268,7 +1271,11 @@ static void adjoint_step_t(const AdjArgs &a, hipStream_t st) {
     const dim3 gj((unsigned)((a.nj + 15) / 16));
     for (int s0 = 0; s0 < a.nshots;) {
       const int left = a.nshots - s0;
-      if (left >= 8) {
+      if (left >= 16) {
+        hipLaunchKernelGGL((k_adj_gather<T, 16>), gj, dim3(256), 0, st, (T *)a.lam2, (const T *)a.vals, a.jnode,
+                           (const T *)a.jD, a.joff, a.jsrc, (const T *)a.jw, a.nj, a.nshots, s0, a.vol);
+        s0 += 16;
+      } else if (left >= 8) {
         hipLaunchKernelGGL((k_adj_gather<T, 8>), gj, dim3(256), 0, st, (T *)a.lam2, (const T *)a.vals, a.jnode,
                            (const T *)a.jD, a.joff, a.jsrc, (const T *)a.jw, a.nj, a.nshots, s0, a.vol);
         s0 += 8;
