@@ -573,7 +573,7 @@ struct PairW {
   T w[2][NS];
 };
 
-template <typename T, int TX, int TY, int TZ, int HR, int D>
+template <typename T, int TX, int TY, int TZ, int HR, int D, int SC>
 __launch_bounds__(512)
 __global__ void k_patch_tiled_r(const T *__restrict__ un, T *__restrict__ unew, const T *__restrict__ dense,
                                 const PInfoD<T> *__restrict__ pinfo, const int32_t *__restrict__ ball,
@@ -584,10 +584,11 @@ __global__ void k_patch_tiled_r(const T *__restrict__ un, T *__restrict__ unew, 
   constexpr int BMAX = 64 * NS;
   constexpr int NW = 8;                       // wavefronts per workgroup (512 threads)
   constexpr int STEP = 2 * NW;                // points per wavefront group step
-  __shared__ T sp[LZ * LY * LX];
+  // SC shots per pass: their tiles side by side in LDS, each point's weights loaded once
+  __shared__ T sp[SC][LZ * LY * LX];
   __shared__ int16_t lofs[2][BMAX];
   __shared__ TileRec rec[kTileMaxPoints];
-  __shared__ T res[kTileMaxPoints];
+  __shared__ T res[SC][kTileMaxPoints];
   const int64_t tb = xcd_remap(blockIdx.x, gridDim.x);
   if (tb >= ntiles) return;
   const int4 tl = tiles[tb];
@@ -649,8 +650,7 @@ __global__ void k_patch_tiled_r(const T *__restrict__ un, T *__restrict__ unew, 
       }
     }
   };
-  for (int s = 0; s < nshots; ++s) {
-    const T *u = un + (size_t)s * vol;
+  for (int s0 = 0; s0 < nshots; s0 += SC) {
     // records of D + 1 groups ahead, weights of D groups in flight before the staging
     uint32_t wo[D + 1][2], fc[D + 1][2], lcc[D + 1][2];
     PairW<T, NS> W[D + 1];
@@ -664,7 +664,11 @@ __global__ void k_patch_tiled_r(const T *__restrict__ un, T *__restrict__ unew, 
       const int lx = e % LX, ly = (e / LX) % LY, lz = e / (LX * LY);
       const int gz = z0 - HR + lz;
       const int gx = wrapk(x0 - HR + lx, nx), gy = wrapk(y0 - HR + ly, ny);
-      sp[e] = (lx < LX - 1 && gz >= 0 && gz < nz) ? u[(size_t)gz * plane + (size_t)gy * pitch + gx] : T(0);
+      const bool in = lx < LX - 1 && gz >= 0 && gz < nz;
+      const size_t g = (size_t)gz * plane + (size_t)gy * pitch + gx;
+#pragma unroll
+      for (int c = 0; c < SC; ++c)
+        sp[c][e] = (in && s0 + c < nshots) ? un[(size_t)(s0 + c) * vol + g] : T(0);
     }
     __syncthreads();
     for (int p = wave; p < np; p += STEP) {
@@ -681,14 +685,23 @@ __global__ void k_patch_tiled_r(const T *__restrict__ un, T *__restrict__ unew, 
           const int first = (int)(fc[0][h] & 0xffffu);
           const int lc = (int)(lcc[0][h] & 0x7fffffffu);
           const int16_t *lt = lofs[lcc[0][h] >> 31] + first;
-          T acc = T(0);
+          T acc[SC];
+#pragma unroll
+          for (int c = 0; c < SC; ++c) acc[c] = T(0);
 #pragma unroll
           for (int k = 0; k < NS; ++k) {
             const int e = k * 64 + lane;
-            if (e < cnt) acc += W[0].w[h][k] * sp[lc + lt[e]];
+            if (e < cnt) {
+              const int o = lc + lt[e];
+#pragma unroll
+              for (int c = 0; c < SC; ++c) acc[c] += W[0].w[h][k] * sp[c][o];
+            }
           }
-          acc = wave_sum(acc);
-          if (lane == 0) res[q] = acc;
+#pragma unroll
+          for (int c = 0; c < SC; ++c) {
+            const T t = wave_sum(acc[c]);
+            if (lane == 0) res[c][q] = t;
+          }
         }
       }
 #pragma unroll
@@ -703,7 +716,10 @@ __global__ void k_patch_tiled_r(const T *__restrict__ un, T *__restrict__ unew, 
     __syncthreads();
     for (int i = threadIdx.x; i < np; i += blockDim.x) {
       const PInfoD<T> P = pinfo[p0 + i];
-      unew[(size_t)s * vol + (size_t)P.z * plane + (size_t)P.y * pitch + P.x] += P.scale * res[i];
+      const size_t g = (size_t)P.z * plane + (size_t)P.y * pitch + P.x;
+#pragma unroll
+      for (int c = 0; c < SC; ++c)
+        if (s0 + c < nshots) unew[(size_t)(s0 + c) * vol + g] += P.scale * res[c][i];
     }
     __syncthreads();
   }
@@ -943,6 +959,13 @@ __global__ void k_sample(const T *unew, const int64_t *ridx, const T *rw, int nr
   traces[((size_t)s * nsteps + tl) * nrec + r] = v;
 }
 
+// Shots per pass of the tiled patch when a state holds several: each point's weights are
+// loaded once for the pass, the pass's tiles of p^n sit side by side in LDS.  Two FP32 shots
+// measured fastest (64 shots at 301x301x201: 92 -> 118 Gpts/s; four shots lose occupancy);
+// FP64 keeps one (two FP64 tiles would leave one workgroup per CU).
+template <typename T>
+constexpr int kPatchShots = (sizeof(T) == 8) ? 1 : 2;
+
 // ---- boundary values ----------------------------------------------------------------
 // Inhomogeneous conditions: p^{n+1}_i += sum_q F[i][q] s_q(t_n) at every IB point, F
 // holding K_i / (1 + s_i) times the point's condition-value weights contracted with g_q.
@@ -1041,8 +1064,9 @@ static void launch_patch(const StepArgs &a, hipStream_t st) {
   hipLaunchKernelGGL((k_patch_tiled<T, kTileX, kTileY, kTileZ, kTileHalo, PVV>), dim3((unsigned)nblk), dim3(512), 0, \
                      st, (const T *)a.un, (T *)a.um, (const T *)a.dense, (const PInfoD<T> *)a.pinfo, a.ball,           \
                      a.ball_meta, a.tiles, a.ntiles, a.nx, a.ny, a.nz, a.pitch, a.vol, a.nshots)
-#define IB_PATCH_TILED_R(DD)                                                                                        \
-  hipLaunchKernelGGL((k_patch_tiled_r<T, kTileX, kTileY, kTileZ, kTileHalo, DD>), dim3((unsigned)nblk), dim3(512),   \
+#define IB_PATCH_TILED_R(DD, SC)                                                                                    \
+  hipLaunchKernelGGL((k_patch_tiled_r<T, kTileX, kTileY, kTileZ, kTileHalo, DD, SC>), dim3((unsigned)nblk),           \
+                     dim3(512),                                                                                      \
                      0, st, (const T *)a.un, (T *)a.um, (const T *)a.dense, (const PInfoD<T> *)a.pinfo, a.ball,       \
                      a.ball_meta, a.tiles, a.ntiles, a.nx, a.ny, a.nz, a.pitch, a.vol, a.nshots)
     switch (a.patch_variant) {
@@ -1050,9 +1074,14 @@ static void launch_patch(const StepArgs &a, hipStream_t st) {
       case 1: IB_PATCH_TILED(1); break;
       case 2: IB_PATCH_TILED(2); break;
       case 3: IB_PATCH_TILED(3); break;
-      case 4: IB_PATCH_TILED_R(1); break;
-      case 5: IB_PATCH_TILED_R(2); break;
-      case 6: IB_PATCH_TILED_R(3); break;
+      case 4:
+        if (a.nshots >= kPatchShots<T>)
+          IB_PATCH_TILED_R(1, kPatchShots<T>);
+        else
+          IB_PATCH_TILED_R(1, 1);
+        break;
+      case 5: IB_PATCH_TILED_R(2, 1); break;
+      case 6: IB_PATCH_TILED_R(3, 1); break;
       default:
         hipLaunchKernelGGL((k_patch_tiled_m<T, kTileX, kTileY, kTileZ, kTileHalo>), dim3((unsigned)nblk), dim3(512), 0,
                            st, (const T *)a.un, (T *)a.um, a.rec, (const PInfo<T> *)a.pinfo_tm, a.ball, a.ball_meta,
