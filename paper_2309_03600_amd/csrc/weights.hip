@@ -356,7 +356,10 @@ __global__ void k_solve(SolveArgs a) {
         for (int i = 0; i < CH; ++i) nsq += cj[i] * cj[i];
         const double rkk = R[ridx(k, k, NT)];
         double al, v0;
-        if (nsq == 0.0) {
+        // a chunk column of norm below 1e-150 is taken as zero: its reflector would move R by
+        // less than the rounding of its other entries, and al * v0 below must stay a normal
+        // number (its underflow to zero made f infinite and R non-finite)
+        if (!(nsq > 1e-300)) {
           al = rkk;
           v0 = 0.0;
         } else {
