@@ -28,6 +28,7 @@
 #include <cstring>
 
 #include "ib_internal.h"
+#include "wave.h"
 
 namespace ib {
 
@@ -128,7 +129,7 @@ __device__ __forceinline__ int ridx(int i, int j, int NT) {  // packed upper tri
 }
 
 template <int CH>
-__launch_bounds__(256)
+__launch_bounds__(1024)
 __global__ void k_solve(SolveArgs a) {
   extern __shared__ double smem[];
   const int NTB = a.NT;                 // basis terms per block
@@ -143,7 +144,7 @@ __global__ void k_solve(SolveArgs a) {
   double *vcol = nrm + nb * 3;                        // 2 x CH reflector columns (double buffered)
   double *vsc = vcol + 2 * nb;                        // 2 x 2 reflector scalars
   double *C = vsc + 4;                                // NT: the published solution z
-  double *red = C + NT;                               // 16
+  double *red = C + 2 * NT;                           // 16 (C holds z, then 1 / R_kk)
   int *iscr = (int *)(red + 16);                      // 16 ints
   __shared__ int rowop[64];
   __shared__ int rowbp[64];
@@ -216,7 +217,7 @@ __global__ void k_solve(SolveArgs a) {
     }
     // exclusive scan of counts (small: serial over waves via LDS)
     __syncthreads();
-    __shared__ int cnts[256];
+    __shared__ int cnts[1024];
     cnts[tid] = cnt;
     __syncthreads();
     if (tid == 0) {
@@ -276,15 +277,25 @@ __global__ void k_solve(SolveArgs a) {
   __syncthreads();
 
   // ---- streamed Householder QR of A into R ------------------------------------------
-  // Thread j owns column j of the current row chunk in registers.  Column step k: thread
-  // k forms the reflector of [R_kk; chunk column k] from its own registers and publishes
-  // it in LDS (double buffered); every thread j > k applies it to [R_kj; its column].
+  // Four threads (a lane quad) own column j of the current row chunk, a quarter of its
+  // rows each, in registers.  Column step k: the quad of column k forms the reflector of
+  // [R_kk; chunk column k] (quad sums by DPP, identical in its four lanes) and publishes it
+  // in LDS (double buffered); every quad j > k applies it to [R_kj; its column].  Quarter
+  // rows keep the per-thread dependency chains short, and the larger workgroup hides
+  // latency with more wavefronts on the CU that R's LDS footprint limits to one point.
+  constexpr int RQ = CH / 4;                      // chunk rows per quarter
+  const int cjx = tid >> 2, qd = tid & 3;         // column and quarter of this thread
   for (int i = tid; i < NT * (NT + 1) / 2; i += nth) R[i] = 0.0;
-  const int bj = (tid < NT) ? tid / NTB : 0;        // unknown block of column tid
-  const int tj = (tid < NT) ? tid - bj * NTB : 0;   // basis term of column tid
+  const int bj = (cjx < NT) ? cjx / NTB : 0;      // unknown block of column cjx
+  const int tj = (cjx < NT) ? cjx - bj * NTB : 0; // basis term of column cjx
   const int8_t ej0 = c_solve.exps[tj][0];
   const int8_t ej1 = c_solve.exps[tj][1];
   const int8_t ej2 = c_solve.exps[tj][2];
+  auto quad_sum = [](double v) {
+    v += dpp_mov<0xB1>(v);   // quad_perm [1, 0, 3, 2]
+    v += dpp_mov<0x4E>(v);   // quad_perm [2, 3, 0, 1]
+    return v;
+  };
   __syncthreads();
   for (int r0 = 0; r0 < m; r0 += nb) {
     const int nr = min(nb, m - r0);
@@ -322,11 +333,12 @@ __global__ void k_solve(SolveArgs a) {
       }
     }
     __syncthreads();
-    double cj[CH];
+    double cj[RQ];
 #pragma unroll
-    for (int i = 0; i < CH; ++i) {
+    for (int r = 0; r < RQ; ++r) {
+      const int i = qd * RQ + r;
       double v = 0.0;
-      if (i < nr && tid < NT) {
+      if (i < nr && cjx < NT) {
         const double *p = pw + i * 3 * D1;
         const int op = rowop[i];
         if (op < 0) {
@@ -345,15 +357,16 @@ __global__ void k_solve(SolveArgs a) {
           }
         }
       }
-      cj[i] = v;
+      cj[r] = v;
     }
     for (int k = 0; k < NT; ++k) {
       double *vc = vcol + (k & 1) * nb;
       double *sc = vsc + (k & 1) * 2;
-      if (tid == k) {
-        double nsq = 0.0;
+      if (cjx == k) {
+        double part = 0.0;
 #pragma unroll
-        for (int i = 0; i < CH; ++i) nsq += cj[i] * cj[i];
+        for (int r = 0; r < RQ; ++r) part += cj[r] * cj[r];
+        const double nsq = quad_sum(part);
         const double rkk = R[ridx(k, k, NT)];
         double al, v0;
         // a chunk column of norm below 1e-150 is taken as zero: its reflector would move R by
@@ -367,72 +380,80 @@ __global__ void k_solve(SolveArgs a) {
           al = (rkk >= 0.0) ? -nn : nn;
           v0 = rkk - al;
         }
-        sc[0] = al;
-        sc[1] = v0;
+        if (qd == 0) {
+          sc[0] = al;
+          sc[1] = v0;
+          R[ridx(k, k, NT)] = al;
+        }
 #pragma unroll
-        for (int i = 0; i < CH; ++i) vc[i] = cj[i];
-        R[ridx(k, k, NT)] = al;
+        for (int r = 0; r < RQ; ++r) vc[qd * RQ + r] = cj[r];
       }
       __syncthreads();
       const double al = sc[0], v0 = sc[1];
-      if (tid > k && tid < NT && v0 != 0.0) {
-        const int rk = ridx(k, tid, NT);
+      if (cjx > k && cjx < NT && v0 != 0.0) {
+        const int rk = ridx(k, cjx, NT);
         const double rkj = R[rk];
-        double sdot = v0 * rkj;
+        double part = (qd == 0) ? v0 * rkj : 0.0;
 #pragma unroll
-        for (int i = 0; i < CH; ++i) sdot += vc[i] * cj[i];
-        const double f = sdot / (al * v0);
-        R[rk] = rkj + f * v0;
+        for (int r = 0; r < RQ; ++r) part += vc[qd * RQ + r] * cj[r];
+        const double f = quad_sum(part) / (al * v0);
+        if (qd == 0) R[rk] = rkj + f * v0;
 #pragma unroll
-        for (int i = 0; i < CH; ++i) cj[i] += f * vc[i];
+        for (int r = 0; r < RQ; ++r) cj[r] += f * vc[qd * RQ + r];
       }
     }
     __syncthreads();
   }
 
-  // ---- numerical rank and the solve, in wavefront 0 ---------------------------------
+  // ---- numerical rank and the solve --------------------------------------------------
   // Vectors of length NT <= 192 live in registers (entry j in lane j % 64, slot j / 64);
-  // triangular solves and mat-vecs broadcast one entry per step with readlane, so no
-  // workgroup barrier is needed until z is published in LDS.
+  // triangular solves and mat-vecs broadcast one entry per step with readlane, so a
+  // wavefront needs no workgroup barrier inside them.  sigma_max (power iteration) runs on
+  // wavefront 1 while wavefront 0 runs the inverse iteration for sigma_min; wavefront 0
+  // then decides and solves.  The diagonal's reciprocals are formed once.
   double *zv = C;            // reuse the chunk buffer for the published solution
-  if (tid < 64) {
-    const int lane = tid;
-    auto bcast = [](double v, int src) {
-      int lo = __builtin_amdgcn_readlane(__double2loint(v), src);
-      int hi = __builtin_amdgcn_readlane(__double2hiint(v), src);
-      return __hiloint2double(hi, lo);
-    };
-    auto get = [&](const double x[3], int k) { return bcast(k < 64 ? x[0] : (k < 128 ? x[1] : x[2]), k & 63); };
-    auto wsum = [](double v) {
-      for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
-      return v;
-    };
-    // R^T w = x in place (x becomes w)
-    auto solve_rt = [&](double x[3]) {
-      for (int k = 0; k < NT; ++k) {
-        const double wk = get(x, k) / R[ridx(k, k, NT)];
+  double *dinv = C + NT;     // 1 / R_kk
+  for (int k = tid; k < NT; k += nth) dinv[k] = 1.0 / R[ridx(k, k, NT)];
+  __syncthreads();
+  const int wvi = tid >> 6, lane = tid & 63;
+  const bool two = nth >= 128;
+  auto bcast = [](double v, int src) {
+    int lo = __builtin_amdgcn_readlane(__double2loint(v), src);
+    int hi = __builtin_amdgcn_readlane(__double2hiint(v), src);
+    return __hiloint2double(hi, lo);
+  };
+  auto get = [&](const double x[3], int k) { return bcast(k < 64 ? x[0] : (k < 128 ? x[1] : x[2]), k & 63); };
+  auto wsum = [](double v) {
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    return v;
+  };
+  // R^T w = x in place (x becomes w)
+  auto solve_rt = [&](double x[3]) {
+    for (int k = 0; k < NT; ++k) {
+      const double wk = get(x, k) * dinv[k];
 #pragma unroll
-        for (int q = 0; q < 3; ++q) {
-          const int j = lane + 64 * q;
-          if (j > k && j < NT) x[q] -= R[ridx(k, j, NT)] * wk;
-          if (j == k) x[q] = wk;
-        }
+      for (int q = 0; q < 3; ++q) {
+        const int j = lane + 64 * q;
+        if (j > k && j < NT) x[q] -= R[ridx(k, j, NT)] * wk;
+        if (j == k) x[q] = wk;
       }
-    };
-    // R z = w in place
-    auto solve_r = [&](double x[3]) {
-      for (int k = NT - 1; k >= 0; --k) {
-        const double zk = get(x, k) / R[ridx(k, k, NT)];
+    }
+  };
+  // R z = w in place
+  auto solve_r = [&](double x[3]) {
+    for (int k = NT - 1; k >= 0; --k) {
+      const double zk = get(x, k) * dinv[k];
 #pragma unroll
-        for (int q = 0; q < 3; ++q) {
-          const int j = lane + 64 * q;
-          if (j < k) x[q] -= R[ridx(j, k, NT)] * zk;
-          if (j == k) x[q] = zk;
-        }
+      for (int q = 0; q < 3; ++q) {
+        const int j = lane + 64 * q;
+        if (j < k) x[q] -= R[ridx(j, k, NT)] * zk;
+        if (j == k) x[q] = zk;
       }
-    };
-    const double inv_sqrt = 1.0 / sqrt((double)NT);
-    // sigma_max: power iteration on R^T R
+    }
+  };
+  const double inv_sqrt = 1.0 / sqrt((double)NT);
+  // sigma_max: power iteration on R^T R
+  auto power = [&]() {
     double x[3], y[3];
 #pragma unroll
     for (int q = 0; q < 3; ++q) x[q] = (lane + 64 * q < NT) ? inv_sqrt : 0.0;
@@ -462,13 +483,21 @@ __global__ void k_solve(SolveArgs a) {
 #pragma unroll
       for (int q = 0; q < 3; ++q) x[q] = (nn > 0.0) ? x2[q] / nn : 0.0;
     }
+    return smax2;
+  };
+  if (wvi == (two ? 1 : 0)) {
+    const double s2 = power();
+    if (lane == 0) red[0] = s2;
+  }
+  double x[3];
+  double smin2 = 0.0;
+  if (wvi == 0) {
     // sigma_min: inverse iteration on R^T R from an alternating start
 #pragma unroll
     for (int q = 0; q < 3; ++q) {
       const int j = lane + 64 * q;
       x[q] = (j < NT) ? ((j & 1) ? -inv_sqrt : inv_sqrt) : 0.0;
     }
-    double smin2 = 0.0;
     for (int it = 0; it < 6; ++it) {
       solve_rt(x);
       solve_r(x);
@@ -481,7 +510,10 @@ __global__ void k_solve(SolveArgs a) {
 #pragma unroll
       for (int q = 0; q < 3; ++q) x[q] /= nn;
     }
-    const double smax = sqrt(smax2), smin = sqrt(smin2);
+  }
+  __syncthreads();
+  if (wvi == 0) {
+    const double smax = sqrt(red[0]), smin = sqrt(smin2);
     const double tol = (a.rtol > 0.0) ? a.rtol : (double)max(m, NT) * 2.220446049250313e-16;
     const bool full = (smin > tol * smax) && isfinite(smin) && isfinite(smax) && smax > 0.0;
     if (lane == 0) {
@@ -707,6 +739,9 @@ __global__ void k_dense(int64_t nib, const uint32_t *rec32, const uint32_t *roff
   }
 }
 
+// threads of a k_solve workgroup: a lane quad per column of A, whole wavefronts
+static int solve_threads(int ncols) { return std::min(1024, std::max(64, (4 * ncols + 63) / 64 * 64)); }
+
 struct RoundResult {
   int code, k, Mb;
   std::vector<int32_t> acc_pos, acc_id;
@@ -803,7 +838,8 @@ ib_status weights_build(ib_weights *w, const int64_t *col_off_dev, hipStream_t s
   second_derivative_weights(M, sc.w2);
   double max_cond = 0.0, min_margin = INFINITY;
   const double tol_base = 2.220446049250313e-16;
-  const int chunk = (ndim == 3) ? 32 : 48;
+  // rows per streamed chunk: fewer, longer chunks halve the column steps of the 3D systems
+  const int chunk = (ndim == 3) ? 64 : 48;
   // condition-value weights, kept on request: compacted per launch into device chunks,
   // concatenated at the end
   const bool keep_bc = w->prm.keep_bc_weights != 0;
@@ -912,18 +948,19 @@ ib_status weights_build(ib_weights *w, const int64_t *col_off_dev, hipStream_t s
       }
       const int D1 = Mb + 1;
       size_t lds = sizeof(double) * ((size_t)NT * (NT + 1) / 2 + (size_t)chunk * 3 * D1 + (size_t)chunk * 3 +
-                                     2 * (size_t)chunk + 4 + NT + 16) +
+                                     2 * (size_t)chunk + 4 + 2 * NT + 16) +
                    16 * sizeof(int);
-      const void *kfn = (chunk == 32) ? (const void *)k_solve<32> : (const void *)k_solve<48>;
+      const void *kfn = (chunk == 64) ? (const void *)k_solve<64> : (const void *)k_solve<48>;
       IB_HIP(hipFuncSetAttribute(kfn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+      const int sth = solve_threads(NT);
       for (int b0 = 0; b0 < npend; b0 += slots) {
         A.pending = d_pending + b0;
         A.npend = std::min(slots, npend - b0);
         A.out_base = b0;
-        if (chunk == 32)
-          hipLaunchKernelGGL(k_solve<32>, dim3(A.npend), dim3(256), lds, st, A);
+        if (chunk == 64)
+          hipLaunchKernelGGL(k_solve<64>, dim3(A.npend), dim3(sth), lds, st, A);
         else
-          hipLaunchKernelGGL(k_solve<48>, dim3(A.npend), dim3(256), lds, st, A);
+          hipLaunchKernelGGL(k_solve<48>, dim3(A.npend), dim3(sth), lds, st, A);
         IB_HIP(hipGetLastError());
         if (keep_bc) {
           // compact this launch's condition-value weights of the accepted points
@@ -1224,18 +1261,19 @@ ib_status solve_family(ib_weights *w, const FamilySpec &F, const int64_t *col_of
       A.sigma = d_sigma;
       const int D1 = Mb + 1;
       size_t lds = sizeof(double) * ((size_t)NTT * (NTT + 1) / 2 + (size_t)chunk * 3 * D1 + (size_t)chunk * 3 +
-                                     2 * (size_t)chunk + 4 + NTT + 16) +
+                                     2 * (size_t)chunk + 4 + 2 * NTT + 16) +
                    16 * sizeof(int);
       const void *kfn = (chunk == 32) ? (const void *)k_solve<32> : (const void *)k_solve<48>;
       IB_HIP(hipFuncSetAttribute(kfn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+      const int sth = solve_threads(NTT);
       for (int b0 = 0; b0 < npend; b0 += slots) {
         A.pending = d_pending + b0;
         A.npend = std::min(slots, npend - b0);
         A.out_base = b0;
         if (chunk == 32)
-          hipLaunchKernelGGL(k_solve<32>, dim3(A.npend), dim3(256), lds, st, A);
+          hipLaunchKernelGGL(k_solve<32>, dim3(A.npend), dim3(sth), lds, st, A);
         else
-          hipLaunchKernelGGL(k_solve<48>, dim3(A.npend), dim3(256), lds, st, A);
+          hipLaunchKernelGGL(k_solve<48>, dim3(A.npend), dim3(sth), lds, st, A);
         IB_HIP(hipGetLastError());
       }
       std::vector<int32_t> hs(npend), hn(npend);
