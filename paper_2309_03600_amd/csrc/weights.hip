@@ -141,8 +141,8 @@ __global__ void k_solve(SolveArgs a) {
   double *R = smem;                                   // NT(NT+1)/2, packed upper triangle
   double *pw = R + NT * (NT + 1) / 2;                 // CH x 3 x D1 power tables of the chunk rows
   double *nrm = pw + nb * 3 * D1;                     // CH x 3 normals of the chunk rows
-  double *vcol = nrm + nb * 3;                        // 2 x (CH + 4) reflector columns (double buffered)
-  double *vsc = vcol + 2 * (nb + 4);                  // 2 x 2 reflector scalars
+  double *vcol = nrm + nb * 3;                        // 2 x CH reflector columns (double buffered)
+  double *vsc = vcol + 2 * nb;                        // 2 x 2 reflector scalars
   double *C = vsc + 4;                                // NT: the published solution z
   double *red = C + 2 * NT;                           // 16 (C holds z, then 1 / R_kk)
   int *iscr = (int *)(red + 16);                      // 16 ints
@@ -277,8 +277,9 @@ __global__ void k_solve(SolveArgs a) {
   __syncthreads();
 
   // ---- streamed Householder QR of A into R ------------------------------------------
-  // Four threads (a lane quad) own column j of the current row chunk, a quarter of its
-  // rows each, in registers.  Column step k: the quad of column k forms the reflector of
+  // Four threads (a lane quad) own column j of the current row chunk, every fourth row
+  // each (interleaved, so that the quad's LDS reads of rows and reflectors hit adjacent
+  // words), in registers.  Column step k: the quad of column k forms the reflector of
   // [R_kk; chunk column k] (quad sums by DPP, identical in its four lanes) and publishes it
   // in LDS (double buffered); every quad j > k applies it to [R_kj; its column].  Quarter
   // rows keep the per-thread dependency chains short, and the larger workgroup hides
@@ -336,7 +337,7 @@ __global__ void k_solve(SolveArgs a) {
     double cj[RQ];
 #pragma unroll
     for (int r = 0; r < RQ; ++r) {
-      const int i = qd * RQ + r;
+      const int i = 4 * r + qd;
       double v = 0.0;
       if (i < nr && cjx < NT) {
         const double *p = pw + i * 3 * D1;
@@ -360,9 +361,7 @@ __global__ void k_solve(SolveArgs a) {
       cj[r] = v;
     }
     for (int k = 0; k < NT; ++k) {
-      // quarters at an odd stride of RQ + 1 doubles: the four quarter reads of a
-      // wavefront fall on different LDS banks
-      double *vc = vcol + (k & 1) * (nb + 4);
+      double *vc = vcol + (k & 1) * nb;
       double *sc = vsc + (k & 1) * 2;
       if (cjx == k) {
         double part = 0.0;
@@ -388,7 +387,7 @@ __global__ void k_solve(SolveArgs a) {
           R[ridx(k, k, NT)] = al;
         }
 #pragma unroll
-        for (int r = 0; r < RQ; ++r) vc[qd * (RQ + 1) + r] = cj[r];
+        for (int r = 0; r < RQ; ++r) vc[4 * r + qd] = cj[r];
       }
       __syncthreads();
       const double al = sc[0], v0 = sc[1];
@@ -397,11 +396,11 @@ __global__ void k_solve(SolveArgs a) {
         const double rkj = R[rk];
         double part = (qd == 0) ? v0 * rkj : 0.0;
 #pragma unroll
-        for (int r = 0; r < RQ; ++r) part += vc[qd * (RQ + 1) + r] * cj[r];
+        for (int r = 0; r < RQ; ++r) part += vc[4 * r + qd] * cj[r];
         const double f = quad_sum(part) / (al * v0);
         if (qd == 0) R[rk] = rkj + f * v0;
 #pragma unroll
-        for (int r = 0; r < RQ; ++r) cj[r] += f * vc[qd * (RQ + 1) + r];
+        for (int r = 0; r < RQ; ++r) cj[r] += f * vc[4 * r + qd];
       }
     }
     __syncthreads();
@@ -950,7 +949,7 @@ ib_status weights_build(ib_weights *w, const int64_t *col_off_dev, hipStream_t s
       }
       const int D1 = Mb + 1;
       size_t lds = sizeof(double) * ((size_t)NT * (NT + 1) / 2 + (size_t)chunk * 3 * D1 + (size_t)chunk * 3 +
-                                     2 * ((size_t)chunk + 4) + 4 + 2 * NT + 16) +
+                                     2 * (size_t)chunk + 4 + 2 * NT + 16) +
                    16 * sizeof(int);
       const void *kfn = (chunk == 64) ? (const void *)k_solve<64> : (const void *)k_solve<48>;
       IB_HIP(hipFuncSetAttribute(kfn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
@@ -1263,7 +1262,7 @@ ib_status solve_family(ib_weights *w, const FamilySpec &F, const int64_t *col_of
       A.sigma = d_sigma;
       const int D1 = Mb + 1;
       size_t lds = sizeof(double) * ((size_t)NTT * (NTT + 1) / 2 + (size_t)chunk * 3 * D1 + (size_t)chunk * 3 +
-                                     2 * ((size_t)chunk + 4) + 4 + 2 * NTT + 16) +
+                                     2 * (size_t)chunk + 4 + 2 * NTT + 16) +
                    16 * sizeof(int);
       const void *kfn = (chunk == 32) ? (const void *)k_solve<32> : (const void *)k_solve<48>;
       IB_HIP(hipFuncSetAttribute(kfn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
