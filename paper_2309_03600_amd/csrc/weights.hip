@@ -129,7 +129,7 @@ __device__ __forceinline__ int ridx(int i, int j, int NT) {  // packed upper tri
 }
 
 template <int CH>
-__launch_bounds__(1024)
+__launch_bounds__(768)   // a lane quad per column, at most 192 columns
 __global__ void k_solve(SolveArgs a) {
   extern __shared__ double smem[];
   const int NTB = a.NT;                 // basis terms per block
@@ -741,7 +741,7 @@ __global__ void k_dense(int64_t nib, const uint32_t *rec32, const uint32_t *roff
 }
 
 // threads of a k_solve workgroup: a lane quad per column of A, whole wavefronts
-static int solve_threads(int ncols) { return std::min(1024, std::max(64, (4 * ncols + 63) / 64 * 64)); }
+static int solve_threads(int ncols) { return std::min(768, std::max(64, (4 * ncols + 63) / 64 * 64)); }
 
 struct RoundResult {
   int code, k, Mb;
