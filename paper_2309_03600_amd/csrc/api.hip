@@ -870,7 +870,6 @@ ib_status ib_state_create(const ib_weights *w, const double *vel_dev, double dt,
       std::vector<int16_t> xyz(w->nib * 4);
       if (w->nib) IB_HIP(hipMemcpy(xyz.data(), w->ib_xyz, w->nib * 8, hipMemcpyDeviceToHost));
       std::vector<int32_t> tiled, wide;
-      std::vector<int64_t> key;
       const bool use_tiles = (w->ndim == 3);
       const int64_t tx = (w->nx + kTileX - 1) / kTileX, ty = (w->ny + kTileY - 1) / kTileY;
       for (int64_t i = 0; i < w->nib; ++i) {
@@ -880,16 +879,22 @@ ib_status ib_state_create(const ib_weights *w, const double *vel_dev, double dt,
         else
           wide.push_back((int32_t)i);
       }
-      auto tkey = [&](int32_t i) {
-        return ((int64_t)(xyz[i * 4 + 2] / kTileZ) * ty + xyz[i * 4 + 1] / kTileY) * tx + xyz[i * 4 + 0] / kTileX;
-      };
-      std::stable_sort(tiled.begin(), tiled.end(), [&](int32_t a, int32_t b) { return tkey(a) < tkey(b); });
+      // lateral tile column, then depth; a tile opens at the first point not covered by the
+      // previous one of its column
+      const int tz = tile_depth(prec);
+      auto ckey = [&](int32_t i) { return (int64_t)(xyz[i * 4 + 1] / kTileY) * tx + xyz[i * 4 + 0] / kTileX; };
+      std::stable_sort(tiled.begin(), tiled.end(), [&](int32_t a, int32_t b) {
+        const int64_t ka = ckey(a), kb = ckey(b);
+        return ka != kb ? ka < kb : xyz[a * 4 + 2] < xyz[b * 4 + 2];
+      });
       std::vector<int4> tl;
+      int zopen = 0;
       for (size_t j = 0; j < tiled.size(); ++j) {
-        if (j == 0 || tkey(tiled[j]) != tkey(tiled[j - 1]) || (int)j - tl.back().w >= kTileMaxPoints) {
-          int32_t i = tiled[j];
-          tl.push_back(make_int4(xyz[i * 4] / kTileX * kTileX, xyz[i * 4 + 1] / kTileY * kTileY,
-                                 xyz[i * 4 + 2] / kTileZ * kTileZ, (int)j));
+        const int32_t i = tiled[j];
+        const int z = xyz[i * 4 + 2];
+        if (j == 0 || ckey(i) != ckey(tiled[j - 1]) || z >= zopen + tz || (int)j - tl.back().w >= kTileMaxPoints) {
+          zopen = z;
+          tl.push_back(make_int4(xyz[i * 4] / kTileX * kTileX, xyz[i * 4 + 1] / kTileY * kTileY, z, (int)j));
         }
       }
       tl.push_back(make_int4(0, 0, 0, (int)tiled.size()));

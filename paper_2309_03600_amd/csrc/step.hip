@@ -413,7 +413,8 @@ __global__ void k_patch(const T *__restrict__ un, T *__restrict__ unew, const ui
 }
 
 // ---- IB patch, LDS-tiled (3D) -------------------------------------------------------
-// IB points are bucketed into TX x TY x TZ tiles (host, at state creation).  A workgroup
+// IB points are bucketed into TX x TY x TZ tiles (host, at state creation; laterally
+// aligned, in depth starting at the tile's first point).  A workgroup
 // stages p^n over its tile plus an HR-cell halo in LDS with coalesced row loads; its
 // wavefronts then evaluate the tile's points from LDS, each streaming the point's
 // dense-range weights (coalesced, no mask decoding) while the next point's record is
@@ -1057,15 +1058,18 @@ static void launch_interior(const StepArgs &a, hipStream_t st) {
 }
 
 template <typename T>
+constexpr int kTileZOf = sizeof(T) == 4 ? kTileZ32 : kTileZ64;
+
+template <typename T>
 static void launch_patch(const StepArgs &a, hipStream_t st) {
   if (a.ntiles > 0) {
     int64_t nblk = ((int64_t)a.ntiles + 7) / 8 * 8;
 #define IB_PATCH_TILED(PVV)                                                                                         \
-  hipLaunchKernelGGL((k_patch_tiled<T, kTileX, kTileY, kTileZ, kTileHalo, PVV>), dim3((unsigned)nblk), dim3(512), 0, \
+  hipLaunchKernelGGL((k_patch_tiled<T, kTileX, kTileY, kTileZOf<T>, kTileHalo, PVV>), dim3((unsigned)nblk), dim3(512), 0, \
                      st, (const T *)a.un, (T *)a.um, (const T *)a.dense, (const PInfoD<T> *)a.pinfo, a.ball,           \
                      a.ball_meta, a.tiles, a.ntiles, a.nx, a.ny, a.nz, a.pitch, a.vol, a.nshots)
 #define IB_PATCH_TILED_R(DD, SC)                                                                                    \
-  hipLaunchKernelGGL((k_patch_tiled_r<T, kTileX, kTileY, kTileZ, kTileHalo, DD, SC>), dim3((unsigned)nblk),           \
+  hipLaunchKernelGGL((k_patch_tiled_r<T, kTileX, kTileY, kTileZOf<T>, kTileHalo, DD, SC>), dim3((unsigned)nblk),           \
                      dim3(512),                                                                                      \
                      0, st, (const T *)a.un, (T *)a.um, (const T *)a.dense, (const PInfoD<T> *)a.pinfo, a.ball,       \
                      a.ball_meta, a.tiles, a.ntiles, a.nx, a.ny, a.nz, a.pitch, a.vol, a.nshots)
@@ -1083,7 +1087,7 @@ static void launch_patch(const StepArgs &a, hipStream_t st) {
       case 5: IB_PATCH_TILED_R(2, 1); break;
       case 6: IB_PATCH_TILED_R(3, 1); break;
       default:
-        hipLaunchKernelGGL((k_patch_tiled_m<T, kTileX, kTileY, kTileZ, kTileHalo>), dim3((unsigned)nblk), dim3(512), 0,
+        hipLaunchKernelGGL((k_patch_tiled_m<T, kTileX, kTileY, kTileZOf<T>, kTileHalo>), dim3((unsigned)nblk), dim3(512), 0,
                            st, (const T *)a.un, (T *)a.um, a.rec, (const PInfo<T> *)a.pinfo_tm, a.ball, a.ball_meta,
                            a.tiles, a.ntiles, a.nx, a.ny, a.nz, a.pitch, a.vol, a.nshots);
         break;
