@@ -205,7 +205,12 @@ def config5(nt=1500, nshots=16, n=256, damp_width=20):
     linear depth gradient v0 = 1500 -> 3500 m/s; the observed data come from
     v_true = v0 (1 + 0.03 G), G a Gaussian blob (sigma 10 dx, peak 1) centred 90 dx deep;
     16 sources in a 4x4 pattern 50 m below the surface, 64x64 receivers (every 4th column)
-    15 m below the surface, dt = 0.616 ms, 20-cell damping."""
+    15 m below the surface, dt = 0.616 ms, 20-cell damping, exclusion cutoff eta = 0.25.
+
+    The cutoff is chosen empirically, as the paper chooses its own.  With eta = 0.5 this
+    rigid surface has a growing mode at one spot under a steep slope: the modified
+    operator there has a complex eigenvalue whose leapfrog amplification is 1.019 per
+    step.  With eta <= 0.4, 6000 steps show no growth."""
     nx = ny = nz = n
     h = 10.0
     H = _fractal3d(nx, ny, nz, h, 5)
@@ -225,7 +230,7 @@ def config5(nt=1500, nshots=16, n=256, damp_width=20):
     src = np.array(src[:nshots])
     rec = _rec_on_surface(H, h, max(1, n // 64), 15.0, nx, ny)
     return Workload(f"config5-3d-m8-rigid-adjoint-{n}^3-{nshots}shots", 3, (nx, ny, nz), h, 8, "rigid", H, vel,
-                    0.616e-3, nt, 10.0, src, rec, damp_width=damp_width, extra=dict(v_true=v_true))
+                    0.616e-3, nt, 10.0, src, rec, damp_width=damp_width, extra=dict(v_true=v_true), eta=0.25)
 
 
 def small3d(cfg=90, n=24, nz=44, relief=50.0, surface="free", nt=100, h=10.0, nshots=1, z_top_cells=16):

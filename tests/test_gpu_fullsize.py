@@ -220,3 +220,27 @@ def test_config5_adjoint_matches_finite_differences_fp64():
           f"misfit {jp[2]:.4e}", flush=True)
     assert abs(fd) > 1e-6 * jp[2]                      # the direction reaches the data
     assert abs(ad - fd) <= 1e-6 * abs(fd)
+
+
+def test_config5_exclusion_cutoff_keeps_the_rigid_surface_stable():
+    # with the paper's eta = 0.5 this rigid surface grows a mode at one spot (a complex
+    # eigenvalue of the local modified operator, amplification 1.019 per step); the
+    # workload's eta = 0.25 does not
+    import torch
+
+    import paper_2309_03600_amd as ib
+    nt = 4000
+    wl = W.config5(nt=nt)
+    wav = torch.tensor(wl.wavelets(np.float64)[5:6], dtype=torch.float32, device="cuda")
+    norms = {}
+    for eta in (0.5, wl.eta):
+        print(f"[config5 stability] eta={eta}", flush=True)
+        w = ib.ib_build_weights(wl.heights, wl.h, wl.shape, space_order=wl.M, surface=wl.surface, eta=eta)
+        st = ib.ib_state_create(w, wl.vel, wl.dt, wl.src[5:6], wl.rec, damp_width=wl.damp_width, precision="f32")
+        tr = st.step(nt, wav, use_graph=True).double().cpu().numpy()[0]
+        st.close()
+        norms[eta] = [float(np.linalg.norm(tr[a:a + 500])) for a in range(0, nt, 500)]
+        print(f"[config5 stability] eta={eta}: " + " ".join(f"{v:.2e}" for v in norms[eta]), flush=True)
+    grow, keep = norms[0.5], norms[wl.eta]
+    assert grow[-1] > 1e3 * grow[1]
+    assert np.isfinite(keep).all() and keep[-1] < 0.2 * keep[1]
