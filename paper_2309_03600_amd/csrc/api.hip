@@ -881,7 +881,6 @@ ib_status ib_state_create(const ib_weights *w, const double *vel_dev, double dt,
       }
       // lateral tile column, then depth; a tile opens at the first point not covered by the
       // previous one of its column
-      const int tz = tile_depth(prec);
       auto ckey = [&](int32_t i) { return (int64_t)(xyz[i * 4 + 1] / kTileY) * tx + xyz[i * 4 + 0] / kTileX; };
       std::stable_sort(tiled.begin(), tiled.end(), [&](int32_t a, int32_t b) {
         const int64_t ka = ckey(a), kb = ckey(b);
@@ -892,7 +891,7 @@ ib_status ib_state_create(const ib_weights *w, const double *vel_dev, double dt,
       for (size_t j = 0; j < tiled.size(); ++j) {
         const int32_t i = tiled[j];
         const int z = xyz[i * 4 + 2];
-        if (j == 0 || ckey(i) != ckey(tiled[j - 1]) || z >= zopen + tz || (int)j - tl.back().w >= kTileMaxPoints) {
+        if (j == 0 || ckey(i) != ckey(tiled[j - 1]) || z >= zopen + kTileZ || (int)j - tl.back().w >= kTileMaxPoints) {
           zopen = z;
           tl.push_back(make_int4(xyz[i * 4] / kTileX * kTileX, xyz[i * 4 + 1] / kTileY * kTileY, z, (int)j));
         }

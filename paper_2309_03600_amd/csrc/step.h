@@ -9,11 +9,9 @@
 namespace ib {
 
 // LDS tile of the 3D IB patch (points of support radius <= kTileHalo + 1/2).  Tiles are
-// aligned laterally; in depth a tile starts at its first point and spans kTileZ32 (FP32)
-// or kTileZ64 (FP64) planes, so that the thin layer of IB points under the surface falls
-// into few, full tiles (the FP64 tile is shallower to keep three workgroups per CU).
-constexpr int kTileX = 8, kTileY = 8, kTileZ32 = 16, kTileZ64 = 8, kTileHalo = 4;
-inline int tile_depth(int prec) { return prec == IB_F32 ? kTileZ32 : kTileZ64; }
+// aligned laterally; in depth a tile starts at its first point and spans kTileZ planes, so
+// that the thin layer of IB points under the surface falls into few, full tiles.
+constexpr int kTileX = 8, kTileY = 8, kTileZ = 16, kTileHalo = 4;
 constexpr int kTileMaxPoints = 512;   // longer tile lists are split
 
 struct StepArgs {

@@ -1058,18 +1058,15 @@ static void launch_interior(const StepArgs &a, hipStream_t st) {
 }
 
 template <typename T>
-constexpr int kTileZOf = sizeof(T) == 4 ? kTileZ32 : kTileZ64;
-
-template <typename T>
 static void launch_patch(const StepArgs &a, hipStream_t st) {
   if (a.ntiles > 0) {
     int64_t nblk = ((int64_t)a.ntiles + 7) / 8 * 8;
 #define IB_PATCH_TILED(PVV)                                                                                         \
-  hipLaunchKernelGGL((k_patch_tiled<T, kTileX, kTileY, kTileZOf<T>, kTileHalo, PVV>), dim3((unsigned)nblk), dim3(512), 0, \
+  hipLaunchKernelGGL((k_patch_tiled<T, kTileX, kTileY, kTileZ, kTileHalo, PVV>), dim3((unsigned)nblk), dim3(512), 0, \
                      st, (const T *)a.un, (T *)a.um, (const T *)a.dense, (const PInfoD<T> *)a.pinfo, a.ball,           \
                      a.ball_meta, a.tiles, a.ntiles, a.nx, a.ny, a.nz, a.pitch, a.vol, a.nshots)
 #define IB_PATCH_TILED_R(DD, SC)                                                                                    \
-  hipLaunchKernelGGL((k_patch_tiled_r<T, kTileX, kTileY, kTileZOf<T>, kTileHalo, DD, SC>), dim3((unsigned)nblk),           \
+  hipLaunchKernelGGL((k_patch_tiled_r<T, kTileX, kTileY, kTileZ, kTileHalo, DD, SC>), dim3((unsigned)nblk),           \
                      dim3(512),                                                                                      \
                      0, st, (const T *)a.un, (T *)a.um, (const T *)a.dense, (const PInfoD<T> *)a.pinfo, a.ball,       \
                      a.ball_meta, a.tiles, a.ntiles, a.nx, a.ny, a.nz, a.pitch, a.vol, a.nshots)
@@ -1087,7 +1084,7 @@ static void launch_patch(const StepArgs &a, hipStream_t st) {
       case 5: IB_PATCH_TILED_R(2, 1); break;
       case 6: IB_PATCH_TILED_R(3, 1); break;
       default:
-        hipLaunchKernelGGL((k_patch_tiled_m<T, kTileX, kTileY, kTileZOf<T>, kTileHalo>), dim3((unsigned)nblk), dim3(512), 0,
+        hipLaunchKernelGGL((k_patch_tiled_m<T, kTileX, kTileY, kTileZ, kTileHalo>), dim3((unsigned)nblk), dim3(512), 0,
                            st, (const T *)a.un, (T *)a.um, a.rec, (const PInfo<T> *)a.pinfo_tm, a.ball, a.ball_meta,
                            a.tiles, a.ntiles, a.nx, a.ny, a.nz, a.pitch, a.vol, a.nshots);
         break;
