@@ -10,7 +10,7 @@
 //                part of the modified Laplacian (the exterior values the interior
 //                stencil reads are zero, so the standard part is already complete);
 //   k_inject     point sources (also advances the device step counter);
-//   k_sample     receivers.
+//   k_sample     receivers (k_io_small does both in one launch for few receivers).
 #include <hip/hip_runtime.h>
 
 #include "ib_internal.h"
@@ -960,6 +960,40 @@ __global__ void k_sample(const T *unew, const int64_t *ridx, const T *rw, int nr
   traces[((size_t)s * nsteps + tl) * nrec + r] = v;
 }
 
+// Source injection and receiver sampling in one workgroup, for few receivers: the
+// workgroup barrier orders the injection before the sampling, so the step needs one launch
+// less (a small 2D step is launch-bound).  Same arithmetic as k_inject then k_sample.
+template <typename T>
+__global__ void k_io_small(T *unew, const int64_t *sidx, const T *sw, int nshots, int64_t vol, const T *wavelet,
+                           int64_t wstride, const int64_t *ridx, const T *rw, int nrec, T *traces, int64_t nsteps,
+                           int64_t *tcount) {
+  const int64_t t = tcount[0];
+  for (int e = threadIdx.x; e < nshots * 8; e += blockDim.x) {
+    int s = e >> 3;
+    int64_t idx = sidx[e];
+    if (idx >= 0) unew[(size_t)s * vol + idx] += wavelet[(size_t)s * wstride + t] * sw[e];
+  }
+  __syncthreads();
+  const int64_t tl = t - tcount[2];
+  for (int e = threadIdx.x; e < nrec * nshots; e += blockDim.x) {
+    const int s = e / nrec, r = e % nrec;
+    const T *u = unew + (size_t)s * vol;
+    T v = T(0);
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+      int64_t idx = ridx[(size_t)r * 8 + c];
+      if (idx >= 0) v += rw[(size_t)r * 8 + c] * u[idx];
+    }
+    traces[((size_t)s * nsteps + tl) * nrec + r] = v;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    tcount[1] = t;
+    tcount[0] = t + 1;
+  }
+}
+constexpr int kIoSmallMax = 1024;   // receivers x shots handled by k_io_small
+
 // Shots per pass of the tiled patch when a state holds several: each point's weights are
 // loaded once for the pass, the pass's tiles of p^n sit side by side in LDS.  Two FP32 shots
 // measured fastest (64 shots at 301x301x201: 92 -> 118 Gpts/s; four shots lose occupancy);
@@ -1102,6 +1136,12 @@ static void launch_patch(const StepArgs &a, hipStream_t st) {
 
 template <typename T>
 static void launch_io(const StepArgs &a, T *u, hipStream_t st) {
+  if (a.nrec > 0 && a.traces && (int64_t)a.nrec * a.nshots <= kIoSmallMax) {
+    hipLaunchKernelGGL(k_io_small<T>, dim3(1), dim3(256), 0, st, u, a.sidx, (const T *)a.sw, a.nshots, a.vol,
+                       (const T *)a.wavelet, a.wstride, a.ridx, (const T *)a.rw, a.nrec, (T *)a.traces, a.nsteps,
+                       a.tcount);
+    return;
+  }
   hipLaunchKernelGGL(k_inject<T>, dim3(1), dim3(256), 0, st, u, a.sidx, (const T *)a.sw, a.nshots, a.vol,
                      (const T *)a.wavelet, a.wstride, a.tcount);
   if (a.nrec > 0 && a.traces) {
