@@ -312,7 +312,7 @@ ib_status ib_state_run_kernel(ib_state *st, int32_t which, int32_t count, void *
  *     the device);
  *   patch_variant (tiled IB patch): 0-3 point records read per wavefront (bit 0 as scalar
  *     loads, bit 1 DPP wavefront sums); 4-6 records staged in LDS per tile with DPP sums and
- *     1-3 groups of two points' weights in flight (default 4); 7 compact records (bit masks
+ *     1-3 groups of two points' weights in flight, FP32 weights loaded in pairs (default 4); 7 compact records (bit masks
  *     and the data nodes' weights only); -1 keeps the current one.
  * Results do not depend on the interior knobs; the patch variants differ only in the
  * summation order of each point's weighted sum. */

@@ -13,6 +13,8 @@
 //   k_sample     receivers (k_io_small does both in one launch for few receivers).
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "ib_internal.h"
 #include "step.h"
 #include "wave.h"
@@ -574,7 +576,9 @@ struct PairW {
   T w[2][NS];
 };
 
-template <typename T, int TX, int TY, int TZ, int HR, int D, int SC>
+// VW = 2 (FP32): each lane loads two consecutive weights at once (dense ranges start at
+// even offsets and are padded with a zero to an even length), halving the weight loads.
+template <typename T, int TX, int TY, int TZ, int HR, int D, int SC, int VW = 1>
 __launch_bounds__(512)
 __global__ void k_patch_tiled_r(const T *__restrict__ un, T *__restrict__ unew, const T *__restrict__ dense,
                                 const PInfoD<T> *__restrict__ pinfo, const int32_t *__restrict__ ball,
@@ -585,6 +589,9 @@ __global__ void k_patch_tiled_r(const T *__restrict__ un, T *__restrict__ unew, 
   constexpr int BMAX = 64 * NS;
   constexpr int NW = 8;                       // wavefronts per workgroup (512 threads)
   constexpr int STEP = 2 * NW;                // points per wavefront group step
+  static_assert(VW == 1 || (VW == 2 && sizeof(T) == 4), "paired weight loads are FP32 only");
+  using WT = std::conditional_t<VW == 2, float2, T>;
+  constexpr int NSL = (VW == 2) ? 4 : NS;     // load slots per point (64 x VW lattice points each)
   // SC shots per pass: their tiles side by side in LDS, each point's weights loaded once
   __shared__ T sp[SC][LZ * LY * LX];
   __shared__ int16_t lofs[2][BMAX];
@@ -635,16 +642,18 @@ __global__ void k_patch_tiled_r(const T *__restrict__ un, T *__restrict__ unew, 
       woff = 0, fc = 0, lcc = 0;           // count 0: nothing loaded, nothing evaluated
     }
   };
-  auto load = [&](PairW<T, NS> &W, const uint32_t (&wo)[2], const uint32_t (&fc)[2]) {
+  auto load = [&](PairW<WT, NSL> &W, const uint32_t (&wo)[2], const uint32_t (&fc)[2]) {
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
       const int cnt = (int)(fc[h] >> 16);
 #pragma unroll
-      for (int k = 0; k < NS; ++k) {
-        const int e = k * 64 + lane;
+      for (int k = 0; k < NSL; ++k) {
+        const int e = (k * 64 + lane) * VW;
         // the weights are streamed once: non-temporal loads measured faster in FP64 and
         // slightly slower in FP32
-        if constexpr (sizeof(T) == 8)
+        if constexpr (VW == 2)
+          W.w[h][k] = (e < cnt) ? *reinterpret_cast<const float2 *>(&dense[wo[h] + e]) : float2(0.0f, 0.0f);
+        else if constexpr (sizeof(T) == 8)
           W.w[h][k] = (e < cnt) ? __builtin_nontemporal_load(&dense[wo[h] + e]) : T(0);
         else
           W.w[h][k] = (e < cnt) ? dense[wo[h] + e] : T(0);
@@ -654,7 +663,7 @@ __global__ void k_patch_tiled_r(const T *__restrict__ un, T *__restrict__ unew, 
   for (int s0 = 0; s0 < nshots; s0 += SC) {
     // records of D + 1 groups ahead, weights of D groups in flight before the staging
     uint32_t wo[D + 1][2], fc[D + 1][2], lcc[D + 1][2];
-    PairW<T, NS> W[D + 1];
+    PairW<WT, NSL> W[D + 1];
 #pragma unroll
     for (int d = 0; d <= D; ++d)
 #pragma unroll
@@ -690,12 +699,19 @@ __global__ void k_patch_tiled_r(const T *__restrict__ un, T *__restrict__ unew, 
 #pragma unroll
           for (int c = 0; c < SC; ++c) acc[c] = T(0);
 #pragma unroll
-          for (int k = 0; k < NS; ++k) {
-            const int e = k * 64 + lane;
+          for (int k = 0; k < NSL; ++k) {
+            const int e = (k * 64 + lane) * VW;
             if (e < cnt) {
-              const int o = lc + lt[e];
+              if constexpr (VW == 2) {
+                // e + 1 <= count: a zero weight at the record's pad, its lattice index in range
+                const int o0 = lc + lt[e], o1 = lc + lt[e + 1];
 #pragma unroll
-              for (int c = 0; c < SC; ++c) acc[c] += W[0].w[h][k] * sp[c][o];
+                for (int c = 0; c < SC; ++c) acc[c] += W[0].w[h][k].x * sp[c][o0] + W[0].w[h][k].y * sp[c][o1];
+              } else {
+                const int o = lc + lt[e];
+#pragma unroll
+                for (int c = 0; c < SC; ++c) acc[c] += W[0].w[h][k] * sp[c][o];
+              }
             }
           }
 #pragma unroll
@@ -1000,6 +1016,9 @@ constexpr int kIoSmallMax = 1024;   // receivers x shots handled by k_io_small
 // FP64 keeps one (two FP64 tiles would leave one workgroup per CU).
 template <typename T>
 constexpr int kPatchShots = (sizeof(T) == 8) ? 1 : 2;
+// FP32 weights are loaded in pairs (config 3 patch 0.221 -> 0.218 ms)
+template <typename T>
+constexpr int kPatchPairs = (sizeof(T) == 4) ? 2 : 1;
 
 // ---- boundary values ----------------------------------------------------------------
 // Inhomogeneous conditions: p^{n+1}_i += sum_q F[i][q] s_q(t_n) at every IB point, F
@@ -1100,7 +1119,8 @@ static void launch_patch(const StepArgs &a, hipStream_t st) {
                      st, (const T *)a.un, (T *)a.um, (const T *)a.dense, (const PInfoD<T> *)a.pinfo, a.ball,           \
                      a.ball_meta, a.tiles, a.ntiles, a.nx, a.ny, a.nz, a.pitch, a.vol, a.nshots)
 #define IB_PATCH_TILED_R(DD, SC)                                                                                    \
-  hipLaunchKernelGGL((k_patch_tiled_r<T, kTileX, kTileY, kTileZ, kTileHalo, DD, SC>), dim3((unsigned)nblk),           \
+  hipLaunchKernelGGL((k_patch_tiled_r<T, kTileX, kTileY, kTileZ, kTileHalo, DD, SC, kPatchPairs<T>>),                  \
+                     dim3((unsigned)nblk),                                                                           \
                      dim3(512),                                                                                      \
                      0, st, (const T *)a.un, (T *)a.um, (const T *)a.dense, (const PInfoD<T> *)a.pinfo, a.ball,       \
                      a.ball_meta, a.tiles, a.ntiles, a.nx, a.ny, a.nz, a.pitch, a.vol, a.nshots)

@@ -786,10 +786,12 @@ ib_status build_dense_records(ib_weights *w, hipStream_t st) {
     IB_HIP(hipMemcpyAsync(hf.data(), d_first, nib * 4, hipMemcpyDeviceToHost, st));
     IB_HIP(hipMemcpyAsync(hc.data(), d_count, nib * 4, hipMemcpyDeviceToHost, st));
     IB_HIP(hipStreamSynchronize(st));
+    // each record starts at an even offset (a zero pads odd lengths), so that the tiled
+    // patch can load FP32 weights in pairs
     int64_t sd = 0;
     for (int64_t i = 0; i < nib; ++i) {
       ho[i] = (uint32_t)sd;
-      sd += hc[i];
+      sd += (hc[i] + 1) & ~1;
     }
     if (sd >= (int64_t)UINT32_MAX) {
       set_error("dense stencil table too large");
@@ -797,8 +799,10 @@ ib_status build_dense_records(ib_weights *w, hipStream_t st) {
     }
     w->dense_words = sd;
     w->stats.dense_weights = sd;
-    if ((s = dalloc_t(&w->dense32, std::max<int64_t>(sd, 1))) || (s = dalloc_t(&w->dense64, std::max<int64_t>(sd, 1))))
+    if ((s = dalloc_t(&w->dense32, std::max<int64_t>(sd, 2))) || (s = dalloc_t(&w->dense64, std::max<int64_t>(sd, 2))))
       return s;
+    IB_HIP(hipMemsetAsync(w->dense32, 0, std::max<int64_t>(sd, 2) * sizeof(float), st));
+    IB_HIP(hipMemsetAsync(w->dense64, 0, std::max<int64_t>(sd, 2) * sizeof(double), st));
     IB_HIP(hipMemcpyAsync(d_doff, ho.data(), nib * 4, hipMemcpyHostToDevice, st));
     if (nib)
       hipLaunchKernelGGL(k_dense, dim3((unsigned)nib), dim3(64), 0, st, nib, w->rec32, w->rec_off32, w->ib_meta,
