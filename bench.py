@@ -19,6 +19,7 @@ into profiles/traffic.json by ``--summarize-counters FETCH_DIR WRITE_DIR``.
 from __future__ import annotations
 
 import argparse
+import dataclasses
 import hashlib
 import json
 import os
@@ -142,7 +143,8 @@ def cpu_baseline(budget_steps=5000):
     from oracle import stepper
     from oracle.parallel import solve_points
     from oracle.weights import IBModel
-    wl = W.small3d(cfg=95, n=24, nz=301, relief=50.0, nt=budget_steps, z_top_cells=20)
+    wl = dataclasses.replace(W.small3d(cfg=95, n=24, nz=301, relief=50.0, nt=budget_steps, z_top_cells=20),
+                             eta=W.config3(nt=1, with_velocity=False).eta)
     t0 = time.time()
     m = IBModel(wl.heights, wl.h, wl.shape, M=wl.M, surface=wl.surface, eta=wl.eta)
     sols = solve_points(m, procs=min(16, os.cpu_count() or 1))
@@ -319,14 +321,13 @@ def bench_config5(args):
 def bench_pv3d(args):
     """3D first-order p-v form, fourth order (the order of the paper's examples), over the
     401x401x301 fractal free surface of the headline workload; FP32 and FP64."""
-    import dataclasses
 
     import torch
 
     import paper_2309_03600_amd as ib
     from paper_2309_03600_amd import workloads as W
     K, Wm = args.steps, args.warmup
-    wl = dataclasses.replace(W.config3(nt=K + Wm + 8, lateral=args.lateral, depth=args.depth), M=4)
+    wl = dataclasses.replace(W.config3(nt=K + Wm + 8, lateral=args.lateral, depth=args.depth), M=4, eta=0.5)
     t0 = time.time()
     w = ib.ib_build_weights(wl.heights, wl.h, wl.shape, space_order=4, surface=wl.surface, eta=wl.eta, form="pv1")
     torch.cuda.synchronize()
