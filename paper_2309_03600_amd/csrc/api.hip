@@ -39,6 +39,8 @@ struct ib_state {
   int4 *tiles = nullptr;
   int ntiles = 0;
   int64_t nwide = 0;
+  hipStream_t aux = nullptr;   // the wide points' gather kernel runs here (3D, both kinds of points)
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   int32_t *delta = nullptr;
   int64_t *sidx = nullptr;
   void *sw = nullptr;
@@ -121,6 +123,9 @@ StepArgs make_args(ib_state *st, const void *wavelet, int64_t wstride, void *tra
   a.pinfo_wide = st->pinfo_w;
   a.pinfo_tm = st->pinfo_tm;
   a.nwide = st->nwide;
+  a.aux = st->aux;
+  a.ev_fork = st->ev_fork;
+  a.ev_join = st->ev_join;
   a.delta = st->delta;
   a.ball = w->ball;
   a.ball_meta = w->ball_meta;
@@ -899,6 +904,11 @@ ib_status ib_state_create(const ib_weights *w, const double *vel_dev, double dt,
       tl.push_back(make_int4(0, 0, 0, (int)tiled.size()));
       S->ntiles = (int)tl.size() - 1;
       S->nwide = (int64_t)wide.size();
+      if (S->ntiles > 0 && S->nwide > 0) {
+        IB_HIP(hipStreamCreateWithFlags(&S->aux, hipStreamNonBlocking));
+        IB_HIP(hipEventCreateWithFlags(&S->ev_fork, hipEventDisableTiming));
+        IB_HIP(hipEventCreateWithFlags(&S->ev_join, hipEventDisableTiming));
+      }
       int32_t *d_perm = nullptr;
       if ((s = dalloc(&S->pinfo_t, std::max<size_t>(tiled.size(), 1) * pinfo_dense_bytes(prec))) ||
           (s = dalloc(&S->pinfo_w, std::max<size_t>(wide.size(), 1) * pinfo_bytes(prec))) ||
@@ -1001,6 +1011,9 @@ void ib_state_free(ib_state *S) {
   if (!S) return;
   if (S->gexec) (void)hipGraphExecDestroy(S->gexec);
   if (S->graph) (void)hipGraphDestroy(S->graph);
+  if (S->aux) (void)hipStreamDestroy(S->aux);
+  if (S->ev_fork) (void)hipEventDestroy(S->ev_fork);
+  if (S->ev_join) (void)hipEventDestroy(S->ev_join);
   dfree(S->buf[0]);
   dfree(S->buf[1]);
   dfree(S->K);

@@ -37,6 +37,10 @@ struct StepArgs {
   int ntiles;
   const void *pinfo_wide;     // points handled by the gather kernel
   int64_t nwide;
+  // second stream and events on which the gather kernel of the wide points runs beside
+  // the tiled kernel (null: both on the step's stream)
+  hipStream_t aux;
+  hipEvent_t ev_fork, ev_join;
   const int32_t *ball;
   const int32_t *delta;       // linear offsets of the ball lattice points for this layout
   const int32_t *ball_meta;   // [code][2]: start, count

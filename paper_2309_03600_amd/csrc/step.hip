@@ -1112,6 +1112,7 @@ static void launch_interior(const StepArgs &a, hipStream_t st) {
 
 template <typename T>
 static void launch_patch(const StepArgs &a, hipStream_t st) {
+  if (a.ntiles > 0 && a.nwide > 0 && a.aux != nullptr) (void)hipEventRecord(a.ev_fork, st);
   if (a.ntiles > 0) {
     int64_t nblk = ((int64_t)a.ntiles + 7) / 8 * 8;
 #define IB_PATCH_TILED(PVV)                                                                                         \
@@ -1147,10 +1148,19 @@ static void launch_patch(const StepArgs &a, hipStream_t st) {
 #undef IB_PATCH_TILED_R
   }
   if (a.nwide > 0) {
+    // the few points with wider supports touch other nodes than the tiled points: their
+    // gather kernel runs on the second stream, beside the tiled kernel
+    const bool fork = a.ntiles > 0 && a.aux != nullptr;
+    hipStream_t ws = fork ? a.aux : st;
+    if (fork) (void)hipStreamWaitEvent(a.aux, a.ev_fork, 0);
     int64_t nblk = ((a.nwide + 3) / 4 + 7) / 8 * 8;
-    hipLaunchKernelGGL(k_patch<T>, dim3((unsigned)nblk), dim3(256), 0, st, (const T *)a.un, (T *)a.um, a.rec,
+    hipLaunchKernelGGL(k_patch<T>, dim3((unsigned)nblk), dim3(256), 0, ws, (const T *)a.un, (T *)a.um, a.rec,
                        (const PInfo<T> *)a.pinfo_wide, a.ball, a.delta, a.ball_meta, a.nwide, a.nx, a.ny, a.nz,
                        a.pitch, a.vol, a.nshots);
+    if (fork) {
+      (void)hipEventRecord(a.ev_join, a.aux);
+      (void)hipStreamWaitEvent(st, a.ev_join, 0);
+    }
   }
 }
 
