@@ -46,9 +46,12 @@ def test_config3_sampled_points_match_oracle():
     rng = np.random.default_rng([2309, 3, 11])
     nib = len(ex["ib_nodes"])
     pick = np.sort(rng.choice(nib, 48, replace=False))
+    # plus points whose support grew past the first radius (the gather kernel's points)
+    wide = np.flatnonzero(ex["ib_meta"][:, 0] > 0)[:16]
+    pick = np.union1d(pick, wide)
     nodes = ex["ib_nodes"][pick]
     pts = np.stack([nodes % nx, (nodes // nx) % ny, nodes // (nx * ny)], 1)
-    print(f"[config3] oracle solves of {len(pts)} sampled IB points", flush=True)
+    print(f"[config3] oracle solves of {len(pts)} sampled IB points ({len(wide)} with a grown support)", flush=True)
     res = pool_map(window_task, [(wl.heights, wl.h, nz, wl.M, wl.surface, wl.eta, tuple(p)) for p in pts])
     worst = 0.0
     for j, (s, _) in zip(pick, res):
