@@ -430,7 +430,9 @@ def main():
         ms_int = time_kernel(st, 0, nrep, torch)
         ms_patch = time_kernel(st, 1, nrep, torch)
         esz = 4 if prec == "f32" else 8
-        b_int = (4 * esz) * N
+        # interior kernel: p^n, p^{n-1} and K read, p^{n+1} written at each physical-side node
+        # (exterior nodes hold zeros that need no traffic)
+        b_int = (4 * esz) * stats["n_interior"]
         b_patch = esz * stats["sum_nw"] + (13 if prec == "f32" else 21) * stats["n_ib"]
         results[prec] = dict(ms_per_step=ms, host_ms_per_step=t_host * 1e3 / K, gpts=N / (ms * 1e-3) / 1e9,
                              interior_ms=ms_int, patch_ms=ms_patch,

@@ -270,7 +270,10 @@ ib_status ib_adjoint(ib_state *st, const void *residual_dev, const void *wavelet
  * state precision, device memory):  which = 0: p^n (newest), 1: p^{n-1}.
  * First-order form: which = 0: p^n, 2 + k: v_k^{n-1/2} (k < ndim; in 2D k = 1 is the
  * vertical velocity), 1 is invalid.
- * direction 0 copies out of the state, 1 copies into it. */
+ * direction 0 copies out of the state, 1 copies into it.  Values written at exterior
+ * nodes must be zero: the method takes the wavefield as zero outside the physical domain
+ * (the stencils of interior nodes read those nodes), and the interior kernels skip planes
+ * that hold exterior nodes only. */
 ib_status ib_state_field(ib_state *st, int32_t which, int32_t shot, void *dev_buf, int32_t direction,
                          void *stream);
 int64_t ib_state_step_count(const ib_state *st);

@@ -39,6 +39,7 @@ struct ib_state {
   int4 *tiles = nullptr;
   int ntiles = 0;
   int64_t nwide = 0;
+  int2 *zrange16 = nullptr, *zrange32 = nullptr;   // interior tiles' plane ranges (3D, M = 8)
   hipStream_t aux = nullptr;   // the wide points' gather kernel runs here (3D, both kinds of points)
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   int32_t *delta = nullptr;
@@ -123,6 +124,8 @@ StepArgs make_args(ib_state *st, const void *wavelet, int64_t wstride, void *tra
   a.pinfo_wide = st->pinfo_w;
   a.pinfo_tm = st->pinfo_tm;
   a.nwide = st->nwide;
+  a.zrange16 = st->zrange16;
+  a.zrange32 = st->zrange32;
   a.aux = st->aux;
   a.ev_fork = st->ev_fork;
   a.ev_join = st->ev_join;
@@ -940,6 +943,34 @@ ib_status ib_state_create(const ib_weights *w, const double *vel_dev, double dt,
   // sources: interior corners only; amplitude factor dt^2 w / (h^d (1 + s))
   std::vector<uint8_t> cls(w->N);
   IB_HIP(hipMemcpy(cls.data(), w->node_class, w->N, hipMemcpyDeviceToHost));
+  if (w->ndim == 3 && w->M == 8) {
+    // planes holding interior nodes, per column, then per 64 x TY interior tile
+    const int64_t nx = w->nx, ny = w->ny, nz = w->nz;
+    std::vector<int> clo(nx * ny, (int)nz), chi(nx * ny, 0);
+    for (int64_t z = 0; z < nz; ++z)
+      for (int64_t c = 0; c < nx * ny; ++c)
+        if (cls[z * nx * ny + c] & 1) {
+          clo[c] = std::min(clo[c], (int)z);
+          chi[c] = std::max(chi[c], (int)z + 1);
+        }
+    for (int ty : {16, 32}) {
+      const int64_t ntx = (nx + 63) / 64, nty = (ny + ty - 1) / ty;
+      std::vector<int2> zr(ntx * nty);
+      for (int64_t by = 0; by < nty; ++by)
+        for (int64_t bx = 0; bx < ntx; ++bx) {
+          int lo = (int)nz, hi = 0;
+          for (int64_t y = by * ty; y < std::min(ny, (by + 1) * ty); ++y)
+            for (int64_t x = bx * 64; x < std::min(nx, (bx + 1) * 64); ++x) {
+              lo = std::min(lo, clo[y * nx + x]);
+              hi = std::max(hi, chi[y * nx + x]);
+            }
+          zr[by * ntx + bx] = make_int2(lo, hi);
+        }
+      int2 **dst = (ty == 16) ? &S->zrange16 : &S->zrange32;
+      if ((s = dalloc_t(dst, zr.size()))) return fail(s);
+      IB_HIP(hipMemcpy(*dst, zr.data(), zr.size() * sizeof(int2), hipMemcpyHostToDevice));
+    }
+  }
   std::vector<int64_t> sidx(nshots * 8, -1);
   std::vector<double> swv(nshots * 8, 0.0);
   const double hd = std::pow(w->h, w->ndim);
@@ -1026,6 +1057,8 @@ void ib_state_free(ib_state *S) {
   dfree(S->pinfo_w);
   dfree(S->pinfo_tm);
   dfree(S->tiles);
+  dfree(S->zrange16);
+  dfree(S->zrange32);
   dfree(S->delta);
   dfree(S->sidx);
   dfree(S->sw);

@@ -23,6 +23,9 @@ struct StepArgs {
   int zchunk;
   int variant;          // 3D M=8 interior kernel: 0 basic, 1 pipelined 64x16, 2 pipelined 64x32
   int patch_variant;    // tiled IB patch: bit0 scalar records + weights fetched before staging, bit1 DPP sum
+  // per 64 x 16 and 64 x 32 interior tile: the planes [x, y) that hold interior nodes of its
+  // columns (3D eighth-order interior kernels)
+  const int2 *zrange16, *zrange32;
   const void *un;       // p^n
   void *um;             // p^{n-1} in, p^{n+1} out
   const void *K;

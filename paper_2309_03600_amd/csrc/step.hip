@@ -160,7 +160,7 @@ __launch_bounds__(64 * NW)
 __global__ void k_interior3d_p(const T *__restrict__ un, T *__restrict__ um, const T *__restrict__ K,
                                const T *__restrict__ sx, const T *__restrict__ sy, const T *__restrict__ sz,
                                StencilW<T> W, int nx, int ny, int nz, int64_t pitch, int64_t vol, int zchunk,
-                               int ntx, int nty, int nzc, int nshots) {
+                               int ntx, int nty, int nzc, int nshots, const int2 *__restrict__ zrange) {
   constexpr int TX = 64, TY = NW * RY, LX = TX + 2 * H, LY = TY + 2 * H;
   __shared__ T tile[2][LY][LX];
   const int64_t nblk = (int64_t)ntx * nty * nzc * nshots;
@@ -174,7 +174,14 @@ __global__ void k_interior3d_p(const T *__restrict__ un, T *__restrict__ um, con
   const int shot = (int)(L / nzc);
   const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
   const int x0 = bxi * TX, y0 = byi * TY;
-  const int z0 = bzi * zchunk, z1 = min(nz, z0 + zchunk);
+  // planes of the tile's columns outside [zrange.x, zrange.y) hold exterior nodes only,
+  // whose values stay zero: the tile's nzc chunks split that range evenly, so that the
+  // blocks of shallow and deep tiles carry the same work
+  (void)zchunk;                               // the host derives nzc from it
+  const int2 zr = zrange[byi * ntx + bxi];
+  const int zcs = (zr.y - zr.x + nzc - 1) / nzc;
+  const int z0 = zr.x + bzi * zcs, z1 = min(zr.y, z0 + zcs);
+  if (z0 >= z1) return;
   // 32-bit element offsets inside one shot's volume (the launcher checks the volume fits),
   // so that addresses are a scalar base plus one 32-bit offset
   const uint32_t plane = (uint32_t)(pitch * ny);
@@ -1052,11 +1059,13 @@ static void launch_interior(const StepArgs &a, hipStream_t st) {
   T *um = (T *)a.um;
   const T *K = (const T *)a.K;
   const T *sx = (const T *)a.sx, *sy = (const T *)a.sy, *sz = (const T *)a.sz;
-  if (a.ndim == 3 && a.M == 8 && a.variant >= 1 && a.vol * (int64_t)sizeof(T) < (int64_t(1) << 31)) {
+  if (a.ndim == 3 && a.M == 8 && a.variant >= 1 && a.vol * (int64_t)sizeof(T) < (int64_t(1) << 31) && a.zrange16 &&
+      a.zrange32) {
     const int RY = (a.variant == 2) ? 8 : (a.variant == 4 ? 2 : 4);
     const int NW = (a.variant == 3 || a.variant == 4) ? 8 : 4;
     const int TY = RY * NW;
     const int ntx = (a.nx + 63) / 64, nty = (a.ny + TY - 1) / TY;
+    const int2 *zr = (TY == 32) ? a.zrange32 : a.zrange16;
     const int zc = a.zchunk > 0 ? a.zchunk : a.nz;
     const int nzc = (a.nz + zc - 1) / zc;
     int64_t nblk = (int64_t)ntx * nty * nzc * a.nshots;
@@ -1064,16 +1073,16 @@ static void launch_interior(const StepArgs &a, hipStream_t st) {
     const StencilW<T> W = stencil_weights<T>(a.M);
     if (a.variant == 2)
       hipLaunchKernelGGL((k_interior3d_p<T, 4, 8, 4>), dim3((unsigned)nblk8), dim3(256), 0, st, un, um, K, sx, sy, sz,
-                         W, a.nx, a.ny, a.nz, a.pitch, a.vol, zc, ntx, nty, nzc, a.nshots);
+                         W, a.nx, a.ny, a.nz, a.pitch, a.vol, zc, ntx, nty, nzc, a.nshots, zr);
     else if (a.variant == 3)
       hipLaunchKernelGGL((k_interior3d_p<T, 4, 4, 8>), dim3((unsigned)nblk8), dim3(512), 0, st, un, um, K, sx, sy, sz,
-                         W, a.nx, a.ny, a.nz, a.pitch, a.vol, zc, ntx, nty, nzc, a.nshots);
+                         W, a.nx, a.ny, a.nz, a.pitch, a.vol, zc, ntx, nty, nzc, a.nshots, zr);
     else if (a.variant == 4)
       hipLaunchKernelGGL((k_interior3d_p<T, 4, 2, 8>), dim3((unsigned)nblk8), dim3(512), 0, st, un, um, K, sx, sy, sz,
-                         W, a.nx, a.ny, a.nz, a.pitch, a.vol, zc, ntx, nty, nzc, a.nshots);
+                         W, a.nx, a.ny, a.nz, a.pitch, a.vol, zc, ntx, nty, nzc, a.nshots, zr);
     else
       hipLaunchKernelGGL((k_interior3d_p<T, 4, 4, 4>), dim3((unsigned)nblk8), dim3(256), 0, st, un, um, K, sx, sy, sz,
-                         W, a.nx, a.ny, a.nz, a.pitch, a.vol, zc, ntx, nty, nzc, a.nshots);
+                         W, a.nx, a.ny, a.nz, a.pitch, a.vol, zc, ntx, nty, nzc, a.nshots, zr);
     return;
   }
   if (a.ndim == 3 && a.M == 8) {
