@@ -467,77 +467,83 @@ ib_status ib_build_weights(const ib_grid *g, const double *height_dev, const ib_
     return IB_ERR_ARG;
   }
   hipStream_t st = (hipStream_t)stream;
-  IB_HIP(hipGetDevice(&w->device));
-  ib_status s = geometry_build(w, height_dev, st);
-  if (s != IB_OK) {
-    ib_weights_free(w);
-    return s;
-  }
-  if (p->surface == IB_SURF_ROBIN && w->nb > 0) {
-    // the coefficient at each boundary point, kept in slot 6 of its record
-    hipLaunchKernelGGL(k_bp_robin, dim3((unsigned)((w->nb + 255) / 256)), dim3(256), 0, st, w->bp, w->nb,
-                       p->robin_dev, (int)w->nx, (int)w->ny, w->ndim - 1);
-    IB_HIP(hipGetLastError());
-    IB_HIP(hipStreamSynchronize(st));
-  }
-  w->prm.robin_dev = nullptr;   // borrowed for this call only
-  // the surface band must stay clear of the top and bottom of the box
-  {
-    std::vector<double> hs(w->nx * w->ny);
-    IB_HIP(hipMemcpy(hs.data(), w->Hs, hs.size() * 8, hipMemcpyDeviceToHost));
-    double lo = *std::min_element(hs.begin(), hs.end()), hi = *std::max_element(hs.begin(), hs.end());
-    double margin = (w->M + 1 + 2 * p->max_radius_steps) / 2.0 + w->M / 2 + 2;
-    if (lo < margin || hi > (double)(w->nz - 1) - margin) {
-      set_error("surface depth range [%.2f, %.2f] cells must keep %.1f cells from the top and bottom", lo, hi, margin);
-      ib_weights_free(w);
-      return IB_ERR_ARG;
-    }
-  }
-  w->form = p->form;
-  if (w->form == IB_FORM_P2 && (s = ib_points_build(w, st)) != IB_OK) {
-    ib_weights_free(w);
-    return s;
-  }
-  // boundary points are stored per column: rebuild column offsets for the solver
-  int64_t *col_off = nullptr;
-  {
-    int64_t ncol = w->nx * w->ny;
-    std::vector<double> bp(w->nb * 8);
-    if (w->nb) IB_HIP(hipMemcpy(bp.data(), w->bp, bp.size() * 8, hipMemcpyDeviceToHost));
-    std::vector<int64_t> off(ncol + 1, 0);
-    for (int64_t j = 0; j < w->nb; ++j) {
-      int64_t c = (int64_t)bp[j * 8 + 1] * w->nx + (int64_t)bp[j * 8 + 0];
-      off[c + 1]++;
-    }
-    for (int64_t c = 0; c < ncol; ++c) off[c + 1] += off[c];
-    if ((s = dalloc_t(&col_off, ncol + 1)) != IB_OK) {
-      ib_weights_free(w);
+  int64_t *col_off = nullptr;   // solver column offsets, released by the body or below
+  // every failure in the body returns through here, which frees the partly built table
+  auto build = [&]() -> ib_status {
+    IB_HIP(hipGetDevice(&w->device));
+    ib_status s = geometry_build(w, height_dev, st);
+    if (s != IB_OK) {
       return s;
     }
-    IB_HIP(hipMemcpy(col_off, off.data(), (ncol + 1) * 8, hipMemcpyHostToDevice));
-  }
-  if (w->form == IB_FORM_PV1)
-    s = pv_build(w, col_off, st);
-  else
-    s = (p->method == IB_METHOD_1D) ? mulder_build(w, st) : weights_build(w, col_off, st);
-  dfree(col_off);
-  if (s != IB_OK) {
+    if (p->surface == IB_SURF_ROBIN && w->nb > 0) {
+      // the coefficient at each boundary point, kept in slot 6 of its record
+      hipLaunchKernelGGL(k_bp_robin, dim3((unsigned)((w->nb + 255) / 256)), dim3(256), 0, st, w->bp, w->nb,
+                         p->robin_dev, (int)w->nx, (int)w->ny, w->ndim - 1);
+      IB_HIP(hipGetLastError());
+      IB_HIP(hipStreamSynchronize(st));
+    }
+    w->prm.robin_dev = nullptr;   // borrowed for this call only
+    // the surface band must stay clear of the top and bottom of the box
+    {
+      std::vector<double> hs(w->nx * w->ny);
+      IB_HIP(hipMemcpy(hs.data(), w->Hs, hs.size() * 8, hipMemcpyDeviceToHost));
+      double lo = *std::min_element(hs.begin(), hs.end()), hi = *std::max_element(hs.begin(), hs.end());
+      double margin = (w->M + 1 + 2 * p->max_radius_steps) / 2.0 + w->M / 2 + 2;
+      if (lo < margin || hi > (double)(w->nz - 1) - margin) {
+        set_error("surface depth range [%.2f, %.2f] cells must keep %.1f cells from the top and bottom", lo, hi, margin);
+        return IB_ERR_ARG;
+      }
+    }
+    w->form = p->form;
+    if (w->form == IB_FORM_P2 && (s = ib_points_build(w, st)) != IB_OK) {
+      return s;
+    }
+    // boundary points are stored per column: rebuild column offsets for the solver
+    {
+      int64_t ncol = w->nx * w->ny;
+      std::vector<double> bp(w->nb * 8);
+      if (w->nb) IB_HIP(hipMemcpy(bp.data(), w->bp, bp.size() * 8, hipMemcpyDeviceToHost));
+      std::vector<int64_t> off(ncol + 1, 0);
+      for (int64_t j = 0; j < w->nb; ++j) {
+        int64_t c = (int64_t)bp[j * 8 + 1] * w->nx + (int64_t)bp[j * 8 + 0];
+        off[c + 1]++;
+      }
+      for (int64_t c = 0; c < ncol; ++c) off[c + 1] += off[c];
+      if ((s = dalloc_t(&col_off, ncol + 1)) != IB_OK) {
+        return s;
+      }
+      IB_HIP(hipMemcpy(col_off, off.data(), (ncol + 1) * 8, hipMemcpyHostToDevice));
+    }
+    if (w->form == IB_FORM_PV1)
+      s = pv_build(w, col_off, st);
+    else
+      s = (p->method == IB_METHOD_1D) ? mulder_build(w, st) : weights_build(w, col_off, st);
+    dfree(col_off);
+    col_off = nullptr;
+    if (s != IB_OK) {
+      return s;
+    }
+    // statistics
+    {
+      std::vector<uint8_t> cls(w->N);
+      IB_HIP(hipMemcpy(cls.data(), w->node_class, w->N, hipMemcpyDeviceToHost));
+      int64_t ni = 0;
+      for (auto c : cls) ni += (c & 1);
+      w->stats.n_nodes = w->N;
+      w->stats.n_interior = ni;
+      w->stats.n_boundary_points = w->nb;
+      w->stats.n_ib = w->nib;
+    }
+    IB_HIP(hipStreamSynchronize(st));
+    w->stats.build_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    return IB_OK;
+  };
+  const ib_status status = build();
+  if (status != IB_OK) {
+    dfree(col_off);
     ib_weights_free(w);
-    return s;
+    return status;
   }
-  // statistics
-  {
-    std::vector<uint8_t> cls(w->N);
-    IB_HIP(hipMemcpy(cls.data(), w->node_class, w->N, hipMemcpyDeviceToHost));
-    int64_t ni = 0;
-    for (auto c : cls) ni += (c & 1);
-    w->stats.n_nodes = w->N;
-    w->stats.n_interior = ni;
-    w->stats.n_boundary_points = w->nb;
-    w->stats.n_ib = w->nib;
-  }
-  IB_HIP(hipStreamSynchronize(st));
-  w->stats.build_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
   *out = w;
   return IB_OK;
 }
@@ -715,324 +721,330 @@ ib_status ib_state_create(const ib_weights *w, const double *vel_dev, double dt,
   S->dt = dt;
   S->nrec = nrec;
   S->zchunk = 0;
-  ib_status s;
-  auto fail = [&](ib_status e) {
-    ib_state_free(S);
-    return e;
-  };
-  const size_t fbytes = (size_t)S->vol * nshots * S->esz;
-  if ((s = dalloc(&S->buf[0], fbytes)) || (s = dalloc(&S->buf[1], fbytes)) || (s = dalloc(&S->K, S->vol * S->esz)))
-    return fail(s);
-  IB_HIP(hipMemsetAsync(S->buf[0], 0, fbytes, st));
-  IB_HIP(hipMemsetAsync(S->buf[1], 0, fbytes, st));
-  IB_HIP(hipMemsetAsync(S->K, 0, S->vol * S->esz, st));
-  const double f = dt / w->h;
-  const int T = 256;
-  if (prec == IB_F32)
-    hipLaunchKernelGGL(k_make_K<float>, dim3((w->N + T - 1) / T), dim3(T), 0, st, vel_dev, w->node_class,
-                       (float *)S->K, (int)w->nx, (int)w->ny, (int)w->nz, S->pitch, f);
-  else
-    hipLaunchKernelGGL(k_make_K<double>, dim3((w->N + T - 1) / T), dim3(T), 0, st, vel_dev, w->node_class,
-                       (double *)S->K, (int)w->nx, (int)w->ny, (int)w->nz, S->pitch, f);
-  IB_HIP(hipGetLastError());
-  // damping tables
-  double vmax = 0.0;
-  {
-    std::vector<double> v(w->N);
-    IB_HIP(hipMemcpyAsync(v.data(), vel_dev, w->N * 8, hipMemcpyDeviceToHost, st));
-    IB_HIP(hipStreamSynchronize(st));
-    for (double x : v) vmax = std::max(vmax, x);
-  }
-  const double dmax = (damp_width > 0) ? 3.0 * vmax * std::log(1.0 / damp_R) / (2.0 * damp_width * w->h) : 0.0;
-  std::vector<double> ax = damping_axis(w->nx, damp_width, dmax, dt, true);
-  std::vector<double> ay = (w->ndim == 3) ? damping_axis(w->ny, damp_width, dmax, dt, true) : std::vector<double>(1, 0.0);
-  std::vector<double> az = damping_axis(w->nz, damp_width, dmax, dt, false);
-  double *d_ax = nullptr, *d_ay = nullptr, *d_az = nullptr;
-  if ((s = dalloc_t(&d_ax, ax.size())) || (s = dalloc_t(&d_ay, ay.size())) || (s = dalloc_t(&d_az, az.size())))
-    return fail(s);
-  IB_HIP(hipMemcpy(d_ax, ax.data(), ax.size() * 8, hipMemcpyHostToDevice));
-  IB_HIP(hipMemcpy(d_ay, ay.data(), ay.size() * 8, hipMemcpyHostToDevice));
-  IB_HIP(hipMemcpy(d_az, az.data(), az.size() * 8, hipMemcpyHostToDevice));
-  auto upload_cast = [&](const std::vector<double> &v, void **dst) -> ib_status {
-    ib_status e = dalloc(dst, v.size() * S->esz);
-    if (e) return e;
-    if (prec == IB_F32) {
-      std::vector<float> t(v.begin(), v.end());
-      IB_HIP(hipMemcpy(*dst, t.data(), t.size() * 4, hipMemcpyHostToDevice));
+  // every failure in the body returns through here, which frees the partly built state
+  auto build = [&]() -> ib_status {
+    ib_status s;
+    auto fail = [](ib_status e) { return e; };
+    const size_t fbytes = (size_t)S->vol * nshots * S->esz;
+    if ((s = dalloc(&S->buf[0], fbytes)) || (s = dalloc(&S->buf[1], fbytes)) || (s = dalloc(&S->K, S->vol * S->esz)))
+      return fail(s);
+    IB_HIP(hipMemsetAsync(S->buf[0], 0, fbytes, st));
+    IB_HIP(hipMemsetAsync(S->buf[1], 0, fbytes, st));
+    IB_HIP(hipMemsetAsync(S->K, 0, S->vol * S->esz, st));
+    const double f = dt / w->h;
+    const int T = 256;
+    if (prec == IB_F32)
+      hipLaunchKernelGGL(k_make_K<float>, dim3((w->N + T - 1) / T), dim3(T), 0, st, vel_dev, w->node_class,
+                         (float *)S->K, (int)w->nx, (int)w->ny, (int)w->nz, S->pitch, f);
+    else
+      hipLaunchKernelGGL(k_make_K<double>, dim3((w->N + T - 1) / T), dim3(T), 0, st, vel_dev, w->node_class,
+                         (double *)S->K, (int)w->nx, (int)w->ny, (int)w->nz, S->pitch, f);
+    IB_HIP(hipGetLastError());
+    // damping tables
+    double vmax = 0.0;
+    {
+      std::vector<double> v(w->N);
+      IB_HIP(hipMemcpyAsync(v.data(), vel_dev, w->N * 8, hipMemcpyDeviceToHost, st));
+      IB_HIP(hipStreamSynchronize(st));
+      for (double x : v) vmax = std::max(vmax, x);
+    }
+    const double dmax = (damp_width > 0) ? 3.0 * vmax * std::log(1.0 / damp_R) / (2.0 * damp_width * w->h) : 0.0;
+    std::vector<double> ax = damping_axis(w->nx, damp_width, dmax, dt, true);
+    std::vector<double> ay = (w->ndim == 3) ? damping_axis(w->ny, damp_width, dmax, dt, true) : std::vector<double>(1, 0.0);
+    std::vector<double> az = damping_axis(w->nz, damp_width, dmax, dt, false);
+    double *d_ax = nullptr, *d_ay = nullptr, *d_az = nullptr;
+    if ((s = dalloc_t(&d_ax, ax.size())) || (s = dalloc_t(&d_ay, ay.size())) || (s = dalloc_t(&d_az, az.size())))
+      return fail(s);
+    IB_HIP(hipMemcpy(d_ax, ax.data(), ax.size() * 8, hipMemcpyHostToDevice));
+    IB_HIP(hipMemcpy(d_ay, ay.data(), ay.size() * 8, hipMemcpyHostToDevice));
+    IB_HIP(hipMemcpy(d_az, az.data(), az.size() * 8, hipMemcpyHostToDevice));
+    auto upload_cast = [&](const std::vector<double> &v, void **dst) -> ib_status {
+      ib_status e = dalloc(dst, v.size() * S->esz);
+      if (e) return e;
+      if (prec == IB_F32) {
+        std::vector<float> t(v.begin(), v.end());
+        IB_HIP(hipMemcpy(*dst, t.data(), t.size() * 4, hipMemcpyHostToDevice));
+      } else {
+        IB_HIP(hipMemcpy(*dst, v.data(), v.size() * 8, hipMemcpyHostToDevice));
+      }
+      return IB_OK;
+    };
+    if ((s = upload_cast(ax, &S->sx)) || (s = upload_cast(ay, &S->sy)) || (s = upload_cast(az, &S->sz))) return fail(s);
+    S->ax = ax;
+    S->ay = ay;
+    S->az = az;
+    S->form = w->form;
+    if (w->form == IB_FORM_PV1) {
+      // first-order form: K holds dt c^2 / h at interior p nodes, kv dt / h at interior v nodes
+      S->nv = w->ndim;
+      if ((int64_t)S->vol * S->nv >= ((int64_t)1 << 32)) {
+        // modified-row entries address the velocity fields with 32-bit indices
+        set_error("the first-order form needs ndim * padded grid < 2^32 nodes");
+        return fail(IB_ERR_ARG);
+      }
+      const size_t vbytes = (size_t)S->vol * S->nv * nshots * S->esz;
+      if ((s = dalloc(&S->vbuf, vbytes)) || (s = dalloc(&S->kv, (size_t)S->vol * S->nv * S->esz))) return fail(s);
+      IB_HIP(hipMemsetAsync(S->vbuf, 0, vbytes, st));
+      IB_HIP(hipMemsetAsync(S->kv, 0, (size_t)S->vol * S->nv * S->esz, st));
+      for (int n = 0; n < S->nv; ++n) {
+        char *dst = (char *)S->kv + (size_t)n * S->vol * S->esz;
+        if (prec == IB_F32)
+          hipLaunchKernelGGL(k_make_coef<float>, dim3((w->N + T - 1) / T), dim3(T), 0, st, vel_dev, w->vcls[n],
+                             (float *)dst, (int)w->nx, (int)w->ny, (int)w->nz, S->pitch, f, 0);
+        else
+          hipLaunchKernelGGL(k_make_coef<double>, dim3((w->N + T - 1) / T), dim3(T), 0, st, vel_dev, w->vcls[n],
+                             (double *)dst, (int)w->nx, (int)w->ny, (int)w->nz, S->pitch, f, 0);
+      }
+      if (prec == IB_F32)
+        hipLaunchKernelGGL(k_make_coef<float>, dim3((w->N + T - 1) / T), dim3(T), 0, st, vel_dev, w->node_class,
+                           (float *)S->K, (int)w->nx, (int)w->ny, (int)w->nz, S->pitch, dt / w->h, 1);
+      else
+        hipLaunchKernelGGL(k_make_coef<double>, dim3((w->N + T - 1) / T), dim3(T), 0, st, vel_dev, w->node_class,
+                           (double *)S->K, (int)w->nx, (int)w->ny, (int)w->nz, S->pitch, dt / w->h, 1);
+      IB_HIP(hipGetLastError());
+      // modified rows with their scales, in the state layout
+      std::vector<double> velh(w->N);
+      IB_HIP(hipMemcpy(velh.data(), vel_dev, w->N * 8, hipMemcpyDeviceToHost));
+      auto padded = [&](int64_t node) {
+        const int64_t x = node % w->nx, y = (node / w->nx) % w->ny, z = node / (w->nx * w->ny);
+        return (z * w->ny + y) * S->pitch + x;
+      };
+      auto sig = [&](int64_t node) {
+        const int64_t x = node % w->nx, y = (node / w->nx) % w->ny, z = node / (w->nx * w->ny);
+        return ax[x] + ay[w->ndim == 3 ? y : 0] + az[z];
+      };
+      std::vector<int64_t> gn, gs(1, 0), ge, dn, ds(1, 0), de;
+      std::vector<double> gsc, gw, dsc, dw;
+      const int64_t nr = (int64_t)w->pv_row_fam.size();
+      for (int64_t r = 0; r < nr; ++r) {
+        const int fam = w->pv_row_fam[r];
+        const int64_t node = w->pv_row_node[r];
+        const bool grad = fam < S->nv;
+        for (int64_t e = w->pv_row_start[r]; e < w->pv_row_start[r + 1]; ++e) {
+          const int fld = w->pv_ent_field[e];
+          const int64_t q = padded(w->pv_ent_node[e]) + (fld >= 0 ? (int64_t)fld * S->vol : 0);
+          (grad ? ge : de).push_back(q);
+          (grad ? gw : dw).push_back(w->pv_ent_w[e]);
+        }
+        if (grad) {
+          gn.push_back((int64_t)fam * S->vol + padded(node));
+          gsc.push_back(f / (1.0 + sig(node)));
+          gs.push_back((int64_t)ge.size());
+        } else {
+          const double c = velh[node];
+          dn.push_back(padded(node));
+          dsc.push_back((dt * c * c / w->h) / (1.0 + sig(node)));
+          ds.push_back((int64_t)de.size());
+        }
+      }
+      S->nrows_g = (int64_t)gn.size();
+      S->nrows_d = (int64_t)dn.size();
+      // rows of fewer than 40 entries on average take 8 lanes each (more rows per wavefront)
+      S->g_lanes = (gn.empty() || ge.size() >= 40 * gn.size()) ? 16 : 8;
+      S->d_lanes = (dn.empty() || de.size() >= 40 * dn.size()) ? 16 : 8;
+      auto up64 = [&](const std::vector<int64_t> &v, int64_t **d) -> ib_status {
+        ib_status e = dalloc_t(d, std::max<size_t>(v.size(), 1));
+        if (e) return e;
+        if (!v.empty()) IB_HIP(hipMemcpy(*d, v.data(), v.size() * 8, hipMemcpyHostToDevice));
+        return IB_OK;
+      };
+      auto up32 = [&](const std::vector<int64_t> &v, uint32_t **d) -> ib_status {
+        std::vector<uint32_t> n32(v.begin(), v.end());
+        ib_status e = dalloc_t(d, std::max<size_t>(n32.size(), 1));
+        if (e) return e;
+        if (!n32.empty()) IB_HIP(hipMemcpy(*d, n32.data(), n32.size() * 4, hipMemcpyHostToDevice));
+        return IB_OK;
+      };
+      if ((s = up64(gn, &S->g_node)) || (s = up64(gs, &S->g_start)) || (s = up32(ge, &S->g_enode)) ||
+          (s = up64(dn, &S->d_node)) || (s = up64(ds, &S->d_start)) || (s = up32(de, &S->d_enode)) ||
+          (s = upload_cast(gsc.empty() ? std::vector<double>(1, 0.0) : gsc, &S->g_scale)) ||
+          (s = upload_cast(gw.empty() ? std::vector<double>(1, 0.0) : gw, &S->g_w)) ||
+          (s = upload_cast(dsc.empty() ? std::vector<double>(1, 0.0) : dsc, &S->d_scale)) ||
+          (s = upload_cast(dw.empty() ? std::vector<double>(1, 0.0) : dw, &S->d_w)))
+        return fail(s);
     } else {
-      IB_HIP(hipMemcpy(*dst, v.data(), v.size() * 8, hipMemcpyHostToDevice));
+      if ((s = dalloc(&S->scale, std::max<int64_t>(w->nib, 1) * S->esz))) return fail(s);
+      if (w->nib > 0) {
+        if (prec == IB_F32)
+          hipLaunchKernelGGL(k_make_scale<float>, dim3((w->nib + T - 1) / T), dim3(T), 0, st, w->ib_xyz, w->nib, vel_dev,
+                             (int)w->nx, (int)w->ny, f, d_ax, d_ay, d_az, (float *)S->scale);
+        else
+          hipLaunchKernelGGL(k_make_scale<double>, dim3((w->nib + T - 1) / T), dim3(T), 0, st, w->ib_xyz, w->nib,
+                             vel_dev, (int)w->nx, (int)w->ny, f, d_ax, d_ay, d_az, (double *)S->scale);
+        IB_HIP(hipGetLastError());
+      }
+      if ((s = dalloc(&S->pinfo, std::max<int64_t>(w->nib, 1) * pinfo_bytes(prec))) ||
+          (s = dalloc_t(&S->delta, std::max<size_t>(w->balls.packed.size(), 1))))
+        return fail(s);
+      enqueue_make_pinfo(prec, w->ib_xyz, prec == IB_F32 ? w->rec_off32 : w->rec_off64, S->scale, nullptr, w->nib,
+                         S->pinfo, st);
+      {
+        // bucket the IB points into LDS tiles (3D); wider supports go to the gather kernel
+        std::vector<int16_t> xyz(w->nib * 4);
+        if (w->nib) IB_HIP(hipMemcpy(xyz.data(), w->ib_xyz, w->nib * 8, hipMemcpyDeviceToHost));
+        std::vector<int32_t> tiled, wide;
+        const bool use_tiles = (w->ndim == 3);
+        const int64_t tx = (w->nx + kTileX - 1) / kTileX, ty = (w->ny + kTileY - 1) / kTileY;
+        for (int64_t i = 0; i < w->nib; ++i) {
+          const int code = xyz[i * 4 + 3];
+          if (use_tiles && (code == 8 || code == 9) && kTileHalo == 4)
+            tiled.push_back((int32_t)i);
+          else
+            wide.push_back((int32_t)i);
+        }
+        // lateral tile column, then depth; a tile opens at the first point not covered by the
+        // previous one of its column
+        auto ckey = [&](int32_t i) { return (int64_t)(xyz[i * 4 + 1] / kTileY) * tx + xyz[i * 4 + 0] / kTileX; };
+        std::stable_sort(tiled.begin(), tiled.end(), [&](int32_t a, int32_t b) {
+          const int64_t ka = ckey(a), kb = ckey(b);
+          return ka != kb ? ka < kb : xyz[a * 4 + 2] < xyz[b * 4 + 2];
+        });
+        std::vector<int4> tl;
+        int zopen = 0;
+        for (size_t j = 0; j < tiled.size(); ++j) {
+          const int32_t i = tiled[j];
+          const int z = xyz[i * 4 + 2];
+          if (j == 0 || ckey(i) != ckey(tiled[j - 1]) || z >= zopen + kTileZ || (int)j - tl.back().w >= kTileMaxPoints) {
+            zopen = z;
+            tl.push_back(make_int4(xyz[i * 4] / kTileX * kTileX, xyz[i * 4 + 1] / kTileY * kTileY, z, (int)j));
+          }
+        }
+        tl.push_back(make_int4(0, 0, 0, (int)tiled.size()));
+        S->ntiles = (int)tl.size() - 1;
+        S->nwide = (int64_t)wide.size();
+        if (S->ntiles > 0 && S->nwide > 0) {
+          IB_HIP(hipStreamCreateWithFlags(&S->aux, hipStreamNonBlocking));
+          IB_HIP(hipEventCreateWithFlags(&S->ev_fork, hipEventDisableTiming));
+          IB_HIP(hipEventCreateWithFlags(&S->ev_join, hipEventDisableTiming));
+        }
+        int32_t *d_perm = nullptr;
+        if ((s = dalloc(&S->pinfo_t, std::max<size_t>(tiled.size(), 1) * pinfo_dense_bytes(prec))) ||
+            (s = dalloc(&S->pinfo_w, std::max<size_t>(wide.size(), 1) * pinfo_bytes(prec))) ||
+            (s = dalloc(&S->pinfo_tm, std::max<size_t>(tiled.size(), 1) * pinfo_bytes(prec))) ||
+            (s = dalloc_t(&S->tiles, tl.size())) ||
+            (s = dalloc_t(&d_perm, std::max<size_t>(std::max(tiled.size(), wide.size()), 1))))
+          return fail(s);
+        IB_HIP(hipMemcpy(S->tiles, tl.data(), tl.size() * sizeof(int4), hipMemcpyHostToDevice));
+        const uint32_t *ro = (prec == IB_F32) ? w->rec_off32 : w->rec_off64;
+        if (!tiled.empty()) {
+          IB_HIP(hipMemcpy(d_perm, tiled.data(), tiled.size() * 4, hipMemcpyHostToDevice));
+          enqueue_make_pinfo_dense(prec, w->ib_xyz, w->dense_first, w->dense_count, w->dense_off, S->scale, d_perm,
+                                   (int64_t)tiled.size(), S->pinfo_t, st);
+          enqueue_make_pinfo(prec, w->ib_xyz, ro, S->scale, d_perm, (int64_t)tiled.size(), S->pinfo_tm, st);
+          IB_HIP(hipStreamSynchronize(st));
+        }
+        if (!wide.empty()) {
+          IB_HIP(hipMemcpy(d_perm, wide.data(), wide.size() * 4, hipMemcpyHostToDevice));
+          enqueue_make_pinfo(prec, w->ib_xyz, ro, S->scale, d_perm, (int64_t)wide.size(), S->pinfo_w, st);
+          IB_HIP(hipStreamSynchronize(st));
+        }
+        dfree(d_perm);
+      }
+      enqueue_make_delta(w->ball, (int)w->balls.packed.size(), S->pitch, S->pitch * w->ny, S->delta, st);
+      IB_HIP(hipGetLastError());
+    }
+    IB_HIP(hipStreamSynchronize(st));
+    dfree(d_ax), dfree(d_ay), dfree(d_az);
+    // sources: interior corners only; amplitude factor dt^2 w / (h^d (1 + s))
+    std::vector<uint8_t> cls(w->N);
+    IB_HIP(hipMemcpy(cls.data(), w->node_class, w->N, hipMemcpyDeviceToHost));
+    if (w->ndim == 3 && w->M == 8) {
+      // planes holding interior nodes, per column, then per 64 x TY interior tile
+      const int64_t nx = w->nx, ny = w->ny, nz = w->nz;
+      std::vector<int> clo(nx * ny, (int)nz), chi(nx * ny, 0);
+      for (int64_t z = 0; z < nz; ++z)
+        for (int64_t c = 0; c < nx * ny; ++c)
+          if (cls[z * nx * ny + c] & 1) {
+            clo[c] = std::min(clo[c], (int)z);
+            chi[c] = std::max(chi[c], (int)z + 1);
+          }
+      for (int ty : {16, 32}) {
+        const int64_t ntx = (nx + 63) / 64, nty = (ny + ty - 1) / ty;
+        std::vector<int2> zr(ntx * nty);
+        for (int64_t by = 0; by < nty; ++by)
+          for (int64_t bx = 0; bx < ntx; ++bx) {
+            int lo = (int)nz, hi = 0;
+            for (int64_t y = by * ty; y < std::min(ny, (by + 1) * ty); ++y)
+              for (int64_t x = bx * 64; x < std::min(nx, (bx + 1) * 64); ++x) {
+                lo = std::min(lo, clo[y * nx + x]);
+                hi = std::max(hi, chi[y * nx + x]);
+              }
+            zr[by * ntx + bx] = make_int2(lo, hi);
+          }
+        int2 **dst = (ty == 16) ? &S->zrange16 : &S->zrange32;
+        if ((s = dalloc_t(dst, zr.size()))) return fail(s);
+        IB_HIP(hipMemcpy(*dst, zr.data(), zr.size() * sizeof(int2), hipMemcpyHostToDevice));
+      }
+    }
+    std::vector<int64_t> sidx(nshots * 8, -1);
+    std::vector<double> swv(nshots * 8, 0.0);
+    const double hd = std::pow(w->h, w->ndim);
+    for (int sh = 0; sh < nshots; ++sh) {
+      int64_t idx[8], idu[8];
+      double wt[8];
+      if (!corners(w, src_pos + (size_t)sh * w->ndim, idx, wt, S->pitch, true) ||
+          !corners(w, src_pos + (size_t)sh * w->ndim, idu, wt, S->pitch, false)) {
+        set_error("source %d outside the box", sh);
+        return fail(IB_ERR_ARG);
+      }
+      for (int c = 0; c < 8; ++c) {
+        if (idx[c] < 0) continue;
+        if (!(cls[idu[c]] & 1)) {
+          set_error("source %d touches an exterior node", sh);
+          return fail(IB_ERR_ARG);
+        }
+        int64_t x = idu[c] % w->nx, y = (idu[c] / w->nx) % w->ny, z = idu[c] / (w->nx * w->ny);
+        double sd = ax[x] + ay[(w->ndim == 3) ? y : 0] + az[z];
+        sidx[sh * 8 + c] = idx[c];
+        swv[sh * 8 + c] = (w->form == IB_FORM_PV1 ? dt : dt * dt) * wt[c] / (hd * (1.0 + sd));
+      }
+    }
+    if ((s = dalloc_t(&S->sidx, nshots * 8)) || (s = dalloc(&S->sw, nshots * 8 * S->esz))) return fail(s);
+    IB_HIP(hipMemcpy(S->sidx, sidx.data(), nshots * 64, hipMemcpyHostToDevice));
+    {
+      void *tmp = nullptr;
+      std::vector<double> v(swv);
+      if ((s = upload_cast(v, &tmp))) return fail(s);
+      IB_HIP(hipMemcpy(S->sw, tmp, nshots * 8 * S->esz, hipMemcpyDeviceToDevice));
+      dfree(tmp);
+    }
+    // receivers
+    std::vector<int64_t> ridx(std::max(nrec, 1) * 8, -1);
+    std::vector<double> rwv(std::max(nrec, 1) * 8, 0.0);
+    for (int r = 0; r < nrec; ++r) {
+      int64_t idx[8];
+      double wt[8];
+      if (!corners(w, rec_pos + (size_t)r * w->ndim, idx, wt, S->pitch, true)) {
+        set_error("receiver %d outside the box", r);
+        return fail(IB_ERR_ARG);
+      }
+      for (int c = 0; c < 8; ++c) {
+        ridx[r * 8 + c] = idx[c];
+        rwv[r * 8 + c] = wt[c];
+      }
+    }
+    if ((s = dalloc_t(&S->ridx, ridx.size())) || (s = upload_cast(rwv, &S->rw))) return fail(s);
+    S->ridx_h = ridx;
+    S->rw_h = rwv;
+    IB_HIP(hipMemcpy(S->ridx, ridx.data(), ridx.size() * 8, hipMemcpyHostToDevice));
+    if ((s = dalloc_t(&S->tcount, 4))) return fail(s);
+    IB_HIP(hipMemset(S->tcount, 0, 32));
+    IB_HIP(hipStreamSynchronize(st));
+    // z-chunking of the 3D interior kernel: enough workgroups to fill 256 CUs
+    if (w->ndim == 3 && w->form == IB_FORM_P2) {
+      int64_t tiles = ((w->nx + 63) / 64) * ((w->ny + 15) / 16) * nshots;
+      int64_t want = 2048;
+      int nzc = (int)std::max<int64_t>(1, std::min<int64_t>(w->nz / 16, (want + tiles - 1) / tiles));
+      S->zchunk = (int)((w->nz + nzc - 1) / nzc);
+      S->zchunk_auto = S->zchunk;
+      if ((s = autotune_interior(S, st))) return fail(s);
     }
     return IB_OK;
   };
-  if ((s = upload_cast(ax, &S->sx)) || (s = upload_cast(ay, &S->sy)) || (s = upload_cast(az, &S->sz))) return fail(s);
-  S->ax = ax;
-  S->ay = ay;
-  S->az = az;
-  S->form = w->form;
-  if (w->form == IB_FORM_PV1) {
-    // first-order form: K holds dt c^2 / h at interior p nodes, kv dt / h at interior v nodes
-    S->nv = w->ndim;
-    if ((int64_t)S->vol * S->nv >= ((int64_t)1 << 32)) {
-      // modified-row entries address the velocity fields with 32-bit indices
-      set_error("the first-order form needs ndim * padded grid < 2^32 nodes");
-      return fail(IB_ERR_ARG);
-    }
-    const size_t vbytes = (size_t)S->vol * S->nv * nshots * S->esz;
-    if ((s = dalloc(&S->vbuf, vbytes)) || (s = dalloc(&S->kv, (size_t)S->vol * S->nv * S->esz))) return fail(s);
-    IB_HIP(hipMemsetAsync(S->vbuf, 0, vbytes, st));
-    IB_HIP(hipMemsetAsync(S->kv, 0, (size_t)S->vol * S->nv * S->esz, st));
-    for (int n = 0; n < S->nv; ++n) {
-      char *dst = (char *)S->kv + (size_t)n * S->vol * S->esz;
-      if (prec == IB_F32)
-        hipLaunchKernelGGL(k_make_coef<float>, dim3((w->N + T - 1) / T), dim3(T), 0, st, vel_dev, w->vcls[n],
-                           (float *)dst, (int)w->nx, (int)w->ny, (int)w->nz, S->pitch, f, 0);
-      else
-        hipLaunchKernelGGL(k_make_coef<double>, dim3((w->N + T - 1) / T), dim3(T), 0, st, vel_dev, w->vcls[n],
-                           (double *)dst, (int)w->nx, (int)w->ny, (int)w->nz, S->pitch, f, 0);
-    }
-    if (prec == IB_F32)
-      hipLaunchKernelGGL(k_make_coef<float>, dim3((w->N + T - 1) / T), dim3(T), 0, st, vel_dev, w->node_class,
-                         (float *)S->K, (int)w->nx, (int)w->ny, (int)w->nz, S->pitch, dt / w->h, 1);
-    else
-      hipLaunchKernelGGL(k_make_coef<double>, dim3((w->N + T - 1) / T), dim3(T), 0, st, vel_dev, w->node_class,
-                         (double *)S->K, (int)w->nx, (int)w->ny, (int)w->nz, S->pitch, dt / w->h, 1);
-    IB_HIP(hipGetLastError());
-    // modified rows with their scales, in the state layout
-    std::vector<double> velh(w->N);
-    IB_HIP(hipMemcpy(velh.data(), vel_dev, w->N * 8, hipMemcpyDeviceToHost));
-    auto padded = [&](int64_t node) {
-      const int64_t x = node % w->nx, y = (node / w->nx) % w->ny, z = node / (w->nx * w->ny);
-      return (z * w->ny + y) * S->pitch + x;
-    };
-    auto sig = [&](int64_t node) {
-      const int64_t x = node % w->nx, y = (node / w->nx) % w->ny, z = node / (w->nx * w->ny);
-      return ax[x] + ay[w->ndim == 3 ? y : 0] + az[z];
-    };
-    std::vector<int64_t> gn, gs(1, 0), ge, dn, ds(1, 0), de;
-    std::vector<double> gsc, gw, dsc, dw;
-    const int64_t nr = (int64_t)w->pv_row_fam.size();
-    for (int64_t r = 0; r < nr; ++r) {
-      const int fam = w->pv_row_fam[r];
-      const int64_t node = w->pv_row_node[r];
-      const bool grad = fam < S->nv;
-      for (int64_t e = w->pv_row_start[r]; e < w->pv_row_start[r + 1]; ++e) {
-        const int fld = w->pv_ent_field[e];
-        const int64_t q = padded(w->pv_ent_node[e]) + (fld >= 0 ? (int64_t)fld * S->vol : 0);
-        (grad ? ge : de).push_back(q);
-        (grad ? gw : dw).push_back(w->pv_ent_w[e]);
-      }
-      if (grad) {
-        gn.push_back((int64_t)fam * S->vol + padded(node));
-        gsc.push_back(f / (1.0 + sig(node)));
-        gs.push_back((int64_t)ge.size());
-      } else {
-        const double c = velh[node];
-        dn.push_back(padded(node));
-        dsc.push_back((dt * c * c / w->h) / (1.0 + sig(node)));
-        ds.push_back((int64_t)de.size());
-      }
-    }
-    S->nrows_g = (int64_t)gn.size();
-    S->nrows_d = (int64_t)dn.size();
-    // rows of fewer than 40 entries on average take 8 lanes each (more rows per wavefront)
-    S->g_lanes = (gn.empty() || ge.size() >= 40 * gn.size()) ? 16 : 8;
-    S->d_lanes = (dn.empty() || de.size() >= 40 * dn.size()) ? 16 : 8;
-    auto up64 = [&](const std::vector<int64_t> &v, int64_t **d) -> ib_status {
-      ib_status e = dalloc_t(d, std::max<size_t>(v.size(), 1));
-      if (e) return e;
-      if (!v.empty()) IB_HIP(hipMemcpy(*d, v.data(), v.size() * 8, hipMemcpyHostToDevice));
-      return IB_OK;
-    };
-    auto up32 = [&](const std::vector<int64_t> &v, uint32_t **d) -> ib_status {
-      std::vector<uint32_t> n32(v.begin(), v.end());
-      ib_status e = dalloc_t(d, std::max<size_t>(n32.size(), 1));
-      if (e) return e;
-      if (!n32.empty()) IB_HIP(hipMemcpy(*d, n32.data(), n32.size() * 4, hipMemcpyHostToDevice));
-      return IB_OK;
-    };
-    if ((s = up64(gn, &S->g_node)) || (s = up64(gs, &S->g_start)) || (s = up32(ge, &S->g_enode)) ||
-        (s = up64(dn, &S->d_node)) || (s = up64(ds, &S->d_start)) || (s = up32(de, &S->d_enode)) ||
-        (s = upload_cast(gsc.empty() ? std::vector<double>(1, 0.0) : gsc, &S->g_scale)) ||
-        (s = upload_cast(gw.empty() ? std::vector<double>(1, 0.0) : gw, &S->g_w)) ||
-        (s = upload_cast(dsc.empty() ? std::vector<double>(1, 0.0) : dsc, &S->d_scale)) ||
-        (s = upload_cast(dw.empty() ? std::vector<double>(1, 0.0) : dw, &S->d_w)))
-      return fail(s);
-  } else {
-    if ((s = dalloc(&S->scale, std::max<int64_t>(w->nib, 1) * S->esz))) return fail(s);
-    if (w->nib > 0) {
-      if (prec == IB_F32)
-        hipLaunchKernelGGL(k_make_scale<float>, dim3((w->nib + T - 1) / T), dim3(T), 0, st, w->ib_xyz, w->nib, vel_dev,
-                           (int)w->nx, (int)w->ny, f, d_ax, d_ay, d_az, (float *)S->scale);
-      else
-        hipLaunchKernelGGL(k_make_scale<double>, dim3((w->nib + T - 1) / T), dim3(T), 0, st, w->ib_xyz, w->nib,
-                           vel_dev, (int)w->nx, (int)w->ny, f, d_ax, d_ay, d_az, (double *)S->scale);
-      IB_HIP(hipGetLastError());
-    }
-    if ((s = dalloc(&S->pinfo, std::max<int64_t>(w->nib, 1) * pinfo_bytes(prec))) ||
-        (s = dalloc_t(&S->delta, std::max<size_t>(w->balls.packed.size(), 1))))
-      return fail(s);
-    enqueue_make_pinfo(prec, w->ib_xyz, prec == IB_F32 ? w->rec_off32 : w->rec_off64, S->scale, nullptr, w->nib,
-                       S->pinfo, st);
-    {
-      // bucket the IB points into LDS tiles (3D); wider supports go to the gather kernel
-      std::vector<int16_t> xyz(w->nib * 4);
-      if (w->nib) IB_HIP(hipMemcpy(xyz.data(), w->ib_xyz, w->nib * 8, hipMemcpyDeviceToHost));
-      std::vector<int32_t> tiled, wide;
-      const bool use_tiles = (w->ndim == 3);
-      const int64_t tx = (w->nx + kTileX - 1) / kTileX, ty = (w->ny + kTileY - 1) / kTileY;
-      for (int64_t i = 0; i < w->nib; ++i) {
-        const int code = xyz[i * 4 + 3];
-        if (use_tiles && (code == 8 || code == 9) && kTileHalo == 4)
-          tiled.push_back((int32_t)i);
-        else
-          wide.push_back((int32_t)i);
-      }
-      // lateral tile column, then depth; a tile opens at the first point not covered by the
-      // previous one of its column
-      auto ckey = [&](int32_t i) { return (int64_t)(xyz[i * 4 + 1] / kTileY) * tx + xyz[i * 4 + 0] / kTileX; };
-      std::stable_sort(tiled.begin(), tiled.end(), [&](int32_t a, int32_t b) {
-        const int64_t ka = ckey(a), kb = ckey(b);
-        return ka != kb ? ka < kb : xyz[a * 4 + 2] < xyz[b * 4 + 2];
-      });
-      std::vector<int4> tl;
-      int zopen = 0;
-      for (size_t j = 0; j < tiled.size(); ++j) {
-        const int32_t i = tiled[j];
-        const int z = xyz[i * 4 + 2];
-        if (j == 0 || ckey(i) != ckey(tiled[j - 1]) || z >= zopen + kTileZ || (int)j - tl.back().w >= kTileMaxPoints) {
-          zopen = z;
-          tl.push_back(make_int4(xyz[i * 4] / kTileX * kTileX, xyz[i * 4 + 1] / kTileY * kTileY, z, (int)j));
-        }
-      }
-      tl.push_back(make_int4(0, 0, 0, (int)tiled.size()));
-      S->ntiles = (int)tl.size() - 1;
-      S->nwide = (int64_t)wide.size();
-      if (S->ntiles > 0 && S->nwide > 0) {
-        IB_HIP(hipStreamCreateWithFlags(&S->aux, hipStreamNonBlocking));
-        IB_HIP(hipEventCreateWithFlags(&S->ev_fork, hipEventDisableTiming));
-        IB_HIP(hipEventCreateWithFlags(&S->ev_join, hipEventDisableTiming));
-      }
-      int32_t *d_perm = nullptr;
-      if ((s = dalloc(&S->pinfo_t, std::max<size_t>(tiled.size(), 1) * pinfo_dense_bytes(prec))) ||
-          (s = dalloc(&S->pinfo_w, std::max<size_t>(wide.size(), 1) * pinfo_bytes(prec))) ||
-          (s = dalloc(&S->pinfo_tm, std::max<size_t>(tiled.size(), 1) * pinfo_bytes(prec))) ||
-          (s = dalloc_t(&S->tiles, tl.size())) ||
-          (s = dalloc_t(&d_perm, std::max<size_t>(std::max(tiled.size(), wide.size()), 1))))
-        return fail(s);
-      IB_HIP(hipMemcpy(S->tiles, tl.data(), tl.size() * sizeof(int4), hipMemcpyHostToDevice));
-      const uint32_t *ro = (prec == IB_F32) ? w->rec_off32 : w->rec_off64;
-      if (!tiled.empty()) {
-        IB_HIP(hipMemcpy(d_perm, tiled.data(), tiled.size() * 4, hipMemcpyHostToDevice));
-        enqueue_make_pinfo_dense(prec, w->ib_xyz, w->dense_first, w->dense_count, w->dense_off, S->scale, d_perm,
-                                 (int64_t)tiled.size(), S->pinfo_t, st);
-        enqueue_make_pinfo(prec, w->ib_xyz, ro, S->scale, d_perm, (int64_t)tiled.size(), S->pinfo_tm, st);
-        IB_HIP(hipStreamSynchronize(st));
-      }
-      if (!wide.empty()) {
-        IB_HIP(hipMemcpy(d_perm, wide.data(), wide.size() * 4, hipMemcpyHostToDevice));
-        enqueue_make_pinfo(prec, w->ib_xyz, ro, S->scale, d_perm, (int64_t)wide.size(), S->pinfo_w, st);
-        IB_HIP(hipStreamSynchronize(st));
-      }
-      dfree(d_perm);
-    }
-    enqueue_make_delta(w->ball, (int)w->balls.packed.size(), S->pitch, S->pitch * w->ny, S->delta, st);
-    IB_HIP(hipGetLastError());
-  }
-  IB_HIP(hipStreamSynchronize(st));
-  dfree(d_ax), dfree(d_ay), dfree(d_az);
-  // sources: interior corners only; amplitude factor dt^2 w / (h^d (1 + s))
-  std::vector<uint8_t> cls(w->N);
-  IB_HIP(hipMemcpy(cls.data(), w->node_class, w->N, hipMemcpyDeviceToHost));
-  if (w->ndim == 3 && w->M == 8) {
-    // planes holding interior nodes, per column, then per 64 x TY interior tile
-    const int64_t nx = w->nx, ny = w->ny, nz = w->nz;
-    std::vector<int> clo(nx * ny, (int)nz), chi(nx * ny, 0);
-    for (int64_t z = 0; z < nz; ++z)
-      for (int64_t c = 0; c < nx * ny; ++c)
-        if (cls[z * nx * ny + c] & 1) {
-          clo[c] = std::min(clo[c], (int)z);
-          chi[c] = std::max(chi[c], (int)z + 1);
-        }
-    for (int ty : {16, 32}) {
-      const int64_t ntx = (nx + 63) / 64, nty = (ny + ty - 1) / ty;
-      std::vector<int2> zr(ntx * nty);
-      for (int64_t by = 0; by < nty; ++by)
-        for (int64_t bx = 0; bx < ntx; ++bx) {
-          int lo = (int)nz, hi = 0;
-          for (int64_t y = by * ty; y < std::min(ny, (by + 1) * ty); ++y)
-            for (int64_t x = bx * 64; x < std::min(nx, (bx + 1) * 64); ++x) {
-              lo = std::min(lo, clo[y * nx + x]);
-              hi = std::max(hi, chi[y * nx + x]);
-            }
-          zr[by * ntx + bx] = make_int2(lo, hi);
-        }
-      int2 **dst = (ty == 16) ? &S->zrange16 : &S->zrange32;
-      if ((s = dalloc_t(dst, zr.size()))) return fail(s);
-      IB_HIP(hipMemcpy(*dst, zr.data(), zr.size() * sizeof(int2), hipMemcpyHostToDevice));
-    }
-  }
-  std::vector<int64_t> sidx(nshots * 8, -1);
-  std::vector<double> swv(nshots * 8, 0.0);
-  const double hd = std::pow(w->h, w->ndim);
-  for (int sh = 0; sh < nshots; ++sh) {
-    int64_t idx[8], idu[8];
-    double wt[8];
-    if (!corners(w, src_pos + (size_t)sh * w->ndim, idx, wt, S->pitch, true) ||
-        !corners(w, src_pos + (size_t)sh * w->ndim, idu, wt, S->pitch, false)) {
-      set_error("source %d outside the box", sh);
-      return fail(IB_ERR_ARG);
-    }
-    for (int c = 0; c < 8; ++c) {
-      if (idx[c] < 0) continue;
-      if (!(cls[idu[c]] & 1)) {
-        set_error("source %d touches an exterior node", sh);
-        return fail(IB_ERR_ARG);
-      }
-      int64_t x = idu[c] % w->nx, y = (idu[c] / w->nx) % w->ny, z = idu[c] / (w->nx * w->ny);
-      double sd = ax[x] + ay[(w->ndim == 3) ? y : 0] + az[z];
-      sidx[sh * 8 + c] = idx[c];
-      swv[sh * 8 + c] = (w->form == IB_FORM_PV1 ? dt : dt * dt) * wt[c] / (hd * (1.0 + sd));
-    }
-  }
-  if ((s = dalloc_t(&S->sidx, nshots * 8)) || (s = dalloc(&S->sw, nshots * 8 * S->esz))) return fail(s);
-  IB_HIP(hipMemcpy(S->sidx, sidx.data(), nshots * 64, hipMemcpyHostToDevice));
-  {
-    void *tmp = nullptr;
-    std::vector<double> v(swv);
-    if ((s = upload_cast(v, &tmp))) return fail(s);
-    IB_HIP(hipMemcpy(S->sw, tmp, nshots * 8 * S->esz, hipMemcpyDeviceToDevice));
-    dfree(tmp);
-  }
-  // receivers
-  std::vector<int64_t> ridx(std::max(nrec, 1) * 8, -1);
-  std::vector<double> rwv(std::max(nrec, 1) * 8, 0.0);
-  for (int r = 0; r < nrec; ++r) {
-    int64_t idx[8];
-    double wt[8];
-    if (!corners(w, rec_pos + (size_t)r * w->ndim, idx, wt, S->pitch, true)) {
-      set_error("receiver %d outside the box", r);
-      return fail(IB_ERR_ARG);
-    }
-    for (int c = 0; c < 8; ++c) {
-      ridx[r * 8 + c] = idx[c];
-      rwv[r * 8 + c] = wt[c];
-    }
-  }
-  if ((s = dalloc_t(&S->ridx, ridx.size())) || (s = upload_cast(rwv, &S->rw))) return fail(s);
-  S->ridx_h = ridx;
-  S->rw_h = rwv;
-  IB_HIP(hipMemcpy(S->ridx, ridx.data(), ridx.size() * 8, hipMemcpyHostToDevice));
-  if ((s = dalloc_t(&S->tcount, 4))) return fail(s);
-  IB_HIP(hipMemset(S->tcount, 0, 32));
-  IB_HIP(hipStreamSynchronize(st));
-  // z-chunking of the 3D interior kernel: enough workgroups to fill 256 CUs
-  if (w->ndim == 3 && w->form == IB_FORM_P2) {
-    int64_t tiles = ((w->nx + 63) / 64) * ((w->ny + 15) / 16) * nshots;
-    int64_t want = 2048;
-    int nzc = (int)std::max<int64_t>(1, std::min<int64_t>(w->nz / 16, (want + tiles - 1) / tiles));
-    S->zchunk = (int)((w->nz + nzc - 1) / nzc);
-    S->zchunk_auto = S->zchunk;
-    if ((s = autotune_interior(S, st))) return fail(s);
+  const ib_status status = build();
+  if (status != IB_OK) {
+    ib_state_free(S);
+    return status;
   }
   *out = S;
   return IB_OK;
