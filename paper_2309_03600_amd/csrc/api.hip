@@ -40,6 +40,7 @@ struct ib_state {
   int ntiles = 0;
   int64_t nwide = 0;
   int2 *zrange16 = nullptr, *zrange32 = nullptr;   // interior tiles' plane ranges (3D, M = 8)
+  int2 *zr4 = nullptr;         // first-order form, 3D: plane ranges of the 64 x 4 column blocks
   hipStream_t aux = nullptr;   // the wide points' gather kernel runs here (3D, both kinds of points)
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   int32_t *delta = nullptr;
@@ -976,6 +977,38 @@ ib_status ib_state_create(const ib_weights *w, const double *vel_dev, double dt,
         IB_HIP(hipMemcpy(*dst, zr.data(), zr.size() * sizeof(int2), hipMemcpyHostToDevice));
       }
     }
+    if (w->form == IB_FORM_PV1 && w->ndim == 3) {
+      // planes holding interior p or v nodes, per column, then per 64 x 4 column block
+      const int64_t nx = w->nx, ny = w->ny, nz = w->nz, nc = nx * ny;
+      std::vector<uint8_t> any(cls.size());
+      for (size_t q = 0; q < cls.size(); ++q) any[q] = cls[q] & 1;
+      std::vector<uint8_t> vc(w->N);
+      for (int n = 0; n < 3; ++n) {
+        IB_HIP(hipMemcpy(vc.data(), w->vcls[n], w->N, hipMemcpyDeviceToHost));
+        for (size_t q = 0; q < vc.size(); ++q) any[q] |= vc[q] & 1;
+      }
+      std::vector<int> clo(nc, (int)nz), chi(nc, 0);
+      for (int64_t z = 0; z < nz; ++z)
+        for (int64_t c = 0; c < nc; ++c)
+          if (any[z * nc + c]) {
+            clo[c] = std::min(clo[c], (int)z);
+            chi[c] = std::max(chi[c], (int)z + 1);
+          }
+      const int64_t nbx = (nx + 63) / 64, nby = (ny + 3) / 4;
+      std::vector<int2> zr(nbx * nby);
+      for (int64_t by = 0; by < nby; ++by)
+        for (int64_t bx = 0; bx < nbx; ++bx) {
+          int lo = (int)nz, hi = 0;
+          for (int64_t y = by * 4; y < std::min(ny, (by + 1) * 4); ++y)
+            for (int64_t x = bx * 64; x < std::min(nx, (bx + 1) * 64); ++x) {
+              lo = std::min(lo, clo[y * nx + x]);
+              hi = std::max(hi, chi[y * nx + x]);
+            }
+          zr[by * nbx + bx] = make_int2(lo, hi);
+        }
+      if ((s = dalloc_t(&S->zr4, zr.size()))) return fail(s);
+      IB_HIP(hipMemcpy(S->zr4, zr.data(), zr.size() * sizeof(int2), hipMemcpyHostToDevice));
+    }
     std::vector<int64_t> sidx(nshots * 8, -1);
     std::vector<double> swv(nshots * 8, 0.0);
     const double hd = std::pow(w->h, w->ndim);
@@ -1070,6 +1103,7 @@ void ib_state_free(ib_state *S) {
   dfree(S->pinfo_tm);
   dfree(S->tiles);
   dfree(S->zrange16);
+  dfree(S->zr4);
   dfree(S->zrange32);
   dfree(S->delta);
   dfree(S->sidx);
@@ -1123,6 +1157,7 @@ PVArgs make_pv_args(const ib_state *S) {
   a.pitch = S->pitch;
   a.vol = S->vol;
   a.nshots = S->nshots;
+  a.zr4 = S->zr4;
   a.p = S->buf[0];
   a.v = S->vbuf;
   a.kp = S->K;

@@ -297,14 +297,20 @@ __launch_bounds__(256)
 __global__ void k_pv_velocity3d(T *__restrict__ v, const T *__restrict__ p, const uint8_t *__restrict__ c0,
                                 const uint8_t *__restrict__ c1, const uint8_t *__restrict__ c2, T fv,
                                 const T *__restrict__ sx, const T *__restrict__ sy, const T *__restrict__ sz,
-                                StaggerW<T> W, int nx, int ny, int nz, int64_t pitch, int64_t vol, int zc) {
+                                StaggerW<T> W, int nx, int ny, int nz, int64_t pitch, int64_t vol, int zc,
+                                const int2 *__restrict__ zr) {
   const int x = blockIdx.x * 64 + (threadIdx.x & 63);
   const int y = blockIdx.y * 4 + (threadIdx.x >> 6);
   const int nzc = (nz + zc - 1) / zc;
   const int shot = blockIdx.z / nzc;
-  const int z0 = (blockIdx.z - shot * nzc) * zc;
+  // the block's nzc chunks split evenly the planes that hold interior nodes of its columns
+  // (the others hold zeros that stay zero)
+  const int2 r = zr[blockIdx.y * gridDim.x + blockIdx.x];
+  const int zcs = (r.y - r.x + nzc - 1) / nzc;
+  const int z0 = r.x + (blockIdx.z - shot * nzc) * zcs;
   if (x >= nx || y >= ny) return;
-  const int z1 = min(z0 + zc, nz);
+  const int z1 = min(z0 + zcs, r.y);
+  if (z0 >= z1) return;
   const int64_t plane = pitch * ny;
   const T *pp = p + (size_t)shot * vol;
   int xo[2 * H], yo[2 * H];
@@ -349,14 +355,20 @@ template <typename T, int H>
 __launch_bounds__(256)
 __global__ void k_pv_pressure3d(T *__restrict__ p, const T *__restrict__ v, const T *__restrict__ kp,
                                 const T *__restrict__ sx, const T *__restrict__ sy, const T *__restrict__ sz,
-                                StaggerW<T> W, int nx, int ny, int nz, int64_t pitch, int64_t vol, int zc) {
+                                StaggerW<T> W, int nx, int ny, int nz, int64_t pitch, int64_t vol, int zc,
+                                const int2 *__restrict__ zr) {
   const int x = blockIdx.x * 64 + (threadIdx.x & 63);
   const int y = blockIdx.y * 4 + (threadIdx.x >> 6);
   const int nzc = (nz + zc - 1) / zc;
   const int shot = blockIdx.z / nzc;
-  const int z0 = (blockIdx.z - shot * nzc) * zc;
+  // the block's nzc chunks split evenly the planes that hold interior nodes of its columns
+  // (the others hold zeros that stay zero)
+  const int2 r = zr[blockIdx.y * gridDim.x + blockIdx.x];
+  const int zcs = (r.y - r.x + nzc - 1) / nzc;
+  const int z0 = r.x + (blockIdx.z - shot * nzc) * zcs;
   if (x >= nx || y >= ny) return;
-  const int z1 = min(z0 + zc, nz);
+  const int z1 = min(z0 + zcs, r.y);
+  if (z0 >= z1) return;
   const int64_t plane = pitch * ny;
   const T *v0 = v + (size_t)shot * 3 * vol, *v1 = v0 + vol, *v2 = v1 + vol;
   int xo[2 * H], yo[2 * H];
@@ -445,10 +457,10 @@ static void pv_step_h(const PVArgs &a, hipStream_t st) {
   const int zc = 32;
   const dim3 g3((unsigned)((a.nx + 63) / 64), (unsigned)((a.ny + 3) / 4),
                 (unsigned)(((a.nz + zc - 1) / zc) * a.nshots));
-  if (a.ndim == 3)
+  if (a.ndim == 3 && a.zr4)
     hipLaunchKernelGGL((k_pv_velocity3d<T, H>), g3, b, 0, st, (T *)a.v, (const T *)a.p, a.vcls[0], a.vcls[1],
                        a.vcls[2], (T)a.fv, (const T *)a.sx, (const T *)a.sy, (const T *)a.sz, W, a.nx, a.ny, a.nz,
-                       a.pitch, a.vol, zc);
+                       a.pitch, a.vol, zc, a.zr4);
   else
     hipLaunchKernelGGL((k_pv_velocity<T, H>), gv, b, 0, st, (T *)a.v, (const T *)a.p, (const T *)a.kv,
                        (const T *)a.sx, (const T *)a.sy, (const T *)a.sz, W, a.nx, a.ny, a.nz, a.pitch, a.vol, a.nv,
@@ -463,9 +475,10 @@ static void pv_step_h(const PVArgs &a, hipStream_t st) {
                          (int64_t)a.nv * a.vol, (const T *)a.p, a.vol, a.g_node, (const T *)a.g_scale, a.g_start,
                          a.g_enode, (const T *)a.g_w, a.nrows_g, a.nshots);
   }
-  if (a.ndim == 3)
+  if (a.ndim == 3 && a.zr4)
     hipLaunchKernelGGL((k_pv_pressure3d<T, H>), g3, b, 0, st, (T *)a.p, (const T *)a.v, (const T *)a.kp,
-                       (const T *)a.sx, (const T *)a.sy, (const T *)a.sz, W, a.nx, a.ny, a.nz, a.pitch, a.vol, zc);
+                       (const T *)a.sx, (const T *)a.sy, (const T *)a.sz, W, a.nx, a.ny, a.nz, a.pitch, a.vol, zc,
+                       a.zr4);
   else
     hipLaunchKernelGGL((k_pv_pressure<T, H>), gp, b, 0, st, (T *)a.p, (const T *)a.v, (const T *)a.kp,
                        (const T *)a.sx, (const T *)a.sy, (const T *)a.sz, W, a.nx, a.ny, a.nz, a.pitch, a.vol, a.nv,

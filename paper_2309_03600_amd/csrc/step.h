@@ -92,6 +92,8 @@ struct PVArgs {
   const uint32_t *g_enode, *d_enode;   // entry source nodes: padded index + field * vol (< 2^32)
   const void *g_scale, *g_w, *d_scale, *d_w;
   int g_lanes, d_lanes;        // lanes per modified row (8 for short rows, else 16)
+  const int2 *zr4;             // 3D: per 64 x 4 column block, the planes [x, y) that hold
+                               // interior p or v nodes of its columns
 };
 void enqueue_pv_step(const PVArgs &a, hipStream_t st);
 void enqueue_interior_only(const StepArgs &a, hipStream_t st);
