@@ -41,6 +41,7 @@ struct ib_state {
   int64_t nwide = 0;
   int2 *zrange16 = nullptr, *zrange32 = nullptr;   // interior tiles' plane ranges (3D, M = 8)
   int2 *zr4 = nullptr;         // first-order form, 3D: plane ranges of the 64 x 4 column blocks
+  int zfirst = 0, zlast = 0;   // planes [zfirst, zlast) hold every interior node
   hipStream_t aux = nullptr;   // the wide points' gather kernel runs here (3D, both kinds of points)
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   int32_t *delta = nullptr;
@@ -126,6 +127,8 @@ StepArgs make_args(ib_state *st, const void *wavelet, int64_t wstride, void *tra
   a.pinfo_tm = st->pinfo_tm;
   a.nwide = st->nwide;
   a.zrange16 = st->zrange16;
+  a.zfirst = st->zfirst;
+  a.zlast = st->zlast;
   a.zrange32 = st->zrange32;
   a.aux = st->aux;
   a.ev_fork = st->ev_fork;
@@ -949,6 +952,19 @@ ib_status ib_state_create(const ib_weights *w, const double *vel_dev, double dt,
     // sources: interior corners only; amplitude factor dt^2 w / (h^d (1 + s))
     std::vector<uint8_t> cls(w->N);
     IB_HIP(hipMemcpy(cls.data(), w->node_class, w->N, hipMemcpyDeviceToHost));
+    {
+      // planes holding interior nodes, over all columns
+      const int64_t nc = w->nx * w->ny;
+      int lo = (int)w->nz, hi = 0;
+      for (int64_t z = 0; z < w->nz; ++z)
+        for (int64_t c = 0; c < nc; ++c)
+          if (cls[z * nc + c] & 1) {
+            lo = std::min(lo, (int)z);
+            hi = std::max(hi, (int)z + 1);
+          }
+      S->zfirst = lo < hi ? lo : 0;
+      S->zlast = lo < hi ? hi : 0;
+    }
     if (w->ndim == 3 && w->M == 8) {
       // planes holding interior nodes, per column, then per 64 x TY interior tile
       const int64_t nx = w->nx, ny = w->ny, nz = w->nz;

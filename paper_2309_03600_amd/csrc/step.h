@@ -26,6 +26,7 @@ struct StepArgs {
   // per 64 x 16 and 64 x 32 interior tile: the planes [x, y) that hold interior nodes of its
   // columns (3D eighth-order interior kernels)
   const int2 *zrange16, *zrange32;
+  int zfirst, zlast;    // planes [zfirst, zlast) hold all interior nodes (generic interior kernel)
   const void *un;       // p^n
   void *um;             // p^{n-1} in, p^{n+1} out
   const void *K;

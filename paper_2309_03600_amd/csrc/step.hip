@@ -303,8 +303,9 @@ template <typename T, int H>
 __global__ void k_interior_generic(const T *__restrict__ un, T *__restrict__ um, const T *__restrict__ K,
                                    const T *__restrict__ sx, const T *__restrict__ sy, const T *__restrict__ sz,
                                    StencilW<T> W, int nx, int ny, int nz, int lat, int64_t pitch, int64_t vol,
-                                   int nshots) {
-  const int64_t per = (int64_t)nx * ny * nz;
+                                   int nshots, int zf, int zl) {
+  // only the planes [zf, zl) hold interior nodes; the others hold zeros that stay zero
+  const int64_t per = (int64_t)nx * ny * (zl - zf);
   int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (g >= per * nshots) return;
   const int shot = (int)(g / per);
@@ -312,7 +313,7 @@ __global__ void k_interior_generic(const T *__restrict__ un, T *__restrict__ um,
   const int x = (int)(i % nx);
   i /= nx;
   const int y = (int)(i % ny);
-  const int z = (int)(i / ny);
+  const int z = zf + (int)(i / ny);
   const int64_t plane = pitch * ny;
   const T *u = un + (size_t)shot * vol;
   T *o = um + (size_t)shot * vol;
@@ -1096,25 +1097,27 @@ static void launch_interior(const StepArgs &a, hipStream_t st) {
                        stencil_weights<T>(a.M), a.nx, a.ny, a.nz, a.pitch, a.vol, zc, ntx, nty, nzc, a.nshots);
     return;
   }
-  const int64_t tot = (int64_t)a.nx * a.ny * a.nz * a.nshots;
+  const int zf = a.zlast > a.zfirst ? a.zfirst : 0, zl = a.zlast > a.zfirst ? a.zlast : a.nz;
+  const int64_t tot = (int64_t)a.nx * a.ny * (zl - zf) * a.nshots;
+  if (tot == 0) return;
   dim3 g((unsigned)((tot + 255) / 256)), b(256);
   const int lat = a.ndim - 1;
   switch (a.M) {
     case 2:
       hipLaunchKernelGGL((k_interior_generic<T, 1>), g, b, 0, st, un, um, K, sx, sy, sz, stencil_weights<T>(2), a.nx,
-                         a.ny, a.nz, lat, a.pitch, a.vol, a.nshots);
+                         a.ny, a.nz, lat, a.pitch, a.vol, a.nshots, zf, zl);
       break;
     case 4:
       hipLaunchKernelGGL((k_interior_generic<T, 2>), g, b, 0, st, un, um, K, sx, sy, sz, stencil_weights<T>(4), a.nx,
-                         a.ny, a.nz, lat, a.pitch, a.vol, a.nshots);
+                         a.ny, a.nz, lat, a.pitch, a.vol, a.nshots, zf, zl);
       break;
     case 6:
       hipLaunchKernelGGL((k_interior_generic<T, 3>), g, b, 0, st, un, um, K, sx, sy, sz, stencil_weights<T>(6), a.nx,
-                         a.ny, a.nz, lat, a.pitch, a.vol, a.nshots);
+                         a.ny, a.nz, lat, a.pitch, a.vol, a.nshots, zf, zl);
       break;
     default:
       hipLaunchKernelGGL((k_interior_generic<T, 4>), g, b, 0, st, un, um, K, sx, sy, sz, stencil_weights<T>(8), a.nx,
-                         a.ny, a.nz, lat, a.pitch, a.vol, a.nshots);
+                         a.ny, a.nz, lat, a.pitch, a.vol, a.nshots, zf, zl);
       break;
   }
 }
