@@ -206,7 +206,10 @@ ib_status ib_weights_copy(const ib_weights *w, int32_t field, void *dst_host, in
  *   vel_dev:  device float64 [nz][ny][nx] (or [nz][nx]) velocity in m/s.  Borrowed.
  *   dt:       time step (s).  The caller chooses it (e.g. half the interior limit).
  *   damp_width, damp_R: damping layer of ``damp_width`` cells on the lateral faces and
- *             the bottom, d = d_max (l/W)^2, d_max = 3 c_max ln(1/R) / (2 W h);
+ *             the bottom, d = d_max (l/W)^2 with l the depth into the layer in cells,
+ *             d_max = 3 c_max ln(1/R) / (W h) in the second-order form (damping term
+ *             d p_t) and half of it in the first-order form (d on each field), so that a
+ *             wave crossing the layer and back keeps the amplitude fraction R (WKB);
  *             0 disables it.
  *   prec:     IB_F32 or IB_F64 wavefields (weights rounded from the FP64 master).
  *   src_pos_host: host float64 [nshots][ndim], one point source per shot (metres),

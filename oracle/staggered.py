@@ -397,7 +397,7 @@ class StaggeredSimulation:
         self.mask_p = model.inter["p"].ravel()
         self.mask_v = [model.inter[n].ravel() for n in range(self.d)]
         self.c2 = np.where(self.mask_p, vel ** 2, 0.0)
-        self.s = damping_profile(self.shape, self.h, dt, float(vel.max()), damp_width, damp_R)
+        self.s = damping_profile(self.shape, self.h, dt, float(vel.max()), damp_width, damp_R, form="pv1")
         self.src = [multilinear(np.asarray(q, float) / self.h, self.shape) for q in src_pos]
         self.rec = [multilinear(np.asarray(q, float) / self.h, self.shape) for q in rec_pos]
         self.p = np.zeros(self.N)

@@ -13,7 +13,7 @@ one on the outer edges) is the damped leapfrog of p_tt + d(x) p_t = c^2 lap p + 
 
 where L is the grid-unit modified Laplacian.  The profile is
 d = d_max sum_axes (l_axis / W)^2 over the lateral faces and the bottom, l the depth
-into the layer in cells, d_max = 3 c_max ln(1/R) / (2 W h).
+into the layer in cells (``damping_profile``).
 Sources: multilinear spreading of a point source, f = wavelet * w_l / h^d.
 Receivers: multilinear interpolation of p^{n+1}.  Lateral axes periodic; the box is
 zero-padded above and below.
@@ -95,12 +95,23 @@ def solve_all(model, points=None):
     return {tuple(int(v) for v in p): model.solve_point(p) for p in pts}
 
 
-def damping_profile(shape, h, dt, c_max, width, R):
-    """s = d dt / 2 at every node (memory order), lateral faces + bottom."""
+def damping_profile(shape, h, dt, c_max, width, R, form="p2"):
+    """s = d dt / 2 at every node (memory order), lateral faces + bottom.
+
+    d = d_max (l / W)^2 summed over the faces, l the depth into the layer in cells.  The
+    constant makes the WKB amplitude of a wave crossing the layer, reflected by the outer
+    edge and crossing back equal to R: the damping term d p_t of the second-order form
+    attenuates the amplitude at the rate d / 2, the terms of the first-order form (one on
+    each field) at the rate d, and the integral of (l / W)^2 over the layer is W h / 3, so
+    d_max = 3 c_max ln(1/R) / (W h) for ``form`` "p2" and half of it for "pv1"."""
     d = len(shape)
     if width <= 0:
         return np.zeros(int(np.prod(shape)))
-    dmax = 3.0 * c_max * math.log(1.0 / R) / (2.0 * width * h)
+    if form not in ("p2", "pv1"):
+        raise ValueError("form must be 'p2' or 'pv1'")
+    dmax = 3.0 * c_max * math.log(1.0 / R) / (width * h)
+    if form == "pv1":
+        dmax *= 0.5
 
     def axis_prof(n, both):
         i = np.arange(n, dtype=np.float64)

@@ -752,7 +752,11 @@ ib_status ib_state_create(const ib_weights *w, const double *vel_dev, double dt,
       IB_HIP(hipStreamSynchronize(st));
       for (double x : v) vmax = std::max(vmax, x);
     }
-    const double dmax = (damp_width > 0) ? 3.0 * vmax * std::log(1.0 / damp_R) / (2.0 * damp_width * w->h) : 0.0;
+    // d = d_max (l / W)^2: a wave crossing the layer, reflected at its outer edge and
+    // crossing back keeps the amplitude fraction R (WKB); the second-order form's damping
+    // term attenuates at the rate d / 2, the first-order form's terms at the rate d
+    double dmax = (damp_width > 0) ? 3.0 * vmax * std::log(1.0 / damp_R) / (damp_width * w->h) : 0.0;
+    if (w->form == IB_FORM_PV1) dmax *= 0.5;
     std::vector<double> ax = damping_axis(w->nx, damp_width, dmax, dt, true);
     std::vector<double> ay = (w->ndim == 3) ? damping_axis(w->ny, damp_width, dmax, dt, true) : std::vector<double>(1, 0.0);
     std::vector<double> az = damping_axis(w->nz, damp_width, dmax, dt, false);

@@ -183,3 +183,76 @@ def test_lattice_ball_counts_brute_force():
                  if x * x + y * y + z * z <= r * r)
         assert len(ball_offsets(r, 2)) == b2 == n2
         assert len(ball_offsets(r, 3)) == b3 == n3
+
+
+def _odd_null_poly(zs, zd, M, lateral=True):
+    """Coefficients (numpy 2D, axes x, z) of q = (1 + x) (z - zs)((z - zs)^2 - (zd - zs)^2)
+    (without the (1 + x) factor when ``lateral`` is False): odd in z - zs, so every
+    free-surface condition lap^q p = 0 holds on the flat surface z = zs, and zero on the
+    node row z = zd (and its mirror)."""
+    zpoly = P.polymul([-zs, 1.0], P.polysub(P.polypow([-zs, 1.0], 2), [(zd - zs) ** 2]))
+    xpoly = [1.0, 1.0] if lateral else [1.0]
+    c = np.zeros((M + 1, M + 1))
+    for a, xa in enumerate(xpoly):
+        for b, zb in enumerate(zpoly):
+            c[a, b] += xa * zb
+    return c
+
+
+def _taylor_vector(coef, i, Mb):
+    """Scaled derivatives d^e q(i) in the oracle's term order (grid units), so that
+    A @ delta lists q at the data nodes and the conditions at the boundary points."""
+    out = []
+    for e in basis.multi_indices(Mb, 2):
+        out.append(_poly_eval(_poly_deriv(coef, e), np.asarray(i, float)[None, :])[0])
+    return np.array(out)
+
+
+def test_basis_order_reduction_pinned_by_null_polynomials():
+    # A domain one node row thick (2D, M = 4, free surface 0.75 cells above the bottom
+    # row, eta = 0.5 excludes nothing): all data of any support lie on that row, so the
+    # odd polynomials (c + e x)(z - zs)((z - zs)^2 - 0.75^2) (degree 4) and
+    # (z - zs)((z - zs)^2 - 0.75^2) (degree 3) satisfy every row of A at every radius:
+    # orders 4 and 3 stay rank deficient whatever the growth.  At order 2 no odd
+    # polynomial vanishes on the row, and the radius restarts at (2 + 1) / 2 = 1.5, where
+    # 3 data nodes and 3 boundary points already fix all 6 terms.
+    nx, nz = 16, 10
+    zs = nz - 1 - 0.75
+    m = IBModel(np.full(nx, zs), 1.0, (nx, nz), M=4, surface="free", eta=0.5)
+    pts = m.ib_points()
+    assert sorted(set(pts[:, 1].tolist())) == [nz - 1] and len(pts) == nx
+    for i in pts[[0, 7]]:
+        for Mb, lateral in ((4, True), (4, False), (3, False)):
+            q = _odd_null_poly(zs, nz - 1, 4, lateral)
+            delta = _taylor_vector(q, i, Mb)
+            for k in range(4):
+                A, _ = m.system(i, Mb, (Mb + 1) / 2 + k)
+                assert np.abs(A @ delta).max() <= 1e-11 * np.abs(A).max() * np.abs(delta).max()
+        sol = m.solve_point(i)
+        assert (sol["order"], sol["radius_step"], sol["radius"]) == (2, 0, 1.5)
+        assert sol["sigma_ratio"] > 1e-3
+        assert len(sol["offsets"]) == 3 and set(sol["offsets"][:, 1].tolist()) == {0}
+
+
+def test_radius_grows_by_one_cell_pinned_by_null_polynomial():
+    # Flat free surface 0.75 cells above node row 5 of a deep domain, M = 4, eta = 2: rows
+    # 5 and 6 lie within 2 cells of the surface and are excluded, so the first data row is
+    # 7.  For an IB point of row 5 the initial ball (r = 2.5) holds data on row 7 only, and
+    # (1 + x)(z - zs)((z - zs)^2 - 2.75^2) satisfies every row of A: rank deficient.  One
+    # growth of one cell (r = 3.5) brings row 8 (offsets (+-1, 3), |o|^2 = 10 > 3^2) and
+    # full rank; the accepted support holds them.
+    nx, nz = 16, 20
+    zs = 5 - 0.75
+    m = IBModel(np.full(nx, zs), 1.0, (nx, nz), M=4, surface="free", eta=2.0)
+    pts = m.ib_points()
+    assert sorted(set(pts[:, 1].tolist())) == [5, 6]
+    for i in pts[pts[:, 1] == 5][[0, 9]]:
+        A, data = m.system(i, 4, 2.5)
+        assert set(data[:, 1].tolist()) == {2}
+        delta = _taylor_vector(_odd_null_poly(zs, 7, 4), i, 4)
+        assert np.abs(A @ delta).max() <= 1e-11 * np.abs(A).max() * np.abs(delta).max()
+        sol = m.solve_point(i)
+        assert (sol["order"], sol["radius_step"], sol["radius"]) == (4, 1, 3.5)
+        assert sol["sigma_ratio"] > 1e-3
+        d2 = (sol["offsets"] ** 2).sum(axis=1)
+        assert d2.max() == 10 and 3 in sol["offsets"][:, 1]
