@@ -37,7 +37,7 @@
 extern "C" {
 #endif
 
-#define IB_ABI_VERSION 2
+#define IB_ABI_VERSION 3
 
 typedef enum {
   IB_OK = 0,
@@ -140,9 +140,13 @@ typedef struct {
   int64_t table_bytes_f64;
   int64_t max_ball;          /* largest support ball (lattice points) used               */
   double build_ms;           /* wall time of ib_build_weights                            */
-  int64_t dense_weights;     /* entries of the dense-range records streamed by the 3D patch
-                                kernel (>= sum_nw; zeros fill non-data lattice points
-                                between a support's first and last data point)          */
+  int64_t dense_weights;     /* entries of the dense-range records (>= sum_nw; zeros fill
+                                non-data lattice points between a support's first and
+                                last data point)                                        */
+  int64_t col_weights;       /* entries of the column-run records streamed by the 3D tiled
+                                patch kernel (the data nodes' weights of the supports of
+                                radius <= 4.5, plus zeros at the rare non-data node inside
+                                a column's run)                                         */
 } ib_stats;
 
 typedef struct ib_weights ib_weights;
@@ -230,6 +234,10 @@ void ib_state_free(ib_state *st);
 
 /* Advance every shot by ``nsteps`` leapfrog steps:
  *   p^{n+1} = [2 p^n - (1 - s) p^{n-1} + K (L p^n) + dt^2 f^n] / (1 + s),
+ *   which FP32 states evaluate in increment form: with d^n = p^n - p^{n-1} kept in place
+ *   of p^{n-1}, d^{n+1} = [(1 - s) d^n + K (L p^n) + dt^2 f^n] / (1 + s) and
+ *   p^{n+1} = p^n + d^{n+1} (the same recurrence; single-precision rounding of p^{n+1} then
+ *   does not build up as an error of the time difference).  FP64 states keep p^{n-1}.
  *   K = (c dt / h)^2 at interior nodes (0 elsewhere), s = d dt / 2, L the grid-unit
  *   Laplacian with the immersed-boundary rows.
  *   wavelet_dev: device [nshots][wavelet_stride] in the state precision; step n uses
@@ -274,9 +282,11 @@ ib_status ib_adjoint(ib_state *st, const void *residual_dev, const void *wavelet
  * First-order form: which = 0: p^n, 2 + k: v_k^{n-1/2} (k < ndim; in 2D k = 1 is the
  * vertical velocity), 1 is invalid.
  * direction 0 copies out of the state, 1 copies into it.  Values written at exterior
- * nodes must be zero: the method takes the wavefield as zero outside the physical domain
- * (the stencils of interior nodes read those nodes), and the interior kernels skip planes
- * that hold exterior nodes only. */
+ * nodes (velocity fields: exterior v_k nodes) are replaced by zero: the method takes the
+ * wavefield as zero outside the physical domain.
+ * FP32 states of the second-order form keep d^n = p^n - p^{n-1} (increment form, see
+ * ib_step) instead of p^{n-1}: reading which = 1 returns p^n - d^n, writing it sets
+ * d^n = p^n - (the given p^{n-1}) from the current p^n, so write p^n first. */
 ib_status ib_state_field(ib_state *st, int32_t which, int32_t shot, void *dev_buf, int32_t direction,
                          void *stream);
 int64_t ib_state_step_count(const ib_state *st);
@@ -316,10 +326,13 @@ ib_status ib_state_run_kernel(ib_state *st, int32_t which, int32_t count, void *
  *     tiles, 512 threads), 4 (pipelined, 64x16 tiles, 512 threads, 2 rows per thread);
  *   zchunk: depth planes per interior workgroup (0 = automatic: enough workgroups to fill
  *     the device);
- *   patch_variant (tiled IB patch): 0-3 point records read per wavefront (bit 0 as scalar
- *     loads, bit 1 DPP wavefront sums); 4-6 records staged in LDS per tile with DPP sums and
- *     1-3 groups of two points' weights in flight, FP32 weights loaded in pairs (default 4); 7 compact records (bit masks
- *     and the data nodes' weights only); -1 keeps the current one.
+ *   patch_variant (tiled IB patch): 0-3 dense-range records, point records read per
+ *     wavefront (bit 0 as scalar loads, bit 1 DPP wavefront sums); 4-6 dense-range records,
+ *     point records staged in LDS per tile, 1-3 groups of two points' weights in flight;
+ *     7 compact records (bit masks and the data nodes' weights only); 8 column-run records
+ *     (the data nodes' weights, one ball column per lane; the default), 9 the same with two
+ *     FP32 shots per pass (the default for FP32 states of several shots); -1 keeps the
+ *     current one.
  * Results do not depend on the interior knobs; the patch variants differ only in the
  * summation order of each point's weighted sum. */
 ib_status ib_state_set_tuning(ib_state *st, int32_t variant, int32_t zchunk, int32_t patch_variant);

@@ -35,7 +35,8 @@ class ib_stats(C.Structure):
                 ("n_ib", C.c_int64), ("sum_nw", C.c_int64), ("max_nw", C.c_int64),
                 ("radius_hist", C.c_int64 * 8), ("order_hist", C.c_int64 * 17), ("max_cond", C.c_double),
                 ("min_margin", C.c_double), ("table_bytes_f32", C.c_int64), ("table_bytes_f64", C.c_int64),
-                ("max_ball", C.c_int64), ("build_ms", C.c_double), ("dense_weights", C.c_int64)]
+                ("max_ball", C.c_int64), ("build_ms", C.c_double), ("dense_weights", C.c_int64),
+                ("col_weights", C.c_int64)]
 
 
 EXPORTS = {

@@ -30,12 +30,18 @@ struct ib_state {
   size_t esz = 4;
   void *buf[2] = {nullptr, nullptr};
   int cur = 0;                 // buf[cur] holds p^n
+  // increment form (FP32 second-order states): dbuf holds d^n = p^n - p^{n-1} and
+  // buf[1 - cur] only receives p^{n+1}
+  bool incr = false;
+  void *dbuf = nullptr;
   void *K = nullptr, *sx = nullptr, *sy = nullptr, *sz = nullptr;
   void *scale = nullptr;
   void *pinfo = nullptr;       // all points, memory order (gradient kernels)
   void *pinfo_t = nullptr;     // tiled points, tile order
   void *pinfo_w = nullptr;     // wide-support points
   void *pinfo_tm = nullptr;    // tiled points, compact records
+  uint2 *crec = nullptr;       // tiled points, column-run records: entry offset, packed LDS position
+  void *cscale = nullptr;      // tiled points' scales, tile order
   int4 *tiles = nullptr;
   int ntiles = 0;
   int64_t nwide = 0;
@@ -113,6 +119,7 @@ StepArgs make_args(ib_state *st, const void *wavelet, int64_t wstride, void *tra
   a.patch_variant = st->patch_variant;
   a.un = st->buf[cur];
   a.um = st->buf[1 - cur];
+  a.dd = st->incr ? st->dbuf : nullptr;
   a.K = st->K;
   a.sx = st->sx;
   a.sy = st->sy;
@@ -125,6 +132,11 @@ StepArgs make_args(ib_state *st, const void *wavelet, int64_t wstride, void *tra
   a.ntiles = st->ntiles;
   a.pinfo_wide = st->pinfo_w;
   a.pinfo_tm = st->pinfo_tm;
+  a.wcol = (st->prec == IB_F32) ? (const void *)w->col32 : (const void *)w->col64;
+  a.crec = st->crec;
+  a.cscale = st->cscale;
+  a.zfcol = w->zfirst;
+  a.coltab = w->col_tab;
   a.nwide = st->nwide;
   a.zrange16 = st->zrange16;
   a.zfirst = st->zfirst;
@@ -191,6 +203,38 @@ __global__ void k_make_scale(const int16_t *xyz, int64_t nib, const double *vel,
   double k = (v * f) * (v * f);
   double s = sx[x] + sy[y] + sz[z];
   scale[i] = (T)(k / (1.0 + s));
+}
+
+// p^{n-1} of an increment-form state: dir 0 writes p^n - d^n to the caller's dense
+// buffer, dir 1 sets d^n = p^n - (the caller's p^{n-1}) at interior nodes (mask != 0) and 0
+// elsewhere
+template <typename T>
+__global__ void k_field_prev(const T *p, T *d, T *user, const T *mask, int nx, int ny, int nz, int64_t pitch, int dir) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (int64_t)nx * ny * nz) return;
+  const int64_t x = i % nx, r = i / nx;
+  const size_t c = (size_t)r * pitch + x;
+  if (dir == 0)
+    user[i] = p[c] - d[c];
+  else
+    d[c] = (mask[c] != T(0)) ? p[c] - user[i] : T(0);
+}
+
+// a field written by the caller keeps zeros at the nodes where the mask is zero (exterior
+// nodes: the method takes the wavefield as zero there)
+template <typename T>
+__global__ void k_mask_field(T *f, const T *mask, int nx, int ny, int nz, int64_t pitch) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (int64_t)nx * ny * nz) return;
+  const int64_t x = i % nx, r = i / nx;
+  const size_t c = (size_t)r * pitch + x;
+  if (mask[c] == T(0)) f[c] = T(0);
+}
+
+template <typename T>
+__global__ void k_gather_scale(const T *scale, const int32_t *perm, int64_t n, T *out) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j < n) out[j] = scale[perm[j]];
 }
 
 // step counter of a call: [0] next step, [1] step being sampled, [2] first step
@@ -583,6 +627,7 @@ void ib_weights_free(ib_weights *w) {
   dfree(w->dense_first);
   dfree(w->dense_count);
   dfree(w->dense_off);
+  dfree(w->zfirst), dfree(w->col_tab), dfree(w->col_off), dfree(w->col_cnt), dfree(w->col32), dfree(w->col64);
   for (int n = 0; n < 3; ++n) dfree(w->vcls[n]);
   dfree(w->adj_jnode), dfree(w->adj_joff), dfree(w->adj_jsrc), dfree(w->adj_jw32), dfree(w->adj_jw64);
   dfree(w->bc_off), dfree(w->bc_cnt), dfree(w->bc_idx), dfree(w->bc_w);
@@ -734,6 +779,11 @@ ib_status ib_state_create(const ib_weights *w, const double *vel_dev, double dt,
       return fail(s);
     IB_HIP(hipMemsetAsync(S->buf[0], 0, fbytes, st));
     IB_HIP(hipMemsetAsync(S->buf[1], 0, fbytes, st));
+    S->incr = (prec == IB_F32 && w->form == IB_FORM_P2);
+    if (S->incr) {
+      if ((s = dalloc(&S->dbuf, fbytes))) return fail(s);
+      IB_HIP(hipMemsetAsync(S->dbuf, 0, fbytes, st));
+    }
     IB_HIP(hipMemsetAsync(S->K, 0, S->vol * S->esz, st));
     const double f = dt / w->h;
     const int T = 256;
@@ -891,7 +941,10 @@ ib_status ib_state_create(const ib_weights *w, const double *vel_dev, double dt,
         std::vector<int16_t> xyz(w->nib * 4);
         if (w->nib) IB_HIP(hipMemcpy(xyz.data(), w->ib_xyz, w->nib * 8, hipMemcpyDeviceToHost));
         std::vector<int32_t> tiled, wide;
-        const bool use_tiles = (w->ndim == 3);
+        // the tiles' halos wrap once at most: lateral extents of at least 16 nodes
+        // (and buffer loads of one shot's volume: under 2^31 bytes)
+        const bool use_tiles =
+            (w->ndim == 3 && w->nx >= 16 && w->ny >= 16 && S->vol * (int64_t)S->esz < ((int64_t)1 << 31));
         const int64_t tx = (w->nx + kTileX - 1) / kTileX, ty = (w->ny + kTileY - 1) / kTileY;
         for (int64_t i = 0; i < w->nib; ++i) {
           const int code = xyz[i * 4 + 3];
@@ -939,8 +992,35 @@ ib_status ib_state_create(const ib_weights *w, const double *vel_dev, double dt,
           enqueue_make_pinfo_dense(prec, w->ib_xyz, w->dense_first, w->dense_count, w->dense_off, S->scale, d_perm,
                                    (int64_t)tiled.size(), S->pinfo_t, st);
           enqueue_make_pinfo(prec, w->ib_xyz, ro, S->scale, d_perm, (int64_t)tiled.size(), S->pinfo_tm, st);
+          if (w->col_off) {
+            // column-run records: entry offset and the point's LDS position in its tile
+            std::vector<uint32_t> coff(w->nib);
+            IB_HIP(hipMemcpy(coff.data(), w->col_off, w->nib * 4, hipMemcpyDeviceToHost));
+            std::vector<uint2> cr(tiled.size());
+            for (size_t t = 0; t + 1 < tl.size(); ++t)
+              for (int j = tl[t].w; j < tl[t + 1].w; ++j) {
+                const int32_t i = tiled[j];
+                const uint32_t lx = (uint32_t)(xyz[i * 4] - tl[t].x + kTileHalo);
+                const uint32_t ly = (uint32_t)(xyz[i * 4 + 1] - tl[t].y + kTileHalo);
+                const uint32_t lz = (uint32_t)(xyz[i * 4 + 2] - tl[t].z + kTileHalo);
+                cr[j] = make_uint2(coff[i], lx | (ly << 5) | (lz << 10) | (xyz[i * 4 + 3] == 9 ? 0x80000000u : 0u));
+              }
+            if ((s = dalloc_t(&S->crec, cr.size())) || (s = dalloc(&S->cscale, cr.size() * S->esz))) return fail(s);
+            IB_HIP(hipMemcpy(S->crec, cr.data(), cr.size() * sizeof(uint2), hipMemcpyHostToDevice));
+            const unsigned nb = (unsigned)((tiled.size() + 255) / 256);
+            if (prec == IB_F32)
+              hipLaunchKernelGGL(k_gather_scale<float>, dim3(nb), dim3(256), 0, st, (const float *)S->scale, d_perm,
+                                 (int64_t)tiled.size(), (float *)S->cscale);
+            else
+              hipLaunchKernelGGL(k_gather_scale<double>, dim3(nb), dim3(256), 0, st, (const double *)S->scale, d_perm,
+                                 (int64_t)tiled.size(), (double *)S->cscale);
+            IB_HIP(hipGetLastError());
+          }
           IB_HIP(hipStreamSynchronize(st));
         }
+        // the tiled patch streams the column-run records (two FP32 shots per pass when the
+        // state holds several)
+        if (S->crec) S->patch_variant = (prec == IB_F32 && nshots >= 2) ? 9 : 8;
         if (!wide.empty()) {
           IB_HIP(hipMemcpy(d_perm, wide.data(), wide.size() * 4, hipMemcpyHostToDevice));
           enqueue_make_pinfo(prec, w->ib_xyz, ro, S->scale, d_perm, (int64_t)wide.size(), S->pinfo_w, st);
@@ -1112,6 +1192,7 @@ void ib_state_free(ib_state *S) {
   if (S->ev_join) (void)hipEventDestroy(S->ev_join);
   dfree(S->buf[0]);
   dfree(S->buf[1]);
+  dfree(S->dbuf);
   dfree(S->K);
   dfree(S->sx);
   dfree(S->sy);
@@ -1121,6 +1202,8 @@ void ib_state_free(ib_state *S) {
   dfree(S->pinfo_t);
   dfree(S->pinfo_w);
   dfree(S->pinfo_tm);
+  dfree(S->crec);
+  dfree(S->cscale);
   dfree(S->tiles);
   dfree(S->zrange16);
   dfree(S->zr4);
@@ -1144,7 +1227,8 @@ void ib_state_free(ib_state *S) {
 int64_t ib_state_step_count(const ib_state *S) { return S ? S->t : -1; }
 
 ib_status ib_state_set_tuning(ib_state *S, int32_t variant, int32_t zchunk, int32_t patch_variant) {
-  if (!S || zchunk < 0 || variant < 0 || variant > 4 || patch_variant < -1 || patch_variant > 7) {
+  if (!S || zchunk < 0 || variant < 0 || variant > 4 || patch_variant < -1 || patch_variant > 9 ||
+      (patch_variant >= 8 && S->ntiles > 0 && !S->crec)) {
     set_error("ib_state_set_tuning: invalid argument");
     return IB_ERR_ARG;
   }
@@ -1367,11 +1451,13 @@ ib_status ib_forward(ib_state *S, int32_t nt, const void *wavelet, int64_t wstri
   S->ck_every = ckpt_every;
   IB_HIP(hipMemsetAsync(S->buf[0], 0, fbytes, st));
   IB_HIP(hipMemsetAsync(S->buf[1], 0, fbytes, st));
+  if (S->incr) IB_HIP(hipMemsetAsync(S->dbuf, 0, fbytes, st));
   S->t = 0;
   for (int64_t k = 0; k < nck; ++k) {
+    // checkpoint k: p^n and p^{n-1} (plain form) or d^n (increment form)
     char *ck = (char *)S->ckpt + (size_t)k * 2 * fbytes;
     IB_HIP(hipMemcpyAsync(ck, S->buf[S->cur], fbytes, hipMemcpyDeviceToDevice, st));
-    IB_HIP(hipMemcpyAsync(ck + fbytes, S->buf[1 - S->cur], fbytes, hipMemcpyDeviceToDevice, st));
+    IB_HIP(hipMemcpyAsync(ck + fbytes, S->incr ? S->dbuf : S->buf[1 - S->cur], fbytes, hipMemcpyDeviceToDevice, st));
     int64_t n = std::min<int64_t>(ckpt_every, nt - k * ckpt_every);
     ib_status s = run_steps(S, n, wavelet, wstride, traces, nt, 0, false, st);
     if (s) return s;
@@ -1403,22 +1489,27 @@ ib_status ib_adjoint(ib_state *S, const void *residual, const void *wavelet, int
   const int64_t nt = S->ck_nt, C = S->ck_every;
   const size_t fbytes = (size_t)S->vol * S->nshots * S->esz;
   void *lam[2] = {nullptr, nullptr};
+  void *lamd = nullptr;
   void *seg = nullptr;
   double *gK = nullptr;
   auto cleanup = [&]() {
     dfree(lam[0]);
     dfree(lam[1]);
+    dfree(lamd);
     dfree(seg);
     dfree(gK);
   };
-  // seg holds u^{t0-1} .. u^{t0+len} of the segment being reversed (C + 2 fields)
+  // seg holds u^{t0-1} .. u^{t0+len} of the segment being reversed (C + 2 fields; the
+  // increment form keeps d^{t0} .. d^{t0+len}, C + 1 fields); lamd is mu^m - mu^{m+1} of
+  // the increment form
   if ((s = dalloc(&lam[0], fbytes)) || (s = dalloc(&lam[1], fbytes)) || (s = dalloc(&seg, fbytes * (C + 2))) ||
-      (s = dalloc_t(&gK, S->vol))) {
+      (s = dalloc_t(&gK, S->vol)) || (S->incr && (s = dalloc(&lamd, fbytes)))) {
     cleanup();
     return s;
   }
   IB_HIP(hipMemsetAsync(lam[0], 0, fbytes, st));
   IB_HIP(hipMemsetAsync(lam[1], 0, fbytes, st));
+  if (lamd) IB_HIP(hipMemsetAsync(lamd, 0, fbytes, st));
   IB_HIP(hipMemsetAsync(gK, 0, S->vol * sizeof(double), st));
   int a1 = 0, a2 = 1;   // lam[a1] = mu^{m+1}, lam[a2] = mu^{m+2}
   auto field = [&](int64_t q) { return (char *)seg + (size_t)q * fbytes; };
@@ -1426,22 +1517,32 @@ ib_status ib_adjoint(ib_state *S, const void *residual, const void *wavelet, int
     const int64_t t0 = k * C, len = std::min<int64_t>(C, nt - t0);
     char *ck = (char *)S->ckpt + (size_t)k * 2 * fbytes;
     IB_HIP(hipMemcpyAsync(S->buf[S->cur], ck, fbytes, hipMemcpyDeviceToDevice, st));
-    IB_HIP(hipMemcpyAsync(S->buf[1 - S->cur], ck + fbytes, fbytes, hipMemcpyDeviceToDevice, st));
+    IB_HIP(hipMemcpyAsync(S->incr ? S->dbuf : S->buf[1 - S->cur], ck + fbytes, fbytes, hipMemcpyDeviceToDevice, st));
     S->t = t0;
-    IB_HIP(hipMemcpyAsync(field(0), ck + fbytes, fbytes, hipMemcpyDeviceToDevice, st));
-    IB_HIP(hipMemcpyAsync(field(1), ck, fbytes, hipMemcpyDeviceToDevice, st));
+    if (S->incr) {
+      // field(q) = d^{t0+q}
+      IB_HIP(hipMemcpyAsync(field(0), ck + fbytes, fbytes, hipMemcpyDeviceToDevice, st));
+    } else {
+      // field(q) = u^{t0+q-1}
+      IB_HIP(hipMemcpyAsync(field(0), ck + fbytes, fbytes, hipMemcpyDeviceToDevice, st));
+      IB_HIP(hipMemcpyAsync(field(1), ck, fbytes, hipMemcpyDeviceToDevice, st));
+    }
     for (int64_t q = 1; q <= len; ++q) {
       if ((s = run_steps(S, 1, wavelet, wstride, nullptr, 0, 0, false, st))) {
         cleanup();
         return s;
       }
-      IB_HIP(hipMemcpyAsync(field(q + 1), S->buf[S->cur], fbytes, hipMemcpyDeviceToDevice, st));
+      if (S->incr)
+        IB_HIP(hipMemcpyAsync(field(q), S->dbuf, fbytes, hipMemcpyDeviceToDevice, st));
+      else
+        IB_HIP(hipMemcpyAsync(field(q + 1), S->buf[S->cur], fbytes, hipMemcpyDeviceToDevice, st));
     }
     for (int64_t m = t0 + len; m >= t0 + 1; --m) {
       // interior part: the forward interior kernel on mu (mu^{m+2} is overwritten by mu^m)
       StepArgs sa = make_args(S, nullptr, 0, nullptr, 0, S->cur);
       sa.un = lam[a1];
       sa.um = lam[a2];
+      sa.dd = lamd;
       enqueue_interior_only(sa, st);
       AdjArgs a{};
       a.prec = S->prec;
@@ -1455,6 +1556,7 @@ ib_status ib_adjoint(ib_state *S, const void *residual, const void *wavelet, int
       a.nshots = S->nshots;
       a.lam1 = lam[a1];
       a.lam2 = lam[a2];
+      a.lamd = lamd;
       a.K = S->K;
       a.sx = S->sx;
       a.sy = S->sy;
@@ -1479,9 +1581,15 @@ ib_status ib_adjoint(ib_state *S, const void *residual, const void *wavelet, int
       a.nrec = S->nrec;
       a.step = m - 1;
       a.gK = gK;
-      a.u2 = field(m - t0 + 1);   // u^m
-      a.u1 = field(m - t0);       // u^{m-1}
-      a.u0 = field(m - t0 - 1);   // u^{m-2}
+      if (S->incr) {
+        a.u2 = field(m - t0);       // d^m
+        a.u1 = nullptr;
+        a.u0 = field(m - t0 - 1);   // d^{m-1}
+      } else {
+        a.u2 = field(m - t0 + 1);   // u^m
+        a.u1 = field(m - t0);       // u^{m-1}
+        a.u0 = field(m - t0 - 1);   // u^{m-2}
+      }
       a.sidx = S->sidx;
       a.sw = S->sw;
       a.wavelet = wavelet;
@@ -1602,19 +1710,45 @@ ib_status ib_state_field(ib_state *S, int32_t which, int32_t shot, void *dev, in
     return IB_ERR_ARG;
   }
   const ib_weights *w = S->w;
+  const size_t so = (size_t)shot * S->vol * S->esz;
+  hipStream_t st = (hipStream_t)stream;
+  const int64_t n = w->nx * w->ny * w->nz;
+  const dim3 g((unsigned)((n + 255) / 256)), b(256);
+  const int nx = (int)w->nx, ny = (int)w->ny, nz = (int)w->nz;
+  if (S->incr && which == 1) {
+    // the state keeps d^n = p^n - p^{n-1}
+    char *p = (char *)S->buf[S->cur] + so, *d = (char *)S->dbuf + so;
+    if (S->prec == IB_F32)
+      hipLaunchKernelGGL(k_field_prev<float>, g, b, 0, st, (const float *)p, (float *)d, (float *)dev,
+                         (const float *)S->K, nx, ny, nz, S->pitch, direction);
+    else
+      hipLaunchKernelGGL(k_field_prev<double>, g, b, 0, st, (const double *)p, (double *)d, (double *)dev,
+                         (const double *)S->K, nx, ny, nz, S->pitch, direction);
+    IB_HIP(hipGetLastError());
+    return IB_OK;
+  }
   char *base;
-  if (S->form == IB_FORM_PV1)
-    base = (which == 0) ? (char *)S->buf[0] + (size_t)shot * S->vol * S->esz
-                        : (char *)S->vbuf + ((size_t)shot * S->nv + (which - 2)) * S->vol * S->esz;
-  else
-    base = (char *)S->buf[which == 0 ? S->cur : 1 - S->cur] + (size_t)shot * S->vol * S->esz;
+  const void *mask;
+  if (S->form == IB_FORM_PV1) {
+    base = (which == 0) ? (char *)S->buf[0] + so : (char *)S->vbuf + ((size_t)shot * S->nv + (which - 2)) * S->vol * S->esz;
+    mask = (which == 0) ? S->K : (const char *)S->kv + (size_t)(which - 2) * S->vol * S->esz;
+  } else {
+    base = (char *)S->buf[which == 0 ? S->cur : 1 - S->cur] + so;
+    mask = S->K;
+  }
   size_t rowb = w->nx * S->esz, pitchb = S->pitch * S->esz;
   size_t rows = w->ny * w->nz;
-  hipStream_t st = (hipStream_t)stream;
-  if (direction == 0)
+  if (direction == 0) {
     IB_HIP(hipMemcpy2DAsync(dev, rowb, base, pitchb, rowb, rows, hipMemcpyDeviceToDevice, st));
-  else
+  } else {
     IB_HIP(hipMemcpy2DAsync(base, pitchb, dev, rowb, rowb, rows, hipMemcpyDeviceToDevice, st));
+    if (S->prec == IB_F32)
+      hipLaunchKernelGGL(k_mask_field<float>, g, b, 0, st, (float *)base, (const float *)mask, nx, ny, nz, S->pitch);
+    else
+      hipLaunchKernelGGL(k_mask_field<double>, g, b, 0, st, (double *)base, (const double *)mask, nx, ny, nz,
+                         S->pitch);
+    IB_HIP(hipGetLastError());
+  }
   return IB_OK;
 }
 

@@ -15,6 +15,10 @@ constexpr int kMaxTerms = 165;         // binomial(8+3, 3)
 constexpr int kMaxRadiusCode = 40;     // radius codes 2r = 1..40 (r <= 20 cells)
 constexpr int kMaxOps = 8;             // boundary-condition rows per boundary point
 constexpr int kMaxOpTerms = 48;        // derivative terms per boundary-condition row
+// depth columns of the 3D support balls taken by the LDS-tiled patch (radius 4.5 and 4)
+constexpr int kColumns9 = 69, kColumns8 = 49;
+constexpr int32_t kNoColumn = -1;
+constexpr int kColPad = 16;            // entries after the last column-run record
 
 void set_error(const char *fmt, ...);
 ib_status hip_fail(hipError_t e, const char *what, const char *file, int line);
@@ -91,6 +95,7 @@ struct ib_weights;
 namespace ib {
 ib_status upload_ball_tables(ib_weights *w, hipStream_t st);
 ib_status build_dense_records(ib_weights *w, hipStream_t st);
+ib_status build_column_records(ib_weights *w, hipStream_t st);
 ib_status solve_family(ib_weights *w, const FamilySpec &F, const int64_t *col_off_dev, hipStream_t st,
                        std::vector<FamilyPoint> &out);
 }
@@ -131,6 +136,16 @@ struct ib_weights {
   int32_t *dense_first = nullptr, *dense_count = nullptr;
   uint32_t *dense_off = nullptr;
   int64_t dense_words = 0;
+  // column-run records of the 3D supports of radius 4 and 4.5 (build_column_records):
+  // first data plane per grid column, packed column tables (code 9 then code 8: dx, dy,
+  // zr), per-point entry offsets and counts (-1: other supports), entries FP32 and FP64
+  int16_t *zfirst = nullptr;
+  int32_t *col_tab = nullptr;
+  uint32_t *col_off = nullptr;
+  int32_t *col_cnt = nullptr;
+  float *col32 = nullptr;
+  double *col64 = nullptr;
+  int64_t col_words = 0;
   int32_t *ball = nullptr;         // packed ball tables
   int32_t *ball_meta = nullptr;    // [code][2] start, count (device)
   ib::BallTables balls;

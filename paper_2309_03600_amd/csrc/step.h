@@ -28,7 +28,8 @@ struct StepArgs {
   const int2 *zrange16, *zrange32;
   int zfirst, zlast;    // planes [zfirst, zlast) hold all interior nodes (generic interior kernel)
   const void *un;       // p^n
-  void *um;             // p^{n-1} in, p^{n+1} out
+  void *um;             // p^{n-1} in (plain form), p^{n+1} out
+  void *dd;             // increment form: d^n = p^n - p^{n-1} in, d^{n+1} out (null: plain form)
   const void *K;
   const void *sx, *sy, *sz;
   // IB patch
@@ -39,6 +40,14 @@ struct StepArgs {
   const void *dense;          // dense-range weights (state precision)
   const int4 *tiles;          // [ntiles + 1]: x0, y0, z0, first point (the last holds the end)
   int ntiles;
+  // column-run records of the tiled points (patch variants 8 and 9): entries (state
+  // precision), per point (entry offset, packed LDS position) and scale in tile order, first
+  // data plane per grid column, column tables
+  const void *wcol;
+  const uint2 *crec;
+  const void *cscale;
+  const int16_t *zfcol;
+  const int32_t *coltab;
   const void *pinfo_wide;     // points handled by the gather kernel
   int64_t nwide;
   // second stream and events on which the gather kernel of the wide points runs beside
@@ -113,6 +122,7 @@ struct AdjArgs {
   int nshots;
   const void *lam1;      // mu^{m+1} = K lambda^{m+1}
   void *lam2;            // mu^m after the interior stencil (the forward kernel on mu)
+  void *lamd;            // increment form: mu^m - mu^{m+1} (null: plain form)
   const void *K, *sx, *sy, *sz;
   // transposed IB rows (receiving nodes, run offsets, IB point and weight per entry)
   int64_t nj;
@@ -133,7 +143,8 @@ struct AdjArgs {
   // gradient: gK += mu^m (K L u^{m-1}), K L u^{m-1} recovered from three time levels;
   // dJ/dK = gK / K^2
   double *gK;
-  const void *u2, *u1, *u0;   // u^m, u^{m-1}, u^{m-2}
+  // plain form: u^m, u^{m-1}, u^{m-2}; increment form (u1 null): u2 = d^m, u0 = d^{m-1}
+  const void *u2, *u1, *u0;
   const int64_t *sidx;   // source injection of step m - 1 (subtracted from the recovery)
   const void *sw, *wavelet;
   int64_t wstride;

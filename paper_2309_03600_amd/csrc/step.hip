@@ -11,6 +11,13 @@
 //                stencil reads are zero, so the standard part is already complete);
 //   k_inject     point sources (also advances the device step counter);
 //   k_sample     receivers (k_io_small does both in one launch for few receivers).
+//
+// Increment form (FP32 states): the state keeps d^n = p^n - p^{n-1} in place of p^{n-1},
+//   d^{n+1} = [(1 - s) d^n + K (L p^n) + dt^2 f^n] / (1 + s),   p^{n+1} = p^n + d^{n+1},
+// the same recurrence rearranged.  Rounding p^{n+1} to the storage precision then perturbs
+// the field but not its time difference, so round-off does not build up as a velocity
+// error that the leapfrog carries along; every term added after the interior kernel (IB
+// patch, sources, boundary values) goes into both d^{n+1} and p^{n+1}.
 #include <hip/hip_runtime.h>
 
 #include <type_traits>
@@ -27,6 +34,40 @@ struct StencilW {
   T w[kMaxOrder / 2 + 1];   // w[0] centre, w[k] offset +-k
 };
 
+// a product rounded on its own (never fused into a later addition): a term added to both the
+// field and the increment of the increment form rounds the same in every kernel variant
+template <typename T>
+__device__ __forceinline__ T mul_rn(T a, T b) {
+#pragma clang fp contract(off)
+  return a * b;
+}
+
+// The increment form's Laplacian: sum_k w_k ((p_{-k} - p_0) + (p_{+k} - p_0)) over the axes,
+// equal to the centred stencil because its weights annihilate constants.  The centre term
+// w_0 p_0 is several times larger than the Laplacian of a resolved wave and cancels
+// against the neighbours; the differences are small (and exact when neighbours lie within
+// a factor of two), so this order leaves a rounding error several times smaller.  get(k,
+// side) returns the neighbour at offset k on side 0..5 (-x, +x, -y, +y, -z, +z).
+template <int H, typename T, typename G>
+__device__ __forceinline__ T lap_diff(const StencilW<T> &W, T c, G get) {
+  T lap = T(0);
+#pragma unroll
+  for (int k = 1; k <= H; ++k) {
+    const T sk = ((get(k, 0) - c) + (get(k, 1) - c)) + ((get(k, 2) - c) + (get(k, 3) - c)) +
+                 ((get(k, 4) - c) + (get(k, 5) - c));
+    lap = fma(W.w[k], sk, lap);
+  }
+  return lap;
+}
+
+// d^{n+1} = [(1 - s) d^n + K lap] / (1 + s); outside the damping layer (s = 0) the division
+// is by one and is skipped
+template <typename T>
+__device__ __forceinline__ T increment(T K, T lap, T d, T s) {
+  if (s == T(0)) return fma(K, lap, d);
+  return fma(K, lap, mul_rn(T(1) - s, d)) / (T(1) + s);
+}
+
 __device__ __forceinline__ int wrapk(int i, int n) {
   return i < 0 ? i + n : (i >= n ? i - n : i);
 }
@@ -39,13 +80,68 @@ __device__ __forceinline__ int64_t xcd_remap(int64_t b, int64_t nblk) {
   return (b % 8) * per + b / 8;
 }
 
+// ---- buffer loads ---------------------------------------------------------------------
+// A raw buffer resource over [base, base + bytes): a load at an offset out of that range
+// returns 0 without a memory access, which makes conditional loads branch-free (all of a
+// thread's loads are issued before the first result is needed) and skips the traffic of
+// the nodes left out.
+constexpr uint32_t kBufOff = 0x80000000u;   // an offset out of range (bytes < 2^31)
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t buf_rsrc(const void *base, uint32_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), (short)0, (int)bytes, 0x00020000);
+}
+__device__ __forceinline__ float buf_load(__amdgpu_buffer_rsrc_t r, uint32_t off, float) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
+}
+__device__ __forceinline__ double buf_load(__amdgpu_buffer_rsrc_t r, uint32_t off, double) {
+  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
+}
+
+// Stage p^n of SC shots over an LDS tile of LZ x LY x LX nodes (with PAD = 1 the last x of
+// each row is padding) whose node (0, 0, 0) is grid node (gx0, gy0, gz0), laterally
+// periodic: each of the NT threads issues all its loads, then writes them.  keep(lx, ly, lz)
+// leaves a node out (zero) when false; nodes above or below the box are zero.  The caller
+// checks that a shot's volume is under 2^31 bytes.
+template <typename T, int SC, int LX, int LY, int LZ, int NT, int PAD, typename Keep>
+__device__ __forceinline__ void stage_tile(T *sp, int spstride, const T *un, int64_t vol, int s0, int nshots, int gx0,
+                                           int gy0, int gz0, int nx, int ny, int nz, int64_t pitch, Keep keep) {
+  constexpr int N = LX * LY * LZ, NST = (N + NT - 1) / NT;
+  // an opaque thread index keeps the address arithmetic in here: hoisted out of the
+  // caller's loop over shot passes it would hold NST more registers for the whole kernel
+  int tid = (int)threadIdx.x;
+  __asm__ volatile("" : "+v"(tid));
+  __amdgpu_buffer_rsrc_t r[SC];
+#pragma unroll
+  for (int c = 0; c < SC; ++c)
+    r[c] = buf_rsrc(un + (size_t)(s0 + c) * vol, (s0 + c < nshots) ? (uint32_t)(vol * (int64_t)sizeof(T)) : 0u);
+  T v[SC][NST];
+#pragma unroll
+  for (int j = 0; j < NST; ++j) {
+    const int e = tid + j * NT;
+    const int lx = e % LX, ly = (e / LX) % LY, lz = e / (LX * LY);
+    const int gz = gz0 + lz;
+    const bool in = e < N && (PAD == 0 || lx < LX - 1) && gz >= 0 && gz < nz && keep(lx, ly, lz);
+    const int gx = wrapk(gx0 + lx, nx), gy = wrapk(gy0 + ly, ny);
+    const uint32_t off = in ? (uint32_t)(((int64_t)gz * ny + gy) * pitch + gx) * (uint32_t)sizeof(T) : kBufOff;
+#pragma unroll
+    for (int c = 0; c < SC; ++c) v[c][j] = buf_load(r[c], off, T(0));
+  }
+#pragma unroll
+  for (int j = 0; j < NST; ++j) {
+    const int e = tid + j * NT;
+    if (e < N) {
+#pragma unroll
+      for (int c = 0; c < SC; ++c) sp[c * spstride + e] = v[c][j];
+    }
+  }
+}
+
 // ---- 3D interior: xy tile in LDS, register queue along z ---------------------------
-template <typename T, int H, int RY>
+template <typename T, int H, int RY, bool DL>
 __launch_bounds__(256)
-__global__ void k_interior3d(const T *__restrict__ un, T *__restrict__ um, const T *__restrict__ K,
+__global__ void k_interior3d(const T *__restrict__ un, T *__restrict__ um, T *__restrict__ dd, const T *__restrict__ K,
                              const T *__restrict__ sx, const T *__restrict__ sy, const T *__restrict__ sz,
-                             StencilW<T> W, int nx, int ny, int nz, int64_t pitch, int64_t vol, int zchunk,
-                             int ntx, int nty, int nzc, int nshots) {
+                             StencilW<T> W, StencilW<double> WD, int nx, int ny, int nz, int64_t pitch, int64_t vol,
+                             int zchunk, int ntx, int nty, int nzc, int nshots) {
   constexpr int TX = 64, TY = 4 * RY, LX = TX + 2 * H, LY = TY + 2 * H;
   __shared__ T tile[LY][LX];
   const int64_t nblk = (int64_t)ntx * nty * nzc * nshots;
@@ -64,6 +160,7 @@ __global__ void k_interior3d(const T *__restrict__ un, T *__restrict__ um, const
   const int64_t plane = pitch * ny;
   const T *u = un + (size_t)shot * vol;
   T *o = um + (size_t)shot * vol;
+  T *od = DL ? dd + (size_t)shot * vol : nullptr;
   const int xg = x0 + tx;
   const int xw = xg % nx;
   const bool xin = xg < nx;
@@ -107,7 +204,7 @@ __global__ void k_interior3d(const T *__restrict__ un, T *__restrict__ um, const
     for (int r = 0; r < RY; ++r) {
       nxt[r] = (zn < nz) ? u[(size_t)zn * plane + (size_t)yw[r] * pitch + xw] : T(0);
       size_t c = zoff + (size_t)yw[r] * pitch + xw;
-      pm[r] = o[c];
+      pm[r] = DL ? od[c] : o[c];
       kk[r] = K[c];
     }
 #pragma unroll
@@ -133,14 +230,27 @@ __global__ void k_interior3d(const T *__restrict__ un, T *__restrict__ um, const
     for (int r = 0; r < RY; ++r) {
       const int ly = H + ty * RY + r, lx = H + tx;
       const T c = q[r][H];
-      T lap = T(3) * W.w[0] * c;
-#pragma unroll
-      for (int k = 1; k <= H; ++k)
-        lap += W.w[k] * ((tile[ly][lx - k] + tile[ly][lx + k]) + (tile[ly - k][lx] + tile[ly + k][lx]) +
-                         (q[r][H - k] + q[r][H + k]));
       const T s = sxz + sy[yw[r]];
-      const T v = (T(2) * c - (T(1) - s) * pm[r] + kk[r] * lap) / (T(1) + s);
-      if (xin && yin[r]) o[zoff + (size_t)yw[r] * pitch + xw] = v;
+      if constexpr (DL) {
+        const T lap = lap_diff<H>(W, c, [&](int k, int side) {
+          return side == 0 ? tile[ly][lx - k] : side == 1 ? tile[ly][lx + k]
+               : side == 2 ? tile[ly - k][lx] : side == 3 ? tile[ly + k][lx]
+               : side == 4 ? q[r][H - k] : q[r][H + k];
+        });
+        const T d = increment(kk[r], lap, pm[r], s);
+        if (xin && yin[r]) {
+          const size_t g = zoff + (size_t)yw[r] * pitch + xw;
+          od[g] = d;
+          o[g] = c + d;
+        }
+      } else {
+        T lap = T(3) * W.w[0] * c;
+#pragma unroll
+        for (int k = 1; k <= H; ++k)
+          lap += W.w[k] * ((tile[ly][lx - k] + tile[ly][lx + k]) + (tile[ly - k][lx] + tile[ly + k][lx]) +
+                           (q[r][H - k] + q[r][H + k]));
+        if (xin && yin[r]) o[zoff + (size_t)yw[r] * pitch + xw] = (T(2) * c - (T(1) - s) * pm[r] + kk[r] * lap) / (T(1) + s);
+      }
     }
     __syncthreads();
 #pragma unroll
@@ -155,12 +265,12 @@ __global__ void k_interior3d(const T *__restrict__ un, T *__restrict__ um, const
 // Same tiling as k_interior3d, but everything plane z+1 needs from memory (the queue's
 // new plane, p^{n-1}, K and the LDS halo of the centre plane) is requested during plane
 // z, and the LDS centre plane is double buffered so one barrier per plane suffices.
-template <typename T, int H, int RY, int NW>
+template <typename T, int H, int RY, int NW, bool DL>
 __launch_bounds__(64 * NW)
-__global__ void k_interior3d_p(const T *__restrict__ un, T *__restrict__ um, const T *__restrict__ K,
+__global__ void k_interior3d_p(const T *__restrict__ un, T *__restrict__ um, T *__restrict__ dd, const T *__restrict__ K,
                                const T *__restrict__ sx, const T *__restrict__ sy, const T *__restrict__ sz,
-                               StencilW<T> W, int nx, int ny, int nz, int64_t pitch, int64_t vol, int zchunk,
-                               int ntx, int nty, int nzc, int nshots, const int2 *__restrict__ zrange) {
+                               StencilW<T> W, StencilW<double> WD, int nx, int ny, int nz, int64_t pitch, int64_t vol,
+                               int zchunk, int ntx, int nty, int nzc, int nshots, const int2 *__restrict__ zrange) {
   constexpr int TX = 64, TY = NW * RY, LX = TX + 2 * H, LY = TY + 2 * H;
   __shared__ T tile[2][LY][LX];
   const int64_t nblk = (int64_t)ntx * nty * nzc * nshots;
@@ -187,6 +297,9 @@ __global__ void k_interior3d_p(const T *__restrict__ un, T *__restrict__ um, con
   const uint32_t plane = (uint32_t)(pitch * ny);
   const T *u = un + (size_t)shot * vol;
   T *o = um + (size_t)shot * vol;
+  // p^{n-1} (plain) or d^n (increment form) at the centre: read once per node
+  const T *pin = DL ? dd + (size_t)shot * vol : o;
+  T *od = DL ? dd + (size_t)shot * vol : nullptr;
   const int xg = x0 + tx;
   const int xw = xg % nx;
   const bool xin = xg < nx;
@@ -234,7 +347,7 @@ __global__ void k_interior3d_p(const T *__restrict__ un, T *__restrict__ um, con
   T pm[RY], kk[RY], hx[RY], hy[NHY];
 #pragma unroll
   for (int r = 0; r < RY; ++r) {
-    pm[r] = o[(uint32_t)z0 * plane + rowoff[r]];
+    pm[r] = pin[(uint32_t)z0 * plane + rowoff[r]];
     kk[r] = K[(uint32_t)z0 * plane + rowoff[r]];
     hx[r] = (xl || xr) ? u[(uint32_t)z0 * plane + (uint32_t)ywv[r] * (uint32_t)pitch + (uint32_t)xh] : T(0);
   }
@@ -262,7 +375,7 @@ __global__ void k_interior3d_p(const T *__restrict__ un, T *__restrict__ um, con
     for (int r = 0; r < RY; ++r) {
       nq[r] = (zq < nz) ? u[(uint32_t)zq * plane + rowoff[r]] : T(0);
       // p^{n-1} and K are read once: non-temporal, so that p^n halos keep the caches
-      npm[r] = more ? __builtin_nontemporal_load(&o[znoff + rowoff[r]]) : T(0);
+      npm[r] = more ? __builtin_nontemporal_load(&pin[znoff + rowoff[r]]) : T(0);
       nk[r] = more ? __builtin_nontemporal_load(&K[znoff + rowoff[r]]) : T(0);
       nhx[r] = (more && (xl || xr)) ? u[znoff + (uint32_t)ywv[r] * (uint32_t)pitch + (uint32_t)xh] : T(0);
     }
@@ -274,14 +387,29 @@ __global__ void k_interior3d_p(const T *__restrict__ un, T *__restrict__ um, con
     for (int r = 0; r < RY; ++r) {
       const int ly = H + ty * RY + r, lx = H + tx;
       const T c = q[r][H];
-      T lap = T(3) * W.w[0] * c;
-#pragma unroll
-      for (int k = 1; k <= H; ++k)
-        lap += W.w[k] * ((tile[buf][ly][lx - k] + tile[buf][ly][lx + k]) +
-                         (tile[buf][ly - k][lx] + tile[buf][ly + k][lx]) + (q[r][H - k] + q[r][H + k]));
       const T s = sxz + sy[ywv[r]];
-      const T v = (T(2) * c - (T(1) - s) * pm[r] + kk[r] * lap) / (T(1) + s);
-      if (xin && yin[r]) __builtin_nontemporal_store(v, &o[(uint32_t)z * plane + rowoff[r]]);
+      if constexpr (DL) {
+        const T lap = lap_diff<H>(W, c, [&](int k, int side) {
+          return side == 0 ? tile[buf][ly][lx - k] : side == 1 ? tile[buf][ly][lx + k]
+               : side == 2 ? tile[buf][ly - k][lx] : side == 3 ? tile[buf][ly + k][lx]
+               : side == 4 ? q[r][H - k] : q[r][H + k];
+        });
+        const T d = increment(kk[r], lap, pm[r], s);
+        if (xin && yin[r]) {
+          const uint32_t g = (uint32_t)z * plane + rowoff[r];
+          __builtin_nontemporal_store(d, &od[g]);
+          __builtin_nontemporal_store(c + d, &o[g]);
+        }
+      } else {
+        T lap = T(3) * W.w[0] * c;
+#pragma unroll
+        for (int k = 1; k <= H; ++k)
+          lap += W.w[k] * ((tile[buf][ly][lx - k] + tile[buf][ly][lx + k]) +
+                           (tile[buf][ly - k][lx] + tile[buf][ly + k][lx]) + (q[r][H - k] + q[r][H + k]));
+        if (xin && yin[r])
+          __builtin_nontemporal_store((T(2) * c - (T(1) - s) * pm[r] + kk[r] * lap) / (T(1) + s),
+                                      &o[(uint32_t)z * plane + rowoff[r]]);
+      }
     }
 #pragma unroll
     for (int r = 0; r < RY; ++r) {
@@ -299,11 +427,12 @@ __global__ void k_interior3d_p(const T *__restrict__ un, T *__restrict__ um, con
 }
 
 // ---- generic interior (2D, or 3D with other orders): one thread per node ------------
-template <typename T, int H>
-__global__ void k_interior_generic(const T *__restrict__ un, T *__restrict__ um, const T *__restrict__ K,
+template <typename T, int H, bool DL>
+__global__ void k_interior_generic(const T *__restrict__ un, T *__restrict__ um, T *__restrict__ dd,
+                                   const T *__restrict__ K,
                                    const T *__restrict__ sx, const T *__restrict__ sy, const T *__restrict__ sz,
-                                   StencilW<T> W, int nx, int ny, int nz, int lat, int64_t pitch, int64_t vol,
-                                   int nshots, int zf, int zl) {
+                                   StencilW<T> W, StencilW<double> WD, int nx, int ny, int nz, int lat,
+                                   int64_t pitch, int64_t vol, int nshots, int zf, int zl) {
   // only the planes [zf, zl) hold interior nodes; the others hold zeros that stay zero
   const int64_t per = (int64_t)nx * ny * (zl - zf);
   int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -319,6 +448,26 @@ __global__ void k_interior_generic(const T *__restrict__ un, T *__restrict__ um,
   T *o = um + (size_t)shot * vol;
   const size_t c = (size_t)z * plane + (size_t)y * pitch + x;
   const T uc = u[c];
+  const T s = sx[x] + sy[y] + sz[z];
+  if constexpr (DL) {
+    // the increment form's difference Laplacian (see lap_diff); nodes beyond the top and
+    // the bottom of the box hold zero
+    T lap = T(0);
+    for (int k = 1; k <= H; ++k) {
+      T acc = (u[(size_t)z * plane + (size_t)y * pitch + wrapk(x - k, nx)] - uc) +
+              (u[(size_t)z * plane + (size_t)y * pitch + wrapk(x + k, nx)] - uc);
+      if (lat == 2)
+        acc += (u[(size_t)z * plane + (size_t)wrapk(y - k, ny) * pitch + x] - uc) +
+               (u[(size_t)z * plane + (size_t)wrapk(y + k, ny) * pitch + x] - uc);
+      acc += ((z - k >= 0 ? u[c - (size_t)k * plane] : T(0)) - uc) + ((z + k < nz ? u[c + (size_t)k * plane] : T(0)) - uc);
+      lap = fma(W.w[k], acc, lap);
+    }
+    T *od = dd + (size_t)shot * vol;
+    const T d = increment(K[c], lap, od[c], s);
+    od[c] = d;
+    o[c] = uc + d;
+    return;
+  }
   T lap = T(lat + 1) * W.w[0] * uc;
   for (int k = 1; k <= H; ++k) {
     T acc = u[(size_t)z * plane + (size_t)y * pitch + wrapk(x - k, nx)] +
@@ -330,7 +479,6 @@ __global__ void k_interior_generic(const T *__restrict__ un, T *__restrict__ um,
     if (z + k < nz) acc += u[c + (size_t)k * plane];
     lap += W.w[k] * acc;
   }
-  const T s = sx[x] + sy[y] + sz[z];
   o[c] = (T(2) * uc - (T(1) - s) * o[c] + K[c] * lap) / (T(1) + s);
 }
 
@@ -388,7 +536,8 @@ __device__ __forceinline__ void patch_group(const T *__restrict__ u, const T *__
 
 template <typename T>
 __launch_bounds__(256)
-__global__ void k_patch(const T *__restrict__ un, T *__restrict__ unew, const uint32_t *__restrict__ rec,
+__global__ void k_patch(const T *__restrict__ un, T *__restrict__ unew, T *__restrict__ dd,
+                        const uint32_t *__restrict__ rec,
                         const PInfo<T> *__restrict__ pinfo, const int32_t *__restrict__ ball,
                         const int32_t *__restrict__ delta, const int32_t *__restrict__ ball_meta, int64_t nib,
                         int nx, int ny, int nz, int64_t pitch, int64_t vol, int nshots) {
@@ -418,7 +567,11 @@ __global__ void k_patch(const T *__restrict__ un, T *__restrict__ unew, const ui
     for (int g = 0; g < ngroups; ++g)
       patch_group<T, 8>(u, wts, bl, dl, mw, g * 8, nb, lane, edge, x, y, z, nx, ny, pitch, plane, centre, wbase, acc);
     for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
-    if (lane == 0) unew[(size_t)s * vol + centre] += P.scale * acc;
+    if (lane == 0) {
+      const T v = mul_rn(P.scale, acc);
+      unew[(size_t)s * vol + centre] += v;
+      if (dd) dd[(size_t)s * vol + centre] += v;
+    }
   }
 }
 
@@ -441,7 +594,8 @@ struct alignas(16) PInfoD {
 
 template <typename T, int TX, int TY, int TZ, int HR, int PV>
 __launch_bounds__(512)
-__global__ void k_patch_tiled(const T *__restrict__ un, T *__restrict__ unew, const T *__restrict__ dense,
+__global__ void k_patch_tiled(const T *__restrict__ un, T *__restrict__ unew, T *__restrict__ dd,
+                              const T *__restrict__ dense,
                               const PInfoD<T> *__restrict__ pinfo, const int32_t *__restrict__ ball,
                               const int32_t *__restrict__ ball_meta, const int4 *__restrict__ tiles, int ntiles,
                               int nx, int ny, int nz, int64_t pitch, int64_t vol, int nshots) {
@@ -562,7 +716,9 @@ __global__ void k_patch_tiled(const T *__restrict__ un, T *__restrict__ unew, co
     // per-point path, where its load would wait behind the prefetched weights)
     for (int q = p0 + (int)threadIdx.x; q < p1; q += blockDim.x) {
       const PInfoD<T> P = pinfo[q];
-      unew[(size_t)s * vol + (size_t)P.z * plane + (size_t)P.y * pitch + P.x] += res[q - p0];
+      const size_t g = (size_t)s * vol + (size_t)P.z * plane + (size_t)P.y * pitch + P.x;
+      unew[g] += res[q - p0];
+      if (dd) dd[g] += res[q - p0];
     }
     __syncthreads();
   }
@@ -588,7 +744,8 @@ struct PairW {
 // even offsets and are padded with a zero to an even length), halving the weight loads.
 template <typename T, int TX, int TY, int TZ, int HR, int D, int SC, int VW = 1>
 __launch_bounds__(512)
-__global__ void k_patch_tiled_r(const T *__restrict__ un, T *__restrict__ unew, const T *__restrict__ dense,
+__global__ void k_patch_tiled_r(const T *__restrict__ un, T *__restrict__ unew, T *__restrict__ dd,
+                                const T *__restrict__ dense,
                                 const PInfoD<T> *__restrict__ pinfo, const int32_t *__restrict__ ball,
                                 const int32_t *__restrict__ ball_meta, const int4 *__restrict__ tiles, int ntiles,
                                 int nx, int ny, int nz, int64_t pitch, int64_t vol, int nshots) {
@@ -678,16 +835,8 @@ __global__ void k_patch_tiled_r(const T *__restrict__ un, T *__restrict__ unew, 
       for (int h = 0; h < 2; ++h) get(wave + d * STEP + h * NW, wo[d][h], fc[d][h], lcc[d][h]);
 #pragma unroll
     for (int d = 0; d < D; ++d) load(W[d], wo[d], fc[d]);
-    for (int e = threadIdx.x; e < LZ * LY * LX; e += blockDim.x) {
-      const int lx = e % LX, ly = (e / LX) % LY, lz = e / (LX * LY);
-      const int gz = z0 - HR + lz;
-      const int gx = wrapk(x0 - HR + lx, nx), gy = wrapk(y0 - HR + ly, ny);
-      const bool in = lx < LX - 1 && gz >= 0 && gz < nz;
-      const size_t g = (size_t)gz * plane + (size_t)gy * pitch + gx;
-#pragma unroll
-      for (int c = 0; c < SC; ++c)
-        sp[c][e] = (in && s0 + c < nshots) ? un[(size_t)(s0 + c) * vol + g] : T(0);
-    }
+    stage_tile<T, SC, LX, LY, LZ, 512, 1>(&sp[0][0], LZ * LY * LX, un, vol, s0, nshots, x0 - HR, y0 - HR, z0 - HR, nx,
+                                       ny, nz, pitch, [](int, int, int) { return true; });
     __syncthreads();
     for (int p = wave; p < np; p += STEP) {
       // weights of the group D steps ahead; its successor's records
@@ -713,12 +862,13 @@ __global__ void k_patch_tiled_r(const T *__restrict__ un, T *__restrict__ unew, 
               if constexpr (VW == 2) {
                 // e + 1 <= count: a zero weight at the record's pad, its lattice index in range
                 const int o0 = lc + lt[e], o1 = lc + lt[e + 1];
+                // explicit fused multiply-adds: every shot count rounds alike
 #pragma unroll
-                for (int c = 0; c < SC; ++c) acc[c] += W[0].w[h][k].x * sp[c][o0] + W[0].w[h][k].y * sp[c][o1];
+                for (int c = 0; c < SC; ++c) acc[c] = fmaf(W[0].w[h][k].y, sp[c][o1], fmaf(W[0].w[h][k].x, sp[c][o0], acc[c]));
               } else {
                 const int o = lc + lt[e];
 #pragma unroll
-                for (int c = 0; c < SC; ++c) acc[c] += W[0].w[h][k] * sp[c][o];
+                for (int c = 0; c < SC; ++c) acc[c] = fma(W[0].w[h][k], sp[c][o], acc[c]);
               }
             }
           }
@@ -744,7 +894,11 @@ __global__ void k_patch_tiled_r(const T *__restrict__ un, T *__restrict__ unew, 
       const size_t g = (size_t)P.z * plane + (size_t)P.y * pitch + P.x;
 #pragma unroll
       for (int c = 0; c < SC; ++c)
-        if (s0 + c < nshots) unew[(size_t)(s0 + c) * vol + g] += P.scale * res[c][i];
+        if (s0 + c < nshots) {
+          const T v = mul_rn(P.scale, res[c][i]);
+          unew[(size_t)(s0 + c) * vol + g] += v;
+          if (dd) dd[(size_t)(s0 + c) * vol + g] += v;
+        }
     }
     __syncthreads();
   }
@@ -762,7 +916,8 @@ struct TileRecM {
 
 template <typename T, int TX, int TY, int TZ, int HR>
 __launch_bounds__(512)
-__global__ void k_patch_tiled_m(const T *__restrict__ un, T *__restrict__ unew, const uint32_t *__restrict__ rec,
+__global__ void k_patch_tiled_m(const T *__restrict__ un, T *__restrict__ unew, T *__restrict__ dd,
+                                const uint32_t *__restrict__ rec,
                                 const PInfo<T> *__restrict__ pinfo, const int32_t *__restrict__ ball,
                                 const int32_t *__restrict__ ball_meta, const int4 *__restrict__ tiles, int ntiles,
                                 int nx, int ny, int nz, int64_t pitch, int64_t vol, int nshots) {
@@ -910,7 +1065,178 @@ __global__ void k_patch_tiled_m(const T *__restrict__ un, T *__restrict__ unew, 
     __syncthreads();
     for (int i = threadIdx.x; i < np; i += blockDim.x) {
       const PInfo<T> P = pinfo[p0 + i];
-      unew[(size_t)s * vol + (size_t)P.z * plane + (size_t)P.y * pitch + P.x] += P.scale * res[i];
+      const size_t g = (size_t)s * vol + (size_t)P.z * plane + (size_t)P.y * pitch + P.x;
+      const T v = mul_rn(P.scale, res[i]);
+      unew[g] += v;
+      if (dd) dd[g] += v;
+    }
+    __syncthreads();
+  }
+}
+
+// Tiled patch streaming the column-run records: only the data nodes' weights cross HBM
+// (plus a zero at the rare non-data node inside a column's run).  Lane c of the wavefront
+// that evaluates a point takes ball column c (lanes 0..4 also one single-node extra column
+// of the radius-4.5 ball): it finds the column's run from the tile's table of first data
+// planes, its entries' offset by a prefix sum over the lanes (DPP), and loads a window of
+// entries that ends with its run, so that window row k always pairs with the same plane
+// (the bottom of the column minus 8 - k): the reads of p^n are one LDS address plus
+// immediate offsets, and window rows before the run are dropped with one select each.
+// p^n is staged plane by plane with a plane of 256 nodes (bank = column, whatever the
+// plane) under four zero planes.  The kernel keeps the vector instructions per point few:
+// the table streams at HBM rate only if the wavefronts keep up.  Two points per
+// wavefront are in flight (the loads of one while the other is evaluated).  Staging skips
+// the nodes above each column's first data plane (their weights are all zero).
+struct ColDec {
+  int base, mlen, ebase, elen;  // LDS index of the window's first row, run length; extra node, 0/1
+  uint32_t off;                 // entry of window row 0 (the run's first entry at row 9 - mlen)
+};
+
+template <typename T, int SC>
+__launch_bounds__(512)
+__global__ void k_patch_cols(const T *__restrict__ un, T *__restrict__ unew, T *__restrict__ dd,
+                             const T *__restrict__ wcol, const uint2 *__restrict__ recs, const T *__restrict__ scale,
+                             const int16_t *__restrict__ zfirst, const int32_t *__restrict__ coltab,
+                             const int4 *__restrict__ tiles, int ntiles, int nx, int ny, int nz, int64_t pitch,
+                             int64_t vol, int nshots) {
+  constexpr int TX = kTileX, TY = kTileY, TZ = kTileZ, HR = kTileHalo;
+  constexpr int CX = TX + 2 * HR, CY = TY + 2 * HR, LZ = TZ + 2 * HR;
+  constexpr int NE = 2 * HR + 1;          // window rows (the longest column)
+  constexpr int NC = CX * CY;             // columns of the tile with its halo (one LDS plane)
+  constexpr int ZT = NE - 1 - HR;         // zero planes above the tile (window rows of short columns)
+  constexpr int NW = 8;                   // wavefronts per workgroup
+  constexpr int VEC = 16 / sizeof(T);     // entries per 16-byte load
+  constexpr int NWIN = NE + 1;            // window entries used: rows, then the extra node
+  constexpr int NL = (NWIN + VEC - 1) / VEC;
+  static_assert(HR == 4 && NC % 64 == 0, "column tables of radius 4 and 4.5; planes of whole bank rows");
+  __shared__ T sp[SC][(ZT + LZ) * NC];
+  __shared__ int zf[NC];                  // first data plane of each column (tile plane index)
+  __shared__ uint2 rec[kTileMaxPoints];   // entry offset; x | y << 5 | z << 10 | radius code 9 << 31
+  __shared__ T res[SC][kTileMaxPoints];
+  const int64_t tb = xcd_remap(blockIdx.x, gridDim.x);
+  if (tb >= ntiles) return;
+  const int4 tl = tiles[tb];
+  const int x0 = tl.x, y0 = tl.y, z0 = tl.z;
+  const int p0 = tl.w, np = tiles[tb + 1].w - tl.w;
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  const int64_t plane = pitch * ny;
+  // this lane's columns as offsets in a plane (co = dy * CX + dx), with their half height zr
+  // (-1: no column): radius 4.5, radius 4, and the extra column
+  int co9, zr9, co8, zr8, coe;
+  bool hase;
+  {
+    auto unpack = [&](int32_t col, int &co, int &zr) {
+      const int dx = (int8_t)(col & 255), dy = (int8_t)((col >> 8) & 255);
+      co = col == kNoColumn ? 0 : dy * CX + dx;
+      zr = col == kNoColumn ? -1 : (col >> 16) & 255;
+    };
+    unpack(coltab[lane], co9, zr9);
+    unpack(lane < kColumns8 ? coltab[kColumns9 + lane] : kNoColumn, co8, zr8);
+    const int32_t e9 = lane < kColumns9 - 64 ? coltab[64 + lane] : kNoColumn;
+    int zre;
+    unpack(e9, coe, zre);
+    hase = e9 != kNoColumn;
+  }
+  for (int e = threadIdx.x; e < NC; e += blockDim.x) {
+    const int gx = wrapk(x0 - HR + e % CX, nx), gy = wrapk(y0 - HR + e / CX, ny);
+    zf[e] = (int)zfirst[(int64_t)gy * nx + gx] - (z0 - HR);
+  }
+  for (int i = threadIdx.x; i < np; i += blockDim.x) rec[i] = recs[p0 + i];
+  for (int e = threadIdx.x; e < ZT * NC; e += blockDim.x)
+#pragma unroll
+    for (int c = 0; c < SC; ++c) sp[c][e] = T(0);
+  __syncthreads();
+  auto decode = [&](int i) {
+    ColDec D{0, 0, 0, 0, 0u};
+    // past the tile's points: a point at the tile centre without entries (every window,
+    // read and dropped, inside the table's leading padding)
+    uint32_t woff = (uint32_t)kColPad, loc = (uint32_t)(HR | (HR << 5) | (HR << 10));
+    if (i < np) {
+      const uint2 r = rec[i];
+      woff = (uint32_t)__builtin_amdgcn_readfirstlane((int)r.x);
+      loc = (uint32_t)__builtin_amdgcn_readfirstlane((int)r.y);
+    }
+    const int col = (int)((loc >> 5) & 31) * CX + (int)(loc & 31), lz = (loc >> 10) & 63;
+    const bool is9 = (loc >> 31) != 0u;
+    const int co = is9 ? co9 : co8, zr = (i < np) ? (is9 ? zr9 : zr8) : -1;
+    D.mlen = max(min(zr - zf[col + co] + lz + 1, 2 * zr + 1), 0);
+    // window row k: plane lz + zr - 8 + k (a lane without a column reads the top zero plane)
+    D.base = (zr >= 0 ? lz + zr - (NE - 1) + ZT : 0) * NC + col + co;
+    D.elen = (is9 && hase && zf[col + coe] <= lz) ? 1 : 0;
+    D.ebase = (lz + ZT) * NC + col + coe;
+    const int len = D.mlen + D.elen;
+    D.off = woff + (uint32_t)(wave_incl_scan(len) - len) + (uint32_t)D.mlen - (uint32_t)NE;
+    return D;
+  };
+  // straight-line loads (no branch around a load, so the loads of the next point stay in
+  // flight while this one is evaluated); the window's entries outside this lane's own are
+  // read and not used (the table has padding before its first and after its last entry)
+  auto load = [&](const ColDec &D, T(&w)[NL * VEC]) {
+#pragma unroll
+    for (int j = 0; j < NL; ++j) {
+      if constexpr (VEC == 4) {
+        float4 v;
+        __builtin_memcpy(&v, wcol + D.off + j * VEC, sizeof(v));
+        w[j * VEC] = v.x, w[j * VEC + 1] = v.y, w[j * VEC + 2] = v.z, w[j * VEC + 3] = v.w;
+      } else {
+        double2 v;
+        __builtin_memcpy(&v, wcol + D.off + j * VEC, sizeof(v));
+        w[j * VEC] = v.x, w[j * VEC + 1] = v.y;
+      }
+    }
+  };
+  auto eval = [&](const ColDec &D, const T(&w)[NL * VEC], int q) {
+    T acc[SC];
+#pragma unroll
+    for (int c = 0; c < SC; ++c) acc[c] = T(0);
+#pragma unroll
+    for (int k = 0; k < NE; ++k) {
+      const T wk = (k >= NE - D.mlen) ? w[k] : T(0);
+#pragma unroll
+      for (int c = 0; c < SC; ++c) acc[c] = fma(wk, sp[c][D.base + k * NC], acc[c]);
+    }
+    const T we = D.elen ? w[NE] : T(0);
+#pragma unroll
+    for (int c = 0; c < SC; ++c) acc[c] = fma(we, sp[c][D.ebase], acc[c]);
+#pragma unroll
+    for (int c = 0; c < SC; ++c) {
+      const T t = wave_total(acc[c]);
+      if (lane == 0 && q < np) res[c][q] = t;
+    }
+  };
+  for (int s0 = 0; s0 < nshots; s0 += SC) {
+    // the first point's weights are in flight while the tile is staged
+    ColDec D0 = decode(wave), D1;
+    T w0[NL * VEC], w1[NL * VEC];
+    load(D0, w0);
+    stage_tile<T, SC, CX, CY, LZ, 512, 0>(&sp[0][ZT * NC], (ZT + LZ) * NC, un, vol, s0, nshots, x0 - HR, y0 - HR,
+                                           z0 - HR, nx, ny, nz, pitch,
+                                           [&](int lx, int ly, int lz) { return zf[ly * CX + lx] <= lz; });
+    __syncthreads();
+    // points wave, wave + NW, ...: two in flight, roles alternating (no register moves)
+    for (int p = wave; p < np; p += 2 * NW) {
+      D1 = decode(p + NW);
+      load(D1, w1);
+      eval(D0, w0, p);
+      D0 = decode(p + 2 * NW);
+      load(D0, w0);
+      eval(D1, w1, p + NW);
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < np; i += blockDim.x) {
+      const uint32_t loc = rec[i].y;
+      const int gx = wrapk(x0 - HR + (int)(loc & 31), nx), gy = wrapk(y0 - HR + (int)((loc >> 5) & 31), ny);
+      const int gz = z0 - HR + (int)((loc >> 10) & 63);
+      const size_t g = (size_t)gz * plane + (size_t)gy * pitch + gx;
+      const T sc = scale[p0 + i];
+#pragma unroll
+      for (int c = 0; c < SC; ++c)
+        if (s0 + c < nshots) {
+          const T v = mul_rn(sc, res[c][i]);
+          unew[(size_t)(s0 + c) * vol + g] += v;
+          if (dd) dd[(size_t)(s0 + c) * vol + g] += v;
+        }
     }
     __syncthreads();
   }
@@ -952,13 +1278,17 @@ void enqueue_make_pinfo_dense(int prec, const int16_t *xyz, const int32_t *first
 
 // ---- sources and receivers ---------------------------------------------------------
 template <typename T>
-__global__ void k_inject(T *unew, const int64_t *sidx, const T *sw, int nshots, int64_t vol, const T *wavelet,
+__global__ void k_inject(T *unew, T *dd, const int64_t *sidx, const T *sw, int nshots, int64_t vol, const T *wavelet,
                          int64_t wstride, int64_t *tcount) {
   const int64_t t = tcount[0];
   for (int e = threadIdx.x; e < nshots * 8; e += blockDim.x) {
     int s = e >> 3;
     int64_t idx = sidx[e];
-    if (idx >= 0) unew[(size_t)s * vol + idx] += wavelet[(size_t)s * wstride + t] * sw[e];
+    if (idx >= 0) {
+      const T v = mul_rn(wavelet[(size_t)s * wstride + t], sw[e]);
+      unew[(size_t)s * vol + idx] += v;
+      if (dd) dd[(size_t)s * vol + idx] += v;
+    }
   }
   __syncthreads();
   if (threadIdx.x == 0) {
@@ -988,14 +1318,18 @@ __global__ void k_sample(const T *unew, const int64_t *ridx, const T *rw, int nr
 // workgroup barrier orders the injection before the sampling, so the step needs one launch
 // less (a small 2D step is launch-bound).  Same arithmetic as k_inject then k_sample.
 template <typename T>
-__global__ void k_io_small(T *unew, const int64_t *sidx, const T *sw, int nshots, int64_t vol, const T *wavelet,
+__global__ void k_io_small(T *unew, T *dd, const int64_t *sidx, const T *sw, int nshots, int64_t vol, const T *wavelet,
                            int64_t wstride, const int64_t *ridx, const T *rw, int nrec, T *traces, int64_t nsteps,
                            int64_t *tcount) {
   const int64_t t = tcount[0];
   for (int e = threadIdx.x; e < nshots * 8; e += blockDim.x) {
     int s = e >> 3;
     int64_t idx = sidx[e];
-    if (idx >= 0) unew[(size_t)s * vol + idx] += wavelet[(size_t)s * wstride + t] * sw[e];
+    if (idx >= 0) {
+      const T v = mul_rn(wavelet[(size_t)s * wstride + t], sw[e]);
+      unew[(size_t)s * vol + idx] += v;
+      if (dd) dd[(size_t)s * vol + idx] += v;
+    }
   }
   __syncthreads();
   const int64_t tl = t - tcount[2];
@@ -1033,7 +1367,7 @@ constexpr int kPatchPairs = (sizeof(T) == 4) ? 2 : 1;
 // holding K_i / (1 + s_i) times the point's condition-value weights contracted with g_q.
 // Runs before the source injection advances the step counter.
 template <typename T>
-__global__ void k_ib_forcing(T *unew, const int16_t *xyz, const T *F, const T *fs, int nq, int64_t fstride,
+__global__ void k_ib_forcing(T *unew, T *dd, const int16_t *xyz, const T *F, const T *fs, int nq, int64_t fstride,
                              int64_t nib, int ny, int64_t pitch, int64_t vol, int nshots, const int64_t *tcount) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= nib) return;
@@ -1041,7 +1375,10 @@ __global__ void k_ib_forcing(T *unew, const int16_t *xyz, const T *F, const T *f
   T v = T(0);
   for (int q = 0; q < nq; ++q) v += F[i * nq + q] * fs[(size_t)q * fstride + t];
   const int64_t idx = ((int64_t)xyz[i * 4 + 2] * ny + xyz[i * 4 + 1]) * pitch + xyz[i * 4];
-  for (int s = 0; s < nshots; ++s) unew[(size_t)s * vol + idx] += v;
+  for (int s = 0; s < nshots; ++s) {
+    unew[(size_t)s * vol + idx] += v;
+    if (dd) dd[(size_t)s * vol + idx] += v;
+  }
 }
 
 // ---- launch helpers ----------------------------------------------------------------
@@ -1054,10 +1391,11 @@ static StencilW<T> stencil_weights(int M) {
   return W;
 }
 
-template <typename T>
-static void launch_interior(const StepArgs &a, hipStream_t st) {
+template <typename T, bool DL>
+static void launch_interior_t(const StepArgs &a, hipStream_t st) {
   const T *un = (const T *)a.un;
   T *um = (T *)a.um;
+  T *dd = (T *)a.dd;
   const T *K = (const T *)a.K;
   const T *sx = (const T *)a.sx, *sy = (const T *)a.sy, *sz = (const T *)a.sz;
   if (a.ndim == 3 && a.M == 8 && a.variant >= 1 && a.vol * (int64_t)sizeof(T) < (int64_t(1) << 31) && a.zrange16 &&
@@ -1072,18 +1410,19 @@ static void launch_interior(const StepArgs &a, hipStream_t st) {
     int64_t nblk = (int64_t)ntx * nty * nzc * a.nshots;
     int64_t nblk8 = (nblk + 7) / 8 * 8;
     const StencilW<T> W = stencil_weights<T>(a.M);
+    const StencilW<double> WD = stencil_weights<double>(a.M);
     if (a.variant == 2)
-      hipLaunchKernelGGL((k_interior3d_p<T, 4, 8, 4>), dim3((unsigned)nblk8), dim3(256), 0, st, un, um, K, sx, sy, sz,
-                         W, a.nx, a.ny, a.nz, a.pitch, a.vol, zc, ntx, nty, nzc, a.nshots, zr);
+      hipLaunchKernelGGL((k_interior3d_p<T, 4, 8, 4, DL>), dim3((unsigned)nblk8), dim3(256), 0, st, un, um, dd, K, sx,
+                         sy, sz, W, WD, a.nx, a.ny, a.nz, a.pitch, a.vol, zc, ntx, nty, nzc, a.nshots, zr);
     else if (a.variant == 3)
-      hipLaunchKernelGGL((k_interior3d_p<T, 4, 4, 8>), dim3((unsigned)nblk8), dim3(512), 0, st, un, um, K, sx, sy, sz,
-                         W, a.nx, a.ny, a.nz, a.pitch, a.vol, zc, ntx, nty, nzc, a.nshots, zr);
+      hipLaunchKernelGGL((k_interior3d_p<T, 4, 4, 8, DL>), dim3((unsigned)nblk8), dim3(512), 0, st, un, um, dd, K, sx,
+                         sy, sz, W, WD, a.nx, a.ny, a.nz, a.pitch, a.vol, zc, ntx, nty, nzc, a.nshots, zr);
     else if (a.variant == 4)
-      hipLaunchKernelGGL((k_interior3d_p<T, 4, 2, 8>), dim3((unsigned)nblk8), dim3(512), 0, st, un, um, K, sx, sy, sz,
-                         W, a.nx, a.ny, a.nz, a.pitch, a.vol, zc, ntx, nty, nzc, a.nshots, zr);
+      hipLaunchKernelGGL((k_interior3d_p<T, 4, 2, 8, DL>), dim3((unsigned)nblk8), dim3(512), 0, st, un, um, dd, K, sx,
+                         sy, sz, W, WD, a.nx, a.ny, a.nz, a.pitch, a.vol, zc, ntx, nty, nzc, a.nshots, zr);
     else
-      hipLaunchKernelGGL((k_interior3d_p<T, 4, 4, 4>), dim3((unsigned)nblk8), dim3(256), 0, st, un, um, K, sx, sy, sz,
-                         W, a.nx, a.ny, a.nz, a.pitch, a.vol, zc, ntx, nty, nzc, a.nshots, zr);
+      hipLaunchKernelGGL((k_interior3d_p<T, 4, 4, 4, DL>), dim3((unsigned)nblk8), dim3(256), 0, st, un, um, dd, K, sx,
+                         sy, sz, W, WD, a.nx, a.ny, a.nz, a.pitch, a.vol, zc, ntx, nty, nzc, a.nshots, zr);
     return;
   }
   if (a.ndim == 3 && a.M == 8) {
@@ -1093,8 +1432,9 @@ static void launch_interior(const StepArgs &a, hipStream_t st) {
     const int nzc = (a.nz + zc - 1) / zc;
     int64_t nblk = (int64_t)ntx * nty * nzc * a.nshots;
     int64_t nblk8 = (nblk + 7) / 8 * 8;
-    hipLaunchKernelGGL((k_interior3d<T, 4, RY>), dim3((unsigned)nblk8), dim3(256), 0, st, un, um, K, sx, sy, sz,
-                       stencil_weights<T>(a.M), a.nx, a.ny, a.nz, a.pitch, a.vol, zc, ntx, nty, nzc, a.nshots);
+    hipLaunchKernelGGL((k_interior3d<T, 4, RY, DL>), dim3((unsigned)nblk8), dim3(256), 0, st, un, um, dd, K, sx, sy,
+                       sz, stencil_weights<T>(a.M), stencil_weights<double>(a.M), a.nx, a.ny, a.nz, a.pitch, a.vol, zc,
+                       ntx, nty, nzc, a.nshots);
     return;
   }
   const int zf = a.zlast > a.zfirst ? a.zfirst : 0, zl = a.zlast > a.zfirst ? a.zlast : a.nz;
@@ -1104,22 +1444,30 @@ static void launch_interior(const StepArgs &a, hipStream_t st) {
   const int lat = a.ndim - 1;
   switch (a.M) {
     case 2:
-      hipLaunchKernelGGL((k_interior_generic<T, 1>), g, b, 0, st, un, um, K, sx, sy, sz, stencil_weights<T>(2), a.nx,
-                         a.ny, a.nz, lat, a.pitch, a.vol, a.nshots, zf, zl);
+      hipLaunchKernelGGL((k_interior_generic<T, 1, DL>), g, b, 0, st, un, um, dd, K, sx, sy, sz, stencil_weights<T>(2),
+                         stencil_weights<double>(2), a.nx, a.ny, a.nz, lat, a.pitch, a.vol, a.nshots, zf, zl);
       break;
     case 4:
-      hipLaunchKernelGGL((k_interior_generic<T, 2>), g, b, 0, st, un, um, K, sx, sy, sz, stencil_weights<T>(4), a.nx,
-                         a.ny, a.nz, lat, a.pitch, a.vol, a.nshots, zf, zl);
+      hipLaunchKernelGGL((k_interior_generic<T, 2, DL>), g, b, 0, st, un, um, dd, K, sx, sy, sz, stencil_weights<T>(4),
+                         stencil_weights<double>(4), a.nx, a.ny, a.nz, lat, a.pitch, a.vol, a.nshots, zf, zl);
       break;
     case 6:
-      hipLaunchKernelGGL((k_interior_generic<T, 3>), g, b, 0, st, un, um, K, sx, sy, sz, stencil_weights<T>(6), a.nx,
-                         a.ny, a.nz, lat, a.pitch, a.vol, a.nshots, zf, zl);
+      hipLaunchKernelGGL((k_interior_generic<T, 3, DL>), g, b, 0, st, un, um, dd, K, sx, sy, sz, stencil_weights<T>(6),
+                         stencil_weights<double>(6), a.nx, a.ny, a.nz, lat, a.pitch, a.vol, a.nshots, zf, zl);
       break;
     default:
-      hipLaunchKernelGGL((k_interior_generic<T, 4>), g, b, 0, st, un, um, K, sx, sy, sz, stencil_weights<T>(8), a.nx,
-                         a.ny, a.nz, lat, a.pitch, a.vol, a.nshots, zf, zl);
+      hipLaunchKernelGGL((k_interior_generic<T, 4, DL>), g, b, 0, st, un, um, dd, K, sx, sy, sz, stencil_weights<T>(8),
+                         stencil_weights<double>(8), a.nx, a.ny, a.nz, lat, a.pitch, a.vol, a.nshots, zf, zl);
       break;
   }
+}
+
+template <typename T>
+static void launch_interior(const StepArgs &a, hipStream_t st) {
+  if (a.dd)
+    launch_interior_t<T, true>(a, st);
+  else
+    launch_interior_t<T, false>(a, st);
 }
 
 template <typename T>
@@ -1129,14 +1477,14 @@ static void launch_patch(const StepArgs &a, hipStream_t st) {
     int64_t nblk = ((int64_t)a.ntiles + 7) / 8 * 8;
 #define IB_PATCH_TILED(PVV)                                                                                         \
   hipLaunchKernelGGL((k_patch_tiled<T, kTileX, kTileY, kTileZ, kTileHalo, PVV>), dim3((unsigned)nblk), dim3(512), 0, \
-                     st, (const T *)a.un, (T *)a.um, (const T *)a.dense, (const PInfoD<T> *)a.pinfo, a.ball,           \
+                     st, (const T *)a.un, (T *)a.um, (T *)a.dd, (const T *)a.dense, (const PInfoD<T> *)a.pinfo, a.ball, \
                      a.ball_meta, a.tiles, a.ntiles, a.nx, a.ny, a.nz, a.pitch, a.vol, a.nshots)
 #define IB_PATCH_TILED_R(DD, SC)                                                                                    \
   hipLaunchKernelGGL((k_patch_tiled_r<T, kTileX, kTileY, kTileZ, kTileHalo, DD, SC, kPatchPairs<T>>),                  \
                      dim3((unsigned)nblk),                                                                           \
                      dim3(512),                                                                                      \
-                     0, st, (const T *)a.un, (T *)a.um, (const T *)a.dense, (const PInfoD<T> *)a.pinfo, a.ball,       \
-                     a.ball_meta, a.tiles, a.ntiles, a.nx, a.ny, a.nz, a.pitch, a.vol, a.nshots)
+                     0, st, (const T *)a.un, (T *)a.um, (T *)a.dd, (const T *)a.dense, (const PInfoD<T> *)a.pinfo,    \
+                     a.ball, a.ball_meta, a.tiles, a.ntiles, a.nx, a.ny, a.nz, a.pitch, a.vol, a.nshots)
     switch (a.patch_variant) {
       case 0: IB_PATCH_TILED(0); break;
       case 1: IB_PATCH_TILED(1); break;
@@ -1150,9 +1498,28 @@ static void launch_patch(const StepArgs &a, hipStream_t st) {
         break;
       case 5: IB_PATCH_TILED_R(2, 1); break;
       case 6: IB_PATCH_TILED_R(3, 1); break;
+      case 8:
+      case 9: {
+        // two shots per pass in FP32 only (two FP64 tiles would not leave room for a second
+        // workgroup per CU)
+        bool two = false;
+        if constexpr (sizeof(T) == 4) {
+          two = a.patch_variant == 9 && a.nshots >= 2;
+          if (two)
+            hipLaunchKernelGGL((k_patch_cols<T, 2>), dim3((unsigned)nblk), dim3(512), 0, st, (const T *)a.un,
+                               (T *)a.um, (T *)a.dd, (const T *)a.wcol, a.crec, (const T *)a.cscale, a.zfcol, a.coltab,
+                               a.tiles, a.ntiles, a.nx, a.ny, a.nz, a.pitch, a.vol, a.nshots);
+        }
+        if (!two)
+          hipLaunchKernelGGL((k_patch_cols<T, 1>), dim3((unsigned)nblk), dim3(512), 0, st, (const T *)a.un, (T *)a.um,
+                             (T *)a.dd, (const T *)a.wcol, a.crec, (const T *)a.cscale, a.zfcol, a.coltab, a.tiles,
+                             a.ntiles, a.nx, a.ny, a.nz, a.pitch, a.vol, a.nshots);
+        break;
+      }
       default:
         hipLaunchKernelGGL((k_patch_tiled_m<T, kTileX, kTileY, kTileZ, kTileHalo>), dim3((unsigned)nblk), dim3(512), 0,
-                           st, (const T *)a.un, (T *)a.um, a.rec, (const PInfo<T> *)a.pinfo_tm, a.ball, a.ball_meta,
+                           st, (const T *)a.un, (T *)a.um, (T *)a.dd, a.rec, (const PInfo<T> *)a.pinfo_tm, a.ball,
+                           a.ball_meta,
                            a.tiles, a.ntiles, a.nx, a.ny, a.nz, a.pitch, a.vol, a.nshots);
         break;
     }
@@ -1166,7 +1533,7 @@ static void launch_patch(const StepArgs &a, hipStream_t st) {
     hipStream_t ws = fork ? a.aux : st;
     if (fork) (void)hipStreamWaitEvent(a.aux, a.ev_fork, 0);
     int64_t nblk = ((a.nwide + 3) / 4 + 7) / 8 * 8;
-    hipLaunchKernelGGL(k_patch<T>, dim3((unsigned)nblk), dim3(256), 0, ws, (const T *)a.un, (T *)a.um, a.rec,
+    hipLaunchKernelGGL(k_patch<T>, dim3((unsigned)nblk), dim3(256), 0, ws, (const T *)a.un, (T *)a.um, (T *)a.dd, a.rec,
                        (const PInfo<T> *)a.pinfo_wide, a.ball, a.delta, a.ball_meta, a.nwide, a.nx, a.ny, a.nz,
                        a.pitch, a.vol, a.nshots);
     if (fork) {
@@ -1179,12 +1546,12 @@ static void launch_patch(const StepArgs &a, hipStream_t st) {
 template <typename T>
 static void launch_io(const StepArgs &a, T *u, hipStream_t st) {
   if (a.nrec > 0 && a.traces && (int64_t)a.nrec * a.nshots <= kIoSmallMax) {
-    hipLaunchKernelGGL(k_io_small<T>, dim3(1), dim3(256), 0, st, u, a.sidx, (const T *)a.sw, a.nshots, a.vol,
+    hipLaunchKernelGGL(k_io_small<T>, dim3(1), dim3(256), 0, st, u, (T *)a.dd, a.sidx, (const T *)a.sw, a.nshots, a.vol,
                        (const T *)a.wavelet, a.wstride, a.ridx, (const T *)a.rw, a.nrec, (T *)a.traces, a.nsteps,
                        a.tcount);
     return;
   }
-  hipLaunchKernelGGL(k_inject<T>, dim3(1), dim3(256), 0, st, u, a.sidx, (const T *)a.sw, a.nshots, a.vol,
+  hipLaunchKernelGGL(k_inject<T>, dim3(1), dim3(256), 0, st, u, (T *)a.dd, a.sidx, (const T *)a.sw, a.nshots, a.vol,
                      (const T *)a.wavelet, a.wstride, a.tcount);
   if (a.nrec > 0 && a.traces) {
     int64_t tot = (int64_t)a.nrec * a.nshots;
@@ -1198,7 +1565,8 @@ static void launch_step(const StepArgs &a, hipStream_t st) {
   launch_interior<T>(a, st);
   launch_patch<T>(a, st);
   if (a.fF && a.nib > 0)
-    hipLaunchKernelGGL(k_ib_forcing<T>, dim3((unsigned)((a.nib + 255) / 256)), dim3(256), 0, st, (T *)a.um, a.ib_xyz,
+    hipLaunchKernelGGL(k_ib_forcing<T>, dim3((unsigned)((a.nib + 255) / 256)), dim3(256), 0, st, (T *)a.um,
+                       (T *)a.dd, a.ib_xyz,
                        (const T *)a.fF, (const T *)a.fs, a.fnq, a.fstride, a.nib, a.ny, a.pitch, a.vol, a.nshots,
                        (const int64_t *)a.tcount);
   launch_io<T>(a, (T *)a.um, st);
@@ -1265,7 +1633,8 @@ __global__ void k_adj_ibvals(T *__restrict__ v, const T *__restrict__ lam1, cons
 // partial sums are combined with DPP rotations inside the row.
 template <typename T, int SC>
 __launch_bounds__(256)
-__global__ void k_adj_gather(T *__restrict__ lam, const T *__restrict__ v, const uint32_t *__restrict__ jnode,
+__global__ void k_adj_gather(T *__restrict__ lam, T *__restrict__ lamd, const T *__restrict__ v,
+                             const uint32_t *__restrict__ jnode,
                              const T *__restrict__ jD, const uint32_t *__restrict__ joff,
                              const uint32_t *__restrict__ src, const T *__restrict__ wt, int64_t nj, int nshots,
                              int s0, int64_t vol) {
@@ -1290,13 +1659,18 @@ __global__ void k_adj_gather(T *__restrict__ lam, const T *__restrict__ v, const
     const T t = row_sum16(acc[c]);
     if (sub == c) mine = t;
   }
-  if (live && sub < SC && s0 + sub < nshots)
-    lam[(size_t)(s0 + sub) * vol + jnode[j]] += jD[j] * mine;
+  if (live && sub < SC && s0 + sub < nshots) {
+    const size_t g = (size_t)(s0 + sub) * vol + jnode[j];
+    const T add = mul_rn(jD[j], mine);
+    lam[g] += add;
+    if (lamd) lamd[g] += add;
+  }
 }
 
 // mu^m_j += (K D)_j sum over receivers using node j of w * res^{m-1}
 template <typename T>
-__global__ void k_adj_receivers(T *__restrict__ lam, const T *__restrict__ res, int64_t nt, int nrec, int64_t step,
+__global__ void k_adj_receivers(T *__restrict__ lam, T *__restrict__ lamd, const T *__restrict__ res, int64_t nt,
+                                int nrec, int64_t step,
                                 const int64_t *__restrict__ rnode, const T *__restrict__ rD,
                                 const int64_t *__restrict__ roff, const int32_t *__restrict__ rrec,
                                 const T *__restrict__ rw, int64_t nrn, int nshots, int64_t vol) {
@@ -1307,12 +1681,17 @@ __global__ void k_adj_receivers(T *__restrict__ lam, const T *__restrict__ res, 
     const T *r = res + ((size_t)s * nt + step) * nrec;
     T acc = T(0);
     for (int64_t k = a; k < b; ++k) acc += rw[k] * r[rrec[k]];
-    lam[(size_t)s * vol + rnode[j]] += rD[j] * acc;
+    const size_t g = (size_t)s * vol + rnode[j];
+    const T add = mul_rn(rD[j], acc);
+    lam[g] += add;
+    if (lamd) lamd[g] += add;
   }
 }
 
 // g += sum over shots of mu^m ((1 + s) u^m - 2 u^{m-1} + (1 - s) u^{m-2}) at interior nodes,
-// in FP64 from the stored time levels; one thread per node of a padded row
+// in FP64 from the stored time levels; one thread per node of a padded row.  In the
+// increment form the segment keeps d^m = u^m - u^{m-1} and the same quantity is
+// (1 + s) d^m - (1 - s) d^{m-1} (u1 is null, u2 = d^m, u0 = d^{m-1}).
 template <typename T>
 __launch_bounds__(256)
 __global__ void k_grad_pt(double *__restrict__ gK, const T *__restrict__ mu, const T *__restrict__ u2,
@@ -1328,10 +1707,13 @@ __global__ void k_grad_pt(double *__restrict__ gK, const T *__restrict__ mu, con
   double tot = 0.0;
   for (int sh = 0; sh < nshots; ++sh) {
     const size_t q = (size_t)sh * vol + c;
-    // the three time levels are read once here: non-temporal
-    const double l = (1.0 + s) * (double)__builtin_nontemporal_load(&u2[q]) -
-                     2.0 * (double)__builtin_nontemporal_load(&u1[q]) +
-                     (1.0 - s) * (double)__builtin_nontemporal_load(&u0[q]);
+    // the time levels are read once here: non-temporal
+    double l;
+    if (u1)
+      l = (1.0 + s) * (double)__builtin_nontemporal_load(&u2[q]) - 2.0 * (double)__builtin_nontemporal_load(&u1[q]) +
+          (1.0 - s) * (double)__builtin_nontemporal_load(&u0[q]);
+    else
+      l = (1.0 + s) * (double)__builtin_nontemporal_load(&u2[q]) - (1.0 - s) * (double)__builtin_nontemporal_load(&u0[q]);
     tot += (double)mu[q] * l;
   }
   gK[c] += tot;
@@ -1384,19 +1766,23 @@ static void adjoint_step_t(const AdjArgs &a, hipStream_t st) {
     for (int s0 = 0; s0 < a.nshots;) {
       const int left = a.nshots - s0;
       if (left >= 16) {
-        hipLaunchKernelGGL((k_adj_gather<T, 16>), gj, dim3(256), 0, st, (T *)a.lam2, (const T *)a.vals, a.jnode,
+        hipLaunchKernelGGL((k_adj_gather<T, 16>), gj, dim3(256), 0, st, (T *)a.lam2, (T *)a.lamd, (const T *)a.vals,
+                           a.jnode,
                            (const T *)a.jD, a.joff, a.jsrc, (const T *)a.jw, a.nj, a.nshots, s0, a.vol);
         s0 += 16;
       } else if (left >= 8) {
-        hipLaunchKernelGGL((k_adj_gather<T, 8>), gj, dim3(256), 0, st, (T *)a.lam2, (const T *)a.vals, a.jnode,
+        hipLaunchKernelGGL((k_adj_gather<T, 8>), gj, dim3(256), 0, st, (T *)a.lam2, (T *)a.lamd, (const T *)a.vals,
+                           a.jnode,
                            (const T *)a.jD, a.joff, a.jsrc, (const T *)a.jw, a.nj, a.nshots, s0, a.vol);
         s0 += 8;
       } else if (left >= 4) {
-        hipLaunchKernelGGL((k_adj_gather<T, 4>), gj, dim3(256), 0, st, (T *)a.lam2, (const T *)a.vals, a.jnode,
+        hipLaunchKernelGGL((k_adj_gather<T, 4>), gj, dim3(256), 0, st, (T *)a.lam2, (T *)a.lamd, (const T *)a.vals,
+                           a.jnode,
                            (const T *)a.jD, a.joff, a.jsrc, (const T *)a.jw, a.nj, a.nshots, s0, a.vol);
         s0 += 4;
       } else {
-        hipLaunchKernelGGL((k_adj_gather<T, 1>), gj, dim3(256), 0, st, (T *)a.lam2, (const T *)a.vals, a.jnode,
+        hipLaunchKernelGGL((k_adj_gather<T, 1>), gj, dim3(256), 0, st, (T *)a.lam2, (T *)a.lamd, (const T *)a.vals,
+                           a.jnode,
                            (const T *)a.jD, a.joff, a.jsrc, (const T *)a.jw, a.nj, a.nshots, s0, a.vol);
         s0 += 1;
       }
@@ -1404,7 +1790,7 @@ static void adjoint_step_t(const AdjArgs &a, hipStream_t st) {
   }
   if (a.nrn > 0)
     hipLaunchKernelGGL(k_adj_receivers<T>, dim3((unsigned)((a.nrn + 255) / 256)), dim3(256), 0, st, (T *)a.lam2,
-                       (const T *)a.res, a.nt, a.nrec, a.step, a.rnode, (const T *)a.rD, a.roff, a.rrec,
+                       (T *)a.lamd, (const T *)a.res, a.nt, a.nrec, a.step, a.rnode, (const T *)a.rD, a.roff, a.rrec,
                        (const T *)a.rw, a.nrn, a.nshots, a.vol);
   const dim3 gg((unsigned)((a.nx + 255) / 256), (unsigned)a.ny, (unsigned)a.nz);
   hipLaunchKernelGGL(k_grad_pt<T>, gg, dim3(256), 0, st, a.gK, (const T *)a.lam2, (const T *)a.u2,

@@ -740,6 +740,124 @@ __global__ void k_dense(int64_t nib, const uint32_t *rec32, const uint32_t *roff
   }
 }
 
+// ---- column-run records (3D supports of radius 4 and 4.5, the LDS-tiled patch) --------
+// A support ball is a set of depth columns (dx, dy), each spanning dz in [-zr, zr].  The
+// data nodes of a column (interior and not excluded) lie at or below the first data node
+// of their grid column, zfirst(x + dx, y + dy): the column contributes the run
+// [a, zr], a = max(zfirst - z, -zr), and a node of the run that is not data (a rare node
+// excluded below the first data node, or a node below the box) gets a zero weight.  Column
+// c belongs to lane c of a wavefront; the radius-4.5 ball has 69 columns, and its five
+// extra single-node columns (zr = 0) go to lanes 0..4, whose own columns are short.  The
+// record holds each lane's run (then its extra node) contiguously, lanes in order, so a
+// lane's entries start at the count of its lower lanes' entries (a ballot prefix count) and
+// are read with a few wide loads; no per-weight offsets are stored.
+
+// first data plane of every grid column (nz where a column has none)
+__global__ void k_zfirst(const uint8_t *cls, int nx, int ny, int nz, int16_t *zf) {
+  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= (int64_t)nx * ny) return;
+  int z = 0;
+  for (; z < nz; ++z) {
+    const uint8_t v = cls[(int64_t)z * nx * ny + c];
+    if ((v & 1) && !(v & 2)) break;
+  }
+  zf[c] = (int16_t)z;
+}
+
+// the run of the lane's column (and of its extra column) for IB point i; len = -1: no column
+struct ColRun {
+  int dx, dy, a, len;
+};
+__device__ __forceinline__ ColRun col_run(int32_t col, const int16_t *zf, int x, int y, int z, int nx, int ny) {
+  ColRun r{0, 0, 0, 0};
+  if (col == kNoColumn) return r;
+  r.dx = (int8_t)(col & 255);
+  r.dy = (int8_t)((col >> 8) & 255);
+  const int zr = (col >> 16) & 255;
+  int xx = x + r.dx, yy = y + r.dy;
+  xx = xx < 0 ? xx + nx : (xx >= nx ? xx - nx : xx);
+  yy = yy < 0 ? yy + ny : (yy >= ny ? yy - ny : yy);
+  r.a = max((int)zf[(int64_t)yy * nx + xx] - z, -zr);
+  r.len = max(0, zr - r.a + 1);
+  return r;
+}
+
+// the lane's main column and extra column for a support of radius code 8 or 9
+__device__ __forceinline__ void lane_columns(const int32_t *coltab, int code, int lane, int32_t &mc, int32_t &ec) {
+  mc = (code == 9) ? coltab[lane] : (lane < kColumns8 ? coltab[kColumns9 + lane] : kNoColumn);
+  ec = (code == 9 && lane < kColumns9 - 64) ? coltab[64 + lane] : kNoColumn;
+}
+
+// entries per IB point (-1 for supports the tiled patch does not take)
+__global__ void k_col_count(int64_t nib, const int16_t *xyz, const int16_t *zf, const int32_t *coltab, int nx, int ny,
+                            int32_t *cnt) {
+  const int64_t i = blockIdx.x;
+  if (i >= nib) return;
+  const int lane = threadIdx.x;
+  const int code = xyz[i * 4 + 3];
+  if (code != 8 && code != 9) {
+    if (lane == 0) cnt[i] = -1;
+    return;
+  }
+  const int x = xyz[i * 4], y = xyz[i * 4 + 1], z = xyz[i * 4 + 2];
+  int32_t mc, ec;
+  lane_columns(coltab, code, lane, mc, ec);
+  int n = col_run(mc, zf, x, y, z, nx, ny).len + col_run(ec, zf, x, y, z, nx, ny).len;
+  for (int o = 32; o > 0; o >>= 1) n += __shfl_xor(n, o);
+  if (lane == 0) cnt[i] = n;
+}
+
+// entries of one IB point: weights from the compact record (data-membership mask + the
+// data nodes' weights in ball order), zero at non-data nodes of the runs; err counts the
+// points whose data nodes are not all covered by the runs (none, by the construction)
+__global__ void k_col_pack(int64_t nib, const int16_t *xyz, const int32_t *meta, const uint32_t *rec32,
+                           const uint32_t *roff32, const double *w64, const int16_t *zf, const int32_t *coltab,
+                           const int16_t *inv, const int32_t *ball_meta, int nx, int ny, int nz, const uint32_t *off,
+                           const int32_t *cnt, float *c32, double *c64, int32_t *err) {
+  const int64_t i = blockIdx.x;
+  if (i >= nib || cnt[i] < 0) return;
+  const int lane = threadIdx.x;
+  const int code = xyz[i * 4 + 3];
+  const int x = xyz[i * 4], y = xyz[i * 4 + 1], z = xyz[i * 4 + 2];
+  const int16_t *iv = inv + (code == 9 ? 0 : 729);
+  const int nb = ball_meta[2 * code + 1];
+  const uint32_t *m = rec32 + roff32[i];
+  const double *wv = w64 + meta[i * 4 + 3];
+  const int nw = meta[i * 4 + 2];
+  int32_t mc, ec;
+  lane_columns(coltab, code, lane, mc, ec);
+  const ColRun R = col_run(mc, zf, x, y, z, nx, ny);
+  const ColRun E = col_run(ec, zf, x, y, z, nx, ny);
+  // the weight of the node (dx, dy, dz) of this point's ball: 0 unless it is a data node
+  auto weight = [&](int dx, int dy, int dz, int &covered) -> double {
+    if (z + dz >= nz) return 0.0;
+    const int b = iv[((dz + 4) * 9 + (dy + 4)) * 9 + (dx + 4)];
+    if (b < 0 || b >= nb || !((m[b >> 5] >> (b & 31)) & 1u)) return 0.0;
+    int rank = 0;
+    for (int q = 0; q < (b >> 5); ++q) rank += __popc(m[q]);
+    rank += __popc(m[b >> 5] & ((1u << (b & 31)) - 1u));
+    ++covered;
+    return wv[rank];
+  };
+  // this lane's first entry: the entries of the lower lanes (one ballot per entry count)
+  const int len = R.len + E.len;
+  int pos = 0, tot = 0;
+  for (int k = 0; k < 2 * 4 + 2; ++k) {
+    const unsigned long long bal = __ballot(len > k);
+    pos += __popcll(bal & ((1ull << lane) - 1ull));
+    tot += __popcll(bal);
+  }
+  int covered = 0;
+  const uint32_t o = off[i] + (uint32_t)pos;
+  for (int k = 0; k < len; ++k) {
+    const double v = (k < R.len) ? weight(R.dx, R.dy, R.a + k, covered) : weight(E.dx, E.dy, 0, covered);
+    c32[o + k] = (float)v;
+    c64[o + k] = v;
+  }
+  for (int s = 32; s > 0; s >>= 1) covered += __shfl_xor(covered, s);
+  if (lane == 0 && (covered != nw || tot != cnt[i])) atomicAdd(err, 1);
+}
+
 // threads of a k_solve workgroup: a lane quad per column of A, whole wavefronts
 static int solve_threads(int ncols) { return std::min(768, std::max(64, (4 * ncols + 63) / 64 * 64)); }
 
@@ -813,6 +931,119 @@ ib_status build_dense_records(ib_weights *w, hipStream_t st) {
     w->dense_count = d_count;
     w->dense_off = d_doff;
   }
+  return IB_OK;
+}
+
+// Column-run records of the 3D supports of radius 4 and 4.5 (see k_col_pack).
+ib_status build_column_records(ib_weights *w, hipStream_t st) {
+  if (w->ndim != 3 || w->nib == 0) return IB_OK;
+  const int64_t nib = w->nib, ncols = w->nx * w->ny;
+  if (w->nz > 32767) {
+    set_error("column-run records need nz < 32768");
+    return IB_ERR_ARG;
+  }
+  // column tables: code 9 (69 columns, the five extra single-node ones last), then code 8
+  std::vector<int32_t> tab;
+  std::vector<int16_t> inv(2 * 729, -1);
+  for (int q = 0; q < 2; ++q) {
+    const int code = 9 - q;
+    const double r = code / 2.0;
+    std::vector<int32_t> main, extra;
+    for (int dy = -4; dy <= 4; ++dy)
+      for (int dx = -4; dx <= 4; ++dx) {
+        const int d2 = dx * dx + dy * dy;
+        if (4 * d2 > code * code) continue;
+        const int zr = (int)std::floor(std::sqrt(r * r - d2) + 1e-12);
+        main.push_back((int32_t)((uint32_t)(uint8_t)(int8_t)dx | ((uint32_t)(uint8_t)(int8_t)dy << 8) |
+                                 ((uint32_t)zr << 16)));
+      }
+    if (code == 9) {
+      // the last five single-node columns (zr = 0) are the extra columns of lanes 0..4, whose
+      // own columns are the five shortest others (zr <= 1)
+      for (int j = (int)main.size() - 1; j >= 0 && extra.size() < (size_t)(kColumns9 - 64); --j)
+        if (((main[j] >> 16) & 255) == 0) {
+          extra.insert(extra.begin(), main[j]);
+          main.erase(main.begin() + j);
+        }
+      std::stable_sort(main.begin(), main.end(), [](int32_t a, int32_t b) { return ((a >> 16) & 255) < ((b >> 16) & 255); });
+    }
+    if (code == 9 && (main.size() != 64 || extra.size() != (size_t)(kColumns9 - 64))) {
+      set_error("unexpected ball column count");
+      return IB_ERR_ARG;
+    }
+    if (code == 8 && main.size() != (size_t)kColumns8) {
+      set_error("unexpected ball column count");
+      return IB_ERR_ARG;
+    }
+    tab.insert(tab.end(), main.begin(), main.end());
+    tab.insert(tab.end(), extra.begin(), extra.end());
+    const int st0 = w->balls.start[code], nb = w->balls.count[code];
+    for (int b = 0; b < nb; ++b) {
+      const uint32_t e = (uint32_t)w->balls.packed[st0 + b];
+      const int dx = (int8_t)(e & 255), dy = (int8_t)((e >> 8) & 255), dz = (int8_t)((e >> 16) & 255);
+      inv[q * 729 + ((dz + 4) * 9 + (dy + 4)) * 9 + (dx + 4)] = (int16_t)b;
+    }
+  }
+  ib_status s;
+  int16_t *d_inv = nullptr;
+  int32_t *d_cnt = nullptr, *d_err = nullptr;
+  auto cleanup = [&]() {
+    dfree(d_inv);
+    dfree(d_cnt);
+    dfree(d_err);
+  };
+  if ((s = dalloc_t(&w->col_tab, tab.size())) || (s = dalloc_t(&w->zfirst, ncols)) || (s = dalloc_t(&d_inv, inv.size())) ||
+      (s = dalloc_t(&d_cnt, nib)) || (s = dalloc_t(&w->col_off, nib)) || (s = dalloc_t(&d_err, 1))) {
+    cleanup();
+    return s;
+  }
+  IB_HIP(hipMemcpyAsync(w->col_tab, tab.data(), tab.size() * 4, hipMemcpyHostToDevice, st));
+  IB_HIP(hipMemcpyAsync(d_inv, inv.data(), inv.size() * 2, hipMemcpyHostToDevice, st));
+  IB_HIP(hipMemsetAsync(d_err, 0, 4, st));
+  hipLaunchKernelGGL(k_zfirst, dim3((unsigned)((ncols + 255) / 256)), dim3(256), 0, st, w->node_class, (int)w->nx,
+                     (int)w->ny, (int)w->nz, w->zfirst);
+  hipLaunchKernelGGL(k_col_count, dim3((unsigned)nib), dim3(64), 0, st, nib, w->ib_xyz, w->zfirst, w->col_tab,
+                     (int)w->nx, (int)w->ny, d_cnt);
+  IB_HIP(hipGetLastError());
+  std::vector<int32_t> cnt(nib);
+  IB_HIP(hipMemcpyAsync(cnt.data(), d_cnt, nib * 4, hipMemcpyDeviceToHost, st));
+  IB_HIP(hipStreamSynchronize(st));
+  // the records start after kColPad entries: the tiled kernel's load windows reach up to 9
+  // entries before a lane's first entry and up to 12 after it
+  std::vector<uint32_t> off(nib, 0);
+  int64_t tot = kColPad;
+  for (int64_t i = 0; i < nib; ++i) {
+    off[i] = (uint32_t)tot;
+    if (cnt[i] > 0) tot += cnt[i];
+  }
+  if (tot >= (int64_t)UINT32_MAX) {
+    cleanup();
+    set_error("column-run stencil table too large");
+    return IB_ERR_ARG;
+  }
+  if ((s = dalloc_t(&w->col32, tot + kColPad)) || (s = dalloc_t(&w->col64, tot + kColPad))) {
+    cleanup();
+    return s;
+  }
+  IB_HIP(hipMemsetAsync(w->col32, 0, (tot + kColPad) * sizeof(float), st));
+  IB_HIP(hipMemsetAsync(w->col64, 0, (tot + kColPad) * sizeof(double), st));
+  IB_HIP(hipMemcpyAsync(w->col_off, off.data(), nib * 4, hipMemcpyHostToDevice, st));
+  hipLaunchKernelGGL(k_col_pack, dim3((unsigned)nib), dim3(64), 0, st, nib, w->ib_xyz, w->ib_meta, w->rec32,
+                     w->rec_off32, w->w64, w->zfirst, w->col_tab, d_inv, w->ball_meta, (int)w->nx, (int)w->ny,
+                     (int)w->nz, w->col_off, d_cnt, w->col32, w->col64, d_err);
+  IB_HIP(hipGetLastError());
+  int32_t err = 0;
+  IB_HIP(hipMemcpyAsync(&err, d_err, 4, hipMemcpyDeviceToHost, st));
+  IB_HIP(hipStreamSynchronize(st));
+  w->col_cnt = d_cnt;
+  d_cnt = nullptr;
+  cleanup();
+  if (err) {
+    set_error("column-run records: %d IB points have data nodes outside their runs", err);
+    return IB_ERR_HIP;
+  }
+  w->col_words = tot + kColPad;
+  w->stats.col_weights = tot - kColPad;
   return IB_OK;
 }
 
@@ -1144,7 +1375,8 @@ ib_status weights_build(ib_weights *w, const int64_t *col_off_dev, hipStream_t s
     w->nbc = nbc;
     w->bc_nq = make_ops(w->prm.surface, M, ndim).nops;
   }
-  return build_dense_records(w, st);
+  if ((s = build_dense_records(w, st))) return s;
+  return build_column_records(w, st);
 }
 
 // Batched solves of one family of staggered operators (first-order form): the same

@@ -1,6 +1,7 @@
 """The tiled IB patch kernels (dense-range records with point records read per wavefront or
-staged in LDS, and compact records) on one 3D case with many tiles: the variants that
-share a summation order give bit-identical traces, the others agree to rounding."""
+staged in LDS, compact records, and column-run records with one or two shots per pass) on
+one 3D case with many tiles: the variants that share a summation order give bit-identical
+traces, the others agree to rounding."""
 import numpy as np
 import pytest
 
@@ -9,7 +10,7 @@ from paper_2309_03600_amd import workloads as W
 pytestmark = pytest.mark.gpu
 
 SAME_ORDER = [4, 5, 6]
-OTHER_ORDER = [0, 1, 2, 3, 7]
+OTHER_ORDER = [0, 1, 2, 3, 7, 8, 9]
 
 _weights = {}
 
@@ -44,6 +45,8 @@ def test_patch_variants_agree(prec, nshots):
     for v in SAME_ORDER:
         rel = np.abs(out[v] - ref).max() / np.abs(ref).max()
         assert np.array_equal(out[v], ref), (v, rel)
+    # the column-run kernel sums the same way with one or two shots per pass
+    assert np.array_equal(out[8], out[9])
     tol = 1e-12 if prec == "f64" else 1e-5
     for v in OTHER_ORDER:
         rel = np.abs(out[v] - ref).max() / np.abs(ref).max()
