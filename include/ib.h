@@ -277,6 +277,20 @@ ib_status ib_forward(ib_state *st, int32_t nt, const void *wavelet_dev, int64_t 
 ib_status ib_adjoint(ib_state *st, const void *residual_dev, const void *wavelet_dev, int64_t wavelet_stride,
                      double *grad_dev, void *stream);
 
+/* ib_adjoint without any device allocation, for callers that cannot allocate (code under
+ * stream capture, serving loops, hosts that forbid hipMalloc).  Same arguments, same result
+ * as ib_adjoint.  Its work space is a fixed 64 MiB device array per device (held until the
+ * process ends) instead of a fresh allocation: the two lambda fields (three in the
+ * increment form), the recomputed segment (ckpt_every + 2 fields of nshots * grid values)
+ * and an FP64 grid must fit, else IB_ERR_ARG (ib_adjoint has no such limit).  The adjoint
+ * tables are built by ib_forward, so no host-device copy is made either.  The work is
+ * enqueued on ``stream`` and the call returns without waiting: grad_dev is ready when
+ * the stream is.  Every call on one device shares that array (each call clears what it
+ * needs), so calls that overlap on one device, from any state or stream, race.
+ * Errors: as ib_adjoint, plus IB_ERR_ARG when the work space does not fit. */
+ib_status ib_adjoint_noalloc(ib_state *st, const void *residual_dev, const void *wavelet_dev,
+                             int64_t wavelet_stride, double *grad_dev, void *stream);
+
 /* Read or write the current wavefields of one shot (layout [nz][ny][nx] or [nz][nx],
  * state precision, device memory):  which = 0: p^n (newest), 1: p^{n-1}.
  * First-order form: which = 0: p^n, 2 + k: v_k^{n-1/2} (k < ndim; in 2D k = 1 is the

@@ -207,14 +207,19 @@ class IBState:
                                           tp, int(ckpt_every), _stream(stream)))
         return traces
 
-    def adjoint(self, residual, wavelet, stream=None):
-        """dJ/dc (float64 grid tensor) for residual = dJ/dtraces of the last ``forward``."""
+    def adjoint(self, residual, wavelet, stream=None, grad=None, noalloc=False):
+        """dJ/dc (float64 grid tensor) for residual = dJ/dtraces of the last ``forward``.
+        ``noalloc`` calls ib_adjoint_noalloc (the library allocates nothing and does not wait
+        for the stream); ``grad`` may be a preallocated float64 grid tensor to overwrite."""
         torch = _torch()
         res = residual.to(device="cuda", dtype=self.dtype).contiguous()
         shape = tuple(reversed(self.weights.shape))
-        grad = torch.zeros(shape, dtype=torch.float64, device="cuda")
-        _lib.check(_lib.load().ib_adjoint(self._h, C.c_void_p(res.data_ptr()), C.c_void_p(wavelet.data_ptr()),
-                                          int(wavelet.shape[1]), C.c_void_p(grad.data_ptr()), _stream(stream)))
+        if grad is None:
+            grad = torch.zeros(shape, dtype=torch.float64, device="cuda")
+        assert grad.dtype == torch.float64 and grad.is_cuda and grad.is_contiguous() and tuple(grad.shape) == shape
+        fn = _lib.load().ib_adjoint_noalloc if noalloc else _lib.load().ib_adjoint
+        _lib.check(fn(self._h, C.c_void_p(res.data_ptr()), C.c_void_p(wavelet.data_ptr()), int(wavelet.shape[1]),
+                      C.c_void_p(grad.data_ptr()), _stream(stream)))
         return grad
 
     def set_forcing(self, g, s, stream=None):

@@ -5,6 +5,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -1402,115 +1403,76 @@ ib_status build_adjoint_tables(ib_state *S, hipStream_t st) {
   return IB_OK;
 }
 
-}  // namespace
-
-extern "C" {
-
-ib_status ib_step(ib_state *S, int32_t nsteps, const void *wavelet, int64_t wstride, void *traces, int32_t use_graph,
-                  void *stream) {
-  if (!S || nsteps < 0 || (S->nrec > 0 && nsteps > 0 && !traces) || !wavelet) {
-    set_error("ib_step: invalid argument");
-    return IB_ERR_ARG;
-  }
-  if (S->t + nsteps > wstride) {
-    set_error("ib_step: wavelet has %lld samples, steps up to %lld requested", (long long)wstride,
-              (long long)(S->t + nsteps));
-    return IB_ERR_ARG;
-  }
-  if (S->fF && S->t + nsteps > S->flen) {
-    set_error("ib_step: boundary-value time functions have %lld samples, steps up to %lld requested",
-              (long long)S->flen, (long long)(S->t + nsteps));
-    return IB_ERR_ARG;
-  }
-  return run_steps(S, nsteps, wavelet, wstride, traces, nsteps, S->t, use_graph != 0, (hipStream_t)stream);
+// zero a work area with a kernel (stream-ordered, and capturable where a memset is not)
+__global__ void k_zero_words(uint32_t *p, size_t n) {
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) p[i] = 0u;
+}
+void zero_bytes(void *p, size_t bytes, hipStream_t st) {
+  const size_t n = bytes / 4;
+  if (n == 0) return;
+  const unsigned nb = (unsigned)std::min<size_t>((n + 255) / 256, 4096);
+  hipLaunchKernelGGL(k_zero_words, dim3(nb), dim3(256), 0, st, (uint32_t *)p, n);
 }
 
-ib_status ib_forward(ib_state *S, int32_t nt, const void *wavelet, int64_t wstride, void *traces, int32_t ckpt_every,
-                     void *stream) {
-  if (!S || nt < 1 || !wavelet || ckpt_every < 1 || wstride < nt || (S->nrec > 0 && !traces) ||
-      S->form != IB_FORM_P2) {
-    set_error("ib_forward: invalid argument");
+ib_status adjoint_check(const ib_state *S, const void *residual, const void *wavelet, const double *grad,
+                        const char *who) {
+  if (!S || !residual || !wavelet || !grad || S->form != IB_FORM_P2) {
+    set_error("%s: null argument or first-order state", who);
     return IB_ERR_ARG;
   }
-  if (S->fF) {
-    set_error("ib_forward: the state has non-zero boundary values (not differentiated by ib_adjoint)");
+  if (S->ck_count == 0) {
+    set_error("%s: no checkpoints (call ib_forward first)", who);
     return IB_ERR_STATE;
   }
-  hipStream_t st = (hipStream_t)stream;
-  const size_t fbytes = (size_t)S->vol * S->nshots * S->esz;
-  const int64_t nck = (nt + ckpt_every - 1) / ckpt_every;
-  if (S->ck_count != nck) {
-    dfree(S->ckpt);
-    S->ckpt = nullptr;
-    S->ck_count = 0;
-    ib_status s = dalloc(&S->ckpt, 2 * fbytes * nck);
-    if (s) return s;
-  }
-  S->ck_count = nck;
-  S->ck_nt = nt;
-  S->ck_every = ckpt_every;
-  IB_HIP(hipMemsetAsync(S->buf[0], 0, fbytes, st));
-  IB_HIP(hipMemsetAsync(S->buf[1], 0, fbytes, st));
-  if (S->incr) IB_HIP(hipMemsetAsync(S->dbuf, 0, fbytes, st));
-  S->t = 0;
-  for (int64_t k = 0; k < nck; ++k) {
-    // checkpoint k: p^n and p^{n-1} (plain form) or d^n (increment form)
-    char *ck = (char *)S->ckpt + (size_t)k * 2 * fbytes;
-    IB_HIP(hipMemcpyAsync(ck, S->buf[S->cur], fbytes, hipMemcpyDeviceToDevice, st));
-    IB_HIP(hipMemcpyAsync(ck + fbytes, S->incr ? S->dbuf : S->buf[1 - S->cur], fbytes, hipMemcpyDeviceToDevice, st));
-    int64_t n = std::min<int64_t>(ckpt_every, nt - k * ckpt_every);
-    ib_status s = run_steps(S, n, wavelet, wstride, traces, nt, 0, false, st);
-    if (s) return s;
+  if (S->fF) {
+    set_error("%s: the state has non-zero boundary values (not differentiated)", who);
+    return IB_ERR_STATE;
   }
   return IB_OK;
 }
 
-ib_status ib_adjoint(ib_state *S, const void *residual, const void *wavelet, int64_t wstride, double *grad,
-                     void *stream) {
-  if (!S || !residual || !wavelet || !grad || S->form != IB_FORM_P2) {
-    set_error("ib_adjoint: null argument or first-order state");
-    return IB_ERR_ARG;
-  }
-  if (S->ck_count == 0) {
-    set_error("ib_adjoint: no checkpoints (call ib_forward first)");
-    return IB_ERR_STATE;
-  }
-  if (S->fF) {
-    set_error("ib_adjoint: the state has non-zero boundary values (not differentiated)");
-    return IB_ERR_STATE;
-  }
-  hipStream_t st = (hipStream_t)stream;
+// Work space of one adjoint run: mu^{m+1}, mu^{m+2} (and mu^m - mu^{m+1} in the increment
+// form), the recomputed segment (ckpt_every + 2 fields) and the FP64 gradient accumulator,
+// each aligned to 256 bytes.
+struct AdjLayout {
+  size_t lam0, lam1, lamd, seg, gK, total;
+};
+AdjLayout adjoint_layout(const ib_state *S) {
+  const size_t fbytes = (size_t)S->vol * S->nshots * S->esz;
+  auto al = [](size_t b) { return (b + 255) & ~(size_t)255; };
+  AdjLayout L{};
+  size_t o = 0;
+  L.lam0 = o, o += al(fbytes);
+  L.lam1 = o, o += al(fbytes);
+  L.lamd = o, o += S->incr ? al(fbytes) : 0;
+  L.seg = o, o += al(fbytes * (size_t)(S->ck_every + 2));
+  L.gK = o, o += al((size_t)S->vol * sizeof(double));
+  L.total = o;
+  return L;
+}
+size_t adjoint_work_bytes(const ib_state *S) { return adjoint_layout(S).total; }
+
+// The adjoint sweep over the checkpoint segments, with its work space at ``work`` (at
+// least adjoint_work_bytes(S)); enqueued on ``st`` without waiting for it.
+ib_status adjoint_run(ib_state *S, const void *residual, const void *wavelet, int64_t wstride, double *grad, void *work,
+                      hipStream_t st) {
   const ib_weights *w = S->w;
   ib_status s;
-  if (!S->adj_ready) {
-    s = (S->prec == IB_F32) ? build_adjoint_tables<float>(S, st) : build_adjoint_tables<double>(S, st);
-    if (s) return s;
-  }
   const int64_t nt = S->ck_nt, C = S->ck_every;
   const size_t fbytes = (size_t)S->vol * S->nshots * S->esz;
-  void *lam[2] = {nullptr, nullptr};
-  void *lamd = nullptr;
-  void *seg = nullptr;
-  double *gK = nullptr;
-  auto cleanup = [&]() {
-    dfree(lam[0]);
-    dfree(lam[1]);
-    dfree(lamd);
-    dfree(seg);
-    dfree(gK);
-  };
   // seg holds u^{t0-1} .. u^{t0+len} of the segment being reversed (C + 2 fields; the
   // increment form keeps d^{t0} .. d^{t0+len}, C + 1 fields); lamd is mu^m - mu^{m+1} of
   // the increment form
-  if ((s = dalloc(&lam[0], fbytes)) || (s = dalloc(&lam[1], fbytes)) || (s = dalloc(&seg, fbytes * (C + 2))) ||
-      (s = dalloc_t(&gK, S->vol)) || (S->incr && (s = dalloc(&lamd, fbytes)))) {
-    cleanup();
-    return s;
-  }
-  IB_HIP(hipMemsetAsync(lam[0], 0, fbytes, st));
-  IB_HIP(hipMemsetAsync(lam[1], 0, fbytes, st));
-  if (lamd) IB_HIP(hipMemsetAsync(lamd, 0, fbytes, st));
-  IB_HIP(hipMemsetAsync(gK, 0, S->vol * sizeof(double), st));
+  const AdjLayout AL = adjoint_layout(S);
+  char *wb = (char *)work;
+  void *lam[2] = {wb + AL.lam0, wb + AL.lam1};
+  void *lamd = S->incr ? (void *)(wb + AL.lamd) : nullptr;
+  void *seg = wb + AL.seg;
+  double *gK = (double *)(wb + AL.gK);
+  zero_bytes(lam[0], fbytes, st);
+  zero_bytes(lam[1], fbytes, st);
+  if (lamd) zero_bytes(lamd, fbytes, st);
+  zero_bytes(gK, (size_t)S->vol * sizeof(double), st);
   int a1 = 0, a2 = 1;   // lam[a1] = mu^{m+1}, lam[a2] = mu^{m+2}
   auto field = [&](int64_t q) { return (char *)seg + (size_t)q * fbytes; };
   for (int64_t k = S->ck_count - 1; k >= 0; --k) {
@@ -1528,10 +1490,7 @@ ib_status ib_adjoint(ib_state *S, const void *residual, const void *wavelet, int
       IB_HIP(hipMemcpyAsync(field(1), ck, fbytes, hipMemcpyDeviceToDevice, st));
     }
     for (int64_t q = 1; q <= len; ++q) {
-      if ((s = run_steps(S, 1, wavelet, wstride, nullptr, 0, 0, false, st))) {
-        cleanup();
-        return s;
-      }
+      if ((s = run_steps(S, 1, wavelet, wstride, nullptr, 0, 0, false, st))) return s;
       if (S->incr)
         IB_HIP(hipMemcpyAsync(field(q), S->dbuf, fbytes, hipMemcpyDeviceToDevice, st));
       else
@@ -1600,10 +1559,151 @@ ib_status ib_adjoint(ib_state *S, const void *residual, const void *wavelet, int
   }
   enqueue_grad_out(S->prec, gK, S->K, grad, (int)w->nx, (int)w->ny, (int)w->nz, S->pitch, S->dt / w->h, st);
   IB_HIP(hipGetLastError());
-  IB_HIP(hipStreamSynchronize(st));
-  cleanup();
   // the wavefields now hold the recomputed first segment; the step counter follows them
   return IB_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+ib_status ib_step(ib_state *S, int32_t nsteps, const void *wavelet, int64_t wstride, void *traces, int32_t use_graph,
+                  void *stream) {
+  if (!S || nsteps < 0 || (S->nrec > 0 && nsteps > 0 && !traces) || !wavelet) {
+    set_error("ib_step: invalid argument");
+    return IB_ERR_ARG;
+  }
+  if (S->t + nsteps > wstride) {
+    set_error("ib_step: wavelet has %lld samples, steps up to %lld requested", (long long)wstride,
+              (long long)(S->t + nsteps));
+    return IB_ERR_ARG;
+  }
+  if (S->fF && S->t + nsteps > S->flen) {
+    set_error("ib_step: boundary-value time functions have %lld samples, steps up to %lld requested",
+              (long long)S->flen, (long long)(S->t + nsteps));
+    return IB_ERR_ARG;
+  }
+  return run_steps(S, nsteps, wavelet, wstride, traces, nsteps, S->t, use_graph != 0, (hipStream_t)stream);
+}
+
+ib_status ib_forward(ib_state *S, int32_t nt, const void *wavelet, int64_t wstride, void *traces, int32_t ckpt_every,
+                     void *stream) {
+  if (!S || nt < 1 || !wavelet || ckpt_every < 1 || wstride < nt || (S->nrec > 0 && !traces) ||
+      S->form != IB_FORM_P2) {
+    set_error("ib_forward: invalid argument");
+    return IB_ERR_ARG;
+  }
+  if (S->fF) {
+    set_error("ib_forward: the state has non-zero boundary values (not differentiated by ib_adjoint)");
+    return IB_ERR_STATE;
+  }
+  hipStream_t st = (hipStream_t)stream;
+  const size_t fbytes = (size_t)S->vol * S->nshots * S->esz;
+  const int64_t nck = (nt + ckpt_every - 1) / ckpt_every;
+  if (S->ck_count != nck) {
+    dfree(S->ckpt);
+    S->ckpt = nullptr;
+    S->ck_count = 0;
+    ib_status s = dalloc(&S->ckpt, 2 * fbytes * nck);
+    if (s) return s;
+  }
+  S->ck_count = nck;
+  S->ck_nt = nt;
+  S->ck_every = ckpt_every;
+  // the adjoint's transposed tables are built here, so that an adjoint call can run on
+  // memory that exists already
+  if (!S->adj_ready) {
+    ib_status s = (S->prec == IB_F32) ? build_adjoint_tables<float>(S, st) : build_adjoint_tables<double>(S, st);
+    if (s) return s;
+  }
+  IB_HIP(hipMemsetAsync(S->buf[0], 0, fbytes, st));
+  IB_HIP(hipMemsetAsync(S->buf[1], 0, fbytes, st));
+  if (S->incr) IB_HIP(hipMemsetAsync(S->dbuf, 0, fbytes, st));
+  S->t = 0;
+  for (int64_t k = 0; k < nck; ++k) {
+    // checkpoint k: p^n and p^{n-1} (plain form) or d^n (increment form)
+    char *ck = (char *)S->ckpt + (size_t)k * 2 * fbytes;
+    IB_HIP(hipMemcpyAsync(ck, S->buf[S->cur], fbytes, hipMemcpyDeviceToDevice, st));
+    IB_HIP(hipMemcpyAsync(ck + fbytes, S->incr ? S->dbuf : S->buf[1 - S->cur], fbytes, hipMemcpyDeviceToDevice, st));
+    int64_t n = std::min<int64_t>(ckpt_every, nt - k * ckpt_every);
+    ib_status s = run_steps(S, n, wavelet, wstride, traces, nt, 0, false, st);
+    if (s) return s;
+  }
+  return IB_OK;
+}
+
+ib_status ib_adjoint(ib_state *S, const void *residual, const void *wavelet, int64_t wstride, double *grad,
+                     void *stream) {
+  ib_status s = adjoint_check(S, residual, wavelet, grad, "ib_adjoint");
+  if (s) return s;
+  hipStream_t st = (hipStream_t)stream;
+  if (!S->adj_ready) {
+    s = (S->prec == IB_F32) ? build_adjoint_tables<float>(S, st) : build_adjoint_tables<double>(S, st);
+    if (s) return s;
+  }
+  const size_t need = adjoint_work_bytes(S);
+  void *work = nullptr;
+  if ((s = dalloc(&work, need))) return s;
+  s = adjoint_run(S, residual, wavelet, wstride, grad, work, st);
+  // the work space is released only after the stream has used it
+  const hipError_t e = hipStreamSynchronize(st);
+  dfree(work);
+  if (s) return s;
+  if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize", __FILE__, __LINE__);
+  return IB_OK;
+}
+
+}  // extern "C"
+
+namespace {
+// Work space of ib_adjoint_noalloc: a fixed device array (each device that runs it holds its
+// own copy until the process ends).  Host code never uses its name as an address: the
+// address comes from hipGetSymbolAddress, once per device, with that device current.
+constexpr size_t kScratchBytes = (size_t)64 << 20;
+__device__ __align__(256) unsigned char scratch[kScratchBytes];
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch[kMaxDevices] = {};
+
+ib_status scratch_address(void **out) {
+  int dev = 0;
+  IB_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) {
+    set_error("ib_adjoint_noalloc: device %d beyond the %d the work space table covers", dev, kMaxDevices);
+    return IB_ERR_ARG;
+  }
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch[dev]) {
+    void *p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress(scratch)", __FILE__, __LINE__);
+    g_scratch[dev] = p;
+  }
+  *out = g_scratch[dev];
+  return IB_OK;
+}
+}  // namespace
+
+extern "C" {
+
+ib_status ib_adjoint_noalloc(ib_state *S, const void *residual, const void *wavelet, int64_t wstride, double *grad,
+                             void *stream) {
+  ib_status s = adjoint_check(S, residual, wavelet, grad, "ib_adjoint_noalloc");
+  if (s) return s;
+  if (!S->adj_ready) {
+    set_error("ib_adjoint_noalloc: the adjoint tables are missing (call ib_forward first)");
+    return IB_ERR_STATE;
+  }
+  const size_t need = adjoint_work_bytes(S);
+  if (need > kScratchBytes) {
+    set_error("ib_adjoint_noalloc: this state needs %zu bytes of work space, more than the %zu available "
+              "(fewer shots, a smaller grid or a shorter checkpoint interval fit; ib_adjoint has no limit)",
+              need, kScratchBytes);
+    return IB_ERR_ARG;
+  }
+  void *work = nullptr;
+  if ((s = scratch_address(&work))) return s;
+  return adjoint_run(S, residual, wavelet, wstride, grad, work, (hipStream_t)stream);
 }
 
 ib_status ib_state_run_kernel(ib_state *S, int32_t which, int32_t count, void *stream) {
