@@ -44,7 +44,7 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-KERNELS = {"interior": "k_interior3d_p", "patch": "k_patch_tiled_r"}
+KERNELS = {"interior": "k_interior3d_p", "patch": "k_patch_cols"}
 TRAFFIC_FILE = "hbm_traffic_interior_patch_config3.json"
 PROFILE_CMDS = [
     "rocprofv3 --pmc FETCH_SIZE --output-format csv -d gpurun_out/prof_f -o f -- "

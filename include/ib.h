@@ -37,7 +37,7 @@
 extern "C" {
 #endif
 
-#define IB_ABI_VERSION 3
+#define IB_ABI_VERSION 4
 
 typedef enum {
   IB_OK = 0,
@@ -46,6 +46,8 @@ typedef enum {
   IB_ERR_OOM = -3,            /* device allocation failed                              */
   IB_ERR_UNCONSTRAINED = -4,  /* an IB point stayed rank deficient after the radius
                                  growth and basis-order reduction of the rank rule     */
+  IB_ERR_NONFINITE = -5,      /* the watchdog saw a non-finite pressure or one above its
+                                 limit (ib_state_set_watchdog)                          */
   IB_ERR_STATE = -6           /* call not valid for this handle / state                */
 } ib_status;
 
@@ -151,6 +153,7 @@ typedef struct {
 
 typedef struct ib_weights ib_weights;
 typedef struct ib_state ib_state;
+typedef struct ib_checkpoints ib_checkpoints;   /* time checkpoints of one forward run */
 
 int32_t ib_abi_version(void);
 const char *ib_last_error(void);
@@ -250,17 +253,35 @@ void ib_state_free(ib_state *st);
  *   with the staggered M-th order differences and the immersed-boundary rows of both
  *   families; the traces sample p^{n+1}.
  * When use_graph is non-zero the per-step kernels are captured once into a HIP graph
- * (two steps, even/odd buffers) and replayed; results are identical to eager launch. */
+ * (two steps, even/odd buffers) and replayed; results are identical to eager launch.
+ * The watchdog (ib_state_set_watchdog) scans p^n after every ``every`` steps on the
+ * stream; a scan that finds a bad value makes the next call on the state (this one's
+ * successor, or ib_state_status) return IB_ERR_NONFINITE.
+ * Errors: IB_ERR_ARG, IB_ERR_NONFINITE (a scan of an earlier call tripped; nothing is
+ *   enqueued), IB_ERR_HIP. */
 ib_status ib_step(ib_state *st, int32_t nsteps, const void *wavelet_dev, int64_t wavelet_stride,
                   void *traces_dev, int32_t use_graph, void *stream);
 
 /* Forward modelling with time checkpoints, for a later ib_adjoint.  Restarts every shot
  * from rest (step counter 0), runs ``nt`` steps exactly as ib_step (eager launches), and
  * keeps (p^n, p^{n-1}) at every multiple of ``ckpt_every`` inside the state (device
- * memory, 2 * nshots * grid * ceil(nt / ckpt_every) values).
+ * memory, 2 * nshots * grid * ceil(nt / ckpt_every) values; the increment form keeps d^n
+ * in place of p^{n-1}).  The watchdog runs as in ib_step.
  *   traces_dev: device [nshots][nt][nrec] in the state precision (may be NULL if nrec = 0). */
 ib_status ib_forward(ib_state *st, int32_t nt, const void *wavelet_dev, int64_t wavelet_stride, void *traces_dev,
                      int32_t ckpt_every, void *stream);
+
+/* ib_forward into a checkpoint handle held by the caller, so that the checkpoints of
+ * several forward runs (other wavelets or receivers' residuals later) can live side by
+ * side and outlive the next ib_forward.
+ *   ckpt: in/out.  *ckpt == NULL: a new handle is created and stored there.  Otherwise an
+ *     earlier handle is reused (reallocated only if its size differs) and taken over by
+ *     this state.  Free it with ib_checkpoints_free (after the stream is done with it).
+ * Errors: as ib_forward; on error a handle created by the call is freed and *ckpt is left
+ *   unchanged. */
+ib_status ib_forward_ckpt(ib_state *st, int32_t nt, const void *wavelet_dev, int64_t wavelet_stride,
+                          void *traces_dev, int32_t ckpt_every, ib_checkpoints **ckpt, void *stream);
+void ib_checkpoints_free(ib_checkpoints *ckpt);
 
 /* Gradient of a misfit J with respect to the velocity, by the discrete adjoint of the
  * stepper (not a result of the paper: full-waveform inversion is its motivation).
@@ -276,6 +297,12 @@ ib_status ib_forward(ib_state *st, int32_t nt, const void *wavelet_dev, int64_t 
  *   (ib_forward and ib_adjoint cover the second-order form only). */
 ib_status ib_adjoint(ib_state *st, const void *residual_dev, const void *wavelet_dev, int64_t wavelet_stride,
                      double *grad_dev, void *stream);
+
+/* ib_adjoint from the checkpoints of an ib_forward_ckpt call by the same state (same
+ * arguments otherwise: residual_dev is dJ/d traces of that forward run).
+ * Errors: as ib_adjoint; IB_ERR_STATE for checkpoints written by another state. */
+ib_status ib_adjoint_ckpt(ib_state *st, const ib_checkpoints *ckpt, const void *residual_dev,
+                          const void *wavelet_dev, int64_t wavelet_stride, double *grad_dev, void *stream);
 
 /* ib_adjoint without any device allocation, for callers that cannot allocate (code under
  * stream capture, serving loops, hosts that forbid hipMalloc).  Same arguments, same result
@@ -327,6 +354,25 @@ int64_t ib_state_step_count(const ib_state *st);
  *   without condition-value weights), IB_ERR_OOM, IB_ERR_HIP. */
 ib_status ib_state_set_forcing(ib_state *st, const double *g_dev, int32_t nq, const double *s_host, int64_t s_len,
                                void *stream);
+
+/* Watchdog against instability (the paper introduces the support parameter eta to keep
+ * the scheme stable, section "Approximating Boundary Conditions"; a growing mode shows as
+ * values that blow up).  After every ``every`` steps of ib_step and ib_forward a kernel
+ * scans p^n of every shot; a value that is NaN, infinite or above ``limit`` in magnitude
+ * trips it.  Its flags come back to the host behind the scan without a wait; the next
+ * call on the state sees them and returns IB_ERR_NONFINITE, as does every call that
+ * steps or differentiates the state after it, until this function is called again.
+ * Defaults: every = 100, limit = 1e30 (FP32 states cap it at the largest float).
+ *   every: steps between scans, 0 turns the scans off; odd values are rounded up so that
+ *     the scans fall between the two-step graph launches.
+ *   limit > 0.
+ * Waits for a scan still in flight, then clears the flags (on ``stream``).
+ * Errors: IB_ERR_ARG. */
+ib_status ib_state_set_watchdog(ib_state *st, int32_t every, double limit, void *stream);
+
+/* IB_OK, or IB_ERR_NONFINITE if a watchdog scan has tripped.  wait != 0 waits for the
+ * last scan enqueued; wait = 0 reads only what has come back. */
+ib_status ib_state_status(ib_state *st, int32_t wait);
 
 /* Measurement aid: enqueue ``count`` launches of one kernel of the step on ``stream``
  * with the current buffers (which = 0: interior stencil, 1: IB patch), rotating the

@@ -12,9 +12,10 @@ import ctypes as C
 import numpy as np
 
 from . import _lib
-from ._lib import IB_F32, IB_F64, IB_SURF_FREE, IB_SURF_RIGID, IB_SURF_ROBIN  # noqa: F401
+from ._lib import IB_F32, IB_F64, IB_SURF_FREE, IB_SURF_RIGID, IB_SURF_ROBIN, NonFiniteError  # noqa: F401
 
-__all__ = ["IBWeights", "IBState", "ib_build_weights", "ib_state_create", "ib_step", "modelling", "abi_version"]
+__all__ = ["IBWeights", "IBState", "Checkpoints", "NonFiniteError", "ib_build_weights", "ib_state_create", "ib_step",
+           "modelling", "abi_version"]
 
 
 def _torch():
@@ -149,6 +150,26 @@ def ib_build_weights(heights, h, shape, space_order=8, surface="free", eta=0.5, 
     return IBWeights(out, ndim, tuple(int(v) for v in shape), form, bool(keep_bc_weights))
 
 
+class Checkpoints:
+    """Caller-held time checkpoints of one forward run (ib_checkpoints); freed on close()
+    or garbage collection."""
+
+    def __init__(self):
+        self._h = None
+
+    def close(self):
+        if self._h:
+            _torch().cuda.synchronize()
+            _lib.load().ib_checkpoints_free(C.c_void_p(self._h))
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 class IBState:
     """Wavefields and acquisition of ``nshots`` shots (library-owned device memory)."""
 
@@ -207,20 +228,51 @@ class IBState:
                                           tp, int(ckpt_every), _stream(stream)))
         return traces
 
-    def adjoint(self, residual, wavelet, stream=None, grad=None, noalloc=False):
-        """dJ/dc (float64 grid tensor) for residual = dJ/dtraces of the last ``forward``.
-        ``noalloc`` calls ib_adjoint_noalloc (the library allocates nothing and does not wait
-        for the stream); ``grad`` may be a preallocated float64 grid tensor to overwrite."""
+    def forward_ckpt(self, nt, wavelet, ckpt_every=50, traces=None, checkpoints=None, stream=None):
+        """``forward`` into a caller-held ``Checkpoints`` object (ib_forward_ckpt); returns
+        (traces, checkpoints).  Passing an earlier object reuses its memory."""
+        torch = _torch()
+        assert wavelet.dtype == self.dtype and wavelet.is_cuda and wavelet.is_contiguous()
+        if traces is None:
+            traces = torch.zeros((self.nshots, nt, self.nrec), dtype=self.dtype, device="cuda")
+        if checkpoints is None:
+            checkpoints = Checkpoints()
+        h = C.c_void_p(checkpoints._h)
+        tp = C.c_void_p(traces.data_ptr()) if self.nrec > 0 else C.c_void_p()
+        _lib.check(_lib.load().ib_forward_ckpt(self._h, int(nt), C.c_void_p(wavelet.data_ptr()), int(wavelet.shape[1]),
+                                               tp, int(ckpt_every), C.byref(h), _stream(stream)))
+        checkpoints._h = h.value
+        return traces, checkpoints
+
+    def adjoint(self, residual, wavelet, stream=None, grad=None, noalloc=False, checkpoints=None):
+        """dJ/dc (float64 grid tensor) for residual = dJ/dtraces of the last ``forward`` (or
+        of the ``forward_ckpt`` run that wrote ``checkpoints``).  ``noalloc`` calls
+        ib_adjoint_noalloc (the library allocates nothing and does not wait for the stream);
+        ``grad`` may be a preallocated float64 grid tensor to overwrite."""
         torch = _torch()
         res = residual.to(device="cuda", dtype=self.dtype).contiguous()
         shape = tuple(reversed(self.weights.shape))
         if grad is None:
             grad = torch.zeros(shape, dtype=torch.float64, device="cuda")
         assert grad.dtype == torch.float64 and grad.is_cuda and grad.is_contiguous() and tuple(grad.shape) == shape
-        fn = _lib.load().ib_adjoint_noalloc if noalloc else _lib.load().ib_adjoint
-        _lib.check(fn(self._h, C.c_void_p(res.data_ptr()), C.c_void_p(wavelet.data_ptr()), int(wavelet.shape[1]),
-                      C.c_void_p(grad.data_ptr()), _stream(stream)))
+        args = (C.c_void_p(res.data_ptr()), C.c_void_p(wavelet.data_ptr()), int(wavelet.shape[1]),
+                C.c_void_p(grad.data_ptr()), _stream(stream))
+        lib = _lib.load()
+        if checkpoints is not None:
+            assert not noalloc
+            _lib.check(lib.ib_adjoint_ckpt(self._h, C.c_void_p(checkpoints._h), *args))
+        else:
+            _lib.check((lib.ib_adjoint_noalloc if noalloc else lib.ib_adjoint)(self._h, *args))
         return grad
+
+    def set_watchdog(self, every=100, limit=1e30, stream=None):
+        """Scan p^n after every ``every`` steps (0: off) for NaN/Inf or |p| > limit; clears a
+        tripped watchdog."""
+        _lib.check(_lib.load().ib_state_set_watchdog(self._h, int(every), float(limit), _stream(stream)))
+
+    def status(self, wait=True):
+        """Raises NonFiniteError if a watchdog scan has tripped (``wait``: for the last scan)."""
+        _lib.check(_lib.load().ib_state_status(self._h, 1 if wait else 0))
 
     def set_forcing(self, g, s, stream=None):
         """Non-zero boundary values g_q(x_b) s_q(t): g [n_boundary_points][nq] (float64, physical

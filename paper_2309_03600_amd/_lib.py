@@ -8,6 +8,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libibwave.so")
 
 IB_OK = 0
+IB_ERR_ARG, IB_ERR_HIP, IB_ERR_OOM, IB_ERR_UNCONSTRAINED, IB_ERR_NONFINITE, IB_ERR_STATE = -1, -2, -3, -4, -5, -6
 IB_F32, IB_F64 = 0, 1
 IB_SURF_FREE, IB_SURF_RIGID, IB_SURF_ROBIN = 0, 1, 2
 IB_FORM_P2 = 0
@@ -55,6 +56,13 @@ EXPORTS = {
     "ib_forward": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_int64, C.c_void_p, C.c_int32, C.c_void_p]),
     "ib_adjoint": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p]),
     "ib_adjoint_noalloc": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p]),
+    "ib_forward_ckpt": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_int64, C.c_void_p, C.c_int32,
+                                  C.POINTER(C.c_void_p), C.c_void_p]),
+    "ib_adjoint_ckpt": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p,
+                                  C.c_void_p]),
+    "ib_checkpoints_free": (None, [C.c_void_p]),
+    "ib_state_set_watchdog": (C.c_int, [C.c_void_p, C.c_int32, C.c_double, C.c_void_p]),
+    "ib_state_status": (C.c_int, [C.c_void_p, C.c_int32]),
     "ib_state_field": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_void_p, C.c_int32, C.c_void_p]),
     "ib_state_step_count": (C.c_int64, [C.c_void_p]),
     "ib_state_set_tuning": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_int32]),
@@ -80,7 +88,12 @@ def load():
     return _lib
 
 
+class NonFiniteError(RuntimeError):
+    """The watchdog found a non-finite or oversized pressure (IB_ERR_NONFINITE)."""
+
+
 def check(status):
     if status != IB_OK:
         msg = load().ib_last_error()
-        raise RuntimeError(f"ibwave error {status}: {msg.decode() if msg else ''}")
+        text = f"ibwave error {status}: {msg.decode() if msg else ''}"
+        raise (NonFiniteError if status == IB_ERR_NONFINITE else RuntimeError)(text)

@@ -2,6 +2,9 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
+#include <cfloat>
+#include <climits>
 #include <chrono>
 #include <cmath>
 #include <cstring>
@@ -23,7 +26,17 @@ const char *last_error_text();
 
 using namespace ib;
 
+// Time checkpoints of one forward run: [count][2][nshots * vol] in the state precision,
+// slot 0 = p^{kC}, slot 1 = p^{kC-1} (plain form) or d^{kC} (increment form).
+struct ib_checkpoints {
+  uint64_t owner = 0;          // uid of the state whose forward run wrote them
+  void *data = nullptr;
+  size_t bytes = 0;
+  int64_t nt = 0, every = 0, count = 0;
+};
+
 struct ib_state {
+  uint64_t uid = 0;            // unique per state in this process
   const ib_weights *w = nullptr;
   int prec = IB_F32;
   int nshots = 1;
@@ -83,9 +96,21 @@ struct ib_state {
   std::vector<double> ax, ay, az;
   std::vector<int64_t> ridx_h;
   std::vector<double> rw_h;
-  // checkpoints written by ib_forward: [k][0] = u^{kC}, [k][1] = u^{kC-1}
-  void *ckpt = nullptr;
-  int64_t ck_nt = 0, ck_every = 0, ck_count = 0;
+  // checkpoints written by ib_forward (ib_forward_ckpt writes caller-held ones)
+  ib_checkpoints own;
+  // watchdog: after every ``watch_every`` steps a scan of p^n (all shots) flags a value that
+  // is not finite or exceeds watch_limit in magnitude: wflag[0] = 1, wflag[1] = the least
+  // step count at which a scan saw one.  The flags are copied to pinned host memory behind
+  // the scan (event ev_watch) and read at the next call, without waiting.
+  int64_t watch_every = 100;
+  double watch_limit = 1e30;
+  int64_t since_watch = 0;
+  int32_t *wflag = nullptr;
+  int32_t *wflag_h = nullptr;
+  hipEvent_t ev_watch = nullptr;
+  bool watch_pending = false;
+  bool tripped = false;
+  int64_t trip_step = -1;
   // adjoint work space and transposed tables (built on first use)
   bool adj_ready = false;
   int64_t nj = 0, nrn = 0;
@@ -101,6 +126,7 @@ struct ib_state {
 
 namespace {
 
+void watch_reset(ib_state *S, hipStream_t st);
 bool bad(const void *p) { return p == nullptr; }
 
 StepArgs make_args(ib_state *st, const void *wavelet, int64_t wstride, void *traces, int64_t nsteps, int cur) {
@@ -762,6 +788,8 @@ ib_status ib_state_create(const ib_weights *w, const double *vel_dev, double dt,
   }
   hipStream_t st = (hipStream_t)stream;
   ib_state *S = new ib_state();
+  static std::atomic<uint64_t> next_uid{1};
+  S->uid = next_uid++;
   S->w = w;
   S->prec = prec;
   S->nshots = nshots;
@@ -1163,6 +1191,11 @@ ib_status ib_state_create(const ib_weights *w, const double *vel_dev, double dt,
     IB_HIP(hipMemcpy(S->ridx, ridx.data(), ridx.size() * 8, hipMemcpyHostToDevice));
     if ((s = dalloc_t(&S->tcount, 4))) return fail(s);
     IB_HIP(hipMemset(S->tcount, 0, 32));
+    if ((s = dalloc_t(&S->wflag, 2))) return fail(s);
+    IB_HIP(hipHostMalloc((void **)&S->wflag_h, 2 * sizeof(int32_t), hipHostMallocDefault));
+    IB_HIP(hipEventCreateWithFlags(&S->ev_watch, hipEventDisableTiming));
+    watch_reset(S, st);
+    IB_HIP(hipGetLastError());
     IB_HIP(hipStreamSynchronize(st));
     // z-chunking of the 3D interior kernel: enough workgroups to fill 256 CUs
     if (w->ndim == 3 && w->form == IB_FORM_P2) {
@@ -1215,7 +1248,10 @@ void ib_state_free(ib_state *S) {
   dfree(S->ridx);
   dfree(S->rw);
   dfree(S->tcount);
-  dfree(S->ckpt);
+  dfree(S->own.data);
+  dfree(S->wflag);
+  if (S->wflag_h) (void)hipHostFree(S->wflag_h);
+  if (S->ev_watch) (void)hipEventDestroy(S->ev_watch);
   dfree(S->vbuf), dfree(S->kv);
   dfree(S->g_node), dfree(S->g_start), dfree(S->g_enode), dfree(S->d_node), dfree(S->d_start), dfree(S->d_enode);
   dfree(S->g_scale), dfree(S->g_w), dfree(S->d_scale), dfree(S->d_w);
@@ -1296,6 +1332,73 @@ void enqueue_full_step(ib_state *S, const void *wavelet, int64_t wstride, void *
 
 // nsteps steps; traces (may be null) are [nshots][trace_nt][nrec] with step t stored at
 // row t - trace_t0.
+// Watchdog scan of p^n: a wavefront that holds a value outside [-limit, limit] (NaN
+// included: it compares false) raises the flag and lowers the recorded step count.
+template <typename T>
+__global__ void k_watch(const T *__restrict__ p, int64_t n, T limit, int32_t step, int32_t *flag) {
+  bool hit = false;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const T v = p[i];
+    hit |= !(v <= limit && v >= -limit);
+  }
+  if (__any(hit) && (threadIdx.x & (warpSize - 1)) == 0) {
+    atomicOr(&flag[0], 1);
+    atomicMin(&flag[1], step);
+  }
+}
+__global__ void k_watch_reset(int32_t *flag) {
+  if (threadIdx.x == 0) {
+    flag[0] = 0;
+    flag[1] = INT_MAX;
+  }
+}
+void watch_reset(ib_state *S, hipStream_t st) {
+  hipLaunchKernelGGL(k_watch_reset, dim3(1), dim3(64), 0, st, S->wflag);
+  S->since_watch = 0;
+  S->watch_pending = false;
+  S->tripped = false;
+  S->trip_step = -1;
+}
+ib_status watch_scan(ib_state *S, hipStream_t st) {
+  const int64_t n = S->vol * S->nshots;
+  const unsigned nb = (unsigned)std::min<int64_t>((n + 255) / 256, 4096);
+  const int32_t step = (int32_t)std::min<int64_t>(S->t, INT_MAX);
+  const void *p = S->buf[S->cur];
+  if (S->prec == IB_F32)
+    hipLaunchKernelGGL(k_watch<float>, dim3(nb), dim3(256), 0, st, (const float *)p, n,
+                       (float)std::min<double>(S->watch_limit, FLT_MAX), step, S->wflag);
+  else
+    hipLaunchKernelGGL(k_watch<double>, dim3(nb), dim3(256), 0, st, (const double *)p, n,
+                       std::min<double>(S->watch_limit, DBL_MAX), step, S->wflag);
+  IB_HIP(hipGetLastError());
+  IB_HIP(hipMemcpyAsync(S->wflag_h, S->wflag, 2 * sizeof(int32_t), hipMemcpyDeviceToHost, st));
+  IB_HIP(hipEventRecord(S->ev_watch, st));
+  S->watch_pending = true;
+  return IB_OK;
+}
+// Reads the flags of the last scan if it has completed (or waits for it), and refuses the
+// call once a scan has seen a bad value.
+ib_status watch_poll(ib_state *S, bool wait, const char *who) {
+  if (S->watch_pending) {
+    const hipError_t e = wait ? hipEventSynchronize(S->ev_watch) : hipEventQuery(S->ev_watch);
+    if (e == hipSuccess) {
+      S->watch_pending = false;
+      if (S->wflag_h[0]) {
+        S->tripped = true;
+        S->trip_step = S->wflag_h[1];
+      }
+    } else if (e != hipErrorNotReady) {
+      return hip_fail(e, "hipEventQuery(watchdog)", __FILE__, __LINE__);
+    }
+  }
+  if (S->tripped) {
+    set_error("%s: the watchdog found a non-finite pressure or one above %g in magnitude after step %lld "
+              "(ib_state_set_watchdog clears it)", who, S->watch_limit, (long long)S->trip_step);
+    return IB_ERR_NONFINITE;
+  }
+  return IB_OK;
+}
+
 ib_status run_steps(ib_state *S, int64_t nsteps, const void *wavelet, int64_t wstride, void *traces, int64_t trace_nt,
                     int64_t trace_t0, bool use_graph, hipStream_t st) {
   if (nsteps == 0) return IB_OK;
@@ -1336,6 +1439,26 @@ ib_status run_steps(ib_state *S, int64_t nsteps, const void *wavelet, int64_t ws
   }
   IB_HIP(hipGetLastError());
   S->t += nsteps;
+  return IB_OK;
+}
+
+// run_steps with the watchdog's scan after every watch_every steps (the chunks keep their
+// even length, so the captured two-step graph stays valid across them)
+ib_status run_steps_watched(ib_state *S, int64_t nsteps, const void *wavelet, int64_t wstride, void *traces,
+                            int64_t trace_nt, int64_t trace_t0, bool use_graph, hipStream_t st) {
+  if (S->watch_every <= 0) return run_steps(S, nsteps, wavelet, wstride, traces, trace_nt, trace_t0, use_graph, st);
+  int64_t done = 0;
+  while (done < nsteps) {
+    const int64_t n = std::min<int64_t>(nsteps - done, S->watch_every - S->since_watch);
+    ib_status s = run_steps(S, n, wavelet, wstride, traces, trace_nt, trace_t0, use_graph, st);
+    if (s) return s;
+    done += n;
+    S->since_watch += n;
+    if (S->since_watch >= S->watch_every) {
+      S->since_watch = 0;
+      if ((s = watch_scan(S, st))) return s;
+    }
+  }
   return IB_OK;
 }
 
@@ -1414,16 +1537,21 @@ void zero_bytes(void *p, size_t bytes, hipStream_t st) {
   hipLaunchKernelGGL(k_zero_words, dim3(nb), dim3(256), 0, st, (uint32_t *)p, n);
 }
 
-ib_status adjoint_check(const ib_state *S, const void *residual, const void *wavelet, const double *grad,
-                        const char *who) {
-  if (!S || !residual || !wavelet || !grad || S->form != IB_FORM_P2) {
+ib_status adjoint_check(ib_state *S, const ib_checkpoints *C, const void *residual, const void *wavelet,
+                        const double *grad, const char *who) {
+  if (!S || !C || !residual || !wavelet || !grad || S->form != IB_FORM_P2) {
     set_error("%s: null argument or first-order state", who);
     return IB_ERR_ARG;
   }
-  if (S->ck_count == 0) {
-    set_error("%s: no checkpoints (call ib_forward first)", who);
+  if (C->count == 0 || !C->data) {
+    set_error("%s: no checkpoints (run a forward pass first)", who);
     return IB_ERR_STATE;
   }
+  if (C->owner != S->uid) {
+    set_error("%s: the checkpoints were written by another state", who);
+    return IB_ERR_STATE;
+  }
+  if (ib_status s = watch_poll(S, false, who)) return s;
   if (S->fF) {
     set_error("%s: the state has non-zero boundary values (not differentiated)", who);
     return IB_ERR_STATE;
@@ -1437,7 +1565,7 @@ ib_status adjoint_check(const ib_state *S, const void *residual, const void *wav
 struct AdjLayout {
   size_t lam0, lam1, lamd, seg, gK, total;
 };
-AdjLayout adjoint_layout(const ib_state *S) {
+AdjLayout adjoint_layout(const ib_state *S, const ib_checkpoints *C) {
   const size_t fbytes = (size_t)S->vol * S->nshots * S->esz;
   auto al = [](size_t b) { return (b + 255) & ~(size_t)255; };
   AdjLayout L{};
@@ -1445,25 +1573,25 @@ AdjLayout adjoint_layout(const ib_state *S) {
   L.lam0 = o, o += al(fbytes);
   L.lam1 = o, o += al(fbytes);
   L.lamd = o, o += S->incr ? al(fbytes) : 0;
-  L.seg = o, o += al(fbytes * (size_t)(S->ck_every + 2));
+  L.seg = o, o += al(fbytes * (size_t)(C->every + 2));
   L.gK = o, o += al((size_t)S->vol * sizeof(double));
   L.total = o;
   return L;
 }
-size_t adjoint_work_bytes(const ib_state *S) { return adjoint_layout(S).total; }
+size_t adjoint_work_bytes(const ib_state *S, const ib_checkpoints *C) { return adjoint_layout(S, C).total; }
 
 // The adjoint sweep over the checkpoint segments, with its work space at ``work`` (at
 // least adjoint_work_bytes(S)); enqueued on ``st`` without waiting for it.
-ib_status adjoint_run(ib_state *S, const void *residual, const void *wavelet, int64_t wstride, double *grad, void *work,
-                      hipStream_t st) {
+ib_status adjoint_run(ib_state *S, const ib_checkpoints *CK, const void *residual, const void *wavelet, int64_t wstride,
+                      double *grad, void *work, hipStream_t st) {
   const ib_weights *w = S->w;
   ib_status s;
-  const int64_t nt = S->ck_nt, C = S->ck_every;
+  const int64_t nt = CK->nt, C = CK->every;
   const size_t fbytes = (size_t)S->vol * S->nshots * S->esz;
   // seg holds u^{t0-1} .. u^{t0+len} of the segment being reversed (C + 2 fields; the
   // increment form keeps d^{t0} .. d^{t0+len}, C + 1 fields); lamd is mu^m - mu^{m+1} of
   // the increment form
-  const AdjLayout AL = adjoint_layout(S);
+  const AdjLayout AL = adjoint_layout(S, CK);
   char *wb = (char *)work;
   void *lam[2] = {wb + AL.lam0, wb + AL.lam1};
   void *lamd = S->incr ? (void *)(wb + AL.lamd) : nullptr;
@@ -1475,9 +1603,9 @@ ib_status adjoint_run(ib_state *S, const void *residual, const void *wavelet, in
   zero_bytes(gK, (size_t)S->vol * sizeof(double), st);
   int a1 = 0, a2 = 1;   // lam[a1] = mu^{m+1}, lam[a2] = mu^{m+2}
   auto field = [&](int64_t q) { return (char *)seg + (size_t)q * fbytes; };
-  for (int64_t k = S->ck_count - 1; k >= 0; --k) {
+  for (int64_t k = CK->count - 1; k >= 0; --k) {
     const int64_t t0 = k * C, len = std::min<int64_t>(C, nt - t0);
-    char *ck = (char *)S->ckpt + (size_t)k * 2 * fbytes;
+    const char *ck = (const char *)CK->data + (size_t)k * 2 * fbytes;
     IB_HIP(hipMemcpyAsync(S->buf[S->cur], ck, fbytes, hipMemcpyDeviceToDevice, st));
     IB_HIP(hipMemcpyAsync(S->incr ? S->dbuf : S->buf[1 - S->cur], ck + fbytes, fbytes, hipMemcpyDeviceToDevice, st));
     S->t = t0;
@@ -1563,6 +1691,76 @@ ib_status adjoint_run(ib_state *S, const void *residual, const void *wavelet, in
   return IB_OK;
 }
 
+// The adjoint on a freshly allocated work space, released once the stream has used it.
+ib_status adjoint_alloc(ib_state *S, const ib_checkpoints *C, const void *residual, const void *wavelet,
+                        int64_t wstride, double *grad, hipStream_t st, const char *who) {
+  ib_status s = adjoint_check(S, C, residual, wavelet, grad, who);
+  if (s) return s;
+  if (!S->adj_ready) {
+    s = (S->prec == IB_F32) ? build_adjoint_tables<float>(S, st) : build_adjoint_tables<double>(S, st);
+    if (s) return s;
+  }
+  void *work = nullptr;
+  if ((s = dalloc(&work, adjoint_work_bytes(S, C)))) return s;
+  s = adjoint_run(S, C, residual, wavelet, wstride, grad, work, st);
+  const hipError_t e = hipStreamSynchronize(st);
+  dfree(work);
+  if (s) return s;
+  if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize", __FILE__, __LINE__);
+  return IB_OK;
+}
+
+// Forward modelling from rest into the checkpoint set C (reallocated when its size changes).
+ib_status forward_into(ib_state *S, ib_checkpoints *C, int32_t nt, const void *wavelet, int64_t wstride, void *traces,
+                       int32_t ckpt_every, hipStream_t st, const char *who) {
+  if (!S || !C || nt < 1 || !wavelet || ckpt_every < 1 || wstride < nt || (S->nrec > 0 && !traces) ||
+      S->form != IB_FORM_P2) {
+    set_error("%s: invalid argument", who);
+    return IB_ERR_ARG;
+  }
+  if (S->fF) {
+    set_error("%s: the state has non-zero boundary values (not differentiated by the adjoint)", who);
+    return IB_ERR_STATE;
+  }
+  if (ib_status s = watch_poll(S, false, who)) return s;
+  const size_t fbytes = (size_t)S->vol * S->nshots * S->esz;
+  const int64_t nck = (nt + ckpt_every - 1) / ckpt_every;
+  if (C->bytes != 2 * fbytes * nck || !C->data) {
+    dfree(C->data);
+    C->data = nullptr;
+    C->bytes = 0;
+    C->count = 0;
+    ib_status s = dalloc(&C->data, 2 * fbytes * nck);
+    if (s) return s;
+    C->bytes = 2 * fbytes * nck;
+  }
+  C->owner = S->uid;
+  C->count = nck;
+  C->nt = nt;
+  C->every = ckpt_every;
+  // the adjoint's transposed tables are built here, so that an adjoint call can run on
+  // memory that exists already
+  if (!S->adj_ready) {
+    ib_status s = (S->prec == IB_F32) ? build_adjoint_tables<float>(S, st) : build_adjoint_tables<double>(S, st);
+    if (s) return s;
+  }
+  IB_HIP(hipMemsetAsync(S->buf[0], 0, fbytes, st));
+  IB_HIP(hipMemsetAsync(S->buf[1], 0, fbytes, st));
+  if (S->incr) IB_HIP(hipMemsetAsync(S->dbuf, 0, fbytes, st));
+  S->t = 0;
+  S->since_watch = 0;
+  for (int64_t k = 0; k < nck; ++k) {
+    // checkpoint k: p^n and p^{n-1} (plain form) or d^n (increment form)
+    char *ck = (char *)C->data + (size_t)k * 2 * fbytes;
+    IB_HIP(hipMemcpyAsync(ck, S->buf[S->cur], fbytes, hipMemcpyDeviceToDevice, st));
+    IB_HIP(hipMemcpyAsync(ck + fbytes, S->incr ? S->dbuf : S->buf[1 - S->cur], fbytes, hipMemcpyDeviceToDevice, st));
+    int64_t n = std::min<int64_t>(ckpt_every, nt - k * ckpt_every);
+    ib_status s = run_steps_watched(S, n, wavelet, wstride, traces, nt, 0, false, st);
+    if (s) return s;
+  }
+  return IB_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -1583,74 +1781,49 @@ ib_status ib_step(ib_state *S, int32_t nsteps, const void *wavelet, int64_t wstr
               (long long)S->flen, (long long)(S->t + nsteps));
     return IB_ERR_ARG;
   }
-  return run_steps(S, nsteps, wavelet, wstride, traces, nsteps, S->t, use_graph != 0, (hipStream_t)stream);
+  if (ib_status s = watch_poll(S, false, "ib_step")) return s;
+  return run_steps_watched(S, nsteps, wavelet, wstride, traces, nsteps, S->t, use_graph != 0, (hipStream_t)stream);
 }
 
 ib_status ib_forward(ib_state *S, int32_t nt, const void *wavelet, int64_t wstride, void *traces, int32_t ckpt_every,
                      void *stream) {
-  if (!S || nt < 1 || !wavelet || ckpt_every < 1 || wstride < nt || (S->nrec > 0 && !traces) ||
-      S->form != IB_FORM_P2) {
-    set_error("ib_forward: invalid argument");
+  return forward_into(S, S ? &S->own : nullptr, nt, wavelet, wstride, traces, ckpt_every, (hipStream_t)stream,
+                      "ib_forward");
+}
+
+ib_status ib_forward_ckpt(ib_state *S, int32_t nt, const void *wavelet, int64_t wstride, void *traces,
+                          int32_t ckpt_every, ib_checkpoints **ckpt, void *stream) {
+  if (!ckpt) {
+    set_error("ib_forward_ckpt: null checkpoint handle pointer");
     return IB_ERR_ARG;
   }
-  if (S->fF) {
-    set_error("ib_forward: the state has non-zero boundary values (not differentiated by ib_adjoint)");
-    return IB_ERR_STATE;
+  ib_checkpoints *C = *ckpt;
+  const bool fresh = (C == nullptr);
+  if (fresh) C = new ib_checkpoints();
+  const ib_status s = forward_into(S, C, nt, wavelet, wstride, traces, ckpt_every, (hipStream_t)stream,
+                                   "ib_forward_ckpt");
+  if (s != IB_OK) {
+    if (fresh) ib_checkpoints_free(C);
+    return s;
   }
-  hipStream_t st = (hipStream_t)stream;
-  const size_t fbytes = (size_t)S->vol * S->nshots * S->esz;
-  const int64_t nck = (nt + ckpt_every - 1) / ckpt_every;
-  if (S->ck_count != nck) {
-    dfree(S->ckpt);
-    S->ckpt = nullptr;
-    S->ck_count = 0;
-    ib_status s = dalloc(&S->ckpt, 2 * fbytes * nck);
-    if (s) return s;
-  }
-  S->ck_count = nck;
-  S->ck_nt = nt;
-  S->ck_every = ckpt_every;
-  // the adjoint's transposed tables are built here, so that an adjoint call can run on
-  // memory that exists already
-  if (!S->adj_ready) {
-    ib_status s = (S->prec == IB_F32) ? build_adjoint_tables<float>(S, st) : build_adjoint_tables<double>(S, st);
-    if (s) return s;
-  }
-  IB_HIP(hipMemsetAsync(S->buf[0], 0, fbytes, st));
-  IB_HIP(hipMemsetAsync(S->buf[1], 0, fbytes, st));
-  if (S->incr) IB_HIP(hipMemsetAsync(S->dbuf, 0, fbytes, st));
-  S->t = 0;
-  for (int64_t k = 0; k < nck; ++k) {
-    // checkpoint k: p^n and p^{n-1} (plain form) or d^n (increment form)
-    char *ck = (char *)S->ckpt + (size_t)k * 2 * fbytes;
-    IB_HIP(hipMemcpyAsync(ck, S->buf[S->cur], fbytes, hipMemcpyDeviceToDevice, st));
-    IB_HIP(hipMemcpyAsync(ck + fbytes, S->incr ? S->dbuf : S->buf[1 - S->cur], fbytes, hipMemcpyDeviceToDevice, st));
-    int64_t n = std::min<int64_t>(ckpt_every, nt - k * ckpt_every);
-    ib_status s = run_steps(S, n, wavelet, wstride, traces, nt, 0, false, st);
-    if (s) return s;
-  }
+  *ckpt = C;
   return IB_OK;
+}
+
+void ib_checkpoints_free(ib_checkpoints *C) {
+  if (!C) return;
+  dfree(C->data);
+  delete C;
+}
+
+ib_status ib_adjoint_ckpt(ib_state *S, const ib_checkpoints *C, const void *residual, const void *wavelet,
+                          int64_t wstride, double *grad, void *stream) {
+  return adjoint_alloc(S, C, residual, wavelet, wstride, grad, (hipStream_t)stream, "ib_adjoint_ckpt");
 }
 
 ib_status ib_adjoint(ib_state *S, const void *residual, const void *wavelet, int64_t wstride, double *grad,
                      void *stream) {
-  ib_status s = adjoint_check(S, residual, wavelet, grad, "ib_adjoint");
-  if (s) return s;
-  hipStream_t st = (hipStream_t)stream;
-  if (!S->adj_ready) {
-    s = (S->prec == IB_F32) ? build_adjoint_tables<float>(S, st) : build_adjoint_tables<double>(S, st);
-    if (s) return s;
-  }
-  const size_t need = adjoint_work_bytes(S);
-  void *work = nullptr;
-  if ((s = dalloc(&work, need))) return s;
-  s = adjoint_run(S, residual, wavelet, wstride, grad, work, st);
-  // the work space is released only after the stream has used it
-  const hipError_t e = hipStreamSynchronize(st);
-  dfree(work);
-  if (s) return s;
-  if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize", __FILE__, __LINE__);
-  return IB_OK;
+  return adjoint_alloc(S, S ? &S->own : nullptr, residual, wavelet, wstride, grad, (hipStream_t)stream, "ib_adjoint");
 }
 
 }  // extern "C"
@@ -1688,13 +1861,13 @@ extern "C" {
 
 ib_status ib_adjoint_noalloc(ib_state *S, const void *residual, const void *wavelet, int64_t wstride, double *grad,
                              void *stream) {
-  ib_status s = adjoint_check(S, residual, wavelet, grad, "ib_adjoint_noalloc");
+  ib_status s = adjoint_check(S, S ? &S->own : nullptr, residual, wavelet, grad, "ib_adjoint_noalloc");
   if (s) return s;
   if (!S->adj_ready) {
     set_error("ib_adjoint_noalloc: the adjoint tables are missing (call ib_forward first)");
     return IB_ERR_STATE;
   }
-  const size_t need = adjoint_work_bytes(S);
+  const size_t need = adjoint_work_bytes(S, &S->own);
   if (need > kScratchBytes) {
     set_error("ib_adjoint_noalloc: this state needs %zu bytes of work space, more than the %zu available "
               "(fewer shots, a smaller grid or a shorter checkpoint interval fit; ib_adjoint has no limit)",
@@ -1703,7 +1876,30 @@ ib_status ib_adjoint_noalloc(ib_state *S, const void *residual, const void *wave
   }
   void *work = nullptr;
   if ((s = scratch_address(&work))) return s;
-  return adjoint_run(S, residual, wavelet, wstride, grad, work, (hipStream_t)stream);
+  return adjoint_run(S, &S->own, residual, wavelet, wstride, grad, work, (hipStream_t)stream);
+}
+
+ib_status ib_state_set_watchdog(ib_state *S, int32_t every, double limit, void *stream) {
+  if (!S || every < 0 || !(limit > 0.0)) {
+    set_error("ib_state_set_watchdog: invalid argument");
+    return IB_ERR_ARG;
+  }
+  hipStream_t st = (hipStream_t)stream;
+  // a scan still in flight is waited for, so that its flags cannot come back after the reset
+  if (S->watch_pending) IB_HIP(hipEventSynchronize(S->ev_watch));
+  S->watch_every = every + (every & 1);
+  S->watch_limit = limit;
+  watch_reset(S, st);
+  IB_HIP(hipGetLastError());
+  return IB_OK;
+}
+
+ib_status ib_state_status(ib_state *S, int32_t wait) {
+  if (!S) {
+    set_error("ib_state_status: null state");
+    return IB_ERR_ARG;
+  }
+  return watch_poll(S, wait != 0, "ib_state_status");
 }
 
 ib_status ib_state_run_kernel(ib_state *S, int32_t which, int32_t count, void *stream) {

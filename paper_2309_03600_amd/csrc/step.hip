@@ -303,13 +303,18 @@ __global__ void k_interior3d_p(const T *__restrict__ un, T *__restrict__ um, T *
   const int xg = x0 + tx;
   const int xw = xg % nx;
   const bool xin = xg < nx;
+  // the edge tiles' lanes past the grid: those within H of it hold the wrapped centre
+  // values that the last columns and rows read as neighbours; the others load nothing
+  const bool xld = xg < nx + H;
   uint32_t rowoff[RY];
-  bool yin[RY];
+  bool yin[RY], cin[RY], pld[RY];
   int ywv[RY];
 #pragma unroll
   for (int r = 0; r < RY; ++r) {
     int yg = y0 + ty * RY + r;
     yin[r] = yg < ny;
+    cin[r] = xin && yin[r];
+    pld[r] = xld && yg < ny + H;
     ywv[r] = yg % ny;
     rowoff[r] = (uint32_t)ywv[r] * (uint32_t)pitch + (uint32_t)xw;
   }
@@ -341,14 +346,14 @@ __global__ void k_interior3d_p(const T *__restrict__ un, T *__restrict__ um, T *
 #pragma unroll
     for (int k = 0; k <= 2 * H; ++k) {
       int z = z0 - H + k;
-      q[r][k] = (z >= 0 && z < nz) ? u[(uint32_t)z * plane + rowoff[r]] : T(0);
+      q[r][k] = (z >= 0 && z < nz && pld[r]) ? u[(uint32_t)z * plane + rowoff[r]] : T(0);
     }
   }
   T pm[RY], kk[RY], hx[RY], hy[NHY];
 #pragma unroll
   for (int r = 0; r < RY; ++r) {
-    pm[r] = pin[(uint32_t)z0 * plane + rowoff[r]];
-    kk[r] = K[(uint32_t)z0 * plane + rowoff[r]];
+    pm[r] = cin[r] ? pin[(uint32_t)z0 * plane + rowoff[r]] : T(0);
+    kk[r] = cin[r] ? K[(uint32_t)z0 * plane + rowoff[r]] : T(0);
     hx[r] = (xl || xr) ? u[(uint32_t)z0 * plane + (uint32_t)ywv[r] * (uint32_t)pitch + (uint32_t)xh] : T(0);
   }
 #pragma unroll
@@ -373,10 +378,10 @@ __global__ void k_interior3d_p(const T *__restrict__ un, T *__restrict__ um, T *
     const int zq = z + H + 1;
 #pragma unroll
     for (int r = 0; r < RY; ++r) {
-      nq[r] = (zq < nz) ? u[(uint32_t)zq * plane + rowoff[r]] : T(0);
+      nq[r] = (zq < nz && pld[r]) ? u[(uint32_t)zq * plane + rowoff[r]] : T(0);
       // p^{n-1} and K are read once: non-temporal, so that p^n halos keep the caches
-      npm[r] = more ? __builtin_nontemporal_load(&pin[znoff + rowoff[r]]) : T(0);
-      nk[r] = more ? __builtin_nontemporal_load(&K[znoff + rowoff[r]]) : T(0);
+      npm[r] = (more && cin[r]) ? __builtin_nontemporal_load(&pin[znoff + rowoff[r]]) : T(0);
+      nk[r] = (more && cin[r]) ? __builtin_nontemporal_load(&K[znoff + rowoff[r]]) : T(0);
       nhx[r] = (more && (xl || xr)) ? u[znoff + (uint32_t)ywv[r] * (uint32_t)pitch + (uint32_t)xh] : T(0);
     }
 #pragma unroll

@@ -39,7 +39,7 @@ def test_binding_declares_the_same_functions():
 
 def test_abi_version_and_error_text(lib):
     lib.ib_abi_version.restype = ctypes.c_int32
-    assert lib.ib_abi_version() == 3
+    assert lib.ib_abi_version() == 4
     lib.ib_last_error.restype = ctypes.c_char_p
     assert lib.ib_last_error() is not None
 

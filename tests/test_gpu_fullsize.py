@@ -45,13 +45,18 @@ def test_config3_sampled_points_match_oracle():
     N = nx * ny * nz
     rng = np.random.default_rng([2309, 3, 11])
     nib = len(ex["ib_nodes"])
-    pick = np.sort(rng.choice(nib, 48, replace=False))
+    rng_pick = np.sort(rng.choice(nib, 48, replace=False))
+    pick = rng_pick
     # plus points whose support grew past the first radius (the gather kernel's points)
     wide = np.flatnonzero(ex["ib_meta"][:, 0] > 0)[:16]
-    pick = np.union1d(pick, wide)
+    # and the 16 worst-conditioned systems (smallest sigma_min / sigma_max), where the
+    # seminormal solve is most likely to part from the pseudo-inverse
+    worst_cond = np.argsort(ex["sigma"])[:16]
+    pick = np.union1d(np.union1d(pick, wide), worst_cond)
     nodes = ex["ib_nodes"][pick]
     pts = np.stack([nodes % nx, (nodes // nx) % ny, nodes // (nx * ny)], 1)
-    print(f"[config3] oracle solves of {len(pts)} sampled IB points ({len(wide)} with a grown support)", flush=True)
+    print(f"[config3] oracle solves of {len(pts)} sampled IB points ({len(wide)} with a grown support, 16 with "
+          f"sigma ratio <= {ex['sigma'][worst_cond].max():.3g})", flush=True)
     res = pool_map(window_task, [(wl.heights, wl.h, nz, wl.M, wl.surface, wl.eta, tuple(p)) for p in pts])
     worst = 0.0
     for j, (s, _) in zip(pick, res):
@@ -61,7 +66,9 @@ def test_config3_sampled_points_match_oracle():
         err = np.abs(ex["weights"][off:off + nw] - yo).max() / max(1.0, np.abs(yo).max())
         tol = max(1e-11, s["cond"] * 1e-12)           # as for the small cases
         worst = max(worst, err / tol)
-        assert err <= tol
+        assert err <= tol, (j, s["cond"], err)
+        if j in worst_cond:
+            print(f"[config3] point {j}: cond {s['cond']:.3g}, weight error {err:.2e}", flush=True)
     print(f"[config3] sampled weights: worst error / tolerance {worst:.3f}", flush=True)
     # one step from random fields, checked at the sampled IB points and at sampled
     # interior nodes off the boundary
@@ -86,6 +93,11 @@ def test_config3_sampled_points_match_oracle():
                 qq = (g[2] * ny + g[1] % ny) * nx + g[0] % nx
                 row[qq] = row.get(qq, 0.0) + w2[kk + half]
         rows.append(row)
+    # the one-step check covers the random and grown-support points; at the worst-conditioned
+    # ones the step's result differs from the oracle's by the weights' own difference
+    # (about cond * 1e-15, checked above), which the step's 1e-11 bound is not meant to absorb
+    keep = ~np.isin(pick, np.setdiff1d(worst_cond, np.union1d(np.sort(rng_pick), wide)))
+    nodes, rows = nodes[keep], [r for r, k in zip(rows, keep) if k] + rows[len(pick):]
     check = np.concatenate([nodes, others])
     g = torch.Generator(device="cuda")
     g.manual_seed(2309)
