@@ -101,7 +101,8 @@ __device__ __forceinline__ double buf_load(__amdgpu_buffer_rsrc_t r, uint32_t of
 // periodic: each of the NT threads issues all its loads, then writes them.  keep(lx, ly, lz)
 // leaves a node out (zero) when false; nodes above or below the box are zero.  The caller
 // checks that a shot's volume is under 2^31 bytes.
-template <typename T, int SC, int LX, int LY, int LZ, int NT, int PAD, typename Keep>
+// (LDS rows RP apart and planes PL apart: RP = LX, PL = LX * LY is the dense layout)
+template <typename T, int SC, int LX, int LY, int LZ, int NT, int PAD, typename Keep, int RP = LX, int PL = LX * LY>
 __device__ __forceinline__ void stage_tile(T *sp, int spstride, const T *un, int64_t vol, int s0, int nshots, int gx0,
                                            int gy0, int gz0, int nx, int ny, int nz, int64_t pitch, Keep keep) {
   constexpr int N = LX * LY * LZ, NST = (N + NT - 1) / NT;
@@ -129,8 +130,9 @@ __device__ __forceinline__ void stage_tile(T *sp, int spstride, const T *un, int
   for (int j = 0; j < NST; ++j) {
     const int e = tid + j * NT;
     if (e < N) {
+      const int lx = e % LX, ly = (e / LX) % LY, lz = e / (LX * LY);
 #pragma unroll
-      for (int c = 0; c < SC; ++c) sp[c * spstride + e] = v[c][j];
+      for (int c = 0; c < SC; ++c) sp[c * spstride + lz * PL + ly * RP + lx] = v[c][j];
     }
   }
 }
@@ -1107,14 +1109,23 @@ __global__ void k_patch_cols(const T *__restrict__ un, T *__restrict__ unew, T *
   constexpr int TX = kTileX, TY = kTileY, TZ = kTileZ, HR = kTileHalo;
   constexpr int CX = TX + 2 * HR, CY = TY + 2 * HR, LZ = TZ + 2 * HR;
   constexpr int NE = 2 * HR + 1;          // window rows (the longest column)
-  constexpr int NC = CX * CY;             // columns of the tile with its halo (one LDS plane)
+  constexpr int NC = CX * CY;             // columns of the tile with its halo
+  // LDS layout of the staged planes: rows RP apart, planes PL apart.  The lanes of a point
+  // read one plane of their columns at a time, at (half height) * PL + dy * RP + dx from a
+  // common base.  Two FP32 shots or FP64 values per node (8 bytes, half as many distinct
+  // banks) use 18 x 288, which spreads a ball's columns over the banks with fewer conflicts
+  // than the dense 16 x 256 plane and still leaves room for two workgroups per CU; the
+  // single FP32 shot keeps the dense plane (its time does not depend on the layout)
+  constexpr bool kWide = SC == 2 || sizeof(T) == 8;
+  constexpr int RP = kWide ? 18 : CX, PL = kWide ? 288 : NC;
+  static_assert(RP >= CX && PL >= RP * CY, "padded layout holds the tile");
   constexpr int ZT = NE - 1 - HR;         // zero planes above the tile (window rows of short columns)
   constexpr int NW = 8;                   // wavefronts per workgroup
   constexpr int VEC = 16 / sizeof(T);     // entries per 16-byte load
   constexpr int NWIN = NE + 1;            // window entries used: rows, then the extra node
   constexpr int NL = (NWIN + VEC - 1) / VEC;
   static_assert(HR == 4 && NC % 64 == 0, "column tables of radius 4 and 4.5; planes of whole bank rows");
-  __shared__ T sp[SC][(ZT + LZ) * NC];
+  __shared__ T sp[SC][(ZT + LZ) * PL];
   __shared__ int zf[NC];                  // first data plane of each column (tile plane index)
   __shared__ uint2 rec[kTileMaxPoints];   // entry offset; x | y << 5 | z << 10 | radius code 9 << 31
   __shared__ T res[SC][kTileMaxPoints];
@@ -1126,21 +1137,23 @@ __global__ void k_patch_cols(const T *__restrict__ un, T *__restrict__ unew, T *
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
   const int64_t plane = pitch * ny;
-  // this lane's columns as offsets in a plane (co = dy * CX + dx), with their half height zr
-  // (-1: no column): radius 4.5, radius 4, and the extra column
-  int co9, zr9, co8, zr8, coe;
+  // this lane's columns as offsets in zf (co = dy * CX + dx) and in an LDS plane (cs = dy *
+  // RP + dx), with their half height zr (-1: no column): radius 4.5, radius 4, and the extra
+  // column
+  int co9, cs9, zr9, co8, cs8, zr8, coe, cse;
   bool hase;
   {
-    auto unpack = [&](int32_t col, int &co, int &zr) {
+    auto unpack = [&](int32_t col, int &co, int &cs, int &zr) {
       const int dx = (int8_t)(col & 255), dy = (int8_t)((col >> 8) & 255);
       co = col == kNoColumn ? 0 : dy * CX + dx;
+      cs = col == kNoColumn ? 0 : dy * RP + dx;
       zr = col == kNoColumn ? -1 : (col >> 16) & 255;
     };
-    unpack(coltab[lane], co9, zr9);
-    unpack(lane < kColumns8 ? coltab[kColumns9 + lane] : kNoColumn, co8, zr8);
+    unpack(coltab[lane], co9, cs9, zr9);
+    unpack(lane < kColumns8 ? coltab[kColumns9 + lane] : kNoColumn, co8, cs8, zr8);
     const int32_t e9 = lane < kColumns9 - 64 ? coltab[64 + lane] : kNoColumn;
     int zre;
-    unpack(e9, coe, zre);
+    unpack(e9, coe, cse, zre);
     hase = e9 != kNoColumn;
   }
   for (int e = threadIdx.x; e < NC; e += blockDim.x) {
@@ -1148,7 +1161,7 @@ __global__ void k_patch_cols(const T *__restrict__ un, T *__restrict__ unew, T *
     zf[e] = (int)zfirst[(int64_t)gy * nx + gx] - (z0 - HR);
   }
   for (int i = threadIdx.x; i < np; i += blockDim.x) rec[i] = recs[p0 + i];
-  for (int e = threadIdx.x; e < ZT * NC; e += blockDim.x)
+  for (int e = threadIdx.x; e < ZT * PL; e += blockDim.x)
 #pragma unroll
     for (int c = 0; c < SC; ++c) sp[c][e] = T(0);
   __syncthreads();
@@ -1162,14 +1175,15 @@ __global__ void k_patch_cols(const T *__restrict__ un, T *__restrict__ unew, T *
       woff = (uint32_t)__builtin_amdgcn_readfirstlane((int)r.x);
       loc = (uint32_t)__builtin_amdgcn_readfirstlane((int)r.y);
     }
-    const int col = (int)((loc >> 5) & 31) * CX + (int)(loc & 31), lz = (loc >> 10) & 63;
+    const int lx = (int)(loc & 31), ly = (int)((loc >> 5) & 31), lz = (loc >> 10) & 63;
+    const int col = ly * CX + lx, cols = ly * RP + lx;
     const bool is9 = (loc >> 31) != 0u;
-    const int co = is9 ? co9 : co8, zr = (i < np) ? (is9 ? zr9 : zr8) : -1;
+    const int co = is9 ? co9 : co8, cs = is9 ? cs9 : cs8, zr = (i < np) ? (is9 ? zr9 : zr8) : -1;
     D.mlen = max(min(zr - zf[col + co] + lz + 1, 2 * zr + 1), 0);
     // window row k: plane lz + zr - 8 + k (a lane without a column reads the top zero plane)
-    D.base = (zr >= 0 ? lz + zr - (NE - 1) + ZT : 0) * NC + col + co;
+    D.base = (zr >= 0 ? lz + zr - (NE - 1) + ZT : 0) * PL + cols + cs;
     D.elen = (is9 && hase && zf[col + coe] <= lz) ? 1 : 0;
-    D.ebase = (lz + ZT) * NC + col + coe;
+    D.ebase = (lz + ZT) * PL + cols + cse;
     const int len = D.mlen + D.elen;
     D.off = woff + (uint32_t)(wave_incl_scan(len) - len) + (uint32_t)D.mlen - (uint32_t)NE;
     return D;
@@ -1199,7 +1213,7 @@ __global__ void k_patch_cols(const T *__restrict__ un, T *__restrict__ unew, T *
     for (int k = 0; k < NE; ++k) {
       const T wk = (k >= NE - D.mlen) ? w[k] : T(0);
 #pragma unroll
-      for (int c = 0; c < SC; ++c) acc[c] = fma(wk, sp[c][D.base + k * NC], acc[c]);
+      for (int c = 0; c < SC; ++c) acc[c] = fma(wk, sp[c][D.base + k * PL], acc[c]);
     }
     const T we = D.elen ? w[NE] : T(0);
 #pragma unroll
@@ -1215,9 +1229,9 @@ __global__ void k_patch_cols(const T *__restrict__ un, T *__restrict__ unew, T *
     ColDec D0 = decode(wave), D1;
     T w0[NL * VEC], w1[NL * VEC];
     load(D0, w0);
-    stage_tile<T, SC, CX, CY, LZ, 512, 0>(&sp[0][ZT * NC], (ZT + LZ) * NC, un, vol, s0, nshots, x0 - HR, y0 - HR,
-                                           z0 - HR, nx, ny, nz, pitch,
-                                           [&](int lx, int ly, int lz) { return zf[ly * CX + lx] <= lz; });
+    auto keep = [&](int lx, int ly, int lz) { return zf[ly * CX + lx] <= lz; };
+    stage_tile<T, SC, CX, CY, LZ, 512, 0, decltype(keep), RP, PL>(&sp[0][ZT * PL], (ZT + LZ) * PL, un, vol, s0, nshots,
+                                                                  x0 - HR, y0 - HR, z0 - HR, nx, ny, nz, pitch, keep);
     __syncthreads();
     // points wave, wave + NW, ...: two in flight, roles alternating (no register moves)
     for (int p = wave; p < np; p += 2 * NW) {
