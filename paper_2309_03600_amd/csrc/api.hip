@@ -126,6 +126,16 @@ struct ib_state {
 
 namespace {
 
+// frees a temporary device buffer on every way out of its scope
+template <typename P>
+struct FreeOnExit {
+  P *&p;
+  ~FreeOnExit() {
+    dfree(p);
+    p = nullptr;
+  }
+};
+
 void watch_reset(ib_state *S, hipStream_t st);
 bool bad(const void *p) { return p == nullptr; }
 
@@ -840,6 +850,7 @@ ib_status ib_state_create(const ib_weights *w, const double *vel_dev, double dt,
     std::vector<double> ay = (w->ndim == 3) ? damping_axis(w->ny, damp_width, dmax, dt, true) : std::vector<double>(1, 0.0);
     std::vector<double> az = damping_axis(w->nz, damp_width, dmax, dt, false);
     double *d_ax = nullptr, *d_ay = nullptr, *d_az = nullptr;
+    FreeOnExit<double> free_ax{d_ax}, free_ay{d_ay}, free_az{d_az};
     if ((s = dalloc_t(&d_ax, ax.size())) || (s = dalloc_t(&d_ay, ay.size())) || (s = dalloc_t(&d_az, az.size())))
       return fail(s);
     IB_HIP(hipMemcpy(d_ax, ax.data(), ax.size() * 8, hipMemcpyHostToDevice));
@@ -1008,6 +1019,7 @@ ib_status ib_state_create(const ib_weights *w, const double *vel_dev, double dt,
           IB_HIP(hipEventCreateWithFlags(&S->ev_join, hipEventDisableTiming));
         }
         int32_t *d_perm = nullptr;
+        FreeOnExit<int32_t> free_perm{d_perm};
         if ((s = dalloc(&S->pinfo_t, std::max<size_t>(tiled.size(), 1) * pinfo_dense_bytes(prec))) ||
             (s = dalloc(&S->pinfo_w, std::max<size_t>(wide.size(), 1) * pinfo_bytes(prec))) ||
             (s = dalloc(&S->pinfo_tm, std::max<size_t>(tiled.size(), 1) * pinfo_bytes(prec))) ||
@@ -1055,13 +1067,11 @@ ib_status ib_state_create(const ib_weights *w, const double *vel_dev, double dt,
           enqueue_make_pinfo(prec, w->ib_xyz, ro, S->scale, d_perm, (int64_t)wide.size(), S->pinfo_w, st);
           IB_HIP(hipStreamSynchronize(st));
         }
-        dfree(d_perm);
       }
       enqueue_make_delta(w->ball, (int)w->balls.packed.size(), S->pitch, S->pitch * w->ny, S->delta, st);
       IB_HIP(hipGetLastError());
     }
     IB_HIP(hipStreamSynchronize(st));
-    dfree(d_ax), dfree(d_ay), dfree(d_az);
     // sources: interior corners only; amplitude factor dt^2 w / (h^d (1 + s))
     std::vector<uint8_t> cls(w->N);
     IB_HIP(hipMemcpy(cls.data(), w->node_class, w->N, hipMemcpyDeviceToHost));
@@ -1330,8 +1340,6 @@ void enqueue_full_step(ib_state *S, const void *wavelet, int64_t wstride, void *
   }
 }
 
-// nsteps steps; traces (may be null) are [nshots][trace_nt][nrec] with step t stored at
-// row t - trace_t0.
 // Watchdog scan of p^n: a wavefront that holds a value outside [-limit, limit] (NaN
 // included: it compares false) raises the flag and lowers the recorded step count.
 template <typename T>
@@ -1399,6 +1407,8 @@ ib_status watch_poll(ib_state *S, bool wait, const char *who) {
   return IB_OK;
 }
 
+// nsteps steps; traces (may be null) are [nshots][trace_nt][nrec] with step t stored at
+// row t - trace_t0.
 ib_status run_steps(ib_state *S, int64_t nsteps, const void *wavelet, int64_t wstride, void *traces, int64_t trace_nt,
                     int64_t trace_t0, bool use_graph, hipStream_t st) {
   if (nsteps == 0) return IB_OK;

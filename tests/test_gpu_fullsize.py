@@ -284,6 +284,7 @@ def test_config5_exclusion_cutoff_keeps_the_rigid_surface_stable():
         print(f"[config5 stability] eta={eta}", flush=True)
         w = ib.ib_build_weights(wl.heights, wl.h, wl.shape, space_order=wl.M, surface=wl.surface, eta=eta)
         st = ib.ib_state_create(w, wl.vel, wl.dt, wl.src[5:6], wl.rec, damp_width=wl.damp_width, precision="f32")
+        st.set_watchdog(every=0)            # the growth is what this test measures
         tr = st.step(nt, wav, use_graph=True).double().cpu().numpy()[0]
         st.close()
         norms[eta] = [float(np.linalg.norm(tr[a:a + 500])) for a in range(0, nt, 500)]
