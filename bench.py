@@ -46,12 +46,13 @@ def log(*a):
 
 KERNELS = {"interior": "k_interior3d_p", "patch": "k_patch_cols"}
 TRAFFIC_FILE = "hbm_traffic_interior_patch_config3.json"
+# (OUT: any output folder)
 PROFILE_CMDS = [
-    "rocprofv3 --pmc FETCH_SIZE --output-format csv -d gpurun_out/prof_f -o f -- "
+    "rocprofv3 --pmc FETCH_SIZE --output-format csv -d OUT/prof_f -o f -- "
     "python3 bench.py --steps 20 --warmup 5 --no-cpu --no-accuracy --calibrate",
-    "rocprofv3 --pmc WRITE_SIZE --output-format csv -d gpurun_out/prof_w -o w -- "
+    "rocprofv3 --pmc WRITE_SIZE --output-format csv -d OUT/prof_w -o w -- "
     "python3 bench.py --steps 20 --warmup 5 --no-cpu --no-accuracy --calibrate",
-    "python3 bench.py --summarize-counters gpurun_out/prof_f gpurun_out/prof_w",
+    "python3 bench.py --summarize-counters OUT/prof_f OUT/prof_w",
 ]
 CALIB_BYTES = 1 << 30
 
