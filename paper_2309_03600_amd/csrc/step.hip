@@ -276,7 +276,10 @@ __global__ void k_interior3d_p(const T *__restrict__ un, T *__restrict__ um, T *
   constexpr int TX = 64, TY = NW * RY, LX = TX + 2 * H, LY = TY + 2 * H;
   __shared__ T tile[2][LY][LX];
   const int64_t nblk = (int64_t)ntx * nty * nzc * nshots;
-  int64_t L = xcd_remap(blockIdx.x, gridDim.x);
+  // tiles in plain launch order, dealt round-robin to the XCDs: the XCD-aware order
+  // (xcd_remap), which keeps neighbouring tiles and their halos in one L2, raised the L2 hit
+  // rate from 24 % to 39 % but ran 5 % slower on the 401 x 401 x 301 workload
+  int64_t L = blockIdx.x;
   if (L >= nblk) return;
   const int bxi = (int)(L % ntx);
   L /= ntx;
