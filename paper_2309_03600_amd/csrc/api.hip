@@ -77,9 +77,10 @@ struct ib_state {
   int zchunk_auto = 0;
   int variant = 1;
   int patch_variant = 4;
-  // captured two-step graph
-  hipGraphExec_t gexec = nullptr;
-  hipGraph_t graph = nullptr;
+  // captured graphs of two steps and of kLongGraph steps (the same two-step sequence
+  // repeated: fewer launches, each of which costs several microseconds of idle device)
+  hipGraphExec_t gexec[2] = {nullptr, nullptr};
+  hipGraph_t graph[2] = {nullptr, nullptr};
   const void *g_wavelet = nullptr;
   void *g_traces = nullptr;
   int64_t g_wstride = 0, g_nsteps = 0;
@@ -123,6 +124,18 @@ struct ib_state {
   int fnq = 0;
   int64_t flen = 0;
 };
+
+// steps in the long captured graph (even: the two-step sequence repeated)
+constexpr int64_t kLongGraph = 16;
+
+static void drop_graphs(ib_state *S) {
+  for (int k = 0; k < 2; ++k) {
+    if (S->gexec[k]) (void)hipGraphExecDestroy(S->gexec[k]);
+    if (S->graph[k]) (void)hipGraphDestroy(S->graph[k]);
+    S->gexec[k] = nullptr;
+    S->graph[k] = nullptr;
+  }
+}
 
 namespace {
 
@@ -1229,8 +1242,7 @@ ib_status ib_state_create(const ib_weights *w, const double *vel_dev, double dt,
 
 void ib_state_free(ib_state *S) {
   if (!S) return;
-  if (S->gexec) (void)hipGraphExecDestroy(S->gexec);
-  if (S->graph) (void)hipGraphDestroy(S->graph);
+  drop_graphs(S);
   if (S->aux) (void)hipStreamDestroy(S->aux);
   if (S->ev_fork) (void)hipEventDestroy(S->ev_fork);
   if (S->ev_join) (void)hipEventDestroy(S->ev_join);
@@ -1282,12 +1294,7 @@ ib_status ib_state_set_tuning(ib_state *S, int32_t variant, int32_t zchunk, int3
   S->variant = variant;
   if (patch_variant >= 0) S->patch_variant = patch_variant;
   S->zchunk = zchunk > 0 ? zchunk : S->zchunk_auto;
-  if (S->gexec) {
-    (void)hipGraphExecDestroy(S->gexec);
-    (void)hipGraphDestroy(S->graph);
-    S->gexec = nullptr;
-    S->graph = nullptr;
-  }
+  drop_graphs(S);
   return IB_OK;
 }
 
@@ -1415,33 +1422,34 @@ ib_status run_steps(ib_state *S, int64_t nsteps, const void *wavelet, int64_t ws
   hipLaunchKernelGGL(k_set_counter, dim3(1), dim3(1), 0, st, S->tcount, S->t, trace_t0);
   int64_t done = 0;
   if (use_graph && nsteps >= 2) {
-    const bool reuse = S->gexec && S->g_wavelet == wavelet && S->g_traces == traces && S->g_wstride == wstride &&
+    const bool reuse = S->g_wavelet == wavelet && S->g_traces == traces && S->g_wstride == wstride &&
                        S->g_nsteps == trace_nt && S->g_cur == S->cur;
-    if (!reuse) {
-      if (S->gexec) {
-        (void)hipGraphExecDestroy(S->gexec);
-        (void)hipGraphDestroy(S->graph);
-        S->gexec = nullptr;
-        S->graph = nullptr;
-      }
-      hipStream_t cs;
-      IB_HIP(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
-      IB_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
-      for (int q = 0; q < 2; ++q) enqueue_full_step(S, wavelet, wstride, traces, trace_nt, (S->cur + q) & 1, cs);
-      hipError_t e = hipStreamEndCapture(cs, &S->graph);
-      if (e != hipSuccess) {
+    if (!reuse) drop_graphs(S);
+    // the long graph where the call covers it, then the two-step graph
+    const int64_t len[2] = {2, kLongGraph};
+    for (int k = 1; k >= 0; --k) {
+      if (nsteps - done < len[k]) continue;
+      if (!S->gexec[k]) {
+        hipStream_t cs;
+        IB_HIP(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+        IB_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+        for (int64_t q = 0; q < len[k]; ++q)
+          enqueue_full_step(S, wavelet, wstride, traces, trace_nt, (int)((S->cur + q) & 1), cs);
+        hipError_t e = hipStreamEndCapture(cs, &S->graph[k]);
+        if (e != hipSuccess) {
+          (void)hipStreamDestroy(cs);
+          return hip_fail(e, "hipStreamEndCapture", __FILE__, __LINE__);
+        }
         (void)hipStreamDestroy(cs);
-        return hip_fail(e, "hipStreamEndCapture", __FILE__, __LINE__);
+        IB_HIP(hipGraphInstantiate(&S->gexec[k], S->graph[k], nullptr, nullptr, 0));
+        S->g_wavelet = wavelet;
+        S->g_traces = traces;
+        S->g_wstride = wstride;
+        S->g_nsteps = trace_nt;
+        S->g_cur = S->cur;
       }
-      (void)hipStreamDestroy(cs);
-      IB_HIP(hipGraphInstantiate(&S->gexec, S->graph, nullptr, nullptr, 0));
-      S->g_wavelet = wavelet;
-      S->g_traces = traces;
-      S->g_wstride = wstride;
-      S->g_nsteps = trace_nt;
-      S->g_cur = S->cur;
+      for (; done + len[k] <= nsteps; done += len[k]) IB_HIP(hipGraphLaunch(S->gexec[k], st));
     }
-    for (; done + 2 <= nsteps; done += 2) IB_HIP(hipGraphLaunch(S->gexec, st));
   }
   for (; done < nsteps; ++done) {
     enqueue_full_step(S, wavelet, wstride, traces, trace_nt, S->cur, st);
@@ -1945,12 +1953,7 @@ ib_status ib_state_set_forcing(ib_state *S, const double *g, int32_t nq, const d
   }
   hipStream_t st = (hipStream_t)stream;
   // the captured graph holds the old pointers
-  if (S->gexec) {
-    (void)hipGraphExecDestroy(S->gexec);
-    (void)hipGraphDestroy(S->graph);
-    S->gexec = nullptr;
-    S->graph = nullptr;
-  }
+  drop_graphs(S);
   if (!g) {
     IB_HIP(hipStreamSynchronize(st));
     dfree(S->fF), dfree(S->fs);

@@ -544,17 +544,14 @@ __device__ __forceinline__ void patch_group(const T *__restrict__ u, const T *__
   for (int k = 0; k < G; ++k) acc += wv[k] * pv[k];
 }
 
+// point i of pinfo on one wavefront (every lane of it active)
 template <typename T>
-__launch_bounds__(256)
-__global__ void k_patch(const T *__restrict__ un, T *__restrict__ unew, T *__restrict__ dd,
-                        const uint32_t *__restrict__ rec,
-                        const PInfo<T> *__restrict__ pinfo, const int32_t *__restrict__ ball,
-                        const int32_t *__restrict__ delta, const int32_t *__restrict__ ball_meta, int64_t nib,
-                        int nx, int ny, int nz, int64_t pitch, int64_t vol, int nshots) {
+__device__ __forceinline__ void gather_point(int64_t i, const T *__restrict__ un, T *__restrict__ unew,
+                                             T *__restrict__ dd, const uint32_t *__restrict__ rec,
+                                             const PInfo<T> *__restrict__ pinfo, const int32_t *__restrict__ ball,
+                                             const int32_t *__restrict__ delta, const int32_t *__restrict__ ball_meta,
+                                             int nx, int ny, int64_t pitch, int64_t vol, int nshots) {
   const int lane = threadIdx.x & 63;
-  const int64_t blk = xcd_remap(blockIdx.x, gridDim.x);
-  const int64_t i = blk * (blockDim.x >> 6) + (threadIdx.x >> 6);
-  if (i >= nib) return;
   const PInfo<T> P = pinfo[i];
   const int x = P.x, y = P.y, z = P.z, code = P.code;
   const int bstart = ball_meta[2 * code], nb = ball_meta[2 * code + 1];
@@ -583,6 +580,19 @@ __global__ void k_patch(const T *__restrict__ un, T *__restrict__ unew, T *__res
       if (dd) dd[(size_t)s * vol + centre] += v;
     }
   }
+}
+
+template <typename T>
+__launch_bounds__(256)
+__global__ void k_patch(const T *__restrict__ un, T *__restrict__ unew, T *__restrict__ dd,
+                        const uint32_t *__restrict__ rec,
+                        const PInfo<T> *__restrict__ pinfo, const int32_t *__restrict__ ball,
+                        const int32_t *__restrict__ delta, const int32_t *__restrict__ ball_meta, int64_t nib,
+                        int nx, int ny, int nz, int64_t pitch, int64_t vol, int nshots) {
+  const int64_t blk = xcd_remap(blockIdx.x, gridDim.x);
+  const int64_t i = blk * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  if (i >= nib) return;
+  gather_point<T>(i, un, unew, dd, rec, pinfo, ball, delta, ball_meta, nx, ny, pitch, vol, nshots);
 }
 
 // ---- IB patch, LDS-tiled (3D) -------------------------------------------------------
@@ -1108,7 +1118,17 @@ __global__ void k_patch_cols(const T *__restrict__ un, T *__restrict__ unew, T *
                              const T *__restrict__ wcol, const uint2 *__restrict__ recs, const T *__restrict__ scale,
                              const int16_t *__restrict__ zfirst, const int32_t *__restrict__ coltab,
                              const int4 *__restrict__ tiles, int ntiles, int nx, int ny, int nz, int64_t pitch,
-                             int64_t vol, int nshots) {
+                             int64_t vol, int nshots, const uint32_t *__restrict__ wrec,
+                             const PInfo<T> *__restrict__ wpinfo, const int32_t *__restrict__ ball,
+                             const int32_t *__restrict__ wdelta, const int32_t *__restrict__ ball_meta, int64_t nwide,
+                             int nwb) {
+  // the first nwb workgroups take the points of wider supports, one per wavefront, with the
+  // gather of k_patch; they start first, so their longer latency hides under the tiles
+  if ((int)blockIdx.x < nwb) {
+    const int64_t i = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    if (i < nwide) gather_point<T>(i, un, unew, dd, wrec, wpinfo, ball, wdelta, ball_meta, nx, ny, pitch, vol, nshots);
+    return;
+  }
   constexpr int TX = kTileX, TY = kTileY, TZ = kTileZ, HR = kTileHalo;
   constexpr int CX = TX + 2 * HR, CY = TY + 2 * HR, LZ = TZ + 2 * HR;
   constexpr int NE = 2 * HR + 1;          // window rows (the longest column)
@@ -1132,7 +1152,7 @@ __global__ void k_patch_cols(const T *__restrict__ un, T *__restrict__ unew, T *
   __shared__ int zf[NC];                  // first data plane of each column (tile plane index)
   __shared__ uint2 rec[kTileMaxPoints];   // entry offset; x | y << 5 | z << 10 | radius code 9 << 31
   __shared__ T res[SC][kTileMaxPoints];
-  const int64_t tb = xcd_remap(blockIdx.x, gridDim.x);
+  const int64_t tb = xcd_remap(blockIdx.x - nwb, gridDim.x - nwb);
   if (tb >= ntiles) return;
   const int4 tl = tiles[tb];
   const int x0 = tl.x, y0 = tl.y, z0 = tl.z;
@@ -1494,7 +1514,11 @@ static void launch_interior(const StepArgs &a, hipStream_t st) {
 
 template <typename T>
 static void launch_patch(const StepArgs &a, hipStream_t st) {
-  if (a.ntiles > 0 && a.nwide > 0 && a.aux != nullptr) (void)hipEventRecord(a.ev_fork, st);
+  // the column-run kernels take the wide points in their first workgroups; the other
+  // layouts leave them to the gather kernel, on the second stream beside them
+  const bool merged = a.ntiles > 0 && (a.patch_variant == 8 || a.patch_variant == 9);
+  const int nwb = merged ? (int)((a.nwide + 7) / 8) : 0;
+  if (!merged && a.ntiles > 0 && a.nwide > 0 && a.aux != nullptr) (void)hipEventRecord(a.ev_fork, st);
   if (a.ntiles > 0) {
     int64_t nblk = ((int64_t)a.ntiles + 7) / 8 * 8;
 #define IB_PATCH_TILED(PVV)                                                                                         \
@@ -1528,14 +1552,16 @@ static void launch_patch(const StepArgs &a, hipStream_t st) {
         if constexpr (sizeof(T) == 4) {
           two = a.patch_variant == 9 && a.nshots >= 2;
           if (two)
-            hipLaunchKernelGGL((k_patch_cols<T, 2>), dim3((unsigned)nblk), dim3(512), 0, st, (const T *)a.un,
+            hipLaunchKernelGGL((k_patch_cols<T, 2>), dim3((unsigned)(nblk + nwb)), dim3(512), 0, st, (const T *)a.un,
                                (T *)a.um, (T *)a.dd, (const T *)a.wcol, a.crec, (const T *)a.cscale, a.zfcol, a.coltab,
-                               a.tiles, a.ntiles, a.nx, a.ny, a.nz, a.pitch, a.vol, a.nshots);
+                               a.tiles, a.ntiles, a.nx, a.ny, a.nz, a.pitch, a.vol, a.nshots, a.rec,
+                               (const PInfo<T> *)a.pinfo_wide, a.ball, a.delta, a.ball_meta, a.nwide, nwb);
         }
         if (!two)
-          hipLaunchKernelGGL((k_patch_cols<T, 1>), dim3((unsigned)nblk), dim3(512), 0, st, (const T *)a.un, (T *)a.um,
-                             (T *)a.dd, (const T *)a.wcol, a.crec, (const T *)a.cscale, a.zfcol, a.coltab, a.tiles,
-                             a.ntiles, a.nx, a.ny, a.nz, a.pitch, a.vol, a.nshots);
+          hipLaunchKernelGGL((k_patch_cols<T, 1>), dim3((unsigned)(nblk + nwb)), dim3(512), 0, st, (const T *)a.un,
+                             (T *)a.um, (T *)a.dd, (const T *)a.wcol, a.crec, (const T *)a.cscale, a.zfcol, a.coltab,
+                             a.tiles, a.ntiles, a.nx, a.ny, a.nz, a.pitch, a.vol, a.nshots, a.rec,
+                             (const PInfo<T> *)a.pinfo_wide, a.ball, a.delta, a.ball_meta, a.nwide, nwb);
         break;
       }
       default:
@@ -1548,7 +1574,7 @@ static void launch_patch(const StepArgs &a, hipStream_t st) {
 #undef IB_PATCH_TILED
 #undef IB_PATCH_TILED_R
   }
-  if (a.nwide > 0) {
+  if (a.nwide > 0 && !merged) {
     // the few points with wider supports touch other nodes than the tiled points: their
     // gather kernel runs on the second stream, beside the tiled kernel
     const bool fork = a.ntiles > 0 && a.aux != nullptr;
