@@ -252,8 +252,9 @@ void ib_state_free(ib_state *st);
  *   p^{n+1}     = [(1 - s) p^n + (dt c^2 / h) D-.v^{n+1/2} + dt f^n] / (1 + s)  (interior p nodes)
  *   with the staggered M-th order differences and the immersed-boundary rows of both
  *   families; the traces sample p^{n+1}.
- * When use_graph is non-zero the per-step kernels are captured once into a HIP graph
- * (two steps, even/odd buffers) and replayed; results are identical to eager launch.
+ * When use_graph is non-zero the per-step kernels are captured into HIP graphs of two and
+ * of sixteen steps (even/odd buffers), replayed as the call's length allows (the rest is
+ * launched eagerly); results are identical to eager launch.
  * The watchdog (ib_state_set_watchdog) scans p^n after every ``every`` steps on the
  * stream; a scan that finds a bad value makes the next call on the state (this one's
  * successor, or ib_state_status) return IB_ERR_NONFINITE.
@@ -364,7 +365,7 @@ ib_status ib_state_set_forcing(ib_state *st, const double *g_dev, int32_t nq, co
  * steps or differentiates the state after it, until this function is called again.
  * Defaults: every = 100, limit = 1e30 (FP32 states cap it at the largest float).
  *   every: steps between scans, 0 turns the scans off; odd values are rounded up so that
- *     the scans fall between the two-step graph launches.
+ *     the scans fall between graph launches.
  *   limit > 0.
  * Waits for a scan still in flight, then clears the flags (on ``stream``).
  * Errors: IB_ERR_ARG. */
