@@ -77,6 +77,9 @@ struct ib_state {
   int zchunk_auto = 0;
   int variant = 1;
   int patch_variant = 4;
+  // sources injected and receivers sampled inside the column-run patch launch (no source
+  // node is an IB point)
+  bool io_merge = false;
   // captured graphs of two steps and of kLongGraph steps (the same two-step sequence
   // repeated: fewer launches, each of which costs several microseconds of idle device)
   hipGraphExec_t gexec[2] = {nullptr, nullptr};
@@ -203,6 +206,8 @@ StepArgs make_args(ib_state *st, const void *wavelet, int64_t wstride, void *tra
   a.wavelet = wavelet;
   a.wstride = wstride;
   a.tcount = st->tcount;
+  a.io_merge = st->io_merge ? 1 : 0;
+  a.sample_prev = 0;
   a.nrec = st->nrec;
   a.ridx = st->ridx;
   a.rw = st->rw;
@@ -292,6 +297,7 @@ __global__ void k_set_counter(int64_t *tc, int64_t t, int64_t t0) {
   tc[0] = t;
   tc[1] = t;
   tc[2] = t0;
+  tc[3] = 0;
 }
 
 std::vector<double> damping_axis(int64_t n, int width, double dmax, double dt, bool both) {
@@ -1164,6 +1170,9 @@ ib_status ib_state_create(const ib_weights *w, const double *vel_dev, double dt,
     std::vector<int64_t> sidx(nshots * 8, -1);
     std::vector<double> swv(nshots * 8, 0.0);
     const double hd = std::pow(w->h, w->ndim);
+    // the patch launch may carry the injection only where no source node is an IB point
+    // (whose patch row it would race with)
+    bool src_at_ib = false;
     for (int sh = 0; sh < nshots; ++sh) {
       int64_t idx[8], idu[8];
       double wt[8];
@@ -1178,12 +1187,14 @@ ib_status ib_state_create(const ib_weights *w, const double *vel_dev, double dt,
           set_error("source %d touches an exterior node", sh);
           return fail(IB_ERR_ARG);
         }
+        if (cls[idu[c]] & 4) src_at_ib = true;
         int64_t x = idu[c] % w->nx, y = (idu[c] / w->nx) % w->ny, z = idu[c] / (w->nx * w->ny);
         double sd = ax[x] + ay[(w->ndim == 3) ? y : 0] + az[z];
         sidx[sh * 8 + c] = idx[c];
         swv[sh * 8 + c] = (w->form == IB_FORM_PV1 ? dt : dt * dt) * wt[c] / (hd * (1.0 + sd));
       }
     }
+    S->io_merge = w->form == IB_FORM_P2 && w->ndim == 3 && !src_at_ib;
     if ((s = dalloc_t(&S->sidx, nshots * 8)) || (s = dalloc(&S->sw, nshots * 8 * S->esz))) return fail(s);
     IB_HIP(hipMemcpy(S->sidx, sidx.data(), nshots * 64, hipMemcpyHostToDevice));
     {
@@ -1335,16 +1346,26 @@ PVArgs make_pv_args(const ib_state *S) {
   return a;
 }
 
-// one full step of either form: operator update, source injection, receiver sampling
-void enqueue_full_step(ib_state *S, const void *wavelet, int64_t wstride, void *traces, int64_t trace_nt, int cur,
-                       hipStream_t st) {
+// one full step of either form: operator update, source injection, receiver sampling.
+// Where the column-run patch launch carries the io, the step's sampling is left to the next
+// step (sample_prev) or to flush_sample; returns whether it was.
+bool enqueue_full_step(ib_state *S, const void *wavelet, int64_t wstride, void *traces, int64_t trace_nt, int cur,
+                       hipStream_t st, bool sample_prev = false) {
   StepArgs a = make_args(S, wavelet, wstride, traces, trace_nt, cur);
   if (S->form == IB_FORM_PV1) {
     enqueue_pv_step(make_pv_args(S), st);
     enqueue_source_receivers(a, S->buf[0], st);
-  } else {
-    enqueue_step(a, st);
+    return false;
   }
+  a.sample_prev = sample_prev ? 1 : 0;
+  enqueue_step(a, st);
+  return step_samples_in_patch(a);
+}
+
+// the sampling left behind by the last step (its output is the field of parity cur)
+static void flush_sample(ib_state *S, void *traces, int64_t trace_nt, int cur, hipStream_t st) {
+  StepArgs a = make_args(S, nullptr, 0, traces, trace_nt, cur);
+  enqueue_sample(a, S->buf[cur], st);
 }
 
 // Watchdog scan of p^n: a wavefront that holds a value outside [-limit, limit] (NaN
@@ -1433,8 +1454,10 @@ ib_status run_steps(ib_state *S, int64_t nsteps, const void *wavelet, int64_t ws
         hipStream_t cs;
         IB_HIP(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
         IB_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+        bool pending = false;
         for (int64_t q = 0; q < len[k]; ++q)
-          enqueue_full_step(S, wavelet, wstride, traces, trace_nt, (int)((S->cur + q) & 1), cs);
+          pending = enqueue_full_step(S, wavelet, wstride, traces, trace_nt, (int)((S->cur + q) & 1), cs, pending);
+        if (pending) flush_sample(S, traces, trace_nt, S->cur, cs);
         hipError_t e = hipStreamEndCapture(cs, &S->graph[k]);
         if (e != hipSuccess) {
           (void)hipStreamDestroy(cs);
@@ -1451,10 +1474,12 @@ ib_status run_steps(ib_state *S, int64_t nsteps, const void *wavelet, int64_t ws
       for (; done + len[k] <= nsteps; done += len[k]) IB_HIP(hipGraphLaunch(S->gexec[k], st));
     }
   }
+  bool pending = false;
   for (; done < nsteps; ++done) {
-    enqueue_full_step(S, wavelet, wstride, traces, trace_nt, S->cur, st);
+    pending = enqueue_full_step(S, wavelet, wstride, traces, trace_nt, S->cur, st, pending);
     if (S->form == IB_FORM_P2) S->cur ^= 1;
   }
+  if (pending) flush_sample(S, traces, trace_nt, S->cur, st);
   IB_HIP(hipGetLastError());
   S->t += nsteps;
   return IB_OK;

@@ -54,6 +54,10 @@ struct StepArgs {
   // the tiled kernel (null: both on the step's stream)
   hipStream_t aux;
   hipEvent_t ev_fork, ev_join;
+  // io_merge: the column-run patch launch also injects this step's sources and samples the
+  // receivers for the step before (its p^n); the state allows it when no source node is an
+  // IB point and no boundary values are set.  sample_prev: this step samples the step before.
+  int io_merge, sample_prev;
   const int32_t *ball;
   const int32_t *delta;       // linear offsets of the ball lattice points for this layout
   const int32_t *ball_meta;   // [code][2]: start, count
@@ -62,7 +66,8 @@ struct StepArgs {
   const void *sw;
   const void *wavelet;
   int64_t wstride;
-  int64_t *tcount;      // device [0] next step, [1] step being sampled, [2] first step of the call
+  int64_t *tcount;      // device [0] next step, [1] step being sampled, [2] first step of the call,
+                        // [3] completion count of a patch launch that advances them (io_merge)
   int nrec;
   const int64_t *ridx;
   const void *rw;
@@ -78,6 +83,11 @@ struct StepArgs {
 };
 
 void enqueue_step(const StepArgs &a, hipStream_t st);
+// receiver sampling alone, of the field u, for the step tcount[1]
+void enqueue_sample(const StepArgs &a, const void *u, hipStream_t st);
+// whether enqueue_step leaves the sampling of its output to the next step's patch launch
+// (io_merge in effect for this state)
+bool step_samples_in_patch(const StepArgs &a);
 // source injection into u and receiver sampling of u (the sources/receivers fields of a)
 void enqueue_source_receivers(const StepArgs &a, void *u, hipStream_t st);
 

@@ -1107,28 +1107,49 @@ __global__ void k_patch_tiled_m(const T *__restrict__ un, T *__restrict__ unew, 
 // the table streams at HBM rate only if the wavefronts keep up.  Two points per
 // wavefront are in flight (the loads of one while the other is evaluated).  Staging skips
 // the nodes above each column's first data plane (their weights are all zero).
+// ---- sources and receivers (also run inside the column-run patch launch) -------------
+template <typename T>
+__device__ __forceinline__ void inject_sources(T *unew, T *dd, const int64_t *sidx, const T *sw, int nshots, int64_t vol,
+                                               const T *wavelet, int64_t wstride, int64_t t) {
+  for (int e = threadIdx.x; e < nshots * 8; e += blockDim.x) {
+    int s = e >> 3;
+    int64_t idx = sidx[e];
+    if (idx >= 0) {
+      const T v = mul_rn(wavelet[(size_t)s * wstride + t], sw[e]);
+      unew[(size_t)s * vol + idx] += v;
+      if (dd) dd[(size_t)s * vol + idx] += v;
+    }
+  }
+}
+
+// receiver e (shot e / nrec) of field u into trace row tl
+template <typename T>
+__device__ __forceinline__ void sample_receiver(const T *u0, const int64_t *ridx, const T *rw, int nrec, int64_t vol,
+                                                T *traces, int64_t nsteps, int64_t tl, int64_t e) {
+  const int s = (int)(e / nrec), r = (int)(e % nrec);
+  const T *u = u0 + (size_t)s * vol;
+  T v = T(0);
+#pragma unroll
+  for (int c = 0; c < 8; ++c) {
+    int64_t idx = ridx[(size_t)r * 8 + c];
+    if (idx >= 0) v += rw[(size_t)r * 8 + c] * u[idx];
+  }
+  traces[((size_t)s * nsteps + tl) * nrec + r] = v;
+}
+
 struct ColDec {
   int base, mlen, ebase, elen;  // LDS index of the window's first row, run length; extra node, 0/1
   uint32_t off;                 // entry of window row 0 (the run's first entry at row 9 - mlen)
 };
 
+// the points of tile tb (one 512-thread workgroup)
 template <typename T, int SC>
-__launch_bounds__(512)
-__global__ void k_patch_cols(const T *__restrict__ un, T *__restrict__ unew, T *__restrict__ dd,
-                             const T *__restrict__ wcol, const uint2 *__restrict__ recs, const T *__restrict__ scale,
-                             const int16_t *__restrict__ zfirst, const int32_t *__restrict__ coltab,
-                             const int4 *__restrict__ tiles, int ntiles, int nx, int ny, int nz, int64_t pitch,
-                             int64_t vol, int nshots, const uint32_t *__restrict__ wrec,
-                             const PInfo<T> *__restrict__ wpinfo, const int32_t *__restrict__ ball,
-                             const int32_t *__restrict__ wdelta, const int32_t *__restrict__ ball_meta, int64_t nwide,
-                             int nwb) {
-  // the first nwb workgroups take the points of wider supports, one per wavefront, with the
-  // gather of k_patch; they start first, so their longer latency hides under the tiles
-  if ((int)blockIdx.x < nwb) {
-    const int64_t i = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
-    if (i < nwide) gather_point<T>(i, un, unew, dd, wrec, wpinfo, ball, wdelta, ball_meta, nx, ny, pitch, vol, nshots);
-    return;
-  }
+__device__ __forceinline__ void patch_tile(int64_t tb, const T *__restrict__ un, T *__restrict__ unew,
+                                           T *__restrict__ dd, const T *__restrict__ wcol,
+                                           const uint2 *__restrict__ recs, const T *__restrict__ scale,
+                                           const int16_t *__restrict__ zfirst, const int32_t *__restrict__ coltab,
+                                           const int4 *__restrict__ tiles, int nx, int ny, int nz, int64_t pitch,
+                                           int64_t vol, int nshots) {
   constexpr int TX = kTileX, TY = kTileY, TZ = kTileZ, HR = kTileHalo;
   constexpr int CX = TX + 2 * HR, CY = TY + 2 * HR, LZ = TZ + 2 * HR;
   constexpr int NE = 2 * HR + 1;          // window rows (the longest column)
@@ -1152,8 +1173,6 @@ __global__ void k_patch_cols(const T *__restrict__ un, T *__restrict__ unew, T *
   __shared__ int zf[NC];                  // first data plane of each column (tile plane index)
   __shared__ uint2 rec[kTileMaxPoints];   // entry offset; x | y << 5 | z << 10 | radius code 9 << 31
   __shared__ T res[SC][kTileMaxPoints];
-  const int64_t tb = xcd_remap(blockIdx.x - nwb, gridDim.x - nwb);
-  if (tb >= ntiles) return;
   const int4 tl = tiles[tb];
   const int x0 = tl.x, y0 = tl.y, z0 = tl.z;
   const int p0 = tl.w, np = tiles[tb + 1].w - tl.w;
@@ -1284,6 +1303,69 @@ __global__ void k_patch_cols(const T *__restrict__ un, T *__restrict__ unew, T *
   }
 }
 
+// Source injection and receiver sampling carried by the column-run patch launch (nsb,
+// ninj = 0: none).  The sampling workgroups read p^n of this step for the step before it
+// (trace row tcount[1] - tcount[2]); the injection workgroup adds this step's sources
+// (tcount[0]); the last workgroup to finish advances the step counter, as k_inject does.
+template <typename T>
+struct PatchIo {
+  const int64_t *ridx;
+  const T *rw;
+  int nrec, nsb;          // receivers, sampling workgroups
+  T *traces;
+  int64_t nsteps;
+  const int64_t *sidx;
+  const T *sw, *wavelet;
+  int64_t wstride;
+  int ninj;               // injection workgroups (0 or 1)
+  int64_t *tcount;        // null: the launch leaves the counter alone
+};
+
+// The IB patch of the tiled points (column-run records), with in front of the tiles: the
+// points of wider supports (nwb workgroups, one point per wavefront, the gather of k_patch;
+// started first, their longer latency hides under the tiles), then the workgroups of io.
+template <typename T, int SC>
+__launch_bounds__(512)
+__global__ void k_patch_cols(const T *__restrict__ un, T *__restrict__ unew, T *__restrict__ dd,
+                             const T *__restrict__ wcol, const uint2 *__restrict__ recs, const T *__restrict__ scale,
+                             const int16_t *__restrict__ zfirst, const int32_t *__restrict__ coltab,
+                             const int4 *__restrict__ tiles, int ntiles, int nx, int ny, int nz, int64_t pitch,
+                             int64_t vol, int nshots, const uint32_t *__restrict__ wrec, const PInfo<T> *__restrict__ wpinfo,
+                             const int32_t *__restrict__ ball, const int32_t *__restrict__ wdelta,
+                             const int32_t *__restrict__ ball_meta, int64_t nwide, int nwb, PatchIo<T> io) {
+  const int b = (int)blockIdx.x, nsp = nwb + io.nsb + io.ninj;
+  if (b < nwb) {
+    const int64_t i = (int64_t)b * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    if (i < nwide) gather_point<T>(i, un, unew, dd, wrec, wpinfo, ball, wdelta, ball_meta, nx, ny, pitch, vol, nshots);
+  } else if (b < nwb + io.nsb) {
+    const int64_t e = (int64_t)(b - nwb) * blockDim.x + threadIdx.x;
+    if (e < (int64_t)io.nrec * nshots)
+      sample_receiver(un, io.ridx, io.rw, io.nrec, vol, io.traces, io.nsteps, io.tcount[1] - io.tcount[2], e);
+  } else if (b < nsp) {
+    inject_sources(unew, dd, io.sidx, io.sw, nshots, vol, io.wavelet, io.wstride, io.tcount[0]);
+  } else {
+    const int64_t tb = xcd_remap(b - nsp, gridDim.x - nsp);
+    if (tb < ntiles)
+      patch_tile<T, SC>(tb, un, unew, dd, wcol, recs, scale, zfirst, coltab, tiles, nx, ny, nz, pitch, vol, nshots);
+  }
+  if (io.tcount) {
+    // every read of the counter in this workgroup has returned (the barrier waits for them);
+    // the last workgroup to arrive advances it.  No fence: nothing written here is read by
+    // another workgroup of this launch (a device-scope fence would write back the L2 of
+    // each workgroup's XCD)
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      unsigned *done = reinterpret_cast<unsigned *>(io.tcount + 3);
+      if (atomicAdd(done, 1u) == gridDim.x - 1) {
+        const int64_t t = io.tcount[0];
+        io.tcount[1] = t;
+        io.tcount[0] = t + 1;
+        *done = 0u;
+      }
+    }
+  }
+}
+
 template <typename T>
 __global__ void k_make_pinfo_dense(const int16_t *xyz, const int32_t *first, const int32_t *count,
                                    const uint32_t *doff, const T *scale, const int32_t *perm, int64_t n,
@@ -1323,15 +1405,7 @@ template <typename T>
 __global__ void k_inject(T *unew, T *dd, const int64_t *sidx, const T *sw, int nshots, int64_t vol, const T *wavelet,
                          int64_t wstride, int64_t *tcount) {
   const int64_t t = tcount[0];
-  for (int e = threadIdx.x; e < nshots * 8; e += blockDim.x) {
-    int s = e >> 3;
-    int64_t idx = sidx[e];
-    if (idx >= 0) {
-      const T v = mul_rn(wavelet[(size_t)s * wstride + t], sw[e]);
-      unew[(size_t)s * vol + idx] += v;
-      if (dd) dd[(size_t)s * vol + idx] += v;
-    }
-  }
+  inject_sources(unew, dd, sidx, sw, nshots, vol, wavelet, wstride, t);
   __syncthreads();
   if (threadIdx.x == 0) {
     tcount[1] = t;
@@ -1344,16 +1418,7 @@ __global__ void k_sample(const T *unew, const int64_t *ridx, const T *rw, int nr
                          T *traces, int64_t nsteps, const int64_t *tcount) {
   int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= (int64_t)nrec * nshots) return;
-  const int s = (int)(e / nrec), r = (int)(e % nrec);
-  const int64_t tl = tcount[1] - tcount[2];
-  const T *u = unew + (size_t)s * vol;
-  T v = T(0);
-#pragma unroll
-  for (int c = 0; c < 8; ++c) {
-    int64_t idx = ridx[(size_t)r * 8 + c];
-    if (idx >= 0) v += rw[(size_t)r * 8 + c] * u[idx];
-  }
-  traces[((size_t)s * nsteps + tl) * nrec + r] = v;
+  sample_receiver(unew, ridx, rw, nrec, vol, traces, nsteps, tcount[1] - tcount[2], e);
 }
 
 // Source injection and receiver sampling in one workgroup, for few receivers: the
@@ -1513,7 +1578,7 @@ static void launch_interior(const StepArgs &a, hipStream_t st) {
 }
 
 template <typename T>
-static void launch_patch(const StepArgs &a, hipStream_t st) {
+static void launch_patch(const StepArgs &a, hipStream_t st, const PatchIo<T> *io_in = nullptr) {
   // the column-run kernels take the wide points in their first workgroups; the other
   // layouts leave them to the gather kernel, on the second stream beside them
   const bool merged = a.ntiles > 0 && (a.patch_variant == 8 || a.patch_variant == 9);
@@ -1549,19 +1614,21 @@ static void launch_patch(const StepArgs &a, hipStream_t st) {
         // two shots per pass in FP32 only (two FP64 tiles would not leave room for a second
         // workgroup per CU)
         bool two = false;
+        const PatchIo<T> io = io_in ? *io_in : PatchIo<T>{};
+        const unsigned grid = (unsigned)(nblk + nwb + io.nsb + io.ninj);
         if constexpr (sizeof(T) == 4) {
           two = a.patch_variant == 9 && a.nshots >= 2;
           if (two)
-            hipLaunchKernelGGL((k_patch_cols<T, 2>), dim3((unsigned)(nblk + nwb)), dim3(512), 0, st, (const T *)a.un,
-                               (T *)a.um, (T *)a.dd, (const T *)a.wcol, a.crec, (const T *)a.cscale, a.zfcol, a.coltab,
-                               a.tiles, a.ntiles, a.nx, a.ny, a.nz, a.pitch, a.vol, a.nshots, a.rec,
-                               (const PInfo<T> *)a.pinfo_wide, a.ball, a.delta, a.ball_meta, a.nwide, nwb);
+            hipLaunchKernelGGL((k_patch_cols<T, 2>), dim3(grid), dim3(512), 0, st, (const T *)a.un, (T *)a.um,
+                               (T *)a.dd, (const T *)a.wcol, a.crec, (const T *)a.cscale, a.zfcol, a.coltab, a.tiles,
+                               a.ntiles, a.nx, a.ny, a.nz, a.pitch, a.vol, a.nshots, a.rec, (const PInfo<T> *)a.pinfo_wide,
+                               a.ball, a.delta, a.ball_meta, a.nwide, nwb, io);
         }
         if (!two)
-          hipLaunchKernelGGL((k_patch_cols<T, 1>), dim3((unsigned)(nblk + nwb)), dim3(512), 0, st, (const T *)a.un,
-                             (T *)a.um, (T *)a.dd, (const T *)a.wcol, a.crec, (const T *)a.cscale, a.zfcol, a.coltab,
-                             a.tiles, a.ntiles, a.nx, a.ny, a.nz, a.pitch, a.vol, a.nshots, a.rec,
-                             (const PInfo<T> *)a.pinfo_wide, a.ball, a.delta, a.ball_meta, a.nwide, nwb);
+          hipLaunchKernelGGL((k_patch_cols<T, 1>), dim3(grid), dim3(512), 0, st, (const T *)a.un, (T *)a.um,
+                             (T *)a.dd, (const T *)a.wcol, a.crec, (const T *)a.cscale, a.zfcol, a.coltab, a.tiles,
+                             a.ntiles, a.nx, a.ny, a.nz, a.pitch, a.vol, a.nshots, a.rec, (const PInfo<T> *)a.pinfo_wide,
+                             a.ball, a.delta, a.ball_meta, a.nwide, nwb, io);
         break;
       }
       default:
@@ -1608,9 +1675,33 @@ static void launch_io(const StepArgs &a, T *u, hipStream_t st) {
   }
 }
 
+// whether the step's source injection and sampling ride in the column-run patch launch
+static bool io_in_patch(const StepArgs &a) {
+  return a.io_merge && !a.fF && a.ndim == 3 && a.ntiles > 0 && (a.patch_variant == 8 || a.patch_variant == 9);
+}
+
 template <typename T>
 static void launch_step(const StepArgs &a, hipStream_t st) {
   launch_interior<T>(a, st);
+  if (io_in_patch(a)) {
+    PatchIo<T> io{};
+    if (a.sample_prev && a.nrec > 0 && a.traces) {
+      io.ridx = a.ridx;
+      io.rw = (const T *)a.rw;
+      io.nrec = a.nrec;
+      io.nsb = (int)(((int64_t)a.nrec * a.nshots + 511) / 512);
+      io.traces = (T *)a.traces;
+      io.nsteps = a.nsteps;
+    }
+    io.sidx = a.sidx;
+    io.sw = (const T *)a.sw;
+    io.wavelet = (const T *)a.wavelet;
+    io.wstride = a.wstride;
+    io.ninj = 1;
+    io.tcount = a.tcount;
+    launch_patch<T>(a, st, &io);
+    return;
+  }
   launch_patch<T>(a, st);
   if (a.fF && a.nib > 0)
     hipLaunchKernelGGL(k_ib_forcing<T>, dim3((unsigned)((a.nib + 255) / 256)), dim3(256), 0, st, (T *)a.um,
@@ -1626,6 +1717,23 @@ void enqueue_source_receivers(const StepArgs &a, void *u, hipStream_t st) {
   else
     launch_io<double>(a, (double *)u, st);
 }
+
+template <typename T>
+static void launch_sample(const StepArgs &a, const T *u, hipStream_t st) {
+  if (!(a.nrec > 0 && a.traces)) return;
+  const int64_t tot = (int64_t)a.nrec * a.nshots;
+  hipLaunchKernelGGL(k_sample<T>, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, u, a.ridx, (const T *)a.rw,
+                     a.nrec, a.nshots, a.vol, (T *)a.traces, a.nsteps, (const int64_t *)a.tcount);
+}
+
+void enqueue_sample(const StepArgs &a, const void *u, hipStream_t st) {
+  if (a.prec == IB_F32)
+    launch_sample<float>(a, (const float *)u, st);
+  else
+    launch_sample<double>(a, (const double *)u, st);
+}
+
+bool step_samples_in_patch(const StepArgs &a) { return io_in_patch(a); }
 
 void enqueue_step(const StepArgs &a, hipStream_t st) {
   if (a.prec == IB_F32)

@@ -147,6 +147,43 @@ def test_traces_match_oracle(name, prec):
 
 
 @pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_source_at_an_ib_point_matches_oracle(prec):
+    """A source whose interpolation corners include an IB point.  Its injection cannot ride
+    in the patch launch (it would race with that point's patch row) and runs as a launch of
+    its own; traces against the oracle, eager and graph-replayed."""
+    import dataclasses
+
+    import torch
+
+    import paper_2309_03600_amd as ib
+    wl0, w, ex, m, sols = case("3d-m8-free")
+    nx, ny, nz = wl0.shape
+    cls = ex["node_class"].reshape(nz, ny, nx)
+    inter, ibp = (cls & 1).astype(bool), (cls & 4).astype(bool)
+    pick = None
+    for z in range(nz - 1):
+        for y in range(3, ny - 4):
+            for x in range(3, nx - 4):
+                cell = (slice(z, z + 2), slice(y, y + 2), slice(x, x + 2))
+                if pick is None and inter[cell].all() and ibp[cell].any():
+                    pick = (x, y, z)
+    assert pick is not None
+    x, y, z = pick
+    wl = dataclasses.replace(wl0, src=np.array([[(x + 0.5) * wl0.h, (y + 0.5) * wl0.h, (z + 0.5) * wl0.h]]))
+    print(f"[source at IB {prec}] cell {pick}", flush=True)
+    sim, _ = simulation(wl, m, sols)
+    ref = sim.run(wl.wavelets(np.float64), wl.nt)
+    dt = torch.float64 if prec == "f64" else torch.float32
+    wav = torch.tensor(wl.wavelets(np.float64), dtype=dt, device="cuda")
+    for graph in (False, True):
+        st = ib.ib_state_create(w, wl.vel, wl.dt, wl.src, wl.rec, damp_width=wl.damp_width, precision=prec)
+        tr = st.step(wl.nt, wav, use_graph=graph).double().cpu().numpy()[0]
+        e = rel_l2_per_trace(tr, ref)
+        print(f"[source at IB {prec} graph={graph}] per-trace rel-L2: max {e.max():.2e}", flush=True)
+        assert e.max() < (1e-9 if prec == "f64" else 1e-4)
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
 def test_graph_replay_matches_eager(prec):
     import torch
 
