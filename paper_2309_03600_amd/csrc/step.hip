@@ -544,6 +544,75 @@ __device__ __forceinline__ void patch_group(const T *__restrict__ u, const T *__
   for (int k = 0; k < G; ++k) acc += wv[k] * pv[k];
 }
 
+// ---- sources and receivers (also run inside the patch launches) ----------------------
+template <typename T>
+__device__ __forceinline__ void inject_sources(T *unew, T *dd, const int64_t *sidx, const T *sw, int nshots, int64_t vol,
+                                               const T *wavelet, int64_t wstride, int64_t t) {
+  for (int e = threadIdx.x; e < nshots * 8; e += blockDim.x) {
+    int s = e >> 3;
+    int64_t idx = sidx[e];
+    if (idx >= 0) {
+      const T v = mul_rn(wavelet[(size_t)s * wstride + t], sw[e]);
+      unew[(size_t)s * vol + idx] += v;
+      if (dd) dd[(size_t)s * vol + idx] += v;
+    }
+  }
+}
+
+// receiver e (shot e / nrec) of field u into trace row tl
+template <typename T>
+__device__ __forceinline__ void sample_receiver(const T *u0, const int64_t *ridx, const T *rw, int nrec, int64_t vol,
+                                                T *traces, int64_t nsteps, int64_t tl, int64_t e) {
+  const int s = (int)(e / nrec), r = (int)(e % nrec);
+  const T *u = u0 + (size_t)s * vol;
+  T v = T(0);
+#pragma unroll
+  for (int c = 0; c < 8; ++c) {
+    int64_t idx = ridx[(size_t)r * 8 + c];
+    if (idx >= 0) v += rw[(size_t)r * 8 + c] * u[idx];
+  }
+  traces[((size_t)s * nsteps + tl) * nrec + r] = v;
+}
+
+// Source injection and receiver sampling carried by the column-run patch launch (nsb,
+// ninj = 0: none).  The sampling workgroups read p^n of this step for the step before it
+// (trace row tcount[1] - tcount[2]); the injection workgroup adds this step's sources
+// (tcount[0]); the last workgroup to finish advances the step counter, as k_inject does.
+template <typename T>
+struct PatchIo {
+  const int64_t *ridx;
+  const T *rw;
+  int nrec, nsb;          // receivers, sampling workgroups (set by the launcher from nrs)
+  int64_t nrs;            // receiver-shots to sample (0: none)
+  T *traces;
+  int64_t nsteps;
+  const int64_t *sidx;
+  const T *sw, *wavelet;
+  int64_t wstride;
+  int ninj;               // injection workgroups (0 or 1)
+  int64_t *tcount;        // null: the launch leaves the counter alone
+};
+
+
+// the end of every workgroup of a launch that carries io: the last one advances the step
+// counter.  Every read of the counter in the workgroup has returned (the barrier waits for
+// them).  No fence: nothing written here is read by another workgroup of this launch (a
+// device-scope fence would write back the L2 of each workgroup's XCD)
+template <typename T>
+__device__ __forceinline__ void finish_io(const PatchIo<T> &io) {
+  if (!io.tcount) return;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    unsigned *done = reinterpret_cast<unsigned *>(io.tcount + 3);
+    if (atomicAdd(done, 1u) == gridDim.x - 1) {
+      const int64_t t = io.tcount[0];
+      io.tcount[1] = t;
+      io.tcount[0] = t + 1;
+      *done = 0u;
+    }
+  }
+}
+
 // point i of pinfo on one wavefront (every lane of it active)
 template <typename T>
 __device__ __forceinline__ void gather_point(int64_t i, const T *__restrict__ un, T *__restrict__ unew,
@@ -1107,36 +1176,6 @@ __global__ void k_patch_tiled_m(const T *__restrict__ un, T *__restrict__ unew, 
 // the table streams at HBM rate only if the wavefronts keep up.  Two points per
 // wavefront are in flight (the loads of one while the other is evaluated).  Staging skips
 // the nodes above each column's first data plane (their weights are all zero).
-// ---- sources and receivers (also run inside the column-run patch launch) -------------
-template <typename T>
-__device__ __forceinline__ void inject_sources(T *unew, T *dd, const int64_t *sidx, const T *sw, int nshots, int64_t vol,
-                                               const T *wavelet, int64_t wstride, int64_t t) {
-  for (int e = threadIdx.x; e < nshots * 8; e += blockDim.x) {
-    int s = e >> 3;
-    int64_t idx = sidx[e];
-    if (idx >= 0) {
-      const T v = mul_rn(wavelet[(size_t)s * wstride + t], sw[e]);
-      unew[(size_t)s * vol + idx] += v;
-      if (dd) dd[(size_t)s * vol + idx] += v;
-    }
-  }
-}
-
-// receiver e (shot e / nrec) of field u into trace row tl
-template <typename T>
-__device__ __forceinline__ void sample_receiver(const T *u0, const int64_t *ridx, const T *rw, int nrec, int64_t vol,
-                                                T *traces, int64_t nsteps, int64_t tl, int64_t e) {
-  const int s = (int)(e / nrec), r = (int)(e % nrec);
-  const T *u = u0 + (size_t)s * vol;
-  T v = T(0);
-#pragma unroll
-  for (int c = 0; c < 8; ++c) {
-    int64_t idx = ridx[(size_t)r * 8 + c];
-    if (idx >= 0) v += rw[(size_t)r * 8 + c] * u[idx];
-  }
-  traces[((size_t)s * nsteps + tl) * nrec + r] = v;
-}
-
 struct ColDec {
   int base, mlen, ebase, elen;  // LDS index of the window's first row, run length; extra node, 0/1
   uint32_t off;                 // entry of window row 0 (the run's first entry at row 9 - mlen)
@@ -1303,24 +1342,6 @@ __device__ __forceinline__ void patch_tile(int64_t tb, const T *__restrict__ un,
   }
 }
 
-// Source injection and receiver sampling carried by the column-run patch launch (nsb,
-// ninj = 0: none).  The sampling workgroups read p^n of this step for the step before it
-// (trace row tcount[1] - tcount[2]); the injection workgroup adds this step's sources
-// (tcount[0]); the last workgroup to finish advances the step counter, as k_inject does.
-template <typename T>
-struct PatchIo {
-  const int64_t *ridx;
-  const T *rw;
-  int nrec, nsb;          // receivers, sampling workgroups
-  T *traces;
-  int64_t nsteps;
-  const int64_t *sidx;
-  const T *sw, *wavelet;
-  int64_t wstride;
-  int ninj;               // injection workgroups (0 or 1)
-  int64_t *tcount;        // null: the launch leaves the counter alone
-};
-
 // The IB patch of the tiled points (column-run records), with in front of the tiles: the
 // points of wider supports (nwb workgroups, one point per wavefront, the gather of k_patch;
 // started first, their longer latency hides under the tiles), then the workgroups of io.
@@ -1339,7 +1360,7 @@ __global__ void k_patch_cols(const T *__restrict__ un, T *__restrict__ unew, T *
     if (i < nwide) gather_point<T>(i, un, unew, dd, wrec, wpinfo, ball, wdelta, ball_meta, nx, ny, pitch, vol, nshots);
   } else if (b < nwb + io.nsb) {
     const int64_t e = (int64_t)(b - nwb) * blockDim.x + threadIdx.x;
-    if (e < (int64_t)io.nrec * nshots)
+    if (e < io.nrs)
       sample_receiver(un, io.ridx, io.rw, io.nrec, vol, io.traces, io.nsteps, io.tcount[1] - io.tcount[2], e);
   } else if (b < nsp) {
     inject_sources(unew, dd, io.sidx, io.sw, nshots, vol, io.wavelet, io.wstride, io.tcount[0]);
@@ -1348,22 +1369,7 @@ __global__ void k_patch_cols(const T *__restrict__ un, T *__restrict__ unew, T *
     if (tb < ntiles)
       patch_tile<T, SC>(tb, un, unew, dd, wcol, recs, scale, zfirst, coltab, tiles, nx, ny, nz, pitch, vol, nshots);
   }
-  if (io.tcount) {
-    // every read of the counter in this workgroup has returned (the barrier waits for them);
-    // the last workgroup to arrive advances it.  No fence: nothing written here is read by
-    // another workgroup of this launch (a device-scope fence would write back the L2 of
-    // each workgroup's XCD)
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      unsigned *done = reinterpret_cast<unsigned *>(io.tcount + 3);
-      if (atomicAdd(done, 1u) == gridDim.x - 1) {
-        const int64_t t = io.tcount[0];
-        io.tcount[1] = t;
-        io.tcount[0] = t + 1;
-        *done = 0u;
-      }
-    }
-  }
+  finish_io(io);
 }
 
 template <typename T>
@@ -1614,7 +1620,8 @@ static void launch_patch(const StepArgs &a, hipStream_t st, const PatchIo<T> *io
         // two shots per pass in FP32 only (two FP64 tiles would not leave room for a second
         // workgroup per CU)
         bool two = false;
-        const PatchIo<T> io = io_in ? *io_in : PatchIo<T>{};
+        PatchIo<T> io = io_in ? *io_in : PatchIo<T>{};
+        io.nsb = (int)((io.nrs + 511) / 512);
         const unsigned grid = (unsigned)(nblk + nwb + io.nsb + io.ninj);
         if constexpr (sizeof(T) == 4) {
           two = a.patch_variant == 9 && a.nshots >= 2;
@@ -1676,6 +1683,8 @@ static void launch_io(const StepArgs &a, T *u, hipStream_t st) {
 }
 
 // whether the step's source injection and sampling ride in the column-run patch launch
+// (not the 2D gather patch: its launch is short, and the atomic count at the end of its
+// workgroups cost more than the launch it saves, 15.1 -> 19.9 us per step on config 2)
 static bool io_in_patch(const StepArgs &a) {
   return a.io_merge && !a.fF && a.ndim == 3 && a.ntiles > 0 && (a.patch_variant == 8 || a.patch_variant == 9);
 }
@@ -1689,7 +1698,7 @@ static void launch_step(const StepArgs &a, hipStream_t st) {
       io.ridx = a.ridx;
       io.rw = (const T *)a.rw;
       io.nrec = a.nrec;
-      io.nsb = (int)(((int64_t)a.nrec * a.nshots + 511) / 512);
+      io.nrs = (int64_t)a.nrec * a.nshots;
       io.traces = (T *)a.traces;
       io.nsteps = a.nsteps;
     }

@@ -146,31 +146,33 @@ def test_traces_match_oracle(name, prec):
     assert e.max() < (1e-9 if prec == "f64" else 1e-4)
 
 
+@pytest.mark.parametrize("name", ["3d-m8-free", "2d-m8-free"])
 @pytest.mark.parametrize("prec", ["f64", "f32"])
-def test_source_at_an_ib_point_matches_oracle(prec):
-    """A source whose interpolation corners include an IB point.  Its injection cannot ride
-    in the patch launch (it would race with that point's patch row) and runs as a launch of
-    its own; traces against the oracle, eager and graph-replayed."""
+def test_source_at_an_ib_point_matches_oracle(prec, name):
+    """A source whose interpolation corners include an IB point.  In 3D its injection cannot
+    ride in the column-run patch launch (it would race with that point's patch row) and runs
+    as a launch of its own; traces against the oracle, eager and graph-replayed."""
     import dataclasses
 
     import torch
 
     import paper_2309_03600_amd as ib
-    wl0, w, ex, m, sols = case("3d-m8-free")
-    nx, ny, nz = wl0.shape
-    cls = ex["node_class"].reshape(nz, ny, nx)
+    wl0, w, ex, m, sols = case(name)
+    shape = wl0.shape[::-1]                       # (nz, [ny,] nx)
+    cls = ex["node_class"].reshape(shape)
     inter, ibp = (cls & 1).astype(bool), (cls & 4).astype(bool)
     pick = None
-    for z in range(nz - 1):
-        for y in range(3, ny - 4):
-            for x in range(3, nx - 4):
-                cell = (slice(z, z + 2), slice(y, y + 2), slice(x, x + 2))
-                if pick is None and inter[cell].all() and ibp[cell].any():
-                    pick = (x, y, z)
+    for idx in np.ndindex(*[n - 1 for n in shape]):
+        if any(i < 3 or i >= n - 4 for i, n in zip(idx[1:], shape[1:])):
+            continue                              # away from the lateral edges
+        cell = tuple(slice(i, i + 2) for i in idx)
+        if inter[cell].all() and ibp[cell].any():
+            pick = idx
+            break
     assert pick is not None
-    x, y, z = pick
-    wl = dataclasses.replace(wl0, src=np.array([[(x + 0.5) * wl0.h, (y + 0.5) * wl0.h, (z + 0.5) * wl0.h]]))
-    print(f"[source at IB {prec}] cell {pick}", flush=True)
+    pos = [(i + 0.5) * wl0.h for i in pick[::-1]]   # (x, [y,] z)
+    wl = dataclasses.replace(wl0, src=np.array([pos]))
+    print(f"[source at IB {name} {prec}] cell {pick[::-1]}", flush=True)
     sim, _ = simulation(wl, m, sols)
     ref = sim.run(wl.wavelets(np.float64), wl.nt)
     dt = torch.float64 if prec == "f64" else torch.float32
@@ -179,7 +181,7 @@ def test_source_at_an_ib_point_matches_oracle(prec):
         st = ib.ib_state_create(w, wl.vel, wl.dt, wl.src, wl.rec, damp_width=wl.damp_width, precision=prec)
         tr = st.step(wl.nt, wav, use_graph=graph).double().cpu().numpy()[0]
         e = rel_l2_per_trace(tr, ref)
-        print(f"[source at IB {prec} graph={graph}] per-trace rel-L2: max {e.max():.2e}", flush=True)
+        print(f"[source at IB {name} {prec} graph={graph}] per-trace rel-L2: max {e.max():.2e}", flush=True)
         assert e.max() < (1e-9 if prec == "f64" else 1e-4)
 
 
