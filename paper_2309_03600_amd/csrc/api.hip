@@ -1194,7 +1194,7 @@ ib_status ib_state_create(const ib_weights *w, const double *vel_dev, double dt,
         swv[sh * 8 + c] = (w->form == IB_FORM_PV1 ? dt : dt * dt) * wt[c] / (hd * (1.0 + sd));
       }
     }
-    S->io_merge = w->form == IB_FORM_P2 && w->ndim == 3 && !src_at_ib;
+    S->io_merge = w->form == IB_FORM_P2 && !src_at_ib;
     if ((s = dalloc_t(&S->sidx, nshots * 8)) || (s = dalloc(&S->sw, nshots * 8 * S->esz))) return fail(s);
     IB_HIP(hipMemcpy(S->sidx, sidx.data(), nshots * 64, hipMemcpyHostToDevice));
     {

@@ -574,10 +574,10 @@ __device__ __forceinline__ void sample_receiver(const T *u0, const int64_t *ridx
   traces[((size_t)s * nsteps + tl) * nrec + r] = v;
 }
 
-// Source injection and receiver sampling carried by the column-run patch launch (nsb,
-// ninj = 0: none).  The sampling workgroups read p^n of this step for the step before it
-// (trace row tcount[1] - tcount[2]); the injection workgroup adds this step's sources
-// (tcount[0]); the last workgroup to finish advances the step counter, as k_inject does.
+// Source injection and receiver sampling carried by a patch launch (nsb, ninj = 0: none).
+// The sampling workgroups read p^n of this step for the step before it (trace row
+// tcount[1] - tcount[2]); the injection workgroup adds this step's sources (tcount[0]); the
+// last io workgroup to finish advances the step counter, as k_inject does.
 template <typename T>
 struct PatchIo {
   const int64_t *ridx;
@@ -594,17 +594,16 @@ struct PatchIo {
 };
 
 
-// the end of every workgroup of a launch that carries io: the last one advances the step
-// counter.  Every read of the counter in the workgroup has returned (the barrier waits for
-// them).  No fence: nothing written here is read by another workgroup of this launch (a
-// device-scope fence would write back the L2 of each workgroup's XCD)
+// the end of each io workgroup (the only ones that read the step counter): the last one
+// advances the counter.  Every read of the counter in the workgroup has returned (the
+// barrier waits for them).  No fence: nothing written here is read by another workgroup of
+// this launch (a device-scope fence would write back the L2 of each workgroup's XCD)
 template <typename T>
 __device__ __forceinline__ void finish_io(const PatchIo<T> &io) {
-  if (!io.tcount) return;
   __syncthreads();
   if (threadIdx.x == 0) {
     unsigned *done = reinterpret_cast<unsigned *>(io.tcount + 3);
-    if (atomicAdd(done, 1u) == gridDim.x - 1) {
+    if (atomicAdd(done, 1u) == (unsigned)(io.nsb + io.ninj - 1)) {
       const int64_t t = io.tcount[0];
       io.tcount[1] = t;
       io.tcount[0] = t + 1;
@@ -651,14 +650,28 @@ __device__ __forceinline__ void gather_point(int64_t i, const T *__restrict__ un
   }
 }
 
+// the gather patch, four points per workgroup, after the workgroups of io (2D)
 template <typename T>
 __launch_bounds__(256)
 __global__ void k_patch(const T *__restrict__ un, T *__restrict__ unew, T *__restrict__ dd,
                         const uint32_t *__restrict__ rec,
                         const PInfo<T> *__restrict__ pinfo, const int32_t *__restrict__ ball,
                         const int32_t *__restrict__ delta, const int32_t *__restrict__ ball_meta, int64_t nib,
-                        int nx, int ny, int nz, int64_t pitch, int64_t vol, int nshots) {
-  const int64_t blk = xcd_remap(blockIdx.x, gridDim.x);
+                        int nx, int ny, int nz, int64_t pitch, int64_t vol, int nshots, PatchIo<T> io) {
+  const int b = (int)blockIdx.x, nsp = io.nsb + io.ninj;
+  if (b < io.nsb) {
+    const int64_t e = (int64_t)b * blockDim.x + threadIdx.x;
+    if (e < io.nrs)
+      sample_receiver(un, io.ridx, io.rw, io.nrec, vol, io.traces, io.nsteps, io.tcount[1] - io.tcount[2], e);
+    finish_io(io);
+    return;
+  }
+  if (b < nsp) {
+    inject_sources(unew, dd, io.sidx, io.sw, nshots, vol, io.wavelet, io.wstride, io.tcount[0]);
+    finish_io(io);
+    return;
+  }
+  const int64_t blk = xcd_remap(b - nsp, gridDim.x - nsp);
   const int64_t i = blk * (blockDim.x >> 6) + (threadIdx.x >> 6);
   if (i >= nib) return;
   gather_point<T>(i, un, unew, dd, rec, pinfo, ball, delta, ball_meta, nx, ny, pitch, vol, nshots);
@@ -1362,14 +1375,15 @@ __global__ void k_patch_cols(const T *__restrict__ un, T *__restrict__ unew, T *
     const int64_t e = (int64_t)(b - nwb) * blockDim.x + threadIdx.x;
     if (e < io.nrs)
       sample_receiver(un, io.ridx, io.rw, io.nrec, vol, io.traces, io.nsteps, io.tcount[1] - io.tcount[2], e);
+    finish_io(io);
   } else if (b < nsp) {
     inject_sources(unew, dd, io.sidx, io.sw, nshots, vol, io.wavelet, io.wstride, io.tcount[0]);
+    finish_io(io);
   } else {
     const int64_t tb = xcd_remap(b - nsp, gridDim.x - nsp);
     if (tb < ntiles)
       patch_tile<T, SC>(tb, un, unew, dd, wcol, recs, scale, zfirst, coltab, tiles, nx, ny, nz, pitch, vol, nshots);
   }
-  finish_io(io);
 }
 
 template <typename T>
@@ -1655,9 +1669,11 @@ static void launch_patch(const StepArgs &a, hipStream_t st, const PatchIo<T> *io
     hipStream_t ws = fork ? a.aux : st;
     if (fork) (void)hipStreamWaitEvent(a.aux, a.ev_fork, 0);
     int64_t nblk = ((a.nwide + 3) / 4 + 7) / 8 * 8;
-    hipLaunchKernelGGL(k_patch<T>, dim3((unsigned)nblk), dim3(256), 0, ws, (const T *)a.un, (T *)a.um, (T *)a.dd, a.rec,
-                       (const PInfo<T> *)a.pinfo_wide, a.ball, a.delta, a.ball_meta, a.nwide, a.nx, a.ny, a.nz,
-                       a.pitch, a.vol, a.nshots);
+    PatchIo<T> io = (io_in && !fork) ? *io_in : PatchIo<T>{};
+    io.nsb = (int)((io.nrs + 255) / 256);
+    hipLaunchKernelGGL(k_patch<T>, dim3((unsigned)(nblk + io.nsb + io.ninj)), dim3(256), 0, ws, (const T *)a.un,
+                       (T *)a.um, (T *)a.dd, a.rec, (const PInfo<T> *)a.pinfo_wide, a.ball, a.delta, a.ball_meta,
+                       a.nwide, a.nx, a.ny, a.nz, a.pitch, a.vol, a.nshots, io);
     if (fork) {
       (void)hipEventRecord(a.ev_join, a.aux);
       (void)hipStreamWaitEvent(st, a.ev_join, 0);
@@ -1683,10 +1699,10 @@ static void launch_io(const StepArgs &a, T *u, hipStream_t st) {
 }
 
 // whether the step's source injection and sampling ride in the column-run patch launch
-// (not the 2D gather patch: its launch is short, and the atomic count at the end of its
-// workgroups cost more than the launch it saves, 15.1 -> 19.9 us per step on config 2)
 static bool io_in_patch(const StepArgs &a) {
-  return a.io_merge && !a.fF && a.ndim == 3 && a.ntiles > 0 && (a.patch_variant == 8 || a.patch_variant == 9);
+  if (!a.io_merge || a.fF) return false;
+  if (a.ntiles > 0) return a.ndim == 3 && (a.patch_variant == 8 || a.patch_variant == 9);
+  return a.nwide > 0;   // the gather patch alone (2D)
 }
 
 template <typename T>
