@@ -594,6 +594,17 @@ struct PatchIo {
 };
 
 
+// sampling workgroup b of io.nsb: receiver-shots b * blockDim + tid, then every nsb
+// workgroups further (the workgroups are capped, so that few of them count toward the step
+// counter's advance: one atomic each)
+constexpr int64_t kMaxSampleBlocks = 128;
+template <typename T>
+__device__ __forceinline__ void sample_block(const T *un, const PatchIo<T> &io, int b, int64_t vol) {
+  const int64_t tl = io.tcount[1] - io.tcount[2];
+  for (int64_t e = (int64_t)b * blockDim.x + threadIdx.x; e < io.nrs; e += (int64_t)io.nsb * blockDim.x)
+    sample_receiver(un, io.ridx, io.rw, io.nrec, vol, io.traces, io.nsteps, tl, e);
+}
+
 // the end of each io workgroup (the only ones that read the step counter): the last one
 // advances the counter.  Every read of the counter in the workgroup has returned (the
 // barrier waits for them).  No fence: nothing written here is read by another workgroup of
@@ -660,9 +671,7 @@ __global__ void k_patch(const T *__restrict__ un, T *__restrict__ unew, T *__res
                         int nx, int ny, int nz, int64_t pitch, int64_t vol, int nshots, PatchIo<T> io) {
   const int b = (int)blockIdx.x, nsp = io.nsb + io.ninj;
   if (b < io.nsb) {
-    const int64_t e = (int64_t)b * blockDim.x + threadIdx.x;
-    if (e < io.nrs)
-      sample_receiver(un, io.ridx, io.rw, io.nrec, vol, io.traces, io.nsteps, io.tcount[1] - io.tcount[2], e);
+    sample_block(un, io, b, vol);
     finish_io(io);
     return;
   }
@@ -1372,9 +1381,7 @@ __global__ void k_patch_cols(const T *__restrict__ un, T *__restrict__ unew, T *
     const int64_t i = (int64_t)b * (blockDim.x >> 6) + (threadIdx.x >> 6);
     if (i < nwide) gather_point<T>(i, un, unew, dd, wrec, wpinfo, ball, wdelta, ball_meta, nx, ny, pitch, vol, nshots);
   } else if (b < nwb + io.nsb) {
-    const int64_t e = (int64_t)(b - nwb) * blockDim.x + threadIdx.x;
-    if (e < io.nrs)
-      sample_receiver(un, io.ridx, io.rw, io.nrec, vol, io.traces, io.nsteps, io.tcount[1] - io.tcount[2], e);
+    sample_block(un, io, b - nwb, vol);
     finish_io(io);
   } else if (b < nsp) {
     inject_sources(unew, dd, io.sidx, io.sw, nshots, vol, io.wavelet, io.wstride, io.tcount[0]);
@@ -1635,7 +1642,7 @@ static void launch_patch(const StepArgs &a, hipStream_t st, const PatchIo<T> *io
         // workgroup per CU)
         bool two = false;
         PatchIo<T> io = io_in ? *io_in : PatchIo<T>{};
-        io.nsb = (int)((io.nrs + 511) / 512);
+        io.nsb = (int)std::min<int64_t>((io.nrs + 511) / 512, kMaxSampleBlocks);
         const unsigned grid = (unsigned)(nblk + nwb + io.nsb + io.ninj);
         if constexpr (sizeof(T) == 4) {
           two = a.patch_variant == 9 && a.nshots >= 2;
@@ -1670,7 +1677,7 @@ static void launch_patch(const StepArgs &a, hipStream_t st, const PatchIo<T> *io
     if (fork) (void)hipStreamWaitEvent(a.aux, a.ev_fork, 0);
     int64_t nblk = ((a.nwide + 3) / 4 + 7) / 8 * 8;
     PatchIo<T> io = (io_in && !fork) ? *io_in : PatchIo<T>{};
-    io.nsb = (int)((io.nrs + 255) / 256);
+    io.nsb = (int)std::min<int64_t>((io.nrs + 255) / 256, kMaxSampleBlocks);
     hipLaunchKernelGGL(k_patch<T>, dim3((unsigned)(nblk + io.nsb + io.ninj)), dim3(256), 0, ws, (const T *)a.un,
                        (T *)a.um, (T *)a.dd, a.rec, (const PInfo<T> *)a.pinfo_wide, a.ball, a.delta, a.ball_meta,
                        a.nwide, a.nx, a.ny, a.nz, a.pitch, a.vol, a.nshots, io);
