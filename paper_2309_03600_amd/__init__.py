@@ -295,7 +295,8 @@ class IBState:
         _lib.check(_lib.load().ib_state_run_kernel(self._h, int(which), int(count), _stream(stream)))
 
     def set_tuning(self, variant, zchunk, patch_variant=-1):
-        """Interior-kernel variant (0, 1, 2) and depth planes per workgroup (0 = all)."""
+        """Interior-kernel variant (0-4), depth planes per workgroup (0: the tuned value) and
+        IB-patch variant (-1: keep)."""
         _lib.check(_lib.load().ib_state_set_tuning(self._h, int(variant), int(zchunk), int(patch_variant)))
 
     @property

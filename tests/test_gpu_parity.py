@@ -185,6 +185,30 @@ def test_source_at_an_ib_point_matches_oracle(prec, name):
         assert e.max() < (1e-9 if prec == "f64" else 1e-4)
 
 
+@pytest.mark.parametrize("name", ["3d-m8-free", "2d-m8-free"])
+def test_split_calls_match_one_call(name):
+    """The step counter, the sources and the receivers ride in the patch launch, and a
+    call's last step is sampled at its end: a run split into calls of 1 to 33 steps, eager
+    and graph-replayed, gives the traces of one call, bit for bit."""
+    import torch
+
+    import paper_2309_03600_amd as ib
+    wl, w, ex, m, sols = case(name)
+    wav = torch.tensor(wl.wavelets(np.float32), dtype=torch.float32, device="cuda")
+    chunks = [1, 2, 3, 16, 17, 1, 33, 47]
+    n = sum(chunks)
+    st = ib.ib_state_create(w, wl.vel, wl.dt, wl.src, wl.rec, damp_width=wl.damp_width, precision="f32")
+    one = st.step(n, wav, use_graph=True).cpu().numpy()
+    for graph in (False, True):
+        st = ib.ib_state_create(w, wl.vel, wl.dt, wl.src, wl.rec, damp_width=wl.damp_width, precision="f32")
+        parts = [st.step(c, wav, use_graph=graph) for c in chunks]
+        split = torch.cat(parts, dim=1).cpu().numpy()
+        print(f"[split calls {name} graph={graph}] steps {st.step_count}", flush=True)
+        assert st.step_count == n
+        assert np.abs(one).max() > 0
+        assert np.array_equal(split, one)
+
+
 @pytest.mark.parametrize("prec", ["f64", "f32"])
 def test_graph_replay_matches_eager(prec):
     import torch
