@@ -1834,12 +1834,29 @@ __global__ void k_adj_gather(T *__restrict__ lam, T *__restrict__ lamd, const T 
   T acc[SC];
 #pragma unroll
   for (int c = 0; c < SC; ++c) acc[c] = T(0);
-  for (uint32_t k = a + sub; k < b; k += 16) {
-    const T w = wt[k];
-    const T *vi = v + (size_t)src[k] * nshots + s0;
+  // a point's SC values as 16-byte loads where they are aligned to them (the same products
+  // and sums as the element loads)
+  constexpr int VW = 16 / sizeof(T);
+  if (SC % VW == 0 && nshots % VW == 0 && s0 % VW == 0 && s0 + SC <= nshots) {
+    for (uint32_t k = a + sub; k < b; k += 16) {
+      const T w = wt[k];
+      const T *vi = v + (size_t)src[k] * nshots + s0;
 #pragma unroll
-    for (int c = 0; c < SC; ++c)
-      if (s0 + c < nshots) acc[c] += w * vi[c];
+      for (int c = 0; c < SC; c += VW) {
+        T q[VW];
+        __builtin_memcpy(q, __builtin_assume_aligned(vi + c, 16), 16);
+#pragma unroll
+        for (int e = 0; e < VW; ++e) acc[c + e] += w * q[e];
+      }
+    }
+  } else {
+    for (uint32_t k = a + sub; k < b; k += 16) {
+      const T w = wt[k];
+      const T *vi = v + (size_t)src[k] * nshots + s0;
+#pragma unroll
+      for (int c = 0; c < SC; ++c)
+        if (s0 + c < nshots) acc[c] += w * vi[c];
+    }
   }
   T mine = T(0);
 #pragma unroll
