@@ -101,8 +101,10 @@ __device__ __forceinline__ double buf_load(__amdgpu_buffer_rsrc_t r, uint32_t of
 // periodic: each of the NT threads issues all its loads, then writes them.  keep(lx, ly, lz)
 // leaves a node out (zero) when false; nodes above or below the box are zero.  The caller
 // checks that a shot's volume is under 2^31 bytes.
-// (LDS rows RP apart and planes PL apart: RP = LX, PL = LX * LY is the dense layout)
-template <typename T, int SC, int LX, int LY, int LZ, int NT, int PAD, typename Keep, int RP = LX, int PL = LX * LY>
+// (LDS rows RP apart and planes PL apart: RP = LX, PL = LX * LY is the dense layout; with ILV
+// the SC shots of a node sit side by side, else shot c starts spstride values after shot 0)
+template <typename T, int SC, int LX, int LY, int LZ, int NT, int PAD, typename Keep, int RP = LX, int PL = LX * LY,
+          bool ILV = false>
 __device__ __forceinline__ void stage_tile(T *sp, int spstride, const T *un, int64_t vol, int s0, int nshots, int gx0,
                                            int gy0, int gz0, int nx, int ny, int nz, int64_t pitch, Keep keep) {
   constexpr int N = LX * LY * LZ, NST = (N + NT - 1) / NT;
@@ -132,7 +134,10 @@ __device__ __forceinline__ void stage_tile(T *sp, int spstride, const T *un, int
     if (e < N) {
       const int lx = e % LX, ly = (e / LX) % LY, lz = e / (LX * LY);
 #pragma unroll
-      for (int c = 0; c < SC; ++c) sp[c * spstride + lz * PL + ly * RP + lx] = v[c][j];
+      for (int c = 0; c < SC; ++c) {
+        const int node = lz * PL + ly * RP + lx;
+        sp[ILV ? node * SC + c : c * spstride + node] = v[c][j];
+      }
     }
   }
 }
@@ -1230,7 +1235,10 @@ __device__ __forceinline__ void patch_tile(int64_t tb, const T *__restrict__ un,
   constexpr int NWIN = NE + 1;            // window entries used: rows, then the extra node
   constexpr int NL = (NWIN + VEC - 1) / VEC;
   static_assert(HR == 4 && NC % 64 == 0, "column tables of radius 4 and 4.5; planes of whole bank rows");
-  __shared__ T sp[SC][(ZT + LZ) * PL];
+  // two FP32 shots sit side by side per node (one 8-byte LDS read for both)
+  constexpr bool ILV = SC == 2 && sizeof(T) == 4;
+  __shared__ __align__(16) T sp[SC * (ZT + LZ) * PL];
+  auto at = [&](int c, int node) -> int { return ILV ? node * SC + c : c * (ZT + LZ) * PL + node; };
   __shared__ int zf[NC];                  // first data plane of each column (tile plane index)
   __shared__ uint2 rec[kTileMaxPoints];   // entry offset; x | y << 5 | z << 10 | radius code 9 << 31
   __shared__ T res[SC][kTileMaxPoints];
@@ -1266,7 +1274,7 @@ __device__ __forceinline__ void patch_tile(int64_t tb, const T *__restrict__ un,
   for (int i = threadIdx.x; i < np; i += blockDim.x) rec[i] = recs[p0 + i];
   for (int e = threadIdx.x; e < ZT * PL; e += blockDim.x)
 #pragma unroll
-    for (int c = 0; c < SC; ++c) sp[c][e] = T(0);
+    for (int c = 0; c < SC; ++c) sp[at(c, e)] = T(0);
   __syncthreads();
   auto decode = [&](int i) {
     ColDec D{0, 0, 0, 0, 0u};
@@ -1315,12 +1323,19 @@ __device__ __forceinline__ void patch_tile(int64_t tb, const T *__restrict__ un,
 #pragma unroll
     for (int k = 0; k < NE; ++k) {
       const T wk = (k >= NE - D.mlen) ? w[k] : T(0);
+      if constexpr (ILV) {
+        float2 pv;
+        __builtin_memcpy(&pv, &sp[(D.base + k * PL) * 2], 8);
+        acc[0] = fma(wk, pv.x, acc[0]);
+        acc[1] = fma(wk, pv.y, acc[1]);
+      } else {
 #pragma unroll
-      for (int c = 0; c < SC; ++c) acc[c] = fma(wk, sp[c][D.base + k * PL], acc[c]);
+        for (int c = 0; c < SC; ++c) acc[c] = fma(wk, sp[at(c, D.base + k * PL)], acc[c]);
+      }
     }
     const T we = D.elen ? w[NE] : T(0);
 #pragma unroll
-    for (int c = 0; c < SC; ++c) acc[c] = fma(we, sp[c][D.ebase], acc[c]);
+    for (int c = 0; c < SC; ++c) acc[c] = fma(we, sp[at(c, D.ebase)], acc[c]);
 #pragma unroll
     for (int c = 0; c < SC; ++c) {
       const T t = wave_total(acc[c]);
@@ -1333,8 +1348,9 @@ __device__ __forceinline__ void patch_tile(int64_t tb, const T *__restrict__ un,
     T w0[NL * VEC], w1[NL * VEC];
     load(D0, w0);
     auto keep = [&](int lx, int ly, int lz) { return zf[ly * CX + lx] <= lz; };
-    stage_tile<T, SC, CX, CY, LZ, 512, 0, decltype(keep), RP, PL>(&sp[0][ZT * PL], (ZT + LZ) * PL, un, vol, s0, nshots,
-                                                                  x0 - HR, y0 - HR, z0 - HR, nx, ny, nz, pitch, keep);
+    stage_tile<T, SC, CX, CY, LZ, 512, 0, decltype(keep), RP, PL, ILV>(&sp[at(0, ZT * PL)], (ZT + LZ) * PL, un, vol,
+                                                                       s0, nshots, x0 - HR, y0 - HR, z0 - HR, nx, ny,
+                                                                       nz, pitch, keep);
     __syncthreads();
     // points wave, wave + NW, ...: two in flight, roles alternating (no register moves)
     for (int p = wave; p < np; p += 2 * NW) {
