@@ -476,8 +476,8 @@ def main():
         summarize_counters(*args.summarize_counters)
         return
     if args.gpus != 1:
-        print("bench.py: this build runs on one GPU only; multi-GPU sharding is a design note, "
-              "not an implemented path (use --gpus 1)", file=sys.stderr)
+        print("bench.py: the library runs on one GPU; sharding shots or a slab decomposition over "
+              "several GPUs is not implemented (use --gpus 1)", file=sys.stderr)
         sys.exit(2)
     if args.workload != "config3":
         {"config2": bench_config2, "config4": bench_config4, "config5": bench_config5,
