@@ -77,8 +77,8 @@ struct ib_state {
   int zchunk_auto = 0;
   int variant = 1;
   int patch_variant = 4;
-  // sources injected and receivers sampled inside the column-run patch launch (3D
-  // second-order form, no source node is an IB point)
+  // sources injected and receivers sampled inside the patch launch (second-order form, no
+  // source node is an IB point)
   bool io_merge = false;
   // captured graphs of two steps and of kLongGraph steps (the same two-step sequence
   // repeated: fewer launches, each of which costs several microseconds of idle device)

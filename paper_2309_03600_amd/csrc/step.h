@@ -54,9 +54,10 @@ struct StepArgs {
   // the tiled kernel (null: both on the step's stream)
   hipStream_t aux;
   hipEvent_t ev_fork, ev_join;
-  // io_merge: the column-run patch launch also injects this step's sources and samples the
-  // receivers for the step before (its p^n); the state allows it when no source node is an
-  // IB point and no boundary values are set.  sample_prev: this step samples the step before.
+  // io_merge: the patch launch (the column-run kernel in 3D, the gather kernel in 2D) also
+  // injects this step's sources and samples the receivers for the step before (its p^n);
+  // the state allows it when no source node is an IB point and no boundary values are set.
+  // sample_prev: this step samples the step before.
   int io_merge, sample_prev;
   const int32_t *ball;
   const int32_t *delta;       // linear offsets of the ball lattice points for this layout
