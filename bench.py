@@ -59,7 +59,7 @@ CALIB_BYTES = 1 << 30
 
 def kernel_source_hash():
     h = hashlib.sha256()
-    for f in ("step.hip", "step.h"):
+    for f in ("step.hip", "step.h", "io.h"):
         h.update(open(os.path.join(ROOT, "paper_2309_03600_amd", "csrc", f), "rb").read())
     return h.hexdigest()[:16]
 

@@ -77,8 +77,8 @@ struct ib_state {
   int zchunk_auto = 0;
   int variant = 1;
   int patch_variant = 4;
-  // sources injected and receivers sampled inside the patch launch (second-order form, no
-  // source node is an IB point)
+  // sources injected and receivers sampled inside the patch launch (second-order form) or
+  // the rows launches (first-order form); no source node is an IB point or a modified row
   bool io_merge = false;
   // captured graphs of two steps and of kLongGraph steps (the same two-step sequence
   // repeated: fewer launches, each of which costs several microseconds of idle device)
@@ -99,6 +99,7 @@ struct ib_state {
   // host copies needed by the adjoint
   std::vector<double> ax, ay, az;
   std::vector<int64_t> ridx_h;
+  std::vector<int64_t> dnode_h;   // first-order form: the divergence rows' p nodes, sorted
   std::vector<double> rw_h;
   // checkpoints written by ib_forward (ib_forward_ckpt writes caller-held ones)
   ib_checkpoints own;
@@ -956,6 +957,8 @@ ib_status ib_state_create(const ib_weights *w, const double *vel_dev, double dt,
       }
       S->nrows_g = (int64_t)gn.size();
       S->nrows_d = (int64_t)dn.size();
+      S->dnode_h = dn;
+      std::sort(S->dnode_h.begin(), S->dnode_h.end());
       // rows of fewer than 40 entries on average take 8 lanes each (more rows per wavefront)
       S->g_lanes = (gn.empty() || ge.size() >= 40 * gn.size()) ? 16 : 8;
       S->d_lanes = (dn.empty() || de.size() >= 40 * dn.size()) ? 16 : 8;
@@ -1188,13 +1191,15 @@ ib_status ib_state_create(const ib_weights *w, const double *vel_dev, double dt,
           return fail(IB_ERR_ARG);
         }
         if (cls[idu[c]] & 4) src_at_ib = true;
+        if (w->form == IB_FORM_PV1 && std::binary_search(S->dnode_h.begin(), S->dnode_h.end(), idx[c]))
+          src_at_ib = true;
         int64_t x = idu[c] % w->nx, y = (idu[c] / w->nx) % w->ny, z = idu[c] / (w->nx * w->ny);
         double sd = ax[x] + ay[(w->ndim == 3) ? y : 0] + az[z];
         sidx[sh * 8 + c] = idx[c];
         swv[sh * 8 + c] = (w->form == IB_FORM_PV1 ? dt : dt * dt) * wt[c] / (hd * (1.0 + sd));
       }
     }
-    S->io_merge = w->form == IB_FORM_P2 && !src_at_ib;
+    S->io_merge = !src_at_ib && (w->form == IB_FORM_P2 || (S->nrows_g > 0 && S->nrows_d > 0));
     if ((s = dalloc_t(&S->sidx, nshots * 8)) || (s = dalloc(&S->sw, nshots * 8 * S->esz))) return fail(s);
     IB_HIP(hipMemcpy(S->sidx, sidx.data(), nshots * 64, hipMemcpyHostToDevice));
     {
@@ -1347,13 +1352,30 @@ PVArgs make_pv_args(const ib_state *S) {
 }
 
 // one full step of either form: operator update, source injection, receiver sampling.
-// Where the column-run patch launch carries the io, the step's sampling is left to the next
-// step (sample_prev) or to flush_sample; returns whether it was.
+// Where the patch (or the first-order rows) launches carry the io, the step's sampling is
+// left to the next step (sample_prev) or to flush_sample; returns whether it was.
 bool enqueue_full_step(ib_state *S, const void *wavelet, int64_t wstride, void *traces, int64_t trace_nt, int cur,
                        hipStream_t st, bool sample_prev = false) {
   StepArgs a = make_args(S, wavelet, wstride, traces, trace_nt, cur);
   if (S->form == IB_FORM_PV1) {
-    enqueue_pv_step(make_pv_args(S), st);
+    PVArgs pa = make_pv_args(S);
+    if (S->io_merge) {
+      pa.io_merge = 1;
+      pa.sample_prev = sample_prev ? 1 : 0;
+      pa.sidx = a.sidx;
+      pa.sw = a.sw;
+      pa.wavelet = a.wavelet;
+      pa.wstride = a.wstride;
+      pa.ridx = a.ridx;
+      pa.rw = a.rw;
+      pa.nrec = a.nrec;
+      pa.traces = a.traces;
+      pa.nsteps = a.nsteps;
+      pa.tcount = a.tcount;
+      enqueue_pv_step(pa, st);
+      return true;
+    }
+    enqueue_pv_step(pa, st);
     enqueue_source_receivers(a, S->buf[0], st);
     return false;
   }
@@ -1362,10 +1384,11 @@ bool enqueue_full_step(ib_state *S, const void *wavelet, int64_t wstride, void *
   return step_samples_in_patch(a);
 }
 
-// the sampling left behind by the last step (its output is the field of parity cur)
+// the sampling left behind by the last step (its output is the field of parity cur; the
+// first-order form keeps p in buf[0])
 static void flush_sample(ib_state *S, void *traces, int64_t trace_nt, int cur, hipStream_t st) {
   StepArgs a = make_args(S, nullptr, 0, traces, trace_nt, cur);
-  enqueue_sample(a, S->buf[cur], st);
+  enqueue_sample(a, S->form == IB_FORM_PV1 ? S->buf[0] : S->buf[cur], st);
 }
 
 // Watchdog scan of p^n: a wavefront that holds a value outside [-limit, limit] (NaN

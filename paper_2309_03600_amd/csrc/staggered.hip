@@ -21,6 +21,7 @@
 #include "ib_internal.h"
 #include "step.h"
 #include "surface.h"
+#include "io.h"
 #include "wave.h"
 
 namespace ib {
@@ -416,9 +417,22 @@ __launch_bounds__(256)
 __global__ void k_pv_rows(T *__restrict__ dst, int64_t dst_shot_stride, const T *__restrict__ src,
                           int64_t src_shot_stride, const int64_t *__restrict__ rnode, const T *__restrict__ rscale,
                           const int64_t *__restrict__ rstart, const uint32_t *__restrict__ enode,
-                          const T *__restrict__ ew, int64_t nrows, int nshots) {
+                          const T *__restrict__ ew, int64_t nrows, int nshots, PatchIo<T> io, T *pf,
+                          int64_t pvol) {
+  // the io workgroups first (sampling from, or injection into, the pressure field pf)
+  const int blk = (int)blockIdx.x, nsp = io.nsb + io.ninj;
+  if (blk < io.nsb) {
+    sample_block(pf, io, blk, pvol);
+    finish_io(io);
+    return;
+  }
+  if (blk < nsp) {
+    inject_sources(pf, (T *)nullptr, io.sidx, io.sw, nshots, pvol, io.wavelet, io.wstride, io.tcount[0]);
+    finish_io(io);
+    return;
+  }
   const int sub = threadIdx.x & (L - 1);
-  const int64_t r = (int64_t)blockIdx.x * (blockDim.x / L) + threadIdx.x / L;
+  const int64_t r = (int64_t)(blk - nsp) * (blockDim.x / L) + threadIdx.x / L;
   const bool live = r < nrows;
   // rows stay complete (no early return) so that the DPP exchanges see all lanes
   const int64_t a = live ? rstart[r] : 0, b = live ? rstart[r + 1] : 0;
@@ -465,15 +479,37 @@ static void pv_step_h(const PVArgs &a, hipStream_t st) {
     hipLaunchKernelGGL((k_pv_velocity<T, H>), gv, b, 0, st, (T *)a.v, (const T *)a.p, (const T *)a.kv,
                        (const T *)a.sx, (const T *)a.sy, (const T *)a.sz, W, a.nx, a.ny, a.nz, a.pitch, a.vol, a.nv,
                        a.ndim, a.nshots);
+  // the sources and receivers (io_merge): sampling for the step before in the gradient
+  // rows, which read p; injection and the counter's advance in the divergence rows
+  PatchIo<T> gio{}, dio{};
+  if (a.io_merge) {
+    if (a.sample_prev && a.nrec > 0 && a.traces) {
+      gio.ridx = a.ridx;
+      gio.rw = (const T *)a.rw;
+      gio.nrec = a.nrec;
+      gio.nrs = (int64_t)a.nrec * a.nshots;
+      gio.nsb = (int)std::min<int64_t>((gio.nrs + 255) / 256, kMaxSampleBlocks);
+      gio.traces = (T *)a.traces;
+      gio.nsteps = a.nsteps;
+      gio.tcount = a.tcount;
+    }
+    dio.sidx = a.sidx;
+    dio.sw = (const T *)a.sw;
+    dio.wavelet = (const T *)a.wavelet;
+    dio.wstride = a.wstride;
+    dio.ninj = 1;
+    dio.tcount = a.tcount;
+    dio.advance = 1;
+  }
   if (a.nrows_g > 0) {
     if (a.g_lanes == 8)
-      hipLaunchKernelGGL((k_pv_rows<T, 8>), dim3((unsigned)((a.nrows_g + 31) / 32)), b, 0, st, (T *)a.v,
+      hipLaunchKernelGGL((k_pv_rows<T, 8>), dim3((unsigned)((a.nrows_g + 31) / 32 + gio.nsb)), b, 0, st, (T *)a.v,
                          (int64_t)a.nv * a.vol, (const T *)a.p, a.vol, a.g_node, (const T *)a.g_scale, a.g_start,
-                         a.g_enode, (const T *)a.g_w, a.nrows_g, a.nshots);
+                         a.g_enode, (const T *)a.g_w, a.nrows_g, a.nshots, gio, (T *)a.p, a.vol);
     else
-      hipLaunchKernelGGL((k_pv_rows<T, 16>), dim3((unsigned)((a.nrows_g + 15) / 16)), b, 0, st, (T *)a.v,
+      hipLaunchKernelGGL((k_pv_rows<T, 16>), dim3((unsigned)((a.nrows_g + 15) / 16 + gio.nsb)), b, 0, st, (T *)a.v,
                          (int64_t)a.nv * a.vol, (const T *)a.p, a.vol, a.g_node, (const T *)a.g_scale, a.g_start,
-                         a.g_enode, (const T *)a.g_w, a.nrows_g, a.nshots);
+                         a.g_enode, (const T *)a.g_w, a.nrows_g, a.nshots, gio, (T *)a.p, a.vol);
   }
   if (a.ndim == 3 && a.zr4)
     hipLaunchKernelGGL((k_pv_pressure3d<T, H>), g3, b, 0, st, (T *)a.p, (const T *)a.v, (const T *)a.kp,
@@ -485,13 +521,13 @@ static void pv_step_h(const PVArgs &a, hipStream_t st) {
                        a.ndim, a.nshots);
   if (a.nrows_d > 0) {
     if (a.d_lanes == 8)
-      hipLaunchKernelGGL((k_pv_rows<T, 8>), dim3((unsigned)((a.nrows_d + 31) / 32)), b, 0, st, (T *)a.p, a.vol,
-                         (const T *)a.v, (int64_t)a.nv * a.vol, a.d_node, (const T *)a.d_scale, a.d_start,
-                         a.d_enode, (const T *)a.d_w, a.nrows_d, a.nshots);
+      hipLaunchKernelGGL((k_pv_rows<T, 8>), dim3((unsigned)((a.nrows_d + 31) / 32 + dio.ninj)), b, 0, st, (T *)a.p,
+                         a.vol, (const T *)a.v, (int64_t)a.nv * a.vol, a.d_node, (const T *)a.d_scale, a.d_start,
+                         a.d_enode, (const T *)a.d_w, a.nrows_d, a.nshots, dio, (T *)a.p, a.vol);
     else
-      hipLaunchKernelGGL((k_pv_rows<T, 16>), dim3((unsigned)((a.nrows_d + 15) / 16)), b, 0, st, (T *)a.p, a.vol,
-                         (const T *)a.v, (int64_t)a.nv * a.vol, a.d_node, (const T *)a.d_scale, a.d_start,
-                         a.d_enode, (const T *)a.d_w, a.nrows_d, a.nshots);
+      hipLaunchKernelGGL((k_pv_rows<T, 16>), dim3((unsigned)((a.nrows_d + 15) / 16 + dio.ninj)), b, 0, st, (T *)a.p,
+                         a.vol, (const T *)a.v, (int64_t)a.nv * a.vol, a.d_node, (const T *)a.d_scale, a.d_start,
+                         a.d_enode, (const T *)a.d_w, a.nrows_d, a.nshots, dio, (T *)a.p, a.vol);
   }
 }
 

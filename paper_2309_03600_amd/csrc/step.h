@@ -115,6 +115,16 @@ struct PVArgs {
   int g_lanes, d_lanes;        // lanes per modified row (8 for short rows, else 16)
   const int2 *zr4;             // 3D: per 64 x 4 column block, the planes [x, y) that hold
                                // interior p or v nodes of its columns
+  // io_merge: the rows launches carry the sources and receivers.  The gradient rows of a
+  // step sample the receivers for the step before (sample_prev), from p; the divergence
+  // rows inject this step's sources into p and advance the step counter.
+  int io_merge, sample_prev;
+  const int64_t *sidx, *ridx;
+  const void *sw, *rw, *wavelet;
+  int64_t wstride, nsteps;
+  int nrec;
+  void *traces;
+  int64_t *tcount;
 };
 void enqueue_pv_step(const PVArgs &a, hipStream_t st);
 void enqueue_interior_only(const StepArgs &a, hipStream_t st);

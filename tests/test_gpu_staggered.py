@@ -159,6 +159,64 @@ def test_traces_match_oracle(name, prec):
     assert e.max() < (1e-9 if prec == "f64" else 1e-4)
 
 
+def test_split_calls_match_one_call():
+    """The rows launches carry the sources (divergence rows) and the receivers of the step
+    before (gradient rows), and a call's last step is sampled at its end: a run split into
+    calls of 1 to 47 steps, eager and graph-replayed, gives the traces of one call, bit for
+    bit."""
+    import torch
+
+    import paper_2309_03600_amd as ib
+    wl, w, *_ = case("2d-m8-free")
+    wav = torch.tensor(wl.wavelets(np.float32), dtype=torch.float32, device="cuda")
+    chunks = [1, 2, 3, 16, 17, 1, 33, 47]
+    n = sum(chunks)
+    st = ib.ib_state_create(w, wl.vel, wl.dt, wl.src, wl.rec, damp_width=wl.damp_width, precision="f32")
+    one = st.step(n, wav, use_graph=True).cpu().numpy()
+    for graph in (False, True):
+        st = ib.ib_state_create(w, wl.vel, wl.dt, wl.src, wl.rec, damp_width=wl.damp_width, precision="f32")
+        split = torch.cat([st.step(c, wav, use_graph=graph) for c in chunks], dim=1).cpu().numpy()
+        print(f"[pv split calls graph={graph}] steps {st.step_count}", flush=True)
+        assert st.step_count == n
+        assert np.abs(one).max() > 0
+        assert np.array_equal(split, one)
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_source_at_a_modified_row_matches_oracle(prec):
+    """A source whose interpolation corners include a p node just under the surface (a
+    modified divergence row): its injection would race with the row's update inside the
+    rows launch, so it runs as a launch of its own; traces against the oracle."""
+    import dataclasses
+
+    import torch
+
+    import paper_2309_03600_amd as ib
+    wl0, w, ex, m, vsol, psol, G, D = case("2d-m8-free")
+    nx, nz = wl0.shape
+    inter = np.asarray(m.inter["p"]).reshape(nz, nx).astype(bool)
+    pick = None
+    for z in range(nz - 1):
+        for x in range(3, nx - 4):
+            cell = inter[z:z + 2, x:x + 2]
+            depth = z * wl0.h - wl0.heights[x]
+            if pick is None and cell.all() and 0.0 < depth < wl0.h:
+                pick = (x, z)
+    assert pick is not None
+    x, z = pick
+    wl = dataclasses.replace(wl0, src=np.array([[(x + 0.5) * wl0.h, (z + 0.5) * wl0.h]]))
+    print(f"[pv source at a row {prec}] cell {pick}", flush=True)
+    sim = _oracle_sim(wl, m, G, D)
+    ref = sim.run(wl.wavelets(np.float64), wl.nt)
+    tdt = torch.float64 if prec == "f64" else torch.float32
+    wav = torch.tensor(wl.wavelets(np.float64), dtype=tdt, device="cuda")
+    st = ib.ib_state_create(w, wl.vel, wl.dt, wl.src, wl.rec, damp_width=wl.damp_width, precision=prec)
+    tr = st.step(wl.nt, wav, use_graph=True).double().cpu().numpy()[0]
+    e = rel_l2_per_trace(tr, ref)
+    print(f"[pv source at a row {prec}] per-trace rel-L2: max {e.max():.2e}", flush=True)
+    assert e.max() < (1e-9 if prec == "f64" else 1e-4)
+
+
 @pytest.mark.parametrize("prec", ["f64", "f32"])
 def test_graph_replay_matches_eager(prec):
     import torch
